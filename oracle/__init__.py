@@ -1,0 +1,263 @@
+"""FP64 CPU oracle for the SBM elasticity multigrid solve (arXiv:2212.02362).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the CPU-baseline
+leg of the benchmark may import this package; the library under
+``paper_2212_02362_amd`` never does, and the two share no code.
+
+The arithmetic lives in ``sbm_oracle.c`` (plain loops, IEEE double, built with
+``-ffp-contract=off``); this module only loads it and marshals numpy arrays.
+Every function cites the passage of the paper it follows in the C source.
+
+Conventions: node vectors have shape ``(d, *nodes)`` in numpy order, i.e.
+``(d, ny+1, nx+1)`` in 2D and ``(d, nz+1, ny+1, nx+1)`` in 3D (x fastest in
+memory); cell scalars have shape ``(ny, nx)`` / ``(nz, ny, nx)``.  ``ncell``
+is given as ``(nx, ny[, nz])``.  Boundary kinds/values are ``(6, 3)`` arrays
+over faces x-, x+, y-, y+, z-, z+ and components.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "sbm_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+TRACTION = 0
+DISPLACEMENT = 1
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2 -fopenmp -ffp-contract=off)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
+             "-std=c11", "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        _lib = ctypes.CDLL(_LIB)
+    return _lib
+
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_lp = ctypes.POINTER(ctypes.c_long)
+_ip = ctypes.POINTER(ctypes.c_int)
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+
+
+def _d(a):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_dp)
+
+
+def _u8(a):
+    assert a.dtype == np.uint8 and a.flags.c_contiguous
+    return a.ctypes.data_as(_u8p)
+
+
+def _long3(nc):
+    v = list(nc) + [0] * (3 - len(nc))
+    return (ctypes.c_long * 3)(*v)
+
+
+def _dbl3(h):
+    v = list(h) + [1.0] * (3 - len(h))
+    return (ctypes.c_double * 3)(*v)
+
+
+def node_shape(ncell):
+    return tuple(n + 1 for n in reversed(ncell))
+
+
+def cell_shape(ncell):
+    return tuple(reversed(ncell))
+
+
+def _bc(kind, val):
+    k = np.ascontiguousarray(kind, dtype=np.int32).reshape(6, 3)
+    v = np.ascontiguousarray(val, dtype=np.float64).reshape(6, 3)
+    return k, v
+
+
+def apply(ncell, h, lam, mu, psi, u):
+    """Ku by eq. K (node rows written out with the full C_ijkl tensor)."""
+    d = len(ncell)
+    psi = np.ascontiguousarray(psi, np.float64)
+    u = np.ascontiguousarray(u, np.float64)
+    assert psi.shape == cell_shape(ncell) and u.shape == (d,) + node_shape(ncell)
+    out = np.empty_like(u)
+    lib().orc_apply(d, _long3(ncell), _dbl3(h), ctypes.c_double(lam), ctypes.c_double(mu),
+                    _d(psi), _d(u), _d(out))
+    return out
+
+
+def diag(ncell, h, lam, mu, psi):
+    d = len(ncell)
+    psi = np.ascontiguousarray(psi, np.float64)
+    out = np.empty((d,) + node_shape(ncell))
+    lib().orc_diag(d, _long3(ncell), _dbl3(h), ctypes.c_double(lam), ctypes.c_double(mu),
+                   _d(psi), _d(out))
+    return out
+
+
+def floor_psi(psi_raw, floor):
+    return np.maximum(np.asarray(psi_raw, np.float64), floor)
+
+
+def dirichlet(ncell, kind, val):
+    """(mask uint8, uD) node vectors."""
+    d = len(ncell)
+    k, v = _bc(kind, val)
+    mask = np.empty((d,) + node_shape(ncell), np.uint8)
+    uD = np.empty((d,) + node_shape(ncell))
+    lib().orc_dirichlet_mask(d, _long3(ncell), k.ctypes.data_as(_ip), _d(v), _u8(mask), _d(uD))
+    return mask, uD
+
+
+def rhs(ncell, h, lam, mu, psi, kind, val, b=None):
+    """(fA, fB, uD): load with traction source, lifted load, prescribed values."""
+    d = len(ncell)
+    k, v = _bc(kind, val)
+    psi = np.ascontiguousarray(psi, np.float64)
+    shp = (d,) + node_shape(ncell)
+    fA, fB, uD = np.empty(shp), np.empty(shp), np.empty(shp)
+    bb = None if b is None else np.ascontiguousarray(b, np.float64)
+    lib().orc_rhs(d, _long3(ncell), _dbl3(h), ctypes.c_double(lam), ctypes.c_double(mu),
+                  _d(psi), k.ctypes.data_as(_ip), _d(v), _d(bb), _d(fA), _d(fB), _d(uD))
+    return fA, fB, uD
+
+
+def residual(ncell, h, lam, mu, psi, mask, u, f):
+    d = len(ncell)
+    out = np.empty((d,) + node_shape(ncell))
+    lib().orc_residual(d, _long3(ncell), _dbl3(h), ctypes.c_double(lam), ctypes.c_double(mu),
+                       _d(np.ascontiguousarray(psi, np.float64)), _u8(mask),
+                       _d(np.ascontiguousarray(u, np.float64)),
+                       _d(np.ascontiguousarray(f, np.float64)), _d(out))
+    return out
+
+
+def jacobi(ncell, h, lam, mu, psi, mask, omega, u, f):
+    d = len(ncell)
+    out = np.empty((d,) + node_shape(ncell))
+    lib().orc_jacobi(d, _long3(ncell), _dbl3(h), ctypes.c_double(lam), ctypes.c_double(mu),
+                     _d(np.ascontiguousarray(psi, np.float64)), _u8(mask), ctypes.c_double(omega),
+                     _d(np.ascontiguousarray(u, np.float64)),
+                     _d(np.ascontiguousarray(f, np.float64)), _d(out))
+    return out
+
+
+def rb_half(ncell, h, lam, mu, psi, mask, omega, colour, u, f):
+    d = len(ncell)
+    out = np.empty((d,) + node_shape(ncell))
+    lib().orc_rb_half(d, _long3(ncell), _dbl3(h), ctypes.c_double(lam), ctypes.c_double(mu),
+                      _d(np.ascontiguousarray(psi, np.float64)), _u8(mask), ctypes.c_double(omega),
+                      int(colour), _d(np.ascontiguousarray(u, np.float64)),
+                      _d(np.ascontiguousarray(f, np.float64)), _d(out))
+    return out
+
+
+def prolong_add(ncell_coarse, e, mask_fine, u_fine):
+    d = len(ncell_coarse)
+    u = np.array(u_fine, np.float64, copy=True, order="C")
+    lib().orc_prolong_add(d, _long3(ncell_coarse), _d(np.ascontiguousarray(e, np.float64)),
+                          _u8(mask_fine), _d(u))
+    return u
+
+
+def restrict(ncell_fine, r, mask_coarse):
+    d = len(ncell_fine)
+    ncc = tuple(n // 2 for n in ncell_fine)
+    out = np.empty((d,) + node_shape(ncc))
+    lib().orc_restrict(d, _long3(ncell_fine), _d(np.ascontiguousarray(r, np.float64)),
+                       _u8(mask_coarse), _d(out))
+    return out
+
+
+def coarsen_psi(ncell_fine, psi):
+    d = len(ncell_fine)
+    ncc = tuple(n // 2 for n in ncell_fine)
+    out = np.empty(cell_shape(ncc))
+    lib().orc_coarsen_psi(d, _long3(ncell_fine), _d(np.ascontiguousarray(psi, np.float64)),
+                          _d(out))
+    return out
+
+
+def cg(ncell, h, lam, mu, psi, mask, f, x0=None, rtol=1e-12, maxit=None):
+    d = len(ncell)
+    x = np.zeros((d,) + node_shape(ncell)) if x0 is None else np.array(x0, np.float64, copy=True)
+    if maxit is None:
+        maxit = 4 * int((mask == 0).sum())
+    it = lib().orc_cg(d, _long3(ncell), _dbl3(h), ctypes.c_double(lam), ctypes.c_double(mu),
+                      _d(np.ascontiguousarray(psi, np.float64)), _u8(mask),
+                      _d(np.ascontiguousarray(f, np.float64)), _d(x), ctypes.c_double(rtol),
+                      int(maxit))
+    return x, it
+
+
+def num_levels(ncell):
+    return lib().orc_num_levels(len(ncell), _long3(ncell))
+
+
+def solve(ncell, h, lam, mu, psi_raw, psi_floor, kind, val, b=None, *, smoother=0,
+          omega=None, nu_pre=2, nu_post=2, rtol=1e-10, max_cycles=200, bottom_rtol=1e-12,
+          bottom_max_iter=0, u0=None):
+    """FP64 V-cycle solve. Returns (u, hist, status)."""
+    d = len(ncell)
+    if omega is None:
+        omega = 1.0 if smoother == 0 else 0.8
+    k, v = _bc(kind, val)
+    u = np.zeros((d,) + node_shape(ncell)) if u0 is None else np.array(u0, np.float64, copy=True)
+    hist = np.zeros(max_cycles + 1)
+    ncyc = ctypes.c_int(0)
+    bb = None if b is None else np.ascontiguousarray(b, np.float64)
+    st = lib().orc_solve(d, _long3(ncell), _dbl3(h), ctypes.c_double(lam), ctypes.c_double(mu),
+                         _d(np.ascontiguousarray(psi_raw, np.float64)), ctypes.c_double(psi_floor),
+                         k.ctypes.data_as(_ip), _d(v), _d(bb), int(smoother),
+                         ctypes.c_double(omega), int(nu_pre), int(nu_post), ctypes.c_double(rtol),
+                         int(max_cycles), ctypes.c_double(bottom_rtol), int(bottom_max_iter),
+                         _d(u), _d(hist), int(max_cycles + 1), ctypes.byref(ncyc))
+    return u, hist[: ncyc.value + 1].copy(), st
+
+
+def sensitivity(ncell, h, lam, mu, kind, val, u, adj, rho=None, psi_floor=0.0):
+    """dL/dpsi per cell (or dL/drho when rho is given, psi = max(rho^3, floor))."""
+    d = len(ncell)
+    k, v = _bc(kind, val)
+    g = np.empty(cell_shape(ncell))
+    rr = None if rho is None else np.ascontiguousarray(rho, np.float64)
+    lib().orc_sensitivity(d, _long3(ncell), _dbl3(h), ctypes.c_double(lam), ctypes.c_double(mu),
+                          k.ctypes.data_as(_ip), _d(v), _d(np.ascontiguousarray(u, np.float64)),
+                          _d(np.ascontiguousarray(adj, np.float64)), _d(rr),
+                          ctypes.c_double(psi_floor), _d(g))
+    return g
+
+
+def assemble(ncell, h, lam, mu, psi):
+    """Dense K (small grids only) built column by column from ``apply``."""
+    d = len(ncell)
+    shp = (d,) + node_shape(ncell)
+    n = int(np.prod(shp))
+    K = np.empty((n, n))
+    e = np.zeros(n)
+    for j in range(n):
+        e[j] = 1.0
+        K[:, j] = apply(ncell, h, lam, mu, psi, e.reshape(shp)).ravel()
+        e[j] = 0.0
+    return K

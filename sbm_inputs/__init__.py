@@ -1,0 +1,223 @@
+"""Seeded synthetic inputs for the SBM elasticity solve.
+
+This module builds problem *inputs* only: cell indicator fields, boundary
+tables, body forces and grid sizes.  It holds none of the solver's arithmetic
+(no operator, no floor, no source terms) and is the only module shared by the
+HIP library's tests and the CPU oracle.
+
+The workloads stand in for the geometries of arXiv:2212.02362 (no public
+dataset exists): a 2D plate with a circular void (Sec. 3.1), a 3D block with
+spherical voids (Sec. 3.1), a near-singular diffuse crack in a random void
+field (Sec. 3.2), ellipsoidal voids for the adaptive case, and a SIMP-like
+random density for the topology-optimisation gradient (Sec. 3.3).  Every
+generator draws from ``numpy.random.default_rng(seed)`` in the order written.
+
+Array conventions: cells ``(ny, nx)`` / ``(nz, ny, nx)``; node vectors
+``(d, ny+1, nx+1)`` / ``(d, nz+1, ny+1, nx+1)``; ``ncell = (nx, ny[, nz])``.
+Boundary tables are ``(6, 3)`` over faces x-, x+, y-, y+, z-, z+.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional
+
+import numpy as np
+
+TRACTION = 0
+DISPLACEMENT = 1
+
+
+def lame(E: float, nu: float):
+    """(lambda, mu) from Young's modulus and Poisson's ratio."""
+    return E * nu / ((1 + nu) * (1 - 2 * nu)), E / (2 * (1 + nu))
+
+
+@dataclasses.dataclass
+class Problem:
+    name: str
+    ncell: tuple
+    h: tuple
+    lam: float
+    mu: float
+    psi_floor: float
+    psi_raw: np.ndarray            # cells, before the floor
+    kind: np.ndarray               # (6, 3) int32
+    val: np.ndarray                # (6, 3) float64
+    b: Optional[np.ndarray] = None  # node body force or None
+    rho: Optional[np.ndarray] = None  # density (topology-optimisation input)
+    fd_cells: Optional[np.ndarray] = None
+    extra: dict = dataclasses.field(default_factory=dict)
+
+    @property
+    def dim(self):
+        return len(self.ncell)
+
+    @property
+    def node_shape(self):
+        return tuple(n + 1 for n in reversed(self.ncell))
+
+    @property
+    def n_nodes(self):
+        return int(np.prod(self.node_shape))
+
+
+def _bc_table():
+    return np.zeros((6, 3), np.int32), np.zeros((6, 3), np.float64)
+
+
+def cell_centres(ncell, h):
+    """Coordinate arrays of the cell centres, numpy axis order (z, y, x)."""
+    axes = [(np.arange(n) + 0.5) * hh for n, hh in zip(ncell, h)]
+    grids = np.meshgrid(*reversed(axes), indexing="ij")
+    return list(reversed(grids))  # [X, Y(, Z)] each shaped like the cells
+
+
+def node_coords(ncell, h):
+    axes = [np.arange(n + 1) * hh for n, hh in zip(ncell, h)]
+    grids = np.meshgrid(*reversed(axes), indexing="ij")
+    return list(reversed(grids))
+
+
+def plate_void_2d(n: int = 64, floor: float = 1e-4) -> Problem:
+    """Unit square, centred circular void of radius 0.25 with tanh width 2h.
+    Bottom edge clamped, uniform normal traction 1e-3 on the top edge, sides
+    traction-free."""
+    h = 1.0 / n
+    X, Y = cell_centres((n, n), (h, h))
+    r = np.hypot(X - 0.5, Y - 0.5)
+    psi = 0.5 * (1 + np.tanh((r - 0.25) / (2 * h)))
+    kind, val = _bc_table()
+    kind[2, :2] = DISPLACEMENT
+    val[3, 1] = 1e-3
+    lam, mu = lame(1.0, 0.3)
+    return Problem("plate_void_2d", (n, n), (h, h), lam, mu, floor, psi, kind, val)
+
+
+def spherical_voids_3d(n: int = 128, seed: int = 0, nvoid: int = 20,
+                       floor: float = 1e-6) -> Problem:
+    """Unit cube with seeded spherical voids (centres U[0,1]^3, radii
+    U[0.05,0.15], tanh width 2h).  z=0 clamped, u=(0,0,1e-3) on z=1."""
+    rng = np.random.default_rng(seed)
+    centres = rng.uniform(0.0, 1.0, (nvoid, 3))
+    radii = rng.uniform(0.05, 0.15, nvoid)
+    h = 1.0 / n
+    X, Y, Z = cell_centres((n, n, n), (h, h, h))
+    psi = np.ones_like(X)
+    for c, R in zip(centres, radii):
+        dist = np.sqrt((X - c[0]) ** 2 + (Y - c[1]) ** 2 + (Z - c[2]) ** 2)
+        psi *= 0.5 * (1 + np.tanh((dist - R) / (2 * h)))
+    kind, val = _bc_table()
+    kind[4, :] = DISPLACEMENT
+    kind[5, :] = DISPLACEMENT
+    val[5, 2] = 1e-3
+    lam, mu = lame(1.0, 0.3)
+    return Problem("spherical_voids_3d", (n, n, n), (h, h, h), lam, mu, floor, psi, kind, val,
+                   extra={"centres": centres, "radii": radii})
+
+
+def _smooth_field(rng, shape, sigma_cells):
+    from scipy.ndimage import gaussian_filter
+    g = rng.standard_normal(shape)
+    g = gaussian_filter(g, sigma_cells, mode="reflect")
+    return (g - g.mean()) / g.std()
+
+
+def diffuse_crack_3d(n: int = 256, seed: int = 0, floor: float = 1e-6) -> Problem:
+    """Planar disc crack (radius 0.3, centre (1/2,1/2,1/2), seeded normal) with
+    crack factor 1-exp(-d/2h), times a random void field in which 40% of the
+    cells fall below 0.01.  Mode-I displacement loading on the faces normal to
+    the dominant normal axis."""
+    rng = np.random.default_rng(seed)
+    v = rng.standard_normal(3)
+    nrm = v / np.linalg.norm(v)
+    h = 1.0 / n
+    X, Y, Z = cell_centres((n, n, n), (h, h, h))
+    dx, dy, dz = X - 0.5, Y - 0.5, Z - 0.5
+    z = dx * nrm[0] + dy * nrm[1] + dz * nrm[2]
+    px, py, pz = dx - z * nrm[0], dy - z * nrm[1], dz - z * nrm[2]
+    rho_par = np.sqrt(px * px + py * py + pz * pz)
+    dist = np.sqrt(z * z + np.maximum(rho_par - 0.3, 0.0) ** 2)
+    psi_cr = 1.0 - np.exp(-dist / (2 * h))
+    del X, Y, Z, dx, dy, dz, z, px, py, pz, rho_par, dist
+    g = _smooth_field(rng, (n, n, n), 8.0 / math.sqrt(2.0))
+    tau = np.quantile(g, 0.4)
+    psi_v = 1.0 / (1.0 + np.exp(-((g - tau) / 0.05 - math.log(99.0))))
+    psi = psi_cr * psi_v
+    a = int(np.argmax(np.abs(nrm)))
+    kind, val = _bc_table()
+    kind[2 * a, :] = DISPLACEMENT
+    kind[2 * a + 1, :] = DISPLACEMENT
+    val[2 * a + 1, a] = 1e-3
+    lam, mu = lame(1.0, 0.3)
+    return Problem("diffuse_crack_3d", (n, n, n), (h, h, h), lam, mu, floor, psi, kind, val,
+                   extra={"normal": nrm, "axis": a, "void_fraction": float((psi_v < 0.01).mean())})
+
+
+def cantilever_density_3d(nx: int = 192, ny: int = 96, nz: int = 96, seed: int = 0,
+                          floor: float = 1e-4, n_fd: int = 32) -> Problem:
+    """Topology-optimisation gradient workload: domain [0,2]x[0,1]x[0,1],
+    density rho = sigmoid of a standardised Gaussian random field (correlation
+    length 8h), psi = rho^3 (raw), x=0 clamped, unit load (0,0,-1) smoothed
+    over a 4h ball at the far corner (2,1,1) with weights (1-(r/4h)^2)^2
+    normalised so that h^3 sum(b) = F."""
+    rng = np.random.default_rng(seed)
+    h = 1.0 / ny
+    g = _smooth_field(rng, (nz, ny, nx), 8.0 / math.sqrt(2.0))
+    rho = 1.0 / (1.0 + np.exp(-g))
+    fd = rng.choice(nx * ny * nz, size=n_fd, replace=False)
+    Xn, Yn, Zn = node_coords((nx, ny, nz), (h, h, h))
+    r = np.sqrt((Xn - nx * h) ** 2 + (Yn - ny * h) ** 2 + (Zn - nz * h) ** 2)
+    w = np.where(r < 4 * h, (1 - (r / (4 * h)) ** 2) ** 2, 0.0)
+    F = np.array([0.0, 0.0, -1.0])
+    b = np.zeros((3,) + w.shape)
+    for k in range(3):
+        b[k] = F[k] * w / (h ** 3 * w.sum())
+    kind, val = _bc_table()
+    kind[0, :] = DISPLACEMENT
+    lam, mu = lame(1.0, 0.3)
+    return Problem("cantilever_density_3d", (nx, ny, nz), (h, h, h), lam, mu, floor, rho ** 3,
+                   kind, val, b=b, rho=rho, fd_cells=fd)
+
+
+def kirsch_quarter_plate(n: int = 128, L: float = 16.0, a: float = 1.0, width: float = 0.5,
+                         sigma: float = 1e-3, floor: float = 1e-6) -> Problem:
+    """Quarter model of an infinite plate with a circular hole (radius a at the
+    origin) under remote uniaxial stress sigma along x: rollers on x=0 (u_x=0)
+    and y=0 (u_y=0), traction (sigma, 0) on x=L, y=L traction-free.  The
+    indicator is 0.5(1+tanh((r-a)/width))."""
+    h = L / n
+    X, Y = cell_centres((n, n), (h, h))
+    r = np.hypot(X, Y)
+    psi = 0.5 * (1 + np.tanh((r - a) / width))
+    kind, val = _bc_table()
+    kind[0, 0] = DISPLACEMENT
+    kind[2, 1] = DISPLACEMENT
+    val[1, 0] = sigma
+    lam, mu = lame(1.0, 0.3)
+    return Problem("kirsch_quarter_plate", (n, n), (h, h), lam, mu, floor, psi, kind, val,
+                   extra={"L": L, "a": a, "sigma": sigma, "width": width})
+
+
+def random_fields(ncell, seed=0, psi_lo=1e-6, psi_hi=1.0):
+    """Random psi (cells) and u, f (nodes) for kernel-level parity tests."""
+    rng = np.random.default_rng(seed)
+    d = len(ncell)
+    cs = tuple(reversed(ncell))
+    ns = (d,) + tuple(n + 1 for n in reversed(ncell))
+    psi = rng.uniform(psi_lo, psi_hi, cs)
+    u = rng.standard_normal(ns)
+    f = rng.standard_normal(ns)
+    return psi, u, f
+
+
+def mixed_bc(dim, seed=0):
+    """A boundary table mixing traction and displacement faces/components."""
+    rng = np.random.default_rng(seed)
+    kind, val = _bc_table()
+    for F in range(2 * dim):
+        for k in range(dim):
+            kind[F, k] = int(rng.integers(0, 2))
+            val[F, k] = rng.uniform(-1e-3, 1e-3)
+    kind[0, :dim] = DISPLACEMENT  # something always pins the rigid modes
+    return kind, val
