@@ -1,0 +1,241 @@
+#!/usr/bin/env python
+"""Benchmark of the SBM elasticity multigrid solve on one MI355X.
+
+One step = one complete solve of the workload to a relative residual of
+1e-10 from a zero initial guess: load assembly, psi hierarchy and every
+V-cycle, with the inputs already resident in device memory.  The metric is
+free DOF solved per second.  The FP64 solve gives ``value``; the mixed solve
+(FP32 cycles, FP64 residual/correction/bottom refinement) is timed beside it.
+
+The dominant kernel is the finest-level Gauss-Seidel half-sweep; its average
+launch time is measured with HIP events inside the timed region and set
+against its algorithmic bytes (80 B per node in FP64: u 24 + psi 8 + f 24
+read, u 24 written) and the 8 TB/s HBM peak.
+
+The CPU baseline is the FP64 oracle (plain loops, OpenMP, not a tuned solver)
+on the host cores: its setup and one V-cycle are timed on the same workload
+and projected to the FP64 cycle count.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DOF/s solved to 1e-10 rel. residual, FP64 vs mixed; stencil HBM GB/s % peak"
+HBM_PEAK_GBS = 8000.0
+
+# algorithmic bytes per finest-level node and launch, FP64 (FP32 halves the vector parts)
+ALGO_BYTES = {              # (FP64, FP32) bytes per finest-level node
+    "smooth": (80.0, 40.0),    # u, psi, f read, u written
+    "residual": (80.0, 40.0),  # u, psi, f read, r written
+    "restrict": (27.0, 13.5),  # r read, coarse f written (1/8 of the nodes)
+    "prolong": (51.0, 25.5),   # coarse e read, u read and written
+    "norm": (56.0, 56.0),      # u, psi, f read (always FP64)
+}
+
+
+def _workload(name):
+    import sbm_inputs as si
+    if name == "spherical_voids_129":
+        return si.spherical_voids_3d(128), (
+            "3D unit cube, 129^3 nodes (128^3 cells), E=1 nu=0.3, 20 seeded spherical voids "
+            "(seed 0), psi floor 1e-6, z=0 clamped, u=(0,0,1e-3) on z=1; V(2,2) two-colour "
+            "Gauss-Seidel, rtol 1e-10")
+    if name == "diffuse_crack_257":
+        return si.diffuse_crack_3d(256), (
+            "3D unit cube, 257^3 nodes, diffuse disc crack in a 40% void field (seed 0), psi "
+            "floor 1e-6, mode-I displacement loading; V(2,2) two-colour Gauss-Seidel, rtol 1e-10")
+    if name == "cantilever_193x97x97":
+        return si.cantilever_density_3d(), (
+            "3D cantilever 193x97x97 nodes, psi = rho^3 (rho = sigmoid of a seeded Gaussian "
+            "random field), floor 1e-4, x=0 clamped, smoothed corner load; V(2,2) two-colour "
+            "Gauss-Seidel, rtol 1e-10")
+    raise SystemExit(f"unknown workload {name}")
+
+
+def _free_dof(p):
+    import numpy as np
+    d = p.dim
+    shp = p.node_shape
+    free = 0
+    for k in range(d):
+        m = np.zeros(shp, bool)
+        for F in range(2 * d):
+            if p.kind[F, k] != 1:
+                continue
+            a = F // 2
+            ax = d - 1 - a
+            sl = [slice(None)] * d
+            sl[ax] = 0 if F % 2 == 0 else shp[ax] - 1
+            m[tuple(sl)] = True
+        free += int((~m).sum())
+    return free
+
+
+def _kernel_hash():
+    h = hashlib.sha256()
+    for fn in ("sbm_device.h", "sbm_kernels.hip"):
+        with open(os.path.join(ROOT, "paper_2212_02362_amd", "csrc", fn), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic(kernel_key, nodes):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        data = json.load(fh)
+    ent = data.get(kernel_key)
+    if not ent or ent.get("kernel_hash") != _kernel_hash() or ent.get("nodes") != nodes:
+        return None
+    return ent.get("hbm_bytes_per_launch")
+
+
+def _time_solves(S, p, psi_dev, b_dev, precision, steps, warmup):
+    import torch
+    S.set_options(precision=precision)
+
+    def one():
+        S.set_problem(psi_dev, p.lam, p.mu, p.psi_floor, p.kind, p.val, b_dev)
+        return S.solve()
+
+    for _ in range(warmup):
+        one()
+    torch.cuda.synchronize()
+    S.profile(True)
+    t0 = time.perf_counter()
+    cycles, status, final = [], [], []
+    for _ in range(steps):
+        u, hist, st = one()
+        cycles.append(len(hist) - 1)
+        status.append(int(st))
+        final.append(float(hist[-1]))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = S.profile_read()
+    S.profile(False)
+    return (t1 - t0) / steps, cycles, status, final, prof
+
+
+def _cpu_baseline(p, cycles_fp64, free):
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    oracle.solve(p.ncell, p.h, p.lam, p.mu, p.psi_raw, p.psi_floor, p.kind, p.val, p.b,
+                 rtol=0.0, max_cycles=0)
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.solve(p.ncell, p.h, p.lam, p.mu, p.psi_raw, p.psi_floor, p.kind, p.val, p.b,
+                 rtol=0.0, max_cycles=1)
+    t_one = time.perf_counter() - t0
+    per_cycle = max(t_one - t_setup, 1e-9)
+    projected = t_setup + cycles_fp64 * per_cycle
+    return {
+        "value": free / projected, "unit": "DOF/s", "cores": threads, "kind": "oracle",
+        "sample": (f"FP64 oracle (plain C loops, OpenMP, not a tuned solver) on the same workload: "
+                   f"setup + 1 V-cycle timed ({t_one:.1f} s), projected to the {cycles_fp64} "
+                   f"cycles of the FP64 solve (projected {projected:.1f} s per solve)"),
+        "seconds_setup": t_setup, "seconds_per_cycle": per_cycle,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="spherical_voids_129",
+                    choices=["spherical_voids_129", "diffuse_crack_257", "cantilever_193x97x97"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for "
+              f"--gpus {args.gpus}).  Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2212_02362_amd import Solver
+
+    p, desc = _workload(args.workload)
+    free = _free_dof(p)
+    nodes = p.n_nodes
+    print(f"[bench] {args.workload}: {nodes} nodes, {free} free DOF", file=sys.stderr, flush=True)
+    psi_dev = torch.tensor(p.psi_raw, dtype=torch.float64, device="cuda")
+    b_dev = None if p.b is None else torch.tensor(p.b, dtype=torch.float64, device="cuda")
+    S = Solver(p.ncell, p.h, rtol=1e-10, max_cycles=400)
+
+    t64, cyc64, st64, fin64, prof64 = _time_solves(S, p, psi_dev, b_dev, 0, args.steps, args.warmup)
+    print(f"[bench] fp64: {t64 * 1e3:.2f} ms/solve, cycles {cyc64}", file=sys.stderr, flush=True)
+    res = {}
+    if not args.no_mixed:
+        t32, cyc32, st32, fin32, prof32 = _time_solves(S, p, psi_dev, b_dev, 1, args.steps,
+                                                        args.warmup)
+        print(f"[bench] mixed: {t32 * 1e3:.2f} ms/solve, cycles {cyc32}", file=sys.stderr,
+              flush=True)
+
+    def kstats(prof, fp32):
+        out = {}
+        for k, (ms, n) in prof.items():
+            if n == 0:
+                continue
+            avg = ms / n
+            ent = {"launches": n, "avg_us": avg * 1e3}
+            if k in ALGO_BYTES:
+                by = ALGO_BYTES[k][1 if fp32 and k != "norm" else 0] * nodes
+                ent["algo_GBps"] = by / (avg * 1e-3) / 1e9
+                ent["frac_hbm_peak"] = ent["algo_GBps"] / HBM_PEAK_GBS
+            out[k] = ent
+        return out
+
+    ms_s, n_s = prof64["smooth"]
+    avg_ms = ms_s / max(n_s, 1)
+    by = ALGO_BYTES["smooth"][0] * nodes
+    achieved = by / (avg_ms * 1e-3) / 1e9
+    traffic = _traffic("k_rb_half<double,3>", nodes)
+    line = {
+        "metric": METRIC,
+        "value": free / t64,
+        "unit": "DOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t64 * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "nodes": nodes, "free_dof": free, "precision": "fp64",
+                   "cycles": cyc64, "final_rel_residual": max(fin64), "status": st64},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_rb_half<double,3> (finest-level Gauss-Seidel half-sweep)",
+                     "algo_bytes_per_launch": by, "avg_launch_us": avg_ms * 1e3},
+        "kernels_fp64": kstats(prof64, False),
+    }
+    if not args.no_mixed:
+        line["mixed"] = {"value": free / t32, "unit": "DOF/s", "ms_per_step": t32 * 1e3,
+                         "dtype": "f32 cycles + f64 refinement", "cycles": cyc32,
+                         "final_rel_residual": max(fin32), "status": st32,
+                         "speedup_vs_fp64": t64 / t32, "kernels": kstats(prof32, True)}
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = _cpu_baseline(p, int(np.median(cyc64)), free)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,272 @@
+/*
+ * sbm.h -- C ABI of the MI355X (gfx950) smooth-boundary-method elasticity
+ * multigrid library.
+ *
+ * The library solves the diffuse-boundary equilibrium of Agrawal & Runnels,
+ * arXiv:2212.02362, Sec. 2.1 (eq. SBMLinearElasticity):
+ *
+ *     div(psi C : grad u) + b = 0,      written  K u = f,  K = -div(psi C grad .)
+ *
+ * on a box, with the displacement u on the nodes and the indicator psi in the
+ * cells (Sec. 2.3), isotropic moduli given as Lame constants (Sec. 2.4),
+ * traction boundary data entering as source terms (Sec. 2.1) and displacement
+ * data eliminated at the nodes (Sec. 2.1: essential conditions are not
+ * diffused).  The solver is geometric multigrid (Sec. 2.2) with Jacobi or
+ * two-colour Gauss-Seidel smoothing (Sec. 2.3), full-weighting restriction,
+ * multilinear prolongation, coarse operators re-discretised on averaged psi
+ * and a CG bottom solve.
+ *
+ * Layouts (all arrays dense, row-major, x fastest):
+ *   node vector  v[k][z][y][x]   k < dim components, (nx+1)(ny+1)(nz+1) nodes
+ *                                (2D: v[k][y][x])
+ *   cell scalar  s[z][y][x]      nx*ny*nz cells (2D: s[y][x])
+ * where (nx, ny, nz) = grid.ncell.  Faces are numbered x-,x+,y-,y+,z-,z+.
+ *
+ * Pointers: every array argument is a DEVICE pointer unless its name ends in
+ * _host.  The caller owns all memory.  The library never allocates device
+ * memory: every device buffer it needs is carved from the caller's workspace
+ * (sbm_workspace_bytes), which must stay alive until sbm_destroy.
+ *
+ * Streams: all device work is enqueued on the HIP stream given to sbm_create.
+ * Calls documented "async" return before the work completes; the others
+ * return with the stream idle.
+ *
+ * Errors: no exception crosses the ABI.  A negative status means the outputs
+ * are unspecified; sbm_last_error() (thread-local) describes the failure.
+ * SBM_NOT_CONVERGED (> 0) means the outputs are valid.
+ *
+ * Threading: a context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef SBM_H
+#define SBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sbm_ctx sbm_ctx;
+
+typedef enum {
+  SBM_OK = 0,
+  SBM_NOT_CONVERGED = 1, /* max_cycles reached; u and history valid */
+  SBM_E_ARG = -1,        /* null pointer or out-of-range argument */
+  SBM_E_SHAPE = -2,      /* unsupported grid (dim, cell counts) */
+  SBM_E_HIP = -3,        /* a HIP runtime call failed */
+  SBM_E_NONFINITE = -4,  /* NaN/Inf in psi, b, u0 or a residual */
+  SBM_E_DIVERGED = -5,   /* residual grew 1e3 x above its minimum */
+  SBM_E_DIAG = -6,       /* a free DOF has a zero diagonal (psi = 0 around it) */
+  SBM_E_WORKSPACE = -7   /* workspace too small or misaligned */
+} sbm_status;
+
+typedef enum { SBM_TRACTION = 0, SBM_DISPLACEMENT = 1 } sbm_bc_kind;
+
+/* Grid: dim 2 or 3; ncell[a] >= 1 for a < dim (unused entries ignored);
+ * h[a] > 0 is the spacing along axis a.  Nodes per axis are ncell[a] + 1. */
+typedef struct {
+  int dim;
+  int64_t ncell[3];
+  double h[3];
+} sbm_grid;
+
+/* Boundary data per face F (x-,x+,y-,y+,z-,z+) and component k:
+ *   kind TRACTION:     value is the traction component t_k on F (outward
+ *                      normal convention: sigma n = t).  It enters as the
+ *                      source (t_k / h_perp) * (mean of the 2^(d-1) cells that
+ *                      contain the node and touch F), Sec. 2.1.
+ *   kind DISPLACEMENT: the k-th displacement of every node of F is fixed to
+ *                      value.  Where several displacement faces meet, the last
+ *                      face in the order above wins. Displacement beats
+ *                      traction on shared edges. */
+typedef struct {
+  int kind[6][3];
+  double value[6][3];
+} sbm_bc;
+
+/* Isotropic Lame constants (Sec. 2.4) and the floor applied cell-wise to psi:
+ * psi = max(psi_raw, psi_floor). */
+typedef struct {
+  double lambda, mu, psi_floor;
+} sbm_material;
+
+/* Solver options (the paper leaves these open; defaults in brackets):
+ *   smoother       0 two-colour Gauss-Seidel [0], 1 damped Jacobi
+ *   omega          relaxation factor [1.0 for Gauss-Seidel, 0.8 for Jacobi]
+ *   nu_pre/post    smoothing sweeps per V-cycle leg [2, 2]
+ *   precision      0 FP64 cycles [0]; 1 FP32 cycles with FP64 residual,
+ *                  correction and bottom refinement
+ *   rtol           stop when ||f - K u||_2 <= rtol ||f||_2 over free DOF [1e-10]
+ *   max_cycles     V-cycle cap [200]
+ *   bottom_rtol    CG tolerance on the bottom grid, relative [1e-12]
+ *   bottom_max_iter CG iteration cap; <= 0 means 4 x free bottom DOF [0] */
+typedef struct {
+  int smoother;
+  double omega;
+  int nu_pre, nu_post;
+  int precision;
+  double rtol;
+  int max_cycles;
+  double bottom_rtol;
+  int bottom_max_iter;
+} sbm_options;
+
+/* Fills *opts with the defaults above. */
+void sbm_default_options(sbm_options *opts);
+
+/* Number of multigrid levels for a grid: the grid is halved while every
+ * active cell count is even and >= 4 (power-of-two grids, Sec. 3.3); the last
+ * level is the bottom.  Returns <= 0 for an invalid grid. */
+int sbm_num_levels(const sbm_grid *grid);
+
+/* Device workspace bytes needed by sbm_create for this grid (FP64 and FP32
+ * hierarchies, residual partial sums, bottom scratch).  0 on invalid input. */
+size_t sbm_workspace_bytes(const sbm_grid *grid, const sbm_options *opts);
+
+/* Creates a context.  workspace: device pointer, 256-byte aligned, at least
+ * sbm_workspace_bytes bytes, owned by the caller.  hip_stream: a hipStream_t
+ * (NULL = default stream).  The current HIP device must own the workspace. */
+sbm_status sbm_create(const sbm_grid *grid, const sbm_options *opts, void *workspace,
+                      size_t workspace_bytes, void *hip_stream, sbm_ctx **out);
+
+/* Replaces the solver options (same grid and workspace). */
+sbm_status sbm_set_options(sbm_ctx *ctx, const sbm_options *opts);
+
+/* Sets the problem (Sec. 2.1): psi_raw (cells, device) is floored, averaged
+ * down the hierarchy (coarse psi = mean of the 2^d children) and cast for the
+ * FP32 cycle; the load f = b + traction source (zero on displacement DOF) is
+ * assembled.  body_force (node vector, device) may be NULL.  The inputs are
+ * copied; the caller may free them afterwards.  Fails with SBM_E_NONFINITE on
+ * NaN/Inf in psi_raw or b, SBM_E_DIAG when a free DOF has no solid cell
+ * around it. */
+sbm_status sbm_set_problem(sbm_ctx *ctx, const double *psi_raw, const sbm_material *mat,
+                           const sbm_bc *bc, const double *body_force);
+
+/* Solves K u = f (Sec. 2.2, V-cycles until rtol).  u (node vector, device):
+ * in = initial guess (warm start, Sec. 3.2), out = solution; its displacement
+ * DOF are overwritten with the prescribed values.  res_hist_host receives the
+ * relative residuals rho_0 .. rho_m (at most hist_cap values; may be NULL),
+ * *n_cycles_host the number m of V-cycles run, *final_rel_res_host rho_m.
+ * Returns SBM_OK, SBM_NOT_CONVERGED, SBM_E_DIVERGED or SBM_E_NONFINITE. */
+sbm_status sbm_solve(sbm_ctx *ctx, double *u, double *res_hist_host, int hist_cap,
+                     int *n_cycles_host, double *final_rel_res_host);
+
+/* Solves K x = g on the free DOF with x = 0 on displacement DOF (the adjoint
+ * problem: K is symmetric).  g (node vector, device; its displacement DOF are
+ * ignored), x (device, in = guess, out = solution).  Same history outputs. */
+sbm_status sbm_solve_rhs(sbm_ctx *ctx, const double *g, double *x, double *res_hist_host,
+                         int hist_cap, int *n_cycles_host, double *final_rel_res_host);
+
+/* Ku = K u on every node of the finest grid (no boundary masking).  Async. */
+sbm_status sbm_apply(sbm_ctx *ctx, const double *u, double *Ku);
+
+/* r = f - K u on free DOF, 0 on displacement DOF (f from sbm_set_problem).
+ * If norm_host is non-NULL, *norm_host = ||r||_2 and the call synchronises;
+ * otherwise it is async.  r may be NULL when only the norm is wanted. */
+sbm_status sbm_residual(sbm_ctx *ctx, const double *u, double *r, double *norm_host);
+
+/* The assembled load of sbm_set_problem: fA (body force + traction source,
+ * 0 on displacement DOF) and, if fB is non-NULL, the lifted load
+ * fB = fA - K uD on free DOF (uD = prescribed values), whose norm normalises
+ * the residual.  Async. */
+sbm_status sbm_rhs(sbm_ctx *ctx, double *fA, double *fB);
+
+/* Adjoint sensitivity per cell: g_c = -lam_c^T K_c u_c + lam^T df/dpsi_c,
+ * where K = sum_c psi_c K_c and f depends on psi through the traction source.
+ * This is dL/dpsi for L(u(psi)) with K lam = dL/du.  u: node vector carrying
+ * its prescribed values; lam: node vector, must be 0 on displacement DOF; it
+ * is used as lam_scale * lam (Sec. 3.3's compliance J = h^d f.u is
+ * self-adjoint: lam = h^d u, i.e. lam = u and lam_scale = h^d).
+ * chain selects what g is differentiated with respect to:
+ *   SBM_CHAIN_PSI   (0): the floored psi; design may be NULL;
+ *   SBM_CHAIN_FLOOR (1): psi_raw (design = psi_raw cells): g where
+ *                        psi_raw > psi_floor, 0 elsewhere;
+ *   SBM_CHAIN_RHO3  (2): rho (design = rho cells, psi_raw = rho^3):
+ *                        3 rho^2 g where rho^3 > psi_floor, 0 elsewhere.
+ * g: cells.  Async. */
+typedef enum { SBM_CHAIN_PSI = 0, SBM_CHAIN_FLOOR = 1, SBM_CHAIN_RHO3 = 2 } sbm_chain;
+sbm_status sbm_sensitivity(sbm_ctx *ctx, const double *u, const double *lam, double lam_scale,
+                           const double *design, int chain, double *g);
+
+/* sbm_set_problem with psi_raw = rho^3 computed on the device from the
+ * density rho (cells): the stiffness interpolation of Sec. 3.3, whose
+ * (eta + zeta)^2 C becomes rho^3 C with the floor playing zeta^2. */
+sbm_status sbm_set_problem_density(sbm_ctx *ctx, const double *rho, const sbm_material *mat,
+                                   const sbm_bc *bc, const double *body_force);
+
+/* Compliance J = h^d sum over free DOF of fA . u (Sec. 3.3, the work of the
+ * load), written to *J_host; synchronises. */
+sbm_status sbm_compliance(sbm_ctx *ctx, const double *u, double *J_host);
+
+/* Live kernel timing.  While enabled, every finest-level launch of the
+ * classes below is bracketed by HIP events on the context's stream; the
+ * elapsed times are collected at the solve's per-cycle synchronisation.
+ * sbm_profile(ctx, 1) enables and clears, sbm_profile(ctx, 0) disables.
+ * sbm_profile_read fills ms_host[SBM_PROF_N] (total milliseconds) and
+ * count_host[SBM_PROF_N] (launches) per class. */
+typedef enum {
+  SBM_PROF_SMOOTH = 0,   /* smoother sweep / half-sweep on the finest level */
+  SBM_PROF_RESIDUAL = 1, /* residual feeding the restriction, finest level */
+  SBM_PROF_RESTRICT = 2, /* restriction from the finest level */
+  SBM_PROF_PROLONG = 3,  /* prolongation-add into the finest level */
+  SBM_PROF_NORM = 4,     /* convergence-test residual norm (+ FP32 cast) */
+  SBM_PROF_BOTTOM = 5,   /* whole bottom solve */
+  SBM_PROF_N = 6
+} sbm_prof_class;
+sbm_status sbm_profile(sbm_ctx *ctx, int enable);
+sbm_status sbm_profile_read(sbm_ctx *ctx, double *ms_host, int64_t *count_host);
+
+/* Releases host-side state; the workspace stays the caller's. */
+void sbm_destroy(sbm_ctx *ctx);
+
+/* Thread-local description of the last failure ("" if none). */
+const char *sbm_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Component entry points: one multigrid step at a time, on level l of the
+ * context's hierarchy (0 = finest), for parity checks of each kernel.  All
+ * arrays are device arrays in the level's layout; all calls are async.
+ * ---------------------------------------------------------------------- */
+
+/* Cells per axis of level l (ncell_host[3]; inactive axes 0). */
+sbm_status sbm_level_shape(sbm_ctx *ctx, int level, int64_t *ncell_host);
+
+/* The floored (level 0) or averaged (l > 0) psi of level l (FP64 cells). */
+sbm_status sbm_level_psi(sbm_ctx *ctx, int level, double *psi);
+
+/* Ku on level l (FP64), and the same operator evaluated in FP32 on the FP32
+ * psi copy. */
+sbm_status sbm_level_apply(sbm_ctx *ctx, int level, const double *u, double *Ku);
+sbm_status sbm_level_apply_f32(sbm_ctx *ctx, int level, const float *u, float *Ku);
+
+/* One smoothing step on level l, out of place (u_out != u_in):
+ * colour < 0: damped Jacobi sweep u_out = u + omega D^-1 (f - K u) (Sec. 2.3);
+ * colour 0/1: colour-synchronous Gauss-Seidel half-sweep updating the nodes
+ * with (x+y+z) mod 2 == colour from the state u_in, copying the others.
+ * Displacement DOF are copied unchanged. */
+sbm_status sbm_level_smooth(sbm_ctx *ctx, int level, int colour, double omega,
+                            const double *u_in, const double *f, double *u_out);
+
+/* r = f - K u on free DOF of level l, 0 on displacement DOF. */
+sbm_status sbm_level_residual(sbm_ctx *ctx, int level, const double *u, const double *f,
+                              double *r);
+
+/* f_coarse = P^T r_fine / 2^d from level l to l+1 (full weighting), 0 on
+ * coarse displacement DOF. */
+sbm_status sbm_level_restrict(sbm_ctx *ctx, int level, const double *r_fine, double *f_coarse);
+
+/* u_fine += P e_coarse from level l+1 to level l (multilinear), free DOF only. */
+sbm_status sbm_level_prolong_add(sbm_ctx *ctx, int level, const double *e_coarse,
+                                 double *u_fine);
+
+/* Bottom solve: x += CG solution of K_FF d = (f - K x)_F on the bottom level,
+ * with the context's bottom tolerance.  *iters_host (may be NULL) receives
+ * the iteration count (this call synchronises). */
+sbm_status sbm_bottom_solve(sbm_ctx *ctx, const double *f, double *x, int *iters_host);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SBM_H */

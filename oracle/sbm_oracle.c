@@ -166,43 +166,57 @@ static double grad_at(const grid_t *g, const double *u, int k, const long *n, in
          (2.0 * g->h[l]);
 }
 
-/* One row of eq. K: (Ku)_i at node n. */
-static double K_row(const grid_t *g, const psi_src *ps, const double *u, const long *n, int i) {
+/* All rows of eq. K at node n: out[i] = (Ku)_i(n), i < d.  The edge and face
+ * means of psi are evaluated once per node and shared by the rows. */
+static void K_node(const grid_t *g, const psi_src *ps, const double *u, const long *n,
+                   double *out) {
   const int d = g->dim;
-  double out = 0.0;
-  /* direct terms, j = l */
+  double pe[3][2];       /* psiE(n, -e_j), psiE(n, +e_j) */
+  double pf[3][3][2][2]; /* psiF for (j, l, sj, sl) */
   for (int j = 0; j < d; ++j) {
-    long np[3] = {n[0], n[1], n[2]}, nm[3] = {n[0], n[1], n[2]};
-    np[j] += 1;
-    nm[j] -= 1;
-    double pe_p = psi_edge(g, ps, n, j, +1);
-    double pe_m = psi_edge(g, ps, n, j, -1);
-    for (int k = 0; k < d; ++k) {
-      double Cc = g->C[i][j][k][j];
-      if (Cc == 0.0) continue;
-      double uc = u_at(g, u, k, n);
-      double flux = pe_p * (u_at(g, u, k, np) - uc) - pe_m * (uc - u_at(g, u, k, nm));
-      out -= Cc * flux / (g->h[j] * g->h[j]);
+    pe[j][0] = psi_edge(g, ps, n, j, -1);
+    pe[j][1] = psi_edge(g, ps, n, j, +1);
+    for (int l = 0; l < d; ++l) {
+      if (l == j) continue;
+      for (int sj = 0; sj < 2; ++sj)
+        for (int sl = 0; sl < 2; ++sl)
+          pf[j][l][sj][sl] = psi_face(g, ps, n, j, 2 * sj - 1, l, 2 * sl - 1);
     }
   }
-  /* cross terms, j != l */
-  for (int j = 0; j < d; ++j)
-    for (int l = 0; l < d; ++l) {
-      if (j == l) continue;
-      for (int sj = -1; sj <= 1; sj += 2)
-        for (int sl = -1; sl <= 1; sl += 2) {
-          double pf = psi_face(g, ps, n, j, sj, l, sl);
-          if (pf == 0.0) continue;
-          double acc = 0.0;
-          for (int k = 0; k < d; ++k) {
-            double Cc = g->C[i][j][k][l];
-            if (Cc == 0.0) continue;
-            acc += Cc * grad_at(g, u, k, n, j, sj, l, sl);
-          }
-          out -= sj * pf * acc / (2.0 * g->h[j]);
-        }
+  for (int i = 0; i < d; ++i) {
+    double acc = 0.0;
+    /* direct terms, j = l */
+    for (int j = 0; j < d; ++j) {
+      long np[3] = {n[0], n[1], n[2]}, nm[3] = {n[0], n[1], n[2]};
+      np[j] += 1;
+      nm[j] -= 1;
+      for (int k = 0; k < d; ++k) {
+        double Cc = g->C[i][j][k][j];
+        if (Cc == 0.0) continue;
+        double uc = u_at(g, u, k, n);
+        double flux = pe[j][1] * (u_at(g, u, k, np) - uc) - pe[j][0] * (uc - u_at(g, u, k, nm));
+        acc -= Cc * flux / (g->h[j] * g->h[j]);
+      }
     }
-  return out;
+    /* cross terms, j != l */
+    for (int j = 0; j < d; ++j)
+      for (int l = 0; l < d; ++l) {
+        if (j == l) continue;
+        for (int sj = -1; sj <= 1; sj += 2)
+          for (int sl = -1; sl <= 1; sl += 2) {
+            double f = pf[j][l][(sj + 1) / 2][(sl + 1) / 2];
+            if (f == 0.0) continue;
+            double gsum = 0.0;
+            for (int k = 0; k < d; ++k) {
+              double Cc = g->C[i][j][k][l];
+              if (Cc == 0.0) continue;
+              gsum += Cc * grad_at(g, u, k, n, j, sj, l, sl);
+            }
+            acc -= sj * f * gsum / (2.0 * g->h[j]);
+          }
+      }
+    out[i] = acc;
+  }
 }
 
 static void node_of(const grid_t *g, long id, long *n) {
@@ -257,8 +271,10 @@ void orc_apply(int dim, const long *nc, const double *h, double lam, double mu,
 #pragma omp parallel for schedule(static)
   for (long id = 0; id < g.NN; ++id) {
     long n[3];
+    double out[3];
     node_of(&g, id, n);
-    for (int i = 0; i < dim; ++i) Ku[(long)i * g.NN + id] = K_row(&g, &ps, u, n, i);
+    K_node(&g, &ps, u, n, out);
+    for (int i = 0; i < dim; ++i) Ku[(long)i * g.NN + id] = out[i];
   }
 }
 
@@ -277,6 +293,7 @@ void orc_diag(int dim, const long *nc, const double *h, double lam, double mu,
   grid_t g;
   grid_init(&g, dim, nc, h, lam, mu);
   psi_src ps = {psi, -1};
+#pragma omp parallel for schedule(static)
   for (long id = 0; id < g.NN; ++id) {
     long n[3];
     node_of(&g, id, n);
@@ -393,6 +410,7 @@ void orc_rb_half(int dim, const long *nc, const double *h, double lam, double mu
   double *D = (double *)malloc(sizeof(double) * n3);
   orc_residual(dim, nc, h, lam, mu, psi, mask, u, f, r);
   orc_diag(dim, nc, h, lam, mu, psi, D);
+#pragma omp parallel for schedule(static)
   for (long id = 0; id < g.NN; ++id) {
     long n[3];
     node_of(&g, id, n);
@@ -424,6 +442,7 @@ void orc_prolong_add(int dim, const long *nc_coarse, const double *e,
   long ncf[3] = {2 * nc_coarse[0], 2 * nc_coarse[1], dim > 2 ? 2 * nc_coarse[2] : 0};
   grid_init(&gc, dim, nc_coarse, h, 0, 0);
   grid_init(&gf, dim, ncf, h, 0, 0);
+#pragma omp parallel for schedule(static)
   for (long id = 0; id < gf.NN; ++id) {
     long n[3];
     node_of(&gf, id, n);
@@ -450,7 +469,8 @@ void orc_prolong_add(int dim, const long *nc_coarse, const double *e,
   }
 }
 
-/* f_coarse = (P^T r_fine) / 2^d, zero on coarse Dirichlet DOF. */
+/* f_coarse = (P^T r_fine) / 2^d, zero on coarse Dirichlet DOF:
+ * f_coarse(I) = 2^-d sum over fine nodes n of P(n, I) r(n). */
 void orc_restrict(int dim, const long *nc_fine, const double *r, const uint8_t *mask_coarse,
                   double *f_coarse) {
   grid_t gc, gf;
@@ -458,30 +478,33 @@ void orc_restrict(int dim, const long *nc_fine, const double *r, const uint8_t *
   long ncc[3] = {nc_fine[0] / 2, nc_fine[1] / 2, dim > 2 ? nc_fine[2] / 2 : 0};
   grid_init(&gc, dim, ncc, h, 0, 0);
   grid_init(&gf, dim, nc_fine, h, 0, 0);
-  memset(f_coarse, 0, sizeof(double) * dim * gc.NN);
-  /* accumulate P^T: every fine node scatters to the coarse nodes it interpolates from */
-  for (long id = 0; id < gf.NN; ++id) {
-    long n[3];
-    node_of(&gf, id, n);
+  double scale = 1.0 / (double)(1 << dim);
+#pragma omp parallel for schedule(static)
+  for (long cid = 0; cid < gc.NN; ++cid) {
+    long I[3];
+    node_of(&gc, cid, I);
+    /* the fine nodes with P(n, I) != 0 lie within one node of 2I */
     long lo[3], hi[3];
     for (int a = 0; a < 3; ++a) {
-      if (a < dim) { lo[a] = n[a] / 2; hi[a] = (n[a] + 1) / 2; }
+      if (a < dim) { lo[a] = 2 * I[a] - 1; hi[a] = 2 * I[a] + 1; }
       else { lo[a] = hi[a] = 0; }
     }
-    for (long I2 = lo[2]; I2 <= hi[2]; ++I2)
-      for (long I1 = lo[1]; I1 <= hi[1]; ++I1)
-        for (long I0 = lo[0]; I0 <= hi[0]; ++I0) {
-          long I[3] = {I0, I1, I2};
+    double acc[3] = {0, 0, 0};
+    for (long n2 = lo[2]; n2 <= hi[2]; ++n2)
+      for (long n1 = lo[1]; n1 <= hi[1]; ++n1)
+        for (long n0 = lo[0]; n0 <= hi[0]; ++n0) {
+          long n[3] = {n0, n1, n2};
+          if (!node_inside(&gf, n)) continue;
           double w = 1.0;
           for (int a = 0; a < dim; ++a) w *= p_weight_axis(n[a], I[a]);
-          long cid = node_id(&gc, I);
-          for (int k = 0; k < dim; ++k)
-            f_coarse[(long)k * gc.NN + cid] += w * r[(long)k * gf.NN + id];
+          long fid = node_id(&gf, n);
+          for (int k = 0; k < dim; ++k) acc[k] += w * r[(long)k * gf.NN + fid];
         }
+    for (int k = 0; k < dim; ++k) {
+      long q = (long)k * gc.NN + cid;
+      f_coarse[q] = mask_coarse[q] ? 0.0 : acc[k] * scale;
+    }
   }
-  double scale = 1.0 / (double)(1 << dim);
-  for (long q = 0; q < (long)dim * gc.NN; ++q)
-    f_coarse[q] = mask_coarse[q] ? 0.0 : f_coarse[q] * scale;
 }
 
 /* Coarse psi: mean of the 2^d child cells. */
@@ -704,7 +727,9 @@ void orc_sensitivity(int dim, const long *nc, const double *h, double lam_, doub
       for (int i = 0; i < dim; ++i) {
         double li = lam[(long)i * gr.NN + id];
         if (li == 0.0) continue;
-        acc -= li * K_row(&gr, &ps, u, n, i);
+        double row[3];
+        K_node(&gr, &ps, u, n, row);
+        acc -= li * row[i];
         /* traction source: face F of the box touched by cell c and containing n */
         for (int a = 0; a < dim; ++a)
           for (int side = 0; side < 2; ++side) {

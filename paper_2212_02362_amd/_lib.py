@@ -1,0 +1,113 @@
+"""ctypes declarations of the C ABI in include/sbm.h (argument marshalling only).
+
+The library is loaded from this package directory; there is no fallback: if
+``libsbm.so`` is missing the import of the solver fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsbm.so")
+
+SBM_OK = 0
+SBM_NOT_CONVERGED = 1
+STATUS_NAMES = {0: "SBM_OK", 1: "SBM_NOT_CONVERGED", -1: "SBM_E_ARG", -2: "SBM_E_SHAPE",
+                -3: "SBM_E_HIP", -4: "SBM_E_NONFINITE", -5: "SBM_E_DIVERGED", -6: "SBM_E_DIAG",
+                -7: "SBM_E_WORKSPACE"}
+TRACTION = 0
+DISPLACEMENT = 1
+CHAIN_PSI, CHAIN_FLOOR, CHAIN_RHO3 = 0, 1, 2
+PROF_CLASSES = ("smooth", "residual", "restrict", "prolong", "norm", "bottom")
+
+
+class SbmGrid(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("ncell", ctypes.c_int64 * 3), ("h", ctypes.c_double * 3)]
+
+
+class SbmBc(ctypes.Structure):
+    _fields_ = [("kind", (ctypes.c_int * 3) * 6), ("value", (ctypes.c_double * 3) * 6)]
+
+
+class SbmMaterial(ctypes.Structure):
+    _fields_ = [("lambda_", ctypes.c_double), ("mu", ctypes.c_double),
+                ("psi_floor", ctypes.c_double)]
+
+
+class SbmOptions(ctypes.Structure):
+    _fields_ = [("smoother", ctypes.c_int), ("omega", ctypes.c_double), ("nu_pre", ctypes.c_int),
+                ("nu_post", ctypes.c_int), ("precision", ctypes.c_int), ("rtol", ctypes.c_double),
+                ("max_cycles", ctypes.c_int), ("bottom_rtol", ctypes.c_double),
+                ("bottom_max_iter", ctypes.c_int)]
+
+
+_P = ctypes.c_void_p
+_DP = ctypes.POINTER(ctypes.c_double)
+_IP = ctypes.POINTER(ctypes.c_int)
+_I64P = ctypes.POINTER(ctypes.c_int64)
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "sbm_default_options": (None, [ctypes.POINTER(SbmOptions)]),
+    "sbm_num_levels": (ctypes.c_int, [ctypes.POINTER(SbmGrid)]),
+    "sbm_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(SbmGrid), ctypes.POINTER(SbmOptions)]),
+    "sbm_create": (ctypes.c_int, [ctypes.POINTER(SbmGrid), ctypes.POINTER(SbmOptions), _P,
+                                  ctypes.c_size_t, _P, ctypes.POINTER(_P)]),
+    "sbm_set_options": (ctypes.c_int, [_P, ctypes.POINTER(SbmOptions)]),
+    "sbm_set_problem": (ctypes.c_int, [_P, _P, ctypes.POINTER(SbmMaterial), ctypes.POINTER(SbmBc),
+                                       _P]),
+    "sbm_solve": (ctypes.c_int, [_P, _P, _DP, ctypes.c_int, _IP, _DP]),
+    "sbm_solve_rhs": (ctypes.c_int, [_P, _P, _P, _DP, ctypes.c_int, _IP, _DP]),
+    "sbm_apply": (ctypes.c_int, [_P, _P, _P]),
+    "sbm_residual": (ctypes.c_int, [_P, _P, _P, _DP]),
+    "sbm_rhs": (ctypes.c_int, [_P, _P, _P]),
+    "sbm_sensitivity": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, _P, ctypes.c_int, _P]),
+    "sbm_set_problem_density": (ctypes.c_int, [_P, _P, ctypes.POINTER(SbmMaterial),
+                                               ctypes.POINTER(SbmBc), _P]),
+    "sbm_compliance": (ctypes.c_int, [_P, _P, _DP]),
+    "sbm_profile": (ctypes.c_int, [_P, ctypes.c_int]),
+    "sbm_profile_read": (ctypes.c_int, [_P, _DP, _I64P]),
+    "sbm_destroy": (None, [_P]),
+    "sbm_last_error": (ctypes.c_char_p, []),
+    "sbm_level_shape": (ctypes.c_int, [_P, ctypes.c_int, _I64P]),
+    "sbm_level_psi": (ctypes.c_int, [_P, ctypes.c_int, _P]),
+    "sbm_level_apply": (ctypes.c_int, [_P, ctypes.c_int, _P, _P]),
+    "sbm_level_apply_f32": (ctypes.c_int, [_P, ctypes.c_int, _P, _P]),
+    "sbm_level_smooth": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_double, _P, _P,
+                                        _P]),
+    "sbm_level_residual": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P]),
+    "sbm_level_restrict": (ctypes.c_int, [_P, ctypes.c_int, _P, _P]),
+    "sbm_level_prolong_add": (ctypes.c_int, [_P, ctypes.c_int, _P, _P]),
+    "sbm_bottom_solve": (ctypes.c_int, [_P, _P, _P, _IP]),
+}
+
+_lib = None
+
+
+class SbmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def lib():
+    """Loads libsbm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(status, allow=(SBM_OK,)):
+    if status in allow:
+        return status
+    raise SbmError(status, lib().sbm_last_error().decode())

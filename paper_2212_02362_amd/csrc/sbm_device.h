@@ -1,0 +1,232 @@
+// sbm_device.h -- device-side building blocks of the gfx950 SBM multigrid:
+// level geometry, operator coefficients, the node stencil of K, Dirichlet
+// masks and deterministic block reductions.
+//
+// Operator (Agrawal & Runnels, Sec. 2.1 eq. SBMLinearElasticity with the
+// cell-based indicator of Sec. 2.3): K u = -div(psi C grad u), displacement on
+// nodes, psi on cells, psi = 0 outside the box.  In 2D/3D the divergence is
+// taken in split flux form:
+//   * direct part (derivative and flux along the same axis j): a 3-point
+//     flux difference whose edge coefficient is the mean psi of the 2^(d-1)
+//     cells around the edge;
+//   * cross part (flux along j of the l-derivative, j != l): evaluated on the
+//     four quadrants p = n + (sa e_a + sb e_b)/2 of each coordinate plane with
+//     the mean psi of the 2^(d-2) cells touching p.
+// For isotropic C the cross part of the quadrant (sa, sb) in plane (a, b)
+// reduces to
+//   row a -= sa sb Fsum [ cp (u_b(n+sa e_a+sb e_b) - u_b(n)) + cm (u_b(n+sb e_b) - u_b(n+sa e_a)) ]
+//   row b -= sa sb Fsum [ cp (u_a(n+sa e_a+sb e_b) - u_a(n)) + cm (u_a(n+sa e_a) - u_a(n+sb e_b)) ]
+// with cp = (lambda+mu)/(4 h_a h_b 2^(d-2)), cm = (lambda-mu)/(4 h_a h_b 2^(d-2))
+// and Fsum the plain sum of the touching cells; the direct part is
+//   row i -= sum_j cd_ij [ Esum(+j)(u_i(n+e_j)-u_i(n)) + Esum(-j)(u_i(n-e_j)-u_i(n)) ]
+// with cd_ij = (mu + (lambda+mu) delta_ij) / (h_j^2 2^(d-1)).  The diagonal
+// (Sec. 2.3, the Jacobi D) comes from the direct part only:
+//   D_i = sum_j cd_ij (Esum(+j) + Esum(-j)).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sbm {
+
+constexpr int kBlock = 256;  // threads per block of the node-parallel kernels
+
+struct Geom {
+  int dim;
+  int nx, ny, nz;   // nodes per axis (nz = 1 in 2D)
+  int cx, cy, cz;   // cells per axis (cz = 1 in 2D)
+  int64_t nn;       // nodes
+  int64_t nc;       // cells
+  uint32_t dmask;   // bit 3*F + k: face F fixes component k (F = x-,x+,y-,y+,z-,z+)
+};
+
+template <typename T>
+struct Coef {
+  T cd[3][3];  // direct coefficients
+  T cp[3];     // cross (lambda+mu) part, planes xy, xz, yz
+  T cm[3];     // cross (lambda-mu) part
+};
+
+__device__ __forceinline__ bool is_dirichlet(const Geom &g, int i, int j, int k, int comp) {
+  const uint32_t m = g.dmask >> comp;
+  bool d = ((i == 0) && (m & 1u)) || ((i == g.nx - 1) && ((m >> 3) & 1u)) ||
+           ((j == 0) && ((m >> 6) & 1u)) || ((j == g.ny - 1) && ((m >> 9) & 1u));
+  if (g.dim == 3) d = d || ((k == 0) && ((m >> 12) & 1u)) || ((k == g.nz - 1) && ((m >> 15) & 1u));
+  return d;
+}
+
+// Node coordinates of a linear node index.
+__device__ __forceinline__ void node_ijk(const Geom &g, int64_t id, int &i, int &j, int &k) {
+  const int64_t nxy = (int64_t)g.nx * g.ny;
+  k = (int)(id / nxy);
+  const int64_t rem = id - (int64_t)k * nxy;
+  j = (int)(rem / g.nx);
+  i = (int)(rem - (int64_t)j * g.nx);
+}
+
+// Evaluates (K u)(n) for all components and the diagonal at node (i, j, k).
+// Neighbour offsets are clamped at the box boundary: every term that would
+// reach outside carries a zero psi weight, so the clamped value never counts.
+template <typename T, int DIM>
+__device__ __forceinline__ void node_stencil(const Geom &g, const Coef<T> &C,
+                                             const T *__restrict__ psi,
+                                             const T *__restrict__ u, int i, int j, int k,
+                                             T out[3], T diag[3]) {
+  const int64_t sy = g.nx, sz = (int64_t)g.nx * g.ny;
+  const int64_t idx = i + sy * j + sz * k;
+  const int64_t ox[3] = {i > 0 ? -1 : 0, 0, i < g.nx - 1 ? 1 : 0};
+  const int64_t oy[3] = {j > 0 ? -sy : 0, 0, j < g.ny - 1 ? sy : 0};
+  const int64_t nn = g.nn;
+  if constexpr (DIM == 3) {
+    const int64_t oz[3] = {k > 0 ? -sz : 0, 0, k < g.nz - 1 ? sz : 0};
+    // cells around the node: P[oz][oy][ox] is cell (i-1+ox, j-1+oy, k-1+oz)
+    T P[2][2][2];
+#pragma unroll
+    for (int c2 = 0; c2 < 2; ++c2)
+#pragma unroll
+      for (int c1 = 0; c1 < 2; ++c1)
+#pragma unroll
+        for (int c0 = 0; c0 < 2; ++c0) {
+          const int xi = i - 1 + c0, yj = j - 1 + c1, zk = k - 1 + c2;
+          const bool in = xi >= 0 && xi < g.cx && yj >= 0 && yj < g.cy && zk >= 0 && zk < g.cz;
+          P[c2][c1][c0] = in ? psi[xi + (int64_t)g.cx * (yj + (int64_t)g.cy * zk)] : T(0);
+        }
+    T E[3][2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      E[0][s] = P[0][0][s] + P[0][1][s] + P[1][0][s] + P[1][1][s];
+      E[1][s] = P[0][s][0] + P[0][s][1] + P[1][s][0] + P[1][s][1];
+      E[2][s] = P[s][0][0] + P[s][0][1] + P[s][1][0] + P[s][1][1];
+    }
+    auto U = [&](int c, int dx, int dy, int dz) -> T {
+      return u[c * nn + idx + ox[dx + 1] + oy[dy + 1] + oz[dz + 1]];
+    };
+    // direct part
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const T uc = U(c, 0, 0, 0);
+      const T xp = U(c, 1, 0, 0) - uc, xm = U(c, -1, 0, 0) - uc;
+      const T yp = U(c, 0, 1, 0) - uc, ym = U(c, 0, -1, 0) - uc;
+      const T zp = U(c, 0, 0, 1) - uc, zm = U(c, 0, 0, -1) - uc;
+      out[c] = -(C.cd[c][0] * (E[0][1] * xp + E[0][0] * xm) +
+                 C.cd[c][1] * (E[1][1] * yp + E[1][0] * ym) +
+                 C.cd[c][2] * (E[2][1] * zp + E[2][0] * zm));
+      diag[c] = C.cd[c][0] * (E[0][0] + E[0][1]) + C.cd[c][1] * (E[1][0] + E[1][1]) +
+                C.cd[c][2] * (E[2][0] + E[2][1]);
+    }
+    // cross part, plane (a, b) with third axis m
+#pragma unroll
+    for (int pl = 0; pl < 3; ++pl) {
+      const int a = (pl == 2) ? 1 : 0;
+      const int b = (pl == 0) ? 1 : 2;
+      const T cp = C.cp[pl], cm = C.cm[pl];
+      const T ua0 = U(a, 0, 0, 0), ub0 = U(b, 0, 0, 0);
+      T ra = T(0), rb = T(0);
+#pragma unroll
+      for (int qa = 0; qa < 2; ++qa)
+#pragma unroll
+        for (int qb = 0; qb < 2; ++qb) {
+          const int sa = 2 * qa - 1, sb = 2 * qb - 1;
+          int da[3] = {0, 0, 0}, db[3] = {0, 0, 0};
+          da[a] = sa;
+          db[b] = sb;
+          T F;
+          if (pl == 0) F = P[0][qb][qa] + P[1][qb][qa];       // (x, y), m = z
+          else if (pl == 1) F = P[qb][0][qa] + P[qb][1][qa];  // (x, z), m = y
+          else F = P[qb][qa][0] + P[qb][qa][1];               // (y, z), m = x
+          const T w = (sa * sb > 0) ? F : -F;
+          const T uaab = U(a, da[0] + db[0], da[1] + db[1], da[2] + db[2]);
+          const T ubab = U(b, da[0] + db[0], da[1] + db[1], da[2] + db[2]);
+          const T uaa = U(a, da[0], da[1], da[2]), uab = U(a, db[0], db[1], db[2]);
+          const T uba = U(b, da[0], da[1], da[2]), ubb = U(b, db[0], db[1], db[2]);
+          ra += w * (cp * (ubab - ub0) + cm * (ubb - uba));
+          rb += w * (cp * (uaab - ua0) + cm * (uaa - uab));
+        }
+      out[a] -= ra;
+      out[b] -= rb;
+    }
+  } else {
+    T P[2][2];  // P[oy][ox]
+#pragma unroll
+    for (int c1 = 0; c1 < 2; ++c1)
+#pragma unroll
+      for (int c0 = 0; c0 < 2; ++c0) {
+        const int xi = i - 1 + c0, yj = j - 1 + c1;
+        const bool in = xi >= 0 && xi < g.cx && yj >= 0 && yj < g.cy;
+        P[c1][c0] = in ? psi[xi + (int64_t)g.cx * yj] : T(0);
+      }
+    T E[2][2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      E[0][s] = P[0][s] + P[1][s];
+      E[1][s] = P[s][0] + P[s][1];
+    }
+    auto U = [&](int c, int dx, int dy) -> T { return u[c * nn + idx + ox[dx + 1] + oy[dy + 1]]; };
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const T uc = U(c, 0, 0);
+      const T xp = U(c, 1, 0) - uc, xm = U(c, -1, 0) - uc;
+      const T yp = U(c, 0, 1) - uc, ym = U(c, 0, -1) - uc;
+      out[c] = -(C.cd[c][0] * (E[0][1] * xp + E[0][0] * xm) +
+                 C.cd[c][1] * (E[1][1] * yp + E[1][0] * ym));
+      diag[c] = C.cd[c][0] * (E[0][0] + E[0][1]) + C.cd[c][1] * (E[1][0] + E[1][1]);
+    }
+    const T cp = C.cp[0], cm = C.cm[0];
+    const T ux0 = U(0, 0, 0), uy0 = U(1, 0, 0);
+    T rx = T(0), ry = T(0);
+#pragma unroll
+    for (int qa = 0; qa < 2; ++qa)
+#pragma unroll
+      for (int qb = 0; qb < 2; ++qb) {
+        const int sa = 2 * qa - 1, sb = 2 * qb - 1;
+        const T F = P[qb][qa];
+        const T w = (sa * sb > 0) ? F : -F;
+        const T uxab = U(0, sa, sb), uyab = U(1, sa, sb);
+        const T uxa = U(0, sa, 0), uxb = U(0, 0, sb);
+        const T uya = U(1, sa, 0), uyb = U(1, 0, sb);
+        rx += w * (cp * (uyab - uy0) + cm * (uyb - uya));
+        ry += w * (cp * (uxab - ux0) + cm * (uxa - uxb));
+      }
+    out[0] -= rx;
+    out[1] -= ry;
+    out[2] = T(0);
+    diag[2] = T(0);
+  }
+}
+
+// Sum over a block of kBlock threads in a fixed order; the result is valid in
+// thread 0.  lds must hold kBlock/64 doubles.
+__device__ __forceinline__ double block_sum(double v, double *lds) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) lds[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    const int nw = blockDim.x >> 6;
+    for (int q = 0; q < nw; ++q) s += lds[q];
+  }
+  return s;
+}
+
+// Sum over the whole block, broadcast to every thread.  lds must hold
+// blockDim/64 + 1 doubles.
+__device__ __forceinline__ double block_allsum(double v, double *lds) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) lds[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    const int nw = blockDim.x >> 6;
+    for (int q = 0; q < nw; ++q) s += lds[q];
+    lds[nw] = s;
+  }
+  __syncthreads();
+  return lds[blockDim.x >> 6];
+}
+
+}  // namespace sbm

@@ -1,0 +1,89 @@
+// sbm_internal.h -- host-side declarations shared by the kernel launchers
+// (sbm_kernels.hip) and the solver / C ABI (sbm_solver.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "sbm_device.h"
+
+namespace sbm {
+
+// Traction source table: t[F][k] (0 where the face/component is not a
+// traction condition) and 1/h_perp per face.
+struct Traction {
+  double t[6][3];
+  double inv_h[6];
+};
+
+// Displacement values per face/component (used where dmask is set).
+struct DispValues {
+  double v[6][3];
+};
+
+struct Level {
+  Geom g;
+  double h[3];
+  Coef<double> c64;
+  Coef<float> c32;
+  double *psi64 = nullptr;
+  float *psi32 = nullptr;
+  // FP64 vectors: level 0 uses f (load), r (residual / ping-pong); coarse
+  // levels use e (correction), f (restricted residual), t (ping-pong / residual)
+  double *e = nullptr, *f = nullptr, *t = nullptr;
+  // FP32 vectors of the mixed cycle
+  float *e32 = nullptr, *f32 = nullptr, *t32 = nullptr;
+};
+
+// ---------------------------------------------------------------- launchers
+// All launchers enqueue on `st` and return the launch status.
+template <typename T>
+hipError_t launch_apply(const Level &L, const T *psi, const Coef<T> &C, const T *u, T *y,
+                        hipStream_t st);
+template <typename T>
+hipError_t launch_residual(const Level &L, const T *psi, const Coef<T> &C, const T *u,
+                           const T *f, T *r, double *partials, hipStream_t st);
+hipError_t launch_residual_cast(const Level &L, const double *u, const double *f, float *r32,
+                                double inv_s, hipStream_t st);
+template <typename T>
+hipError_t launch_jacobi(const Level &L, const T *psi, const Coef<T> &C, const T *u, const T *f,
+                         T *u_out, double omega, hipStream_t st);
+template <typename T>
+hipError_t launch_rb_half(const Level &L, const T *psi, const Coef<T> &C, const T *u,
+                          const T *f, T *u_out, double omega, int colour, hipStream_t st);
+template <typename T>
+hipError_t launch_restrict(const Level &F, const Level &Cl, const T *r, T *fc, hipStream_t st);
+template <typename T>
+hipError_t launch_prolong_add(const Level &F, const Level &Cl, const T *e, T *u, hipStream_t st);
+template <typename T>
+hipError_t launch_fill(T *p, int64_t n, T v, hipStream_t st);
+template <typename T>
+hipError_t launch_copy(const T *src, T *dst, int64_t n, hipStream_t st);
+hipError_t launch_correct(const Level &L, double *u, const float *e32, double s, hipStream_t st);
+hipError_t launch_set_dirichlet(const Level &L, double *u, const DispValues &dv, hipStream_t st);
+hipError_t launch_floor_psi(const double *raw, double floor_, double *psi64, float *psi32,
+                            int64_t n, int cube, int *flag, hipStream_t st);
+hipError_t launch_coarsen_psi(const Level &F, const Level &Cl, hipStream_t st);
+hipError_t launch_rhs(const Level &L, const Traction &tr, const double *b, double *fA, int *flag,
+                      hipStream_t st);
+hipError_t launch_check_diag(const Level &L, int *flag, hipStream_t st);
+hipError_t launch_finalize_sum(const double *partials, int n, double *out, hipStream_t st);
+hipError_t launch_dot_free(const Level &L, const double *a, const double *b, double *partials,
+                           hipStream_t st);
+hipError_t launch_sumsq_free(const Level &L, const double *v, double *partials, hipStream_t st);
+int num_blocks(int64_t n);
+template <typename T>
+hipError_t launch_bottom_cg(const Level &L, const T *psi, const Coef<T> &C, const T *f, T *x,
+                            T *r, T *p, T *Ap, double rtol, int maxit, int *iters,
+                            hipStream_t st);
+hipError_t launch_bottom_mixed(const Level &L, const float *b32, float *e32, double *x64,
+                               double *r64, float *r32, float *p32, float *Ap32, float *d32,
+                               double rtol, int maxit, int *iters, hipStream_t st);
+hipError_t launch_sensitivity(const Level &L, double lam, double mu, const Traction &tr,
+                              const double *u, const double *adj, double lam_scale,
+                              const double *design, int chain, double psi_floor, double *g,
+                              hipStream_t st);
+
+}  // namespace sbm

@@ -1,0 +1,875 @@
+// sbm_kernels.hip -- gfx950 kernels of the SBM elasticity multigrid and their
+// launchers.  Every kernel is a coalesced sweep over nodes or cells of one
+// level (HBM-bound stencils); reductions are deterministic two-pass block
+// sums; the bottom solve is a single-workgroup CG.
+#include <math.h>
+
+#include "sbm_internal.h"
+
+namespace sbm {
+
+int num_blocks(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
+
+// ------------------------------------------------------------------ apply --
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(kBlock) void k_apply(Geom g, Coef<T> C, const T *__restrict__ psi,
+                                                  const T *__restrict__ u, T *__restrict__ y) {
+  const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (id >= g.nn) return;
+  int i, j, k;
+  node_ijk(g, id, i, j, k);
+  T out[3], dg[3];
+  node_stencil<T, DIM>(g, C, psi, u, i, j, k, out, dg);
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) y[c * g.nn + id] = out[c];
+}
+
+// r = f - K u on free DOF (0 on displacement DOF); optional per-block sums of r^2.
+template <typename T, int DIM>
+__global__ __launch_bounds__(kBlock) void k_residual(Geom g, Coef<T> C, const T *__restrict__ psi,
+                                                     const T *__restrict__ u,
+                                                     const T *__restrict__ f, T *__restrict__ r,
+                                                     double *__restrict__ partials) {
+  __shared__ double lds[kBlock / 64 + 1];
+  const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  double ss = 0.0;
+  if (id < g.nn) {
+    int i, j, k;
+    node_ijk(g, id, i, j, k);
+    T out[3], dg[3];
+    node_stencil<T, DIM>(g, C, psi, u, i, j, k, out, dg);
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+      const int64_t q = c * g.nn + id;
+      const T v = is_dirichlet(g, i, j, k, c) ? T(0) : f[q] - out[c];
+      if (r) r[q] = v;
+      ss += (double)v * (double)v;
+    }
+  }
+  if (partials) {
+    const double s = block_sum(ss, lds);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  }
+}
+
+// r32 = fp32((f - K u) / s) on free DOF: the scaled residual handed to the
+// FP32 cycle of the mixed-precision solve.
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_residual_cast(Geom g, Coef<double> C,
+                                                          const double *__restrict__ psi,
+                                                          const double *__restrict__ u,
+                                                          const double *__restrict__ f,
+                                                          float *__restrict__ r32, double inv_s) {
+  const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (id >= g.nn) return;
+  int i, j, k;
+  node_ijk(g, id, i, j, k);
+  double out[3], dg[3];
+  node_stencil<double, DIM>(g, C, psi, u, i, j, k, out, dg);
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) {
+    const int64_t q = c * g.nn + id;
+    r32[q] = is_dirichlet(g, i, j, k, c) ? 0.0f : (float)((f[q] - out[c]) * inv_s);
+  }
+}
+
+// ------------------------------------------------------------- smoothers --
+
+// Damped Jacobi (Sec. 2.3): u_out = u + omega D^-1 (f - K u) on free DOF.
+template <typename T, int DIM>
+__global__ __launch_bounds__(kBlock) void k_jacobi(Geom g, Coef<T> C, const T *__restrict__ psi,
+                                                   const T *__restrict__ u,
+                                                   const T *__restrict__ f,
+                                                   T *__restrict__ u_out, T omega) {
+  const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (id >= g.nn) return;
+  int i, j, k;
+  node_ijk(g, id, i, j, k);
+  T out[3], dg[3];
+  node_stencil<T, DIM>(g, C, psi, u, i, j, k, out, dg);
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) {
+    const int64_t q = c * g.nn + id;
+    const T uc = u[q];
+    u_out[q] = is_dirichlet(g, i, j, k, c) ? uc : uc + omega * (f[q] - out[c]) / dg[c];
+  }
+}
+
+// Colour-synchronous Gauss-Seidel half-sweep: every node of the given colour
+// ((x+y+z) mod 2) is relaxed from the state at the start of the half-sweep,
+// all components together; nodes of the other colour are copied.  One thread
+// owns the x-pair (2p, 2p+1) of a row: one node of each colour.
+template <typename T, int DIM>
+__global__ __launch_bounds__(kBlock) void k_rb_half(Geom g, Coef<T> C, const T *__restrict__ psi,
+                                                    const T *__restrict__ u,
+                                                    const T *__restrict__ f,
+                                                    T *__restrict__ u_out, T omega, int colour) {
+  const int npx = (g.nx + 1) >> 1;
+  const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t total = (int64_t)npx * g.ny * g.nz;
+  if (tid >= total) return;
+  const int p = (int)(tid % npx);
+  const int64_t rest = tid / npx;
+  const int j = (int)(rest % g.ny);
+  const int k = (int)(rest / g.ny);
+  const int par = (colour + j + k) & 1;
+  const int iu = 2 * p + par, ic = 2 * p + 1 - par;
+  const int64_t row = (int64_t)g.nx * (j + (int64_t)g.ny * k);
+  if (ic < g.nx) {
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) u_out[c * g.nn + row + ic] = u[c * g.nn + row + ic];
+  }
+  if (iu < g.nx) {
+    T out[3], dg[3];
+    node_stencil<T, DIM>(g, C, psi, u, iu, j, k, out, dg);
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+      const int64_t q = c * g.nn + row + iu;
+      const T uc = u[q];
+      u_out[q] = is_dirichlet(g, iu, j, k, c) ? uc : uc + omega * (f[q] - out[c]) / dg[c];
+    }
+  }
+}
+
+// -------------------------------------------------------------- transfers --
+
+// f_coarse(I) = 2^-d sum_n P(n, I) r(n): full weighting [1/2, 1, 1/2] per axis
+// around the coincident fine node 2I; fine nodes outside the box are absent.
+template <typename T, int DIM>
+__global__ __launch_bounds__(kBlock) void k_restrict(Geom gf, Geom gc, const T *__restrict__ r,
+                                                     T *__restrict__ fc) {
+  const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (id >= gc.nn) return;
+  int I, J, K;
+  node_ijk(gc, id, I, J, K);
+  T acc[3] = {T(0), T(0), T(0)};
+  const int zlo = (DIM == 3) ? -1 : 0, zhi = (DIM == 3) ? 1 : 0;
+  for (int dz = zlo; dz <= zhi; ++dz) {
+    const int fk = 2 * K + dz;
+    if (fk < 0 || fk >= gf.nz) continue;
+    const T wz = dz == 0 ? T(1) : T(0.5);
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int fj = 2 * J + dy;
+      if (fj < 0 || fj >= gf.ny) continue;
+      const T wy = dy == 0 ? T(1) : T(0.5);
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int fi = 2 * I + dx;
+        if (fi < 0 || fi >= gf.nx) continue;
+        const T w = wz * wy * (dx == 0 ? T(1) : T(0.5));
+        const int64_t q = fi + (int64_t)gf.nx * (fj + (int64_t)gf.ny * fk);
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) acc[c] += w * r[c * gf.nn + q];
+      }
+    }
+  }
+  const T scale = (DIM == 3) ? T(0.125) : T(0.25);
+#pragma unroll
+  for (int c = 0; c < DIM; ++c)
+    fc[c * gc.nn + id] = is_dirichlet(gc, I, J, K, c) ? T(0) : acc[c] * scale;
+}
+
+// u_fine += P e_coarse (multilinear, node-centred) on free fine DOF.
+template <typename T, int DIM>
+__global__ __launch_bounds__(kBlock) void k_prolong_add(Geom gf, Geom gc, const T *__restrict__ e,
+                                                        T *__restrict__ u) {
+  const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (id >= gf.nn) return;
+  int i, j, k;
+  node_ijk(gf, id, i, j, k);
+  const int i0 = i >> 1, j0 = j >> 1, k0 = k >> 1;
+  const int ni = (i & 1) ? 2 : 1, nj = (j & 1) ? 2 : 1, nk = (DIM == 3 && (k & 1)) ? 2 : 1;
+  const T w = T(1) / T(ni * nj * nk);
+  T acc[3] = {T(0), T(0), T(0)};
+  for (int b = 0; b < nk; ++b)
+    for (int a = 0; a < nj; ++a)
+      for (int o = 0; o < ni; ++o) {
+        const int64_t q = (i0 + o) + (int64_t)gc.nx * ((j0 + a) + (int64_t)gc.ny * (k0 + b));
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) acc[c] += e[c * gc.nn + q];
+      }
+#pragma unroll
+  for (int c = 0; c < DIM; ++c)
+    if (!is_dirichlet(gf, i, j, k, c)) u[c * gf.nn + id] += w * acc[c];
+}
+
+// ----------------------------------------------------------------- vectors --
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fill(T *__restrict__ p, int64_t n, T v) {
+  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < n;
+       q += (int64_t)gridDim.x * kBlock)
+    p[q] = v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_copy(const T *__restrict__ s, T *__restrict__ d,
+                                                 int64_t n) {
+  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < n;
+       q += (int64_t)gridDim.x * kBlock)
+    d[q] = s[q];
+}
+
+// u += s * e32 on free DOF (FP64 correction of the mixed cycle).
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_correct(Geom g, double *__restrict__ u,
+                                                    const float *__restrict__ e32, double s) {
+  const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (id >= g.nn) return;
+  int i, j, k;
+  node_ijk(g, id, i, j, k);
+#pragma unroll
+  for (int c = 0; c < DIM; ++c)
+    if (!is_dirichlet(g, i, j, k, c)) u[c * g.nn + id] += s * (double)e32[c * g.nn + id];
+}
+
+// Displacement DOF take the value of the last fixing face (x-,x+,y-,y+,z-,z+).
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_set_dirichlet(Geom g, double *__restrict__ u,
+                                                          DispValues dv) {
+  const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (id >= g.nn) return;
+  int i, j, k;
+  node_ijk(g, id, i, j, k);
+  const int at[6] = {i == 0, i == g.nx - 1, j == 0, j == g.ny - 1,
+                     DIM == 3 && k == 0, DIM == 3 && k == g.nz - 1};
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) {
+    bool set = false;
+    double v = 0.0;
+#pragma unroll
+    for (int F = 0; F < 2 * DIM; ++F)
+      if (at[F] && ((g.dmask >> (3 * F + c)) & 1u)) {
+        set = true;
+        v = dv.v[F][c];
+      }
+    if (set) u[c * g.nn + id] = v;
+  }
+}
+
+// ------------------------------------------------------------------- setup --
+
+// psi = max(raw, floor) (raw = rho^3 when cube is set), plus its FP32 copy.
+// raw may alias p64.
+__global__ __launch_bounds__(kBlock) void k_floor_psi(const double *raw, double fl, double *p64,
+                                                      float *__restrict__ p32, int64_t n,
+                                                      int cube, int *flag) {
+  const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (q >= n) return;
+  double v = raw[q];
+  if (cube) v = v * v * v;
+  if (!isfinite(v)) atomicOr(flag, 1);
+  const double p = v > fl ? v : fl;
+  p64[q] = p;
+  p32[q] = (float)p;
+}
+
+// Coarse psi = mean of the 2^d child cells (FP64), plus its FP32 copy.
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_coarsen_psi(Geom gf, Geom gc,
+                                                        const double *__restrict__ pf,
+                                                        double *__restrict__ pc,
+                                                        float *__restrict__ pc32) {
+  const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (id >= gc.nc) return;
+  const int64_t cxy = (int64_t)gc.cx * gc.cy;
+  const int K = (int)(id / cxy);
+  const int64_t rem = id - (int64_t)K * cxy;
+  const int J = (int)(rem / gc.cx), I = (int)(rem - (int64_t)J * gc.cx);
+  double s = 0.0;
+  for (int o = 0; o < (1 << DIM); ++o) {
+    const int fi = 2 * I + (o & 1), fj = 2 * J + ((o >> 1) & 1);
+    const int fk = (DIM == 3) ? 2 * K + ((o >> 2) & 1) : 0;
+    s += pf[fi + (int64_t)gf.cx * (fj + (int64_t)gf.cy * fk)];
+  }
+  const double m = s / (double)(1 << DIM);
+  pc[id] = m;
+  pc32[id] = (float)m;
+}
+
+// Load: f = b + sum over traction faces F containing the node of
+// (t_F / h_perp) * (mean of the 2^(d-1) cells that contain the node and touch
+// F); 0 on displacement DOF.
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_rhs(Geom g, Traction tr, const double *__restrict__ psi,
+                                                const double *__restrict__ b,
+                                                double *__restrict__ fA, int *flag) {
+  const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (id >= g.nn) return;
+  int n[3];
+  node_ijk(g, id, n[0], n[1], n[2]);
+  const int nn_[3] = {g.nx, g.ny, g.nz};
+  const int nc_[3] = {g.cx, g.cy, g.cz};
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) {
+    const int64_t q = c * g.nn + id;
+    if (is_dirichlet(g, n[0], n[1], n[2], c)) {
+      fA[q] = 0.0;
+      continue;
+    }
+    double f = 0.0;
+    if (b) {
+      f = b[q];
+      if (!isfinite(f)) atomicOr(flag, 1);
+    }
+    for (int a = 0; a < DIM; ++a)
+      for (int side = 0; side < 2; ++side) {
+        const int F = 2 * a + side;
+        const double t = tr.t[F][c];
+        if (t == 0.0) continue;
+        if (n[a] != (side ? nn_[a] - 1 : 0)) continue;
+        // the other axes' cells around the node
+        const int o1 = (a == 0) ? 1 : 0;
+        const int o2 = (a == 2) ? 1 : 2;
+        const int ca = side ? nc_[a] - 1 : 0;
+        double s = 0.0;
+        const int nb = (DIM == 3) ? 4 : 2;
+        for (int o = 0; o < nb; ++o) {
+          int cc[3];
+          cc[a] = ca;
+          cc[o1] = n[o1] - 1 + (o & 1);
+          if (DIM == 3) cc[o2] = n[o2] - 1 + ((o >> 1) & 1);
+          else cc[2] = 0;
+          bool in = cc[o1] >= 0 && cc[o1] < nc_[o1];
+          if (DIM == 3) in = in && cc[o2] >= 0 && cc[o2] < nc_[o2];
+          if (in) s += psi[cc[0] + (int64_t)g.cx * (cc[1] + (int64_t)g.cy * cc[2])];
+        }
+        f += t * tr.inv_h[F] * (s / nb);
+      }
+    fA[q] = f;
+  }
+}
+
+// Flags a free DOF whose diagonal vanishes (no solid cell around it).
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_check_diag(Geom g, const double *__restrict__ psi,
+                                                       int *flag) {
+  const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (id >= g.nn) return;
+  int i, j, k;
+  node_ijk(g, id, i, j, k);
+  double s = 0.0;
+  for (int o = 0; o < (1 << DIM); ++o) {
+    const int xi = i - 1 + (o & 1), yj = j - 1 + ((o >> 1) & 1);
+    const int zk = (DIM == 3) ? k - 1 + ((o >> 2) & 1) : 0;
+    const bool in = xi >= 0 && xi < g.cx && yj >= 0 && yj < g.cy && zk >= 0 && zk < g.cz;
+    if (in) s += psi[xi + (int64_t)g.cx * (yj + (int64_t)g.cy * zk)];
+  }
+  if (s > 0.0) return;
+  for (int c = 0; c < DIM; ++c)
+    if (!is_dirichlet(g, i, j, k, c)) atomicOr(flag, 2);
+}
+
+// ------------------------------------------------------------ reductions --
+
+// Deterministic sum of n partials by one block of 1024 threads.
+__global__ __launch_bounds__(1024) void k_finalize_sum(const double *__restrict__ partials, int n,
+                                                       double *__restrict__ out) {
+  __shared__ double lds[1024 / 64 + 1];
+  double s = 0.0;
+  for (int q = threadIdx.x; q < n; q += 1024) s += partials[q];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < 16; ++w) t += lds[w];
+    *out = t;
+  }
+}
+
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_sumsq_free(Geom g, const double *__restrict__ v,
+                                                       double *__restrict__ partials) {
+  __shared__ double lds[kBlock / 64 + 1];
+  const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  double ss = 0.0;
+  if (id < g.nn) {
+    int i, j, k;
+    node_ijk(g, id, i, j, k);
+#pragma unroll
+    for (int c = 0; c < DIM; ++c)
+      if (!is_dirichlet(g, i, j, k, c)) {
+        const double x = v[c * g.nn + id];
+        ss += x * x;
+      }
+  }
+  const double s = block_sum(ss, lds);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_dot_free(Geom g, const double *__restrict__ a,
+                                                     const double *__restrict__ b,
+                                                     double *__restrict__ partials) {
+  __shared__ double lds[kBlock / 64 + 1];
+  const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  double ss = 0.0;
+  if (id < g.nn) {
+    int i, j, k;
+    node_ijk(g, id, i, j, k);
+#pragma unroll
+    for (int c = 0; c < DIM; ++c)
+      if (!is_dirichlet(g, i, j, k, c)) ss += a[c * g.nn + id] * b[c * g.nn + id];
+  }
+  const double s = block_sum(ss, lds);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// ----------------------------------------------------------------- bottom --
+
+constexpr int kBottomThreads = 1024;
+
+// CG on the free DOF, one workgroup.  On entry r holds the initial residual
+// (0 on displacement DOF) and x the initial iterate; returns the iterations.
+// Dot products are accumulated in FP64 whatever T is.
+template <typename T, int DIM>
+__device__ int cg_core(const Geom &g, const Coef<T> &C, const T *__restrict__ psi, T *x, T *r,
+                       T *p, T *Ap, double rtol, int maxit, double *lds) {
+  const int64_t n = g.nn;
+  double loc = 0.0;
+  for (int64_t id = threadIdx.x; id < n; id += blockDim.x)
+    for (int c = 0; c < DIM; ++c) {
+      const T v = r[c * n + id];
+      p[c * n + id] = v;
+      loc += (double)v * (double)v;
+    }
+  double rr = block_allsum(loc, lds);
+  const double r0 = sqrt(rr);
+  int it = 0;
+  while (r0 > 0.0 && sqrt(rr) > rtol * r0 && it < maxit) {
+    __syncthreads();
+    double pap = 0.0;
+    for (int64_t id = threadIdx.x; id < n; id += blockDim.x) {
+      int i, j, k;
+      node_ijk(g, id, i, j, k);
+      T out[3], dg[3];
+      node_stencil<T, DIM>(g, C, psi, p, i, j, k, out, dg);
+      for (int c = 0; c < DIM; ++c) {
+        const T a = is_dirichlet(g, i, j, k, c) ? T(0) : out[c];
+        Ap[c * n + id] = a;
+        pap += (double)p[c * n + id] * (double)a;
+      }
+    }
+    pap = block_allsum(pap, lds);
+    if (!(pap > 0.0)) break;
+    const double alpha = rr / pap;
+    double rn = 0.0;
+    for (int64_t id = threadIdx.x; id < n; id += blockDim.x) {
+      int i, j, k;
+      node_ijk(g, id, i, j, k);
+      for (int c = 0; c < DIM; ++c) {
+        if (is_dirichlet(g, i, j, k, c)) continue;
+        const int64_t q = c * n + id;
+        x[q] = (T)((double)x[q] + alpha * (double)p[q]);
+        const T rv = (T)((double)r[q] - alpha * (double)Ap[q]);
+        r[q] = rv;
+        rn += (double)rv * (double)rv;
+      }
+    }
+    rn = block_allsum(rn, lds);
+    const double beta = rn / rr;
+    rr = rn;
+    __syncthreads();
+    for (int64_t id = threadIdx.x; id < n; id += blockDim.x) {
+      int i, j, k;
+      node_ijk(g, id, i, j, k);
+      for (int c = 0; c < DIM; ++c) {
+        const int64_t q = c * n + id;
+        p[q] = is_dirichlet(g, i, j, k, c) ? T(0) : (T)((double)r[q] + beta * (double)p[q]);
+      }
+    }
+    ++it;
+  }
+  __syncthreads();
+  return it;
+}
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(kBottomThreads) void k_bottom_cg(Geom g, Coef<T> C,
+                                                              const T *__restrict__ psi,
+                                                              const T *__restrict__ f, T *x, T *r,
+                                                              T *p, T *Ap, double rtol, int maxit,
+                                                              int *iters) {
+  __shared__ double lds[kBottomThreads / 64 + 1];
+  const int64_t n = g.nn;
+  for (int64_t id = threadIdx.x; id < n; id += blockDim.x) {
+    int i, j, k;
+    node_ijk(g, id, i, j, k);
+    T out[3], dg[3];
+    node_stencil<T, DIM>(g, C, psi, x, i, j, k, out, dg);
+    for (int c = 0; c < DIM; ++c) {
+      const int64_t q = c * n + id;
+      r[q] = is_dirichlet(g, i, j, k, c) ? T(0) : f[q] - out[c];
+    }
+  }
+  __syncthreads();
+  const int it = cg_core<T, DIM>(g, C, psi, x, r, p, Ap, rtol, maxit, lds);
+  if (threadIdx.x == 0 && iters) *iters = it;
+}
+
+// Bottom solve of the mixed cycle: FP32 CG inside FP64 iterative refinement.
+// x64 accumulates the solution of K x = b (b = FP32 bottom load) until the
+// FP64 residual meets rtol; the result is returned in e32.
+template <int DIM>
+__global__ __launch_bounds__(kBottomThreads) void k_bottom_mixed(
+    Geom g, Coef<double> C64, Coef<float> C32, const double *__restrict__ psi64,
+    const float *__restrict__ psi32, const float *__restrict__ b32, float *e32, double *x64,
+    double *r64, float *r32, float *p32, float *Ap32, float *d32, double rtol, int maxit,
+    int *iters) {
+  __shared__ double lds[kBottomThreads / 64 + 1];
+  const int64_t n = g.nn;
+  double loc = 0.0;
+  for (int64_t id = threadIdx.x; id < n; id += blockDim.x) {
+    int i, j, k;
+    node_ijk(g, id, i, j, k);
+    for (int c = 0; c < DIM; ++c) {
+      x64[c * n + id] = 0.0;
+      if (!is_dirichlet(g, i, j, k, c)) loc += (double)b32[c * n + id] * (double)b32[c * n + id];
+    }
+  }
+  const double bnorm = sqrt(block_allsum(loc, lds));
+  int total = 0;
+  for (int outer = 0; outer < 40 && bnorm > 0.0; ++outer) {
+    __syncthreads();
+    double rl = 0.0;
+    for (int64_t id = threadIdx.x; id < n; id += blockDim.x) {
+      int i, j, k;
+      node_ijk(g, id, i, j, k);
+      double out[3], dg[3];
+      node_stencil<double, DIM>(g, C64, psi64, x64, i, j, k, out, dg);
+      for (int c = 0; c < DIM; ++c) {
+        const int64_t q = c * n + id;
+        const double v = is_dirichlet(g, i, j, k, c) ? 0.0 : (double)b32[q] - out[c];
+        r64[q] = v;
+        rl += v * v;
+      }
+    }
+    const double rn = sqrt(block_allsum(rl, lds));
+    if (rn <= rtol * bnorm || total >= maxit) break;
+    for (int64_t id = threadIdx.x; id < n; id += blockDim.x)
+      for (int c = 0; c < DIM; ++c) {
+        const int64_t q = c * n + id;
+        r32[q] = (float)(r64[q] / rn);
+        d32[q] = 0.0f;
+      }
+    __syncthreads();
+    total += cg_core<float, DIM>(g, C32, psi32, d32, r32, p32, Ap32, 1e-5, maxit - total, lds);
+    for (int64_t id = threadIdx.x; id < n; id += blockDim.x)
+      for (int c = 0; c < DIM; ++c) {
+        const int64_t q = c * n + id;
+        x64[q] += rn * (double)d32[q];
+      }
+  }
+  __syncthreads();
+  for (int64_t id = threadIdx.x; id < n; id += blockDim.x)
+    for (int c = 0; c < DIM; ++c) e32[c * n + id] = (float)x64[c * n + id];
+  if (threadIdx.x == 0 && iters) *iters = total;
+}
+
+// ------------------------------------------------------------ sensitivity --
+
+// g_c = -lam_c^T K_c u_c + lam^T df/dpsi_c per cell, with K_c in energy form:
+//   edges (1/2^(d-1) each): sum_i a_ij / h_j^2 (d lam_i)(d u_i), a_ij = mu + (lam+mu) delta_ij
+//   faces of the cell (3D: 1/2 each; 2D: the cell itself), plane (a, b):
+//     lame (da lam_a db u_b + db lam_b da u_a) + mu (db lam_a da u_b + da lam_b db u_a)
+//   with face-centre derivatives averaged over the face's two edges.
+// lam enters scaled by lam_scale.  chain 1: g masked where the raw psi
+// (design) is at or below the floor; chain 2: dL/drho = 3 rho^2 g where
+// rho^3 > floor, else 0 (design = rho).
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_sensitivity(Geom g, double lame, double mu,
+                                                        double h0, double h1, double h2,
+                                                        Traction tr, const double *__restrict__ u,
+                                                        const double *__restrict__ adj,
+                                                        double lam_scale,
+                                                        const double *__restrict__ design,
+                                                        int chain, double fl,
+                                                        double *__restrict__ out) {
+  const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (id >= g.nc) return;
+  const int64_t cxy = (int64_t)g.cx * g.cy;
+  const int ck = (int)(id / cxy);
+  const int64_t rem = id - (int64_t)ck * cxy;
+  const int cj = (int)(rem / g.cx), ci = (int)(rem - (int64_t)cj * g.cx);
+  constexpr int NCO = 1 << DIM;
+  double U[3][NCO], A[3][NCO];
+#pragma unroll
+  for (int o = 0; o < NCO; ++o) {
+    const int64_t node = (ci + (o & 1)) + (int64_t)g.nx * ((cj + ((o >> 1) & 1)) +
+                                                            (int64_t)g.ny * (ck + ((o >> 2) & 1)));
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+      U[c][o] = u[c * g.nn + node];
+      A[c][o] = adj[c * g.nn + node];
+    }
+  }
+  const double h[3] = {h0, h1, h2};
+  const double we = 1.0 / (double)(1 << (DIM - 1));
+  double acc = 0.0;
+  // direct (edge) part
+#pragma unroll
+  for (int jx = 0; jx < DIM; ++jx) {
+    const double ih2 = 1.0 / (h[jx] * h[jx]);
+#pragma unroll
+    for (int o = 0; o < NCO; ++o) {
+      if ((o >> jx) & 1) continue;
+      const int o2 = o | (1 << jx);
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) {
+        const double a = mu + (lame + mu) * (c == jx ? 1.0 : 0.0);
+        acc += we * a * ih2 * (A[c][o2] - A[c][o]) * (U[c][o2] - U[c][o]);
+      }
+    }
+  }
+  // cross (face) part
+  const double wf = (DIM == 3) ? 0.5 : 1.0;
+  const int nfaces = (DIM == 3) ? 6 : 1;
+#pragma unroll
+  for (int fidx = 0; fidx < nfaces; ++fidx) {
+    int a, b, m = -1, sm = 0;
+    if (DIM == 3) {
+      m = fidx >> 1;
+      sm = fidx & 1;
+      a = (m == 0) ? 1 : 0;
+      b = (m == 2) ? 1 : 2;
+    } else {
+      a = 0;
+      b = 1;
+    }
+    // corner index of face point (alpha, beta)
+    auto cidx = [&](int al, int be) {
+      int o = (al << a) | (be << b);
+      if (m >= 0) o |= (sm << m);
+      return o;
+    };
+    const int o00 = cidx(0, 0), o10 = cidx(1, 0), o01 = cidx(0, 1), o11 = cidx(1, 1);
+    auto da = [&](const double (*V)[NCO], int c) {
+      return ((V[c][o10] - V[c][o00]) + (V[c][o11] - V[c][o01])) / (2.0 * h[a]);
+    };
+    auto db = [&](const double (*V)[NCO], int c) {
+      return ((V[c][o01] - V[c][o00]) + (V[c][o11] - V[c][o10])) / (2.0 * h[b]);
+    };
+    const double e = lame * (da(A, a) * db(U, b) + db(A, b) * da(U, a)) +
+                     mu * (db(A, a) * da(U, b) + da(A, b) * db(U, a));
+    acc += wf * e;
+  }
+  double gval = -acc;
+  // traction source: df_n/dpsi_c = t / h_perp / 2^(d-1) on the corners n of c
+  // lying on a traction face that c touches
+  const int cc[3] = {ci, cj, ck};
+  const int ncx[3] = {g.cx, g.cy, g.cz};
+#pragma unroll
+  for (int ax = 0; ax < DIM; ++ax)
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      if (cc[ax] != (side ? ncx[ax] - 1 : 0)) continue;
+      const int F = 2 * ax + side;
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) {
+        const double t = tr.t[F][c];
+        if (t == 0.0) continue;
+        double s = 0.0;
+#pragma unroll
+        for (int o = 0; o < NCO; ++o)
+          if (((o >> ax) & 1) == side) s += A[c][o];
+        gval += s * t * tr.inv_h[F] * we;
+      }
+    }
+  gval *= lam_scale;
+  if (chain == 1) {
+    gval = design[id] > fl ? gval : 0.0;
+  } else if (chain == 2) {
+    const double rv = design[id];
+    gval = (rv * rv * rv > fl) ? 3.0 * rv * rv * gval : 0.0;
+  }
+  out[id] = gval;
+}
+
+// ---------------------------------------------------------------- launchers --
+
+#define SBM_LAUNCH(kern, grid, block, st, ...)                         \
+  do {                                                                 \
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, st, __VA_ARGS__); \
+    return hipGetLastError();                                          \
+  } while (0)
+
+static int fill_blocks(int64_t n) {
+  const int64_t b = (n + kBlock - 1) / kBlock;
+  return (int)(b < 65536 ? (b > 0 ? b : 1) : 65536);
+}
+
+template <typename T>
+hipError_t launch_apply(const Level &L, const T *psi, const Coef<T> &C, const T *u, T *y,
+                        hipStream_t st) {
+  if (L.g.dim == 3) SBM_LAUNCH((k_apply<T, 3>), num_blocks(L.g.nn), kBlock, st, L.g, C, psi, u, y);
+  SBM_LAUNCH((k_apply<T, 2>), num_blocks(L.g.nn), kBlock, st, L.g, C, psi, u, y);
+}
+
+template <typename T>
+hipError_t launch_residual(const Level &L, const T *psi, const Coef<T> &C, const T *u,
+                           const T *f, T *r, double *partials, hipStream_t st) {
+  if (L.g.dim == 3)
+    SBM_LAUNCH((k_residual<T, 3>), num_blocks(L.g.nn), kBlock, st, L.g, C, psi, u, f, r, partials);
+  SBM_LAUNCH((k_residual<T, 2>), num_blocks(L.g.nn), kBlock, st, L.g, C, psi, u, f, r, partials);
+}
+
+hipError_t launch_residual_cast(const Level &L, const double *u, const double *f, float *r32,
+                                double inv_s, hipStream_t st) {
+  if (L.g.dim == 3)
+    SBM_LAUNCH((k_residual_cast<3>), num_blocks(L.g.nn), kBlock, st, L.g, L.c64, L.psi64, u, f,
+               r32, inv_s);
+  SBM_LAUNCH((k_residual_cast<2>), num_blocks(L.g.nn), kBlock, st, L.g, L.c64, L.psi64, u, f, r32,
+             inv_s);
+}
+
+template <typename T>
+hipError_t launch_jacobi(const Level &L, const T *psi, const Coef<T> &C, const T *u, const T *f,
+                         T *u_out, double omega, hipStream_t st) {
+  if (L.g.dim == 3)
+    SBM_LAUNCH((k_jacobi<T, 3>), num_blocks(L.g.nn), kBlock, st, L.g, C, psi, u, f, u_out,
+               (T)omega);
+  SBM_LAUNCH((k_jacobi<T, 2>), num_blocks(L.g.nn), kBlock, st, L.g, C, psi, u, f, u_out, (T)omega);
+}
+
+template <typename T>
+hipError_t launch_rb_half(const Level &L, const T *psi, const Coef<T> &C, const T *u,
+                          const T *f, T *u_out, double omega, int colour, hipStream_t st) {
+  const int64_t pairs = (int64_t)((L.g.nx + 1) / 2) * L.g.ny * L.g.nz;
+  if (L.g.dim == 3)
+    SBM_LAUNCH((k_rb_half<T, 3>), num_blocks(pairs), kBlock, st, L.g, C, psi, u, f, u_out,
+               (T)omega, colour);
+  SBM_LAUNCH((k_rb_half<T, 2>), num_blocks(pairs), kBlock, st, L.g, C, psi, u, f, u_out, (T)omega,
+             colour);
+}
+
+template <typename T>
+hipError_t launch_restrict(const Level &F, const Level &Cl, const T *r, T *fc, hipStream_t st) {
+  if (F.g.dim == 3) SBM_LAUNCH((k_restrict<T, 3>), num_blocks(Cl.g.nn), kBlock, st, F.g, Cl.g, r, fc);
+  SBM_LAUNCH((k_restrict<T, 2>), num_blocks(Cl.g.nn), kBlock, st, F.g, Cl.g, r, fc);
+}
+
+template <typename T>
+hipError_t launch_prolong_add(const Level &F, const Level &Cl, const T *e, T *u, hipStream_t st) {
+  if (F.g.dim == 3)
+    SBM_LAUNCH((k_prolong_add<T, 3>), num_blocks(F.g.nn), kBlock, st, F.g, Cl.g, e, u);
+  SBM_LAUNCH((k_prolong_add<T, 2>), num_blocks(F.g.nn), kBlock, st, F.g, Cl.g, e, u);
+}
+
+template <typename T>
+hipError_t launch_fill(T *p, int64_t n, T v, hipStream_t st) {
+  SBM_LAUNCH((k_fill<T>), fill_blocks(n), kBlock, st, p, n, v);
+}
+
+template <typename T>
+hipError_t launch_copy(const T *src, T *dst, int64_t n, hipStream_t st) {
+  SBM_LAUNCH((k_copy<T>), fill_blocks(n), kBlock, st, src, dst, n);
+}
+
+hipError_t launch_correct(const Level &L, double *u, const float *e32, double s, hipStream_t st) {
+  if (L.g.dim == 3) SBM_LAUNCH((k_correct<3>), num_blocks(L.g.nn), kBlock, st, L.g, u, e32, s);
+  SBM_LAUNCH((k_correct<2>), num_blocks(L.g.nn), kBlock, st, L.g, u, e32, s);
+}
+
+hipError_t launch_set_dirichlet(const Level &L, double *u, const DispValues &dv, hipStream_t st) {
+  if (L.g.dim == 3) SBM_LAUNCH((k_set_dirichlet<3>), num_blocks(L.g.nn), kBlock, st, L.g, u, dv);
+  SBM_LAUNCH((k_set_dirichlet<2>), num_blocks(L.g.nn), kBlock, st, L.g, u, dv);
+}
+
+hipError_t launch_floor_psi(const double *raw, double floor_, double *psi64, float *psi32,
+                            int64_t n, int cube, int *flag, hipStream_t st) {
+  SBM_LAUNCH(k_floor_psi, num_blocks(n), kBlock, st, raw, floor_, psi64, psi32, n, cube, flag);
+}
+
+hipError_t launch_coarsen_psi(const Level &F, const Level &Cl, hipStream_t st) {
+  if (F.g.dim == 3)
+    SBM_LAUNCH((k_coarsen_psi<3>), num_blocks(Cl.g.nc), kBlock, st, F.g, Cl.g, F.psi64, Cl.psi64,
+               Cl.psi32);
+  SBM_LAUNCH((k_coarsen_psi<2>), num_blocks(Cl.g.nc), kBlock, st, F.g, Cl.g, F.psi64, Cl.psi64,
+             Cl.psi32);
+}
+
+hipError_t launch_rhs(const Level &L, const Traction &tr, const double *b, double *fA, int *flag,
+                      hipStream_t st) {
+  if (L.g.dim == 3) SBM_LAUNCH((k_rhs<3>), num_blocks(L.g.nn), kBlock, st, L.g, tr, L.psi64, b, fA, flag);
+  SBM_LAUNCH((k_rhs<2>), num_blocks(L.g.nn), kBlock, st, L.g, tr, L.psi64, b, fA, flag);
+}
+
+hipError_t launch_check_diag(const Level &L, int *flag, hipStream_t st) {
+  if (L.g.dim == 3) SBM_LAUNCH((k_check_diag<3>), num_blocks(L.g.nn), kBlock, st, L.g, L.psi64, flag);
+  SBM_LAUNCH((k_check_diag<2>), num_blocks(L.g.nn), kBlock, st, L.g, L.psi64, flag);
+}
+
+hipError_t launch_finalize_sum(const double *partials, int n, double *out, hipStream_t st) {
+  SBM_LAUNCH(k_finalize_sum, 1, 1024, st, partials, n, out);
+}
+
+hipError_t launch_dot_free(const Level &L, const double *a, const double *b, double *partials,
+                           hipStream_t st) {
+  if (L.g.dim == 3) SBM_LAUNCH((k_dot_free<3>), num_blocks(L.g.nn), kBlock, st, L.g, a, b, partials);
+  SBM_LAUNCH((k_dot_free<2>), num_blocks(L.g.nn), kBlock, st, L.g, a, b, partials);
+}
+
+hipError_t launch_sumsq_free(const Level &L, const double *v, double *partials, hipStream_t st) {
+  if (L.g.dim == 3) SBM_LAUNCH((k_sumsq_free<3>), num_blocks(L.g.nn), kBlock, st, L.g, v, partials);
+  SBM_LAUNCH((k_sumsq_free<2>), num_blocks(L.g.nn), kBlock, st, L.g, v, partials);
+}
+
+template <typename T>
+hipError_t launch_bottom_cg(const Level &L, const T *psi, const Coef<T> &C, const T *f, T *x,
+                            T *r, T *p, T *Ap, double rtol, int maxit, int *iters,
+                            hipStream_t st) {
+  if (L.g.dim == 3)
+    SBM_LAUNCH((k_bottom_cg<T, 3>), 1, kBottomThreads, st, L.g, C, psi, f, x, r, p, Ap, rtol,
+               maxit, iters);
+  SBM_LAUNCH((k_bottom_cg<T, 2>), 1, kBottomThreads, st, L.g, C, psi, f, x, r, p, Ap, rtol, maxit,
+             iters);
+}
+
+hipError_t launch_bottom_mixed(const Level &L, const float *b32, float *e32, double *x64,
+                               double *r64, float *r32, float *p32, float *Ap32, float *d32,
+                               double rtol, int maxit, int *iters, hipStream_t st) {
+  if (L.g.dim == 3)
+    SBM_LAUNCH((k_bottom_mixed<3>), 1, kBottomThreads, st, L.g, L.c64, L.c32, L.psi64, L.psi32,
+               b32, e32, x64, r64, r32, p32, Ap32, d32, rtol, maxit, iters);
+  SBM_LAUNCH((k_bottom_mixed<2>), 1, kBottomThreads, st, L.g, L.c64, L.c32, L.psi64, L.psi32, b32,
+             e32, x64, r64, r32, p32, Ap32, d32, rtol, maxit, iters);
+}
+
+hipError_t launch_sensitivity(const Level &L, double lam, double mu, const Traction &tr,
+                              const double *u, const double *adj, double lam_scale,
+                              const double *design, int chain, double psi_floor, double *g,
+                              hipStream_t st) {
+  if (L.g.dim == 3)
+    SBM_LAUNCH((k_sensitivity<3>), num_blocks(L.g.nc), kBlock, st, L.g, lam, mu, L.h[0], L.h[1],
+               L.h[2], tr, u, adj, lam_scale, design, chain, psi_floor, g);
+  SBM_LAUNCH((k_sensitivity<2>), num_blocks(L.g.nc), kBlock, st, L.g, lam, mu, L.h[0], L.h[1],
+             L.h[2], tr, u, adj, lam_scale, design, chain, psi_floor, g);
+}
+
+#define SBM_INST(T)                                                                            \
+  template hipError_t launch_apply<T>(const Level &, const T *, const Coef<T> &, const T *, T *, \
+                                      hipStream_t);                                            \
+  template hipError_t launch_residual<T>(const Level &, const T *, const Coef<T> &, const T *,  \
+                                         const T *, T *, double *, hipStream_t);               \
+  template hipError_t launch_jacobi<T>(const Level &, const T *, const Coef<T> &, const T *,    \
+                                       const T *, T *, double, hipStream_t);                   \
+  template hipError_t launch_rb_half<T>(const Level &, const T *, const Coef<T> &, const T *,   \
+                                        const T *, T *, double, int, hipStream_t);             \
+  template hipError_t launch_restrict<T>(const Level &, const Level &, const T *, T *,          \
+                                         hipStream_t);                                         \
+  template hipError_t launch_prolong_add<T>(const Level &, const Level &, const T *, T *,       \
+                                            hipStream_t);                                      \
+  template hipError_t launch_fill<T>(T *, int64_t, T, hipStream_t);                             \
+  template hipError_t launch_copy<T>(const T *, T *, int64_t, hipStream_t);                     \
+  template hipError_t launch_bottom_cg<T>(const Level &, const T *, const Coef<T> &, const T *, \
+                                          T *, T *, T *, T *, double, int, int *, hipStream_t);
+
+SBM_INST(double)
+SBM_INST(float)
+template hipError_t launch_fill<int>(int *, int64_t, int, hipStream_t);
+
+}  // namespace sbm

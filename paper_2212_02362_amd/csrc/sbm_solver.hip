@@ -1,0 +1,767 @@
+// sbm_solver.hip -- host orchestration (hierarchy, V-cycle, mixed-precision
+// refinement, adjoint solve) and the C ABI declared in include/sbm.h.
+//
+// Multigrid follows Sec. 2.2-2.3 of Agrawal & Runnels: smoothing with Jacobi or
+// Gauss-Seidel, levels coarsened by 2 while every cell count is even and >= 4
+// (power-of-two grids, Sec. 3.3), coarse operators re-discretised on averaged
+// psi, V(nu_pre, nu_post) cycles until the relative residual meets rtol.  The
+// mixed mode runs the whole V-cycle in FP32 on a residual scaled to unit norm
+// and keeps the fine residual, the correction and the bottom refinement in
+// FP64.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/sbm.h"
+#include "sbm_internal.h"
+
+using namespace sbm;
+
+static thread_local std::string g_last_error;
+
+static sbm_status fail(sbm_status s, const std::string &msg) {
+  g_last_error = msg;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(SBM_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));            \
+  } while (0)
+
+struct sbm_ctx {
+  int dim = 0;
+  int nlev = 0;
+  std::vector<Level> L;
+  sbm_options opt;
+  hipStream_t st = nullptr;
+  char *ws = nullptr;
+  size_t ws_bytes = 0;
+  double *partials = nullptr;
+  int npart = 0;
+  double *scal = nullptr;  // device scalars
+  int *iflag = nullptr;    // device int flags / counters
+  // bottom scratch
+  double *b_r = nullptr, *b_p = nullptr, *b_Ap = nullptr, *b_x64 = nullptr, *b_r64 = nullptr;
+  float *b_r32 = nullptr, *b_p32 = nullptr, *b_Ap32 = nullptr, *b_d32 = nullptr;
+  double *host = nullptr;  // pinned host scalars
+  bool have_problem = false;
+  sbm_material mat{};
+  sbm_bc bc{};
+  Traction tr{};
+  DispValues dv{};
+  DispValues zero_dv{};
+  double fnorm = 0.0;
+  int last_bottom_iters = 0;
+  // live kernel timing (sbm_profile)
+  bool prof_on = false;
+  std::vector<hipEvent_t> prof_ev;  // pairs
+  std::vector<int> prof_cls;        // class of each pair in use
+  double prof_ms[SBM_PROF_N] = {0};
+  int64_t prof_n[SBM_PROF_N] = {0};
+};
+
+// Brackets one launch sequence with an event pair when profiling is on.
+struct ProfScope {
+  sbm_ctx *c;
+  int cls;
+  bool on;
+  size_t pair;
+  ProfScope(sbm_ctx *c_, int cls_, bool active) : c(c_), cls(cls_), on(c_->prof_on && active) {
+    if (!on) return;
+    pair = c->prof_cls.size();
+    while (c->prof_ev.size() < 2 * (pair + 1)) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) {
+        on = false;
+        return;
+      }
+      c->prof_ev.push_back(e);
+    }
+    c->prof_cls.push_back(cls);
+    (void)hipEventRecord(c->prof_ev[2 * pair], c->st);
+  }
+  ~ProfScope() {
+    if (on) (void)hipEventRecord(c->prof_ev[2 * pair + 1], c->st);
+  }
+};
+
+// Collects the elapsed times of completed event pairs (stream is idle).
+static void prof_harvest(sbm_ctx *c) {
+  for (size_t p = 0; p < c->prof_cls.size(); ++p) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, c->prof_ev[2 * p], c->prof_ev[2 * p + 1]) == hipSuccess) {
+      c->prof_ms[c->prof_cls[p]] += ms;
+      c->prof_n[c->prof_cls[p]] += 1;
+    }
+  }
+  c->prof_cls.clear();
+}
+
+// ------------------------------------------------------------ grid helpers
+
+static bool grid_ok(const sbm_grid *g) {
+  if (!g || (g->dim != 2 && g->dim != 3)) return false;
+  for (int a = 0; a < g->dim; ++a) {
+    if (g->ncell[a] < 1 || g->ncell[a] > (1 << 20)) return false;
+    if (!(g->h[a] > 0.0) || !isfinite(g->h[a])) return false;
+  }
+  int64_t nodes = 1;
+  for (int a = 0; a < g->dim; ++a) nodes *= g->ncell[a] + 1;
+  return nodes <= ((int64_t)1 << 30);
+}
+
+static int count_levels(const sbm_grid *g) {
+  int64_t c[3] = {g->ncell[0], g->ncell[1], g->dim > 2 ? g->ncell[2] : 4};
+  int n = 1;
+  for (;;) {
+    bool ok = true;
+    for (int a = 0; a < g->dim; ++a)
+      if (c[a] % 2 != 0 || c[a] < 4) ok = false;
+    if (!ok) break;
+    for (int a = 0; a < g->dim; ++a) c[a] /= 2;
+    ++n;
+  }
+  return n;
+}
+
+static void level_shapes(const sbm_grid *g, int nlev, std::vector<Level> &L) {
+  L.assign(nlev, Level());
+  for (int l = 0; l < nlev; ++l) {
+    Level &lv = L[l];
+    Geom &G = lv.g;
+    G.dim = g->dim;
+    int64_t c[3];
+    for (int a = 0; a < 3; ++a) {
+      if (a < g->dim) {
+        c[a] = g->ncell[a] >> l;
+        lv.h[a] = g->h[a] * (double)(1 << l);
+      } else {
+        c[a] = 1;
+        lv.h[a] = 1.0;
+      }
+    }
+    G.cx = (int)c[0];
+    G.cy = (int)c[1];
+    G.cz = (int)c[2];
+    G.nx = G.cx + 1;
+    G.ny = G.cy + 1;
+    G.nz = g->dim > 2 ? G.cz + 1 : 1;
+    G.nn = (int64_t)G.nx * G.ny * G.nz;
+    G.nc = (int64_t)G.cx * G.cy * G.cz;
+    G.dmask = 0;
+  }
+}
+
+// Workspace carving: the same walk sizes the workspace (base == nullptr) and
+// assigns the pointers.
+struct Carver {
+  char *base;
+  size_t off = 0;
+  template <typename T>
+  T *take(int64_t n) {
+    off = (off + 255) & ~(size_t)255;
+    T *p = base ? (T *)(base + off) : nullptr;
+    off += (size_t)n * sizeof(T);
+    return p;
+  }
+};
+
+static size_t carve(sbm_ctx *c, char *base) {
+  Carver cv{base};
+  const int d = c->dim;
+  int64_t maxblocks = 1;
+  for (int l = 0; l < c->nlev; ++l) {
+    Level &L = c->L[l];
+    const int64_t nv = (int64_t)d * L.g.nn;
+    L.psi64 = cv.take<double>(L.g.nc);
+    L.psi32 = cv.take<float>(L.g.nc);
+    L.e = cv.take<double>(nv);
+    L.f = cv.take<double>(nv);
+    L.t = cv.take<double>(nv);
+    L.e32 = cv.take<float>(nv);
+    L.f32 = cv.take<float>(nv);
+    L.t32 = cv.take<float>(nv);
+    maxblocks = std::max<int64_t>(maxblocks, num_blocks(L.g.nn));
+    maxblocks = std::max<int64_t>(maxblocks, num_blocks(L.g.nc));
+  }
+  c->npart = (int)maxblocks;
+  c->partials = cv.take<double>(maxblocks);
+  c->scal = cv.take<double>(16);
+  c->iflag = cv.take<int>(16);
+  const Level &B = c->L[c->nlev - 1];
+  const int64_t nb = (int64_t)d * B.g.nn;
+  c->b_r = cv.take<double>(nb);
+  c->b_p = cv.take<double>(nb);
+  c->b_Ap = cv.take<double>(nb);
+  c->b_x64 = cv.take<double>(nb);
+  c->b_r64 = cv.take<double>(nb);
+  c->b_r32 = cv.take<float>(nb);
+  c->b_p32 = cv.take<float>(nb);
+  c->b_Ap32 = cv.take<float>(nb);
+  c->b_d32 = cv.take<float>(nb);
+  return cv.off + 256;
+}
+
+static void set_coefs(Level &L, double lam, double mu, int dim) {
+  const double dfac = 1.0 / (double)(1 << (dim - 1));
+  const double pfac = dim == 3 ? 0.5 : 1.0;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double v = 0.0;
+      if (i < dim && j < dim) v = (mu + (lam + mu) * (i == j ? 1.0 : 0.0)) / (L.h[j] * L.h[j]) * dfac;
+      L.c64.cd[i][j] = v;
+      L.c32.cd[i][j] = (float)v;
+    }
+  const int pa[3] = {0, 0, 1}, pb[3] = {1, 2, 2};
+  for (int p = 0; p < 3; ++p) {
+    double cp = 0.0, cm = 0.0;
+    if (pb[p] < dim) {
+      const double ih = 1.0 / (4.0 * L.h[pa[p]] * L.h[pb[p]]);
+      cp = (lam + mu) * ih * pfac;
+      cm = (lam - mu) * ih * pfac;
+    }
+    L.c64.cp[p] = cp;
+    L.c64.cm[p] = cm;
+    L.c32.cp[p] = (float)cp;
+    L.c32.cm[p] = (float)cm;
+  }
+}
+
+static double opt_omega(const sbm_options &o) {
+  if (o.omega > 0.0) return o.omega;
+  return o.smoother == 1 ? 0.8 : 1.0;
+}
+
+static int bottom_maxit(const sbm_ctx *c) {
+  if (c->opt.bottom_max_iter > 0) return c->opt.bottom_max_iter;
+  const Level &B = c->L[c->nlev - 1];
+  return (int)std::min<int64_t>(4 * (int64_t)c->dim * B.g.nn, 1 << 30);
+}
+
+// ---------------------------------------------------------------- V-cycle
+
+template <typename T>
+struct Prec;
+template <>
+struct Prec<double> {
+  static const double *psi(const Level &L) { return L.psi64; }
+  static const Coef<double> &coef(const Level &L) { return L.c64; }
+  static double *e(Level &L) { return L.e; }
+  static double *f(Level &L) { return L.f; }
+  static double *t(Level &L) { return L.t; }
+};
+template <>
+struct Prec<float> {
+  static const float *psi(const Level &L) { return L.psi32; }
+  static const Coef<float> &coef(const Level &L) { return L.c32; }
+  static float *e(Level &L) { return L.e32; }
+  static float *f(Level &L) { return L.f32; }
+  static float *t(Level &L) { return L.t32; }
+};
+
+// nu sweeps on level l for x with load f; tmp is the ping-pong buffer.
+template <typename T>
+static hipError_t smooth(sbm_ctx *c, int l, T *x, const T *f, T *tmp, int nu) {
+  Level &L = c->L[l];
+  const T *psi = Prec<T>::psi(L);
+  const Coef<T> &C = Prec<T>::coef(L);
+  const double om = opt_omega(c->opt);
+  hipError_t e = hipSuccess;
+  if (c->opt.smoother == 1) {
+    T *src = x, *dst = tmp;
+    for (int s = 0; s < nu; ++s) {
+      ProfScope ps(c, SBM_PROF_SMOOTH, l == 0);
+      if ((e = launch_jacobi<T>(L, psi, C, src, f, dst, om, c->st)) != hipSuccess) return e;
+      std::swap(src, dst);
+    }
+    if (src != x) e = launch_copy<T>(src, x, (int64_t)c->dim * L.g.nn, c->st);
+    return e;
+  }
+  for (int s = 0; s < nu; ++s) {
+    {
+      ProfScope ps(c, SBM_PROF_SMOOTH, l == 0);
+      if ((e = launch_rb_half<T>(L, psi, C, x, f, tmp, om, 0, c->st)) != hipSuccess) return e;
+    }
+    ProfScope ps(c, SBM_PROF_SMOOTH, l == 0);
+    if ((e = launch_rb_half<T>(L, psi, C, tmp, f, x, om, 1, c->st)) != hipSuccess) return e;
+  }
+  return e;
+}
+
+static hipError_t bottom64(sbm_ctx *c, const double *f, double *x) {
+  Level &B = c->L[c->nlev - 1];
+  return launch_bottom_cg<double>(B, B.psi64, B.c64, f, x, c->b_r, c->b_p, c->b_Ap,
+                                  c->opt.bottom_rtol, bottom_maxit(c), c->iflag + 4, c->st);
+}
+
+static hipError_t bottom32(sbm_ctx *c, const float *f, float *x) {
+  Level &B = c->L[c->nlev - 1];
+  return launch_bottom_mixed(B, f, x, c->b_x64, c->b_r64, c->b_r32, c->b_p32, c->b_Ap32, c->b_d32,
+                             c->opt.bottom_rtol, bottom_maxit(c), c->iflag + 4, c->st);
+}
+
+// V-cycle on level l: x (in/out), f (load), tmp (scratch of level l).
+template <typename T>
+static hipError_t vcycle(sbm_ctx *c, int l, T *x, const T *f, T *tmp) {
+  hipError_t e;
+  if (l == c->nlev - 1) {
+    ProfScope ps(c, SBM_PROF_BOTTOM, true);
+    if constexpr (sizeof(T) == 8) return bottom64(c, f, x);
+    else return bottom32(c, f, x);
+  }
+  Level &L = c->L[l];
+  Level &C = c->L[l + 1];
+  if ((e = smooth<T>(c, l, x, f, tmp, c->opt.nu_pre)) != hipSuccess) return e;
+  {
+    ProfScope ps(c, SBM_PROF_RESIDUAL, l == 0);
+    if ((e = launch_residual<T>(L, Prec<T>::psi(L), Prec<T>::coef(L), x, f, tmp, nullptr,
+                                c->st)) != hipSuccess)
+      return e;
+  }
+  {
+    ProfScope ps(c, SBM_PROF_RESTRICT, l == 0);
+    if ((e = launch_restrict<T>(L, C, tmp, Prec<T>::f(C), c->st)) != hipSuccess) return e;
+  }
+  const int64_t nvc = (int64_t)c->dim * C.g.nn;
+  if ((e = launch_fill<T>(Prec<T>::e(C), nvc, T(0), c->st)) != hipSuccess) return e;
+  if ((e = vcycle<T>(c, l + 1, Prec<T>::e(C), Prec<T>::f(C), Prec<T>::t(C))) != hipSuccess) return e;
+  {
+    ProfScope ps(c, SBM_PROF_PROLONG, l == 0);
+    if ((e = launch_prolong_add<T>(L, C, Prec<T>::e(C), x, c->st)) != hipSuccess) return e;
+  }
+  return smooth<T>(c, l, x, f, tmp, c->opt.nu_post);
+}
+
+// ||r||_2^2 of the level-0 residual f - K u (free DOF), synchronising.
+static sbm_status residual_norm2(sbm_ctx *c, const double *u, const double *f, double *out) {
+  Level &L = c->L[0];
+  {
+    ProfScope ps(c, SBM_PROF_NORM, true);
+    HIP_TRY((launch_residual<double>(L, L.psi64, L.c64, u, f, nullptr, c->partials, c->st)));
+  }
+  HIP_TRY(launch_finalize_sum(c->partials, num_blocks(L.g.nn), c->scal, c->st));
+  HIP_TRY(hipMemcpyAsync(c->host, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIP_TRY(hipStreamSynchronize(c->st));
+  if (c->prof_on) prof_harvest(c);
+  *out = c->host[0];
+  return SBM_OK;
+}
+
+// Outer loop on the finest level for K u = f, u carrying its displacement
+// values; fnorm normalises the residual.
+static sbm_status solve_impl(sbm_ctx *c, const double *f, double fnorm, double *u, double *hist,
+                             int cap, int *ncyc, double *final_rel) {
+  Level &L0 = c->L[0];
+  const int64_t nv = (int64_t)c->dim * L0.g.nn;
+  double rho_min = INFINITY, rho = 0.0;
+  int m = 0;
+  sbm_status status = SBM_NOT_CONVERGED;
+  for (m = 0;; ++m) {
+    double ss = 0.0;
+    sbm_status s = residual_norm2(c, u, f, &ss);
+    if (s != SBM_OK) return s;
+    rho = fnorm > 0.0 ? sqrt(ss) / fnorm : (ss > 0.0 ? INFINITY : 0.0);
+    if (hist && m < cap) hist[m] = rho;
+    if (!isfinite(rho)) {
+      status = fail(SBM_E_NONFINITE, "non-finite residual at cycle " + std::to_string(m));
+      break;
+    }
+    if (rho <= c->opt.rtol) {
+      status = SBM_OK;
+      break;
+    }
+    if (rho > 1e3 * rho_min) {
+      status = fail(SBM_E_DIVERGED, "residual grew above 1e3 x its minimum at cycle " +
+                                        std::to_string(m));
+      break;
+    }
+    rho_min = std::min(rho_min, rho);
+    if (m >= c->opt.max_cycles) {
+      g_last_error = "max_cycles reached";
+      status = SBM_NOT_CONVERGED;
+      break;
+    }
+    if (c->opt.precision == 1) {
+      const double sc = sqrt(ss);
+      HIP_TRY(launch_residual_cast(L0, u, f, L0.f32, 1.0 / sc, c->st));
+      HIP_TRY(launch_fill<float>(L0.e32, nv, 0.0f, c->st));
+      HIP_TRY(vcycle<float>(c, 0, L0.e32, L0.f32, L0.t32));
+      HIP_TRY(launch_correct(L0, u, L0.e32, sc, c->st));
+    } else {
+      HIP_TRY(vcycle<double>(c, 0, u, f, L0.t));
+    }
+  }
+  if (ncyc) *ncyc = m;
+  if (final_rel) *final_rel = rho;
+  HIP_TRY(hipStreamSynchronize(c->st));
+  if (c->prof_on) prof_harvest(c);
+  return status;
+}
+
+// ------------------------------------------------------------------- ABI
+
+extern "C" {
+
+void sbm_default_options(sbm_options *o) {
+  if (!o) return;
+  o->smoother = 0;
+  o->omega = 0.0;
+  o->nu_pre = 2;
+  o->nu_post = 2;
+  o->precision = 0;
+  o->rtol = 1e-10;
+  o->max_cycles = 200;
+  o->bottom_rtol = 1e-12;
+  o->bottom_max_iter = 0;
+}
+
+const char *sbm_last_error(void) { return g_last_error.c_str(); }
+
+int sbm_num_levels(const sbm_grid *grid) {
+  if (!grid_ok(grid)) return 0;
+  return count_levels(grid);
+}
+
+static bool opts_ok(const sbm_options *o) {
+  return o && (o->smoother == 0 || o->smoother == 1) && o->nu_pre >= 0 && o->nu_post >= 0 &&
+         (o->precision == 0 || o->precision == 1) && o->rtol >= 0.0 && o->max_cycles >= 0 &&
+         o->bottom_rtol >= 0.0 && isfinite(o->omega) && o->omega >= 0.0 && o->omega < 2.0;
+}
+
+size_t sbm_workspace_bytes(const sbm_grid *grid, const sbm_options *opts) {
+  if (!grid_ok(grid) || !opts_ok(opts)) return 0;
+  sbm_ctx c;
+  c.dim = grid->dim;
+  c.nlev = count_levels(grid);
+  level_shapes(grid, c.nlev, c.L);
+  return carve(&c, nullptr);
+}
+
+sbm_status sbm_create(const sbm_grid *grid, const sbm_options *opts, void *workspace,
+                      size_t workspace_bytes, void *hip_stream, sbm_ctx **out) {
+  if (!out) return fail(SBM_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (!grid_ok(grid)) return fail(SBM_E_SHAPE, "invalid grid (dim 2/3, ncell >= 1, h > 0)");
+  if (!opts_ok(opts)) return fail(SBM_E_ARG, "invalid options");
+  if (!workspace || ((uintptr_t)workspace & 255))
+    return fail(SBM_E_WORKSPACE, "workspace NULL or not 256-byte aligned");
+  sbm_ctx *c = new sbm_ctx();
+  c->dim = grid->dim;
+  c->nlev = count_levels(grid);
+  level_shapes(grid, c->nlev, c->L);
+  const size_t need = carve(c, nullptr);
+  if (workspace_bytes < need) {
+    delete c;
+    return fail(SBM_E_WORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+  }
+  c->ws = (char *)workspace;
+  c->ws_bytes = workspace_bytes;
+  carve(c, c->ws);
+  c->opt = *opts;
+  c->st = (hipStream_t)hip_stream;
+  hipError_t e = hipHostMalloc((void **)&c->host, 64 * sizeof(double), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    delete c;
+    return fail(SBM_E_HIP, std::string("hipHostMalloc: ") + hipGetErrorString(e));
+  }
+  *out = c;
+  return SBM_OK;
+}
+
+sbm_status sbm_set_options(sbm_ctx *c, const sbm_options *opts) {
+  if (!c) return fail(SBM_E_ARG, "ctx is NULL");
+  if (!opts_ok(opts)) return fail(SBM_E_ARG, "invalid options");
+  c->opt = *opts;
+  return SBM_OK;
+}
+
+void sbm_destroy(sbm_ctx *c) {
+  if (!c) return;
+  if (c->host) (void)hipHostFree(c->host);
+  for (hipEvent_t e : c->prof_ev) (void)hipEventDestroy(e);
+  delete c;
+}
+
+sbm_status sbm_profile(sbm_ctx *c, int enable) {
+  if (!c) return fail(SBM_E_ARG, "ctx is NULL");
+  HIP_TRY(hipStreamSynchronize(c->st));
+  c->prof_cls.clear();
+  for (int k = 0; k < SBM_PROF_N; ++k) {
+    c->prof_ms[k] = 0.0;
+    c->prof_n[k] = 0;
+  }
+  c->prof_on = enable != 0;
+  return SBM_OK;
+}
+
+sbm_status sbm_profile_read(sbm_ctx *c, double *ms, int64_t *cnt) {
+  if (!c || !ms || !cnt) return fail(SBM_E_ARG, "NULL argument");
+  HIP_TRY(hipStreamSynchronize(c->st));
+  prof_harvest(c);
+  for (int k = 0; k < SBM_PROF_N; ++k) {
+    ms[k] = c->prof_ms[k];
+    cnt[k] = c->prof_n[k];
+  }
+  return SBM_OK;
+}
+
+static sbm_status set_problem_impl(sbm_ctx *c, const double *psi_raw, int cube,
+                                   const sbm_material *mat, const sbm_bc *bc, const double *b) {
+  if (!c || !psi_raw || !mat || !bc) return fail(SBM_E_ARG, "NULL argument");
+  if (!isfinite(mat->lambda) || !isfinite(mat->mu) || !(mat->mu > 0.0) ||
+      !(mat->lambda + mat->mu > 0.0) || !(mat->psi_floor >= 0.0))
+    return fail(SBM_E_ARG, "material needs mu > 0, lambda + mu > 0, psi_floor >= 0");
+  uint32_t dmask = 0;
+  for (int F = 0; F < 2 * c->dim; ++F)
+    for (int k = 0; k < c->dim; ++k) {
+      if (bc->kind[F][k] != SBM_TRACTION && bc->kind[F][k] != SBM_DISPLACEMENT)
+        return fail(SBM_E_ARG, "bc kind must be TRACTION or DISPLACEMENT");
+      if (!isfinite(bc->value[F][k])) return fail(SBM_E_NONFINITE, "non-finite bc value");
+      if (bc->kind[F][k] == SBM_DISPLACEMENT) dmask |= 1u << (3 * F + k);
+    }
+  c->mat = *mat;
+  c->bc = *bc;
+  memset(&c->tr, 0, sizeof(c->tr));
+  memset(&c->dv, 0, sizeof(c->dv));
+  memset(&c->zero_dv, 0, sizeof(c->zero_dv));
+  for (int F = 0; F < 6; ++F) {
+    const int a = F / 2;
+    c->tr.inv_h[F] = a < c->dim ? 1.0 / c->L[0].h[a] : 0.0;
+    for (int k = 0; k < 3; ++k) {
+      if (F < 2 * c->dim && k < c->dim) {
+        if (bc->kind[F][k] == SBM_TRACTION) c->tr.t[F][k] = bc->value[F][k];
+        else c->dv.v[F][k] = bc->value[F][k];
+      }
+    }
+  }
+  for (int l = 0; l < c->nlev; ++l) {
+    c->L[l].g.dmask = dmask;
+    set_coefs(c->L[l], mat->lambda, mat->mu, c->dim);
+  }
+  Level &L0 = c->L[0];
+  HIP_TRY(launch_fill<int>(c->iflag, 16, 0, c->st));
+  HIP_TRY(launch_floor_psi(psi_raw, mat->psi_floor, L0.psi64, L0.psi32, L0.g.nc, cube, c->iflag,
+                           c->st));
+  for (int l = 1; l < c->nlev; ++l) HIP_TRY(launch_coarsen_psi(c->L[l - 1], c->L[l], c->st));
+  HIP_TRY(launch_rhs(L0, c->tr, b, L0.f, c->iflag, c->st));
+  HIP_TRY(launch_check_diag(L0, c->iflag, c->st));
+  int flags = 0;
+  HIP_TRY(hipMemcpyAsync(c->host, c->iflag, sizeof(int), hipMemcpyDeviceToHost, c->st));
+  HIP_TRY(hipStreamSynchronize(c->st));
+  memcpy(&flags, c->host, sizeof(int));
+  c->have_problem = false;
+  if (flags & 1) return fail(SBM_E_NONFINITE, "NaN/Inf in psi or body force");
+  if (flags & 2) return fail(SBM_E_DIAG, "a free DOF has no solid cell around it (zero diagonal)");
+  // fnorm = ||fA - K uD|| over free DOF (uD: prescribed values, 0 elsewhere)
+  const int64_t nv = (int64_t)c->dim * L0.g.nn;
+  HIP_TRY(launch_fill<double>(L0.t, nv, 0.0, c->st));
+  HIP_TRY(launch_set_dirichlet(L0, L0.t, c->dv, c->st));
+  double ss = 0.0;
+  sbm_status s = residual_norm2(c, L0.t, L0.f, &ss);
+  if (s != SBM_OK) return s;
+  if (!isfinite(ss)) return fail(SBM_E_NONFINITE, "non-finite load");
+  c->fnorm = sqrt(ss);
+  c->have_problem = true;
+  return SBM_OK;
+}
+
+sbm_status sbm_set_problem(sbm_ctx *c, const double *psi_raw, const sbm_material *mat,
+                           const sbm_bc *bc, const double *b) {
+  return set_problem_impl(c, psi_raw, 0, mat, bc, b);
+}
+
+sbm_status sbm_set_problem_density(sbm_ctx *c, const double *rho, const sbm_material *mat,
+                                   const sbm_bc *bc, const double *b) {
+  return set_problem_impl(c, rho, 1, mat, bc, b);
+}
+
+#define NEED_PROBLEM(c)                                                     \
+  do {                                                                      \
+    if (!(c)) return fail(SBM_E_ARG, "ctx is NULL");                        \
+    if (!(c)->have_problem) return fail(SBM_E_ARG, "sbm_set_problem first"); \
+  } while (0)
+
+sbm_status sbm_solve(sbm_ctx *c, double *u, double *hist, int cap, int *ncyc, double *final_rel) {
+  NEED_PROBLEM(c);
+  if (!u) return fail(SBM_E_ARG, "u is NULL");
+  Level &L0 = c->L[0];
+  HIP_TRY(launch_set_dirichlet(L0, u, c->dv, c->st));
+  return solve_impl(c, L0.f, c->fnorm, u, hist, cap, ncyc, final_rel);
+}
+
+sbm_status sbm_solve_rhs(sbm_ctx *c, const double *g, double *x, double *hist, int cap, int *ncyc,
+                         double *final_rel) {
+  NEED_PROBLEM(c);
+  if (!g || !x) return fail(SBM_E_ARG, "NULL argument");
+  Level &L0 = c->L[0];
+  const int64_t nv = (int64_t)c->dim * L0.g.nn;
+  // masked copy of g: r = g - K*0 on free DOF via the residual kernel
+  HIP_TRY(launch_fill<double>(L0.t, nv, 0.0, c->st));
+  HIP_TRY((launch_residual<double>(L0, L0.psi64, L0.c64, L0.t, g, L0.e, c->partials, c->st)));
+  HIP_TRY(launch_finalize_sum(c->partials, num_blocks(L0.g.nn), c->scal, c->st));
+  HIP_TRY(hipMemcpyAsync(c->host, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIP_TRY(hipStreamSynchronize(c->st));
+  const double gn = sqrt(c->host[0]);
+  HIP_TRY(launch_set_dirichlet(L0, x, c->zero_dv, c->st));
+  return solve_impl(c, L0.e, gn, x, hist, cap, ncyc, final_rel);
+}
+
+sbm_status sbm_apply(sbm_ctx *c, const double *u, double *Ku) {
+  NEED_PROBLEM(c);
+  if (!u || !Ku) return fail(SBM_E_ARG, "NULL argument");
+  Level &L0 = c->L[0];
+  HIP_TRY(launch_apply<double>(L0, L0.psi64, L0.c64, u, Ku, c->st));
+  return SBM_OK;
+}
+
+sbm_status sbm_residual(sbm_ctx *c, const double *u, double *r, double *norm_host) {
+  NEED_PROBLEM(c);
+  if (!u) return fail(SBM_E_ARG, "u is NULL");
+  Level &L0 = c->L[0];
+  if (!norm_host) {
+    if (!r) return fail(SBM_E_ARG, "r and norm_host both NULL");
+    HIP_TRY((launch_residual<double>(L0, L0.psi64, L0.c64, u, L0.f, r, nullptr, c->st)));
+    return SBM_OK;
+  }
+  HIP_TRY((launch_residual<double>(L0, L0.psi64, L0.c64, u, L0.f, r, c->partials, c->st)));
+  HIP_TRY(launch_finalize_sum(c->partials, num_blocks(L0.g.nn), c->scal, c->st));
+  HIP_TRY(hipMemcpyAsync(c->host, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIP_TRY(hipStreamSynchronize(c->st));
+  *norm_host = sqrt(c->host[0]);
+  return SBM_OK;
+}
+
+sbm_status sbm_rhs(sbm_ctx *c, double *fA, double *fB) {
+  NEED_PROBLEM(c);
+  if (!fA) return fail(SBM_E_ARG, "fA is NULL");
+  Level &L0 = c->L[0];
+  const int64_t nv = (int64_t)c->dim * L0.g.nn;
+  HIP_TRY(launch_copy<double>(L0.f, fA, nv, c->st));
+  if (fB) {
+    HIP_TRY(launch_fill<double>(L0.t, nv, 0.0, c->st));
+    HIP_TRY(launch_set_dirichlet(L0, L0.t, c->dv, c->st));
+    HIP_TRY((launch_residual<double>(L0, L0.psi64, L0.c64, L0.t, L0.f, fB, nullptr, c->st)));
+  }
+  return SBM_OK;
+}
+
+sbm_status sbm_sensitivity(sbm_ctx *c, const double *u, const double *lam, double lam_scale,
+                           const double *design, int chain, double *g) {
+  NEED_PROBLEM(c);
+  if (!u || !lam || !g) return fail(SBM_E_ARG, "NULL argument");
+  if (chain < 0 || chain > 2 || (chain > 0 && !design))
+    return fail(SBM_E_ARG, "chain must be 0, 1 or 2 (1 and 2 need design)");
+  if (!isfinite(lam_scale)) return fail(SBM_E_ARG, "lam_scale must be finite");
+  Level &L0 = c->L[0];
+  HIP_TRY(launch_sensitivity(L0, c->mat.lambda, c->mat.mu, c->tr, u, lam, lam_scale, design, chain,
+                             c->mat.psi_floor, g, c->st));
+  return SBM_OK;
+}
+
+sbm_status sbm_compliance(sbm_ctx *c, const double *u, double *J) {
+  NEED_PROBLEM(c);
+  if (!u || !J) return fail(SBM_E_ARG, "NULL argument");
+  Level &L0 = c->L[0];
+  HIP_TRY(launch_dot_free(L0, L0.f, u, c->partials, c->st));
+  HIP_TRY(launch_finalize_sum(c->partials, num_blocks(L0.g.nn), c->scal, c->st));
+  HIP_TRY(hipMemcpyAsync(c->host, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIP_TRY(hipStreamSynchronize(c->st));
+  double hd = 1.0;
+  for (int a = 0; a < c->dim; ++a) hd *= L0.h[a];
+  *J = hd * c->host[0];
+  return SBM_OK;
+}
+
+// ------------------------------------------------------- component entries
+
+#define LEVEL_OK(c, l)                                                      \
+  do {                                                                      \
+    NEED_PROBLEM(c);                                                        \
+    if ((l) < 0 || (l) >= (c)->nlev) return fail(SBM_E_ARG, "level out of range"); \
+  } while (0)
+
+sbm_status sbm_level_shape(sbm_ctx *c, int l, int64_t *nc) {
+  if (!c || !nc) return fail(SBM_E_ARG, "NULL argument");
+  if (l < 0 || l >= c->nlev) return fail(SBM_E_ARG, "level out of range");
+  const Geom &G = c->L[l].g;
+  nc[0] = G.cx;
+  nc[1] = G.cy;
+  nc[2] = c->dim > 2 ? G.cz : 0;
+  return SBM_OK;
+}
+
+sbm_status sbm_level_psi(sbm_ctx *c, int l, double *psi) {
+  LEVEL_OK(c, l);
+  if (!psi) return fail(SBM_E_ARG, "psi is NULL");
+  HIP_TRY(launch_copy<double>(c->L[l].psi64, psi, c->L[l].g.nc, c->st));
+  return SBM_OK;
+}
+
+sbm_status sbm_level_apply(sbm_ctx *c, int l, const double *u, double *Ku) {
+  LEVEL_OK(c, l);
+  if (!u || !Ku) return fail(SBM_E_ARG, "NULL argument");
+  Level &L = c->L[l];
+  HIP_TRY(launch_apply<double>(L, L.psi64, L.c64, u, Ku, c->st));
+  return SBM_OK;
+}
+
+sbm_status sbm_level_apply_f32(sbm_ctx *c, int l, const float *u, float *Ku) {
+  LEVEL_OK(c, l);
+  if (!u || !Ku) return fail(SBM_E_ARG, "NULL argument");
+  Level &L = c->L[l];
+  HIP_TRY(launch_apply<float>(L, L.psi32, L.c32, u, Ku, c->st));
+  return SBM_OK;
+}
+
+sbm_status sbm_level_smooth(sbm_ctx *c, int l, int colour, double omega, const double *u_in,
+                            const double *f, double *u_out) {
+  LEVEL_OK(c, l);
+  if (!u_in || !f || !u_out || u_in == u_out) return fail(SBM_E_ARG, "bad buffers");
+  if (!(omega > 0.0 && omega < 2.0) || colour > 1) return fail(SBM_E_ARG, "bad omega/colour");
+  Level &L = c->L[l];
+  if (colour < 0) HIP_TRY(launch_jacobi<double>(L, L.psi64, L.c64, u_in, f, u_out, omega, c->st));
+  else HIP_TRY(launch_rb_half<double>(L, L.psi64, L.c64, u_in, f, u_out, omega, colour, c->st));
+  return SBM_OK;
+}
+
+sbm_status sbm_level_residual(sbm_ctx *c, int l, const double *u, const double *f, double *r) {
+  LEVEL_OK(c, l);
+  if (!u || !f || !r) return fail(SBM_E_ARG, "NULL argument");
+  Level &L = c->L[l];
+  HIP_TRY((launch_residual<double>(L, L.psi64, L.c64, u, f, r, nullptr, c->st)));
+  return SBM_OK;
+}
+
+sbm_status sbm_level_restrict(sbm_ctx *c, int l, const double *r, double *fc) {
+  LEVEL_OK(c, l);
+  if (l + 1 >= c->nlev) return fail(SBM_E_ARG, "no coarser level");
+  if (!r || !fc) return fail(SBM_E_ARG, "NULL argument");
+  HIP_TRY(launch_restrict<double>(c->L[l], c->L[l + 1], r, fc, c->st));
+  return SBM_OK;
+}
+
+sbm_status sbm_level_prolong_add(sbm_ctx *c, int l, const double *e, double *u) {
+  LEVEL_OK(c, l);
+  if (l + 1 >= c->nlev) return fail(SBM_E_ARG, "no coarser level");
+  if (!e || !u) return fail(SBM_E_ARG, "NULL argument");
+  HIP_TRY(launch_prolong_add<double>(c->L[l], c->L[l + 1], e, u, c->st));
+  return SBM_OK;
+}
+
+sbm_status sbm_bottom_solve(sbm_ctx *c, const double *f, double *x, int *iters) {
+  NEED_PROBLEM(c);
+  if (!f || !x) return fail(SBM_E_ARG, "NULL argument");
+  HIP_TRY(bottom64(c, f, x));
+  HIP_TRY(hipMemcpyAsync(c->host, c->iflag + 4, sizeof(int), hipMemcpyDeviceToHost, c->st));
+  HIP_TRY(hipStreamSynchronize(c->st));
+  if (iters) memcpy(iters, c->host, sizeof(int));
+  return SBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,73 @@
+"""Parity at the full workload sizes, in the launch configuration the
+benchmark times (default options, FP64 and mixed).  The oracle cannot run a
+whole solve there in seconds, so the checks are properties it can evaluate:
+
+* the oracle's own FP64 Apply of the GPU solution gives a relative residual
+  within the tolerance (any size);
+* Apply parity on the full grid;
+* the first two V-cycles match the oracle's two cycles (129^3 only);
+* central differences of the GPU compliance at the 32 drawn cells of the
+  193x97x97 density workload."""
+import numpy as np
+import pytest
+
+import oracle
+import sbm_inputs as si
+from _util import oracle_solve, rel_l2, rel_max, say, solver_for, to_np
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+def _oracle_rel_residual(p, u):
+    psi = oracle.floor_psi(p.psi_raw, p.psi_floor)
+    fA, fB, _ = oracle.rhs(p.ncell, p.h, p.lam, p.mu, psi, p.kind, p.val, p.b)
+    mask, _ = oracle.dirichlet(p.ncell, p.kind, p.val)
+    r = oracle.residual(p.ncell, p.h, p.lam, p.mu, psi, mask, u, fA)
+    return np.linalg.norm(r) / np.linalg.norm(fB[mask == 0])
+
+
+WORKLOADS = {
+    "spherical_voids_129": lambda: si.spherical_voids_3d(128),
+    "cantilever_193x97x97": lambda: si.cantilever_density_3d(),
+    "diffuse_crack_257": lambda: si.diffuse_crack_3d(256),
+}
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("name", list(WORKLOADS))
+def test_fullsize_solution_residual(name, precision):
+    p = WORKLOADS[name]()
+    say("full size", name, "precision", precision)
+    S = solver_for(p, precision=precision, rtol=1e-10, max_cycles=400)
+    u, hist, st = S.solve()
+    assert st == 0, hist[-5:]
+    un = to_np(u)
+    del u
+    rho = _oracle_rel_residual(p, un)
+    print(f"[fullsize] {name} precision {precision}: {len(hist) - 1} cycles, "
+          f"GPU rho {hist[-1]:.3e}, oracle-evaluated rho {rho:.3e}")
+    assert rho <= 1.05e-10
+
+
+def test_fullsize_apply_and_first_cycles_129():
+    p = WORKLOADS["spherical_voids_129"]()
+    S = solver_for(p, rtol=0.0, max_cycles=2)
+    psi = oracle.floor_psi(p.psi_raw, p.psi_floor)
+    u = np.random.default_rng(0).standard_normal((3,) + p.node_shape)
+    say("full apply 129")
+    assert rel_max(to_np(S.apply(u)), oracle.apply(p.ncell, p.h, p.lam, p.mu, psi, u)) < 1e-13
+    say("two cycles 129")
+    ug, hg, _ = S.solve()
+    uo, ho, _ = oracle_solve(p, rtol=0.0, max_cycles=2)
+    assert np.all(np.abs(hg - ho) <= 1e-9 * ho)
+    assert rel_l2(to_np(ug), uo) <= 1e-11
+
+
+def test_fullsize_compliance_fd_193():
+    from paper_2212_02362_amd import compliance_grad
+    from test_gpu_grad import _fd_check
+    p = WORKLOADS["cantilever_193x97x97"]()
+    S = solver_for(p, rtol=1e-10, max_cycles=400)
+    say("compliance grad full size")
+    J, g, u = compliance_grad(S, p.rho, p, return_u=True)
+    _fd_check(S, p, to_np(g), u, p.fd_cells, step=1e-6)
