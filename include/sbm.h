@@ -100,7 +100,10 @@ typedef struct {
  *   rtol           stop when ||f - K u||_2 <= rtol ||f||_2 over free DOF [1e-10]
  *   max_cycles     V-cycle cap [200]
  *   bottom_rtol    CG tolerance on the bottom grid, relative [1e-12]
- *   bottom_max_iter CG iteration cap; <= 0 means 4 x free bottom DOF [0] */
+ *   bottom_max_iter CG iteration cap; <= 0 means 4 x free bottom DOF [0]
+ *   use_graphs     1: each V-cycle is captured once into a HIP graph and
+ *                  replayed (same kernels, same order, fewer launches) [1];
+ *                  0: kernels are launched one by one */
 typedef struct {
   int smoother;
   double omega;
@@ -110,6 +113,7 @@ typedef struct {
   int max_cycles;
   double bottom_rtol;
   int bottom_max_iter;
+  int use_graphs;
 } sbm_options;
 
 /* Fills *opts with the defaults above. */
@@ -202,6 +206,7 @@ sbm_status sbm_compliance(sbm_ctx *ctx, const double *u, double *J_host);
 /* Live kernel timing.  While enabled, every finest-level launch of the
  * classes below is bracketed by HIP events on the context's stream; the
  * elapsed times are collected at the solve's per-cycle synchronisation.
+ * Cycles then run launch by launch (use_graphs is ignored while enabled).
  * sbm_profile(ctx, 1) enables and clears, sbm_profile(ctx, 0) disables.
  * sbm_profile_read fills ms_host[SBM_PROF_N] (total milliseconds) and
  * count_host[SBM_PROF_N] (launches) per class. */
@@ -216,6 +221,11 @@ typedef enum {
 } sbm_prof_class;
 sbm_status sbm_profile(sbm_ctx *ctx, int enable);
 sbm_status sbm_profile_read(sbm_ctx *ctx, double *ms_host, int64_t *count_host);
+
+/* Captured V-cycle graphs: number of captures and of graph launches since
+ * sbm_create (both 0 when use_graphs is 0 or capture was not possible; the
+ * reason of a failed capture is then in sbm_last_error()). */
+sbm_status sbm_graph_info(sbm_ctx *ctx, int64_t *captures_host, int64_t *launches_host);
 
 /* Releases host-side state; the workspace stays the caller's. */
 void sbm_destroy(sbm_ctx *ctx);

@@ -39,7 +39,7 @@ class SbmOptions(ctypes.Structure):
     _fields_ = [("smoother", ctypes.c_int), ("omega", ctypes.c_double), ("nu_pre", ctypes.c_int),
                 ("nu_post", ctypes.c_int), ("precision", ctypes.c_int), ("rtol", ctypes.c_double),
                 ("max_cycles", ctypes.c_int), ("bottom_rtol", ctypes.c_double),
-                ("bottom_max_iter", ctypes.c_int)]
+                ("bottom_max_iter", ctypes.c_int), ("use_graphs", ctypes.c_int)]
 
 
 _P = ctypes.c_void_p
@@ -67,6 +67,7 @@ SIGNATURES = {
                                                ctypes.POINTER(SbmBc), _P]),
     "sbm_compliance": (ctypes.c_int, [_P, _P, _DP]),
     "sbm_profile": (ctypes.c_int, [_P, ctypes.c_int]),
+    "sbm_graph_info": (ctypes.c_int, [_P, _I64P, _I64P]),
     "sbm_profile_read": (ctypes.c_int, [_P, _DP, _I64P]),
     "sbm_destroy": (None, [_P]),
     "sbm_last_error": (ctypes.c_char_p, []),

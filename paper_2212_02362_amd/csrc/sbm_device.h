@@ -27,6 +27,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "sbm_fastdiv.h"
+
 namespace sbm {
 
 constexpr int kBlock = 256;  // threads per block of the node-parallel kernels
@@ -35,9 +37,12 @@ struct Geom {
   int dim;
   int nx, ny, nz;   // nodes per axis (nz = 1 in 2D)
   int cx, cy, cz;   // cells per axis (cz = 1 in 2D)
-  int64_t nn;       // nodes
+  int64_t nn;       // nodes (< 2^31)
   int64_t nc;       // cells
   uint32_t dmask;   // bit 3*F + k: face F fixes component k (F = x-,x+,y-,y+,z-,z+)
+  FastDiv fnx, fny; // division by nx and ny (node index decoding)
+  FastDiv fcx, fcy; // division by cx and cy (cell index decoding)
+  FastDiv fpx;      // division by (nx + 1) / 2 (x-pairs of the colour sweeps)
 };
 
 template <typename T>
@@ -57,11 +62,20 @@ __device__ __forceinline__ bool is_dirichlet(const Geom &g, int i, int j, int k,
 
 // Node coordinates of a linear node index.
 __device__ __forceinline__ void node_ijk(const Geom &g, int64_t id, int &i, int &j, int &k) {
-  const int64_t nxy = (int64_t)g.nx * g.ny;
-  k = (int)(id / nxy);
-  const int64_t rem = id - (int64_t)k * nxy;
-  j = (int)(rem / g.nx);
-  i = (int)(rem - (int64_t)j * g.nx);
+  const uint32_t n = (uint32_t)id;
+  const uint32_t row = g.fnx.div(n);
+  i = (int)(n - row * (uint32_t)g.nx);
+  k = (int)g.fny.div(row);
+  j = (int)(row - (uint32_t)k * (uint32_t)g.ny);
+}
+
+// Cell coordinates of a linear cell index.
+__device__ __forceinline__ void cell_ijk(const Geom &g, int64_t id, int &i, int &j, int &k) {
+  const uint32_t n = (uint32_t)id;
+  const uint32_t row = g.fcx.div(n);
+  i = (int)(n - row * (uint32_t)g.cx);
+  k = (int)g.fcy.div(row);
+  j = (int)(row - (uint32_t)k * (uint32_t)g.cy);
 }
 
 // Evaluates (K u)(n) for all components and the diagonal at node (i, j, k).
@@ -72,13 +86,14 @@ __device__ __forceinline__ void node_stencil(const Geom &g, const Coef<T> &C,
                                              const T *__restrict__ psi,
                                              const T *__restrict__ u, int i, int j, int k,
                                              T out[3], T diag[3]) {
-  const int64_t sy = g.nx, sz = (int64_t)g.nx * g.ny;
-  const int64_t idx = i + sy * j + sz * k;
-  const int64_t ox[3] = {i > 0 ? -1 : 0, 0, i < g.nx - 1 ? 1 : 0};
-  const int64_t oy[3] = {j > 0 ? -sy : 0, 0, j < g.ny - 1 ? sy : 0};
-  const int64_t nn = g.nn;
+  // every index fits in 32 bits (nodes x components < 2^31)
+  const int sy = g.nx, sz = g.nx * g.ny;
+  const int idx = i + sy * j + sz * k;
+  const int ox[3] = {i > 0 ? -1 : 0, 0, i < g.nx - 1 ? 1 : 0};
+  const int oy[3] = {j > 0 ? -sy : 0, 0, j < g.ny - 1 ? sy : 0};
+  const int nn = (int)g.nn;
   if constexpr (DIM == 3) {
-    const int64_t oz[3] = {k > 0 ? -sz : 0, 0, k < g.nz - 1 ? sz : 0};
+    const int oz[3] = {k > 0 ? -sz : 0, 0, k < g.nz - 1 ? sz : 0};
     // cells around the node: P[oz][oy][ox] is cell (i-1+ox, j-1+oy, k-1+oz)
     T P[2][2][2];
 #pragma unroll
@@ -89,7 +104,7 @@ __device__ __forceinline__ void node_stencil(const Geom &g, const Coef<T> &C,
         for (int c0 = 0; c0 < 2; ++c0) {
           const int xi = i - 1 + c0, yj = j - 1 + c1, zk = k - 1 + c2;
           const bool in = xi >= 0 && xi < g.cx && yj >= 0 && yj < g.cy && zk >= 0 && zk < g.cz;
-          P[c2][c1][c0] = in ? psi[xi + (int64_t)g.cx * (yj + (int64_t)g.cy * zk)] : T(0);
+          P[c2][c1][c0] = in ? psi[xi + g.cx * (yj + g.cy * zk)] : T(0);
         }
     T E[3][2];
 #pragma unroll
@@ -153,7 +168,7 @@ __device__ __forceinline__ void node_stencil(const Geom &g, const Coef<T> &C,
       for (int c0 = 0; c0 < 2; ++c0) {
         const int xi = i - 1 + c0, yj = j - 1 + c1;
         const bool in = xi >= 0 && xi < g.cx && yj >= 0 && yj < g.cy;
-        P[c1][c0] = in ? psi[xi + (int64_t)g.cx * yj] : T(0);
+        P[c1][c0] = in ? psi[xi + g.cx * yj] : T(0);
       }
     T E[2][2];
 #pragma unroll

@@ -46,7 +46,7 @@ template <typename T>
 hipError_t launch_residual(const Level &L, const T *psi, const Coef<T> &C, const T *u,
                            const T *f, T *r, double *partials, hipStream_t st);
 hipError_t launch_residual_cast(const Level &L, const double *u, const double *f, float *r32,
-                                double inv_s, hipStream_t st);
+                                const double *ss, hipStream_t st);
 template <typename T>
 hipError_t launch_jacobi(const Level &L, const T *psi, const Coef<T> &C, const T *u, const T *f,
                          T *u_out, double omega, hipStream_t st);
@@ -61,7 +61,8 @@ template <typename T>
 hipError_t launch_fill(T *p, int64_t n, T v, hipStream_t st);
 template <typename T>
 hipError_t launch_copy(const T *src, T *dst, int64_t n, hipStream_t st);
-hipError_t launch_correct(const Level &L, double *u, const float *e32, double s, hipStream_t st);
+hipError_t launch_correct(const Level &L, double *u, const float *e32, const double *ss,
+                          hipStream_t st);
 hipError_t launch_set_dirichlet(const Level &L, double *u, const DispValues &dv, hipStream_t st);
 hipError_t launch_floor_psi(const double *raw, double floor_, double *psi64, float *psi32,
                             int64_t n, int cube, int *flag, hipStream_t st);

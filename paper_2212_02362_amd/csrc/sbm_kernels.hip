@@ -54,15 +54,20 @@ __global__ __launch_bounds__(kBlock) void k_residual(Geom g, Coef<T> C, const T 
 }
 
 // r32 = fp32((f - K u) / s) on free DOF: the scaled residual handed to the
-// FP32 cycle of the mixed-precision solve.
+// FP32 cycle of the mixed-precision solve.  s = sqrt(*ss) is the residual
+// norm the convergence test just computed (device-resident, so a captured
+// cycle needs no host-side argument).
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_residual_cast(Geom g, Coef<double> C,
                                                           const double *__restrict__ psi,
                                                           const double *__restrict__ u,
                                                           const double *__restrict__ f,
-                                                          float *__restrict__ r32, double inv_s) {
+                                                          float *__restrict__ r32,
+                                                          const double *__restrict__ ss) {
   const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (id >= g.nn) return;
+  const double sn = sqrt(*ss);
+  const double inv_s = sn > 0.0 ? 1.0 / sn : 0.0;
   int i, j, k;
   node_ijk(g, id, i, j, k);
   double out[3], dg[3];
@@ -109,10 +114,10 @@ __global__ __launch_bounds__(kBlock) void k_rb_half(Geom g, Coef<T> C, const T *
   const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int64_t total = (int64_t)npx * g.ny * g.nz;
   if (tid >= total) return;
-  const int p = (int)(tid % npx);
-  const int64_t rest = tid / npx;
-  const int j = (int)(rest % g.ny);
-  const int k = (int)(rest / g.ny);
+  const uint32_t rest = g.fpx.div((uint32_t)tid);
+  const int p = (int)((uint32_t)tid - rest * (uint32_t)npx);
+  const int k = (int)g.fny.div(rest);
+  const int j = (int)(rest - (uint32_t)k * (uint32_t)g.ny);
   const int par = (colour + j + k) & 1;
   const int iu = 2 * p + par, ic = 2 * p + 1 - par;
   const int64_t row = (int64_t)g.nx * (j + (int64_t)g.ny * k);
@@ -212,12 +217,14 @@ __global__ __launch_bounds__(kBlock) void k_copy(const T *__restrict__ s, T *__r
     d[q] = s[q];
 }
 
-// u += s * e32 on free DOF (FP64 correction of the mixed cycle).
+// u += s * e32 on free DOF (FP64 correction of the mixed cycle), s = sqrt(*ss).
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_correct(Geom g, double *__restrict__ u,
-                                                    const float *__restrict__ e32, double s) {
+                                                    const float *__restrict__ e32,
+                                                    const double *__restrict__ ss) {
   const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (id >= g.nn) return;
+  const double s = sqrt(*ss);
   int i, j, k;
   node_ijk(g, id, i, j, k);
 #pragma unroll
@@ -274,10 +281,8 @@ __global__ __launch_bounds__(kBlock) void k_coarsen_psi(Geom gf, Geom gc,
                                                         float *__restrict__ pc32) {
   const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (id >= gc.nc) return;
-  const int64_t cxy = (int64_t)gc.cx * gc.cy;
-  const int K = (int)(id / cxy);
-  const int64_t rem = id - (int64_t)K * cxy;
-  const int J = (int)(rem / gc.cx), I = (int)(rem - (int64_t)J * gc.cx);
+  int I, J, K;
+  cell_ijk(gc, id, I, J, K);
   double s = 0.0;
   for (int o = 0; o < (1 << DIM); ++o) {
     const int fi = 2 * I + (o & 1), fj = 2 * J + ((o >> 1) & 1);
@@ -421,7 +426,7 @@ __global__ __launch_bounds__(kBlock) void k_dot_free(Geom g, const double *__res
 
 // ----------------------------------------------------------------- bottom --
 
-constexpr int kBottomThreads = 1024;
+constexpr int kBottomThreads = 256;  // keeps the per-thread state of the global-memory CG in registers
 
 // CG on the free DOF, one workgroup.  On entry r holds the initial residual
 // (0 on displacement DOF) and x the initial iterate; returns the iterations.
@@ -570,6 +575,259 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom_mixed(
   if (threadIdx.x == 0 && iters) *iters = total;
 }
 
+// ---------------------------------------------------- LDS-resident bottom --
+//
+// The bottom grid is small (a few to a few hundred nodes), so the whole CG
+// runs in one workgroup with the search direction and psi in LDS and each
+// thread's share of x, r, A p in registers.  Reductions sum the per-wave
+// partials in every thread in the same fixed order (one barrier each; the
+// partial buffers alternate so a reduction never overwrites partials that a
+// slower thread is still reading).
+
+constexpr int kBotQ = 4;          // nodes per thread
+constexpr int kBotThreads = 256;  // at most: the per-thread state stays in registers
+
+struct BotRed {
+  double *buf;  // 2 x 16 doubles of LDS
+  int phase;
+};
+
+__device__ __forceinline__ double bot_allsum(double v, BotRed &R) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  double *b = R.buf + 16 * R.phase;
+  R.phase ^= 1;
+  if ((threadIdx.x & 63) == 0) b[threadIdx.x >> 6] = v;
+  __syncthreads();
+  const int nw = blockDim.x >> 6;
+  double s = 0.0;
+  for (int w = 0; w < nw; ++w) s += b[w];
+  return s;
+}
+
+// CG on K_FF d = r (d from 0) with p and psi in LDS; r and d in registers.
+// Returns iterations; on return d holds the solution increment.
+template <typename T, int DIM, int Q>
+__device__ int bot_cg(const Geom &g, const Coef<T> &C, const T *psi_l, T *p_l, T (&r)[Q][3],
+                      T (&d)[Q][3], const bool (&dir)[Q][3], const int (&cijk)[Q][3],
+                      double rtol, int maxit, BotRed &R) {
+  const int64_t n = g.nn;
+  double loc = 0.0;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int64_t id = threadIdx.x + (int64_t)q * blockDim.x;
+    if (id >= n) continue;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+      d[q][c] = T(0);
+      p_l[c * n + id] = r[q][c];
+      loc += (double)r[q][c] * (double)r[q][c];
+    }
+  }
+  double rr = bot_allsum(loc, R);
+  const double r0 = sqrt(rr);
+  int it = 0;
+  while (r0 > 0.0 && sqrt(rr) > rtol * r0 && it < maxit) {
+    __syncthreads();  // p visible
+    T ap[Q][3];
+    double pap = 0.0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int64_t id = threadIdx.x + (int64_t)q * blockDim.x;
+      if (id >= n) continue;
+      T out[3], dg[3];
+      node_stencil<T, DIM>(g, C, psi_l, p_l, cijk[q][0], cijk[q][1], cijk[q][2], out, dg);
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) {
+        ap[q][c] = dir[q][c] ? T(0) : out[c];
+        pap += (double)p_l[c * n + id] * (double)ap[q][c];
+      }
+    }
+    pap = bot_allsum(pap, R);  // its barrier also ends every read of p
+    if (!(pap > 0.0)) break;
+    const double alpha = rr / pap;
+    double rn = 0.0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int64_t id = threadIdx.x + (int64_t)q * blockDim.x;
+      if (id >= n) continue;
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) {
+        d[q][c] = (T)((double)d[q][c] + alpha * (double)p_l[c * n + id]);
+        r[q][c] = (T)((double)r[q][c] - alpha * (double)ap[q][c]);
+        rn += (double)r[q][c] * (double)r[q][c];
+      }
+    }
+    rn = bot_allsum(rn, R);
+    const double beta = rn / rr;
+    rr = rn;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int64_t id = threadIdx.x + (int64_t)q * blockDim.x;
+      if (id >= n) continue;
+#pragma unroll
+      for (int c = 0; c < DIM; ++c)
+        p_l[c * n + id] = dir[q][c] ? T(0) : (T)((double)r[q][c] + beta * (double)p_l[c * n + id]);
+    }
+    ++it;
+  }
+  __syncthreads();
+  return it;
+}
+
+// FP64 bottom: x += CG solution of K_FF d = (f - K x)_F.
+template <int DIM>
+__global__ __launch_bounds__(kBotThreads) void k_bottom_lds64(Geom g, Coef<double> C,
+                                                       const double *__restrict__ psi,
+                                                       const double *__restrict__ f, double *x,
+                                                       double rtol, int maxit, int *iters) {
+  extern __shared__ double smem[];
+  __shared__ double red[32];
+  BotRed R{red, 0};
+  const int64_t n = g.nn;
+  double *psi_l = smem;
+  double *p_l = smem + ((g.nc + 1) & ~(int64_t)1);
+  for (int64_t q = threadIdx.x; q < g.nc; q += blockDim.x) psi_l[q] = psi[q];
+  bool dir[kBotQ][3];
+  int cijk[kBotQ][3];
+  double r[kBotQ][3], dd[kBotQ][3], xv[kBotQ][3];
+#pragma unroll
+  for (int q = 0; q < kBotQ; ++q) {
+    const int64_t id = threadIdx.x + (int64_t)q * blockDim.x;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      dir[q][c] = true;
+      r[q][c] = dd[q][c] = xv[q][c] = 0.0;
+      cijk[q][c] = 0;
+    }
+    if (id >= n) continue;
+    node_ijk(g, id, cijk[q][0], cijk[q][1], cijk[q][2]);
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+      dir[q][c] = is_dirichlet(g, cijk[q][0], cijk[q][1], cijk[q][2], c);
+      xv[q][c] = x[c * n + id];
+      p_l[c * n + id] = xv[q][c];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kBotQ; ++q) {
+    const int64_t id = threadIdx.x + (int64_t)q * blockDim.x;
+    if (id >= n) continue;
+    double out[3], dg[3];
+    node_stencil<double, DIM>(g, C, psi_l, p_l, cijk[q][0], cijk[q][1], cijk[q][2], out, dg);
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) r[q][c] = dir[q][c] ? 0.0 : f[c * n + id] - out[c];
+  }
+  __syncthreads();
+  const int it = bot_cg<double, DIM, kBotQ>(g, C, psi_l, p_l, r, dd, dir, cijk, rtol, maxit, R);
+#pragma unroll
+  for (int q = 0; q < kBotQ; ++q) {
+    const int64_t id = threadIdx.x + (int64_t)q * blockDim.x;
+    if (id >= n) continue;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c)
+      if (!dir[q][c]) x[c * n + id] = xv[q][c] + dd[q][c];
+  }
+  if (threadIdx.x == 0 && iters) *iters = it;
+}
+
+// Mixed bottom: FP32 CG (LDS) inside FP64 iterative refinement.  The FP64
+// iterate lives in LDS (each thread updates its own entries), where it also
+// feeds the FP64 residual stencil.
+constexpr int kBotQMixed = 2;
+
+template <int DIM>
+__global__ __launch_bounds__(kBotThreads) void k_bottom_lds_mixed(Geom g, Coef<double> C64,
+                                                                  Coef<float> C32,
+                                                                  const double *__restrict__ psi64,
+                                                                  const float *__restrict__ psi32,
+                                                                  const float *__restrict__ b32,
+                                                                  float *e32, double rtol,
+                                                                  int maxit, int *iters) {
+  constexpr int Q = kBotQMixed;
+  extern __shared__ double smem[];
+  __shared__ double red[32];
+  BotRed R{red, 0};
+  const int64_t n = g.nn;
+  const int64_t nc2 = (g.nc + 1) & ~(int64_t)1;
+  double *psi_l = smem;
+  double *x_l = smem + nc2;
+  float *psi32_l = (float *)(x_l + DIM * n);
+  float *p_l = psi32_l + nc2;
+  for (int64_t q = threadIdx.x; q < g.nc; q += blockDim.x) {
+    psi_l[q] = psi64[q];
+    psi32_l[q] = psi32[q];
+  }
+  bool dir[Q][3];
+  int cijk[Q][3];
+  float r32[Q][3], d32[Q][3];
+  double loc = 0.0;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int64_t id = threadIdx.x + (int64_t)q * blockDim.x;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      dir[q][c] = true;
+      r32[q][c] = d32[q][c] = 0.0f;
+      cijk[q][c] = 0;
+    }
+    if (id >= n) continue;
+    node_ijk(g, id, cijk[q][0], cijk[q][1], cijk[q][2]);
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+      dir[q][c] = is_dirichlet(g, cijk[q][0], cijk[q][1], cijk[q][2], c);
+      x_l[c * n + id] = 0.0;
+      if (!dir[q][c]) loc += (double)b32[c * n + id] * (double)b32[c * n + id];
+    }
+  }
+  const double bnorm = sqrt(bot_allsum(loc, R));  // its barrier also publishes x_l
+  int total = 0;
+  for (int outer = 0; outer < 40 && bnorm > 0.0; ++outer) {
+    double r64[Q][3];
+    double rl = 0.0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int64_t id = threadIdx.x + (int64_t)q * blockDim.x;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) r64[q][c] = 0.0;
+      if (id >= n) continue;
+      double out[3], dg[3];
+      node_stencil<double, DIM>(g, C64, psi_l, x_l, cijk[q][0], cijk[q][1], cijk[q][2], out, dg);
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) {
+        r64[q][c] = dir[q][c] ? 0.0 : (double)b32[c * n + id] - out[c];
+        rl += r64[q][c] * r64[q][c];
+      }
+    }
+    const double rn = sqrt(bot_allsum(rl, R));  // barrier: every read of x_l is done
+    if (rn <= rtol * bnorm || total >= maxit) break;
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) r32[q][c] = (float)(r64[q][c] / rn);
+    total += bot_cg<float, DIM, Q>(g, C32, psi32_l, p_l, r32, d32, dir, cijk, 1e-5, maxit - total,
+                                   R);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int64_t id = threadIdx.x + (int64_t)q * blockDim.x;
+      if (id >= n) continue;
+#pragma unroll
+      for (int c = 0; c < DIM; ++c)
+        if (!dir[q][c]) x_l[c * n + id] += rn * (double)d32[q][c];
+    }
+    __syncthreads();  // updated x_l visible to the next residual
+  }
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int64_t id = threadIdx.x + (int64_t)q * blockDim.x;
+    if (id >= n) continue;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) e32[c * n + id] = (float)x_l[c * n + id];
+  }
+  if (threadIdx.x == 0 && iters) *iters = total;
+}
+
 // ------------------------------------------------------------ sensitivity --
 
 // g_c = -lam_c^T K_c u_c + lam^T df/dpsi_c per cell, with K_c in energy form:
@@ -591,10 +849,8 @@ __global__ __launch_bounds__(kBlock) void k_sensitivity(Geom g, double lame, dou
                                                         double *__restrict__ out) {
   const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (id >= g.nc) return;
-  const int64_t cxy = (int64_t)g.cx * g.cy;
-  const int ck = (int)(id / cxy);
-  const int64_t rem = id - (int64_t)ck * cxy;
-  const int cj = (int)(rem / g.cx), ci = (int)(rem - (int64_t)cj * g.cx);
+  int ci, cj, ck;
+  cell_ijk(g, id, ci, cj, ck);
   constexpr int NCO = 1 << DIM;
   double U[3][NCO], A[3][NCO];
 #pragma unroll
@@ -691,10 +947,14 @@ __global__ __launch_bounds__(kBlock) void k_sensitivity(Geom g, double lame, dou
 
 // ---------------------------------------------------------------- launchers --
 
-#define SBM_LAUNCH(kern, grid, block, st, ...)                         \
-  do {                                                                 \
+// The runtime's last-error slot is shared with every other HIP user of the
+// thread; it is cleared before the launch so that the status returned is the
+// launch's own.
+#define SBM_LAUNCH(kern, grid, block, st, ...)                             \
+  do {                                                                     \
+    (void)hipGetLastError();                                               \
     hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, st, __VA_ARGS__); \
-    return hipGetLastError();                                          \
+    return hipGetLastError();                                              \
   } while (0)
 
 static int fill_blocks(int64_t n) {
@@ -718,12 +978,12 @@ hipError_t launch_residual(const Level &L, const T *psi, const Coef<T> &C, const
 }
 
 hipError_t launch_residual_cast(const Level &L, const double *u, const double *f, float *r32,
-                                double inv_s, hipStream_t st) {
+                                const double *ss, hipStream_t st) {
   if (L.g.dim == 3)
     SBM_LAUNCH((k_residual_cast<3>), num_blocks(L.g.nn), kBlock, st, L.g, L.c64, L.psi64, u, f,
-               r32, inv_s);
+               r32, ss);
   SBM_LAUNCH((k_residual_cast<2>), num_blocks(L.g.nn), kBlock, st, L.g, L.c64, L.psi64, u, f, r32,
-             inv_s);
+             ss);
 }
 
 template <typename T>
@@ -769,9 +1029,10 @@ hipError_t launch_copy(const T *src, T *dst, int64_t n, hipStream_t st) {
   SBM_LAUNCH((k_copy<T>), fill_blocks(n), kBlock, st, src, dst, n);
 }
 
-hipError_t launch_correct(const Level &L, double *u, const float *e32, double s, hipStream_t st) {
-  if (L.g.dim == 3) SBM_LAUNCH((k_correct<3>), num_blocks(L.g.nn), kBlock, st, L.g, u, e32, s);
-  SBM_LAUNCH((k_correct<2>), num_blocks(L.g.nn), kBlock, st, L.g, u, e32, s);
+hipError_t launch_correct(const Level &L, double *u, const float *e32, const double *ss,
+                          hipStream_t st) {
+  if (L.g.dim == 3) SBM_LAUNCH((k_correct<3>), num_blocks(L.g.nn), kBlock, st, L.g, u, e32, ss);
+  SBM_LAUNCH((k_correct<2>), num_blocks(L.g.nn), kBlock, st, L.g, u, e32, ss);
 }
 
 hipError_t launch_set_dirichlet(const Level &L, double *u, const DispValues &dv, hipStream_t st) {
@@ -818,10 +1079,43 @@ hipError_t launch_sumsq_free(const Level &L, const double *v, double *partials, 
   SBM_LAUNCH((k_sumsq_free<2>), num_blocks(L.g.nn), kBlock, st, L.g, v, partials);
 }
 
+static int bottom_threads(int64_t nn) {
+  int64_t t = ((nn + kBotQ - 1) / kBotQ + 63) / 64 * 64;
+  return (int)(t < 64 ? 64 : t);
+}
+
+static bool bottom_fits_lds(const Geom &g, size_t bytes) {
+  return g.nn <= (int64_t)kBotQ * kBotThreads && bytes <= 64 * 1024;
+}
+
+static size_t bottom_lds64_bytes(const Geom &g) {
+  return sizeof(double) * (size_t)(((g.nc + 1) & ~(int64_t)1) + g.dim * g.nn);
+}
+
+static size_t bottom_lds_mixed_bytes(const Geom &g) {
+  const size_t nc2 = (size_t)((g.nc + 1) & ~(int64_t)1);
+  return sizeof(double) * (nc2 + g.dim * g.nn) + sizeof(float) * (nc2 + g.dim * g.nn);
+}
+
 template <typename T>
 hipError_t launch_bottom_cg(const Level &L, const T *psi, const Coef<T> &C, const T *f, T *x,
                             T *r, T *p, T *Ap, double rtol, int maxit, int *iters,
                             hipStream_t st) {
+  if constexpr (sizeof(T) == 8) {
+    const size_t by = bottom_lds64_bytes(L.g);
+    if (bottom_fits_lds(L.g, by)) {
+      const int nt = bottom_threads(L.g.nn);
+      (void)hipGetLastError();
+      if (L.g.dim == 3) {
+        hipLaunchKernelGGL((k_bottom_lds64<3>), dim3(1), dim3(nt), by, st, L.g, C, psi, f, x,
+                           rtol, maxit, iters);
+      } else {
+        hipLaunchKernelGGL((k_bottom_lds64<2>), dim3(1), dim3(nt), by, st, L.g, C, psi, f, x,
+                           rtol, maxit, iters);
+      }
+      return hipGetLastError();
+    }
+  }
   if (L.g.dim == 3)
     SBM_LAUNCH((k_bottom_cg<T, 3>), 1, kBottomThreads, st, L.g, C, psi, f, x, r, p, Ap, rtol,
                maxit, iters);
@@ -832,6 +1126,20 @@ hipError_t launch_bottom_cg(const Level &L, const T *psi, const Coef<T> &C, cons
 hipError_t launch_bottom_mixed(const Level &L, const float *b32, float *e32, double *x64,
                                double *r64, float *r32, float *p32, float *Ap32, float *d32,
                                double rtol, int maxit, int *iters, hipStream_t st) {
+  const size_t by = bottom_lds_mixed_bytes(L.g);
+  if (L.g.nn <= (int64_t)kBotQMixed * kBotThreads && by <= 64 * 1024) {
+    int nt = (int)(((L.g.nn + kBotQMixed - 1) / kBotQMixed + 63) / 64 * 64);
+    if (nt < 64) nt = 64;
+    (void)hipGetLastError();
+    if (L.g.dim == 3) {
+      hipLaunchKernelGGL((k_bottom_lds_mixed<3>), dim3(1), dim3(nt), by, st, L.g, L.c64, L.c32,
+                         L.psi64, L.psi32, b32, e32, rtol, maxit, iters);
+    } else {
+      hipLaunchKernelGGL((k_bottom_lds_mixed<2>), dim3(1), dim3(nt), by, st, L.g, L.c64, L.c32,
+                         L.psi64, L.psi32, b32, e32, rtol, maxit, iters);
+    }
+    return hipGetLastError();
+  }
   if (L.g.dim == 3)
     SBM_LAUNCH((k_bottom_mixed<3>), 1, kBottomThreads, st, L.g, L.c64, L.c32, L.psi64, L.psi32,
                b32, e32, x64, r64, r32, p32, Ap32, d32, rtol, maxit, iters);

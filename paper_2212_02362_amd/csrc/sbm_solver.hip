@@ -58,12 +58,31 @@ struct sbm_ctx {
   DispValues zero_dv{};
   double fnorm = 0.0;
   int last_bottom_iters = 0;
+  double *x0 = nullptr;  // finest-level iterate (fixed address for captured cycles)
   // live kernel timing (sbm_profile)
   bool prof_on = false;
   std::vector<hipEvent_t> prof_ev;  // pairs
   std::vector<int> prof_cls;        // class of each pair in use
   double prof_ms[SBM_PROF_N] = {0};
   int64_t prof_n[SBM_PROF_N] = {0};
+  // captured V-cycles
+  struct CycleGraph {
+    int precision;
+    const double *f;
+    bool prof;
+    bool failed = false;
+    hipGraphExec_t exec = nullptr;
+    std::vector<hipEvent_t> ev;  // timing pairs recorded inside the graph
+    std::vector<int> cls;
+  };
+  std::vector<CycleGraph *> graphs;
+  CycleGraph *capturing = nullptr;  // graph under capture
+  CycleGraph *pending = nullptr;    // graph launched since the last harvest
+  hipStream_t cap_st = nullptr;
+  int64_t graph_captures = 0, graph_launches = 0;
+  std::string graph_error;
+  double g_lam = NAN, g_mu = NAN;
+  uint32_t g_dmask = 0;
 };
 
 // Brackets one launch sequence with an event pair when profiling is on.
@@ -72,35 +91,55 @@ struct ProfScope {
   int cls;
   bool on;
   size_t pair;
+  std::vector<hipEvent_t> *ev;
   ProfScope(sbm_ctx *c_, int cls_, bool active) : c(c_), cls(cls_), on(c_->prof_on && active) {
     if (!on) return;
-    pair = c->prof_cls.size();
-    while (c->prof_ev.size() < 2 * (pair + 1)) {
+    // inside a capture the pair belongs to the graph and is recorded by every replay
+    ev = c->capturing ? &c->capturing->ev : &c->prof_ev;
+    std::vector<int> &cl = c->capturing ? c->capturing->cls : c->prof_cls;
+    pair = cl.size();
+    while (ev->size() < 2 * (pair + 1)) {
       hipEvent_t e;
       if (hipEventCreate(&e) != hipSuccess) {
         on = false;
         return;
       }
-      c->prof_ev.push_back(e);
+      ev->push_back(e);
     }
-    c->prof_cls.push_back(cls);
-    (void)hipEventRecord(c->prof_ev[2 * pair], c->st);
+    cl.push_back(cls);
+    (void)hipEventRecord((*ev)[2 * pair], c->st);
   }
   ~ProfScope() {
-    if (on) (void)hipEventRecord(c->prof_ev[2 * pair + 1], c->st);
+    if (on) (void)hipEventRecord((*ev)[2 * pair + 1], c->st);
   }
 };
 
-// Collects the elapsed times of completed event pairs (stream is idle).
+// Collects the elapsed times of completed event pairs (stream is idle): the
+// pairs recorded eagerly and those of the last replayed graph.
 static void prof_harvest(sbm_ctx *c) {
-  for (size_t p = 0; p < c->prof_cls.size(); ++p) {
-    float ms = 0.0f;
-    if (hipEventElapsedTime(&ms, c->prof_ev[2 * p], c->prof_ev[2 * p + 1]) == hipSuccess) {
-      c->prof_ms[c->prof_cls[p]] += ms;
-      c->prof_n[c->prof_cls[p]] += 1;
+  auto take = [c](const std::vector<hipEvent_t> &ev, const std::vector<int> &cls) {
+    for (size_t p = 0; p < cls.size(); ++p) {
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, ev[2 * p], ev[2 * p + 1]) == hipSuccess) {
+        c->prof_ms[cls[p]] += ms;
+        c->prof_n[cls[p]] += 1;
+      }
     }
-  }
+  };
+  take(c->prof_ev, c->prof_cls);
   c->prof_cls.clear();
+  if (c->pending) take(c->pending->ev, c->pending->cls);
+  c->pending = nullptr;
+}
+
+static void drop_graphs(sbm_ctx *c) {
+  for (auto *g : c->graphs) {
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    for (hipEvent_t e : g->ev) (void)hipEventDestroy(e);
+    delete g;
+  }
+  c->graphs.clear();
+  c->pending = nullptr;
 }
 
 // ------------------------------------------------------------ grid helpers
@@ -113,7 +152,7 @@ static bool grid_ok(const sbm_grid *g) {
   }
   int64_t nodes = 1;
   for (int a = 0; a < g->dim; ++a) nodes *= g->ncell[a] + 1;
-  return nodes <= ((int64_t)1 << 30);
+  return nodes * g->dim < ((int64_t)1 << 31);  // 32-bit indexing of every vector
 }
 
 static int count_levels(const sbm_grid *g) {
@@ -155,6 +194,11 @@ static void level_shapes(const sbm_grid *g, int nlev, std::vector<Level> &L) {
     G.nn = (int64_t)G.nx * G.ny * G.nz;
     G.nc = (int64_t)G.cx * G.cy * G.cz;
     G.dmask = 0;
+    G.fnx = make_fastdiv((uint32_t)G.nx);
+    G.fny = make_fastdiv((uint32_t)G.ny);
+    G.fcx = make_fastdiv((uint32_t)G.cx);
+    G.fcy = make_fastdiv((uint32_t)G.cy);
+    G.fpx = make_fastdiv((uint32_t)((G.nx + 1) / 2));
   }
 }
 
@@ -190,6 +234,7 @@ static size_t carve(sbm_ctx *c, char *base) {
     maxblocks = std::max<int64_t>(maxblocks, num_blocks(L.g.nn));
     maxblocks = std::max<int64_t>(maxblocks, num_blocks(L.g.nc));
   }
+  c->x0 = cv.take<double>((int64_t)d * c->L[0].g.nn);
   c->npart = (int)maxblocks;
   c->partials = cv.take<double>(maxblocks);
   c->scal = cv.take<double>(16);
@@ -353,8 +398,91 @@ static sbm_status residual_norm2(sbm_ctx *c, const double *u, const double *f, d
   return SBM_OK;
 }
 
+// One cycle of the outer loop on the finest iterate x0 for the load f: an
+// FP64 V-cycle, or (mixed) r32 = (f - K x0)/s, an FP32 V-cycle for e32 from
+// zero, x0 += s e32 with s the residual norm left in scal[0] by the
+// convergence test.
+static hipError_t cycle_body(sbm_ctx *c, const double *f) {
+  Level &L0 = c->L[0];
+  const int64_t nv = (int64_t)c->dim * L0.g.nn;
+  hipError_t e;
+  if (c->opt.precision == 1) {
+    if ((e = launch_residual_cast(L0, c->x0, f, L0.f32, c->scal, c->st)) != hipSuccess) return e;
+    if ((e = launch_fill<float>(L0.e32, nv, 0.0f, c->st)) != hipSuccess) return e;
+    if ((e = vcycle<float>(c, 0, L0.e32, L0.f32, L0.t32)) != hipSuccess) return e;
+    return launch_correct(L0, c->x0, L0.e32, c->scal, c->st);
+  }
+  return vcycle<double>(c, 0, c->x0, f, L0.t);
+}
+
+// Finds or captures the graph of cycle_body for (precision, f, profiling).
+// Returns nullptr when capture is not possible (the cycle then runs eagerly).
+static sbm_ctx::CycleGraph *cycle_graph(sbm_ctx *c, const double *f) {
+  for (auto *g : c->graphs)
+    if (g->precision == c->opt.precision && g->f == f && g->prof == c->prof_on)
+      return g->failed ? nullptr : g;
+  auto *g = new sbm_ctx::CycleGraph();
+  g->precision = c->opt.precision;
+  g->f = f;
+  g->prof = c->prof_on;
+  c->graphs.push_back(g);
+  if (!c->cap_st && hipStreamCreateWithFlags(&c->cap_st, hipStreamNonBlocking) != hipSuccess) {
+    c->cap_st = nullptr;
+    g->failed = true;
+    return nullptr;
+  }
+  hipStream_t user = c->st;
+  c->st = c->cap_st;
+  c->capturing = g;
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamBeginCapture(c->cap_st, hipStreamCaptureModeRelaxed);
+  hipError_t eb = hipSuccess;
+  if (e == hipSuccess) {
+    eb = cycle_body(c, f);
+    e = hipStreamEndCapture(c->cap_st, &graph);
+  }
+  c->capturing = nullptr;
+  c->st = user;
+  if (e == hipSuccess && eb == hipSuccess && graph)
+    e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+  else if (e == hipSuccess)
+    e = eb != hipSuccess ? eb : hipErrorUnknown;
+  if (graph) {
+    hipError_t ed = hipGraphDestroy(graph);
+    if (e == hipSuccess) e = ed;
+  }
+  if (e != hipSuccess) {
+    c->graph_error = hipGetErrorString(e);
+    (void)hipGetLastError();
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    g->exec = nullptr;
+    g->failed = true;
+    return nullptr;
+  }
+  ++c->graph_captures;
+  return g;
+}
+
+static sbm_status run_cycle(sbm_ctx *c, const double *f) {
+  // Live timing brackets single launches with events, so it runs the cycle
+  // launch by launch (event records inside a replayed graph give no timings
+  // on this runtime).
+  if (c->opt.use_graphs && !c->prof_on) {
+    sbm_ctx::CycleGraph *g = cycle_graph(c, f);
+    if (g) {
+      HIP_TRY(hipGraphLaunch(g->exec, c->st));
+      ++c->graph_launches;
+      c->pending = g;
+      return SBM_OK;
+    }
+  }
+  HIP_TRY(cycle_body(c, f));
+  return SBM_OK;
+}
+
 // Outer loop on the finest level for K u = f, u carrying its displacement
-// values; fnorm normalises the residual.
+// values; fnorm normalises the residual.  The iterate lives in x0 during the
+// solve.
 static sbm_status solve_impl(sbm_ctx *c, const double *f, double fnorm, double *u, double *hist,
                              int cap, int *ncyc, double *final_rel) {
   Level &L0 = c->L[0];
@@ -362,9 +490,10 @@ static sbm_status solve_impl(sbm_ctx *c, const double *f, double fnorm, double *
   double rho_min = INFINITY, rho = 0.0;
   int m = 0;
   sbm_status status = SBM_NOT_CONVERGED;
+  HIP_TRY(launch_copy<double>(u, c->x0, nv, c->st));
   for (m = 0;; ++m) {
     double ss = 0.0;
-    sbm_status s = residual_norm2(c, u, f, &ss);
+    sbm_status s = residual_norm2(c, c->x0, f, &ss);
     if (s != SBM_OK) return s;
     rho = fnorm > 0.0 ? sqrt(ss) / fnorm : (ss > 0.0 ? INFINITY : 0.0);
     if (hist && m < cap) hist[m] = rho;
@@ -387,18 +516,12 @@ static sbm_status solve_impl(sbm_ctx *c, const double *f, double fnorm, double *
       status = SBM_NOT_CONVERGED;
       break;
     }
-    if (c->opt.precision == 1) {
-      const double sc = sqrt(ss);
-      HIP_TRY(launch_residual_cast(L0, u, f, L0.f32, 1.0 / sc, c->st));
-      HIP_TRY(launch_fill<float>(L0.e32, nv, 0.0f, c->st));
-      HIP_TRY(vcycle<float>(c, 0, L0.e32, L0.f32, L0.t32));
-      HIP_TRY(launch_correct(L0, u, L0.e32, sc, c->st));
-    } else {
-      HIP_TRY(vcycle<double>(c, 0, u, f, L0.t));
-    }
+    s = run_cycle(c, f);
+    if (s != SBM_OK) return s;
   }
   if (ncyc) *ncyc = m;
   if (final_rel) *final_rel = rho;
+  HIP_TRY(launch_copy<double>(c->x0, u, nv, c->st));
   HIP_TRY(hipStreamSynchronize(c->st));
   if (c->prof_on) prof_harvest(c);
   return status;
@@ -419,6 +542,7 @@ void sbm_default_options(sbm_options *o) {
   o->max_cycles = 200;
   o->bottom_rtol = 1e-12;
   o->bottom_max_iter = 0;
+  o->use_graphs = 1;
 }
 
 const char *sbm_last_error(void) { return g_last_error.c_str(); }
@@ -431,7 +555,8 @@ int sbm_num_levels(const sbm_grid *grid) {
 static bool opts_ok(const sbm_options *o) {
   return o && (o->smoother == 0 || o->smoother == 1) && o->nu_pre >= 0 && o->nu_post >= 0 &&
          (o->precision == 0 || o->precision == 1) && o->rtol >= 0.0 && o->max_cycles >= 0 &&
-         o->bottom_rtol >= 0.0 && isfinite(o->omega) && o->omega >= 0.0 && o->omega < 2.0;
+         o->bottom_rtol >= 0.0 && isfinite(o->omega) && o->omega >= 0.0 && o->omega < 2.0 &&
+         (o->use_graphs == 0 || o->use_graphs == 1);
 }
 
 size_t sbm_workspace_bytes(const sbm_grid *grid, const sbm_options *opts) {
@@ -477,12 +602,23 @@ sbm_status sbm_create(const sbm_grid *grid, const sbm_options *opts, void *works
 sbm_status sbm_set_options(sbm_ctx *c, const sbm_options *opts) {
   if (!c) return fail(SBM_E_ARG, "ctx is NULL");
   if (!opts_ok(opts)) return fail(SBM_E_ARG, "invalid options");
+  const sbm_options &o = c->opt;
+  const bool same = o.smoother == opts->smoother && o.omega == opts->omega &&
+                    o.nu_pre == opts->nu_pre && o.nu_post == opts->nu_post &&
+                    o.bottom_rtol == opts->bottom_rtol && o.bottom_max_iter == opts->bottom_max_iter;
+  if (!same) {
+    HIP_TRY(hipStreamSynchronize(c->st));
+    drop_graphs(c);
+  }
   c->opt = *opts;
   return SBM_OK;
 }
 
 void sbm_destroy(sbm_ctx *c) {
   if (!c) return;
+  (void)hipStreamSynchronize(c->st);
+  drop_graphs(c);
+  if (c->cap_st) (void)hipStreamDestroy(c->cap_st);
   if (c->host) (void)hipHostFree(c->host);
   for (hipEvent_t e : c->prof_ev) (void)hipEventDestroy(e);
   delete c;
@@ -497,6 +633,14 @@ sbm_status sbm_profile(sbm_ctx *c, int enable) {
     c->prof_n[k] = 0;
   }
   c->prof_on = enable != 0;
+  return SBM_OK;
+}
+
+sbm_status sbm_graph_info(sbm_ctx *c, int64_t *captures, int64_t *launches) {
+  if (!c || !captures || !launches) return fail(SBM_E_ARG, "NULL argument");
+  *captures = c->graph_captures;
+  *launches = c->graph_launches;
+  if (!c->graph_error.empty()) g_last_error = "last capture failed: " + c->graph_error;
   return SBM_OK;
 }
 
@@ -539,6 +683,14 @@ static sbm_status set_problem_impl(sbm_ctx *c, const double *psi_raw, int cube,
         else c->dv.v[F][k] = bc->value[F][k];
       }
     }
+  }
+  if (!(c->g_lam == mat->lambda && c->g_mu == mat->mu && c->g_dmask == dmask)) {
+    // captured cycles hold the coefficients and masks as kernel arguments
+    HIP_TRY(hipStreamSynchronize(c->st));
+    drop_graphs(c);
+    c->g_lam = mat->lambda;
+    c->g_mu = mat->mu;
+    c->g_dmask = dmask;
   }
   for (int l = 0; l < c->nlev; ++l) {
     c->L[l].g.dmask = dmask;

@@ -229,6 +229,12 @@ class Solver:
         check(lib().sbm_profile_read(self._ctx, ms, cnt))
         return {k: (ms[i], int(cnt[i])) for i, k in enumerate(PROF_CLASSES)}
 
+    def graph_info(self):
+        """(captures, graph launches) of the V-cycle graphs of this context."""
+        a, b = ctypes.c_int64(0), ctypes.c_int64(0)
+        check(lib().sbm_graph_info(self._ctx, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
     # ----------------------------------------------------- component steps
     def _level_nodes(self, level, dtype=torch.float64):
         nc = self.level_shape(level)

@@ -104,9 +104,11 @@ def test_transfers(ncell):
     assert rel_max(got, ref) < 1e-14
 
 
-@pytest.mark.parametrize("ncell", [(16, 16), (24, 12, 12), (8, 8, 8)])
+@pytest.mark.parametrize("ncell", [(16, 16), (24, 12, 12), (8, 8, 8), (35, 33)])
 def test_bottom_cg(ncell):
-    """The single-workgroup CG on the bottom grid reaches the dense solution."""
+    """The single-workgroup CG on the bottom grid reaches the dense solution
+    (LDS-resident up to 1024 nodes; (35, 33) cannot be coarsened, so its
+    1224-node bottom takes the global-memory variant)."""
     p, S, psi, mask, u, f = _setup(ncell, seed=4)
     L = S.nlevels - 1
     ncb = S.level_shape(L)

@@ -4,8 +4,12 @@ versions of the 3D workloads).
 
 Protocol: the oracle solves to a relative residual of 1e-10 in m* V-cycles;
 the GPU runs exactly m* cycles (rtol 0, max_cycles m*) with the same options.
-Bar: every residual of the history agrees to 1e-6 relative and the
-displacement to 1e-9 relative L2.  The mixed-precision solve converges to the
+Bar: every residual of the history agrees to 1e-6 relative plus an absolute
+1e-13, and the displacement to 1e-9 relative L2.  The absolute term is the
+FP64 rounding floor of evaluating rho = ||f - K u|| / ||f||: each entry of
+K u is a sum of O(20) stencil terms of size up to ~1e3 |f|, so summation
+order alone moves rho by ~1e-15..1e-14 whatever the iterate; 1e-13 leaves a
+decade of margin above the largest difference observed (5e-15).  The mixed-precision solve converges to the
 same tolerance; its error against the FP64 oracle is reported and bounded."""
 import numpy as np
 import pytest
@@ -15,6 +19,8 @@ from _util import oracle_solve, random_problem, rel_l2, say, solver_for, to_np
 
 pytestmark = pytest.mark.gpu
 
+RHO_ATOL = 1e-13  # rounding floor of the FP64 residual evaluation (module docstring)
+
 CASES = {
     "plate_void_2d_64": lambda: si.plate_void_2d(64),
     "spherical_voids_16": lambda: si.spherical_voids_3d(16),
@@ -23,6 +29,8 @@ CASES = {
     "cantilever_24x12x12": lambda: si.cantilever_density_3d(24, 12, 12),
     "random_mixed_2d_40x24": lambda: random_problem((40, 24), seed=3),
     "random_mixed_3d_16x8x12": lambda: random_problem((16, 8, 12), seed=4, floor=1e-3),
+    # 624-node bottom: LDS CG in FP64, global-memory CG in the mixed cycle
+    "random_mixed_2d_50x46": lambda: random_problem((50, 46), seed=5, floor=1e-2),
 }
 
 
@@ -42,12 +50,13 @@ def test_fp64_trajectory_parity(case, smoother):
     say("fp64 parity", case, "smoother", smoother)
     S, u_o, hist_o, u_g, hist_g, st_g, m = _run_pair(p, smoother)
     assert len(hist_g) == m + 1
-    assert np.all(np.abs(hist_g - hist_o) <= 1e-6 * hist_o), np.abs(hist_g / hist_o - 1).max()
+    dh = np.abs(hist_g - hist_o)
+    assert np.all(dh <= 1e-6 * hist_o + RHO_ATOL), dh.max()
     assert rel_l2(u_g, u_o) <= 1e-9, rel_l2(u_g, u_o)
 
 
 @pytest.mark.parametrize("case", ["plate_void_2d_64", "spherical_voids_32", "cantilever_24x12x12",
-                                  "random_mixed_3d_16x8x12"])
+                                  "random_mixed_3d_16x8x12", "random_mixed_2d_50x46"])
 def test_mixed_precision_converges_to_fp64_solution(case):
     p = CASES[case]()
     say("mixed", case)
@@ -101,5 +110,34 @@ def test_adjoint_solve_parity(case):
     S = solver_for(p, rtol=0.0, max_cycles=m)
     say("adjoint", case)
     x, hist, st = S.solve_rhs(g)
-    assert np.all(np.abs(hist - hist_o) <= 1e-6 * hist_o)
+    assert np.all(np.abs(hist - hist_o) <= 1e-6 * hist_o + RHO_ATOL)
     assert rel_l2(to_np(x), u_o) <= 1e-9
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_graph_replay_matches_eager(precision):
+    """Captured V-cycles replayed from a HIP graph give bit-identical
+    histories and solutions to kernel-by-kernel launches, across repeated
+    solves with eager work (problem setup, norms, copies) in between; a timed
+    solve afterwards (launch by launch) still agrees."""
+    p = CASES["spherical_voids_32"]()
+    say("graph vs eager", precision)
+    S1 = solver_for(p, precision=precision, use_graphs=0, rtol=1e-10)
+    S2 = solver_for(p, precision=precision, use_graphs=1, rtol=1e-10)
+    u1, h1, _ = S1.solve()
+    u1 = to_np(u1)
+    for rep in range(3):
+        S2.set_problem_from(p)
+        if rep == 2:
+            S2.profile(True)
+        u2, h2, _ = S2.solve()
+        assert np.array_equal(h2, h1), rep
+        assert np.array_equal(to_np(u2), u1), rep
+    prof = S2.profile_read()
+    S2.profile(False)
+    ncyc = len(h1) - 1
+    captures, launches = S2.graph_info()
+    assert S1.graph_info() == (0, 0)
+    assert captures == 1 and launches == 2 * ncyc  # the timed solve runs launch by launch
+    assert prof["smooth"][1] == 2 * 4 * ncyc and prof["smooth"][0] > 0
+    assert prof["bottom"][1] == ncyc
