@@ -103,7 +103,12 @@ typedef struct {
  *   bottom_max_iter CG iteration cap; <= 0 means 4 x free bottom DOF [0]
  *   use_graphs     1: each V-cycle is captured once into a HIP graph and
  *                  replayed (same kernels, same order, fewer launches) [1];
- *                  0: kernels are launched one by one */
+ *                  0: kernels are launched one by one
+ *   krylov         0: stationary V-cycle iteration [0]; 1: flexible conjugate
+ *                  gradients (Polak-Ribiere) preconditioned by one V-cycle
+ *                  from zero per iteration, post-smoothing colours reversed
+ *                  (black, red); the history then has one entry per CG
+ *                  iteration and max_cycles caps the iterations */
 typedef struct {
   int smoother;
   double omega;
@@ -114,6 +119,7 @@ typedef struct {
   double bottom_rtol;
   int bottom_max_iter;
   int use_graphs;
+  int krylov;
 } sbm_options;
 
 /* Fills *opts with the defaults above. */

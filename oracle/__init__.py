@@ -217,8 +217,9 @@ def num_levels(ncell):
 
 def solve(ncell, h, lam, mu, psi_raw, psi_floor, kind, val, b=None, *, smoother=0,
           omega=None, nu_pre=2, nu_post=2, rtol=1e-10, max_cycles=200, bottom_rtol=1e-12,
-          bottom_max_iter=0, u0=None):
-    """FP64 V-cycle solve. Returns (u, hist, status)."""
+          bottom_max_iter=0, krylov=0, u0=None):
+    """FP64 solve by V-cycles (krylov=0) or V-cycle-preconditioned flexible
+    CG (krylov=1).  Returns (u, hist, status)."""
     d = len(ncell)
     if omega is None:
         omega = 1.0 if smoother == 0 else 0.8
@@ -232,7 +233,7 @@ def solve(ncell, h, lam, mu, psi_raw, psi_floor, kind, val, b=None, *, smoother=
                          k.ctypes.data_as(_ip), _d(v), _d(bb), int(smoother),
                          ctypes.c_double(omega), int(nu_pre), int(nu_post), ctypes.c_double(rtol),
                          int(max_cycles), ctypes.c_double(bottom_rtol), int(bottom_max_iter),
-                         _d(u), _d(hist), int(max_cycles + 1), ctypes.byref(ncyc))
+                         int(krylov), _d(u), _d(hist), int(max_cycles + 1), ctypes.byref(ncyc))
     return u, hist[: ncyc.value + 1].copy(), st
 
 

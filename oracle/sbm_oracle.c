@@ -526,9 +526,10 @@ void orc_coarsen_psi(int dim, const long *nc_fine, const double *psi_f, double *
 
 /* -------------------------------------------------------------- bottom -- */
 
-/* Unpreconditioned CG on the free DOF: solves K_FF d = (f - K x)_F and adds d
- * to x.  Stops when ||r|| <= rtol ||r0|| or after maxit iterations.  Returns
- * the iteration count. */
+/* Conjugate gradients with diagonal (Jacobi) preconditioning on the free DOF:
+ * solves K_FF d = (f - K x)_F and adds d to x.  Stops when ||r|| <= rtol ||r0||
+ * (unpreconditioned residual) or after maxit iterations.  Returns the
+ * iteration count. */
 int orc_cg(int dim, const long *nc, const double *h, double lam, double mu,
            const double *psi, const uint8_t *mask, const double *f, double *x,
            double rtol, int maxit) {
@@ -536,36 +537,48 @@ int orc_cg(int dim, const long *nc, const double *h, double lam, double mu,
   grid_init(&g, dim, nc, h, lam, mu);
   long n3 = (long)dim * g.NN;
   double *r = (double *)malloc(sizeof(double) * n3);
+  double *z = (double *)malloc(sizeof(double) * n3);
   double *p = (double *)malloc(sizeof(double) * n3);
   double *Ap = (double *)malloc(sizeof(double) * n3);
+  double *D = (double *)malloc(sizeof(double) * n3);
+  orc_diag(dim, nc, h, lam, mu, psi, D);
   orc_residual(dim, nc, h, lam, mu, psi, mask, x, f, r);
-  double rr = 0.0;
-  for (long q = 0; q < n3; ++q) rr += r[q] * r[q];
+  double rr = 0.0, rz = 0.0;
+  for (long q = 0; q < n3; ++q) {
+    z[q] = mask[q] ? 0.0 : r[q] / D[q];
+    rr += r[q] * r[q];
+    rz += r[q] * z[q];
+  }
   double r0 = sqrt(rr);
   int it = 0;
-  for (long q = 0; q < n3; ++q) p[q] = r[q];
+  for (long q = 0; q < n3; ++q) p[q] = z[q];
   while (r0 > 0.0 && sqrt(rr) > rtol * r0 && it < maxit) {
     orc_apply(dim, nc, h, lam, mu, psi, p, Ap); /* p is zero on Dirichlet DOF */
     double pAp = 0.0;
     for (long q = 0; q < n3; ++q)
       if (!mask[q]) pAp += p[q] * Ap[q];
     if (!(pAp > 0.0)) break;
-    double alpha = rr / pAp;
-    double rr_new = 0.0;
+    double alpha = rz / pAp;
+    double rr_new = 0.0, rz_new = 0.0;
     for (long q = 0; q < n3; ++q) {
       if (mask[q]) continue;
       x[q] += alpha * p[q];
       r[q] -= alpha * Ap[q];
+      z[q] = r[q] / D[q];
       rr_new += r[q] * r[q];
+      rz_new += r[q] * z[q];
     }
-    double beta = rr_new / rr;
+    double beta = rz_new / rz;
     rr = rr_new;
-    for (long q = 0; q < n3; ++q) p[q] = mask[q] ? 0.0 : r[q] + beta * p[q];
+    rz = rz_new;
+    for (long q = 0; q < n3; ++q) p[q] = mask[q] ? 0.0 : z[q] + beta * p[q];
     ++it;
   }
   free(r);
+  free(z);
   free(p);
   free(Ap);
+  free(D);
   return it;
 }
 
@@ -579,6 +592,7 @@ typedef struct {
   int max_cycles;
   double bottom_rtol;
   int bottom_max_iter; /* <= 0: 4 x (number of free DOF) */
+  int krylov;          /* 1: V-cycle-preconditioned flexible CG (post-smoothing black first) */
 } orc_opts;
 
 typedef struct {
@@ -606,14 +620,17 @@ static int count_levels(int dim, const long *nc) {
 
 int orc_num_levels(int dim, const long *nc) { return count_levels(dim, nc); }
 
+/* reverse: colours in the order black, red (the adjoint of red, black), used
+ * for post-smoothing when the V-cycle preconditions CG. */
 static void smooth(int dim, level_t *L, double lam, double mu, const orc_opts *o,
-                   double *x, const double *f, int sweeps) {
+                   double *x, const double *f, int sweeps, int reverse) {
   for (int s = 0; s < sweeps; ++s) {
     if (o->smoother == 1) {
       orc_jacobi(dim, L->nc, L->h, lam, mu, L->psi, L->mask, o->omega, x, f, L->tmp);
       memcpy(x, L->tmp, sizeof(double) * L->n3);
     } else {
-      for (int c = 0; c < 2; ++c) {
+      for (int k = 0; k < 2; ++k) {
+        int c = reverse ? 1 - k : k;
         orc_rb_half(dim, L->nc, L->h, lam, mu, L->psi, L->mask, o->omega, c, x, f, L->tmp);
         memcpy(x, L->tmp, sizeof(double) * L->n3);
       }
@@ -636,13 +653,13 @@ static void vcycle(int dim, level_t *lev, int nlev, int l, double lam, double mu
     return;
   }
   level_t *C = &lev[l + 1];
-  smooth(dim, L, lam, mu, o, x, f, o->nu_pre);
+  smooth(dim, L, lam, mu, o, x, f, o->nu_pre, 0);
   orc_residual(dim, L->nc, L->h, lam, mu, L->psi, L->mask, x, f, L->r);
   orc_restrict(dim, L->nc, L->r, C->mask, C->f);
   memset(C->e, 0, sizeof(double) * C->n3);
   vcycle(dim, lev, nlev, l + 1, lam, mu, o, C->e, C->f);
   orc_prolong_add(dim, C->nc, C->e, L->mask, x);
-  smooth(dim, L, lam, mu, o, x, f, o->nu_post);
+  smooth(dim, L, lam, mu, o, x, f, o->nu_post, o->krylov);
 }
 
 /* Full FP64 solve.  u: in = initial guess, out = solution (Dirichlet DOF set to
@@ -652,8 +669,9 @@ int orc_solve(int dim, const long *nc, const double *h, double lam, double mu,
               const double *psi_raw, double psi_floor, const int *kind, const double *val,
               const double *b, int smoother, double omega, int nu_pre, int nu_post,
               double rtol, int max_cycles, double bottom_rtol, int bottom_max_iter,
-              double *u, double *hist, int hist_cap, int *n_cycles) {
-  orc_opts o = {smoother, omega, nu_pre, nu_post, rtol, max_cycles, bottom_rtol, bottom_max_iter};
+              int krylov, double *u, double *hist, int hist_cap, int *n_cycles) {
+  orc_opts o = {smoother, omega, nu_pre, nu_post, rtol, max_cycles, bottom_rtol, bottom_max_iter,
+                krylov};
   int nlev = count_levels(dim, nc);
   level_t *lev = (level_t *)calloc(nlev, sizeof(level_t));
   for (int l = 0; l < nlev; ++l) {
@@ -684,13 +702,68 @@ int orc_solve(int dim, const long *nc, const double *h, double lam, double mu,
     if (T->mask[q]) u[q] = uD[q];
   double fn = norm2_free(T->n3, fB, T->mask);
   int status = 1, m = 0;
-  for (m = 0;; ++m) {
-    orc_residual(dim, T->nc, T->h, lam, mu, T->psi, T->mask, u, fA, T->r);
-    double rho = fn > 0.0 ? norm2_free(T->n3, T->r, T->mask) / fn : 0.0;
-    if (m < hist_cap) hist[m] = rho;
-    if (rho <= rtol) { status = 0; break; }
-    if (m >= max_cycles) break;
-    vcycle(dim, lev, nlev, 0, lam, mu, &o, u, fA);
+  if (!krylov) {
+    for (m = 0;; ++m) {
+      orc_residual(dim, T->nc, T->h, lam, mu, T->psi, T->mask, u, fA, T->r);
+      double rho = fn > 0.0 ? norm2_free(T->n3, T->r, T->mask) / fn : 0.0;
+      if (m < hist_cap) hist[m] = rho;
+      if (rho <= rtol) { status = 0; break; }
+      if (m >= max_cycles) break;
+      vcycle(dim, lev, nlev, 0, lam, mu, &o, u, fA);
+    }
+  } else {
+    /* Flexible preconditioned CG (Polak-Ribiere beta), one V-cycle from zero
+     * per iteration as the preconditioner z = M r. */
+    long n3 = T->n3;
+    double *r = (double *)malloc(sizeof(double) * n3), *z = (double *)malloc(sizeof(double) * n3);
+    double *pv = (double *)malloc(sizeof(double) * n3), *q = (double *)malloc(sizeof(double) * n3);
+    orc_residual(dim, T->nc, T->h, lam, mu, T->psi, T->mask, u, fA, r);
+    double rho = fn > 0.0 ? norm2_free(n3, r, T->mask) / fn : 0.0;
+    if (hist_cap > 0) hist[0] = rho;
+    int restart = 1;
+    double rz = 0.0;
+    for (m = 0;;) {
+      if (rho <= rtol) { status = 0; break; }
+      if (m >= max_cycles) break;
+      if (restart) {
+        memset(z, 0, sizeof(double) * n3);
+        vcycle(dim, lev, nlev, 0, lam, mu, &o, z, r);
+        rz = 0.0;
+        for (long i = 0; i < n3; ++i) if (!T->mask[i]) rz += r[i] * z[i];
+        for (long i = 0; i < n3; ++i) pv[i] = T->mask[i] ? 0.0 : z[i];
+        restart = 0;
+      }
+      orc_apply(dim, T->nc, T->h, lam, mu, T->psi, pv, q);
+      double pq = 0.0;
+      for (long i = 0; i < n3; ++i) if (!T->mask[i]) pq += pv[i] * q[i];
+      if (!(pq > 0.0)) break;
+      double alpha = rz / pq, rzold = 0.0;
+      for (long i = 0; i < n3; ++i) {
+        if (T->mask[i]) continue;
+        u[i] += alpha * pv[i];
+        r[i] -= alpha * q[i];
+        rzold += r[i] * z[i];
+      }
+      ++m;
+      rho = fn > 0.0 ? norm2_free(n3, r, T->mask) / fn : 0.0;
+      if (rho <= rtol) {
+        /* accept only if the true residual agrees; else restart from it */
+        orc_residual(dim, T->nc, T->h, lam, mu, T->psi, T->mask, u, fA, r);
+        rho = fn > 0.0 ? norm2_free(n3, r, T->mask) / fn : 0.0;
+        if (m < hist_cap) hist[m] = rho;
+        if (rho > rtol) restart = 1;
+        continue;
+      }
+      if (m < hist_cap) hist[m] = rho;
+      memset(z, 0, sizeof(double) * n3);
+      vcycle(dim, lev, nlev, 0, lam, mu, &o, z, r);
+      double rznew = 0.0;
+      for (long i = 0; i < n3; ++i) if (!T->mask[i]) rznew += r[i] * z[i];
+      double beta = (rznew - rzold) / rz;
+      rz = rznew;
+      for (long i = 0; i < n3; ++i) pv[i] = T->mask[i] ? 0.0 : z[i] + beta * pv[i];
+    }
+    free(r); free(z); free(pv); free(q);
   }
   *n_cycles = m;
   for (int l = 0; l < nlev; ++l) {

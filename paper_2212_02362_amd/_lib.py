@@ -39,7 +39,8 @@ class SbmOptions(ctypes.Structure):
     _fields_ = [("smoother", ctypes.c_int), ("omega", ctypes.c_double), ("nu_pre", ctypes.c_int),
                 ("nu_post", ctypes.c_int), ("precision", ctypes.c_int), ("rtol", ctypes.c_double),
                 ("max_cycles", ctypes.c_int), ("bottom_rtol", ctypes.c_double),
-                ("bottom_max_iter", ctypes.c_int), ("use_graphs", ctypes.c_int)]
+                ("bottom_max_iter", ctypes.c_int), ("use_graphs", ctypes.c_int),
+                ("krylov", ctypes.c_int)]
 
 
 _P = ctypes.c_void_p

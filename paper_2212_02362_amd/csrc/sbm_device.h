@@ -209,6 +209,32 @@ __device__ __forceinline__ void node_stencil(const Geom &g, const Coef<T> &C,
   }
 }
 
+// Diagonal of K at node (i, j, k) (the Jacobi D of Sec. 2.3): the direct
+// part's edge sums only.
+template <typename T, int DIM>
+__device__ __forceinline__ void node_diag(const Geom &g, const Coef<T> &C,
+                                          const T *__restrict__ psi, int i, int j, int k,
+                                          T diag[3]) {
+  T E[3][2] = {{T(0), T(0)}, {T(0), T(0)}, {T(0), T(0)}};
+#pragma unroll
+  for (int o = 0; o < (1 << DIM); ++o) {
+    const int b0 = o & 1, b1 = (o >> 1) & 1, b2 = (o >> 2) & 1;
+    const int xi = i - 1 + b0, yj = j - 1 + b1, zk = (DIM == 3) ? k - 1 + b2 : 0;
+    const bool in = xi >= 0 && xi < g.cx && yj >= 0 && yj < g.cy && zk >= 0 && zk < g.cz;
+    const T v = in ? psi[xi + g.cx * (yj + g.cy * zk)] : T(0);
+    E[0][b0] += v;
+    E[1][b1] += v;
+    if (DIM == 3) E[2][b2] += v;
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    diag[c] = T(0);
+    if (c >= DIM) continue;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) diag[c] += C.cd[c][a] * (E[a][0] + E[a][1]);
+  }
+}
+
 // Sum over a block of kBlock threads in a fixed order; the result is valid in
 // thread 0.  lds must hold kBlock/64 doubles.
 __device__ __forceinline__ double block_sum(double v, double *lds) {

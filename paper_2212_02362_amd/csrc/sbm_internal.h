@@ -74,6 +74,17 @@ hipError_t launch_finalize_sum(const double *partials, int n, double *out, hipSt
 hipError_t launch_dot_free(const Level &L, const double *a, const double *b, double *partials,
                            hipStream_t st);
 hipError_t launch_sumsq_free(const Level &L, const double *v, double *partials, hipStream_t st);
+hipError_t launch_apply_dot(const Level &L, const double *p, double *q, double *partials,
+                           hipStream_t st);
+hipError_t launch_cg_update(const Level &L, double *x, double *r, const double *p, const double *q,
+                            const double *z, const double *rz, const double *pq, double *pr,
+                            double *pz, hipStream_t st);
+hipError_t launch_xpby(const Level &L, double *p, const double *z, const double *rznew,
+                       const double *rzold, const double *rz, hipStream_t st);
+hipError_t launch_cast_scaled(const double *r, float *r32, int64_t n, const double *ss,
+                              hipStream_t st);
+hipError_t launch_scale_set(double *z, const float *e32, int64_t n, const double *ss,
+                            hipStream_t st);
 int num_blocks(int64_t n);
 template <typename T>
 hipError_t launch_bottom_cg(const Level &L, const T *psi, const Coef<T> &C, const T *f, T *x,

@@ -424,25 +424,145 @@ __global__ __launch_bounds__(kBlock) void k_dot_free(Geom g, const double *__res
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
+// ------------------------------------------------------------- Krylov ops --
+// Vectors of the flexible CG on the finest level; every reduction writes one
+// deterministic partial per block.
+
+// q = K p on free DOF (0 on displacement DOF); partials of p.q.
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_apply_dot(Geom g, Coef<double> C,
+                                                      const double *__restrict__ psi,
+                                                      const double *__restrict__ p,
+                                                      double *__restrict__ q,
+                                                      double *__restrict__ partials) {
+  __shared__ double lds[kBlock / 64 + 1];
+  const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  double ss = 0.0;
+  if (id < g.nn) {
+    int i, j, k;
+    node_ijk(g, id, i, j, k);
+    double out[3], dg[3];
+    node_stencil<double, DIM>(g, C, psi, p, i, j, k, out, dg);
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+      const int64_t qi = c * g.nn + id;
+      const double v = is_dirichlet(g, i, j, k, c) ? 0.0 : out[c];
+      q[qi] = v;
+      ss += p[qi] * v;
+    }
+  }
+  const double s = block_sum(ss, lds);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// x += alpha p, r -= alpha q on free DOF, alpha = rz / pq read from device
+// scalars; partials of r.r (pr) and r.z (pz, z = the previous preconditioned
+// residual).
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_cg_update(Geom g, double *__restrict__ x,
+                                                      double *__restrict__ r,
+                                                      const double *__restrict__ p,
+                                                      const double *__restrict__ q,
+                                                      const double *__restrict__ z,
+                                                      const double *__restrict__ rz,
+                                                      const double *__restrict__ pq,
+                                                      double *__restrict__ pr,
+                                                      double *__restrict__ pz) {
+  __shared__ double lds[kBlock / 64 + 1];
+  const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const double alpha = *rz / *pq;
+  double srr = 0.0, srz = 0.0;
+  if (id < g.nn) {
+    int i, j, k;
+    node_ijk(g, id, i, j, k);
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+      if (is_dirichlet(g, i, j, k, c)) continue;
+      const int64_t qi = c * g.nn + id;
+      x[qi] += alpha * p[qi];
+      const double rv = r[qi] - alpha * q[qi];
+      r[qi] = rv;
+      srr += rv * rv;
+      srz += rv * z[qi];
+    }
+  }
+  const double a = block_sum(srr, lds);
+  __syncthreads();
+  const double b = block_sum(srz, lds);
+  if (threadIdx.x == 0) {
+    pr[blockIdx.x] = a;
+    pz[blockIdx.x] = b;
+  }
+}
+
+// p = z + beta p on free DOF (0 on displacement DOF), beta = (rznew - rzold) / rz
+// from device scalars (beta = 0 when rz is NULL: restart).
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_xpby(Geom g, double *__restrict__ p,
+                                                 const double *__restrict__ z,
+                                                 const double *__restrict__ rznew,
+                                                 const double *__restrict__ rzold,
+                                                 const double *__restrict__ rz) {
+  const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (id >= g.nn) return;
+  const double beta = rz ? (*rznew - *rzold) / *rz : 0.0;
+  int i, j, k;
+  node_ijk(g, id, i, j, k);
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) {
+    const int64_t qi = c * g.nn + id;
+    p[qi] = is_dirichlet(g, i, j, k, c) ? 0.0 : z[qi] + (rz ? beta * p[qi] : 0.0);
+  }
+}
+
+// r32 = fp32(r / s) and z = s * e32 (s = sqrt(*ss)): the FP32 preconditioner
+// of the mixed flexible CG sees a unit-norm residual.
+__global__ __launch_bounds__(kBlock) void k_cast_scaled(const double *__restrict__ r,
+                                                        float *__restrict__ r32, int64_t n,
+                                                        const double *__restrict__ ss) {
+  const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (q >= n) return;
+  const double sn = sqrt(*ss);
+  r32[q] = sn > 0.0 ? (float)(r[q] / sn) : 0.0f;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scale_set(double *__restrict__ z,
+                                                      const float *__restrict__ e32, int64_t n,
+                                                      const double *__restrict__ ss) {
+  const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (q >= n) return;
+  z[q] = sqrt(*ss) * (double)e32[q];
+}
+
 // ----------------------------------------------------------------- bottom --
 
 constexpr int kBottomThreads = 256;  // keeps the per-thread state of the global-memory CG in registers
 
-// CG on the free DOF, one workgroup.  On entry r holds the initial residual
-// (0 on displacement DOF) and x the initial iterate; returns the iterations.
-// Dot products are accumulated in FP64 whatever T is.
+// Jacobi-preconditioned CG on the free DOF, one workgroup, vectors in global
+// memory (the variant for bottom grids too large for LDS).  On entry r holds
+// the initial residual (0 on displacement DOF) and x the initial iterate;
+// stops when ||r|| <= rtol ||r0||; returns the iterations.  Dot products are
+// accumulated in FP64 whatever T is.
 template <typename T, int DIM>
 __device__ int cg_core(const Geom &g, const Coef<T> &C, const T *__restrict__ psi, T *x, T *r,
                        T *p, T *Ap, double rtol, int maxit, double *lds) {
   const int64_t n = g.nn;
-  double loc = 0.0;
-  for (int64_t id = threadIdx.x; id < n; id += blockDim.x)
+  double lrr = 0.0, lrz = 0.0;
+  for (int64_t id = threadIdx.x; id < n; id += blockDim.x) {
+    int i, j, k;
+    node_ijk(g, id, i, j, k);
+    T dg[3];
+    node_diag<T, DIM>(g, C, psi, i, j, k, dg);
     for (int c = 0; c < DIM; ++c) {
       const T v = r[c * n + id];
-      p[c * n + id] = v;
-      loc += (double)v * (double)v;
+      const T z = is_dirichlet(g, i, j, k, c) ? T(0) : v / dg[c];
+      p[c * n + id] = z;
+      lrr += (double)v * (double)v;
+      lrz += (double)v * (double)z;
     }
-  double rr = block_allsum(loc, lds);
+  }
+  double rr = block_allsum(lrr, lds);
+  double rz = block_allsum(lrz, lds);
   const double r0 = sqrt(rr);
   int it = 0;
   while (r0 > 0.0 && sqrt(rr) > rtol * r0 && it < maxit) {
@@ -461,30 +581,39 @@ __device__ int cg_core(const Geom &g, const Coef<T> &C, const T *__restrict__ ps
     }
     pap = block_allsum(pap, lds);
     if (!(pap > 0.0)) break;
-    const double alpha = rr / pap;
-    double rn = 0.0;
+    const double alpha = rz / pap;
+    double nrr = 0.0, nrz = 0.0;
     for (int64_t id = threadIdx.x; id < n; id += blockDim.x) {
       int i, j, k;
       node_ijk(g, id, i, j, k);
+      T dg[3];
+      node_diag<T, DIM>(g, C, psi, i, j, k, dg);
       for (int c = 0; c < DIM; ++c) {
         if (is_dirichlet(g, i, j, k, c)) continue;
         const int64_t q = c * n + id;
         x[q] = (T)((double)x[q] + alpha * (double)p[q]);
         const T rv = (T)((double)r[q] - alpha * (double)Ap[q]);
         r[q] = rv;
-        rn += (double)rv * (double)rv;
+        nrr += (double)rv * (double)rv;
+        nrz += (double)rv * ((double)rv / (double)dg[c]);
       }
     }
-    rn = block_allsum(rn, lds);
-    const double beta = rn / rr;
-    rr = rn;
+    nrr = block_allsum(nrr, lds);
+    nrz = block_allsum(nrz, lds);
+    const double beta = nrz / rz;
+    rr = nrr;
+    rz = nrz;
     __syncthreads();
     for (int64_t id = threadIdx.x; id < n; id += blockDim.x) {
       int i, j, k;
       node_ijk(g, id, i, j, k);
+      T dg[3];
+      node_diag<T, DIM>(g, C, psi, i, j, k, dg);
       for (int c = 0; c < DIM; ++c) {
         const int64_t q = c * n + id;
-        p[q] = is_dirichlet(g, i, j, k, c) ? T(0) : (T)((double)r[q] + beta * (double)p[q]);
+        p[q] = is_dirichlet(g, i, j, k, c)
+                   ? T(0)
+                   : (T)((double)r[q] / (double)dg[c] + beta * (double)p[q]);
       }
     }
     ++it;
@@ -588,14 +717,19 @@ constexpr int kBotQ = 4;          // nodes per thread
 constexpr int kBotThreads = 256;  // at most: the per-thread state stays in registers
 
 struct BotRed {
-  double *buf;  // 2 x 16 doubles of LDS
+  double *buf;  // 2 phases x 32 doubles of LDS
   int phase;
 };
 
-__device__ __forceinline__ double bot_allsum(double v, BotRed &R) {
+__device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  double *b = R.buf + 16 * R.phase;
+  return v;
+}
+
+__device__ __forceinline__ double bot_allsum(double v, BotRed &R) {
+  v = wave_sum(v);
+  double *b = R.buf + 32 * R.phase;
   R.phase ^= 1;
   if ((threadIdx.x & 63) == 0) b[threadIdx.x >> 6] = v;
   __syncthreads();
@@ -605,26 +739,57 @@ __device__ __forceinline__ double bot_allsum(double v, BotRed &R) {
   return s;
 }
 
-// CG on K_FF d = r (d from 0) with p and psi in LDS; r and d in registers.
-// Returns iterations; on return d holds the solution increment.
+// Two sums with one barrier.
+__device__ __forceinline__ void bot_allsum2(double &v0, double &v1, BotRed &R) {
+  v0 = wave_sum(v0);
+  v1 = wave_sum(v1);
+  double *b = R.buf + 32 * R.phase;
+  R.phase ^= 1;
+  if ((threadIdx.x & 63) == 0) {
+    b[threadIdx.x >> 6] = v0;
+    b[16 + (threadIdx.x >> 6)] = v1;
+  }
+  __syncthreads();
+  const int nw = blockDim.x >> 6;
+  double s0 = 0.0, s1 = 0.0;
+  for (int w = 0; w < nw; ++w) {
+    s0 += b[w];
+    s1 += b[16 + w];
+  }
+  v0 = s0;
+  v1 = s1;
+}
+
+// Jacobi-preconditioned CG on K_FF d = r (d from 0) with p and psi in LDS;
+// r, d and the inverse diagonal in registers.  Stops when
+// ||r|| <= rtol ||r0||.  Returns the iterations; d holds the increment.
 template <typename T, int DIM, int Q>
 __device__ int bot_cg(const Geom &g, const Coef<T> &C, const T *psi_l, T *p_l, T (&r)[Q][3],
                       T (&d)[Q][3], const bool (&dir)[Q][3], const int (&cijk)[Q][3],
                       double rtol, int maxit, BotRed &R) {
   const int64_t n = g.nn;
-  double loc = 0.0;
+  T dinv[Q][3];
+  double lrr = 0.0, lrz = 0.0;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int64_t id = threadIdx.x + (int64_t)q * blockDim.x;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) dinv[q][c] = T(0);
     if (id >= n) continue;
+    T dg[3];
+    node_diag<T, DIM>(g, C, psi_l, cijk[q][0], cijk[q][1], cijk[q][2], dg);
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
+      dinv[q][c] = dir[q][c] ? T(0) : T(1) / dg[c];
       d[q][c] = T(0);
-      p_l[c * n + id] = r[q][c];
-      loc += (double)r[q][c] * (double)r[q][c];
+      const T z = r[q][c] * dinv[q][c];
+      p_l[c * n + id] = z;
+      lrr += (double)r[q][c] * (double)r[q][c];
+      lrz += (double)r[q][c] * (double)z;
     }
   }
-  double rr = bot_allsum(loc, R);
+  bot_allsum2(lrr, lrz, R);
+  double rr = lrr, rz = lrz;
   const double r0 = sqrt(rr);
   int it = 0;
   while (r0 > 0.0 && sqrt(rr) > rtol * r0 && it < maxit) {
@@ -645,8 +810,8 @@ __device__ int bot_cg(const Geom &g, const Coef<T> &C, const T *psi_l, T *p_l, T
     }
     pap = bot_allsum(pap, R);  // its barrier also ends every read of p
     if (!(pap > 0.0)) break;
-    const double alpha = rr / pap;
-    double rn = 0.0;
+    const double alpha = rz / pap;
+    double nrr = 0.0, nrz = 0.0;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int64_t id = threadIdx.x + (int64_t)q * blockDim.x;
@@ -655,19 +820,22 @@ __device__ int bot_cg(const Geom &g, const Coef<T> &C, const T *psi_l, T *p_l, T
       for (int c = 0; c < DIM; ++c) {
         d[q][c] = (T)((double)d[q][c] + alpha * (double)p_l[c * n + id]);
         r[q][c] = (T)((double)r[q][c] - alpha * (double)ap[q][c]);
-        rn += (double)r[q][c] * (double)r[q][c];
+        nrr += (double)r[q][c] * (double)r[q][c];
+        nrz += (double)r[q][c] * (double)(r[q][c] * dinv[q][c]);
       }
     }
-    rn = bot_allsum(rn, R);
-    const double beta = rn / rr;
-    rr = rn;
+    bot_allsum2(nrr, nrz, R);
+    const double beta = nrz / rz;
+    rr = nrr;
+    rz = nrz;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int64_t id = threadIdx.x + (int64_t)q * blockDim.x;
       if (id >= n) continue;
 #pragma unroll
       for (int c = 0; c < DIM; ++c)
-        p_l[c * n + id] = dir[q][c] ? T(0) : (T)((double)r[q][c] + beta * (double)p_l[c * n + id]);
+        p_l[c * n + id] =
+            dir[q][c] ? T(0) : (T)((double)(r[q][c] * dinv[q][c]) + beta * (double)p_l[c * n + id]);
     }
     ++it;
   }
@@ -682,7 +850,7 @@ __global__ __launch_bounds__(kBotThreads) void k_bottom_lds64(Geom g, Coef<doubl
                                                        const double *__restrict__ f, double *x,
                                                        double rtol, int maxit, int *iters) {
   extern __shared__ double smem[];
-  __shared__ double red[32];
+  __shared__ double red[64];
   BotRed R{red, 0};
   const int64_t n = g.nn;
   double *psi_l = smem;
@@ -747,7 +915,7 @@ __global__ __launch_bounds__(kBotThreads) void k_bottom_lds_mixed(Geom g, Coef<d
                                                                   int maxit, int *iters) {
   constexpr int Q = kBotQMixed;
   extern __shared__ double smem[];
-  __shared__ double red[32];
+  __shared__ double red[64];
   BotRed R{red, 0};
   const int64_t n = g.nn;
   const int64_t nc2 = (g.nc + 1) & ~(int64_t)1;
@@ -1074,14 +1242,46 @@ hipError_t launch_dot_free(const Level &L, const double *a, const double *b, dou
   SBM_LAUNCH((k_dot_free<2>), num_blocks(L.g.nn), kBlock, st, L.g, a, b, partials);
 }
 
+hipError_t launch_apply_dot(const Level &L, const double *p, double *q, double *partials,
+                           hipStream_t st) {
+  if (L.g.dim == 3)
+    SBM_LAUNCH((k_apply_dot<3>), num_blocks(L.g.nn), kBlock, st, L.g, L.c64, L.psi64, p, q, partials);
+  SBM_LAUNCH((k_apply_dot<2>), num_blocks(L.g.nn), kBlock, st, L.g, L.c64, L.psi64, p, q, partials);
+}
+
+hipError_t launch_cg_update(const Level &L, double *x, double *r, const double *p, const double *q,
+                            const double *z, const double *rz, const double *pq, double *pr,
+                            double *pz, hipStream_t st) {
+  if (L.g.dim == 3)
+    SBM_LAUNCH((k_cg_update<3>), num_blocks(L.g.nn), kBlock, st, L.g, x, r, p, q, z, rz, pq, pr, pz);
+  SBM_LAUNCH((k_cg_update<2>), num_blocks(L.g.nn), kBlock, st, L.g, x, r, p, q, z, rz, pq, pr, pz);
+}
+
+hipError_t launch_xpby(const Level &L, double *p, const double *z, const double *rznew,
+                       const double *rzold, const double *rz, hipStream_t st) {
+  if (L.g.dim == 3) SBM_LAUNCH((k_xpby<3>), num_blocks(L.g.nn), kBlock, st, L.g, p, z, rznew, rzold, rz);
+  SBM_LAUNCH((k_xpby<2>), num_blocks(L.g.nn), kBlock, st, L.g, p, z, rznew, rzold, rz);
+}
+
+hipError_t launch_cast_scaled(const double *r, float *r32, int64_t n, const double *ss,
+                              hipStream_t st) {
+  SBM_LAUNCH(k_cast_scaled, num_blocks(n), kBlock, st, r, r32, n, ss);
+}
+
+hipError_t launch_scale_set(double *z, const float *e32, int64_t n, const double *ss,
+                            hipStream_t st) {
+  SBM_LAUNCH(k_scale_set, num_blocks(n), kBlock, st, z, e32, n, ss);
+}
+
 hipError_t launch_sumsq_free(const Level &L, const double *v, double *partials, hipStream_t st) {
   if (L.g.dim == 3) SBM_LAUNCH((k_sumsq_free<3>), num_blocks(L.g.nn), kBlock, st, L.g, v, partials);
   SBM_LAUNCH((k_sumsq_free<2>), num_blocks(L.g.nn), kBlock, st, L.g, v, partials);
 }
 
+// One node per thread up to kBotThreads threads, then up to kBotQ per thread.
 static int bottom_threads(int64_t nn) {
-  int64_t t = ((nn + kBotQ - 1) / kBotQ + 63) / 64 * 64;
-  return (int)(t < 64 ? 64 : t);
+  int64_t t = (nn + 63) / 64 * 64;
+  return (int)(t < 64 ? 64 : (t > kBotThreads ? kBotThreads : t));
 }
 
 static bool bottom_fits_lds(const Geom &g, size_t bytes) {
@@ -1128,8 +1328,7 @@ hipError_t launch_bottom_mixed(const Level &L, const float *b32, float *e32, dou
                                double rtol, int maxit, int *iters, hipStream_t st) {
   const size_t by = bottom_lds_mixed_bytes(L.g);
   if (L.g.nn <= (int64_t)kBotQMixed * kBotThreads && by <= 64 * 1024) {
-    int nt = (int)(((L.g.nn + kBotQMixed - 1) / kBotQMixed + 63) / 64 * 64);
-    if (nt < 64) nt = 64;
+    const int nt = bottom_threads(L.g.nn);
     (void)hipGetLastError();
     if (L.g.dim == 3) {
       hipLaunchKernelGGL((k_bottom_lds_mixed<3>), dim3(1), dim3(nt), by, st, L.g, L.c64, L.c32,

@@ -59,6 +59,8 @@ struct sbm_ctx {
   double fnorm = 0.0;
   int last_bottom_iters = 0;
   double *x0 = nullptr;  // finest-level iterate (fixed address for captured cycles)
+  double *kr = nullptr, *kz = nullptr, *kp = nullptr, *kq = nullptr;  // flexible CG vectors
+  double *partials2 = nullptr;
   // live kernel timing (sbm_profile)
   bool prof_on = false;
   std::vector<hipEvent_t> prof_ev;  // pairs
@@ -67,6 +69,7 @@ struct sbm_ctx {
   int64_t prof_n[SBM_PROF_N] = {0};
   // captured V-cycles
   struct CycleGraph {
+    int mode;  // 0: outer-loop cycle on x0, 1: preconditioner z = M r
     int precision;
     const double *f;
     bool prof;
@@ -235,8 +238,13 @@ static size_t carve(sbm_ctx *c, char *base) {
     maxblocks = std::max<int64_t>(maxblocks, num_blocks(L.g.nc));
   }
   c->x0 = cv.take<double>((int64_t)d * c->L[0].g.nn);
+  c->kr = cv.take<double>((int64_t)d * c->L[0].g.nn);
+  c->kz = cv.take<double>((int64_t)d * c->L[0].g.nn);
+  c->kp = cv.take<double>((int64_t)d * c->L[0].g.nn);
+  c->kq = cv.take<double>((int64_t)d * c->L[0].g.nn);
   c->npart = (int)maxblocks;
   c->partials = cv.take<double>(maxblocks);
+  c->partials2 = cv.take<double>(maxblocks);
   c->scal = cv.take<double>(16);
   c->iflag = cv.take<int>(16);
   const Level &B = c->L[c->nlev - 1];
@@ -312,7 +320,7 @@ struct Prec<float> {
 
 // nu sweeps on level l for x with load f; tmp is the ping-pong buffer.
 template <typename T>
-static hipError_t smooth(sbm_ctx *c, int l, T *x, const T *f, T *tmp, int nu) {
+static hipError_t smooth(sbm_ctx *c, int l, T *x, const T *f, T *tmp, int nu, bool reverse) {
   Level &L = c->L[l];
   const T *psi = Prec<T>::psi(L);
   const Coef<T> &C = Prec<T>::coef(L);
@@ -328,13 +336,14 @@ static hipError_t smooth(sbm_ctx *c, int l, T *x, const T *f, T *tmp, int nu) {
     if (src != x) e = launch_copy<T>(src, x, (int64_t)c->dim * L.g.nn, c->st);
     return e;
   }
+  const int c0 = reverse ? 1 : 0;
   for (int s = 0; s < nu; ++s) {
     {
       ProfScope ps(c, SBM_PROF_SMOOTH, l == 0);
-      if ((e = launch_rb_half<T>(L, psi, C, x, f, tmp, om, 0, c->st)) != hipSuccess) return e;
+      if ((e = launch_rb_half<T>(L, psi, C, x, f, tmp, om, c0, c->st)) != hipSuccess) return e;
     }
     ProfScope ps(c, SBM_PROF_SMOOTH, l == 0);
-    if ((e = launch_rb_half<T>(L, psi, C, tmp, f, x, om, 1, c->st)) != hipSuccess) return e;
+    if ((e = launch_rb_half<T>(L, psi, C, tmp, f, x, om, 1 - c0, c->st)) != hipSuccess) return e;
   }
   return e;
 }
@@ -362,7 +371,7 @@ static hipError_t vcycle(sbm_ctx *c, int l, T *x, const T *f, T *tmp) {
   }
   Level &L = c->L[l];
   Level &C = c->L[l + 1];
-  if ((e = smooth<T>(c, l, x, f, tmp, c->opt.nu_pre)) != hipSuccess) return e;
+  if ((e = smooth<T>(c, l, x, f, tmp, c->opt.nu_pre, false)) != hipSuccess) return e;
   {
     ProfScope ps(c, SBM_PROF_RESIDUAL, l == 0);
     if ((e = launch_residual<T>(L, Prec<T>::psi(L), Prec<T>::coef(L), x, f, tmp, nullptr,
@@ -380,7 +389,9 @@ static hipError_t vcycle(sbm_ctx *c, int l, T *x, const T *f, T *tmp) {
     ProfScope ps(c, SBM_PROF_PROLONG, l == 0);
     if ((e = launch_prolong_add<T>(L, C, Prec<T>::e(C), x, c->st)) != hipSuccess) return e;
   }
-  return smooth<T>(c, l, x, f, tmp, c->opt.nu_post);
+  // as a CG preconditioner the cycle is made symmetric: post-smoothing runs
+  // the colours in reverse order
+  return smooth<T>(c, l, x, f, tmp, c->opt.nu_post, c->opt.krylov == 1);
 }
 
 // ||r||_2^2 of the level-0 residual f - K u (free DOF), synchronising.
@@ -402,10 +413,22 @@ static sbm_status residual_norm2(sbm_ctx *c, const double *u, const double *f, d
 // FP64 V-cycle, or (mixed) r32 = (f - K x0)/s, an FP32 V-cycle for e32 from
 // zero, x0 += s e32 with s the residual norm left in scal[0] by the
 // convergence test.
-static hipError_t cycle_body(sbm_ctx *c, const double *f) {
+static hipError_t cycle_body(sbm_ctx *c, const double *f, int mode) {
   Level &L0 = c->L[0];
   const int64_t nv = (int64_t)c->dim * L0.g.nn;
   hipError_t e;
+  if (mode == 1) {
+    // preconditioner: kz = M kr, one V-cycle from zero (mixed: on kr / ||kr||
+    // in FP32, ||kr||^2 in scal[0])
+    if (c->opt.precision == 1) {
+      if ((e = launch_cast_scaled(c->kr, L0.f32, nv, c->scal, c->st)) != hipSuccess) return e;
+      if ((e = launch_fill<float>(L0.e32, nv, 0.0f, c->st)) != hipSuccess) return e;
+      if ((e = vcycle<float>(c, 0, L0.e32, L0.f32, L0.t32)) != hipSuccess) return e;
+      return launch_scale_set(c->kz, L0.e32, nv, c->scal, c->st);
+    }
+    if ((e = launch_fill<double>(c->kz, nv, 0.0, c->st)) != hipSuccess) return e;
+    return vcycle<double>(c, 0, c->kz, c->kr, L0.t);
+  }
   if (c->opt.precision == 1) {
     if ((e = launch_residual_cast(L0, c->x0, f, L0.f32, c->scal, c->st)) != hipSuccess) return e;
     if ((e = launch_fill<float>(L0.e32, nv, 0.0f, c->st)) != hipSuccess) return e;
@@ -417,11 +440,12 @@ static hipError_t cycle_body(sbm_ctx *c, const double *f) {
 
 // Finds or captures the graph of cycle_body for (precision, f, profiling).
 // Returns nullptr when capture is not possible (the cycle then runs eagerly).
-static sbm_ctx::CycleGraph *cycle_graph(sbm_ctx *c, const double *f) {
+static sbm_ctx::CycleGraph *cycle_graph(sbm_ctx *c, const double *f, int mode) {
   for (auto *g : c->graphs)
-    if (g->precision == c->opt.precision && g->f == f && g->prof == c->prof_on)
+    if (g->mode == mode && g->precision == c->opt.precision && g->f == f && g->prof == c->prof_on)
       return g->failed ? nullptr : g;
   auto *g = new sbm_ctx::CycleGraph();
+  g->mode = mode;
   g->precision = c->opt.precision;
   g->f = f;
   g->prof = c->prof_on;
@@ -438,7 +462,7 @@ static sbm_ctx::CycleGraph *cycle_graph(sbm_ctx *c, const double *f) {
   hipError_t e = hipStreamBeginCapture(c->cap_st, hipStreamCaptureModeRelaxed);
   hipError_t eb = hipSuccess;
   if (e == hipSuccess) {
-    eb = cycle_body(c, f);
+    eb = cycle_body(c, f, mode);
     e = hipStreamEndCapture(c->cap_st, &graph);
   }
   c->capturing = nullptr;
@@ -463,12 +487,12 @@ static sbm_ctx::CycleGraph *cycle_graph(sbm_ctx *c, const double *f) {
   return g;
 }
 
-static sbm_status run_cycle(sbm_ctx *c, const double *f) {
+static sbm_status run_cycle(sbm_ctx *c, const double *f, int mode) {
   // Live timing brackets single launches with events, so it runs the cycle
   // launch by launch (event records inside a replayed graph give no timings
   // on this runtime).
   if (c->opt.use_graphs && !c->prof_on) {
-    sbm_ctx::CycleGraph *g = cycle_graph(c, f);
+    sbm_ctx::CycleGraph *g = cycle_graph(c, f, mode);
     if (g) {
       HIP_TRY(hipGraphLaunch(g->exec, c->st));
       ++c->graph_launches;
@@ -476,8 +500,114 @@ static sbm_status run_cycle(sbm_ctx *c, const double *f) {
       return SBM_OK;
     }
   }
-  HIP_TRY(cycle_body(c, f));
+  HIP_TRY(cycle_body(c, f, mode));
   return SBM_OK;
+}
+
+// Finalises `n` partials into scal[slot] and copies scal[slot] to host[slot].
+static sbm_status fin_to_host(sbm_ctx *c, const double *partials, int n, int slot) {
+  HIP_TRY(launch_finalize_sum(partials, n, c->scal + slot, c->st));
+  HIP_TRY(hipMemcpyAsync(c->host + slot, c->scal + slot, sizeof(double), hipMemcpyDeviceToHost,
+                         c->st));
+  return SBM_OK;
+}
+
+#define SBM_TRY(expr)                      \
+  do {                                     \
+    sbm_status s_ = (expr);                \
+    if (s_ != SBM_OK) return s_;           \
+  } while (0)
+
+// Flexible CG (Polak-Ribiere beta) on the finest level, preconditioned by one
+// V-cycle from zero per iteration.  Device scalars: scal[0] = r.r,
+// scal[1] = r.z (new), scal[2] = p.q, scal[3] = r.z (old z), scal[4] = r.z
+// of the previous iteration.
+static sbm_status solve_krylov(sbm_ctx *c, const double *f, double fnorm, double *u, double *hist,
+                               int cap, int *ncyc, double *final_rel) {
+  Level &L0 = c->L[0];
+  const int64_t nv = (int64_t)c->dim * L0.g.nn;
+  const int nb = num_blocks(L0.g.nn);
+  double rho_min = INFINITY, rho = 0.0;
+  sbm_status status = SBM_NOT_CONVERGED;
+  HIP_TRY(launch_copy<double>(u, c->x0, nv, c->st));
+  {
+    ProfScope ps(c, SBM_PROF_NORM, true);
+    HIP_TRY((launch_residual<double>(L0, L0.psi64, L0.c64, c->x0, f, c->kr, c->partials, c->st)));
+  }
+  SBM_TRY(fin_to_host(c, c->partials, nb, 0));
+  HIP_TRY(hipStreamSynchronize(c->st));
+  rho = fnorm > 0.0 ? sqrt(c->host[0]) / fnorm : (c->host[0] > 0.0 ? INFINITY : 0.0);
+  if (hist && cap > 0) hist[0] = rho;
+  bool restart = true;
+  int m = 0;
+  for (;;) {
+    if (!isfinite(rho)) {
+      status = fail(SBM_E_NONFINITE, "non-finite residual at iteration " + std::to_string(m));
+      break;
+    }
+    if (rho <= c->opt.rtol) {
+      status = SBM_OK;
+      break;
+    }
+    if (rho > 1e3 * rho_min) {
+      status = fail(SBM_E_DIVERGED, "residual grew above 1e3 x its minimum at iteration " +
+                                        std::to_string(m));
+      break;
+    }
+    rho_min = std::min(rho_min, rho);
+    if (m >= c->opt.max_cycles) {
+      g_last_error = "max_cycles reached";
+      break;
+    }
+    if (restart) {
+      SBM_TRY(run_cycle(c, nullptr, 1));
+      HIP_TRY(launch_dot_free(L0, c->kr, c->kz, c->partials, c->st));
+      HIP_TRY(launch_finalize_sum(c->partials, nb, c->scal + 4, c->st));
+      HIP_TRY(launch_xpby(L0, c->kp, c->kz, nullptr, nullptr, nullptr, c->st));
+      restart = false;
+    }
+    HIP_TRY(launch_apply_dot(L0, c->kp, c->kq, c->partials, c->st));
+    SBM_TRY(fin_to_host(c, c->partials, nb, 2));
+    HIP_TRY(hipStreamSynchronize(c->st));
+    if (c->prof_on) prof_harvest(c);
+    if (!(c->host[2] > 0.0)) {
+      status = fail(SBM_E_DIVERGED, "preconditioned CG lost positivity (p.Kp <= 0)");
+      break;
+    }
+    HIP_TRY(launch_cg_update(L0, c->x0, c->kr, c->kp, c->kq, c->kz, c->scal + 4, c->scal + 2,
+                             c->partials, c->partials2, c->st));
+    SBM_TRY(fin_to_host(c, c->partials, nb, 0));
+    SBM_TRY(fin_to_host(c, c->partials2, nb, 3));
+    HIP_TRY(hipStreamSynchronize(c->st));
+    ++m;
+    rho = fnorm > 0.0 ? sqrt(c->host[0]) / fnorm : 0.0;
+    if (rho <= c->opt.rtol) {
+      // accept on the true residual only; otherwise restart from it
+      {
+        ProfScope ps(c, SBM_PROF_NORM, true);
+        HIP_TRY((launch_residual<double>(L0, L0.psi64, L0.c64, c->x0, f, c->kr, c->partials,
+                                         c->st)));
+      }
+      SBM_TRY(fin_to_host(c, c->partials, nb, 0));
+      HIP_TRY(hipStreamSynchronize(c->st));
+      rho = fnorm > 0.0 ? sqrt(c->host[0]) / fnorm : 0.0;
+      if (hist && m < cap) hist[m] = rho;
+      if (rho > c->opt.rtol) restart = true;
+      continue;
+    }
+    if (hist && m < cap) hist[m] = rho;
+    SBM_TRY(run_cycle(c, nullptr, 1));
+    HIP_TRY(launch_dot_free(L0, c->kr, c->kz, c->partials, c->st));
+    HIP_TRY(launch_finalize_sum(c->partials, nb, c->scal + 1, c->st));
+    HIP_TRY(launch_xpby(L0, c->kp, c->kz, c->scal + 1, c->scal + 3, c->scal + 4, c->st));
+    HIP_TRY(launch_copy<double>(c->scal + 1, c->scal + 4, 1, c->st));
+  }
+  if (ncyc) *ncyc = m;
+  if (final_rel) *final_rel = rho;
+  HIP_TRY(launch_copy<double>(c->x0, u, nv, c->st));
+  HIP_TRY(hipStreamSynchronize(c->st));
+  if (c->prof_on) prof_harvest(c);
+  return status;
 }
 
 // Outer loop on the finest level for K u = f, u carrying its displacement
@@ -485,6 +615,7 @@ static sbm_status run_cycle(sbm_ctx *c, const double *f) {
 // solve.
 static sbm_status solve_impl(sbm_ctx *c, const double *f, double fnorm, double *u, double *hist,
                              int cap, int *ncyc, double *final_rel) {
+  if (c->opt.krylov == 1) return solve_krylov(c, f, fnorm, u, hist, cap, ncyc, final_rel);
   Level &L0 = c->L[0];
   const int64_t nv = (int64_t)c->dim * L0.g.nn;
   double rho_min = INFINITY, rho = 0.0;
@@ -516,7 +647,7 @@ static sbm_status solve_impl(sbm_ctx *c, const double *f, double fnorm, double *
       status = SBM_NOT_CONVERGED;
       break;
     }
-    s = run_cycle(c, f);
+    s = run_cycle(c, f, 0);
     if (s != SBM_OK) return s;
   }
   if (ncyc) *ncyc = m;
@@ -543,6 +674,7 @@ void sbm_default_options(sbm_options *o) {
   o->bottom_rtol = 1e-12;
   o->bottom_max_iter = 0;
   o->use_graphs = 1;
+  o->krylov = 0;
 }
 
 const char *sbm_last_error(void) { return g_last_error.c_str(); }
@@ -556,7 +688,7 @@ static bool opts_ok(const sbm_options *o) {
   return o && (o->smoother == 0 || o->smoother == 1) && o->nu_pre >= 0 && o->nu_post >= 0 &&
          (o->precision == 0 || o->precision == 1) && o->rtol >= 0.0 && o->max_cycles >= 0 &&
          o->bottom_rtol >= 0.0 && isfinite(o->omega) && o->omega >= 0.0 && o->omega < 2.0 &&
-         (o->use_graphs == 0 || o->use_graphs == 1);
+         (o->use_graphs == 0 || o->use_graphs == 1) && (o->krylov == 0 || o->krylov == 1);
 }
 
 size_t sbm_workspace_bytes(const sbm_grid *grid, const sbm_options *opts) {
@@ -605,7 +737,8 @@ sbm_status sbm_set_options(sbm_ctx *c, const sbm_options *opts) {
   const sbm_options &o = c->opt;
   const bool same = o.smoother == opts->smoother && o.omega == opts->omega &&
                     o.nu_pre == opts->nu_pre && o.nu_post == opts->nu_post &&
-                    o.bottom_rtol == opts->bottom_rtol && o.bottom_max_iter == opts->bottom_max_iter;
+                    o.bottom_rtol == opts->bottom_rtol && o.bottom_max_iter == opts->bottom_max_iter &&
+                    o.krylov == opts->krylov;
   if (!same) {
     HIP_TRY(hipStreamSynchronize(c->st));
     drop_graphs(c);

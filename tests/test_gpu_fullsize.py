@@ -33,12 +33,17 @@ WORKLOADS = {
 }
 
 
+# The 257^3 crack with 40 % voids converges too slowly for plain V-cycles
+# (about 0.996 per cycle); it is solved by V-cycle-preconditioned CG.
+KRYLOV = {"spherical_voids_129": 0, "cantilever_193x97x97": 0, "diffuse_crack_257": 1}
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 @pytest.mark.parametrize("name", list(WORKLOADS))
 def test_fullsize_solution_residual(name, precision):
     p = WORKLOADS[name]()
     say("full size", name, "precision", precision)
-    S = solver_for(p, precision=precision, rtol=1e-10, max_cycles=400)
+    S = solver_for(p, precision=precision, rtol=1e-10, max_cycles=400, krylov=KRYLOV[name])
     u, hist, st = S.solve()
     assert st == 0, hist[-5:]
     un = to_np(u)

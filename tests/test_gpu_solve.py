@@ -35,6 +35,7 @@ CASES = {
 
 
 def _run_pair(p, smoother, **kw):
+    """Oracle to rtol 1e-10 in m* iterations, then the GPU for exactly m*."""
     u_o, hist_o, st_o = oracle_solve(p, smoother=smoother, rtol=1e-10, max_cycles=400, **kw)
     assert st_o == 0, "oracle did not converge"
     m = len(hist_o) - 1
@@ -55,20 +56,35 @@ def test_fp64_trajectory_parity(case, smoother):
     assert rel_l2(u_g, u_o) <= 1e-9, rel_l2(u_g, u_o)
 
 
+@pytest.mark.parametrize("smoother", [0, 1])
+@pytest.mark.parametrize("case", ["plate_void_2d_64", "spherical_voids_32", "diffuse_crack_32",
+                                  "cantilever_24x12x12", "random_mixed_2d_40x24"])
+def test_krylov_trajectory_parity(case, smoother):
+    """V-cycle-preconditioned flexible CG: same iterates as the oracle's."""
+    p = CASES[case]()
+    say("krylov parity", case, smoother)
+    S, u_o, hist_o, u_g, hist_g, st_g, m = _run_pair(p, smoother, krylov=1)
+    assert len(hist_g) == m + 1
+    dh = np.abs(hist_g - hist_o)
+    assert np.all(dh <= 1e-6 * hist_o + RHO_ATOL), dh.max()
+    assert rel_l2(u_g, u_o) <= 1e-9, rel_l2(u_g, u_o)
+
+
 @pytest.mark.parametrize("case", ["plate_void_2d_64", "spherical_voids_32", "cantilever_24x12x12",
                                   "random_mixed_3d_16x8x12", "random_mixed_2d_50x46"])
 def test_mixed_precision_converges_to_fp64_solution(case):
     p = CASES[case]()
     say("mixed", case)
     u_o, hist_o, st_o = oracle_solve(p, rtol=1e-10, max_cycles=400)
-    S = solver_for(p, precision=1, rtol=1e-10, max_cycles=400)
-    u_g, hist_g, st = S.solve()
-    assert st == 0
-    assert hist_g[-1] <= 1e-10
-    err = rel_l2(to_np(u_g), u_o)
-    print(f"[mixed] {case}: cycles {len(hist_g) - 1} (fp64 oracle {len(hist_o) - 1}), "
-          f"rel L2 error vs FP64 oracle {err:.3e}")
-    assert err <= 1e-7
+    for krylov in (0, 1):
+        S = solver_for(p, precision=1, rtol=1e-10, max_cycles=400, krylov=krylov)
+        u_g, hist_g, st = S.solve()
+        assert st == 0
+        assert hist_g[-1] <= 1e-10
+        err = rel_l2(to_np(u_g), u_o)
+        print(f"[mixed] {case} krylov {krylov}: iterations {len(hist_g) - 1} (fp64 oracle "
+              f"{len(hist_o) - 1}), rel L2 error vs FP64 oracle {err:.3e}")
+        assert err <= 1e-7
 
 
 def test_warm_start_and_history():
