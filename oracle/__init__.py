@@ -199,6 +199,15 @@ def coarsen_psi(ncell_fine, psi):
     return out
 
 
+def amr_tags(ncell, h, psi, thresh):
+    """Refinement tags of a level's (floored) cell psi."""
+    psi = np.ascontiguousarray(psi, np.float64)
+    tags = np.empty(psi.shape, np.uint8)
+    lib().orc_amr_tags(len(ncell), _long3(ncell), _dbl3(h), _d(psi), ctypes.c_double(thresh),
+                       _u8(tags))
+    return tags
+
+
 def cg(ncell, h, lam, mu, psi, mask, f, x0=None, rtol=1e-12, maxit=None):
     d = len(ncell)
     x = np.zeros((d,) + node_shape(ncell)) if x0 is None else np.array(x0, np.float64, copy=True)
@@ -262,3 +271,100 @@ def assemble(ncell, h, lam, mu, psi):
         K[:, j] = apply(ncell, h, lam, mu, psi, e.reshape(shp)).ravel()
         e[j] = 0.0
     return K
+
+
+# ------------------------------------------------------------------ BSAMR
+
+class AmrProblem:
+    """Oracle of the block-structured adaptive composite solve.  psi_levels
+    are the raw indicators sampled at each level's cell centres (dense,
+    level a has ncell0 * 2^a cells per axis)."""
+
+    def __init__(self, ncell0, h0, lam, mu, psi_levels, psi_floor, kind, val, *, block=32,
+                 thresh=0.05, smoother=0, omega=None, nu_pre=2, nu_post=2, bottom_rtol=1e-12,
+                 bottom_max_iter=0, blocks=None):
+        L = lib()
+        L.orc_amr_new.restype = ctypes.c_void_p
+        L.orc_amr_fnorm.restype = ctypes.c_double
+        L.orc_amr_residual.restype = ctypes.c_double
+        self.dim = len(ncell0)
+        self.A = len(psi_levels) - 1
+        self.ncell0 = tuple(ncell0)
+        self.h0 = tuple(h0)
+        self.block = block
+        if omega is None:
+            omega = 1.0 if smoother == 0 else 0.8
+        self._psi = [np.ascontiguousarray(p, np.float64) for p in psi_levels]
+        for a, p in enumerate(self._psi):
+            assert p.shape == cell_shape(self.ncell(a)), (a, p.shape)
+        arr = (_dp * len(self._psi))(*[_d(p) for p in self._psi])
+        k, v = _bc(kind, val)
+        blk = None
+        if blocks is not None:  # block flags of levels 1..A, shape (nbz, nby, nbx) each
+            self._blk = [np.ascontiguousarray(b, np.uint8) for b in blocks]
+            blk = (_u8p * len(self._blk))(*[_u8(b) for b in self._blk])
+        self._ctx = L.orc_amr_new(self.dim, self.A, int(block), _long3(ncell0), _dbl3(h0),
+                                  ctypes.c_double(lam), ctypes.c_double(mu), arr,
+                                  ctypes.c_double(psi_floor), k.ctypes.data_as(_ip), _d(v),
+                                  ctypes.c_double(thresh), int(smoother), ctypes.c_double(omega),
+                                  int(nu_pre), int(nu_post), ctypes.c_double(bottom_rtol),
+                                  int(bottom_max_iter), blk)
+
+    def __del__(self):
+        if getattr(self, "_ctx", None):
+            lib().orc_amr_free(ctypes.c_void_p(self._ctx))
+            self._ctx = None
+
+    def ncell(self, a):
+        return tuple(n << a for n in self.ncell0)
+
+    def h(self, a):
+        return tuple(x / (1 << a) for x in self.h0)
+
+    def node_shape(self, a):
+        return (self.dim,) + node_shape(self.ncell(a))
+
+    def info(self, a):
+        """(block flags, node classes, psi) of level a (flags/classes None at a = 0)."""
+        nc = self.ncell(a)
+        nb = (ctypes.c_long * 3)()
+        psi = np.empty(cell_shape(nc))
+        if a == 0:
+            lib().orc_amr_info(ctypes.c_void_p(self._ctx), 0, None, None, _d(psi), nb)
+            return None, None, psi
+        nbl = tuple(n // self.block for n in nc)
+        blk = np.empty(tuple(reversed(nbl)), np.uint8)
+        cls = np.empty(node_shape(nc), np.uint8)
+        lib().orc_amr_info(ctypes.c_void_p(self._ctx), a, _u8(blk), _u8(cls), _d(psi), nb)
+        return blk, cls, psi
+
+    def fnorm(self):
+        return lib().orc_amr_fnorm(ctypes.c_void_p(self._ctx))
+
+    def _ptrs(self, arrs):
+        return (_dp * len(arrs))(*[_d(x) for x in arrs])
+
+    def residual(self, u_levels, f_levels=None):
+        """(composite residual per level, norm over the composite unknowns);
+        the ghosts of u are refilled in place."""
+        u = [np.ascontiguousarray(x, np.float64) for x in u_levels]
+        r = [np.zeros(self.node_shape(a)) for a in range(self.A + 1)]
+        f = None if f_levels is None else self._ptrs(
+            [np.ascontiguousarray(x, np.float64) for x in f_levels])
+        nrm = lib().orc_amr_residual(ctypes.c_void_p(self._ctx), self._ptrs(u), f, self._ptrs(r))
+        return r, nrm, u
+
+    def ghost_fill(self, a, xc, xf):
+        xf = np.array(xf, np.float64, copy=True)
+        lib().orc_amr_ghost_fill(ctypes.c_void_p(self._ctx), int(a),
+                                 _d(np.ascontiguousarray(xc, np.float64)), _d(xf))
+        return xf
+
+    def solve(self, rtol=1e-10, max_cycles=200, u0=None):
+        u = [np.zeros(self.node_shape(a)) if u0 is None else np.array(u0[a], np.float64, copy=True)
+             for a in range(self.A + 1)]
+        hist = np.zeros(max_cycles + 1)
+        n = ctypes.c_int(0)
+        st = lib().orc_amr_solve(ctypes.c_void_p(self._ctx), ctypes.c_double(rtol), int(max_cycles),
+                                 self._ptrs(u), _d(hist), int(max_cycles + 1), ctypes.byref(n))
+        return u, hist[: n.value + 1].copy(), st

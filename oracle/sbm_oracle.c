@@ -820,3 +820,561 @@ void orc_sensitivity(int dim, const long *nc, const double *h, double lam_, doub
     g[cid] = acc;
   }
 }
+
+/* ======================================================================
+ * Block-structured adaptive composite solve (BSAMR).
+ *
+ * The paper solves on block-structured AMR levels of equal cell size that
+ * exchange data by averaging (fine to coarse) and ghost cells (coarse to
+ * fine), treats the refined levels as an extension of the multigrid level
+ * sequence (Sec. 2.2), and pads levels with an extra ghost layer so that
+ * restriction keeps its translational symmetry and no special coarse-fine
+ * stencil is needed (Sec. 2.2, reflux-free).  The details live in a cited
+ * work; the reading implemented here:
+ *
+ *  - AMR level a (0..A) has spacing h0 / 2^a and is stored densely over the
+ *    whole box; levels a >= 1 are active on a union of cubic blocks of bc
+ *    cells.  Level-a cells are tagged where |grad psi| h > threshold
+ *    (central differences, clamped at the box; Sec. 3.3 uses 0.05); a
+ *    level-(a+1) block is active if a tagged level-a cell lies in its
+ *    footprint grown by one cell; every active block has its parent active,
+ *    and the parent's neighbours on the sides the block touches.
+ *  - Node classes of level a >= 1: 1 interior (unknown), 2 interface (on
+ *    the boundary of the active region inside the box: owned by level a-1),
+ *    3 and 4 the first and second layer outside.  Classes 2-4 are ghosts
+ *    filled by tensor-product quadratic interpolation from level a-1.
+ *  - psi is sampled per level; covered coarse cells take the mean of their
+ *    children.  Covered coarse nodes take the injected fine values.
+ *  - Composite residual: fine residual on classes 1-3 (padded region);
+ *    coarse nodes on or inside the fine region take R of it; other coarse
+ *    nodes take their own residual.
+ *  - Composite cycle: full-approximation (FAS) multilevel cycle over the AMR
+ *    levels (smooth level a, restrict its padded residual, coarse FAS load
+ *    R w + K_c x_c on covered/interface nodes, recurse, correct with
+ *    P(x_c - inject(x_f)), smooth), ending in the uniform V-cycle of the
+ *    base grid; applied in correction form inside an FP64 outer loop.
+ * ====================================================================== */
+
+#define AMR_MAXL 4
+
+typedef struct {
+  int dim, A, bc;
+  double lam, mu;
+  int kind[18];
+  double val[18];
+  grid_t g[AMR_MAXL];         /* dense grid of each AMR level */
+  long nb[AMR_MAXL][3];       /* blocks per axis (a >= 1) */
+  uint8_t *blk[AMR_MAXL];     /* block flags (a >= 1) */
+  uint8_t *cls[AMR_MAXL];     /* node classes (a >= 1) */
+  double *psi[AMR_MAXL];      /* floored, averaged-down psi */
+  uint8_t *dm[AMR_MAXL];      /* Dirichlet masks */
+  double *uD[AMR_MAXL];       /* prescribed values */
+  double *fP[AMR_MAXL];       /* loads */
+  orc_opts o;
+  level_t *hier;              /* uniform hierarchy of the base level */
+  int nlev;
+  double fnorm;
+} amr_t;
+
+
+/* Cells tagged for refinement: |grad psi| h > thresh with central differences
+ * (neighbour indices clamped to the box), h the largest spacing. */
+void orc_amr_tags(int dim, const long *nc, const double *h, const double *psi, double thresh,
+                  uint8_t *tags) {
+  grid_t g;
+  grid_init(&g, dim, nc, h, 0, 0);
+  double hmax = 0.0;
+  for (int a = 0; a < dim; ++a) hmax = h[a] > hmax ? h[a] : hmax;
+  for (long c = 0; c < g.NC; ++c) {
+    long ci[3] = {c % g.nc[0], (c / g.nc[0]) % g.nc[1], c / (g.nc[0] * g.nc[1])};
+    double s = 0.0;
+    for (int a = 0; a < dim; ++a) {
+      long p[3] = {ci[0], ci[1], ci[2]}, m[3] = {ci[0], ci[1], ci[2]};
+      p[a] = ci[a] + 1 < g.nc[a] ? ci[a] + 1 : ci[a];
+      m[a] = ci[a] > 0 ? ci[a] - 1 : ci[a];
+      double d = psi[p[0] + g.nc[0] * (p[1] + g.nc[1] * p[2])] -
+                 psi[m[0] + g.nc[0] * (m[1] + g.nc[1] * m[2])];
+      double gr = d / (2.0 * h[a]);
+      s = s + gr * gr;
+    }
+    tags[c] = (s * (hmax * hmax) > thresh * thresh) ? 1 : 0;
+  }
+}
+
+/* Block flags of levels 1..A from the tags of levels 0..A-1. */
+static void amr_blocks(amr_t *m, uint8_t *const *tags) {
+  const int d = m->dim;
+  for (int a = 1; a <= m->A; ++a) {
+    grid_t *gc = &m->g[a - 1];
+    long half = m->bc / 2; /* a block covers bc/2 coarse cells per axis */
+    long nbt = m->nb[a][0] * m->nb[a][1] * m->nb[a][2];
+    for (long b = 0; b < nbt; ++b) {
+      long bi[3] = {b % m->nb[a][0], (b / m->nb[a][0]) % m->nb[a][1], b / (m->nb[a][0] * m->nb[a][1])};
+      long lo[3], hi[3];
+      for (int ax = 0; ax < 3; ++ax) {
+        if (ax < d) {
+          lo[ax] = bi[ax] * half - 1;
+          hi[ax] = bi[ax] * half + half; /* inclusive: footprint grown by one cell */
+          if (lo[ax] < 0) lo[ax] = 0;
+          if (hi[ax] > gc->nc[ax] - 1) hi[ax] = gc->nc[ax] - 1;
+        } else { lo[ax] = hi[ax] = 0; }
+      }
+      int on = 0;
+      for (long k = lo[2]; k <= hi[2] && !on; ++k)
+        for (long j = lo[1]; j <= hi[1] && !on; ++j)
+          for (long i = lo[0]; i <= hi[0] && !on; ++i)
+            if (tags[a - 1][i + gc->nc[0] * (j + gc->nc[1] * k)]) on = 1;
+      m->blk[a][b] = (uint8_t)on;
+    }
+  }
+  /* nesting, finest first: parent and the parent's neighbours on the sides
+   * the block touches */
+  for (int a = m->A; a >= 2; --a) {
+    long nbt = m->nb[a][0] * m->nb[a][1] * m->nb[a][2];
+    for (long b = 0; b < nbt; ++b) {
+      if (!m->blk[a][b]) continue;
+      long bi[3] = {b % m->nb[a][0], (b / m->nb[a][0]) % m->nb[a][1], b / (m->nb[a][0] * m->nb[a][1])};
+      long pb[3], sgn[3];
+      for (int ax = 0; ax < 3; ++ax) {
+        pb[ax] = bi[ax] / 2;
+        sgn[ax] = (ax < d) ? ((bi[ax] % 2) ? 1 : -1) : 0;
+      }
+      for (int o = 0; o < 8; ++o) {
+        long q[3];
+        int ok = 1;
+        for (int ax = 0; ax < 3; ++ax) {
+          int bit = (o >> ax) & 1;
+          if (ax >= d && bit) ok = 0;
+          q[ax] = pb[ax] + (bit ? sgn[ax] : 0);
+          if (ax < d && (q[ax] < 0 || q[ax] >= m->nb[a - 1][ax])) ok = 0;
+        }
+        if (!ok) continue;
+        m->blk[a - 1][q[0] + m->nb[a - 1][0] * (q[1] + m->nb[a - 1][1] * q[2])] = 1;
+      }
+    }
+  }
+}
+
+static int amr_cell_active(const amr_t *m, int a, const long *c) {
+  for (int ax = 0; ax < m->dim; ++ax)
+    if (c[ax] < 0 || c[ax] >= m->g[a].nc[ax]) return -1; /* outside the box */
+  long b[3] = {0, 0, 0};
+  for (int ax = 0; ax < m->dim; ++ax) b[ax] = c[ax] / m->bc;
+  return m->blk[a][b[0] + m->nb[a][0] * (b[1] + m->nb[a][1] * b[2])];
+}
+
+/* Node classes of level a >= 1 (0 none, 1 interior, 2 interface, 3/4 outer layers). */
+static void amr_classify(amr_t *m, int a) {
+  grid_t *g = &m->g[a];
+  const int d = m->dim;
+  uint8_t *clo = (uint8_t *)calloc(g->NN, 1); /* in the closure of the active region */
+  for (long id = 0; id < g->NN; ++id) {
+    long n[3];
+    node_of(g, id, n);
+    int any = 0, all = 1;
+    for (int o = 0; o < (1 << d); ++o) {
+      long c[3] = {0, 0, 0};
+      for (int ax = 0; ax < d; ++ax) c[ax] = n[ax] - 1 + ((o >> ax) & 1);
+      int act = amr_cell_active(m, a, c);
+      if (act < 0) continue;
+      if (act) any = 1; else all = 0;
+    }
+    clo[id] = (uint8_t)any;
+    m->cls[a][id] = any ? (all ? 1 : 2) : 0;
+  }
+  for (int layer = 1; layer <= 2; ++layer)
+    for (long id = 0; id < g->NN; ++id) {
+      if (m->cls[a][id] != 0) continue;
+      long n[3];
+      node_of(g, id, n);
+      int near = 0;
+      for (long dk = (d > 2 ? -layer : 0); dk <= (d > 2 ? layer : 0) && !near; ++dk)
+        for (long dj = -layer; dj <= layer && !near; ++dj)
+          for (long di = -layer; di <= layer && !near; ++di) {
+            long q[3] = {n[0] + di, n[1] + dj, n[2] + dk};
+            if (!node_inside(g, q)) continue;
+            if (clo[node_id(g, q)]) near = 1;
+          }
+      if (near) m->cls[a][id] = (uint8_t)(2 + layer);
+    }
+  free(clo);
+}
+
+/* Quadratic interpolation weights along one axis for fine index n:
+ * even n -> coarse n/2 (weight 1); odd n = 2I+1 -> nodes {I-1, I, I+1}
+ * with (-1/8, 3/4, 3/8), or {I, I+1, I+2} with (3/8, 3/4, -1/8) when I = 0. */
+static int quad_axis(long n, long ncn, long *idx, double *w) {
+  (void)ncn;
+  if (n % 2 == 0) { idx[0] = n / 2; w[0] = 1.0; return 1; }
+  long I = (n - 1) / 2;
+  if (I >= 1) { idx[0] = I - 1; idx[1] = I; idx[2] = I + 1; w[0] = -0.125; w[1] = 0.75; w[2] = 0.375; }
+  else { idx[0] = I; idx[1] = I + 1; idx[2] = I + 2; w[0] = 0.375; w[1] = 0.75; w[2] = -0.125; }
+  return 3;
+}
+
+/* Ghost nodes (classes 2-4) of level a from level a-1; displacement DOF keep
+ * their values. */
+static void amr_ghost_fill(const amr_t *m, int a, const double *xc, double *xf) {
+  const grid_t *gf = &m->g[a], *gc = &m->g[a - 1];
+  const int d = m->dim;
+  for (long id = 0; id < gf->NN; ++id) {
+    uint8_t c = m->cls[a][id];
+    if (c < 2) continue;
+    long n[3];
+    node_of(gf, id, n);
+    long ix[3][3];
+    double w[3][3];
+    int cnt[3] = {1, 1, 1};
+    for (int ax = 0; ax < 3; ++ax) {
+      if (ax < d) cnt[ax] = quad_axis(n[ax], gc->nn[ax], ix[ax], w[ax]);
+      else { ix[ax][0] = 0; w[ax][0] = 1.0; }
+    }
+    for (int k = 0; k < d; ++k) {
+      long q = (long)k * gf->NN + id;
+      if (m->dm[a][q]) continue;
+      double s = 0.0;
+      for (int t2 = 0; t2 < cnt[2]; ++t2)
+        for (int t1 = 0; t1 < cnt[1]; ++t1)
+          for (int t0 = 0; t0 < cnt[0]; ++t0) {
+            long I[3] = {ix[0][t0], ix[1][t1], ix[2][t2]};
+            s += w[0][t0] * w[1][t1] * w[2][t2] * xc[(long)k * gc->NN + node_id(gc, I)];
+          }
+      xf[q] = s;
+    }
+  }
+}
+
+void orc_amr_ghost_fill(void *ctx, int level, const double *xc, double *xf) {
+  amr_ghost_fill((amr_t *)ctx, level, xc, xf);
+}
+
+/* fine class at the node coinciding with coarse node cid of level a-1 */
+static uint8_t amr_fine_class_at(const amr_t *m, int a, long cid) {
+  long n[3];
+  node_of(&m->g[a - 1], cid, n);
+  long f[3] = {2 * n[0], 2 * n[1], m->dim > 2 ? 2 * n[2] : 0};
+  return m->cls[a][node_id(&m->g[a], f)];
+}
+
+/* padded residual r = f - K x on the rows of level a that carry one
+ * (a = 0: all nodes; a >= 1: classes 1-3), 0 elsewhere and on fixed DOF. */
+static void amr_level_residual(const amr_t *m, int a, const double *x, const double *f, double *r) {
+  const grid_t *g = &m->g[a];
+  orc_residual(m->dim, g->nc, g->h, m->lam, m->mu, m->psi[a], m->dm[a], x, f, r);
+  if (a == 0) return;
+  for (long id = 0; id < g->NN; ++id) {
+    uint8_t c = m->cls[a][id];
+    if (c >= 1 && c <= 3) continue;
+    for (int k = 0; k < m->dim; ++k) r[(long)k * g->NN + id] = 0.0;
+  }
+}
+
+/* (R w_f)(I) = 2^-d sum P(n, I) w_f(n) at coarse node cid of level a-1 */
+static void amr_restrict_at(const amr_t *m, int a, long cid, const double *wf, double *out) {
+  const grid_t *gc = &m->g[a - 1], *gf = &m->g[a];
+  const int d = m->dim;
+  long I[3];
+  node_of(gc, cid, I);
+  for (int k = 0; k < d; ++k) out[k] = 0.0;
+  for (long dk = (d > 2 ? -1 : 0); dk <= (d > 2 ? 1 : 0); ++dk)
+    for (long dj = -1; dj <= 1; ++dj)
+      for (long di = -1; di <= 1; ++di) {
+        long n[3] = {2 * I[0] + di, 2 * I[1] + dj, d > 2 ? 2 * I[2] + dk : 0};
+        if (!node_inside(gf, n)) continue;
+        double w = 1.0;
+        for (int ax = 0; ax < d; ++ax) w *= p_weight_axis(n[ax], I[ax]);
+        long fid = node_id(gf, n);
+        for (int k = 0; k < d; ++k) out[k] += w * wf[(long)k * gf->NN + fid];
+      }
+  for (int k = 0; k < d; ++k) out[k] /= (double)(1 << d);
+}
+
+/* Composite residual of (x, f): padded level residuals, coarse nodes on or
+ * inside the next finer region replaced by R of its padded residual.
+ * Ghosts of x are filled first.  Returns ||r|| over composite unknowns. */
+static double amr_comp_residual(const amr_t *m, double **x, double *const *f, double **r) {
+  const int d = m->dim;
+  for (int a = 1; a <= m->A; ++a) amr_ghost_fill(m, a, x[a - 1], x[a]);
+  for (int a = m->A; a >= 0; --a) {
+    amr_level_residual(m, a, x[a], f[a], r[a]);
+    if (a == m->A) continue;
+    const grid_t *g = &m->g[a];
+    for (long id = 0; id < g->NN; ++id) {
+      uint8_t fc = amr_fine_class_at(m, a + 1, id);
+      if (fc != 1 && fc != 2) continue;
+      double rr[3];
+      amr_restrict_at(m, a + 1, id, r[a + 1], rr);
+      for (int k = 0; k < d; ++k) {
+        long q = (long)k * g->NN + id;
+        r[a][q] = m->dm[a][q] ? 0.0 : rr[k];
+      }
+    }
+  }
+  double s = 0.0;
+  for (int a = 0; a <= m->A; ++a) {
+    const grid_t *g = &m->g[a];
+    for (long id = 0; id < g->NN; ++id) {
+      if (a >= 1 && m->cls[a][id] != 1) continue;
+      if (a < m->A && amr_fine_class_at(m, a + 1, id) == 1) continue; /* covered */
+      for (int k = 0; k < d; ++k) {
+        long q = (long)k * g->NN + id;
+        if (!m->dm[a][q]) s += r[a][q] * r[a][q];
+      }
+    }
+  }
+  return sqrt(s);
+}
+
+/* coarse nodes strictly inside level a's region take the injected fine values */
+static void amr_inject(const amr_t *m, int a, const double *xf, double *xc) {
+  const grid_t *gc = &m->g[a - 1], *gf = &m->g[a];
+  for (long id = 0; id < gc->NN; ++id) {
+    if (amr_fine_class_at(m, a, id) != 1) continue;
+    long n[3];
+    node_of(gc, id, n);
+    long fn[3] = {2 * n[0], 2 * n[1], m->dim > 2 ? 2 * n[2] : 0};
+    long fid = node_id(gf, fn);
+    for (int k = 0; k < m->dim; ++k) xc[(long)k * gc->NN + id] = xf[(long)k * gf->NN + fid];
+  }
+}
+
+/* Colour-synchronous Gauss-Seidel half-sweep on the unknowns of level a >= 1
+ * (class 1, free DOF); every other node keeps its value. */
+static void amr_smooth(const amr_t *m, int a, double *x, const double *f, int sweeps, int reverse,
+                       double *tmp) {
+  const grid_t *g = &m->g[a];
+  long n3 = (long)m->dim * g->NN;
+  for (int s = 0; s < sweeps; ++s)
+    for (int h = 0; h < 2; ++h) {
+      int colour = reverse ? 1 - h : h;
+      if (m->o.smoother == 1) { if (h == 1) break; }
+      if (m->o.smoother == 1)
+        orc_jacobi(m->dim, g->nc, g->h, m->lam, m->mu, m->psi[a], m->dm[a], m->o.omega, x, f, tmp);
+      else
+        orc_rb_half(m->dim, g->nc, g->h, m->lam, m->mu, m->psi[a], m->dm[a], m->o.omega, colour, x,
+                    f, tmp);
+      for (long q = 0; q < n3; ++q) {
+        long id = q % g->NN;
+        if (m->cls[a][id] == 1) x[q] = tmp[q];
+      }
+    }
+}
+
+/* FAS multilevel cycle over levels a..1 (x, f per level; f may be modified
+ * at covered/interface nodes of coarser levels), ending in the base
+ * V-cycle. */
+static void amr_fas(amr_t *m, int a, double **x, double **f, double **w, double **xinj,
+                    double **tmp) {
+  const int d = m->dim;
+  if (a == 0) {
+    vcycle(d, m->hier, m->nlev, 0, m->lam, m->mu, &m->o, x[0], f[0]);
+    return;
+  }
+  const grid_t *gc = &m->g[a - 1], *gf = &m->g[a];
+  amr_ghost_fill(m, a, x[a - 1], x[a]);
+  amr_smooth(m, a, x[a], f[a], m->o.nu_pre, 0, tmp[a]);
+  amr_ghost_fill(m, a, x[a - 1], x[a]);
+  amr_level_residual(m, a, x[a], f[a], w[a]);
+  amr_inject(m, a, x[a], x[a - 1]);
+  memcpy(xinj[a - 1], x[a - 1], sizeof(double) * d * gc->NN);
+  /* FAS load on covered and interface coarse nodes: R w + K_c x_c */
+  double *Kx = tmp[a - 1];
+  orc_apply(d, gc->nc, gc->h, m->lam, m->mu, m->psi[a - 1], x[a - 1], Kx);
+  for (long id = 0; id < gc->NN; ++id) {
+    uint8_t fc = amr_fine_class_at(m, a, id);
+    if (fc != 1 && fc != 2) continue;
+    double rr[3];
+    amr_restrict_at(m, a, id, w[a], rr);
+    for (int k = 0; k < d; ++k) {
+      long q = (long)k * gc->NN + id;
+      if (!m->dm[a - 1][q]) f[a - 1][q] = rr[k] + Kx[q];
+    }
+  }
+  amr_fas(m, a - 1, x, f, w, xinj, tmp);
+  /* x_f += P (x_c - inject(x_f)) on the unknowns of level a */
+  double *dc = tmp[a - 1];
+  for (long q = 0; q < (long)d * gc->NN; ++q) dc[q] = x[a - 1][q] - xinj[a - 1][q];
+  double *pf = w[a];
+  memset(pf, 0, sizeof(double) * d * gf->NN);
+  orc_prolong_add(d, gc->nc, dc, m->dm[a], pf);
+  for (long q = 0; q < (long)d * gf->NN; ++q)
+    if (m->cls[a][q % gf->NN] == 1) x[a][q] += pf[q];
+  amr_ghost_fill(m, a, x[a - 1], x[a]);
+  amr_smooth(m, a, x[a], f[a], m->o.nu_post, 0, tmp[a]);
+}
+
+/* psi_raw[a]: raw indicator sampled at level a's cell centres (dense). */
+void *orc_amr_new(int dim, int A, int bc, const long *nc0, const double *h0, double lam, double mu,
+                  const double *const *psi_raw, double psi_floor, const int *kind, const double *val,
+                  double thresh, int smoother, double omega, int nu_pre, int nu_post,
+                  double bottom_rtol, int bottom_max_iter, const uint8_t *const *blk_in) {
+  amr_t *m = (amr_t *)calloc(1, sizeof(amr_t));
+  m->dim = dim; m->A = A; m->bc = bc; m->lam = lam; m->mu = mu;
+  memcpy(m->kind, kind, sizeof(int) * 18);
+  memcpy(m->val, val, sizeof(double) * 18);
+  orc_opts o = {smoother, omega, nu_pre, nu_post, 0.0, 0, bottom_rtol, bottom_max_iter, 0};
+  m->o = o;
+  for (int a = 0; a <= A; ++a) {
+    long nc[3];
+    double h[3];
+    for (int ax = 0; ax < 3; ++ax) {
+      nc[ax] = ax < dim ? nc0[ax] << a : 0;
+      h[ax] = ax < dim ? h0[ax] / (double)(1 << a) : 1.0;
+    }
+    grid_init(&m->g[a], dim, nc, h, lam, mu);
+    m->psi[a] = (double *)malloc(sizeof(double) * m->g[a].NC);
+    orc_floor(m->g[a].NC, psi_raw[a], psi_floor, m->psi[a]);
+    m->dm[a] = (uint8_t *)malloc((size_t)dim * m->g[a].NN);
+    m->uD[a] = (double *)malloc(sizeof(double) * dim * m->g[a].NN);
+    orc_dirichlet_mask(dim, nc, kind, val, m->dm[a], m->uD[a]);
+    if (a >= 1) {
+      for (int ax = 0; ax < 3; ++ax) m->nb[a][ax] = ax < dim ? m->g[a].nc[ax] / bc : 1;
+      m->blk[a] = (uint8_t *)calloc(m->nb[a][0] * m->nb[a][1] * m->nb[a][2], 1);
+      m->cls[a] = (uint8_t *)calloc(m->g[a].NN, 1);
+    }
+  }
+  if (blk_in) { /* block flags given (levels 1..A) */
+    for (int a = 1; a <= A; ++a)
+      memcpy(m->blk[a], blk_in[a - 1], m->nb[a][0] * m->nb[a][1] * m->nb[a][2]);
+  } else {
+    uint8_t *tags[AMR_MAXL] = {0};
+    for (int a = 0; a < A; ++a) {
+      tags[a] = (uint8_t *)malloc(m->g[a].NC);
+      orc_amr_tags(dim, m->g[a].nc, m->g[a].h, m->psi[a], thresh, tags[a]);
+    }
+    amr_blocks(m, tags);
+    for (int a = 0; a < A; ++a) free(tags[a]);
+  }
+  for (int a = 1; a <= A; ++a) amr_classify(m, a);
+  /* psi of covered coarse cells: mean of the children, finest first */
+  for (int a = A; a >= 1; --a) {
+    grid_t *gc = &m->g[a - 1];
+    for (long c = 0; c < gc->NC; ++c) {
+      long ci[3] = {c % gc->nc[0], (c / gc->nc[0]) % gc->nc[1], c / (gc->nc[0] * gc->nc[1])};
+      long fc[3] = {2 * ci[0], 2 * ci[1], dim > 2 ? 2 * ci[2] : 0};
+      if (amr_cell_active(m, a, fc) != 1) continue;
+      double s = 0.0;
+      for (int o2 = 0; o2 < (1 << dim); ++o2) {
+        long q[3] = {fc[0] + (o2 & 1), fc[1] + ((o2 >> 1) & 1), dim > 2 ? fc[2] + ((o2 >> 2) & 1) : 0};
+        s += m->psi[a][q[0] + m->g[a].nc[0] * (q[1] + m->g[a].nc[1] * q[2])];
+      }
+      m->psi[a - 1][c] = s / (double)(1 << dim);
+    }
+  }
+  for (int a = 0; a <= A; ++a) {
+    m->fP[a] = (double *)malloc(sizeof(double) * dim * m->g[a].NN);
+    orc_rhs(dim, m->g[a].nc, m->g[a].h, lam, mu, m->psi[a], kind, val, NULL, m->fP[a], NULL, NULL);
+  }
+  /* uniform hierarchy of the base level */
+  m->nlev = count_levels(dim, nc0);
+  m->hier = (level_t *)calloc(m->nlev, sizeof(level_t));
+  for (int l = 0; l < m->nlev; ++l) {
+    level_t *L = &m->hier[l];
+    for (int ax = 0; ax < 3; ++ax) {
+      L->nc[ax] = (ax < dim) ? (l == 0 ? nc0[ax] : m->hier[l - 1].nc[ax] / 2) : 0;
+      L->h[ax] = (ax < dim) ? (l == 0 ? h0[ax] : 2.0 * m->hier[l - 1].h[ax]) : 1.0;
+    }
+    long NC = 1, NN = 1;
+    for (int ax = 0; ax < dim; ++ax) { NC *= L->nc[ax]; NN *= L->nc[ax] + 1; }
+    L->n3 = (long)dim * NN;
+    L->psi = (double *)malloc(sizeof(double) * NC);
+    L->mask = (uint8_t *)malloc(L->n3);
+    L->e = (double *)calloc(L->n3, sizeof(double));
+    L->f = (double *)calloc(L->n3, sizeof(double));
+    L->r = (double *)calloc(L->n3, sizeof(double));
+    L->tmp = (double *)calloc(L->n3, sizeof(double));
+    if (l == 0) memcpy(L->psi, m->psi[0], sizeof(double) * NC);
+    else orc_coarsen_psi(dim, m->hier[l - 1].nc, m->hier[l - 1].psi, L->psi);
+    orc_dirichlet_mask(dim, L->nc, kind, val, L->mask, NULL);
+  }
+  /* ||lifted load||: composite residual of the prescribed values */
+  double *x[AMR_MAXL], *r[AMR_MAXL];
+  for (int a = 0; a <= A; ++a) {
+    x[a] = m->uD[a];
+    r[a] = (double *)malloc(sizeof(double) * dim * m->g[a].NN);
+  }
+  double *xs[AMR_MAXL];
+  for (int a = 0; a <= A; ++a) {
+    xs[a] = (double *)malloc(sizeof(double) * dim * m->g[a].NN);
+    memcpy(xs[a], x[a], sizeof(double) * dim * m->g[a].NN);
+  }
+  m->fnorm = amr_comp_residual(m, xs, m->fP, r);
+  for (int a = 0; a <= A; ++a) { free(r[a]); free(xs[a]); }
+  return m;
+}
+
+void orc_amr_free(void *ctx) {
+  amr_t *m = (amr_t *)ctx;
+  if (!m) return;
+  for (int a = 0; a <= m->A; ++a) {
+    free(m->blk[a]); free(m->cls[a]); free(m->psi[a]); free(m->dm[a]); free(m->uD[a]); free(m->fP[a]);
+  }
+  for (int l = 0; l < m->nlev; ++l) {
+    free(m->hier[l].psi); free(m->hier[l].mask); free(m->hier[l].e);
+    free(m->hier[l].f); free(m->hier[l].r); free(m->hier[l].tmp);
+  }
+  free(m->hier);
+  free(m);
+}
+
+/* Level info: block flags (a >= 1), node classes (a >= 1), psi (all). */
+void orc_amr_info(void *ctx, int a, uint8_t *blk, uint8_t *cls, double *psi, long *nb) {
+  amr_t *m = (amr_t *)ctx;
+  if (nb) for (int ax = 0; ax < 3; ++ax) nb[ax] = a >= 1 ? m->nb[a][ax] : 0;
+  if (blk && a >= 1) memcpy(blk, m->blk[a], m->nb[a][0] * m->nb[a][1] * m->nb[a][2]);
+  if (cls && a >= 1) memcpy(cls, m->cls[a], m->g[a].NN);
+  if (psi) memcpy(psi, m->psi[a], sizeof(double) * m->g[a].NC);
+}
+
+double orc_amr_fnorm(void *ctx) { return ((amr_t *)ctx)->fnorm; }
+
+/* Composite residual of the levels' x (ghosts of x are refilled) for the
+ * problem's loads, or for the loads f when f is not NULL. */
+double orc_amr_residual(void *ctx, double **x, double **f, double **r) {
+  amr_t *m = (amr_t *)ctx;
+  return amr_comp_residual(m, x, f ? f : m->fP, r);
+}
+
+/* Composite solve: u[a] in = guess (displacement DOF overwritten), out =
+ * solution with covered nodes injected and ghosts filled. */
+int orc_amr_solve(void *ctx, double rtol, int max_cycles, double **u, double *hist, int hist_cap,
+                  int *n_cycles) {
+  amr_t *m = (amr_t *)ctx;
+  const int d = m->dim, A = m->A;
+  double *r[AMR_MAXL], *e[AMR_MAXL], *w[AMR_MAXL], *xinj[AMR_MAXL], *tmp[AMR_MAXL];
+  for (int a = 0; a <= A; ++a) {
+    long n3 = (long)d * m->g[a].NN;
+    for (long q = 0; q < n3; ++q)
+      if (m->dm[a][q]) u[a][q] = m->uD[a][q];
+    r[a] = (double *)malloc(sizeof(double) * n3);
+    e[a] = (double *)malloc(sizeof(double) * n3);
+    w[a] = (double *)malloc(sizeof(double) * n3);
+    xinj[a] = (double *)malloc(sizeof(double) * n3);
+    tmp[a] = (double *)malloc(sizeof(double) * n3);
+  }
+  for (int a = A; a >= 1; --a) amr_inject(m, a, u[a], u[a - 1]);
+  int status = 1, cyc;
+  for (cyc = 0;; ++cyc) {
+    double rn = amr_comp_residual(m, u, m->fP, r);
+    double rho = m->fnorm > 0.0 ? rn / m->fnorm : 0.0;
+    if (cyc < hist_cap) hist[cyc] = rho;
+    if (rho <= rtol) { status = 0; break; }
+    if (cyc >= max_cycles) break;
+    /* correction cycle: loads = composite residual, x = 0 */
+    for (int a = 0; a <= A; ++a) memset(e[a], 0, sizeof(double) * d * m->g[a].NN);
+    amr_fas(m, A, e, r, w, xinj, tmp);
+    for (int a = 0; a <= A; ++a) {
+      long n3 = (long)d * m->g[a].NN;
+      for (long q = 0; q < n3; ++q) {
+        if (m->dm[a][q]) continue;
+        if (a >= 1 && m->cls[a][q % m->g[a].NN] != 1) continue;
+        u[a][q] += e[a][q];
+      }
+    }
+    for (int a = A; a >= 1; --a) amr_inject(m, a, u[a], u[a - 1]);
+  }
+  for (int a = 1; a <= A; ++a) amr_ghost_fill(m, a, u[a - 1], u[a]);
+  *n_cycles = cyc;
+  for (int a = 0; a <= A; ++a) { free(r[a]); free(e[a]); free(w[a]); free(xinj[a]); free(tmp[a]); }
+  return status;
+}

@@ -221,3 +221,57 @@ def mixed_bc(dim, seed=0):
             val[F, k] = rng.uniform(-1e-3, 1e-3)
     kind[0, :dim] = DISPLACEMENT  # something always pins the rigid modes
     return kind, val
+
+
+def _quat_rot(q):
+    w, x, y, z = q / np.linalg.norm(q)
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                     [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                     [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+
+
+def ellipsoidal_voids_amr(base: int = 64, levels: int = 3, block: int = 32, seed: int = 0,
+                          nvoid: int = 10, floor: float = 1e-5):
+    """Unit cube with seeded ellipsoidal voids for the adaptive solve: centres
+    U[0,1]^3, then semi-axes U[0.04,0.12] (nvoid x 3), then orientations from
+    unit quaternions drawn from N(0, I4).  The indicator is the product of
+    0.5 (1 + tanh(d / (2 h_f))) with d = (q - 1)/|grad q|, q = |A^-1 R^T (x - c)|
+    and h_f the finest spacing, sampled at the cell centres of every level
+    (level a: base * 2^a cells per axis).  z=0 clamped, u=(0,0,1e-3) on z=1.
+    Returns (Problem of the base level, list of per-level raw psi)."""
+    rng = np.random.default_rng(seed)
+    centres = rng.uniform(0.0, 1.0, (nvoid, 3))
+    axes = rng.uniform(0.04, 0.12, (nvoid, 3))
+    quats = rng.standard_normal((nvoid, 4))
+    hf = 1.0 / (base << (levels - 1))
+    psis = []
+    for a in range(levels):
+        n = base << a
+        h = 1.0 / n
+        X, Y, Z = cell_centres((n, n, n), (h, h, h))
+        psi = np.ones_like(X)
+        for c, ax, q in zip(centres, axes, quats):
+            M = np.diag(1.0 / ax) @ _quat_rot(q).T
+            dx, dy, dz = X - c[0], Y - c[1], Z - c[2]
+            y0 = M[0, 0] * dx + M[0, 1] * dy + M[0, 2] * dz
+            y1 = M[1, 0] * dx + M[1, 1] * dy + M[1, 2] * dz
+            y2 = M[2, 0] * dx + M[2, 1] * dy + M[2, 2] * dz
+            qn = np.sqrt(y0 * y0 + y1 * y1 + y2 * y2)
+            MtM = M.T @ M
+            gx = (MtM[0, 0] * dx + MtM[0, 1] * dy + MtM[0, 2] * dz)
+            gy = (MtM[1, 0] * dx + MtM[1, 1] * dy + MtM[1, 2] * dz)
+            gz = (MtM[2, 0] * dx + MtM[2, 1] * dy + MtM[2, 2] * dz)
+            gq = np.sqrt(gx * gx + gy * gy + gz * gz) / np.maximum(qn, 1e-300)
+            dist = (qn - 1.0) / np.maximum(gq, 1e-300)
+            psi *= 0.5 * (1 + np.tanh(dist / (2 * hf)))
+        psis.append(psi)
+    kind, val = _bc_table()
+    kind[4, :] = DISPLACEMENT
+    kind[5, :] = DISPLACEMENT
+    val[5, 2] = 1e-3
+    lam, mu = lame(1.0, 0.3)
+    h0 = 1.0 / base
+    p = Problem("ellipsoidal_voids_amr", (base, base, base), (h0, h0, h0), lam, mu, floor, psis[0],
+                kind, val, extra={"levels": levels, "block": block, "centres": centres,
+                                  "axes": axes, "quats": quats})
+    return p, psis
