@@ -281,6 +281,100 @@ sbm_status sbm_level_prolong_add(sbm_ctx *ctx, int level, const double *e_coarse
  * the iteration count (this call synchronises). */
 sbm_status sbm_bottom_solve(sbm_ctx *ctx, const double *f, double *x, int *iters_host);
 
+/* ------------------------------------------------------------------------
+ * Block-structured adaptive composite solve (Sec. 2.2: AMR levels of the
+ * same operator exchanging data by averaging and ghost cells, the refined
+ * levels forming the upper part of the multigrid level sequence, every level
+ * padded by a ghost layer so that no special coarse-fine stencil is needed).
+ *
+ * Layout: AMR level a = 0..levels-1 has cells ncell0 * 2^a per axis and
+ * spacing h0 / 2^a and is stored DENSELY over the box (node vectors and cell
+ * arrays in the layouts above).  Levels a >= 1 are active on cubic blocks of
+ * `block` cells; block flags are uint8 [nbz][nby][nbx] with nb = ncell / block.
+ * Nodes of a level a >= 1 carry a class (uint8, node layout): 0 unused,
+ * 1 unknown (interior of the active region), 2 interface (owned by level
+ * a-1), 3 and 4 the first and second node layer outside.  Classes 2-4 are
+ * ghosts filled from level a-1 by tensor-product quadratic interpolation:
+ * along an axis an even fine index copies the coinciding coarse node, an odd
+ * index 2I+1 takes nodes I-1, I, I+1 with weights -1/8, 3/4, 3/8 (I = 0:
+ * nodes 0, 1, 2 with 3/8, 3/4, -1/8).
+ *
+ * Refinement (when no block flags are given): level-a cells (a < levels-1)
+ * are tagged where |grad psi| h > tag_threshold (central differences on the
+ * floored psi, neighbours clamped at the box, h the largest spacing;
+ * Sec. 3.3 uses 0.05); a level-(a+1) block is active when a tagged level-a
+ * cell lies in its footprint grown by one cell; each active block then
+ * activates its parent block and the parent's neighbours on the sides it
+ * touches.  Covered coarse cells take the mean psi of their 2^d children.
+ *
+ * Composite residual: on levels a >= 1 the level residual on classes 1-3
+ * (0 elsewhere); coarse nodes whose coinciding fine node has class 1 or 2
+ * take the full-weighting restriction of it; the norm runs over the
+ * composite unknowns (class 1 at a >= 1, every node at a = 0, minus nodes
+ * covered by a finer class-1 node, minus displacement DOF), relative to the
+ * same norm of the lifted load.
+ *
+ * Composite cycle: full-approximation cycle over the AMR levels (smooth the
+ * unknowns, restrict the padded residual, coarse load R w + K_c x_c on
+ * covered and interface nodes, recurse, correct the unknowns by
+ * P (x_c - inject x_f), smooth) ending in one V-cycle of the base grid's
+ * uniform hierarchy; run in correction form on the composite residual inside
+ * an FP64 outer loop (options.precision 1: the cycle in FP32 on the residual
+ * scaled to unit norm).  options.krylov must be 0.
+ *
+ * Conventions as above: device pointers unless _host, the caller owns all
+ * memory, the workspace is carved (sbm_amr_workspace_bytes), work is
+ * enqueued on the given stream.  Arrays of per-level pointers are HOST
+ * arrays with `levels` entries (block flags: levels-1 entries for a >= 1).
+ * ---------------------------------------------------------------------- */
+typedef struct sbm_amr_ctx sbm_amr_ctx;
+
+/* Workspace bytes for a base grid, levels (1..4, base included), block size
+ * (even, dividing 2 * ncell0 on every axis) and options; 0 if unsupported. */
+size_t sbm_amr_workspace_bytes(const sbm_grid *base, int levels, int block,
+                               const sbm_options *opts);
+
+sbm_status sbm_amr_create(const sbm_grid *base, int levels, int block, const sbm_options *opts,
+                          void *workspace, size_t workspace_bytes, void *hip_stream,
+                          sbm_amr_ctx **out);
+
+sbm_status sbm_amr_set_options(sbm_amr_ctx *ctx, const sbm_options *opts);
+
+/* psi_raw[a]: raw indicator at the cell centres of level a (device, dense),
+ * floored cell-wise by mat->psi_floor.  blocks_host: NULL (tag with
+ * tag_threshold) or levels-1 host arrays of block flags of levels 1.. that
+ * are used as given.  Synchronises. */
+sbm_status sbm_amr_set_problem(sbm_amr_ctx *ctx, const double *const *psi_raw,
+                               const sbm_material *mat, const sbm_bc *bc, double tag_threshold,
+                               const uint8_t *const *blocks_host);
+
+/* Level a: cells per axis, blocks per axis (0 at a = 0), block flags (host,
+ * a >= 1), node classes (device, a >= 1) and the floored, averaged-down psi
+ * (device); every output may be NULL.  Synchronises. */
+sbm_status sbm_amr_level_info(sbm_amr_ctx *ctx, int level, int64_t *ncell_host,
+                              int64_t *nblocks_host, uint8_t *blocks_host, uint8_t *classes,
+                              double *psi);
+
+/* Number of composite unknowns (free DOF) and the norm of the lifted load. */
+sbm_status sbm_amr_stats(sbm_amr_ctx *ctx, int64_t *composite_dof_host, double *fnorm_host);
+
+/* Ghost nodes (classes 2-4, free DOF) of level a >= 1 in xf from xc of level
+ * a-1 (async). */
+sbm_status sbm_amr_ghost_fill(sbm_amr_ctx *ctx, int level, const double *xc, double *xf);
+
+/* Composite residual of u (ghosts of u are refilled in place) into r (per
+ * level; r or any r[a] may be NULL) and its norm (absolute).  Synchronises. */
+sbm_status sbm_amr_residual(sbm_amr_ctx *ctx, double *const *u, double *const *r,
+                            double *norm_host);
+
+/* Composite solve: u[a] in = guess (displacement DOF set, covered coarse
+ * nodes injected), out = solution with covered nodes injected and ghosts
+ * filled; history of relative composite residuals as in sbm_solve. */
+sbm_status sbm_amr_solve(sbm_amr_ctx *ctx, double *const *u, double *hist_host, int hist_cap,
+                         int *n_cycles_host, double *final_rel_host);
+
+void sbm_amr_destroy(sbm_amr_ctx *ctx);
+
 #ifdef __cplusplus
 }
 #endif

@@ -6,3 +6,4 @@ include/sbm.h.  This package only marshals arguments to that library."""
 from ._lib import DISPLACEMENT, TRACTION, SbmError, lib  # noqa: F401
 from .solver import Solver  # noqa: F401
 from .autograd import SBMSolve, compliance_grad  # noqa: F401
+from .amr import AmrSolver  # noqa: F401

@@ -82,6 +82,23 @@ SIGNATURES = {
     "sbm_level_restrict": (ctypes.c_int, [_P, ctypes.c_int, _P, _P]),
     "sbm_level_prolong_add": (ctypes.c_int, [_P, ctypes.c_int, _P, _P]),
     "sbm_bottom_solve": (ctypes.c_int, [_P, _P, _P, _IP]),
+    # block-structured adaptive composite solve; per-level pointer arrays are
+    # host arrays of device pointers
+    "sbm_amr_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(SbmGrid), ctypes.c_int,
+                                                  ctypes.c_int, ctypes.POINTER(SbmOptions)]),
+    "sbm_amr_create": (ctypes.c_int, [ctypes.POINTER(SbmGrid), ctypes.c_int, ctypes.c_int,
+                                      ctypes.POINTER(SbmOptions), _P, ctypes.c_size_t, _P,
+                                      ctypes.POINTER(_P)]),
+    "sbm_amr_set_options": (ctypes.c_int, [_P, ctypes.POINTER(SbmOptions)]),
+    "sbm_amr_set_problem": (ctypes.c_int, [_P, ctypes.POINTER(_P), ctypes.POINTER(SbmMaterial),
+                                           ctypes.POINTER(SbmBc), ctypes.c_double,
+                                           ctypes.POINTER(_P)]),
+    "sbm_amr_level_info": (ctypes.c_int, [_P, ctypes.c_int, _I64P, _I64P, _P, _P, _P]),
+    "sbm_amr_stats": (ctypes.c_int, [_P, _I64P, _DP]),
+    "sbm_amr_ghost_fill": (ctypes.c_int, [_P, ctypes.c_int, _P, _P]),
+    "sbm_amr_residual": (ctypes.c_int, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), _DP]),
+    "sbm_amr_solve": (ctypes.c_int, [_P, ctypes.POINTER(_P), _DP, ctypes.c_int, _IP, _DP]),
+    "sbm_amr_destroy": (None, [_P]),
 }
 
 _lib = None

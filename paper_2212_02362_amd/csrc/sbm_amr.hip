@@ -1,0 +1,1152 @@
+// sbm_amr.hip -- block-structured adaptive composite solve (BSAMR) on one GPU:
+// refinement tags and block flags, node classes, coarse-fine ghost fill, the
+// composite residual and the composite multilevel cycle, plus the sbm_amr_*
+// C ABI.
+//
+// The paper (Sec. 2.2) runs the same operator on block-structured AMR levels
+// that exchange data by averaging fine to coarse and by ghost cells coarse to
+// fine, treats the refined levels as the upper part of the multigrid level
+// sequence, and pads every level with one extra ghost layer so that the
+// restriction stencil stays translation invariant and no special coarse-fine
+// stencil is needed.  Reading used here (the details of the cited AMR
+// framework are not in the paper):
+//   * AMR level a has spacing h0 / 2^a and is stored densely over the box;
+//     levels a >= 1 are active on cubic blocks of `block` cells.  Level-a
+//     cells are tagged where |grad psi| h > threshold (central differences
+//     clamped at the box, h the largest spacing; Sec. 3.3 uses 0.05).  A
+//     level-(a+1) block is active when a tagged level-a cell lies in its
+//     footprint grown by one cell; nesting activates the parent block and the
+//     parent's neighbours on the sides the block touches.
+//   * Node classes of a level a >= 1: 1 interior (unknown), 2 interface
+//     (owned by level a-1), 3 and 4 the first and second node layers outside
+//     the active region.  Classes 2-4 are ghosts, filled from level a-1 by
+//     tensor-product quadratic interpolation.
+//   * Covered coarse cells take the mean psi of their children; covered
+//     coarse nodes take the injected fine values.
+//   * Composite residual: padded fine residual on classes 1-3; coarse nodes
+//     on or inside the finer region (fine class 1 or 2) take R of it; other
+//     nodes keep their level residual.  Norm over the composite unknowns.
+//   * Composite cycle: full-approximation multilevel cycle over the AMR levels
+//     (smooth, restrict the padded residual, coarse load R w + K_c x_c on
+//     covered and interface nodes, recurse, correct with P(x_c - inject x_f),
+//     smooth) ending in one V-cycle of the base grid's uniform hierarchy; it
+//     is applied in correction form inside an FP64 outer loop (mixed
+//     precision: the cycle runs in FP32 on the residual scaled to unit norm).
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/sbm.h"
+#include "sbm_internal.h"
+
+using namespace sbm;
+
+namespace {
+
+constexpr int kMaxAmrLevels = 4;  // base + up to 3 refined levels
+
+#define AMR_LAUNCH(kern, grid, block, st, ...)                             \
+  do {                                                                     \
+    (void)hipGetLastError();                                               \
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, st, __VA_ARGS__); \
+    return hipGetLastError();                                              \
+  } while (0)
+
+__device__ __forceinline__ int64_t fine_of_coarse(const Geom &gf, int I, int J, int K) {
+  return 2 * I + (int64_t)gf.nx * (2 * J + (int64_t)gf.ny * (2 * K));
+}
+
+// ------------------------------------------------------------- setup kernels
+
+// Refinement tags of the cells of one level: |grad psi|^2 h^2 > threshold^2
+// with central differences (neighbours clamped at the box).  Evaluated without
+// contraction so that the integer decision does not depend on FMA formation.
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_amr_tags(Geom g, double hx, double hy, double hz,
+                                                     double hmax2, double thr2,
+                                                     const double *__restrict__ psi,
+                                                     uint8_t *__restrict__ tags) {
+#pragma clang fp contract(off)
+  const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (id >= g.nc) return;
+  int i, j, k;
+  cell_ijk(g, id, i, j, k);
+  const int c[3] = {i, j, k};
+  const int n[3] = {g.cx, g.cy, g.cz};
+  const double h[3] = {hx, hy, hz};
+  double s = 0.0;
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    int p[3] = {c[0], c[1], c[2]}, m[3] = {c[0], c[1], c[2]};
+    p[a] = c[a] + 1 < n[a] ? c[a] + 1 : c[a];
+    m[a] = c[a] > 0 ? c[a] - 1 : c[a];
+    const double d = psi[p[0] + (int64_t)g.cx * (p[1] + (int64_t)g.cy * p[2])] -
+                     psi[m[0] + (int64_t)g.cx * (m[1] + (int64_t)g.cy * m[2])];
+    const double gr = d / (2.0 * h[a]);
+    s = s + gr * gr;
+  }
+  tags[id] = (s * hmax2 > thr2) ? 1 : 0;
+}
+
+// Block flags of level a from the tags of level a-1: one workgroup per block,
+// OR over the block's coarse footprint grown by one cell.
+__global__ __launch_bounds__(kBlock) void k_amr_blocks(Geom gc, int dim, int nbx, int nby,
+                                                       int half, const uint8_t *__restrict__ tags,
+                                                       uint8_t *__restrict__ blk) {
+  const int b = blockIdx.x;
+  const int bi[3] = {b % nbx, (b / nbx) % nby, b / (nbx * nby)};
+  const int n[3] = {gc.cx, gc.cy, gc.cz};
+  int lo[3], len[3];
+  for (int a = 0; a < 3; ++a) {
+    if (a < dim) {
+      const int l = max(bi[a] * half - 1, 0);
+      const int h = min(bi[a] * half + half, n[a] - 1);
+      lo[a] = l;
+      len[a] = h - l + 1;
+    } else {
+      lo[a] = 0;
+      len[a] = 1;
+    }
+  }
+  const int count = len[0] * len[1] * len[2];
+  int any = 0;
+  for (int t = threadIdx.x; t < count; t += blockDim.x) {
+    const int x = lo[0] + t % len[0];
+    const int y = lo[1] + (t / len[0]) % len[1];
+    const int z = lo[2] + t / (len[0] * len[1]);
+    if (tags[x + (int64_t)gc.cx * (y + (int64_t)gc.cy * z)]) any = 1;
+  }
+  any = __syncthreads_or(any);
+  if (threadIdx.x == 0) blk[b] = (uint8_t)(any ? 1 : 0);
+}
+
+// Nesting: every active block of level a activates its parent block and the
+// parent's neighbours on the sides the block touches (flags of level a-1).
+__global__ __launch_bounds__(kBlock) void k_amr_nest(int dim, int nbx, int nby, int nbz,
+                                                     const uint8_t *__restrict__ blk, int pnx,
+                                                     int pny, int pnz, uint8_t *pblk) {
+  const int b = blockIdx.x * kBlock + threadIdx.x;
+  if (b >= nbx * nby * nbz || !blk[b]) return;
+  const int bi[3] = {b % nbx, (b / nbx) % nby, b / (nbx * nby)};
+  const int pn[3] = {pnx, pny, pnz};
+  int pb[3], sg[3];
+  for (int a = 0; a < 3; ++a) {
+    pb[a] = bi[a] / 2;
+    sg[a] = a < dim ? ((bi[a] % 2) ? 1 : -1) : 0;
+  }
+  for (int o = 0; o < 8; ++o) {
+    int q[3];
+    bool ok = true;
+    for (int a = 0; a < 3; ++a) {
+      const int bit = (o >> a) & 1;
+      if (a >= dim && bit) ok = false;
+      q[a] = pb[a] + (bit ? sg[a] : 0);
+      if (a < dim && (q[a] < 0 || q[a] >= pn[a])) ok = false;
+    }
+    if (ok) pblk[q[0] + pnx * (q[1] + pny * q[2])] = 1;
+  }
+}
+
+// Node classes, pass 1: closure of the active region (clo) and classes 1/2.
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_amr_classify(Geom g, int bc, int nbx, int nby,
+                                                         const uint8_t *__restrict__ blk,
+                                                         uint8_t *__restrict__ clo,
+                                                         uint8_t *__restrict__ cls) {
+  const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (id >= g.nn) return;
+  int i, j, k;
+  node_ijk(g, id, i, j, k);
+  bool any = false, all = true;
+#pragma unroll
+  for (int o = 0; o < (1 << DIM); ++o) {
+    const int x = i - 1 + (o & 1), y = j - 1 + ((o >> 1) & 1);
+    const int z = DIM == 3 ? k - 1 + ((o >> 2) & 1) : 0;
+    if (x < 0 || x >= g.cx || y < 0 || y >= g.cy || z < 0 || z >= g.cz) continue;
+    const bool act = blk[x / bc + nbx * (y / bc + nby * (z / bc))] != 0;
+    any = any || act;
+    all = all && act;
+  }
+  clo[id] = any ? 1 : 0;
+  cls[id] = any ? (all ? 1 : 2) : 0;
+}
+
+// Node classes, pass 2: the first (3) and second (4) node layers around the
+// closure (Chebyshev distance 1 and 2).
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_amr_layers(Geom g, const uint8_t *__restrict__ clo,
+                                                       uint8_t *__restrict__ cls) {
+  const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (id >= g.nn || cls[id] != 0) return;
+  int i, j, k;
+  node_ijk(g, id, i, j, k);
+  int best = 3;
+  const int zr = DIM == 3 ? 2 : 0;
+  for (int dz = -zr; dz <= zr; ++dz)
+    for (int dy = -2; dy <= 2; ++dy)
+      for (int dx = -2; dx <= 2; ++dx) {
+        const int x = i + dx, y = j + dy, z = k + dz;
+        if (x < 0 || x >= g.nx || y < 0 || y >= g.ny || z < 0 || z >= g.nz) continue;
+        if (!clo[x + (int64_t)g.nx * (y + (int64_t)g.ny * z)]) continue;
+        const int d = max(max(abs(dx), abs(dy)), abs(dz));
+        best = min(best, d);
+      }
+  if (best <= 2) cls[id] = (uint8_t)(2 + best);
+}
+
+// psi of covered coarse cells: mean of the 2^d children (children summed in
+// x-fastest order), FP64 and its FP32 copy.
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_amr_avgdown(Geom gc, Geom gf, int bc, int nbx,
+                                                        int nby, const uint8_t *__restrict__ blkf,
+                                                        const double *__restrict__ psif,
+                                                        double *__restrict__ psic,
+                                                        float *__restrict__ psic32) {
+  const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (id >= gc.nc) return;
+  int I, J, K;
+  cell_ijk(gc, id, I, J, K);
+  const int x = 2 * I, y = 2 * J, z = DIM == 3 ? 2 * K : 0;
+  if (!blkf[x / bc + nbx * (y / bc + nby * (z / bc))]) return;
+  double s = 0.0;
+#pragma unroll
+  for (int o = 0; o < (1 << DIM); ++o) {
+    const int qx = x + (o & 1), qy = y + ((o >> 1) & 1), qz = DIM == 3 ? z + ((o >> 2) & 1) : 0;
+    s += psif[qx + (int64_t)gf.cx * (qy + (int64_t)gf.cy * qz)];
+  }
+  const double v = s / (double)(1 << DIM);
+  psic[id] = v;
+  psic32[id] = (float)v;
+}
+
+// ------------------------------------------------------------ cycle kernels
+
+// Quadratic interpolation along one axis for fine node index n: even n takes
+// coarse node n/2; odd n = 2I+1 takes {I-1, I, I+1} with (-1/8, 3/4, 3/8), or
+// {0, 1, 2} with (3/8, 3/4, -1/8) when I = 0.
+template <typename T>
+__device__ __forceinline__ int quad_axis(int n, int idx[3], T w[3]) {
+  if ((n & 1) == 0) {
+    idx[0] = n >> 1;
+    w[0] = T(1);
+    return 1;
+  }
+  const int I = (n - 1) >> 1;
+  if (I >= 1) {
+    idx[0] = I - 1; idx[1] = I; idx[2] = I + 1;
+    w[0] = T(-0.125); w[1] = T(0.75); w[2] = T(0.375);
+  } else {
+    idx[0] = I; idx[1] = I + 1; idx[2] = I + 2;
+    w[0] = T(0.375); w[1] = T(0.75); w[2] = T(-0.125);
+  }
+  return 3;
+}
+
+// Ghost nodes (classes 2-4) of the fine level from the coarse level; fixed
+// displacement DOF keep their values.  Weight products are exact dyadic
+// numbers; every term is rounded before it is added.
+template <typename T, int DIM>
+__global__ __launch_bounds__(kBlock) void k_amr_ghost(Geom gf, Geom gc,
+                                                      const uint8_t *__restrict__ cls,
+                                                      const T *__restrict__ xc,
+                                                      T *__restrict__ xf) {
+#pragma clang fp contract(off)
+  const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (id >= gf.nn || cls[id] < 2) return;
+  int i, j, k;
+  node_ijk(gf, id, i, j, k);
+  int ix[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  T w[3][3] = {{T(1), T(0), T(0)}, {T(1), T(0), T(0)}, {T(1), T(0), T(0)}};
+  int cnt[3] = {1, 1, 1};
+  cnt[0] = quad_axis<T>(i, ix[0], w[0]);
+  cnt[1] = quad_axis<T>(j, ix[1], w[1]);
+  if (DIM == 3) cnt[2] = quad_axis<T>(k, ix[2], w[2]);
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) {
+    if (is_dirichlet(gf, i, j, k, c)) continue;
+    T s = T(0);
+    for (int t2 = 0; t2 < cnt[2]; ++t2)
+      for (int t1 = 0; t1 < cnt[1]; ++t1)
+        for (int t0 = 0; t0 < cnt[0]; ++t0) {
+          const int64_t q = ix[0][t0] + (int64_t)gc.nx * (ix[1][t1] + (int64_t)gc.ny * ix[2][t2]);
+          s += w[0][t0] * w[1][t1] * w[2][t2] * xc[c * gc.nn + q];
+        }
+    xf[c * gf.nn + id] = s;
+  }
+}
+
+// Coarse nodes on or inside the fine region (fine class 1 or 2 at the
+// coinciding node), free DOF: out = R r_f (+ add) (+ add2), R the
+// full-weighting transpose of multilinear P over 2^d.  With ONLY_GHOSTS only
+// fine nodes of class 2 and 3 contribute.  Other nodes are left untouched.
+template <typename T, int DIM, bool ONLY_GHOSTS>
+__global__ __launch_bounds__(kBlock) void k_amr_restrict_cif(Geom gf, Geom gc,
+                                                             const uint8_t *__restrict__ clsf,
+                                                             const T *__restrict__ rf,
+                                                             const T *__restrict__ add,
+                                                             const T *__restrict__ add2,
+                                                             T *__restrict__ out) {
+  const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (id >= gc.nn) return;
+  int I, J, K;
+  node_ijk(gc, id, I, J, K);
+  const uint8_t fc = clsf[fine_of_coarse(gf, I, J, K)];
+  if (fc != 1 && fc != 2) return;
+  T acc[3] = {T(0), T(0), T(0)};
+  const int zlo = (DIM == 3) ? -1 : 0, zhi = (DIM == 3) ? 1 : 0;
+  for (int dz = zlo; dz <= zhi; ++dz) {
+    const int fk = 2 * K + dz;
+    if (fk < 0 || fk >= gf.nz) continue;
+    const T wz = dz == 0 ? T(1) : T(0.5);
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int fj = 2 * J + dy;
+      if (fj < 0 || fj >= gf.ny) continue;
+      const T wy = dy == 0 ? T(1) : T(0.5);
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int fi = 2 * I + dx;
+        if (fi < 0 || fi >= gf.nx) continue;
+        const T wgt = wz * wy * (dx == 0 ? T(1) : T(0.5));
+        const int64_t q = fi + (int64_t)gf.nx * (fj + (int64_t)gf.ny * fk);
+        if (ONLY_GHOSTS && clsf[q] != 2 && clsf[q] != 3) continue;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) acc[c] += wgt * rf[c * gf.nn + q];
+      }
+    }
+  }
+  const T scale = (DIM == 3) ? T(0.125) : T(0.25);
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) {
+    if (is_dirichlet(gc, I, J, K, c)) continue;
+    T v = acc[c] * scale;
+    if (add) v = v + add[c * gc.nn + id];
+    if (add2) v = v + add2[c * gc.nn + id];
+    out[c * gc.nn + id] = v;
+  }
+}
+
+// r32 = r / sqrt(*ss) in FP32, 0 on the padded ghost rows (classes 2 and 3)
+// of an adaptive level (every node when cls is NULL).
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_amr_cast(Geom g, const uint8_t *__restrict__ cls,
+                                                     const double *__restrict__ r,
+                                                     float *__restrict__ r32,
+                                                     const double *__restrict__ ss) {
+  const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (id >= g.nn) return;
+  const double sn = sqrt(*ss);
+  const bool ghost = cls && (cls[id] == 2 || cls[id] == 3);
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) {
+    const int64_t q = c * g.nn + id;
+    r32[q] = (ghost || !(sn > 0.0)) ? 0.0f : (float)(r[q] / sn);
+  }
+}
+
+// Coarse nodes strictly inside the fine region (fine class 1) take the fine
+// values at the coinciding node.
+template <typename T, int DIM>
+__global__ __launch_bounds__(kBlock) void k_amr_inject(Geom gf, Geom gc,
+                                                       const uint8_t *__restrict__ clsf,
+                                                       const T *__restrict__ xf,
+                                                       T *__restrict__ xc) {
+  const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (id >= gc.nn) return;
+  int I, J, K;
+  node_ijk(gc, id, I, J, K);
+  const int64_t fid = fine_of_coarse(gf, I, J, K);
+  if (clsf[fid] != 1) return;
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) xc[c * gc.nn + id] = xf[c * gf.nn + fid];
+}
+
+// x_f += P (x_c - xinj_c) on the unknowns (class 1, free DOF) of the fine level.
+template <typename T, int DIM>
+__global__ __launch_bounds__(kBlock) void k_amr_correct(Geom gf, Geom gc,
+                                                        const uint8_t *__restrict__ clsf,
+                                                        const T *__restrict__ xc,
+                                                        const T *__restrict__ xinj,
+                                                        T *__restrict__ xf) {
+  const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (id >= gf.nn || clsf[id] != 1) return;
+  int i, j, k;
+  node_ijk(gf, id, i, j, k);
+  const int lo[3] = {i >> 1, j >> 1, DIM == 3 ? k >> 1 : 0};
+  const int hi[3] = {(i + 1) >> 1, (j + 1) >> 1, DIM == 3 ? (k + 1) >> 1 : 0};
+  const T wx = lo[0] == hi[0] ? T(1) : T(0.5), wy = lo[1] == hi[1] ? T(1) : T(0.5);
+  const T wz = lo[2] == hi[2] ? T(1) : T(0.5);
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) {
+    if (is_dirichlet(gf, i, j, k, c)) continue;
+    T acc = T(0);
+    for (int I2 = lo[2]; I2 <= hi[2]; ++I2)
+      for (int I1 = lo[1]; I1 <= hi[1]; ++I1)
+        for (int I0 = lo[0]; I0 <= hi[0]; ++I0) {
+          const int64_t q = c * gc.nn + I0 + (int64_t)gc.nx * (I1 + (int64_t)gc.ny * I2);
+          acc += wx * wy * wz * (xc[q] - xinj[q]);
+        }
+    xf[c * gf.nn + id] += acc;
+  }
+}
+
+// u += s e on the free DOF of the level's unknowns (all nodes when cls is
+// NULL, class 1 otherwise); s = sqrt(*ss) when ss is given, else 1.
+template <typename T, int DIM>
+__global__ __launch_bounds__(kBlock) void k_amr_update(Geom g, const uint8_t *__restrict__ cls,
+                                                       double *__restrict__ u,
+                                                       const T *__restrict__ e,
+                                                       const double *__restrict__ ss) {
+  const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (id >= g.nn || (cls && cls[id] != 1)) return;
+  int i, j, k;
+  node_ijk(g, id, i, j, k);
+  const double s = ss ? sqrt(*ss) : 1.0;
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) {
+    if (is_dirichlet(g, i, j, k, c)) continue;
+    if (ss) u[c * g.nn + id] += s * (double)e[c * g.nn + id];
+    else u[c * g.nn + id] += (double)e[c * g.nn + id];
+  }
+}
+
+// Per-block partial sums over the composite unknowns of one level: free DOF
+// of class-1 nodes (every node when cls is NULL) not covered by the finer
+// level (fine class 1 at the coinciding node; no finer level when clsf is
+// NULL).  Sums r^2, or counts the DOF when r is NULL.
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_amr_sumsq(Geom g, const uint8_t *__restrict__ cls,
+                                                      Geom gf, const uint8_t *__restrict__ clsf,
+                                                      const double *__restrict__ r,
+                                                      double *__restrict__ partials) {
+  __shared__ double lds[kBlock / 64 + 1];
+  const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  double v = 0.0;
+  if (id < g.nn && (!cls || cls[id] == 1)) {
+    int i, j, k;
+    node_ijk(g, id, i, j, k);
+    if (!clsf || clsf[fine_of_coarse(gf, i, j, k)] != 1) {
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) {
+        if (is_dirichlet(g, i, j, k, c)) continue;
+        if (r) {
+          const double x = r[c * g.nn + id];
+          v += x * x;
+        } else {
+          v += 1.0;
+        }
+      }
+    }
+  }
+  const double s = block_sum(v, lds);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// ---------------------------------------------------------------- launchers
+
+hipError_t launch_tags(const Level &L, double thresh, const double *psi, uint8_t *tags,
+                       hipStream_t st) {
+  double hmax = 0.0;
+  for (int a = 0; a < L.g.dim; ++a) hmax = std::max(hmax, L.h[a]);
+  const double hmax2 = hmax * hmax, thr2 = thresh * thresh;
+  if (L.g.dim == 3)
+    AMR_LAUNCH((k_amr_tags<3>), num_blocks(L.g.nc), kBlock, st, L.g, L.h[0], L.h[1], L.h[2], hmax2,
+               thr2, psi, tags);
+  AMR_LAUNCH((k_amr_tags<2>), num_blocks(L.g.nc), kBlock, st, L.g, L.h[0], L.h[1], L.h[2], hmax2,
+             thr2, psi, tags);
+}
+
+template <typename T>
+hipError_t launch_ghost(const Level &F, const Level &C, const uint8_t *cls, const T *xc, T *xf,
+                        hipStream_t st) {
+  if (F.g.dim == 3) AMR_LAUNCH((k_amr_ghost<T, 3>), num_blocks(F.g.nn), kBlock, st, F.g, C.g, cls, xc, xf);
+  AMR_LAUNCH((k_amr_ghost<T, 2>), num_blocks(F.g.nn), kBlock, st, F.g, C.g, cls, xc, xf);
+}
+
+template <typename T>
+hipError_t launch_restrict_cif(const Level &F, const Level &C, const uint8_t *clsf, const T *rf,
+                               const T *add, const T *add2, T *out, hipStream_t st,
+                               bool only_ghosts = false) {
+  const int nb = num_blocks(C.g.nn);
+  if (only_ghosts) {
+    if (F.g.dim == 3)
+      AMR_LAUNCH((k_amr_restrict_cif<T, 3, true>), nb, kBlock, st, F.g, C.g, clsf, rf, add, add2, out);
+    AMR_LAUNCH((k_amr_restrict_cif<T, 2, true>), nb, kBlock, st, F.g, C.g, clsf, rf, add, add2, out);
+  }
+  if (F.g.dim == 3)
+    AMR_LAUNCH((k_amr_restrict_cif<T, 3, false>), nb, kBlock, st, F.g, C.g, clsf, rf, add, add2, out);
+  AMR_LAUNCH((k_amr_restrict_cif<T, 2, false>), nb, kBlock, st, F.g, C.g, clsf, rf, add, add2, out);
+}
+
+hipError_t launch_amr_cast(const Level &L, const uint8_t *cls, const double *r, float *r32,
+                           const double *ss, hipStream_t st) {
+  if (L.g.dim == 3) AMR_LAUNCH((k_amr_cast<3>), num_blocks(L.g.nn), kBlock, st, L.g, cls, r, r32, ss);
+  AMR_LAUNCH((k_amr_cast<2>), num_blocks(L.g.nn), kBlock, st, L.g, cls, r, r32, ss);
+}
+
+template <typename T>
+hipError_t launch_inject(const Level &F, const Level &C, const uint8_t *clsf, const T *xf, T *xc,
+                         hipStream_t st) {
+  if (F.g.dim == 3) AMR_LAUNCH((k_amr_inject<T, 3>), num_blocks(C.g.nn), kBlock, st, F.g, C.g, clsf, xf, xc);
+  AMR_LAUNCH((k_amr_inject<T, 2>), num_blocks(C.g.nn), kBlock, st, F.g, C.g, clsf, xf, xc);
+}
+
+template <typename T>
+hipError_t launch_amr_correct(const Level &F, const Level &C, const uint8_t *clsf, const T *xc,
+                              const T *xinj, T *xf, hipStream_t st) {
+  if (F.g.dim == 3)
+    AMR_LAUNCH((k_amr_correct<T, 3>), num_blocks(F.g.nn), kBlock, st, F.g, C.g, clsf, xc, xinj, xf);
+  AMR_LAUNCH((k_amr_correct<T, 2>), num_blocks(F.g.nn), kBlock, st, F.g, C.g, clsf, xc, xinj, xf);
+}
+
+template <typename T>
+hipError_t launch_update(const Level &L, const uint8_t *cls, double *u, const T *e,
+                         const double *ss, hipStream_t st) {
+  if (L.g.dim == 3) AMR_LAUNCH((k_amr_update<T, 3>), num_blocks(L.g.nn), kBlock, st, L.g, cls, u, e, ss);
+  AMR_LAUNCH((k_amr_update<T, 2>), num_blocks(L.g.nn), kBlock, st, L.g, cls, u, e, ss);
+}
+
+hipError_t launch_sumsq(const Level &L, const uint8_t *cls, const Level *F, const uint8_t *clsf,
+                        const double *r, double *partials, hipStream_t st) {
+  const Geom gf = F ? F->g : L.g;
+  if (L.g.dim == 3)
+    AMR_LAUNCH((k_amr_sumsq<3>), num_blocks(L.g.nn), kBlock, st, L.g, cls, gf, clsf, r, partials);
+  AMR_LAUNCH((k_amr_sumsq<2>), num_blocks(L.g.nn), kBlock, st, L.g, cls, gf, clsf, r, partials);
+}
+
+struct Carver {
+  char *base;
+  size_t off = 0;
+  template <typename T>
+  T *take(int64_t n) {
+    off = (off + 255) & ~(size_t)255;
+    T *p = base ? (T *)(base + off) : nullptr;
+    off += (size_t)std::max<int64_t>(n, 1) * sizeof(T);
+    return p;
+  }
+};
+
+}  // namespace
+
+// ------------------------------------------------------------------ context
+
+struct AmrLevel {
+  Level L;                 // geometry, coefficients, psi (FP64 / FP32)
+  int nb[3] = {1, 1, 1};   // blocks per axis (a >= 1)
+  uint8_t *blk = nullptr;  // block flags (a >= 1)
+  uint8_t *cls = nullptr;  // node classes (a >= 1)
+  uint8_t *clo = nullptr;  // closure scratch (a >= 1)
+  uint8_t *tags = nullptr; // cell tags (a < A)
+  double *fP = nullptr, *r = nullptr, *e = nullptr, *w = nullptr, *xinj = nullptr, *tmp = nullptr;
+  float *e32 = nullptr, *f32 = nullptr, *w32 = nullptr, *xinj32 = nullptr, *tmp32 = nullptr;
+  float *g32 = nullptr;    // FP32 cycle: R of the finer level's ghost-row loads (a < A)
+  int part_off = 0;        // offset of this level's partial sums
+  Traction tr{};
+  int64_t nblocks() const { return (int64_t)nb[0] * nb[1] * nb[2]; }
+  int64_t nv() const { return (int64_t)L.g.dim * L.g.nn; }
+};
+
+struct sbm_amr_ctx {
+  int dim = 0, A = 0, bc = 0;
+  sbm_grid base_grid{};
+  sbm_options opt{};
+  hipStream_t st = nullptr;
+  std::vector<AmrLevel> lv;
+  sbm_ctx *base = nullptr;
+  size_t base_bytes = 0;
+  double *partials = nullptr;
+  int npart = 0;
+  double *scal = nullptr;
+  int *iflag = nullptr;
+  double *host = nullptr;  // pinned host scalars
+  sbm_material mat{};
+  DispValues dv{};
+  double fnorm = 0.0;
+  int64_t comp_dof = 0;
+  bool have_problem = false;
+};
+
+static sbm_status amr_fail(sbm_status s, const std::string &m) { return set_error(s, m); }
+
+#define AMR_HIP(expr)                                                                       \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return amr_fail(SBM_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));         \
+  } while (0)
+
+#define AMR_TRY(expr)            \
+  do {                           \
+    sbm_status s_ = (expr);      \
+    if (s_ != SBM_OK) return s_; \
+  } while (0)
+
+// Shapes of the AMR levels; false when the layout is not supported.
+static bool amr_layout(const sbm_grid *g, int levels, int block, std::vector<AmrLevel> &lv,
+                       std::string &why) {
+  if (!g || (g->dim != 2 && g->dim != 3)) return why = "dim must be 2 or 3", false;
+  if (levels < 1 || levels > kMaxAmrLevels) return why = "levels must be 1..4", false;
+  if (block < 2 || block % 2) return why = "block must be even and >= 2", false;
+  for (int a = 0; a < g->dim; ++a) {
+    if (g->ncell[a] < 2 || !(g->h[a] > 0.0) || !isfinite(g->h[a]))
+      return why = "base grid needs ncell >= 2 and h > 0", false;
+    if (levels > 1 && (2 * g->ncell[a]) % block)
+      return why = "block must divide twice the base cell count", false;
+  }
+  lv.assign(levels, AmrLevel());
+  for (int a = 0; a < levels; ++a) {
+    int64_t nc[3] = {1, 1, 1};
+    double h[3] = {1.0, 1.0, 1.0};
+    for (int x = 0; x < g->dim; ++x) {
+      nc[x] = g->ncell[x] << a;
+      h[x] = g->h[x] / (double)(1 << a);
+    }
+    int64_t nodes = 1;
+    for (int x = 0; x < g->dim; ++x) nodes *= nc[x] + 1;
+    if (nodes * g->dim >= ((int64_t)1 << 31)) return why = "finest level exceeds 2^31 DOF", false;
+    make_level(g->dim, nc, h, lv[a].L);
+    if (a >= 1)
+      for (int x = 0; x < g->dim; ++x) lv[a].nb[x] = (int)(nc[x] / block);
+  }
+  return true;
+}
+
+static size_t amr_carve(sbm_amr_ctx *c, char *base) {
+  Carver cv{base};
+  const int A = c->A;
+  int npart = 0;
+  for (int a = 0; a <= A; ++a) {
+    AmrLevel &l = c->lv[a];
+    const int64_t nv = l.nv();
+    l.L.psi64 = cv.take<double>(l.L.g.nc);
+    l.L.psi32 = cv.take<float>(l.L.g.nc);
+    if (a >= 1) {
+      l.blk = cv.take<uint8_t>(l.nblocks());
+      l.cls = cv.take<uint8_t>(l.L.g.nn);
+      l.clo = cv.take<uint8_t>(l.L.g.nn);
+    }
+    if (a < A) l.tags = cv.take<uint8_t>(l.L.g.nc);
+    l.fP = cv.take<double>(nv);
+    l.r = cv.take<double>(nv);
+    l.e = cv.take<double>(nv);
+    l.w = cv.take<double>(nv);
+    l.tmp = cv.take<double>(nv);
+    l.e32 = cv.take<float>(nv);
+    l.f32 = cv.take<float>(nv);
+    l.w32 = cv.take<float>(nv);
+    l.tmp32 = cv.take<float>(nv);
+    if (a < A) {
+      l.xinj = cv.take<double>(nv);
+      l.xinj32 = cv.take<float>(nv);
+      l.g32 = cv.take<float>(nv);
+    }
+    l.part_off = npart;
+    npart += num_blocks(l.L.g.nn);
+  }
+  c->npart = npart;
+  c->partials = cv.take<double>(npart);
+  c->scal = cv.take<double>(16);
+  c->iflag = cv.take<int>(16);
+  cv.off = (cv.off + 255) & ~(size_t)255;
+  return cv.off;
+}
+
+static sbm_options base_options(const sbm_options &o) {
+  sbm_options b = o;
+  b.krylov = 0;
+  b.use_graphs = 0;
+  return b;
+}
+
+// ------------------------------------------------------------- cycle (host)
+
+template <typename T>
+struct AV;
+template <>
+struct AV<double> {
+  static double *x(AmrLevel &l) { return l.e; }
+  static double *f(AmrLevel &l) { return l.r; }
+  static double *w(AmrLevel &l) { return l.w; }
+  static double *xinj(AmrLevel &l) { return l.xinj; }
+  static double *tmp(AmrLevel &l) { return l.tmp; }
+  static const double *psi(const AmrLevel &l) { return l.L.psi64; }
+  static const Coef<double> &coef(const AmrLevel &l) { return l.L.c64; }
+};
+template <>
+struct AV<float> {
+  static float *x(AmrLevel &l) { return l.e32; }
+  static float *f(AmrLevel &l) { return l.f32; }
+  static float *w(AmrLevel &l) { return l.w32; }
+  static float *xinj(AmrLevel &l) { return l.xinj32; }
+  static float *tmp(AmrLevel &l) { return l.tmp32; }
+  static const float *psi(const AmrLevel &l) { return l.L.psi32; }
+  static const Coef<float> &coef(const AmrLevel &l) { return l.L.c32; }
+};
+
+static double amr_omega(const sbm_options &o) {
+  if (o.omega > 0.0) return o.omega;
+  return o.smoother == 1 ? 0.8 : 1.0;
+}
+
+// nu sweeps on the unknowns of level a >= 1 (class 1); other nodes keep x.
+template <typename T>
+static hipError_t amr_smooth(sbm_amr_ctx *c, int a, T *x, const T *f, T *tmp, int nu) {
+  AmrLevel &l = c->lv[a];
+  const double om = amr_omega(c->opt);
+  hipError_t e = hipSuccess;
+  if (c->opt.smoother == 1) {
+    T *src = x, *dst = tmp;
+    for (int s = 0; s < nu; ++s) {
+      if ((e = launch_jacobi<T>(l.L, AV<T>::psi(l), AV<T>::coef(l), src, f, dst, om, c->st,
+                                l.cls)) != hipSuccess)
+        return e;
+      std::swap(src, dst);
+    }
+    if (src != x) e = launch_copy<T>(src, x, l.nv(), c->st);
+    return e;
+  }
+  for (int s = 0; s < nu; ++s) {
+    if ((e = launch_rb_half<T>(l.L, AV<T>::psi(l), AV<T>::coef(l), x, f, tmp, om, 0, c->st,
+                               l.cls)) != hipSuccess)
+      return e;
+    if ((e = launch_rb_half<T>(l.L, AV<T>::psi(l), AV<T>::coef(l), tmp, f, x, om, 1, c->st,
+                               l.cls)) != hipSuccess)
+      return e;
+  }
+  return e;
+}
+
+// Full-approximation cycle over AMR levels a..1 on the level vectors of
+// precision T (x, f, w, xinj, tmp), ending in the base V-cycle.
+template <typename T>
+static hipError_t amr_fas(sbm_amr_ctx *c, int a) {
+  if (a == 0) {
+    AmrLevel &l0 = c->lv[0];
+    return base_vcycle(c->base, sizeof(T) == 8 ? 0 : 1, AV<T>::x(l0), AV<T>::f(l0));
+  }
+  AmrLevel &F = c->lv[a];
+  AmrLevel &C = c->lv[a - 1];
+  hipError_t e;
+  T *xf = AV<T>::x(F), *ff = AV<T>::f(F), *wf = AV<T>::w(F), *tf = AV<T>::tmp(F);
+  T *xc = AV<T>::x(C), *fc = AV<T>::f(C), *xi = AV<T>::xinj(C), *tc = AV<T>::tmp(C);
+  if ((e = launch_ghost<T>(F.L, C.L, F.cls, xc, xf, c->st)) != hipSuccess) return e;
+  if ((e = amr_smooth<T>(c, a, xf, ff, tf, c->opt.nu_pre)) != hipSuccess) return e;
+  if ((e = launch_ghost<T>(F.L, C.L, F.cls, xc, xf, c->st)) != hipSuccess) return e;
+  if ((e = launch_residual<T>(F.L, AV<T>::psi(F), AV<T>::coef(F), xf, ff, wf, nullptr, c->st,
+                              F.cls)) != hipSuccess)
+    return e;
+  if ((e = launch_inject<T>(F.L, C.L, F.cls, xf, xc, c->st)) != hipSuccess) return e;
+  if ((e = launch_copy<T>(xc, xi, C.nv(), c->st)) != hipSuccess) return e;
+  // coarse load on covered and interface nodes: R w + K_c x_c
+  if ((e = launch_apply<T>(C.L, AV<T>::psi(C), AV<T>::coef(C), xc, tc, c->st)) != hipSuccess)
+    return e;
+  const T *g = nullptr;
+  if constexpr (sizeof(T) == 4) g = C.g32;
+  if ((e = launch_restrict_cif<T>(F.L, C.L, F.cls, wf, tc, g, fc, c->st)) != hipSuccess) return e;
+  if ((e = amr_fas<T>(c, a - 1)) != hipSuccess) return e;
+  if ((e = launch_amr_correct<T>(F.L, C.L, F.cls, xc, xi, xf, c->st)) != hipSuccess) return e;
+  if ((e = launch_ghost<T>(F.L, C.L, F.cls, xc, xf, c->st)) != hipSuccess) return e;
+  return amr_smooth<T>(c, a, xf, ff, tf, c->opt.nu_post);
+}
+
+// Composite residual of x (ghosts refilled in place) for the loads f into r;
+// ||r||^2 over the composite unknowns lands in scal[0] and host[0].
+static sbm_status amr_comp_residual(sbm_amr_ctx *c, double *const *x, double *const *f,
+                                    double *const *r, bool sync) {
+  const int A = c->A;
+  for (int a = 1; a <= A; ++a)
+    AMR_HIP(launch_ghost<double>(c->lv[a].L, c->lv[a - 1].L, c->lv[a].cls, x[a - 1], x[a], c->st));
+  for (int a = A; a >= 0; --a) {
+    AmrLevel &l = c->lv[a];
+    AMR_HIP(launch_residual<double>(l.L, l.L.psi64, l.L.c64, x[a], f[a], r[a], nullptr, c->st,
+                                    a >= 1 ? l.cls : nullptr));
+    if (a < A)
+      AMR_HIP(launch_restrict_cif<double>(c->lv[a + 1].L, l.L, c->lv[a + 1].cls, r[a + 1], nullptr,
+                                          nullptr, r[a], c->st));
+  }
+  for (int a = 0; a <= A; ++a) {
+    AmrLevel &l = c->lv[a];
+    AMR_HIP(launch_sumsq(l.L, a >= 1 ? l.cls : nullptr, a < A ? &c->lv[a + 1].L : nullptr,
+                         a < A ? c->lv[a + 1].cls : nullptr, r[a], c->partials + l.part_off,
+                         c->st));
+  }
+  AMR_HIP(launch_finalize_sum(c->partials, c->npart, c->scal, c->st));
+  if (sync) {
+    AMR_HIP(hipMemcpyAsync(c->host, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->st));
+    AMR_HIP(hipStreamSynchronize(c->st));
+  }
+  return SBM_OK;
+}
+
+static sbm_status amr_inject_all(sbm_amr_ctx *c, double *const *u) {
+  for (int a = c->A; a >= 1; --a)
+    AMR_HIP(launch_inject<double>(c->lv[a].L, c->lv[a - 1].L, c->lv[a].cls, u[a], u[a - 1], c->st));
+  return SBM_OK;
+}
+
+// ---------------------------------------------------------------------- ABI
+
+extern "C" {
+
+size_t sbm_amr_workspace_bytes(const sbm_grid *base, int levels, int block,
+                               const sbm_options *opts) {
+  if (!opts) return 0;
+  sbm_amr_ctx c;
+  std::string why;
+  if (!amr_layout(base, levels, block, c.lv, why)) return 0;
+  c.dim = base->dim;
+  c.A = levels - 1;
+  const sbm_options bo = base_options(*opts);
+  const size_t bb = sbm_workspace_bytes(base, &bo);
+  if (bb == 0) return 0;
+  return amr_carve(&c, nullptr) + ((bb + 255) & ~(size_t)255);
+}
+
+sbm_status sbm_amr_create(const sbm_grid *base, int levels, int block, const sbm_options *opts,
+                          void *workspace, size_t workspace_bytes, void *hip_stream,
+                          sbm_amr_ctx **out) {
+  if (!out) return amr_fail(SBM_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (!opts) return amr_fail(SBM_E_ARG, "opts is NULL");
+  if (opts->krylov != 0)
+    return amr_fail(SBM_E_ARG, "the composite solve runs stationary cycles only (krylov = 0)");
+  if (!workspace || ((uintptr_t)workspace & 255))
+    return amr_fail(SBM_E_WORKSPACE, "workspace NULL or not 256-byte aligned");
+  sbm_amr_ctx *c = new sbm_amr_ctx();
+  std::string why;
+  if (!amr_layout(base, levels, block, c->lv, why)) {
+    delete c;
+    return amr_fail(SBM_E_SHAPE, "unsupported adaptive layout: " + why);
+  }
+  c->dim = base->dim;
+  c->A = levels - 1;
+  c->bc = block;
+  c->base_grid = *base;
+  c->opt = *opts;
+  c->st = (hipStream_t)hip_stream;
+  const size_t own = amr_carve(c, nullptr);
+  const sbm_options bo = base_options(*opts);
+  const size_t bb = sbm_workspace_bytes(base, &bo);
+  if (bb == 0) {
+    delete c;
+    return amr_fail(SBM_E_ARG, "invalid options or base grid");
+  }
+  const size_t need = own + ((bb + 255) & ~(size_t)255);
+  if (workspace_bytes < need) {
+    delete c;
+    return amr_fail(SBM_E_WORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+  }
+  amr_carve(c, (char *)workspace);
+  sbm_status s = sbm_create(base, &bo, (char *)workspace + own, workspace_bytes - own, hip_stream,
+                            &c->base);
+  if (s != SBM_OK) {
+    delete c;
+    return s;
+  }
+  hipError_t e = hipHostMalloc((void **)&c->host, 64 * sizeof(double), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    sbm_destroy(c->base);
+    delete c;
+    return amr_fail(SBM_E_HIP, std::string("hipHostMalloc: ") + hipGetErrorString(e));
+  }
+  *out = c;
+  return SBM_OK;
+}
+
+void sbm_amr_destroy(sbm_amr_ctx *c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->st);
+  if (c->base) sbm_destroy(c->base);
+  if (c->host) (void)hipHostFree(c->host);
+  delete c;
+}
+
+sbm_status sbm_amr_set_options(sbm_amr_ctx *c, const sbm_options *opts) {
+  if (!c || !opts) return amr_fail(SBM_E_ARG, "NULL argument");
+  if (opts->krylov != 0)
+    return amr_fail(SBM_E_ARG, "the composite solve runs stationary cycles only (krylov = 0)");
+  const sbm_options bo = base_options(*opts);
+  AMR_TRY(sbm_set_options(c->base, &bo));
+  c->opt = *opts;
+  return SBM_OK;
+}
+
+sbm_status sbm_amr_set_problem(sbm_amr_ctx *c, const double *const *psi_raw,
+                               const sbm_material *mat, const sbm_bc *bc, double tag_threshold,
+                               const uint8_t *const *blocks_host) {
+  if (!c || !psi_raw || !mat || !bc) return amr_fail(SBM_E_ARG, "NULL argument");
+  const int A = c->A, d = c->dim;
+  for (int a = 0; a <= A; ++a)
+    if (!psi_raw[a]) return amr_fail(SBM_E_ARG, "psi_raw of a level is NULL");
+  if (!isfinite(mat->lambda) || !isfinite(mat->mu) || !(mat->mu > 0.0) ||
+      !(mat->lambda + mat->mu > 0.0) || !(mat->psi_floor >= 0.0))
+    return amr_fail(SBM_E_ARG, "material needs mu > 0, lambda + mu > 0, psi_floor >= 0");
+  if (!blocks_host && !(tag_threshold >= 0.0 && isfinite(tag_threshold)))
+    return amr_fail(SBM_E_ARG, "tag_threshold must be finite and >= 0");
+  uint32_t dmask = 0;
+  memset(&c->dv, 0, sizeof(c->dv));
+  Traction tr{};
+  for (int F = 0; F < 2 * d; ++F)
+    for (int k = 0; k < d; ++k) {
+      if (bc->kind[F][k] != SBM_TRACTION && bc->kind[F][k] != SBM_DISPLACEMENT)
+        return amr_fail(SBM_E_ARG, "bc kind must be TRACTION or DISPLACEMENT");
+      if (!isfinite(bc->value[F][k])) return amr_fail(SBM_E_NONFINITE, "non-finite bc value");
+      if (bc->kind[F][k] == SBM_DISPLACEMENT) {
+        dmask |= 1u << (3 * F + k);
+        c->dv.v[F][k] = bc->value[F][k];
+      } else {
+        tr.t[F][k] = bc->value[F][k];
+      }
+    }
+  c->have_problem = false;
+  c->mat = *mat;
+  AMR_HIP(launch_fill<int>(c->iflag, 16, 0, c->st));
+  for (int a = 0; a <= A; ++a) {
+    AmrLevel &l = c->lv[a];
+    l.L.g.dmask = dmask;
+    set_coefs(l.L, mat->lambda, mat->mu, d);
+    l.tr = tr;
+    for (int F = 0; F < 6; ++F) l.tr.inv_h[F] = F / 2 < d ? 1.0 / l.L.h[F / 2] : 0.0;
+    AMR_HIP(launch_floor_psi(psi_raw[a], mat->psi_floor, l.L.psi64, l.L.psi32, l.L.g.nc, 0,
+                             c->iflag, c->st));
+  }
+  // block flags: tags of levels 0..A-1 (floored psi), footprints, nesting
+  if (blocks_host) {
+    for (int a = 1; a <= A; ++a) {
+      if (!blocks_host[a - 1]) return amr_fail(SBM_E_ARG, "block flags of a level are NULL");
+      AMR_HIP(hipMemcpyAsync(c->lv[a].blk, blocks_host[a - 1], c->lv[a].nblocks(),
+                             hipMemcpyHostToDevice, c->st));
+    }
+  } else {
+    for (int a = 0; a < A; ++a)
+      AMR_HIP(launch_tags(c->lv[a].L, tag_threshold, c->lv[a].L.psi64, c->lv[a].tags, c->st));
+    for (int a = 1; a <= A; ++a) {
+      AmrLevel &l = c->lv[a];
+      (void)hipGetLastError();
+      hipLaunchKernelGGL(k_amr_blocks, dim3((unsigned)l.nblocks()), dim3(kBlock), 0, c->st,
+                         c->lv[a - 1].L.g, d, l.nb[0], l.nb[1], c->bc / 2, c->lv[a - 1].tags,
+                         l.blk);
+      AMR_HIP(hipGetLastError());
+    }
+    for (int a = A; a >= 2; --a) {
+      AmrLevel &l = c->lv[a], &p = c->lv[a - 1];
+      (void)hipGetLastError();
+      hipLaunchKernelGGL(k_amr_nest, dim3(num_blocks(l.nblocks())), dim3(kBlock), 0, c->st, d,
+                         l.nb[0], l.nb[1], l.nb[2], l.blk, p.nb[0], p.nb[1], p.nb[2], p.blk);
+      AMR_HIP(hipGetLastError());
+    }
+  }
+  // node classes
+  for (int a = 1; a <= A; ++a) {
+    AmrLevel &l = c->lv[a];
+    const int nb = num_blocks(l.L.g.nn);
+    (void)hipGetLastError();
+    if (d == 3) {
+      hipLaunchKernelGGL(k_amr_classify<3>, dim3(nb), dim3(kBlock), 0, c->st, l.L.g, c->bc,
+                         l.nb[0], l.nb[1], l.blk, l.clo, l.cls);
+      hipLaunchKernelGGL(k_amr_layers<3>, dim3(nb), dim3(kBlock), 0, c->st, l.L.g, l.clo, l.cls);
+    } else {
+      hipLaunchKernelGGL(k_amr_classify<2>, dim3(nb), dim3(kBlock), 0, c->st, l.L.g, c->bc,
+                         l.nb[0], l.nb[1], l.blk, l.clo, l.cls);
+      hipLaunchKernelGGL(k_amr_layers<2>, dim3(nb), dim3(kBlock), 0, c->st, l.L.g, l.clo, l.cls);
+    }
+    AMR_HIP(hipGetLastError());
+  }
+  // psi of covered coarse cells, finest first
+  for (int a = A; a >= 1; --a) {
+    AmrLevel &f = c->lv[a], &p = c->lv[a - 1];
+    (void)hipGetLastError();
+    if (d == 3)
+      hipLaunchKernelGGL(k_amr_avgdown<3>, dim3(num_blocks(p.L.g.nc)), dim3(kBlock), 0, c->st,
+                         p.L.g, f.L.g, c->bc, f.nb[0], f.nb[1], f.blk, f.L.psi64, p.L.psi64,
+                         p.L.psi32);
+    else
+      hipLaunchKernelGGL(k_amr_avgdown<2>, dim3(num_blocks(p.L.g.nc)), dim3(kBlock), 0, c->st,
+                         p.L.g, f.L.g, c->bc, f.nb[0], f.nb[1], f.blk, f.L.psi64, p.L.psi64,
+                         p.L.psi32);
+    AMR_HIP(hipGetLastError());
+  }
+  // loads per level and diagonal checks
+  for (int a = 0; a <= A; ++a) {
+    AmrLevel &l = c->lv[a];
+    AMR_HIP(launch_rhs(l.L, l.tr, nullptr, l.fP, c->iflag, c->st));
+    AMR_HIP(launch_check_diag(l.L, c->iflag, c->st));
+  }
+  AMR_HIP(hipMemcpyAsync(c->host, c->iflag, sizeof(int), hipMemcpyDeviceToHost, c->st));
+  AMR_HIP(hipStreamSynchronize(c->st));
+  int flags = 0;
+  memcpy(&flags, c->host, sizeof(int));
+  if (flags & 1) return amr_fail(SBM_E_NONFINITE, "NaN/Inf in psi");
+  if (flags & 2) return amr_fail(SBM_E_DIAG, "a free DOF has no solid cell around it");
+  // uniform hierarchy of the base level on the averaged-down psi
+  AMR_TRY(sbm_set_problem(c->base, c->lv[0].L.psi64, mat, bc, nullptr));
+  // ||lifted load||: composite residual of the prescribed values
+  double *x[kMaxAmrLevels], *f[kMaxAmrLevels], *r[kMaxAmrLevels];
+  for (int a = 0; a <= A; ++a) {
+    AmrLevel &l = c->lv[a];
+    AMR_HIP(launch_fill<double>(l.e, l.nv(), 0.0, c->st));
+    AMR_HIP(launch_set_dirichlet(l.L, l.e, c->dv, c->st));
+    x[a] = l.e;
+    f[a] = l.fP;
+    r[a] = l.r;
+  }
+  AMR_TRY(amr_comp_residual(c, x, f, r, true));
+  if (!isfinite(c->host[0])) return amr_fail(SBM_E_NONFINITE, "non-finite load");
+  c->fnorm = sqrt(c->host[0]);
+  // composite DOF count
+  for (int a = 0; a <= A; ++a) {
+    AmrLevel &l = c->lv[a];
+    AMR_HIP(launch_sumsq(l.L, a >= 1 ? l.cls : nullptr, a < A ? &c->lv[a + 1].L : nullptr,
+                         a < A ? c->lv[a + 1].cls : nullptr, nullptr, c->partials + l.part_off,
+                         c->st));
+  }
+  AMR_HIP(launch_finalize_sum(c->partials, c->npart, c->scal, c->st));
+  AMR_HIP(hipMemcpyAsync(c->host, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->st));
+  AMR_HIP(hipStreamSynchronize(c->st));
+  c->comp_dof = (int64_t)llround(c->host[0]);
+  c->have_problem = true;
+  return SBM_OK;
+}
+
+#define AMR_NEED(c)                                                              \
+  do {                                                                           \
+    if (!(c)) return amr_fail(SBM_E_ARG, "ctx is NULL");                          \
+    if (!(c)->have_problem) return amr_fail(SBM_E_ARG, "sbm_amr_set_problem first"); \
+  } while (0)
+
+sbm_status sbm_amr_level_info(sbm_amr_ctx *c, int level, int64_t *ncell_host,
+                              int64_t *nblocks_host, uint8_t *blocks_host, uint8_t *classes,
+                              double *psi) {
+  AMR_NEED(c);
+  if (level < 0 || level > c->A) return amr_fail(SBM_E_ARG, "level out of range");
+  AmrLevel &l = c->lv[level];
+  if (ncell_host) {
+    ncell_host[0] = l.L.g.cx;
+    ncell_host[1] = l.L.g.cy;
+    ncell_host[2] = c->dim > 2 ? l.L.g.cz : 0;
+  }
+  if (nblocks_host)
+    for (int x = 0; x < 3; ++x) nblocks_host[x] = level >= 1 && x < c->dim ? l.nb[x] : 0;
+  if (blocks_host && level >= 1)
+    AMR_HIP(hipMemcpyAsync(blocks_host, l.blk, l.nblocks(), hipMemcpyDeviceToHost, c->st));
+  if (classes && level >= 1)
+    AMR_HIP(hipMemcpyAsync(classes, l.cls, l.L.g.nn, hipMemcpyDeviceToDevice, c->st));
+  if (psi) AMR_HIP(hipMemcpyAsync(psi, l.L.psi64, sizeof(double) * l.L.g.nc,
+                                  hipMemcpyDeviceToDevice, c->st));
+  AMR_HIP(hipStreamSynchronize(c->st));
+  return SBM_OK;
+}
+
+sbm_status sbm_amr_stats(sbm_amr_ctx *c, int64_t *composite_dof_host, double *fnorm_host) {
+  AMR_NEED(c);
+  if (composite_dof_host) *composite_dof_host = c->comp_dof;
+  if (fnorm_host) *fnorm_host = c->fnorm;
+  return SBM_OK;
+}
+
+sbm_status sbm_amr_ghost_fill(sbm_amr_ctx *c, int level, const double *xc, double *xf) {
+  AMR_NEED(c);
+  if (level < 1 || level > c->A) return amr_fail(SBM_E_ARG, "level must be 1..levels-1");
+  if (!xc || !xf) return amr_fail(SBM_E_ARG, "NULL argument");
+  AMR_HIP(launch_ghost<double>(c->lv[level].L, c->lv[level - 1].L, c->lv[level].cls, xc, xf,
+                               c->st));
+  return SBM_OK;
+}
+
+sbm_status sbm_amr_residual(sbm_amr_ctx *c, double *const *u, double *const *r,
+                            double *norm_host) {
+  AMR_NEED(c);
+  if (!u) return amr_fail(SBM_E_ARG, "u is NULL");
+  double *f[kMaxAmrLevels], *rr[kMaxAmrLevels];
+  for (int a = 0; a <= c->A; ++a) {
+    if (!u[a]) return amr_fail(SBM_E_ARG, "u of a level is NULL");
+    f[a] = c->lv[a].fP;
+    rr[a] = (r && r[a]) ? r[a] : c->lv[a].r;
+  }
+  AMR_TRY(amr_comp_residual(c, u, f, rr, true));
+  if (norm_host) *norm_host = sqrt(c->host[0]);
+  return SBM_OK;
+}
+
+sbm_status sbm_amr_solve(sbm_amr_ctx *c, double *const *u, double *hist_host, int hist_cap,
+                         int *n_cycles_host, double *final_rel_host) {
+  AMR_NEED(c);
+  if (!u) return amr_fail(SBM_E_ARG, "u is NULL");
+  const int A = c->A;
+  double *f[kMaxAmrLevels], *r[kMaxAmrLevels];
+  for (int a = 0; a <= A; ++a) {
+    if (!u[a]) return amr_fail(SBM_E_ARG, "u of a level is NULL");
+    AMR_HIP(launch_set_dirichlet(c->lv[a].L, u[a], c->dv, c->st));
+    f[a] = c->lv[a].fP;
+    r[a] = c->lv[a].r;
+  }
+  AMR_TRY(amr_inject_all(c, u));
+  double rho = 0.0, rho_min = INFINITY;
+  sbm_status status = SBM_NOT_CONVERGED;
+  int m = 0;
+  for (m = 0;; ++m) {
+    AMR_TRY(amr_comp_residual(c, u, f, r, true));
+    const double ss = c->host[0];
+    rho = c->fnorm > 0.0 ? sqrt(ss) / c->fnorm : (ss > 0.0 ? INFINITY : 0.0);
+    if (hist_host && m < hist_cap) hist_host[m] = rho;
+    if (!isfinite(rho)) {
+      status = amr_fail(SBM_E_NONFINITE, "non-finite residual at cycle " + std::to_string(m));
+      break;
+    }
+    if (rho <= c->opt.rtol) {
+      status = SBM_OK;
+      break;
+    }
+    if (rho > 1e3 * rho_min) {
+      status = amr_fail(SBM_E_DIVERGED, "residual grew above 1e3 x its minimum at cycle " +
+                                            std::to_string(m));
+      break;
+    }
+    rho_min = std::min(rho_min, rho);
+    if (m >= c->opt.max_cycles) {
+      set_error(SBM_NOT_CONVERGED, "max_cycles reached");
+      status = SBM_NOT_CONVERGED;
+      break;
+    }
+    if (c->opt.precision == 1) {
+      // The padded residual rows of the ghost nodes (classes 2 and 3) stay
+      // O(1) while the composite residual converges; they reach the cycle
+      // only through R at the coarse covered/interface nodes, where they
+      // largely cancel.  That restriction is taken here in FP64 (g) and the
+      // FP32 loads carry zeros on those rows, so no FP32 sum cancels.
+      for (int a = 0; a <= A; ++a) {
+        AmrLevel &l = c->lv[a];
+        AMR_HIP(launch_amr_cast(l.L, a >= 1 ? l.cls : nullptr, l.r, l.f32, c->scal, c->st));
+        AMR_HIP(launch_fill<float>(l.e32, l.nv(), 0.0f, c->st));
+        if (a < A) {
+          AMR_HIP(launch_fill<double>(l.w, l.nv(), 0.0, c->st));
+          AMR_HIP(launch_restrict_cif<double>(c->lv[a + 1].L, l.L, c->lv[a + 1].cls,
+                                              c->lv[a + 1].r, nullptr, nullptr, l.w, c->st, true));
+          AMR_HIP(launch_cast_scaled(l.w, l.g32, l.nv(), c->scal, c->st));
+        }
+      }
+      AMR_HIP(amr_fas<float>(c, A));
+      for (int a = 0; a <= A; ++a)
+        AMR_HIP(launch_update<float>(c->lv[a].L, a >= 1 ? c->lv[a].cls : nullptr, u[a],
+                                     c->lv[a].e32, c->scal, c->st));
+    } else {
+      for (int a = 0; a <= A; ++a) AMR_HIP(launch_fill<double>(c->lv[a].e, c->lv[a].nv(), 0.0, c->st));
+      AMR_HIP(amr_fas<double>(c, A));
+      for (int a = 0; a <= A; ++a)
+        AMR_HIP(launch_update<double>(c->lv[a].L, a >= 1 ? c->lv[a].cls : nullptr, u[a],
+                                      c->lv[a].e, nullptr, c->st));
+    }
+    AMR_TRY(amr_inject_all(c, u));
+  }
+  for (int a = 1; a <= A; ++a)
+    AMR_HIP(launch_ghost<double>(c->lv[a].L, c->lv[a - 1].L, c->lv[a].cls, u[a - 1], u[a], c->st));
+  AMR_HIP(hipStreamSynchronize(c->st));
+  if (n_cycles_host) *n_cycles_host = m;
+  if (final_rel_host) *final_rel_host = rho;
+  return status;
+}
+
+}  // extern "C"

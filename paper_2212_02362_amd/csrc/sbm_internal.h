@@ -5,8 +5,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
 #include <vector>
 
+#include "../../include/sbm.h"
 #include "sbm_device.h"
 
 namespace sbm {
@@ -44,15 +46,17 @@ hipError_t launch_apply(const Level &L, const T *psi, const Coef<T> &C, const T 
                         hipStream_t st);
 template <typename T>
 hipError_t launch_residual(const Level &L, const T *psi, const Coef<T> &C, const T *u,
-                           const T *f, T *r, double *partials, hipStream_t st);
+                           const T *f, T *r, double *partials, hipStream_t st,
+                           const uint8_t *cls = nullptr);
 hipError_t launch_residual_cast(const Level &L, const double *u, const double *f, float *r32,
                                 const double *ss, hipStream_t st);
 template <typename T>
 hipError_t launch_jacobi(const Level &L, const T *psi, const Coef<T> &C, const T *u, const T *f,
-                         T *u_out, double omega, hipStream_t st);
+                         T *u_out, double omega, hipStream_t st, const uint8_t *cls = nullptr);
 template <typename T>
 hipError_t launch_rb_half(const Level &L, const T *psi, const Coef<T> &C, const T *u,
-                          const T *f, T *u_out, double omega, int colour, hipStream_t st);
+                          const T *f, T *u_out, double omega, int colour, hipStream_t st,
+                          const uint8_t *cls = nullptr);
 template <typename T>
 hipError_t launch_restrict(const Level &F, const Level &Cl, const T *r, T *fc, hipStream_t st);
 template <typename T>
@@ -97,5 +101,16 @@ hipError_t launch_sensitivity(const Level &L, double lam, double mu, const Tract
                               const double *u, const double *adj, double lam_scale,
                               const double *design, int chain, double psi_floor, double *g,
                               hipStream_t st);
+
+// ------------------------------------------------- shared host helpers
+// Records msg as the thread's last error and returns s.
+sbm_status set_error(sbm_status s, const std::string &msg);
+// Geometry of a grid with ncell cells of spacing h (entries >= dim ignored).
+void make_level(int dim, const int64_t *ncell, const double *h, Level &L);
+// Operator coefficients of level L for the Lame constants (FP64 and FP32).
+void set_coefs(Level &L, double lam, double mu, int dim);
+// One V-cycle of the uniform hierarchy of c from its finest level: x (in/out)
+// and f are finest-level vectors in FP64 (precision 0) or FP32 (precision 1).
+hipError_t base_vcycle(sbm_ctx *c, int precision, void *x, const void *f);
 
 }  // namespace sbm

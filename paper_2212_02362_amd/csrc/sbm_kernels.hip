@@ -26,15 +26,20 @@ __global__ __launch_bounds__(kBlock) void k_apply(Geom g, Coef<T> C, const T *__
 }
 
 // r = f - K u on free DOF (0 on displacement DOF); optional per-block sums of r^2.
+// With a class array (adaptive levels) only classes 1-3 (interior, interface,
+// first outer layer: the padded region) carry a residual; elsewhere r = 0.
 template <typename T, int DIM>
 __global__ __launch_bounds__(kBlock) void k_residual(Geom g, Coef<T> C, const T *__restrict__ psi,
                                                      const T *__restrict__ u,
                                                      const T *__restrict__ f, T *__restrict__ r,
-                                                     double *__restrict__ partials) {
+                                                     double *__restrict__ partials,
+                                                     const uint8_t *__restrict__ cls) {
   __shared__ double lds[kBlock / 64 + 1];
   const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   double ss = 0.0;
-  if (id < g.nn) {
+  if (id < g.nn && cls && (cls[id] == 0 || cls[id] > 3)) {
+    for (int c = 0; c < DIM; ++c) r[c * g.nn + id] = T(0);
+  } else if (id < g.nn) {
     int i, j, k;
     node_ijk(g, id, i, j, k);
     T out[3], dg[3];
@@ -82,13 +87,20 @@ __global__ __launch_bounds__(kBlock) void k_residual_cast(Geom g, Coef<double> C
 // ------------------------------------------------------------- smoothers --
 
 // Damped Jacobi (Sec. 2.3): u_out = u + omega D^-1 (f - K u) on free DOF.
+// With a class array only class-1 nodes (the unknowns of an adaptive level)
+// are relaxed; every other node is copied.
 template <typename T, int DIM>
 __global__ __launch_bounds__(kBlock) void k_jacobi(Geom g, Coef<T> C, const T *__restrict__ psi,
                                                    const T *__restrict__ u,
                                                    const T *__restrict__ f,
-                                                   T *__restrict__ u_out, T omega) {
+                                                   T *__restrict__ u_out, T omega,
+                                                   const uint8_t *__restrict__ cls) {
   const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (id >= g.nn) return;
+  if (cls && cls[id] != 1) {
+    for (int c = 0; c < DIM; ++c) u_out[c * g.nn + id] = u[c * g.nn + id];
+    return;
+  }
   int i, j, k;
   node_ijk(g, id, i, j, k);
   T out[3], dg[3];
@@ -105,11 +117,13 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(Geom g, Coef<T> C, const T *_
 // ((x+y+z) mod 2) is relaxed from the state at the start of the half-sweep,
 // all components together; nodes of the other colour are copied.  One thread
 // owns the x-pair (2p, 2p+1) of a row: one node of each colour.
+// With a class array only class-1 nodes are relaxed (adaptive levels).
 template <typename T, int DIM>
 __global__ __launch_bounds__(kBlock) void k_rb_half(Geom g, Coef<T> C, const T *__restrict__ psi,
                                                     const T *__restrict__ u,
                                                     const T *__restrict__ f,
-                                                    T *__restrict__ u_out, T omega, int colour) {
+                                                    T *__restrict__ u_out, T omega, int colour,
+                                                    const uint8_t *__restrict__ cls) {
   const int npx = (g.nx + 1) >> 1;
   const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int64_t total = (int64_t)npx * g.ny * g.nz;
@@ -125,7 +139,10 @@ __global__ __launch_bounds__(kBlock) void k_rb_half(Geom g, Coef<T> C, const T *
 #pragma unroll
     for (int c = 0; c < DIM; ++c) u_out[c * g.nn + row + ic] = u[c * g.nn + row + ic];
   }
-  if (iu < g.nx) {
+  if (iu < g.nx && cls && cls[row + iu] != 1) {
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) u_out[c * g.nn + row + iu] = u[c * g.nn + row + iu];
+  } else if (iu < g.nx) {
     T out[3], dg[3];
     node_stencil<T, DIM>(g, C, psi, u, iu, j, k, out, dg);
 #pragma unroll
@@ -1139,10 +1156,13 @@ hipError_t launch_apply(const Level &L, const T *psi, const Coef<T> &C, const T 
 
 template <typename T>
 hipError_t launch_residual(const Level &L, const T *psi, const Coef<T> &C, const T *u,
-                           const T *f, T *r, double *partials, hipStream_t st) {
+                           const T *f, T *r, double *partials, hipStream_t st,
+                           const uint8_t *cls) {
   if (L.g.dim == 3)
-    SBM_LAUNCH((k_residual<T, 3>), num_blocks(L.g.nn), kBlock, st, L.g, C, psi, u, f, r, partials);
-  SBM_LAUNCH((k_residual<T, 2>), num_blocks(L.g.nn), kBlock, st, L.g, C, psi, u, f, r, partials);
+    SBM_LAUNCH((k_residual<T, 3>), num_blocks(L.g.nn), kBlock, st, L.g, C, psi, u, f, r, partials,
+               cls);
+  SBM_LAUNCH((k_residual<T, 2>), num_blocks(L.g.nn), kBlock, st, L.g, C, psi, u, f, r, partials,
+             cls);
 }
 
 hipError_t launch_residual_cast(const Level &L, const double *u, const double *f, float *r32,
@@ -1156,22 +1176,24 @@ hipError_t launch_residual_cast(const Level &L, const double *u, const double *f
 
 template <typename T>
 hipError_t launch_jacobi(const Level &L, const T *psi, const Coef<T> &C, const T *u, const T *f,
-                         T *u_out, double omega, hipStream_t st) {
+                         T *u_out, double omega, hipStream_t st, const uint8_t *cls) {
   if (L.g.dim == 3)
     SBM_LAUNCH((k_jacobi<T, 3>), num_blocks(L.g.nn), kBlock, st, L.g, C, psi, u, f, u_out,
-               (T)omega);
-  SBM_LAUNCH((k_jacobi<T, 2>), num_blocks(L.g.nn), kBlock, st, L.g, C, psi, u, f, u_out, (T)omega);
+               (T)omega, cls);
+  SBM_LAUNCH((k_jacobi<T, 2>), num_blocks(L.g.nn), kBlock, st, L.g, C, psi, u, f, u_out, (T)omega,
+             cls);
 }
 
 template <typename T>
 hipError_t launch_rb_half(const Level &L, const T *psi, const Coef<T> &C, const T *u,
-                          const T *f, T *u_out, double omega, int colour, hipStream_t st) {
+                          const T *f, T *u_out, double omega, int colour, hipStream_t st,
+                          const uint8_t *cls) {
   const int64_t pairs = (int64_t)((L.g.nx + 1) / 2) * L.g.ny * L.g.nz;
   if (L.g.dim == 3)
     SBM_LAUNCH((k_rb_half<T, 3>), num_blocks(pairs), kBlock, st, L.g, C, psi, u, f, u_out,
-               (T)omega, colour);
+               (T)omega, colour, cls);
   SBM_LAUNCH((k_rb_half<T, 2>), num_blocks(pairs), kBlock, st, L.g, C, psi, u, f, u_out, (T)omega,
-             colour);
+             colour, cls);
 }
 
 template <typename T>
@@ -1361,11 +1383,13 @@ hipError_t launch_sensitivity(const Level &L, double lam, double mu, const Tract
   template hipError_t launch_apply<T>(const Level &, const T *, const Coef<T> &, const T *, T *, \
                                       hipStream_t);                                            \
   template hipError_t launch_residual<T>(const Level &, const T *, const Coef<T> &, const T *,  \
-                                         const T *, T *, double *, hipStream_t);               \
+                                         const T *, T *, double *, hipStream_t,                \
+                                         const uint8_t *);                                     \
   template hipError_t launch_jacobi<T>(const Level &, const T *, const Coef<T> &, const T *,    \
-                                       const T *, T *, double, hipStream_t);                   \
+                                       const T *, T *, double, hipStream_t, const uint8_t *);  \
   template hipError_t launch_rb_half<T>(const Level &, const T *, const Coef<T> &, const T *,   \
-                                        const T *, T *, double, int, hipStream_t);             \
+                                        const T *, T *, double, int, hipStream_t,              \
+                                        const uint8_t *);                                      \
   template hipError_t launch_restrict<T>(const Level &, const Level &, const T *, T *,          \
                                          hipStream_t);                                         \
   template hipError_t launch_prolong_add<T>(const Level &, const Level &, const T *, T *,       \

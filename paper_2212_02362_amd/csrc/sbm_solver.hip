@@ -27,6 +27,8 @@ static sbm_status fail(sbm_status s, const std::string &msg) {
   return s;
 }
 
+sbm_status sbm::set_error(sbm_status s, const std::string &msg) { return fail(s, msg); }
+
 #define HIP_TRY(expr)                                                                      \
   do {                                                                                     \
     hipError_t e_ = (expr);                                                                \
@@ -172,36 +174,45 @@ static int count_levels(const sbm_grid *g) {
   return n;
 }
 
+void sbm::make_level(int dim, const int64_t *ncell, const double *h, Level &lv) {
+  Geom &G = lv.g;
+  G.dim = dim;
+  int64_t c[3];
+  for (int a = 0; a < 3; ++a) {
+    if (a < dim) {
+      c[a] = ncell[a];
+      lv.h[a] = h[a];
+    } else {
+      c[a] = 1;
+      lv.h[a] = 1.0;
+    }
+  }
+  G.cx = (int)c[0];
+  G.cy = (int)c[1];
+  G.cz = (int)c[2];
+  G.nx = G.cx + 1;
+  G.ny = G.cy + 1;
+  G.nz = dim > 2 ? G.cz + 1 : 1;
+  G.nn = (int64_t)G.nx * G.ny * G.nz;
+  G.nc = (int64_t)G.cx * G.cy * G.cz;
+  G.dmask = 0;
+  G.fnx = make_fastdiv((uint32_t)G.nx);
+  G.fny = make_fastdiv((uint32_t)G.ny);
+  G.fcx = make_fastdiv((uint32_t)G.cx);
+  G.fcy = make_fastdiv((uint32_t)G.cy);
+  G.fpx = make_fastdiv((uint32_t)((G.nx + 1) / 2));
+}
+
 static void level_shapes(const sbm_grid *g, int nlev, std::vector<Level> &L) {
   L.assign(nlev, Level());
   for (int l = 0; l < nlev; ++l) {
-    Level &lv = L[l];
-    Geom &G = lv.g;
-    G.dim = g->dim;
-    int64_t c[3];
-    for (int a = 0; a < 3; ++a) {
-      if (a < g->dim) {
-        c[a] = g->ncell[a] >> l;
-        lv.h[a] = g->h[a] * (double)(1 << l);
-      } else {
-        c[a] = 1;
-        lv.h[a] = 1.0;
-      }
+    int64_t c[3] = {1, 1, 1};
+    double h[3] = {1.0, 1.0, 1.0};
+    for (int a = 0; a < g->dim; ++a) {
+      c[a] = g->ncell[a] >> l;
+      h[a] = g->h[a] * (double)(1 << l);
     }
-    G.cx = (int)c[0];
-    G.cy = (int)c[1];
-    G.cz = (int)c[2];
-    G.nx = G.cx + 1;
-    G.ny = G.cy + 1;
-    G.nz = g->dim > 2 ? G.cz + 1 : 1;
-    G.nn = (int64_t)G.nx * G.ny * G.nz;
-    G.nc = (int64_t)G.cx * G.cy * G.cz;
-    G.dmask = 0;
-    G.fnx = make_fastdiv((uint32_t)G.nx);
-    G.fny = make_fastdiv((uint32_t)G.ny);
-    G.fcx = make_fastdiv((uint32_t)G.cx);
-    G.fcy = make_fastdiv((uint32_t)G.cy);
-    G.fpx = make_fastdiv((uint32_t)((G.nx + 1) / 2));
+    make_level(g->dim, c, h, L[l]);
   }
 }
 
@@ -261,7 +272,7 @@ static size_t carve(sbm_ctx *c, char *base) {
   return cv.off + 256;
 }
 
-static void set_coefs(Level &L, double lam, double mu, int dim) {
+void sbm::set_coefs(Level &L, double lam, double mu, int dim) {
   const double dfac = 1.0 / (double)(1 << (dim - 1));
   const double pfac = dim == 3 ? 0.5 : 1.0;
   for (int i = 0; i < 3; ++i)
@@ -392,6 +403,12 @@ static hipError_t vcycle(sbm_ctx *c, int l, T *x, const T *f, T *tmp) {
   // as a CG preconditioner the cycle is made symmetric: post-smoothing runs
   // the colours in reverse order
   return smooth<T>(c, l, x, f, tmp, c->opt.nu_post, c->opt.krylov == 1);
+}
+
+hipError_t sbm::base_vcycle(sbm_ctx *c, int precision, void *x, const void *f) {
+  Level &L0 = c->L[0];
+  if (precision == 1) return vcycle<float>(c, 0, (float *)x, (const float *)f, L0.t32);
+  return vcycle<double>(c, 0, (double *)x, (const double *)f, L0.t);
 }
 
 // ||r||_2^2 of the level-0 residual f - K u (free DOF), synchronising.

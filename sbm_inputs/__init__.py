@@ -94,6 +94,29 @@ def plate_void_2d(n: int = 64, floor: float = 1e-4) -> Problem:
     return Problem("plate_void_2d", (n, n), (h, h), lam, mu, floor, psi, kind, val)
 
 
+def plate_void_amr_2d(base: int = 16, levels: int = 3, block: int = 8, floor: float = 1e-4):
+    """The plate with a centred circular void for the adaptive solve in 2D:
+    the indicator 0.5 (1 + tanh((r - 0.25) / (2 h_f))), h_f the finest
+    spacing, sampled at the cell centres of every level (level a: base * 2^a
+    cells per axis).  Bottom edge clamped, normal traction 1e-3 on the top.
+    Returns (Problem of the base level, list of per-level raw psi)."""
+    hf = 1.0 / (base << (levels - 1))
+    psis = []
+    for a in range(levels):
+        n = base << a
+        X, Y = cell_centres((n, n), (1.0 / n, 1.0 / n))
+        r = np.hypot(X - 0.5, Y - 0.5)
+        psis.append(0.5 * (1 + np.tanh((r - 0.25) / (2 * hf))))
+    kind, val = _bc_table()
+    kind[2, :2] = DISPLACEMENT
+    val[3, 1] = 1e-3
+    lam, mu = lame(1.0, 0.3)
+    h0 = 1.0 / base
+    p = Problem("plate_void_amr_2d", (base, base), (h0, h0), lam, mu, floor, psis[0], kind, val,
+                extra={"levels": levels, "block": block})
+    return p, psis
+
+
 def spherical_voids_3d(n: int = 128, seed: int = 0, nvoid: int = 20,
                        floor: float = 1e-6) -> Problem:
     """Unit cube with seeded spherical voids (centres U[0,1]^3, radii

@@ -90,3 +90,26 @@ def test_python_layer_holds_no_arithmetic():
         src = open(os.path.join(pkg, fn)).read()
         for banned in ("torch.sum", "torch.where", ".sum(", "torch.matmul", "oracle"):
             assert banned not in src, (fn, banned)
+
+
+def test_amr_layout_validation(L):
+    """Adaptive layouts: block even and dividing twice the base cell count,
+    1..4 levels; the workspace covers every dense level."""
+    lib = L.lib()
+    o = L.SbmOptions()
+    lib.sbm_default_options(ctypes.byref(o))
+    g = L.SbmGrid()
+    g.dim = 3
+    for a in range(3):
+        g.ncell[a] = 64
+        g.h[a] = 1 / 64
+    ws = lib.sbm_amr_workspace_bytes(ctypes.byref(g), 3, 32, ctypes.byref(o))
+    # level 2 alone: 257^3 nodes x 3 x (5 FP64 + 4 FP32 vectors)
+    assert ws > 257 ** 3 * 3 * (5 * 8 + 4 * 4)
+    assert lib.sbm_amr_workspace_bytes(ctypes.byref(g), 3, 31, ctypes.byref(o)) == 0
+    assert lib.sbm_amr_workspace_bytes(ctypes.byref(g), 3, 48, ctypes.byref(o)) == 0
+    assert lib.sbm_amr_workspace_bytes(ctypes.byref(g), 5, 32, ctypes.byref(o)) == 0
+    assert lib.sbm_amr_workspace_bytes(ctypes.byref(g), 0, 32, ctypes.byref(o)) == 0
+    assert lib.sbm_amr_workspace_bytes(ctypes.byref(g), 1, 32, ctypes.byref(o)) > 0
+    g.dim = 2
+    assert lib.sbm_amr_workspace_bytes(ctypes.byref(g), 3, 8, ctypes.byref(o)) > 0
