@@ -223,7 +223,8 @@ typedef enum {
   SBM_PROF_PROLONG = 3,  /* prolongation-add into the finest level */
   SBM_PROF_NORM = 4,     /* convergence-test residual norm (+ FP32 cast) */
   SBM_PROF_BOTTOM = 5,   /* whole bottom solve */
-  SBM_PROF_N = 6
+  SBM_PROF_GHOST = 6,    /* coarse-fine ghost fill of the finest adaptive level */
+  SBM_PROF_N = 7
 } sbm_prof_class;
 sbm_status sbm_profile(sbm_ctx *ctx, int enable);
 sbm_status sbm_profile_read(sbm_ctx *ctx, double *ms_host, int64_t *count_host);
@@ -372,6 +373,13 @@ sbm_status sbm_amr_residual(sbm_amr_ctx *ctx, double *const *u, double *const *r
  * filled; history of relative composite residuals as in sbm_solve. */
 sbm_status sbm_amr_solve(sbm_amr_ctx *ctx, double *const *u, double *hist_host, int hist_cap,
                          int *n_cycles_host, double *final_rel_host);
+
+/* Live kernel timing of the finest adaptive level, as sbm_profile /
+ * sbm_profile_read (classes SMOOTH, RESIDUAL (cycle and convergence test),
+ * RESTRICT (restriction to the covered/interface nodes), PROLONG (coarse
+ * correction), GHOST; BOTTOM times the whole base V-cycle). */
+sbm_status sbm_amr_profile(sbm_amr_ctx *ctx, int enable);
+sbm_status sbm_amr_profile_read(sbm_amr_ctx *ctx, double *ms_host, int64_t *count_host);
 
 void sbm_amr_destroy(sbm_amr_ctx *ctx);
 

@@ -19,7 +19,7 @@ STATUS_NAMES = {0: "SBM_OK", 1: "SBM_NOT_CONVERGED", -1: "SBM_E_ARG", -2: "SBM_E
 TRACTION = 0
 DISPLACEMENT = 1
 CHAIN_PSI, CHAIN_FLOOR, CHAIN_RHO3 = 0, 1, 2
-PROF_CLASSES = ("smooth", "residual", "restrict", "prolong", "norm", "bottom")
+PROF_CLASSES = ("smooth", "residual", "restrict", "prolong", "norm", "bottom", "ghost")
 
 
 class SbmGrid(ctypes.Structure):
@@ -98,6 +98,8 @@ SIGNATURES = {
     "sbm_amr_ghost_fill": (ctypes.c_int, [_P, ctypes.c_int, _P, _P]),
     "sbm_amr_residual": (ctypes.c_int, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), _DP]),
     "sbm_amr_solve": (ctypes.c_int, [_P, ctypes.POINTER(_P), _DP, ctypes.c_int, _IP, _DP]),
+    "sbm_amr_profile": (ctypes.c_int, [_P, ctypes.c_int]),
+    "sbm_amr_profile_read": (ctypes.c_int, [_P, _DP, _I64P]),
     "sbm_amr_destroy": (None, [_P]),
 }
 

@@ -166,6 +166,19 @@ class AmrSolver:
         return [torch.zeros(self.node_shape(a), dtype=torch.float64, device=self.device)
                 for a in range(self.levels)]
 
+    def profile(self, enable=True):
+        check(lib().sbm_amr_profile(self._ctx, int(bool(enable))))
+
+    def profile_read(self):
+        """{class: (total_ms, launches)} of the finest-level launches timed
+        with HIP events since profile(True)."""
+        from ._lib import PROF_CLASSES
+        n = len(PROF_CLASSES)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int64 * n)()
+        check(lib().sbm_amr_profile_read(self._ctx, ms, cnt))
+        return {k: (ms[i], int(cnt[i])) for i, k in enumerate(PROF_CLASSES)}
+
     # ---------------------------------------------------------- operators
     def ghost_fill(self, a, xc, xf):
         xc_t = self._dev(xc, self.node_shape(a - 1))

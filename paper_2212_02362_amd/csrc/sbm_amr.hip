@@ -567,7 +567,50 @@ struct sbm_amr_ctx {
   double fnorm = 0.0;
   int64_t comp_dof = 0;
   bool have_problem = false;
+  // live timing of finest-level launches
+  bool prof_on = false;
+  std::vector<hipEvent_t> prof_ev;  // pairs
+  std::vector<int> prof_cls;        // class of each pair in use
+  double prof_ms[SBM_PROF_N] = {0};
+  int64_t prof_n[SBM_PROF_N] = {0};
 };
+
+// Brackets the launches of its scope with an event pair when profiling is on
+// and the scope belongs to the finest level.
+struct AmrProf {
+  sbm_amr_ctx *c;
+  bool on;
+  size_t pair = 0;
+  AmrProf(sbm_amr_ctx *c_, int cls, bool finest) : c(c_), on(c_->prof_on && finest) {
+    if (!on) return;
+    pair = c->prof_cls.size();
+    while (c->prof_ev.size() < 2 * (pair + 1)) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) {
+        on = false;
+        return;
+      }
+      c->prof_ev.push_back(e);
+    }
+    c->prof_cls.push_back(cls);
+    (void)hipEventRecord(c->prof_ev[2 * pair], c->st);
+  }
+  ~AmrProf() {
+    if (on) (void)hipEventRecord(c->prof_ev[2 * pair + 1], c->st);
+  }
+};
+
+// Accumulates the completed pairs (the stream is idle) and frees the pool.
+static void amr_prof_harvest(sbm_amr_ctx *c) {
+  for (size_t p = 0; p < c->prof_cls.size(); ++p) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, c->prof_ev[2 * p], c->prof_ev[2 * p + 1]) == hipSuccess) {
+      c->prof_ms[c->prof_cls[p]] += ms;
+      c->prof_n[c->prof_cls[p]] += 1;
+    }
+  }
+  c->prof_cls.clear();
+}
 
 static sbm_status amr_fail(sbm_status s, const std::string &m) { return set_error(s, m); }
 
@@ -696,10 +739,12 @@ template <typename T>
 static hipError_t amr_smooth(sbm_amr_ctx *c, int a, T *x, const T *f, T *tmp, int nu) {
   AmrLevel &l = c->lv[a];
   const double om = amr_omega(c->opt);
+  const bool fin = a == c->A;
   hipError_t e = hipSuccess;
   if (c->opt.smoother == 1) {
     T *src = x, *dst = tmp;
     for (int s = 0; s < nu; ++s) {
+      AmrProf pr(c, SBM_PROF_SMOOTH, fin);
       if ((e = launch_jacobi<T>(l.L, AV<T>::psi(l), AV<T>::coef(l), src, f, dst, om, c->st,
                                 l.cls)) != hipSuccess)
         return e;
@@ -709,9 +754,13 @@ static hipError_t amr_smooth(sbm_amr_ctx *c, int a, T *x, const T *f, T *tmp, in
     return e;
   }
   for (int s = 0; s < nu; ++s) {
-    if ((e = launch_rb_half<T>(l.L, AV<T>::psi(l), AV<T>::coef(l), x, f, tmp, om, 0, c->st,
-                               l.cls)) != hipSuccess)
-      return e;
+    {
+      AmrProf pr(c, SBM_PROF_SMOOTH, fin);
+      if ((e = launch_rb_half<T>(l.L, AV<T>::psi(l), AV<T>::coef(l), x, f, tmp, om, 0, c->st,
+                                 l.cls)) != hipSuccess)
+        return e;
+    }
+    AmrProf pr(c, SBM_PROF_SMOOTH, fin);
     if ((e = launch_rb_half<T>(l.L, AV<T>::psi(l), AV<T>::coef(l), tmp, f, x, om, 1, c->st,
                                l.cls)) != hipSuccess)
       return e;
@@ -725,19 +774,30 @@ template <typename T>
 static hipError_t amr_fas(sbm_amr_ctx *c, int a) {
   if (a == 0) {
     AmrLevel &l0 = c->lv[0];
+    AmrProf pr(c, SBM_PROF_BOTTOM, true);
     return base_vcycle(c->base, sizeof(T) == 8 ? 0 : 1, AV<T>::x(l0), AV<T>::f(l0));
   }
   AmrLevel &F = c->lv[a];
   AmrLevel &C = c->lv[a - 1];
+  const bool fin = a == c->A;
   hipError_t e;
   T *xf = AV<T>::x(F), *ff = AV<T>::f(F), *wf = AV<T>::w(F), *tf = AV<T>::tmp(F);
   T *xc = AV<T>::x(C), *fc = AV<T>::f(C), *xi = AV<T>::xinj(C), *tc = AV<T>::tmp(C);
-  if ((e = launch_ghost<T>(F.L, C.L, F.cls, xc, xf, c->st)) != hipSuccess) return e;
+  {
+    AmrProf pr(c, SBM_PROF_GHOST, fin);
+    if ((e = launch_ghost<T>(F.L, C.L, F.cls, xc, xf, c->st)) != hipSuccess) return e;
+  }
   if ((e = amr_smooth<T>(c, a, xf, ff, tf, c->opt.nu_pre)) != hipSuccess) return e;
-  if ((e = launch_ghost<T>(F.L, C.L, F.cls, xc, xf, c->st)) != hipSuccess) return e;
-  if ((e = launch_residual<T>(F.L, AV<T>::psi(F), AV<T>::coef(F), xf, ff, wf, nullptr, c->st,
-                              F.cls)) != hipSuccess)
-    return e;
+  {
+    AmrProf pr(c, SBM_PROF_GHOST, fin);
+    if ((e = launch_ghost<T>(F.L, C.L, F.cls, xc, xf, c->st)) != hipSuccess) return e;
+  }
+  {
+    AmrProf pr(c, SBM_PROF_RESIDUAL, fin);
+    if ((e = launch_residual<T>(F.L, AV<T>::psi(F), AV<T>::coef(F), xf, ff, wf, nullptr, c->st,
+                                F.cls)) != hipSuccess)
+      return e;
+  }
   if ((e = launch_inject<T>(F.L, C.L, F.cls, xf, xc, c->st)) != hipSuccess) return e;
   if ((e = launch_copy<T>(xc, xi, C.nv(), c->st)) != hipSuccess) return e;
   // coarse load on covered and interface nodes: R w + K_c x_c
@@ -745,10 +805,19 @@ static hipError_t amr_fas(sbm_amr_ctx *c, int a) {
     return e;
   const T *g = nullptr;
   if constexpr (sizeof(T) == 4) g = C.g32;
-  if ((e = launch_restrict_cif<T>(F.L, C.L, F.cls, wf, tc, g, fc, c->st)) != hipSuccess) return e;
+  {
+    AmrProf pr(c, SBM_PROF_RESTRICT, fin);
+    if ((e = launch_restrict_cif<T>(F.L, C.L, F.cls, wf, tc, g, fc, c->st)) != hipSuccess) return e;
+  }
   if ((e = amr_fas<T>(c, a - 1)) != hipSuccess) return e;
-  if ((e = launch_amr_correct<T>(F.L, C.L, F.cls, xc, xi, xf, c->st)) != hipSuccess) return e;
-  if ((e = launch_ghost<T>(F.L, C.L, F.cls, xc, xf, c->st)) != hipSuccess) return e;
+  {
+    AmrProf pr(c, SBM_PROF_PROLONG, fin);
+    if ((e = launch_amr_correct<T>(F.L, C.L, F.cls, xc, xi, xf, c->st)) != hipSuccess) return e;
+  }
+  {
+    AmrProf pr(c, SBM_PROF_GHOST, fin);
+    if ((e = launch_ghost<T>(F.L, C.L, F.cls, xc, xf, c->st)) != hipSuccess) return e;
+  }
   return amr_smooth<T>(c, a, xf, ff, tf, c->opt.nu_post);
 }
 
@@ -761,6 +830,7 @@ static sbm_status amr_comp_residual(sbm_amr_ctx *c, double *const *x, double *co
     AMR_HIP(launch_ghost<double>(c->lv[a].L, c->lv[a - 1].L, c->lv[a].cls, x[a - 1], x[a], c->st));
   for (int a = A; a >= 0; --a) {
     AmrLevel &l = c->lv[a];
+    AmrProf pr(c, SBM_PROF_NORM, a == A);
     AMR_HIP(launch_residual<double>(l.L, l.L.psi64, l.L.c64, x[a], f[a], r[a], nullptr, c->st,
                                     a >= 1 ? l.cls : nullptr));
     if (a < A)
@@ -777,6 +847,7 @@ static sbm_status amr_comp_residual(sbm_amr_ctx *c, double *const *x, double *co
   if (sync) {
     AMR_HIP(hipMemcpyAsync(c->host, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->st));
     AMR_HIP(hipStreamSynchronize(c->st));
+    if (c->prof_on) amr_prof_harvest(c);
   }
   return SBM_OK;
 }
@@ -856,9 +927,33 @@ sbm_status sbm_amr_create(const sbm_grid *base, int levels, int block, const sbm
   return SBM_OK;
 }
 
+sbm_status sbm_amr_profile(sbm_amr_ctx *c, int enable) {
+  if (!c) return amr_fail(SBM_E_ARG, "ctx is NULL");
+  AMR_HIP(hipStreamSynchronize(c->st));
+  c->prof_cls.clear();
+  for (int k = 0; k < SBM_PROF_N; ++k) {
+    c->prof_ms[k] = 0.0;
+    c->prof_n[k] = 0;
+  }
+  c->prof_on = enable != 0;
+  return SBM_OK;
+}
+
+sbm_status sbm_amr_profile_read(sbm_amr_ctx *c, double *ms, int64_t *cnt) {
+  if (!c || !ms || !cnt) return amr_fail(SBM_E_ARG, "NULL argument");
+  AMR_HIP(hipStreamSynchronize(c->st));
+  amr_prof_harvest(c);
+  for (int k = 0; k < SBM_PROF_N; ++k) {
+    ms[k] = c->prof_ms[k];
+    cnt[k] = c->prof_n[k];
+  }
+  return SBM_OK;
+}
+
 void sbm_amr_destroy(sbm_amr_ctx *c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->st);
+  for (hipEvent_t e : c->prof_ev) (void)hipEventDestroy(e);
   if (c->base) sbm_destroy(c->base);
   if (c->host) (void)hipHostFree(c->host);
   delete c;

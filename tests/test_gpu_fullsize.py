@@ -76,3 +76,53 @@ def test_fullsize_compliance_fd_193():
     say("compliance grad full size")
     J, g, u = compliance_grad(S, p.rho, p, return_u=True)
     _fd_check(S, p, to_np(g), u, p.fd_cells, step=1e-6)
+
+
+_AMR = {}
+
+
+def _amr_c4():
+    """Base 64^3, 3 levels, 32^3-cell blocks, threshold 0.05, 10 ellipsoidal
+    voids, floor 1e-5: the inputs and the oracle's setup (tags, blocks,
+    classes, averaged psi, loads) at full size, built once."""
+    if not _AMR:
+        say("amr full size: generating inputs")
+        p, psis = si.ellipsoidal_voids_amr(base=64, levels=3, block=32, seed=0)
+        say("amr full size: oracle setup")
+        m = oracle.AmrProblem(p.ncell, p.h, p.lam, p.mu, psis, p.psi_floor, p.kind, p.val,
+                              block=32, thresh=0.05)
+        _AMR.update(p=p, psis=psis, m=m)
+    return _AMR["p"], _AMR["psis"], _AMR["m"]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_fullsize_amr_c4(precision):
+    """Setup bit-exact against the oracle at full size; the GPU composite
+    solution's composite residual, evaluated by the oracle, within the
+    tolerance."""
+    from paper_2212_02362_amd import AmrSolver
+    p, psis, m = _amr_c4()
+    say("amr full size: GPU setup, precision", precision)
+    S = AmrSolver(p.ncell, p.h, 3, 32, precision=precision, rtol=1e-10, max_cycles=400)
+    S.set_problem(psis, p.lam, p.mu, p.psi_floor, p.kind, p.val, thresh=0.05)
+    for a in range(3):
+        blk_o, cls_o, psi_o = m.info(a)
+        blk_g, cls_g, psi_g = S.level_info(a)
+        assert np.array_equal(to_np(psi_g), psi_o), a
+        if a >= 1:
+            assert np.array_equal(blk_g, blk_o), a
+            assert np.array_equal(to_np(cls_g), cls_o), a
+        del cls_g, psi_g
+    dof, fnorm = S.stats()
+    assert abs(fnorm - m.fnorm()) <= 1e-12 * m.fnorm()
+    say("amr full size: GPU solve")
+    u, hist, st = S.solve()
+    assert st == 0, hist[-5:]
+    un = [to_np(x) for x in u]
+    del u
+    say("amr full size: oracle composite residual of the GPU solution")
+    _, nrm, _ = m.residual(un)
+    rho = nrm / m.fnorm()
+    print(f"[fullsize] amr C4 precision {precision}: {dof} composite DOF, {len(hist) - 1} cycles, "
+          f"GPU rho {hist[-1]:.3e}, oracle-evaluated rho {rho:.3e}", flush=True)
+    assert rho <= 1.05e-10
