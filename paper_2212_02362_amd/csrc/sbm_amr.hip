@@ -753,17 +753,20 @@ static hipError_t amr_smooth(sbm_amr_ctx *c, int a, T *x, const T *f, T *tmp, in
     if (src != x) e = launch_copy<T>(src, x, l.nv(), c->st);
     return e;
   }
+  const bool tiled = tiled_ok(l.L);
+  auto half = [&](const T *src, T *dst, int colour) {
+    return tiled ? launch_rb_tiled<T>(l.L, AV<T>::psi(l), AV<T>::coef(l), src, f, dst, om, colour,
+                                      c->st, l.cls)
+                 : launch_rb_half<T>(l.L, AV<T>::psi(l), AV<T>::coef(l), src, f, dst, om, colour,
+                                     c->st, l.cls);
+  };
   for (int s = 0; s < nu; ++s) {
     {
       AmrProf pr(c, SBM_PROF_SMOOTH, fin);
-      if ((e = launch_rb_half<T>(l.L, AV<T>::psi(l), AV<T>::coef(l), x, f, tmp, om, 0, c->st,
-                                 l.cls)) != hipSuccess)
-        return e;
+      if ((e = half(x, tmp, 0)) != hipSuccess) return e;
     }
     AmrProf pr(c, SBM_PROF_SMOOTH, fin);
-    if ((e = launch_rb_half<T>(l.L, AV<T>::psi(l), AV<T>::coef(l), tmp, f, x, om, 1, c->st,
-                               l.cls)) != hipSuccess)
-      return e;
+    if ((e = half(tmp, x, 1)) != hipSuccess) return e;
   }
   return e;
 }

@@ -78,6 +78,65 @@ __device__ __forceinline__ void cell_ijk(const Geom &g, int64_t id, int &i, int 
   j = (int)(row - (uint32_t)k * (uint32_t)g.cy);
 }
 
+// 3D eq. K at one node: P[c2][c1][c0] is the psi of cell (i-1+c0, j-1+c1,
+// k-1+c2) (0 outside the box) and U(c, dx, dy, dz) the c-th displacement at the
+// neighbour (i+dx, j+dy, k+dz).  Writes (K u)(n) and the diagonal of K.
+template <typename T, typename UF>
+__device__ __forceinline__ void stencil3(const Coef<T> &C, const T (&P)[2][2][2], UF &&U,
+                                         T out[3], T diag[3]) {
+  T E[3][2];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    E[0][s] = P[0][0][s] + P[0][1][s] + P[1][0][s] + P[1][1][s];
+    E[1][s] = P[0][s][0] + P[0][s][1] + P[1][s][0] + P[1][s][1];
+    E[2][s] = P[s][0][0] + P[s][0][1] + P[s][1][0] + P[s][1][1];
+  }
+  // direct part
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const T uc = U(c, 0, 0, 0);
+    const T xp = U(c, 1, 0, 0) - uc, xm = U(c, -1, 0, 0) - uc;
+    const T yp = U(c, 0, 1, 0) - uc, ym = U(c, 0, -1, 0) - uc;
+    const T zp = U(c, 0, 0, 1) - uc, zm = U(c, 0, 0, -1) - uc;
+    out[c] = -(C.cd[c][0] * (E[0][1] * xp + E[0][0] * xm) +
+               C.cd[c][1] * (E[1][1] * yp + E[1][0] * ym) +
+               C.cd[c][2] * (E[2][1] * zp + E[2][0] * zm));
+    diag[c] = C.cd[c][0] * (E[0][0] + E[0][1]) + C.cd[c][1] * (E[1][0] + E[1][1]) +
+              C.cd[c][2] * (E[2][0] + E[2][1]);
+  }
+  // cross part, plane (a, b) with third axis m
+#pragma unroll
+  for (int pl = 0; pl < 3; ++pl) {
+    const int a = (pl == 2) ? 1 : 0;
+    const int b = (pl == 0) ? 1 : 2;
+    const T cp = C.cp[pl], cm = C.cm[pl];
+    const T ua0 = U(a, 0, 0, 0), ub0 = U(b, 0, 0, 0);
+    T ra = T(0), rb = T(0);
+#pragma unroll
+    for (int qa = 0; qa < 2; ++qa)
+#pragma unroll
+      for (int qb = 0; qb < 2; ++qb) {
+        const int sa = 2 * qa - 1, sb = 2 * qb - 1;
+        int da[3] = {0, 0, 0}, db[3] = {0, 0, 0};
+        da[a] = sa;
+        db[b] = sb;
+        T F;
+        if (pl == 0) F = P[0][qb][qa] + P[1][qb][qa];       // (x, y), m = z
+        else if (pl == 1) F = P[qb][0][qa] + P[qb][1][qa];  // (x, z), m = y
+        else F = P[qb][qa][0] + P[qb][qa][1];               // (y, z), m = x
+        const T w = (sa * sb > 0) ? F : -F;
+        const T uaab = U(a, da[0] + db[0], da[1] + db[1], da[2] + db[2]);
+        const T ubab = U(b, da[0] + db[0], da[1] + db[1], da[2] + db[2]);
+        const T uaa = U(a, da[0], da[1], da[2]), uab = U(a, db[0], db[1], db[2]);
+        const T uba = U(b, da[0], da[1], da[2]), ubb = U(b, db[0], db[1], db[2]);
+        ra += w * (cp * (ubab - ub0) + cm * (ubb - uba));
+        rb += w * (cp * (uaab - ua0) + cm * (uaa - uab));
+      }
+    out[a] -= ra;
+    out[b] -= rb;
+  }
+}
+
 // Evaluates (K u)(n) for all components and the diagonal at node (i, j, k).
 // Neighbour offsets are clamped at the box boundary: every term that would
 // reach outside carries a zero psi weight, so the clamped value never counts.
@@ -106,60 +165,10 @@ __device__ __forceinline__ void node_stencil(const Geom &g, const Coef<T> &C,
           const bool in = xi >= 0 && xi < g.cx && yj >= 0 && yj < g.cy && zk >= 0 && zk < g.cz;
           P[c2][c1][c0] = in ? psi[xi + g.cx * (yj + g.cy * zk)] : T(0);
         }
-    T E[3][2];
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      E[0][s] = P[0][0][s] + P[0][1][s] + P[1][0][s] + P[1][1][s];
-      E[1][s] = P[0][s][0] + P[0][s][1] + P[1][s][0] + P[1][s][1];
-      E[2][s] = P[s][0][0] + P[s][0][1] + P[s][1][0] + P[s][1][1];
-    }
     auto U = [&](int c, int dx, int dy, int dz) -> T {
       return u[c * nn + idx + ox[dx + 1] + oy[dy + 1] + oz[dz + 1]];
     };
-    // direct part
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const T uc = U(c, 0, 0, 0);
-      const T xp = U(c, 1, 0, 0) - uc, xm = U(c, -1, 0, 0) - uc;
-      const T yp = U(c, 0, 1, 0) - uc, ym = U(c, 0, -1, 0) - uc;
-      const T zp = U(c, 0, 0, 1) - uc, zm = U(c, 0, 0, -1) - uc;
-      out[c] = -(C.cd[c][0] * (E[0][1] * xp + E[0][0] * xm) +
-                 C.cd[c][1] * (E[1][1] * yp + E[1][0] * ym) +
-                 C.cd[c][2] * (E[2][1] * zp + E[2][0] * zm));
-      diag[c] = C.cd[c][0] * (E[0][0] + E[0][1]) + C.cd[c][1] * (E[1][0] + E[1][1]) +
-                C.cd[c][2] * (E[2][0] + E[2][1]);
-    }
-    // cross part, plane (a, b) with third axis m
-#pragma unroll
-    for (int pl = 0; pl < 3; ++pl) {
-      const int a = (pl == 2) ? 1 : 0;
-      const int b = (pl == 0) ? 1 : 2;
-      const T cp = C.cp[pl], cm = C.cm[pl];
-      const T ua0 = U(a, 0, 0, 0), ub0 = U(b, 0, 0, 0);
-      T ra = T(0), rb = T(0);
-#pragma unroll
-      for (int qa = 0; qa < 2; ++qa)
-#pragma unroll
-        for (int qb = 0; qb < 2; ++qb) {
-          const int sa = 2 * qa - 1, sb = 2 * qb - 1;
-          int da[3] = {0, 0, 0}, db[3] = {0, 0, 0};
-          da[a] = sa;
-          db[b] = sb;
-          T F;
-          if (pl == 0) F = P[0][qb][qa] + P[1][qb][qa];       // (x, y), m = z
-          else if (pl == 1) F = P[qb][0][qa] + P[qb][1][qa];  // (x, z), m = y
-          else F = P[qb][qa][0] + P[qb][qa][1];               // (y, z), m = x
-          const T w = (sa * sb > 0) ? F : -F;
-          const T uaab = U(a, da[0] + db[0], da[1] + db[1], da[2] + db[2]);
-          const T ubab = U(b, da[0] + db[0], da[1] + db[1], da[2] + db[2]);
-          const T uaa = U(a, da[0], da[1], da[2]), uab = U(a, db[0], db[1], db[2]);
-          const T uba = U(b, da[0], da[1], da[2]), ubb = U(b, db[0], db[1], db[2]);
-          ra += w * (cp * (ubab - ub0) + cm * (ubb - uba));
-          rb += w * (cp * (uaab - ua0) + cm * (uaa - uab));
-        }
-      out[a] -= ra;
-      out[b] -= rb;
-    }
+    stencil3<T>(C, P, U, out, diag);
   } else {
     T P[2][2];  // P[oy][ox]
 #pragma unroll

@@ -57,6 +57,13 @@ template <typename T>
 hipError_t launch_rb_half(const Level &L, const T *psi, const Coef<T> &C, const T *u,
                           const T *f, T *u_out, double omega, int colour, hipStream_t st,
                           const uint8_t *cls = nullptr);
+// LDS-tiled 3D half-sweep (same result as launch_rb_half); tiled_ok tells
+// whether a level is large enough for the 64 x 8 node tiles to pay.
+bool tiled_ok(const Level &L);
+template <typename T>
+hipError_t launch_rb_tiled(const Level &L, const T *psi, const Coef<T> &C, const T *u, const T *f,
+                           T *u_out, double omega, int colour, hipStream_t st,
+                           const uint8_t *cls = nullptr);
 template <typename T>
 hipError_t launch_restrict(const Level &F, const Level &Cl, const T *r, T *fc, hipStream_t st);
 template <typename T>

@@ -348,13 +348,18 @@ static hipError_t smooth(sbm_ctx *c, int l, T *x, const T *f, T *tmp, int nu, bo
     return e;
   }
   const int c0 = reverse ? 1 : 0;
+  const bool tiled = tiled_ok(L);
+  auto half = [&](const T *src, T *dst, int colour) {
+    return tiled ? launch_rb_tiled<T>(L, psi, C, src, f, dst, om, colour, c->st)
+                 : launch_rb_half<T>(L, psi, C, src, f, dst, om, colour, c->st);
+  };
   for (int s = 0; s < nu; ++s) {
     {
       ProfScope ps(c, SBM_PROF_SMOOTH, l == 0);
-      if ((e = launch_rb_half<T>(L, psi, C, x, f, tmp, om, c0, c->st)) != hipSuccess) return e;
+      if ((e = half(x, tmp, c0)) != hipSuccess) return e;
     }
     ProfScope ps(c, SBM_PROF_SMOOTH, l == 0);
-    if ((e = launch_rb_half<T>(L, psi, C, tmp, f, x, om, 1 - c0, c->st)) != hipSuccess) return e;
+    if ((e = half(tmp, x, 1 - c0)) != hipSuccess) return e;
   }
   return e;
 }
@@ -1028,6 +1033,8 @@ sbm_status sbm_level_smooth(sbm_ctx *c, int l, int colour, double omega, const d
   if (!(omega > 0.0 && omega < 2.0) || colour > 1) return fail(SBM_E_ARG, "bad omega/colour");
   Level &L = c->L[l];
   if (colour < 0) HIP_TRY(launch_jacobi<double>(L, L.psi64, L.c64, u_in, f, u_out, omega, c->st));
+  else if (tiled_ok(L))
+    HIP_TRY(launch_rb_tiled<double>(L, L.psi64, L.c64, u_in, f, u_out, omega, colour, c->st));
   else HIP_TRY(launch_rb_half<double>(L, L.psi64, L.c64, u_in, f, u_out, omega, colour, c->st));
   return SBM_OK;
 }

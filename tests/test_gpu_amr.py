@@ -175,6 +175,25 @@ def test_solve_mixed(name):
         assert err < 1e-8, (a, err)
 
 
+def test_midsize_first_cycle():
+    """Base 64^3 with a 129^3-node finest level (32^3-cell blocks, 56 % of
+    them active): the first composite cycle follows the oracle's."""
+    from paper_2212_02362_amd import AmrSolver
+    p, psis = si.ellipsoidal_voids_amr(base=64, levels=2, block=32, seed=4)
+    m = oracle.AmrProblem(p.ncell, p.h, p.lam, p.mu, psis, p.psi_floor, p.kind, p.val, block=32)
+    say("amr mid-size: oracle cycle")
+    u_o, h_o, _ = m.solve(rtol=0.0, max_cycles=1)
+    for prec in (0, 1):
+        S = AmrSolver(p.ncell, p.h, 2, 32, max_cycles=1, rtol=0.0, precision=prec)
+        S.set_problem(psis, p.lam, p.mu, p.psi_floor, p.kind, p.val)
+        say("amr mid-size: GPU cycle, precision", prec)
+        u_g, h_g, _ = S.solve()
+        tol = 1e-11 if prec == 0 else 1e-5
+        assert np.allclose(h_g, h_o, rtol=tol, atol=0), (h_g, h_o)
+        for a in range(2):
+            assert rel_l2(to_np(u_g[a]), u_o[a]) < tol, (prec, a, rel_l2(to_np(u_g[a]), u_o[a]))
+
+
 def test_full_coverage_matches_uniform_fine_solve():
     """A refined level covering the whole box: the composite solve reproduces
     the uniform solve of the fine grid cycle by cycle."""

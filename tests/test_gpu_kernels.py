@@ -85,6 +85,22 @@ def test_residual_and_smoothers(ncell):
         assert np.array_equal(got[other], u[other])
 
 
+@pytest.mark.parametrize("ncell", [(200, 30, 12), (230, 25, 9), (256, 33, 6)])
+def test_tiled_half_sweep(ncell):
+    """Levels wider than 192 nodes in x take the LDS-tiled half-sweep: several
+    64 x 8 tiles, a ragged last tile in x and y, z chunks."""
+    p, S, psi, mask, u, f = _setup(ncell, seed=11)
+    u = np.where(mask == 1, oracle.dirichlet(p.ncell, p.kind, p.val)[1], u)
+    for colour in (0, 1):
+        say("tiled half sweep", ncell, colour)
+        got = to_np(S.level_smooth(0, colour, 1.0, u, f))
+        ref = oracle.rb_half(p.ncell, p.h, p.lam, p.mu, psi, mask, 1.0, colour, u, f)
+        assert rel_max(got, ref) < 1e-13
+        idx = np.indices(p.node_shape).sum(0) % 2
+        other = np.broadcast_to(idx != colour, got.shape)
+        assert np.array_equal(got[other], u[other])
+
+
 @pytest.mark.parametrize("ncell", [(40, 30), (36, 26), (20, 12, 16), (12, 18, 10)])
 def test_transfers(ncell):
     p, S, psi, mask, u, f = _setup(ncell, seed=2)
