@@ -64,6 +64,17 @@ template <typename T>
 hipError_t launch_rb_tiled(const Level &L, const T *psi, const Coef<T> &C, const T *u, const T *f,
                            T *u_out, double omega, int colour, hipStream_t st,
                            const uint8_t *cls = nullptr);
+// Tiled residual / Krylov Apply (same results as the node-parallel kernels);
+// their partial sums number tiled_partials(L).
+int tiled_partials(const Level &L);
+template <typename T>
+hipError_t launch_residual_tiled(const Level &L, const T *psi, const Coef<T> &C, const T *u,
+                                 const T *f, T *r, double *partials, hipStream_t st,
+                                 const uint8_t *cls);
+hipError_t launch_apply_dot_tiled(const Level &L, const double *p, double *q, double *partials,
+                                  hipStream_t st);
+// Number of partial sums launch_residual / launch_apply_dot write for level L.
+int stencil_partials(const Level &L);
 template <typename T>
 hipError_t launch_restrict(const Level &F, const Level &Cl, const T *r, T *fc, hipStream_t st);
 template <typename T>

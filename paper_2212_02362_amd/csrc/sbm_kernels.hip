@@ -1142,6 +1142,16 @@ __global__ __launch_bounds__(kBlock) void k_sensitivity(Geom g, double lame, dou
     return hipGetLastError();                                              \
   } while (0)
 
+// The tiled stencil kernels write one partial sum per tile; they are used
+// where they pay and where their partials fit the per-node-block count.
+static bool use_tiled(const Level &L) {
+  return tiled_ok(L) && tiled_partials(L) <= num_blocks(L.g.nn);
+}
+
+int stencil_partials(const Level &L) {
+  return use_tiled(L) ? tiled_partials(L) : num_blocks(L.g.nn);
+}
+
 static int fill_blocks(int64_t n) {
   const int64_t b = (n + kBlock - 1) / kBlock;
   return (int)(b < 65536 ? (b > 0 ? b : 1) : 65536);
@@ -1158,6 +1168,7 @@ template <typename T>
 hipError_t launch_residual(const Level &L, const T *psi, const Coef<T> &C, const T *u,
                            const T *f, T *r, double *partials, hipStream_t st,
                            const uint8_t *cls) {
+  if (use_tiled(L)) return launch_residual_tiled<T>(L, psi, C, u, f, r, partials, st, cls);
   if (L.g.dim == 3)
     SBM_LAUNCH((k_residual<T, 3>), num_blocks(L.g.nn), kBlock, st, L.g, C, psi, u, f, r, partials,
                cls);
@@ -1266,6 +1277,7 @@ hipError_t launch_dot_free(const Level &L, const double *a, const double *b, dou
 
 hipError_t launch_apply_dot(const Level &L, const double *p, double *q, double *partials,
                            hipStream_t st) {
+  if (use_tiled(L)) return launch_apply_dot_tiled(L, p, q, partials, st);
   if (L.g.dim == 3)
     SBM_LAUNCH((k_apply_dot<3>), num_blocks(L.g.nn), kBlock, st, L.g, L.c64, L.psi64, p, q, partials);
   SBM_LAUNCH((k_apply_dot<2>), num_blocks(L.g.nn), kBlock, st, L.g, L.c64, L.psi64, p, q, partials);

@@ -423,7 +423,7 @@ static sbm_status residual_norm2(sbm_ctx *c, const double *u, const double *f, d
     ProfScope ps(c, SBM_PROF_NORM, true);
     HIP_TRY((launch_residual<double>(L, L.psi64, L.c64, u, f, nullptr, c->partials, c->st)));
   }
-  HIP_TRY(launch_finalize_sum(c->partials, num_blocks(L.g.nn), c->scal, c->st));
+  HIP_TRY(launch_finalize_sum(c->partials, stencil_partials(L), c->scal, c->st));
   HIP_TRY(hipMemcpyAsync(c->host, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->st));
   HIP_TRY(hipStreamSynchronize(c->st));
   if (c->prof_on) prof_harvest(c);
@@ -548,7 +548,8 @@ static sbm_status solve_krylov(sbm_ctx *c, const double *f, double fnorm, double
                                int cap, int *ncyc, double *final_rel) {
   Level &L0 = c->L[0];
   const int64_t nv = (int64_t)c->dim * L0.g.nn;
-  const int nb = num_blocks(L0.g.nn);
+  const int nb = num_blocks(L0.g.nn);       // node-parallel kernels
+  const int ns = stencil_partials(L0);      // residual / Apply kernels
   double rho_min = INFINITY, rho = 0.0;
   sbm_status status = SBM_NOT_CONVERGED;
   HIP_TRY(launch_copy<double>(u, c->x0, nv, c->st));
@@ -556,7 +557,7 @@ static sbm_status solve_krylov(sbm_ctx *c, const double *f, double fnorm, double
     ProfScope ps(c, SBM_PROF_NORM, true);
     HIP_TRY((launch_residual<double>(L0, L0.psi64, L0.c64, c->x0, f, c->kr, c->partials, c->st)));
   }
-  SBM_TRY(fin_to_host(c, c->partials, nb, 0));
+  SBM_TRY(fin_to_host(c, c->partials, ns, 0));
   HIP_TRY(hipStreamSynchronize(c->st));
   rho = fnorm > 0.0 ? sqrt(c->host[0]) / fnorm : (c->host[0] > 0.0 ? INFINITY : 0.0);
   if (hist && cap > 0) hist[0] = rho;
@@ -589,7 +590,7 @@ static sbm_status solve_krylov(sbm_ctx *c, const double *f, double fnorm, double
       restart = false;
     }
     HIP_TRY(launch_apply_dot(L0, c->kp, c->kq, c->partials, c->st));
-    SBM_TRY(fin_to_host(c, c->partials, nb, 2));
+    SBM_TRY(fin_to_host(c, c->partials, ns, 2));
     HIP_TRY(hipStreamSynchronize(c->st));
     if (c->prof_on) prof_harvest(c);
     if (!(c->host[2] > 0.0)) {
@@ -610,7 +611,7 @@ static sbm_status solve_krylov(sbm_ctx *c, const double *f, double fnorm, double
         HIP_TRY((launch_residual<double>(L0, L0.psi64, L0.c64, c->x0, f, c->kr, c->partials,
                                          c->st)));
       }
-      SBM_TRY(fin_to_host(c, c->partials, nb, 0));
+      SBM_TRY(fin_to_host(c, c->partials, ns, 0));
       HIP_TRY(hipStreamSynchronize(c->st));
       rho = fnorm > 0.0 ? sqrt(c->host[0]) / fnorm : 0.0;
       if (hist && m < cap) hist[m] = rho;
@@ -911,7 +912,7 @@ sbm_status sbm_solve_rhs(sbm_ctx *c, const double *g, double *x, double *hist, i
   // masked copy of g: r = g - K*0 on free DOF via the residual kernel
   HIP_TRY(launch_fill<double>(L0.t, nv, 0.0, c->st));
   HIP_TRY((launch_residual<double>(L0, L0.psi64, L0.c64, L0.t, g, L0.e, c->partials, c->st)));
-  HIP_TRY(launch_finalize_sum(c->partials, num_blocks(L0.g.nn), c->scal, c->st));
+  HIP_TRY(launch_finalize_sum(c->partials, stencil_partials(L0), c->scal, c->st));
   HIP_TRY(hipMemcpyAsync(c->host, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->st));
   HIP_TRY(hipStreamSynchronize(c->st));
   const double gn = sqrt(c->host[0]);
@@ -937,7 +938,7 @@ sbm_status sbm_residual(sbm_ctx *c, const double *u, double *r, double *norm_hos
     return SBM_OK;
   }
   HIP_TRY((launch_residual<double>(L0, L0.psi64, L0.c64, u, L0.f, r, c->partials, c->st)));
-  HIP_TRY(launch_finalize_sum(c->partials, num_blocks(L0.g.nn), c->scal, c->st));
+  HIP_TRY(launch_finalize_sum(c->partials, stencil_partials(L0), c->scal, c->st));
   HIP_TRY(hipMemcpyAsync(c->host, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->st));
   HIP_TRY(hipStreamSynchronize(c->st));
   *norm_host = sqrt(c->host[0]);

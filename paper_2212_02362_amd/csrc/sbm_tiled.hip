@@ -277,6 +277,149 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(SBM_TILE_WAV
   }
 }
 
+// Full stencil pass over the tile (every node computed), thread per x-pair:
+//   MODE 0 (residual): v = f - K u on free DOF, 0 on displacement DOF (and,
+//     with MASK, outside classes 1-3); r = v when r is given; partial sum of
+//     v^2 per tile when partials is given;
+//   MODE 1 (Krylov Apply): v = K u on free DOF, 0 on displacement DOF; r = v;
+//     partial sum of u . v per tile.
+// Partials land in partials[tile], tiles in their logical order.
+template <typename T, int MODE, bool MASK>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(SBM_TILE_WAVES))) void
+k_full_tile(TG g, Coef<T> C, const T *__restrict__ psi, const T *__restrict__ u,
+            const T *__restrict__ f, T *__restrict__ r, double *__restrict__ partials,
+            TileGeom tg, const uint8_t *__restrict__ cls) {
+  __shared__ T su[3][NU];
+  __shared__ T sp[2][NP];
+  __shared__ double red[NT / 64 + 1];
+  const int nwg = gridDim.x;  // a multiple of 8
+  const int b = blockIdx.x;
+  const int lt = SBM_TILE_XCD ? (b & 7) * (nwg >> 3) + (b >> 3) : b;
+  if (lt >= tg.ntiles) return;
+  const int tx = lt % tg.ntx;
+  const int rest = lt / tg.ntx;
+  const int ty = rest % tg.nty;
+  const int tz = rest / tg.nty;
+  const int x0 = tx * TX, y0 = ty * TY;
+  const int k0 = tz * tg.kz;
+  const int k1 = min(k0 + tg.kz, g.nz);
+  const int nn = g.nn, nxy = g.nx * g.ny;
+
+  Slots sl;
+  make_slots(g, x0, y0, sl);
+  const int yl = threadIdx.x / (TX / 2), p = threadIdx.x % (TX / 2);
+  const int gy = y0 + yl;
+  const int gx0 = x0 + 2 * p;  // the pair: gx0, gx0 + 1
+  const bool row_ok = gy < g.ny;
+  // loads of f one plane ahead, issued before the plane prefetch (and the
+  // first before the prologue), so no wait for f waits for a prefetch
+  T fv[2][3] = {{T(0), T(0), T(0)}, {T(0), T(0), T(0)}};
+  if (MODE == 0 && row_ok) {
+    const int q = gy * g.nx + k0 * nxy + gx0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+      if (gx0 + h < g.nx)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) fv[h][c] = f[c * nn + q + h];
+  }
+  {
+    T r0[NUPT], r1[NUPT], r2[NUPT], q0[NPPT], q1[NPPT];
+    fetch_u(g, sl, u, k0 - 1, r0);
+    fetch_u(g, sl, u, k0, r1);
+    fetch_u(g, sl, u, k0 + 1, r2);
+    fetch_p(g, sl, psi, k0 - 1, q0);
+    fetch_p(g, sl, psi, k0, q1);
+    put_u(g, sl, k0 - 1, su[(k0 + 2) % 3], r0);
+    put_u(g, sl, k0, su[k0 % 3], r1);
+    put_u(g, sl, k0 + 1, su[(k0 + 1) % 3], r2);
+    put_p(g, sl, k0 - 1, sp[(k0 + 1) & 1], q0);
+    put_p(g, sl, k0, sp[k0 & 1], q1);
+  }
+  __syncthreads();
+
+  double acc = 0.0;
+  for (int k = k0; k < k1; ++k) {
+    const bool pre = k + 1 < k1;
+    T fn[2][3] = {{T(0), T(0), T(0)}, {T(0), T(0), T(0)}};
+    if (MODE == 0 && pre && row_ok) {
+      const int q = gy * g.nx + (k + 1) * nxy + gx0;
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        if (gx0 + h < g.nx)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) fn[h][c] = f[c * nn + q + h];
+    }
+    T ru[NUPT], rp[NPPT];
+    if (pre) {
+      fetch_u(g, sl, u, k + 2, ru);
+      fetch_p(g, sl, psi, k + 1, rp);
+    }
+    const T *Lm = su[(k + 2) % 3];
+    const T *L0 = su[k % 3];
+    const T *L1 = su[(k + 1) % 3];
+    const T *Pm = sp[(k + 1) & 1];
+    const T *P0 = sp[k & 1];
+    if (row_ok) {
+      const int row = gy * g.nx + k * nxy;
+      T v[2][3];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int xl = 2 * p + h, gx = x0 + xl;
+        const int cu = (yl + 1) * LX + xl + 1;
+        const bool live = gx < g.nx && !(MASK && (cls[row + gx] == 0 || cls[row + gx] > 3));
+        v[h][0] = v[h][1] = v[h][2] = T(0);
+        if (live) {
+          T P[2][2][2];
+#pragma unroll
+          for (int c1 = 0; c1 < 2; ++c1)
+#pragma unroll
+            for (int c0 = 0; c0 < 2; ++c0) {
+              P[0][c1][c0] = Pm[(yl + c1) * CXL + xl + c0];
+              P[1][c1][c0] = P0[(yl + c1) * CXL + xl + c0];
+            }
+          auto U = [&](int c, int dx, int dy, int dz) -> T {
+            const T *L = dz < 0 ? Lm : (dz > 0 ? L1 : L0);
+            return L[c * PLANE + cu + dx + dy * LX];
+          };
+          T out[3], dg[3];
+          stencil3<T>(C, P, U, out, dg);
+          const bool face = gx == 0 || gx == g.nx - 1 || gy == 0 || gy == g.ny - 1 || k == 0 ||
+                            k == g.nz - 1;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const bool fixed = face && tg_dirichlet(g, gx, gy, k, c);
+            const T val = MODE == 0 ? fv[h][c] - out[c] : out[c];
+            v[h][c] = fixed ? T(0) : val;
+            if (MODE == 0) acc += (double)v[h][c] * (double)v[h][c];
+            else acc += (double)L0[c * PLANE + cu] * (double)v[h][c];
+          }
+        }
+      }
+      if (r) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          if (gx0 < g.nx) r[c * nn + row + gx0] = v[0][c];
+          if (gx0 + 1 < g.nx) r[c * nn + row + gx0 + 1] = v[1][c];
+        }
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) fv[h][c] = fn[h][c];
+    __syncthreads();
+    if (pre) {
+      put_u(g, sl, k + 2, su[(k + 2) % 3], ru);
+      put_p(g, sl, k + 1, sp[(k + 1) & 1], rp);
+    }
+    __syncthreads();
+  }
+  if (partials) {
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) partials[lt] = s;
+  }
+}
+
 }  // namespace
 
 bool tiled_ok(const Level &L) {
@@ -304,6 +447,45 @@ hipError_t launch_rb_tiled(const Level &L, const T *psi, const Coef<T> &C, const
                        u_out, (T)omega, colour, tg, cls);
   return hipGetLastError();
 }
+
+int tiled_partials(const Level &L) { return tile_geom(make_tg(L.g)).ntiles; }
+
+template <typename T>
+hipError_t launch_residual_tiled(const Level &L, const T *psi, const Coef<T> &C, const T *u,
+                                 const T *f, T *r, double *partials, hipStream_t st,
+                                 const uint8_t *cls) {
+  const TG gg = make_tg(L.g);
+  const TileGeom tg = tile_geom(gg);
+  const int grid = (tg.ntiles + 7) / 8 * 8;
+  (void)hipGetLastError();
+  if (cls)
+    hipLaunchKernelGGL((k_full_tile<T, 0, true>), dim3(grid), dim3(NT), 0, st, gg, C, psi, u, f,
+                       r, partials, tg, cls);
+  else
+    hipLaunchKernelGGL((k_full_tile<T, 0, false>), dim3(grid), dim3(NT), 0, st, gg, C, psi, u, f,
+                       r, partials, tg, cls);
+  return hipGetLastError();
+}
+
+hipError_t launch_apply_dot_tiled(const Level &L, const double *p, double *q, double *partials,
+                                  hipStream_t st) {
+  const TG gg = make_tg(L.g);
+  const TileGeom tg = tile_geom(gg);
+  const int grid = (tg.ntiles + 7) / 8 * 8;
+  (void)hipGetLastError();
+  hipLaunchKernelGGL((k_full_tile<double, 1, false>), dim3(grid), dim3(NT), 0, st, gg, L.c64,
+                     L.psi64, p, (const double *)nullptr, q, partials, tg,
+                     (const uint8_t *)nullptr);
+  return hipGetLastError();
+}
+
+template hipError_t launch_residual_tiled<double>(const Level &, const double *,
+                                                  const Coef<double> &, const double *,
+                                                  const double *, double *, double *, hipStream_t,
+                                                  const uint8_t *);
+template hipError_t launch_residual_tiled<float>(const Level &, const float *, const Coef<float> &,
+                                                 const float *, const float *, float *, double *,
+                                                 hipStream_t, const uint8_t *);
 
 template hipError_t launch_rb_tiled<double>(const Level &, const double *, const Coef<double> &,
                                             const double *, const double *, double *, double,

@@ -101,6 +101,23 @@ def test_tiled_half_sweep(ncell):
         assert np.array_equal(got[other], u[other])
 
 
+@pytest.mark.parametrize("ncell", [(200, 30, 12), (256, 33, 6)])
+def test_tiled_residual_and_norm(ncell):
+    """The tiled residual (r and its per-tile norm partials) at widths that
+    take the tiled path."""
+    p, S, psi, mask, u, f = _setup(ncell, seed=12)
+    u = np.where(mask == 1, oracle.dirichlet(p.ncell, p.kind, p.val)[1], u)
+    say("tiled residual", ncell)
+    got = to_np(S.level_residual(0, u, f))
+    ref = oracle.residual(p.ncell, p.h, p.lam, p.mu, psi, mask, u, f)
+    assert rel_max(got, ref) < 1e-13
+    fA, _, _ = oracle.rhs(p.ncell, p.h, p.lam, p.mu, psi, p.kind, p.val, p.b)
+    r_ref = oracle.residual(p.ncell, p.h, p.lam, p.mu, psi, mask, u, fA)
+    r_got, nrm = S.residual(u)
+    assert rel_max(to_np(r_got), r_ref) < 1e-13
+    assert abs(nrm - np.linalg.norm(r_ref)) <= 1e-12 * np.linalg.norm(r_ref)
+
+
 @pytest.mark.parametrize("ncell", [(40, 30), (36, 26), (20, 12, 16), (12, 18, 10)])
 def test_transfers(ncell):
     p, S, psi, mask, u, f = _setup(ncell, seed=2)

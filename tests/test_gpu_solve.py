@@ -70,6 +70,21 @@ def test_krylov_trajectory_parity(case, smoother):
     assert rel_l2(u_g, u_o) <= 1e-9, rel_l2(u_g, u_o)
 
 
+@pytest.mark.parametrize("krylov", [0, 1])
+def test_wide_grid_first_iterations(krylov):
+    """209 x 33 x 17 nodes: the finest level takes the LDS-tiled half-sweep,
+    residual and (Krylov) Apply; the first iterations follow the oracle's."""
+    p = random_problem((208, 32, 16), seed=6, floor=1e-3)
+    say("wide grid", krylov)
+    u_o, hist_o, _ = oracle_solve(p, rtol=0.0, max_cycles=5, krylov=krylov)
+    S = solver_for(p, rtol=0.0, max_cycles=5, krylov=krylov)
+    u_g, hist_g, _ = S.solve()
+    assert len(hist_g) == len(hist_o) == 6
+    dh = np.abs(hist_g - hist_o)
+    assert np.all(dh <= 1e-9 * hist_o + RHO_ATOL), dh.max()
+    assert rel_l2(to_np(u_g), u_o) <= 1e-11, rel_l2(to_np(u_g), u_o)
+
+
 @pytest.mark.parametrize("case", ["plate_void_2d_64", "spherical_voids_32", "cantilever_24x12x12",
                                   "random_mixed_3d_16x8x12", "random_mixed_2d_50x46"])
 def test_mixed_precision_converges_to_fp64_solution(case):
