@@ -227,6 +227,86 @@ def _traffic(kernel_key, nodes):
     return ent.get("hbm_bytes_per_launch")
 
 
+TRAFFIC_KERNEL = "k_rb_half<double,3>"
+COPY_BYTES = 400_000_000  # calibration copy: this many bytes read and written
+
+
+def _counter_driver():
+    """Workload for the two rocprofv3 counter passes: the finest-level
+    half-sweep of the default workload, launched as inside its V-cycles
+    (same kernel, level and launch shape), then a plain device copy of known
+    size that calibrates FETCH_SIZE / WRITE_SIZE."""
+    import torch
+
+    from paper_2212_02362_amd import Solver
+
+    p, _ = _workload("spherical_voids_129")
+    S = Solver(p.ncell, p.h)
+    S.set_problem(torch.tensor(p.psi_raw, device="cuda"), p.lam, p.mu, p.psi_floor, p.kind, p.val)
+    u = torch.randn((p.dim,) + p.node_shape, dtype=torch.float64, device="cuda")
+    f = torch.randn_like(u)
+    for it in range(10):
+        u = S.level_smooth(0, it % 2, 1.0, u, f)
+    x = torch.randn(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print("[counters] driver done", flush=True)
+
+
+def _counter_summary(fetch_dir, write_dir):
+    """HBM bytes per launch of the dominant kernel from the two counter runs,
+    each counter scaled by its reading for the calibration copy; writes
+    profiles/traffic_counters.json (keyed by the kernel-source hash, so a
+    changed kernel reports no traffic) and a text summary."""
+    import csv
+
+    def read(d, counter):
+        path = None
+        for root, _, files in os.walk(d):
+            for fn in files:
+                if fn.endswith("counter_collection.csv"):
+                    path = os.path.join(root, fn)
+        if path is None:
+            raise SystemExit(f"no counter_collection.csv under {d}")
+        kern, copy = [], []
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] != counter:
+                    continue
+                v = float(r["Counter_Value"]) * 1024.0  # KiB -> bytes
+                name = r["Kernel_Name"]
+                if "k_rb_half<double, 3>" in name:
+                    kern.append(v)
+                elif "copyBuffer" in name and v > 0.25 * COPY_BYTES:
+                    copy.append(v)
+        if not kern or not copy:
+            raise SystemExit(f"{counter}: kernel or calibration copy missing in {path}")
+        return sum(kern) / len(kern), sum(copy) / len(copy), len(kern)
+
+    fk, fc, nf = read(fetch_dir, "FETCH_SIZE")
+    wk, wc, nw = read(write_dir, "WRITE_SIZE")
+    ff, fw = COPY_BYTES / fc, COPY_BYTES / wc
+    p, _ = _workload("spherical_voids_129")
+    nodes = p.n_nodes
+    fetch, write = fk * ff, wk * fw
+    ent = {"kernel_hash": _kernel_hash(), "nodes": nodes, "hbm_bytes_per_launch": fetch + write,
+           "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
+           "fetch_factor": ff, "write_factor": fw, "launches": [nf, nw],
+           "algo_bytes_per_launch": ALGO_BYTES["smooth"][0] * nodes}
+    path = os.path.join(ROOT, "profiles", "traffic_counters.json")
+    data = {}
+    if os.path.exists(path):
+        with open(path) as fh:
+            data = json.load(fh)
+    data[TRAFFIC_KERNEL] = ent
+    with open(path, "w") as fh:
+        json.dump(data, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps(ent))
+
+
 def _time_solves(S, p, psi_dev, b_dev, precision, steps, warmup, krylov=0):
     """Timed region: `steps` complete solves (V-cycles replayed from HIP
     graphs).  Then the same number of solves with live kernel timing (HIP
@@ -294,7 +374,15 @@ def main():
                              AMR_WORKLOAD])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--counter-driver", action="store_true",
+                    help="run the dominant kernel and a calibration copy (under rocprofv3 --pmc)")
+    ap.add_argument("--counter-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="turn two rocprofv3 counter runs into profiles/traffic_counters.json")
     args = ap.parse_args()
+    if args.counter_driver:
+        return _counter_driver()
+    if args.counter_summary:
+        return _counter_summary(*args.counter_summary)
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for "
               f"--gpus {args.gpus}).  Run with --gpus 1.", file=sys.stderr)
@@ -354,7 +442,7 @@ def main():
     avg_ms = ms_s / max(n_s, 1)
     by = ALGO_BYTES["smooth"][0] * nodes
     achieved = by / (avg_ms * 1e-3) / 1e9
-    traffic = _traffic("k_rb_half<double,3>", nodes)
+    traffic = _traffic(TRAFFIC_KERNEL, nodes)
     line = {
         "metric": METRIC,
         "value": free / t64,

@@ -108,6 +108,8 @@ hipError_t launch_cast_scaled(const double *r, float *r32, int64_t n, const doub
 hipError_t launch_scale_set(double *z, const float *e32, int64_t n, const double *ss,
                             hipStream_t st);
 int num_blocks(int64_t n);
+// Grid of the XCD-ordered stencil kernels over n items (>= num_blocks(n)).
+int grid_blocks(int64_t n);
 template <typename T>
 hipError_t launch_bottom_cg(const Level &L, const T *psi, const Coef<T> &C, const T *f, T *x,
                             T *r, T *p, T *Ap, double rtol, int maxit, int *iters,

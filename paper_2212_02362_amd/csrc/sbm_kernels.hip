@@ -10,12 +10,27 @@ namespace sbm {
 
 int num_blocks(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
 
+// Stencil kernels: workgroup b runs on XCD b mod 8, so the logical block order
+// deals each XCD a contiguous range of rows; the neighbouring rows and planes
+// a block reads then sit in its own L2.  Grids of 64 or more blocks are
+// padded to a multiple of 8 (padding blocks find no node).
+int grid_blocks(int64_t n) {
+  const int nb = num_blocks(n);
+  return nb >= 64 ? (nb + 7) / 8 * 8 : nb;
+}
+
+__device__ __forceinline__ int xcd_block() {
+  const int nwg = gridDim.x;
+  return (nwg & 7) == 0 ? (int)(blockIdx.x & 7) * (nwg >> 3) + (int)(blockIdx.x >> 3)
+                        : (int)blockIdx.x;
+}
+
 // ------------------------------------------------------------------ apply --
 
 template <typename T, int DIM>
 __global__ __launch_bounds__(kBlock) void k_apply(Geom g, Coef<T> C, const T *__restrict__ psi,
                                                   const T *__restrict__ u, T *__restrict__ y) {
-  const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t id = (int64_t)xcd_block() * kBlock + threadIdx.x;
   if (id >= g.nn) return;
   int i, j, k;
   node_ijk(g, id, i, j, k);
@@ -35,7 +50,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(Geom g, Coef<T> C, const T 
                                                      double *__restrict__ partials,
                                                      const uint8_t *__restrict__ cls) {
   __shared__ double lds[kBlock / 64 + 1];
-  const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t id = (int64_t)xcd_block() * kBlock + threadIdx.x;
   double ss = 0.0;
   if (id < g.nn && cls && (cls[id] == 0 || cls[id] > 3)) {
     for (int c = 0; c < DIM; ++c) r[c * g.nn + id] = T(0);
@@ -69,7 +84,7 @@ __global__ __launch_bounds__(kBlock) void k_residual_cast(Geom g, Coef<double> C
                                                           const double *__restrict__ f,
                                                           float *__restrict__ r32,
                                                           const double *__restrict__ ss) {
-  const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t id = (int64_t)xcd_block() * kBlock + threadIdx.x;
   if (id >= g.nn) return;
   const double sn = sqrt(*ss);
   const double inv_s = sn > 0.0 ? 1.0 / sn : 0.0;
@@ -95,7 +110,7 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(Geom g, Coef<T> C, const T *_
                                                    const T *__restrict__ f,
                                                    T *__restrict__ u_out, T omega,
                                                    const uint8_t *__restrict__ cls) {
-  const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t id = (int64_t)xcd_block() * kBlock + threadIdx.x;
   if (id >= g.nn) return;
   if (cls && cls[id] != 1) {
     for (int c = 0; c < DIM; ++c) u_out[c * g.nn + id] = u[c * g.nn + id];
@@ -125,7 +140,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_half(Geom g, Coef<T> C, const T *
                                                     T *__restrict__ u_out, T omega, int colour,
                                                     const uint8_t *__restrict__ cls) {
   const int npx = (g.nx + 1) >> 1;
-  const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t tid = (int64_t)xcd_block() * kBlock + threadIdx.x;
   const int64_t total = (int64_t)npx * g.ny * g.nz;
   if (tid >= total) return;
   const uint32_t rest = g.fpx.div((uint32_t)tid);
@@ -135,13 +150,12 @@ __global__ __launch_bounds__(kBlock) void k_rb_half(Geom g, Coef<T> C, const T *
   const int par = (colour + j + k) & 1;
   const int iu = 2 * p + par, ic = 2 * p + 1 - par;
   const int64_t row = (int64_t)g.nx * (j + (int64_t)g.ny * k);
-  if (ic < g.nx) {
-#pragma unroll
-    for (int c = 0; c < DIM; ++c) u_out[c * g.nn + row + ic] = u[c * g.nn + row + ic];
-  }
+  // both nodes of the pair are stored back to back at the end, so that every
+  // written line is complete in L2 when it leaves
+  T nv[3] = {T(0), T(0), T(0)};
   if (iu < g.nx && cls && cls[row + iu] != 1) {
 #pragma unroll
-    for (int c = 0; c < DIM; ++c) u_out[c * g.nn + row + iu] = u[c * g.nn + row + iu];
+    for (int c = 0; c < DIM; ++c) nv[c] = u[c * g.nn + row + iu];
   } else if (iu < g.nx) {
     T out[3], dg[3];
     node_stencil<T, DIM>(g, C, psi, u, iu, j, k, out, dg);
@@ -149,8 +163,13 @@ __global__ __launch_bounds__(kBlock) void k_rb_half(Geom g, Coef<T> C, const T *
     for (int c = 0; c < DIM; ++c) {
       const int64_t q = c * g.nn + row + iu;
       const T uc = u[q];
-      u_out[q] = is_dirichlet(g, iu, j, k, c) ? uc : uc + omega * (f[q] - out[c]) / dg[c];
+      nv[c] = is_dirichlet(g, iu, j, k, c) ? uc : uc + omega * (f[q] - out[c]) / dg[c];
     }
+  }
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) {
+    if (iu < g.nx) u_out[c * g.nn + row + iu] = nv[c];
+    if (ic < g.nx) u_out[c * g.nn + row + ic] = u[c * g.nn + row + ic];
   }
 }
 
@@ -161,7 +180,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_half(Geom g, Coef<T> C, const T *
 template <typename T, int DIM>
 __global__ __launch_bounds__(kBlock) void k_restrict(Geom gf, Geom gc, const T *__restrict__ r,
                                                      T *__restrict__ fc) {
-  const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t id = (int64_t)xcd_block() * kBlock + threadIdx.x;
   if (id >= gc.nn) return;
   int I, J, K;
   node_ijk(gc, id, I, J, K);
@@ -197,7 +216,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict(Geom gf, Geom gc, const T *
 template <typename T, int DIM>
 __global__ __launch_bounds__(kBlock) void k_prolong_add(Geom gf, Geom gc, const T *__restrict__ e,
                                                         T *__restrict__ u) {
-  const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t id = (int64_t)xcd_block() * kBlock + threadIdx.x;
   if (id >= gf.nn) return;
   int i, j, k;
   node_ijk(gf, id, i, j, k);
@@ -453,7 +472,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_dot(Geom g, Coef<double> C,
                                                       double *__restrict__ q,
                                                       double *__restrict__ partials) {
   __shared__ double lds[kBlock / 64 + 1];
-  const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t id = (int64_t)xcd_block() * kBlock + threadIdx.x;
   double ss = 0.0;
   if (id < g.nn) {
     int i, j, k;
@@ -1032,7 +1051,7 @@ __global__ __launch_bounds__(kBlock) void k_sensitivity(Geom g, double lame, dou
                                                         const double *__restrict__ design,
                                                         int chain, double fl,
                                                         double *__restrict__ out) {
-  const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t id = (int64_t)xcd_block() * kBlock + threadIdx.x;
   if (id >= g.nc) return;
   int ci, cj, ck;
   cell_ijk(g, id, ci, cj, ck);
@@ -1149,7 +1168,7 @@ static bool use_tiled(const Level &L) {
 }
 
 int stencil_partials(const Level &L) {
-  return use_tiled(L) ? tiled_partials(L) : num_blocks(L.g.nn);
+  return use_tiled(L) ? tiled_partials(L) : grid_blocks(L.g.nn);
 }
 
 static int fill_blocks(int64_t n) {
@@ -1160,8 +1179,8 @@ static int fill_blocks(int64_t n) {
 template <typename T>
 hipError_t launch_apply(const Level &L, const T *psi, const Coef<T> &C, const T *u, T *y,
                         hipStream_t st) {
-  if (L.g.dim == 3) SBM_LAUNCH((k_apply<T, 3>), num_blocks(L.g.nn), kBlock, st, L.g, C, psi, u, y);
-  SBM_LAUNCH((k_apply<T, 2>), num_blocks(L.g.nn), kBlock, st, L.g, C, psi, u, y);
+  if (L.g.dim == 3) SBM_LAUNCH((k_apply<T, 3>), grid_blocks(L.g.nn), kBlock, st, L.g, C, psi, u, y);
+  SBM_LAUNCH((k_apply<T, 2>), grid_blocks(L.g.nn), kBlock, st, L.g, C, psi, u, y);
 }
 
 template <typename T>
@@ -1170,18 +1189,18 @@ hipError_t launch_residual(const Level &L, const T *psi, const Coef<T> &C, const
                            const uint8_t *cls) {
   if (use_tiled(L)) return launch_residual_tiled<T>(L, psi, C, u, f, r, partials, st, cls);
   if (L.g.dim == 3)
-    SBM_LAUNCH((k_residual<T, 3>), num_blocks(L.g.nn), kBlock, st, L.g, C, psi, u, f, r, partials,
+    SBM_LAUNCH((k_residual<T, 3>), grid_blocks(L.g.nn), kBlock, st, L.g, C, psi, u, f, r, partials,
                cls);
-  SBM_LAUNCH((k_residual<T, 2>), num_blocks(L.g.nn), kBlock, st, L.g, C, psi, u, f, r, partials,
+  SBM_LAUNCH((k_residual<T, 2>), grid_blocks(L.g.nn), kBlock, st, L.g, C, psi, u, f, r, partials,
              cls);
 }
 
 hipError_t launch_residual_cast(const Level &L, const double *u, const double *f, float *r32,
                                 const double *ss, hipStream_t st) {
   if (L.g.dim == 3)
-    SBM_LAUNCH((k_residual_cast<3>), num_blocks(L.g.nn), kBlock, st, L.g, L.c64, L.psi64, u, f,
+    SBM_LAUNCH((k_residual_cast<3>), grid_blocks(L.g.nn), kBlock, st, L.g, L.c64, L.psi64, u, f,
                r32, ss);
-  SBM_LAUNCH((k_residual_cast<2>), num_blocks(L.g.nn), kBlock, st, L.g, L.c64, L.psi64, u, f, r32,
+  SBM_LAUNCH((k_residual_cast<2>), grid_blocks(L.g.nn), kBlock, st, L.g, L.c64, L.psi64, u, f, r32,
              ss);
 }
 
@@ -1189,9 +1208,9 @@ template <typename T>
 hipError_t launch_jacobi(const Level &L, const T *psi, const Coef<T> &C, const T *u, const T *f,
                          T *u_out, double omega, hipStream_t st, const uint8_t *cls) {
   if (L.g.dim == 3)
-    SBM_LAUNCH((k_jacobi<T, 3>), num_blocks(L.g.nn), kBlock, st, L.g, C, psi, u, f, u_out,
+    SBM_LAUNCH((k_jacobi<T, 3>), grid_blocks(L.g.nn), kBlock, st, L.g, C, psi, u, f, u_out,
                (T)omega, cls);
-  SBM_LAUNCH((k_jacobi<T, 2>), num_blocks(L.g.nn), kBlock, st, L.g, C, psi, u, f, u_out, (T)omega,
+  SBM_LAUNCH((k_jacobi<T, 2>), grid_blocks(L.g.nn), kBlock, st, L.g, C, psi, u, f, u_out, (T)omega,
              cls);
 }
 
@@ -1200,24 +1219,23 @@ hipError_t launch_rb_half(const Level &L, const T *psi, const Coef<T> &C, const 
                           const T *f, T *u_out, double omega, int colour, hipStream_t st,
                           const uint8_t *cls) {
   const int64_t pairs = (int64_t)((L.g.nx + 1) / 2) * L.g.ny * L.g.nz;
+  const int nb = grid_blocks(pairs);
   if (L.g.dim == 3)
-    SBM_LAUNCH((k_rb_half<T, 3>), num_blocks(pairs), kBlock, st, L.g, C, psi, u, f, u_out,
-               (T)omega, colour, cls);
-  SBM_LAUNCH((k_rb_half<T, 2>), num_blocks(pairs), kBlock, st, L.g, C, psi, u, f, u_out, (T)omega,
-             colour, cls);
+    SBM_LAUNCH((k_rb_half<T, 3>), nb, kBlock, st, L.g, C, psi, u, f, u_out, (T)omega, colour, cls);
+  SBM_LAUNCH((k_rb_half<T, 2>), nb, kBlock, st, L.g, C, psi, u, f, u_out, (T)omega, colour, cls);
 }
 
 template <typename T>
 hipError_t launch_restrict(const Level &F, const Level &Cl, const T *r, T *fc, hipStream_t st) {
-  if (F.g.dim == 3) SBM_LAUNCH((k_restrict<T, 3>), num_blocks(Cl.g.nn), kBlock, st, F.g, Cl.g, r, fc);
-  SBM_LAUNCH((k_restrict<T, 2>), num_blocks(Cl.g.nn), kBlock, st, F.g, Cl.g, r, fc);
+  if (F.g.dim == 3) SBM_LAUNCH((k_restrict<T, 3>), grid_blocks(Cl.g.nn), kBlock, st, F.g, Cl.g, r, fc);
+  SBM_LAUNCH((k_restrict<T, 2>), grid_blocks(Cl.g.nn), kBlock, st, F.g, Cl.g, r, fc);
 }
 
 template <typename T>
 hipError_t launch_prolong_add(const Level &F, const Level &Cl, const T *e, T *u, hipStream_t st) {
   if (F.g.dim == 3)
-    SBM_LAUNCH((k_prolong_add<T, 3>), num_blocks(F.g.nn), kBlock, st, F.g, Cl.g, e, u);
-  SBM_LAUNCH((k_prolong_add<T, 2>), num_blocks(F.g.nn), kBlock, st, F.g, Cl.g, e, u);
+    SBM_LAUNCH((k_prolong_add<T, 3>), grid_blocks(F.g.nn), kBlock, st, F.g, Cl.g, e, u);
+  SBM_LAUNCH((k_prolong_add<T, 2>), grid_blocks(F.g.nn), kBlock, st, F.g, Cl.g, e, u);
 }
 
 template <typename T>
@@ -1279,8 +1297,8 @@ hipError_t launch_apply_dot(const Level &L, const double *p, double *q, double *
                            hipStream_t st) {
   if (use_tiled(L)) return launch_apply_dot_tiled(L, p, q, partials, st);
   if (L.g.dim == 3)
-    SBM_LAUNCH((k_apply_dot<3>), num_blocks(L.g.nn), kBlock, st, L.g, L.c64, L.psi64, p, q, partials);
-  SBM_LAUNCH((k_apply_dot<2>), num_blocks(L.g.nn), kBlock, st, L.g, L.c64, L.psi64, p, q, partials);
+    SBM_LAUNCH((k_apply_dot<3>), grid_blocks(L.g.nn), kBlock, st, L.g, L.c64, L.psi64, p, q, partials);
+  SBM_LAUNCH((k_apply_dot<2>), grid_blocks(L.g.nn), kBlock, st, L.g, L.c64, L.psi64, p, q, partials);
 }
 
 hipError_t launch_cg_update(const Level &L, double *x, double *r, const double *p, const double *q,
@@ -1385,9 +1403,9 @@ hipError_t launch_sensitivity(const Level &L, double lam, double mu, const Tract
                               const double *design, int chain, double psi_floor, double *g,
                               hipStream_t st) {
   if (L.g.dim == 3)
-    SBM_LAUNCH((k_sensitivity<3>), num_blocks(L.g.nc), kBlock, st, L.g, lam, mu, L.h[0], L.h[1],
+    SBM_LAUNCH((k_sensitivity<3>), grid_blocks(L.g.nc), kBlock, st, L.g, lam, mu, L.h[0], L.h[1],
                L.h[2], tr, u, adj, lam_scale, design, chain, psi_floor, g);
-  SBM_LAUNCH((k_sensitivity<2>), num_blocks(L.g.nc), kBlock, st, L.g, lam, mu, L.h[0], L.h[1],
+  SBM_LAUNCH((k_sensitivity<2>), grid_blocks(L.g.nc), kBlock, st, L.g, lam, mu, L.h[0], L.h[1],
              L.h[2], tr, u, adj, lam_scale, design, chain, psi_floor, g);
 }
 

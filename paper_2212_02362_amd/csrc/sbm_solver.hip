@@ -245,7 +245,7 @@ static size_t carve(sbm_ctx *c, char *base) {
     L.e32 = cv.take<float>(nv);
     L.f32 = cv.take<float>(nv);
     L.t32 = cv.take<float>(nv);
-    maxblocks = std::max<int64_t>(maxblocks, num_blocks(L.g.nn));
+    maxblocks = std::max<int64_t>(maxblocks, grid_blocks(L.g.nn));
     maxblocks = std::max<int64_t>(maxblocks, num_blocks(L.g.nc));
   }
   c->x0 = cv.take<double>((int64_t)d * c->L[0].g.nn);
