@@ -757,10 +757,30 @@ struct BotRed {
   int phase;
 };
 
+// One 32-bit half of a double moved across lanes by a DPP control (lanes
+// whose source lies outside the row read zero).
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWMASK, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWMASK, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a wave, returned in every lane, without LDS
+// traffic: prefix sums inside each 16-lane row (row shifts 1, 2, 4, 8), the
+// row totals carried into rows 1 and 3 and then into rows 2 and 3 (row
+// broadcasts of lanes 15 and 31), the total read from lane 63.  The latency
+// of the bottom CG is dominated by these reductions.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+  v += dpp_move<0x111, 0xf>(v);  // row_shr:1
+  v += dpp_move<0x112, 0xf>(v);  // row_shr:2
+  v += dpp_move<0x114, 0xf>(v);  // row_shr:4
+  v += dpp_move<0x118, 0xf>(v);  // row_shr:8
+  v += dpp_move<0x142, 0xa>(v);  // row_bcast:15
+  v += dpp_move<0x143, 0xc>(v);  // row_bcast:31
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
 }
 
 __device__ __forceinline__ double bot_allsum(double v, BotRed &R) {
@@ -880,7 +900,7 @@ __device__ int bot_cg(const Geom &g, const Coef<T> &C, const T *psi_l, T *p_l, T
 }
 
 // FP64 bottom: x += CG solution of K_FF d = (f - K x)_F.
-template <int DIM>
+template <int DIM, int Q>
 __global__ __launch_bounds__(kBotThreads) void k_bottom_lds64(Geom g, Coef<double> C,
                                                        const double *__restrict__ psi,
                                                        const double *__restrict__ f, double *x,
@@ -892,11 +912,11 @@ __global__ __launch_bounds__(kBotThreads) void k_bottom_lds64(Geom g, Coef<doubl
   double *psi_l = smem;
   double *p_l = smem + ((g.nc + 1) & ~(int64_t)1);
   for (int64_t q = threadIdx.x; q < g.nc; q += blockDim.x) psi_l[q] = psi[q];
-  bool dir[kBotQ][3];
-  int cijk[kBotQ][3];
-  double r[kBotQ][3], dd[kBotQ][3], xv[kBotQ][3];
+  bool dir[Q][3];
+  int cijk[Q][3];
+  double r[Q][3], dd[Q][3], xv[Q][3];
 #pragma unroll
-  for (int q = 0; q < kBotQ; ++q) {
+  for (int q = 0; q < Q; ++q) {
     const int64_t id = threadIdx.x + (int64_t)q * blockDim.x;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -915,7 +935,7 @@ __global__ __launch_bounds__(kBotThreads) void k_bottom_lds64(Geom g, Coef<doubl
   }
   __syncthreads();
 #pragma unroll
-  for (int q = 0; q < kBotQ; ++q) {
+  for (int q = 0; q < Q; ++q) {
     const int64_t id = threadIdx.x + (int64_t)q * blockDim.x;
     if (id >= n) continue;
     double out[3], dg[3];
@@ -924,9 +944,9 @@ __global__ __launch_bounds__(kBotThreads) void k_bottom_lds64(Geom g, Coef<doubl
     for (int c = 0; c < DIM; ++c) r[q][c] = dir[q][c] ? 0.0 : f[c * n + id] - out[c];
   }
   __syncthreads();
-  const int it = bot_cg<double, DIM, kBotQ>(g, C, psi_l, p_l, r, dd, dir, cijk, rtol, maxit, R);
+  const int it = bot_cg<double, DIM, Q>(g, C, psi_l, p_l, r, dd, dir, cijk, rtol, maxit, R);
 #pragma unroll
-  for (int q = 0; q < kBotQ; ++q) {
+  for (int q = 0; q < Q; ++q) {
     const int64_t id = threadIdx.x + (int64_t)q * blockDim.x;
     if (id >= n) continue;
 #pragma unroll
@@ -941,7 +961,7 @@ __global__ __launch_bounds__(kBotThreads) void k_bottom_lds64(Geom g, Coef<doubl
 // feeds the FP64 residual stencil.
 constexpr int kBotQMixed = 2;
 
-template <int DIM>
+template <int DIM, int Q>
 __global__ __launch_bounds__(kBotThreads) void k_bottom_lds_mixed(Geom g, Coef<double> C64,
                                                                   Coef<float> C32,
                                                                   const double *__restrict__ psi64,
@@ -949,7 +969,6 @@ __global__ __launch_bounds__(kBotThreads) void k_bottom_lds_mixed(Geom g, Coef<d
                                                                   const float *__restrict__ b32,
                                                                   float *e32, double rtol,
                                                                   int maxit, int *iters) {
-  constexpr int Q = kBotQMixed;
   extern __shared__ double smem[];
   __shared__ double red[64];
   BotRed R{red, 0};
@@ -1357,13 +1376,22 @@ hipError_t launch_bottom_cg(const Level &L, const T *psi, const Coef<T> &C, cons
     const size_t by = bottom_lds64_bytes(L.g);
     if (bottom_fits_lds(L.g, by)) {
       const int nt = bottom_threads(L.g.nn);
+      const bool one = L.g.nn <= kBotThreads;  // one node per thread: fewer registers
       (void)hipGetLastError();
       if (L.g.dim == 3) {
-        hipLaunchKernelGGL((k_bottom_lds64<3>), dim3(1), dim3(nt), by, st, L.g, C, psi, f, x,
-                           rtol, maxit, iters);
+        if (one)
+          hipLaunchKernelGGL((k_bottom_lds64<3, 1>), dim3(1), dim3(nt), by, st, L.g, C, psi, f, x,
+                             rtol, maxit, iters);
+        else
+          hipLaunchKernelGGL((k_bottom_lds64<3, kBotQ>), dim3(1), dim3(nt), by, st, L.g, C, psi, f,
+                             x, rtol, maxit, iters);
       } else {
-        hipLaunchKernelGGL((k_bottom_lds64<2>), dim3(1), dim3(nt), by, st, L.g, C, psi, f, x,
-                           rtol, maxit, iters);
+        if (one)
+          hipLaunchKernelGGL((k_bottom_lds64<2, 1>), dim3(1), dim3(nt), by, st, L.g, C, psi, f, x,
+                             rtol, maxit, iters);
+        else
+          hipLaunchKernelGGL((k_bottom_lds64<2, kBotQ>), dim3(1), dim3(nt), by, st, L.g, C, psi, f,
+                             x, rtol, maxit, iters);
       }
       return hipGetLastError();
     }
@@ -1381,13 +1409,22 @@ hipError_t launch_bottom_mixed(const Level &L, const float *b32, float *e32, dou
   const size_t by = bottom_lds_mixed_bytes(L.g);
   if (L.g.nn <= (int64_t)kBotQMixed * kBotThreads && by <= 64 * 1024) {
     const int nt = bottom_threads(L.g.nn);
+    const bool one = L.g.nn <= kBotThreads;  // one node per thread: fewer registers
     (void)hipGetLastError();
     if (L.g.dim == 3) {
-      hipLaunchKernelGGL((k_bottom_lds_mixed<3>), dim3(1), dim3(nt), by, st, L.g, L.c64, L.c32,
-                         L.psi64, L.psi32, b32, e32, rtol, maxit, iters);
+      if (one)
+        hipLaunchKernelGGL((k_bottom_lds_mixed<3, 1>), dim3(1), dim3(nt), by, st, L.g, L.c64,
+                           L.c32, L.psi64, L.psi32, b32, e32, rtol, maxit, iters);
+      else
+        hipLaunchKernelGGL((k_bottom_lds_mixed<3, kBotQMixed>), dim3(1), dim3(nt), by, st, L.g,
+                           L.c64, L.c32, L.psi64, L.psi32, b32, e32, rtol, maxit, iters);
     } else {
-      hipLaunchKernelGGL((k_bottom_lds_mixed<2>), dim3(1), dim3(nt), by, st, L.g, L.c64, L.c32,
-                         L.psi64, L.psi32, b32, e32, rtol, maxit, iters);
+      if (one)
+        hipLaunchKernelGGL((k_bottom_lds_mixed<2, 1>), dim3(1), dim3(nt), by, st, L.g, L.c64,
+                           L.c32, L.psi64, L.psi32, b32, e32, rtol, maxit, iters);
+      else
+        hipLaunchKernelGGL((k_bottom_lds_mixed<2, kBotQMixed>), dim3(1), dim3(nt), by, st, L.g,
+                           L.c64, L.c32, L.psi64, L.psi32, b32, e32, rtol, maxit, iters);
     }
     return hipGetLastError();
   }
