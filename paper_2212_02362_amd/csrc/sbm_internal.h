@@ -114,9 +114,11 @@ template <typename T>
 hipError_t launch_bottom_cg(const Level &L, const T *psi, const Coef<T> &C, const T *f, T *x,
                             T *r, T *p, T *Ap, double rtol, int maxit, int *iters,
                             hipStream_t st);
-hipError_t launch_bottom_mixed(const Level &L, const float *b32, float *e32, double *x64,
-                               double *r64, float *r32, float *p32, float *Ap32, float *d32,
-                               double rtol, int maxit, int *iters, hipStream_t st);
+// Bottom solve of the FP32 cycle: the FP64 CG on the FP32 load, the result
+// returned in FP32 (f64 / x64 / r / p / Ap: FP64 scratch of the bottom size).
+hipError_t launch_bottom_f32io(const Level &L, const float *f32, float *x32, double *f64,
+                               double *x64, double *r, double *p, double *Ap, double rtol,
+                               int maxit, int *iters, hipStream_t st);
 hipError_t launch_sensitivity(const Level &L, double lam, double mu, const Traction &tr,
                               const double *u, const double *adj, double lam_scale,
                               const double *design, int chain, double psi_floor, double *g,

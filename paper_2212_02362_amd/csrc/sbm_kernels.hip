@@ -253,6 +253,14 @@ __global__ __launch_bounds__(kBlock) void k_copy(const T *__restrict__ s, T *__r
     d[q] = s[q];
 }
 
+template <typename S, typename D>
+__global__ __launch_bounds__(kBlock) void k_convert(const S *__restrict__ s, D *__restrict__ d,
+                                                    int64_t n) {
+  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < n;
+       q += (int64_t)gridDim.x * kBlock)
+    d[q] = (D)s[q];
+}
+
 // u += s * e32 on free DOF (FP64 correction of the mixed cycle), s = sqrt(*ss).
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_correct(Geom g, double *__restrict__ u,
@@ -681,64 +689,6 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom_cg(Geom g, Coef<T> C,
   if (threadIdx.x == 0 && iters) *iters = it;
 }
 
-// Bottom solve of the mixed cycle: FP32 CG inside FP64 iterative refinement.
-// x64 accumulates the solution of K x = b (b = FP32 bottom load) until the
-// FP64 residual meets rtol; the result is returned in e32.
-template <int DIM>
-__global__ __launch_bounds__(kBottomThreads) void k_bottom_mixed(
-    Geom g, Coef<double> C64, Coef<float> C32, const double *__restrict__ psi64,
-    const float *__restrict__ psi32, const float *__restrict__ b32, float *e32, double *x64,
-    double *r64, float *r32, float *p32, float *Ap32, float *d32, double rtol, int maxit,
-    int *iters) {
-  __shared__ double lds[kBottomThreads / 64 + 1];
-  const int64_t n = g.nn;
-  double loc = 0.0;
-  for (int64_t id = threadIdx.x; id < n; id += blockDim.x) {
-    int i, j, k;
-    node_ijk(g, id, i, j, k);
-    for (int c = 0; c < DIM; ++c) {
-      x64[c * n + id] = 0.0;
-      if (!is_dirichlet(g, i, j, k, c)) loc += (double)b32[c * n + id] * (double)b32[c * n + id];
-    }
-  }
-  const double bnorm = sqrt(block_allsum(loc, lds));
-  int total = 0;
-  for (int outer = 0; outer < 40 && bnorm > 0.0; ++outer) {
-    __syncthreads();
-    double rl = 0.0;
-    for (int64_t id = threadIdx.x; id < n; id += blockDim.x) {
-      int i, j, k;
-      node_ijk(g, id, i, j, k);
-      double out[3], dg[3];
-      node_stencil<double, DIM>(g, C64, psi64, x64, i, j, k, out, dg);
-      for (int c = 0; c < DIM; ++c) {
-        const int64_t q = c * n + id;
-        const double v = is_dirichlet(g, i, j, k, c) ? 0.0 : (double)b32[q] - out[c];
-        r64[q] = v;
-        rl += v * v;
-      }
-    }
-    const double rn = sqrt(block_allsum(rl, lds));
-    if (rn <= rtol * bnorm || total >= maxit) break;
-    for (int64_t id = threadIdx.x; id < n; id += blockDim.x)
-      for (int c = 0; c < DIM; ++c) {
-        const int64_t q = c * n + id;
-        r32[q] = (float)(r64[q] / rn);
-        d32[q] = 0.0f;
-      }
-    __syncthreads();
-    total += cg_core<float, DIM>(g, C32, psi32, d32, r32, p32, Ap32, 1e-5, maxit - total, lds);
-    for (int64_t id = threadIdx.x; id < n; id += blockDim.x)
-      for (int c = 0; c < DIM; ++c) {
-        const int64_t q = c * n + id;
-        x64[q] += rn * (double)d32[q];
-      }
-  }
-  __syncthreads();
-  for (int64_t id = threadIdx.x; id < n; id += blockDim.x)
-    for (int c = 0; c < DIM; ++c) e32[c * n + id] = (float)x64[c * n + id];
-  if (threadIdx.x == 0 && iters) *iters = total;
-}
 
 // ---------------------------------------------------- LDS-resident bottom --
 //
@@ -899,11 +849,12 @@ __device__ int bot_cg(const Geom &g, const Coef<T> &C, const T *psi_l, T *p_l, T
   return it;
 }
 
-// FP64 bottom: x += CG solution of K_FF d = (f - K x)_F.
-template <int DIM, int Q>
+// FP64 bottom: x += CG solution of K_FF d = (f - K x)_F.  f and x are FP64,
+// or FP32 in the mixed cycle (read into and written from the FP64 solve).
+template <int DIM, int Q, typename IO>
 __global__ __launch_bounds__(kBotThreads) void k_bottom_lds64(Geom g, Coef<double> C,
                                                        const double *__restrict__ psi,
-                                                       const double *__restrict__ f, double *x,
+                                                       const IO *__restrict__ f, IO *x,
                                                        double rtol, int maxit, int *iters) {
   extern __shared__ double smem[];
   __shared__ double red[64];
@@ -929,7 +880,7 @@ __global__ __launch_bounds__(kBotThreads) void k_bottom_lds64(Geom g, Coef<doubl
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
       dir[q][c] = is_dirichlet(g, cijk[q][0], cijk[q][1], cijk[q][2], c);
-      xv[q][c] = x[c * n + id];
+      xv[q][c] = (double)x[c * n + id];
       p_l[c * n + id] = xv[q][c];
     }
   }
@@ -941,7 +892,7 @@ __global__ __launch_bounds__(kBotThreads) void k_bottom_lds64(Geom g, Coef<doubl
     double out[3], dg[3];
     node_stencil<double, DIM>(g, C, psi_l, p_l, cijk[q][0], cijk[q][1], cijk[q][2], out, dg);
 #pragma unroll
-    for (int c = 0; c < DIM; ++c) r[q][c] = dir[q][c] ? 0.0 : f[c * n + id] - out[c];
+    for (int c = 0; c < DIM; ++c) r[q][c] = dir[q][c] ? 0.0 : (double)f[c * n + id] - out[c];
   }
   __syncthreads();
   const int it = bot_cg<double, DIM, Q>(g, C, psi_l, p_l, r, dd, dir, cijk, rtol, maxit, R);
@@ -951,105 +902,11 @@ __global__ __launch_bounds__(kBotThreads) void k_bottom_lds64(Geom g, Coef<doubl
     if (id >= n) continue;
 #pragma unroll
     for (int c = 0; c < DIM; ++c)
-      if (!dir[q][c]) x[c * n + id] = xv[q][c] + dd[q][c];
+      if (!dir[q][c]) x[c * n + id] = (IO)(xv[q][c] + dd[q][c]);
   }
   if (threadIdx.x == 0 && iters) *iters = it;
 }
 
-// Mixed bottom: FP32 CG (LDS) inside FP64 iterative refinement.  The FP64
-// iterate lives in LDS (each thread updates its own entries), where it also
-// feeds the FP64 residual stencil.
-constexpr int kBotQMixed = 2;
-
-template <int DIM, int Q>
-__global__ __launch_bounds__(kBotThreads) void k_bottom_lds_mixed(Geom g, Coef<double> C64,
-                                                                  Coef<float> C32,
-                                                                  const double *__restrict__ psi64,
-                                                                  const float *__restrict__ psi32,
-                                                                  const float *__restrict__ b32,
-                                                                  float *e32, double rtol,
-                                                                  int maxit, int *iters) {
-  extern __shared__ double smem[];
-  __shared__ double red[64];
-  BotRed R{red, 0};
-  const int64_t n = g.nn;
-  const int64_t nc2 = (g.nc + 1) & ~(int64_t)1;
-  double *psi_l = smem;
-  double *x_l = smem + nc2;
-  float *psi32_l = (float *)(x_l + DIM * n);
-  float *p_l = psi32_l + nc2;
-  for (int64_t q = threadIdx.x; q < g.nc; q += blockDim.x) {
-    psi_l[q] = psi64[q];
-    psi32_l[q] = psi32[q];
-  }
-  bool dir[Q][3];
-  int cijk[Q][3];
-  float r32[Q][3], d32[Q][3];
-  double loc = 0.0;
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int64_t id = threadIdx.x + (int64_t)q * blockDim.x;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      dir[q][c] = true;
-      r32[q][c] = d32[q][c] = 0.0f;
-      cijk[q][c] = 0;
-    }
-    if (id >= n) continue;
-    node_ijk(g, id, cijk[q][0], cijk[q][1], cijk[q][2]);
-#pragma unroll
-    for (int c = 0; c < DIM; ++c) {
-      dir[q][c] = is_dirichlet(g, cijk[q][0], cijk[q][1], cijk[q][2], c);
-      x_l[c * n + id] = 0.0;
-      if (!dir[q][c]) loc += (double)b32[c * n + id] * (double)b32[c * n + id];
-    }
-  }
-  const double bnorm = sqrt(bot_allsum(loc, R));  // its barrier also publishes x_l
-  int total = 0;
-  for (int outer = 0; outer < 40 && bnorm > 0.0; ++outer) {
-    double r64[Q][3];
-    double rl = 0.0;
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int64_t id = threadIdx.x + (int64_t)q * blockDim.x;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) r64[q][c] = 0.0;
-      if (id >= n) continue;
-      double out[3], dg[3];
-      node_stencil<double, DIM>(g, C64, psi_l, x_l, cijk[q][0], cijk[q][1], cijk[q][2], out, dg);
-#pragma unroll
-      for (int c = 0; c < DIM; ++c) {
-        r64[q][c] = dir[q][c] ? 0.0 : (double)b32[c * n + id] - out[c];
-        rl += r64[q][c] * r64[q][c];
-      }
-    }
-    const double rn = sqrt(bot_allsum(rl, R));  // barrier: every read of x_l is done
-    if (rn <= rtol * bnorm || total >= maxit) break;
-#pragma unroll
-    for (int q = 0; q < Q; ++q)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) r32[q][c] = (float)(r64[q][c] / rn);
-    total += bot_cg<float, DIM, Q>(g, C32, psi32_l, p_l, r32, d32, dir, cijk, 1e-5, maxit - total,
-                                   R);
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int64_t id = threadIdx.x + (int64_t)q * blockDim.x;
-      if (id >= n) continue;
-#pragma unroll
-      for (int c = 0; c < DIM; ++c)
-        if (!dir[q][c]) x_l[c * n + id] += rn * (double)d32[q][c];
-    }
-    __syncthreads();  // updated x_l visible to the next residual
-  }
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int64_t id = threadIdx.x + (int64_t)q * blockDim.x;
-    if (id >= n) continue;
-#pragma unroll
-    for (int c = 0; c < DIM; ++c) e32[c * n + id] = (float)x_l[c * n + id];
-  }
-  if (threadIdx.x == 0 && iters) *iters = total;
-}
 
 // ------------------------------------------------------------ sensitivity --
 
@@ -1363,10 +1220,6 @@ static size_t bottom_lds64_bytes(const Geom &g) {
   return sizeof(double) * (size_t)(((g.nc + 1) & ~(int64_t)1) + g.dim * g.nn);
 }
 
-static size_t bottom_lds_mixed_bytes(const Geom &g) {
-  const size_t nc2 = (size_t)((g.nc + 1) & ~(int64_t)1);
-  return sizeof(double) * (nc2 + g.dim * g.nn) + sizeof(float) * (nc2 + g.dim * g.nn);
-}
 
 template <typename T>
 hipError_t launch_bottom_cg(const Level &L, const T *psi, const Coef<T> &C, const T *f, T *x,
@@ -1380,17 +1233,17 @@ hipError_t launch_bottom_cg(const Level &L, const T *psi, const Coef<T> &C, cons
       (void)hipGetLastError();
       if (L.g.dim == 3) {
         if (one)
-          hipLaunchKernelGGL((k_bottom_lds64<3, 1>), dim3(1), dim3(nt), by, st, L.g, C, psi, f, x,
+          hipLaunchKernelGGL((k_bottom_lds64<3, 1, double>), dim3(1), dim3(nt), by, st, L.g, C, psi, f, x,
                              rtol, maxit, iters);
         else
-          hipLaunchKernelGGL((k_bottom_lds64<3, kBotQ>), dim3(1), dim3(nt), by, st, L.g, C, psi, f,
+          hipLaunchKernelGGL((k_bottom_lds64<3, kBotQ, double>), dim3(1), dim3(nt), by, st, L.g, C, psi, f,
                              x, rtol, maxit, iters);
       } else {
         if (one)
-          hipLaunchKernelGGL((k_bottom_lds64<2, 1>), dim3(1), dim3(nt), by, st, L.g, C, psi, f, x,
+          hipLaunchKernelGGL((k_bottom_lds64<2, 1, double>), dim3(1), dim3(nt), by, st, L.g, C, psi, f, x,
                              rtol, maxit, iters);
         else
-          hipLaunchKernelGGL((k_bottom_lds64<2, kBotQ>), dim3(1), dim3(nt), by, st, L.g, C, psi, f,
+          hipLaunchKernelGGL((k_bottom_lds64<2, kBotQ, double>), dim3(1), dim3(nt), by, st, L.g, C, psi, f,
                              x, rtol, maxit, iters);
       }
       return hipGetLastError();
@@ -1403,36 +1256,46 @@ hipError_t launch_bottom_cg(const Level &L, const T *psi, const Coef<T> &C, cons
              iters);
 }
 
-hipError_t launch_bottom_mixed(const Level &L, const float *b32, float *e32, double *x64,
-                               double *r64, float *r32, float *p32, float *Ap32, float *d32,
-                               double rtol, int maxit, int *iters, hipStream_t st) {
-  const size_t by = bottom_lds_mixed_bytes(L.g);
-  if (L.g.nn <= (int64_t)kBotQMixed * kBotThreads && by <= 64 * 1024) {
+hipError_t launch_bottom_f32io(const Level &L, const float *f32, float *x32, double *f64,
+                               double *x64, double *r, double *p, double *Ap, double rtol,
+                               int maxit, int *iters, hipStream_t st) {
+  const size_t by = bottom_lds64_bytes(L.g);
+  if (bottom_fits_lds(L.g, by)) {
     const int nt = bottom_threads(L.g.nn);
-    const bool one = L.g.nn <= kBotThreads;  // one node per thread: fewer registers
+    const bool one = L.g.nn <= kBotThreads;
     (void)hipGetLastError();
     if (L.g.dim == 3) {
       if (one)
-        hipLaunchKernelGGL((k_bottom_lds_mixed<3, 1>), dim3(1), dim3(nt), by, st, L.g, L.c64,
-                           L.c32, L.psi64, L.psi32, b32, e32, rtol, maxit, iters);
+        hipLaunchKernelGGL((k_bottom_lds64<3, 1, float>), dim3(1), dim3(nt), by, st, L.g, L.c64,
+                           L.psi64, f32, x32, rtol, maxit, iters);
       else
-        hipLaunchKernelGGL((k_bottom_lds_mixed<3, kBotQMixed>), dim3(1), dim3(nt), by, st, L.g,
-                           L.c64, L.c32, L.psi64, L.psi32, b32, e32, rtol, maxit, iters);
+        hipLaunchKernelGGL((k_bottom_lds64<3, kBotQ, float>), dim3(1), dim3(nt), by, st, L.g,
+                           L.c64, L.psi64, f32, x32, rtol, maxit, iters);
     } else {
       if (one)
-        hipLaunchKernelGGL((k_bottom_lds_mixed<2, 1>), dim3(1), dim3(nt), by, st, L.g, L.c64,
-                           L.c32, L.psi64, L.psi32, b32, e32, rtol, maxit, iters);
+        hipLaunchKernelGGL((k_bottom_lds64<2, 1, float>), dim3(1), dim3(nt), by, st, L.g, L.c64,
+                           L.psi64, f32, x32, rtol, maxit, iters);
       else
-        hipLaunchKernelGGL((k_bottom_lds_mixed<2, kBotQMixed>), dim3(1), dim3(nt), by, st, L.g,
-                           L.c64, L.c32, L.psi64, L.psi32, b32, e32, rtol, maxit, iters);
+        hipLaunchKernelGGL((k_bottom_lds64<2, kBotQ, float>), dim3(1), dim3(nt), by, st, L.g,
+                           L.c64, L.psi64, f32, x32, rtol, maxit, iters);
     }
     return hipGetLastError();
   }
-  if (L.g.dim == 3)
-    SBM_LAUNCH((k_bottom_mixed<3>), 1, kBottomThreads, st, L.g, L.c64, L.c32, L.psi64, L.psi32,
-               b32, e32, x64, r64, r32, p32, Ap32, d32, rtol, maxit, iters);
-  SBM_LAUNCH((k_bottom_mixed<2>), 1, kBottomThreads, st, L.g, L.c64, L.c32, L.psi64, L.psi32, b32,
-             e32, x64, r64, r32, p32, Ap32, d32, rtol, maxit, iters);
+  // larger bottoms: the global-memory FP64 CG on converted copies
+  const int64_t nv = (int64_t)L.g.dim * L.g.nn;
+  hipError_t e;
+  (void)hipGetLastError();
+  hipLaunchKernelGGL((k_convert<float, double>), dim3(fill_blocks(nv)), dim3(kBlock), 0, st, f32,
+                     f64, nv);
+  hipLaunchKernelGGL((k_convert<float, double>), dim3(fill_blocks(nv)), dim3(kBlock), 0, st, x32,
+                     x64, nv);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = launch_bottom_cg<double>(L, L.psi64, L.c64, f64, x64, r, p, Ap, rtol, maxit, iters,
+                                    st)) != hipSuccess)
+    return e;
+  hipLaunchKernelGGL((k_convert<double, float>), dim3(fill_blocks(nv)), dim3(kBlock), 0, st, x64,
+                     x32, nv);
+  return hipGetLastError();
 }
 
 hipError_t launch_sensitivity(const Level &L, double lam, double mu, const Traction &tr,

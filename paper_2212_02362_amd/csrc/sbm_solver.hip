@@ -50,7 +50,6 @@ struct sbm_ctx {
   int *iflag = nullptr;    // device int flags / counters
   // bottom scratch
   double *b_r = nullptr, *b_p = nullptr, *b_Ap = nullptr, *b_x64 = nullptr, *b_r64 = nullptr;
-  float *b_r32 = nullptr, *b_p32 = nullptr, *b_Ap32 = nullptr, *b_d32 = nullptr;
   double *host = nullptr;  // pinned host scalars
   bool have_problem = false;
   sbm_material mat{};
@@ -265,10 +264,6 @@ static size_t carve(sbm_ctx *c, char *base) {
   c->b_Ap = cv.take<double>(nb);
   c->b_x64 = cv.take<double>(nb);
   c->b_r64 = cv.take<double>(nb);
-  c->b_r32 = cv.take<float>(nb);
-  c->b_p32 = cv.take<float>(nb);
-  c->b_Ap32 = cv.take<float>(nb);
-  c->b_d32 = cv.take<float>(nb);
   return cv.off + 256;
 }
 
@@ -371,8 +366,9 @@ static hipError_t bottom64(sbm_ctx *c, const double *f, double *x) {
 }
 
 static hipError_t bottom32(sbm_ctx *c, const float *f, float *x) {
+  // the near-singular bottom is solved in FP64 also inside the FP32 cycle
   Level &B = c->L[c->nlev - 1];
-  return launch_bottom_mixed(B, f, x, c->b_x64, c->b_r64, c->b_r32, c->b_p32, c->b_Ap32, c->b_d32,
+  return launch_bottom_f32io(B, f, x, c->b_r64, c->b_x64, c->b_r, c->b_p, c->b_Ap,
                              c->opt.bottom_rtol, bottom_maxit(c), c->iflag + 4, c->st);
 }
 

@@ -29,8 +29,10 @@ CASES = {
     "cantilever_24x12x12": lambda: si.cantilever_density_3d(24, 12, 12),
     "random_mixed_2d_40x24": lambda: random_problem((40, 24), seed=3),
     "random_mixed_3d_16x8x12": lambda: random_problem((16, 8, 12), seed=4, floor=1e-3),
-    # 624-node bottom: LDS CG in FP64, global-memory CG in the mixed cycle
+    # 624-node bottom (LDS CG)
     "random_mixed_2d_50x46": lambda: random_problem((50, 46), seed=5, floor=1e-2),
+    # odd cell counts: the grid is its own 1224-node bottom (global-memory CG)
+    "random_mixed_2d_35x33": lambda: random_problem((35, 33), seed=7, floor=1e-2),
 }
 
 
@@ -86,7 +88,8 @@ def test_wide_grid_first_iterations(krylov):
 
 
 @pytest.mark.parametrize("case", ["plate_void_2d_64", "spherical_voids_32", "cantilever_24x12x12",
-                                  "random_mixed_3d_16x8x12", "random_mixed_2d_50x46"])
+                                  "random_mixed_3d_16x8x12", "random_mixed_2d_50x46",
+                                  "random_mixed_2d_35x33"])
 def test_mixed_precision_converges_to_fp64_solution(case):
     p = CASES[case]()
     say("mixed", case)
