@@ -59,6 +59,33 @@ __device__ __forceinline__ int64_t fine_of_coarse(const Geom &gf, int I, int J, 
   return 2 * I + (int64_t)gf.nx * (2 * J + (int64_t)gf.ny * (2 * K));
 }
 
+// Node iteration of the level kernels: one node per thread over the whole
+// level, or (TILED) one workgroup per listed tile, looping over its nodes.
+struct TileArg {
+  TileGeom tg;
+  const int *ids;
+};
+
+template <bool TILED, class F>
+__device__ __forceinline__ void for_nodes(const Geom &g, const TileArg &ta, F &&fn) {
+  if constexpr (!TILED) {
+    const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (id < g.nn) fn(id);
+  } else {
+    // one workgroup per plane of a listed tile
+    const int t = ta.ids[blockIdx.x / ta.tg.kz];
+    const int tx = t % ta.tg.ntx, rest = t / ta.tg.ntx;
+    const int ty = rest % ta.tg.nty, tz = rest / ta.tg.nty;
+    const int x0 = tx * kTileX, y0 = ty * kTileY;
+    const int k = tz * ta.tg.kz + (int)(blockIdx.x % ta.tg.kz);
+    if (k >= g.nz) return;
+    for (int e = threadIdx.x; e < kTileX * kTileY; e += kBlock) {
+      const int x = x0 + e % kTileX, y = y0 + e / kTileX;
+      if (x < g.nx && y < g.ny) fn((int64_t)x + (int64_t)g.nx * (y + (int64_t)g.ny * k));
+    }
+  }
+}
+
 // ------------------------------------------------------------- setup kernels
 
 // Refinement tags of the cells of one level: |grad psi|^2 h^2 > threshold^2
@@ -248,34 +275,35 @@ __device__ __forceinline__ int quad_axis(int n, int idx[3], T w[3]) {
 // Ghost nodes (classes 2-4) of the fine level from the coarse level; fixed
 // displacement DOF keep their values.  Weight products are exact dyadic
 // numbers; every term is rounded before it is added.
-template <typename T, int DIM>
+template <typename T, int DIM, bool TILED>
 __global__ __launch_bounds__(kBlock) void k_amr_ghost(Geom gf, Geom gc,
                                                       const uint8_t *__restrict__ cls,
                                                       const T *__restrict__ xc,
-                                                      T *__restrict__ xf) {
+                                                      T *__restrict__ xf, TileArg ta) {
 #pragma clang fp contract(off)
-  const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (id >= gf.nn || cls[id] < 2) return;
-  int i, j, k;
-  node_ijk(gf, id, i, j, k);
-  int ix[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-  T w[3][3] = {{T(1), T(0), T(0)}, {T(1), T(0), T(0)}, {T(1), T(0), T(0)}};
-  int cnt[3] = {1, 1, 1};
-  cnt[0] = quad_axis<T>(i, ix[0], w[0]);
-  cnt[1] = quad_axis<T>(j, ix[1], w[1]);
-  if (DIM == 3) cnt[2] = quad_axis<T>(k, ix[2], w[2]);
+  for_nodes<TILED>(gf, ta, [&](int64_t id) {
+    if (cls[id] < 2) return;
+    int i, j, k;
+    node_ijk(gf, id, i, j, k);
+    int ix[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    T w[3][3] = {{T(1), T(0), T(0)}, {T(1), T(0), T(0)}, {T(1), T(0), T(0)}};
+    int cnt[3] = {1, 1, 1};
+    cnt[0] = quad_axis<T>(i, ix[0], w[0]);
+    cnt[1] = quad_axis<T>(j, ix[1], w[1]);
+    if (DIM == 3) cnt[2] = quad_axis<T>(k, ix[2], w[2]);
 #pragma unroll
-  for (int c = 0; c < DIM; ++c) {
-    if (is_dirichlet(gf, i, j, k, c)) continue;
-    T s = T(0);
-    for (int t2 = 0; t2 < cnt[2]; ++t2)
-      for (int t1 = 0; t1 < cnt[1]; ++t1)
-        for (int t0 = 0; t0 < cnt[0]; ++t0) {
-          const int64_t q = ix[0][t0] + (int64_t)gc.nx * (ix[1][t1] + (int64_t)gc.ny * ix[2][t2]);
-          s += w[0][t0] * w[1][t1] * w[2][t2] * xc[c * gc.nn + q];
-        }
-    xf[c * gf.nn + id] = s;
-  }
+    for (int c = 0; c < DIM; ++c) {
+      if (is_dirichlet(gf, i, j, k, c)) continue;
+      T s = T(0);
+      for (int t2 = 0; t2 < cnt[2]; ++t2)
+        for (int t1 = 0; t1 < cnt[1]; ++t1)
+          for (int t0 = 0; t0 < cnt[0]; ++t0) {
+            const int64_t q = ix[0][t0] + (int64_t)gc.nx * (ix[1][t1] + (int64_t)gc.ny * ix[2][t2]);
+            s += w[0][t0] * w[1][t1] * w[2][t2] * xc[c * gc.nn + q];
+          }
+      xf[c * gf.nn + id] = s;
+    }
+  });
 }
 
 // Coarse nodes on or inside the fine region (fine class 1 or 2 at the
@@ -331,20 +359,20 @@ __global__ __launch_bounds__(kBlock) void k_amr_restrict_cif(Geom gf, Geom gc,
 
 // r32 = r / sqrt(*ss) in FP32, 0 on the padded ghost rows (classes 2 and 3)
 // of an adaptive level (every node when cls is NULL).
-template <int DIM>
+template <int DIM, bool TILED>
 __global__ __launch_bounds__(kBlock) void k_amr_cast(Geom g, const uint8_t *__restrict__ cls,
                                                      const double *__restrict__ r,
                                                      float *__restrict__ r32,
-                                                     const double *__restrict__ ss) {
-  const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (id >= g.nn) return;
+                                                     const double *__restrict__ ss, TileArg ta) {
   const double sn = sqrt(*ss);
-  const bool ghost = cls && (cls[id] == 2 || cls[id] == 3);
+  for_nodes<TILED>(g, ta, [&](int64_t id) {
+    const bool ghost = cls && (cls[id] == 2 || cls[id] == 3);
 #pragma unroll
-  for (int c = 0; c < DIM; ++c) {
-    const int64_t q = c * g.nn + id;
-    r32[q] = (ghost || !(sn > 0.0)) ? 0.0f : (float)(r[q] / sn);
-  }
+    for (int c = 0; c < DIM; ++c) {
+      const int64_t q = c * g.nn + id;
+      r32[q] = (ghost || !(sn > 0.0)) ? 0.0f : (float)(r[q] / sn);
+    }
+  });
 }
 
 // Coarse nodes strictly inside the fine region (fine class 1) take the fine
@@ -365,82 +393,83 @@ __global__ __launch_bounds__(kBlock) void k_amr_inject(Geom gf, Geom gc,
 }
 
 // x_f += P (x_c - xinj_c) on the unknowns (class 1, free DOF) of the fine level.
-template <typename T, int DIM>
+template <typename T, int DIM, bool TILED>
 __global__ __launch_bounds__(kBlock) void k_amr_correct(Geom gf, Geom gc,
                                                         const uint8_t *__restrict__ clsf,
                                                         const T *__restrict__ xc,
                                                         const T *__restrict__ xinj,
-                                                        T *__restrict__ xf) {
-  const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (id >= gf.nn || clsf[id] != 1) return;
-  int i, j, k;
-  node_ijk(gf, id, i, j, k);
-  const int lo[3] = {i >> 1, j >> 1, DIM == 3 ? k >> 1 : 0};
-  const int hi[3] = {(i + 1) >> 1, (j + 1) >> 1, DIM == 3 ? (k + 1) >> 1 : 0};
-  const T wx = lo[0] == hi[0] ? T(1) : T(0.5), wy = lo[1] == hi[1] ? T(1) : T(0.5);
-  const T wz = lo[2] == hi[2] ? T(1) : T(0.5);
+                                                        T *__restrict__ xf, TileArg ta) {
+  for_nodes<TILED>(gf, ta, [&](int64_t id) {
+    if (clsf[id] != 1) return;
+    int i, j, k;
+    node_ijk(gf, id, i, j, k);
+    const int lo[3] = {i >> 1, j >> 1, DIM == 3 ? k >> 1 : 0};
+    const int hi[3] = {(i + 1) >> 1, (j + 1) >> 1, DIM == 3 ? (k + 1) >> 1 : 0};
+    const T wx = lo[0] == hi[0] ? T(1) : T(0.5), wy = lo[1] == hi[1] ? T(1) : T(0.5);
+    const T wz = lo[2] == hi[2] ? T(1) : T(0.5);
 #pragma unroll
-  for (int c = 0; c < DIM; ++c) {
-    if (is_dirichlet(gf, i, j, k, c)) continue;
-    T acc = T(0);
-    for (int I2 = lo[2]; I2 <= hi[2]; ++I2)
-      for (int I1 = lo[1]; I1 <= hi[1]; ++I1)
-        for (int I0 = lo[0]; I0 <= hi[0]; ++I0) {
-          const int64_t q = c * gc.nn + I0 + (int64_t)gc.nx * (I1 + (int64_t)gc.ny * I2);
-          acc += wx * wy * wz * (xc[q] - xinj[q]);
-        }
-    xf[c * gf.nn + id] += acc;
-  }
+    for (int c = 0; c < DIM; ++c) {
+      if (is_dirichlet(gf, i, j, k, c)) continue;
+      T acc = T(0);
+      for (int I2 = lo[2]; I2 <= hi[2]; ++I2)
+        for (int I1 = lo[1]; I1 <= hi[1]; ++I1)
+          for (int I0 = lo[0]; I0 <= hi[0]; ++I0) {
+            const int64_t q = c * gc.nn + I0 + (int64_t)gc.nx * (I1 + (int64_t)gc.ny * I2);
+            acc += wx * wy * wz * (xc[q] - xinj[q]);
+          }
+      xf[c * gf.nn + id] += acc;
+    }
+  });
 }
 
 // u += s e on the free DOF of the level's unknowns (all nodes when cls is
 // NULL, class 1 otherwise); s = sqrt(*ss) when ss is given, else 1.
-template <typename T, int DIM>
+template <typename T, int DIM, bool TILED>
 __global__ __launch_bounds__(kBlock) void k_amr_update(Geom g, const uint8_t *__restrict__ cls,
                                                        double *__restrict__ u,
                                                        const T *__restrict__ e,
-                                                       const double *__restrict__ ss) {
-  const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (id >= g.nn || (cls && cls[id] != 1)) return;
-  int i, j, k;
-  node_ijk(g, id, i, j, k);
+                                                       const double *__restrict__ ss, TileArg ta) {
   const double s = ss ? sqrt(*ss) : 1.0;
+  for_nodes<TILED>(g, ta, [&](int64_t id) {
+    if (cls && cls[id] != 1) return;
+    int i, j, k;
+    node_ijk(g, id, i, j, k);
 #pragma unroll
-  for (int c = 0; c < DIM; ++c) {
-    if (is_dirichlet(g, i, j, k, c)) continue;
-    if (ss) u[c * g.nn + id] += s * (double)e[c * g.nn + id];
-    else u[c * g.nn + id] += (double)e[c * g.nn + id];
-  }
+    for (int c = 0; c < DIM; ++c) {
+      if (is_dirichlet(g, i, j, k, c)) continue;
+      if (ss) u[c * g.nn + id] += s * (double)e[c * g.nn + id];
+      else u[c * g.nn + id] += (double)e[c * g.nn + id];
+    }
+  });
 }
 
 // Per-block partial sums over the composite unknowns of one level: free DOF
 // of class-1 nodes (every node when cls is NULL) not covered by the finer
 // level (fine class 1 at the coinciding node; no finer level when clsf is
 // NULL).  Sums r^2, or counts the DOF when r is NULL.
-template <int DIM>
+template <int DIM, bool TILED>
 __global__ __launch_bounds__(kBlock) void k_amr_sumsq(Geom g, const uint8_t *__restrict__ cls,
                                                       Geom gf, const uint8_t *__restrict__ clsf,
                                                       const double *__restrict__ r,
-                                                      double *__restrict__ partials) {
+                                                      double *__restrict__ partials, TileArg ta) {
   __shared__ double lds[kBlock / 64 + 1];
-  const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   double v = 0.0;
-  if (id < g.nn && (!cls || cls[id] == 1)) {
+  for_nodes<TILED>(g, ta, [&](int64_t id) {
+    if (cls && cls[id] != 1) return;
     int i, j, k;
     node_ijk(g, id, i, j, k);
-    if (!clsf || clsf[fine_of_coarse(gf, i, j, k)] != 1) {
+    if (clsf && clsf[fine_of_coarse(gf, i, j, k)] == 1) return;
 #pragma unroll
-      for (int c = 0; c < DIM; ++c) {
-        if (is_dirichlet(g, i, j, k, c)) continue;
-        if (r) {
-          const double x = r[c * g.nn + id];
-          v += x * x;
-        } else {
-          v += 1.0;
-        }
+    for (int c = 0; c < DIM; ++c) {
+      if (is_dirichlet(g, i, j, k, c)) continue;
+      if (r) {
+        const double x = r[c * g.nn + id];
+        v += x * x;
+      } else {
+        v += 1.0;
       }
     }
-  }
+  });
   const double s = block_sum(v, lds);
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
@@ -459,11 +488,37 @@ hipError_t launch_tags(const Level &L, double thresh, const double *psi, uint8_t
              thr2, psi, tags);
 }
 
+// Grid and tile argument of a level kernel: the listed tiles, or every node.
+struct NodeGrid {
+  int blocks;
+  bool tiled;
+  TileArg ta;
+};
+
+static NodeGrid node_grid(const Level &L, const TileList *tl) {
+  if (tl) {
+    const TileGeom tg = tile_geom_of(L);
+    return NodeGrid{tl->count * tg.kz, true, TileArg{tg, tl->ids}};
+  }
+  return NodeGrid{num_blocks(L.g.nn), false, TileArg{TileGeom{1, 1, 1, 1}, nullptr}};
+}
+
+#define AMR_NODE_LAUNCH(KT, KD, ng, st, ...)                                     \
+  do {                                                                          \
+    if ((ng).blocks == 0) return hipSuccess;                                    \
+    if ((ng).tiled) AMR_LAUNCH(KT, (ng).blocks, kBlock, st, __VA_ARGS__, (ng).ta); \
+    AMR_LAUNCH(KD, (ng).blocks, kBlock, st, __VA_ARGS__, (ng).ta);              \
+  } while (0)
+
 template <typename T>
 hipError_t launch_ghost(const Level &F, const Level &C, const uint8_t *cls, const T *xc, T *xf,
-                        hipStream_t st) {
-  if (F.g.dim == 3) AMR_LAUNCH((k_amr_ghost<T, 3>), num_blocks(F.g.nn), kBlock, st, F.g, C.g, cls, xc, xf);
-  AMR_LAUNCH((k_amr_ghost<T, 2>), num_blocks(F.g.nn), kBlock, st, F.g, C.g, cls, xc, xf);
+                        hipStream_t st, const TileList *tl = nullptr) {
+  const NodeGrid ng = node_grid(F, tl);
+  if (F.g.dim == 3)
+    AMR_NODE_LAUNCH((k_amr_ghost<T, 3, true>), (k_amr_ghost<T, 3, false>), ng, st, F.g, C.g, cls,
+                    xc, xf);
+  AMR_NODE_LAUNCH((k_amr_ghost<T, 2, true>), (k_amr_ghost<T, 2, false>), ng, st, F.g, C.g, cls, xc,
+                  xf);
 }
 
 template <typename T>
@@ -482,9 +537,11 @@ hipError_t launch_restrict_cif(const Level &F, const Level &C, const uint8_t *cl
 }
 
 hipError_t launch_amr_cast(const Level &L, const uint8_t *cls, const double *r, float *r32,
-                           const double *ss, hipStream_t st) {
-  if (L.g.dim == 3) AMR_LAUNCH((k_amr_cast<3>), num_blocks(L.g.nn), kBlock, st, L.g, cls, r, r32, ss);
-  AMR_LAUNCH((k_amr_cast<2>), num_blocks(L.g.nn), kBlock, st, L.g, cls, r, r32, ss);
+                           const double *ss, hipStream_t st, const TileList *tl = nullptr) {
+  const NodeGrid ng = node_grid(L, tl);
+  if (L.g.dim == 3)
+    AMR_NODE_LAUNCH((k_amr_cast<3, true>), (k_amr_cast<3, false>), ng, st, L.g, cls, r, r32, ss);
+  AMR_NODE_LAUNCH((k_amr_cast<2, true>), (k_amr_cast<2, false>), ng, st, L.g, cls, r, r32, ss);
 }
 
 template <typename T>
@@ -496,25 +553,38 @@ hipError_t launch_inject(const Level &F, const Level &C, const uint8_t *clsf, co
 
 template <typename T>
 hipError_t launch_amr_correct(const Level &F, const Level &C, const uint8_t *clsf, const T *xc,
-                              const T *xinj, T *xf, hipStream_t st) {
+                              const T *xinj, T *xf, hipStream_t st, const TileList *tl = nullptr) {
+  const NodeGrid ng = node_grid(F, tl);
   if (F.g.dim == 3)
-    AMR_LAUNCH((k_amr_correct<T, 3>), num_blocks(F.g.nn), kBlock, st, F.g, C.g, clsf, xc, xinj, xf);
-  AMR_LAUNCH((k_amr_correct<T, 2>), num_blocks(F.g.nn), kBlock, st, F.g, C.g, clsf, xc, xinj, xf);
+    AMR_NODE_LAUNCH((k_amr_correct<T, 3, true>), (k_amr_correct<T, 3, false>), ng, st, F.g, C.g,
+                    clsf, xc, xinj, xf);
+  AMR_NODE_LAUNCH((k_amr_correct<T, 2, true>), (k_amr_correct<T, 2, false>), ng, st, F.g, C.g,
+                  clsf, xc, xinj, xf);
 }
 
 template <typename T>
 hipError_t launch_update(const Level &L, const uint8_t *cls, double *u, const T *e,
-                         const double *ss, hipStream_t st) {
-  if (L.g.dim == 3) AMR_LAUNCH((k_amr_update<T, 3>), num_blocks(L.g.nn), kBlock, st, L.g, cls, u, e, ss);
-  AMR_LAUNCH((k_amr_update<T, 2>), num_blocks(L.g.nn), kBlock, st, L.g, cls, u, e, ss);
+                         const double *ss, hipStream_t st, const TileList *tl = nullptr) {
+  const NodeGrid ng = node_grid(L, tl);
+  if (L.g.dim == 3)
+    AMR_NODE_LAUNCH((k_amr_update<T, 3, true>), (k_amr_update<T, 3, false>), ng, st, L.g, cls, u,
+                    e, ss);
+  AMR_NODE_LAUNCH((k_amr_update<T, 2, true>), (k_amr_update<T, 2, false>), ng, st, L.g, cls, u, e,
+                  ss);
 }
 
+// Partial sums land in partials[0 .. blocks); with a tile list the rest of
+// the level's slots must hold zeros.
 hipError_t launch_sumsq(const Level &L, const uint8_t *cls, const Level *F, const uint8_t *clsf,
-                        const double *r, double *partials, hipStream_t st) {
+                        const double *r, double *partials, hipStream_t st,
+                        const TileList *tl = nullptr) {
   const Geom gf = F ? F->g : L.g;
+  const NodeGrid ng = node_grid(L, tl);
   if (L.g.dim == 3)
-    AMR_LAUNCH((k_amr_sumsq<3>), num_blocks(L.g.nn), kBlock, st, L.g, cls, gf, clsf, r, partials);
-  AMR_LAUNCH((k_amr_sumsq<2>), num_blocks(L.g.nn), kBlock, st, L.g, cls, gf, clsf, r, partials);
+    AMR_NODE_LAUNCH((k_amr_sumsq<3, true>), (k_amr_sumsq<3, false>), ng, st, L.g, cls, gf, clsf, r,
+                    partials);
+  AMR_NODE_LAUNCH((k_amr_sumsq<2, true>), (k_amr_sumsq<2, false>), ng, st, L.g, cls, gf, clsf, r,
+                  partials);
 }
 
 struct Carver {
@@ -543,6 +613,10 @@ struct AmrLevel {
   double *fP = nullptr, *r = nullptr, *e = nullptr, *w = nullptr, *xinj = nullptr, *tmp = nullptr;
   float *e32 = nullptr, *f32 = nullptr, *w32 = nullptr, *xinj32 = nullptr, *tmp32 = nullptr;
   float *g32 = nullptr;    // FP32 cycle: R of the finer level's ghost-row loads (a < A)
+  int *tflags = nullptr, *tids = nullptr;  // active column tiles (tiled levels a >= 1)
+  TileList tl;             // the level's active tiles (count 0 until set_problem)
+  bool tiled = false;      // the level sweeps only its active tiles
+  const TileList *tiles() const { return tiled ? &tl : nullptr; }
   int part_off = 0;        // offset of this level's partial sums
   Traction tr{};
   int64_t nblocks() const { return (int64_t)nb[0] * nb[1] * nb[2]; }
@@ -670,6 +744,11 @@ static size_t amr_carve(sbm_amr_ctx *c, char *base) {
       l.blk = cv.take<uint8_t>(l.nblocks());
       l.cls = cv.take<uint8_t>(l.L.g.nn);
       l.clo = cv.take<uint8_t>(l.L.g.nn);
+      l.tiled = tiled_ok(l.L) && tile_geom_of(l.L).ntiles <= num_blocks(l.L.g.nn);
+      if (l.tiled) {
+        l.tflags = cv.take<int>(tile_geom_of(l.L).ntiles);
+        l.tids = cv.take<int>(tile_geom_of(l.L).ntiles);
+      }
     }
     if (a < A) l.tags = cv.take<uint8_t>(l.L.g.nc);
     l.fP = cv.take<double>(nv);
@@ -756,7 +835,7 @@ static hipError_t amr_smooth(sbm_amr_ctx *c, int a, T *x, const T *f, T *tmp, in
   const bool tiled = tiled_ok(l.L);
   auto half = [&](const T *src, T *dst, int colour) {
     return tiled ? launch_rb_tiled<T>(l.L, AV<T>::psi(l), AV<T>::coef(l), src, f, dst, om, colour,
-                                      c->st, l.cls)
+                                      c->st, l.cls, l.tiles())
                  : launch_rb_half<T>(l.L, AV<T>::psi(l), AV<T>::coef(l), src, f, dst, om, colour,
                                      c->st, l.cls);
   };
@@ -788,17 +867,17 @@ static hipError_t amr_fas(sbm_amr_ctx *c, int a) {
   T *xc = AV<T>::x(C), *fc = AV<T>::f(C), *xi = AV<T>::xinj(C), *tc = AV<T>::tmp(C);
   {
     AmrProf pr(c, SBM_PROF_GHOST, fin);
-    if ((e = launch_ghost<T>(F.L, C.L, F.cls, xc, xf, c->st)) != hipSuccess) return e;
+    if ((e = launch_ghost<T>(F.L, C.L, F.cls, xc, xf, c->st, F.tiles())) != hipSuccess) return e;
   }
   if ((e = amr_smooth<T>(c, a, xf, ff, tf, c->opt.nu_pre)) != hipSuccess) return e;
   {
     AmrProf pr(c, SBM_PROF_GHOST, fin);
-    if ((e = launch_ghost<T>(F.L, C.L, F.cls, xc, xf, c->st)) != hipSuccess) return e;
+    if ((e = launch_ghost<T>(F.L, C.L, F.cls, xc, xf, c->st, F.tiles())) != hipSuccess) return e;
   }
   {
     AmrProf pr(c, SBM_PROF_RESIDUAL, fin);
     if ((e = launch_residual<T>(F.L, AV<T>::psi(F), AV<T>::coef(F), xf, ff, wf, nullptr, c->st,
-                                F.cls)) != hipSuccess)
+                                F.cls, F.tiles())) != hipSuccess)
       return e;
   }
   if ((e = launch_inject<T>(F.L, C.L, F.cls, xf, xc, c->st)) != hipSuccess) return e;
@@ -815,11 +894,12 @@ static hipError_t amr_fas(sbm_amr_ctx *c, int a) {
   if ((e = amr_fas<T>(c, a - 1)) != hipSuccess) return e;
   {
     AmrProf pr(c, SBM_PROF_PROLONG, fin);
-    if ((e = launch_amr_correct<T>(F.L, C.L, F.cls, xc, xi, xf, c->st)) != hipSuccess) return e;
+    if ((e = launch_amr_correct<T>(F.L, C.L, F.cls, xc, xi, xf, c->st, F.tiles())) != hipSuccess)
+      return e;
   }
   {
     AmrProf pr(c, SBM_PROF_GHOST, fin);
-    if ((e = launch_ghost<T>(F.L, C.L, F.cls, xc, xf, c->st)) != hipSuccess) return e;
+    if ((e = launch_ghost<T>(F.L, C.L, F.cls, xc, xf, c->st, F.tiles())) != hipSuccess) return e;
   }
   return amr_smooth<T>(c, a, xf, ff, tf, c->opt.nu_post);
 }
@@ -830,12 +910,13 @@ static sbm_status amr_comp_residual(sbm_amr_ctx *c, double *const *x, double *co
                                     double *const *r, bool sync) {
   const int A = c->A;
   for (int a = 1; a <= A; ++a)
-    AMR_HIP(launch_ghost<double>(c->lv[a].L, c->lv[a - 1].L, c->lv[a].cls, x[a - 1], x[a], c->st));
+    AMR_HIP(launch_ghost<double>(c->lv[a].L, c->lv[a - 1].L, c->lv[a].cls, x[a - 1], x[a], c->st,
+                                 c->lv[a].tiles()));
   for (int a = A; a >= 0; --a) {
     AmrLevel &l = c->lv[a];
     AmrProf pr(c, SBM_PROF_NORM, a == A);
     AMR_HIP(launch_residual<double>(l.L, l.L.psi64, l.L.c64, x[a], f[a], r[a], nullptr, c->st,
-                                    a >= 1 ? l.cls : nullptr));
+                                    a >= 1 ? l.cls : nullptr, a >= 1 ? l.tiles() : nullptr));
     if (a < A)
       AMR_HIP(launch_restrict_cif<double>(c->lv[a + 1].L, l.L, c->lv[a + 1].cls, r[a + 1], nullptr,
                                           nullptr, r[a], c->st));
@@ -844,7 +925,7 @@ static sbm_status amr_comp_residual(sbm_amr_ctx *c, double *const *x, double *co
     AmrLevel &l = c->lv[a];
     AMR_HIP(launch_sumsq(l.L, a >= 1 ? l.cls : nullptr, a < A ? &c->lv[a + 1].L : nullptr,
                          a < A ? c->lv[a + 1].cls : nullptr, r[a], c->partials + l.part_off,
-                         c->st));
+                         c->st, a >= 1 ? l.tiles() : nullptr));
   }
   AMR_HIP(launch_finalize_sum(c->partials, c->npart, c->scal, c->st));
   if (sync) {
@@ -1053,6 +1134,12 @@ sbm_status sbm_amr_set_problem(sbm_amr_ctx *c, const double *const *psi_raw,
     }
     AMR_HIP(hipGetLastError());
   }
+  // active column tiles of the tiled levels (their counts read back below)
+  for (int a = 1; a <= A; ++a) {
+    AmrLevel &l = c->lv[a];
+    l.tl = TileList{l.tids, 0};
+    if (l.tiled) AMR_HIP(launch_active_tiles(l.L, l.cls, l.tflags, l.tids, c->iflag + 8 + a, c->st));
+  }
   // psi of covered coarse cells, finest first
   for (int a = A; a >= 1; --a) {
     AmrLevel &f = c->lv[a], &p = c->lv[a - 1];
@@ -1073,10 +1160,15 @@ sbm_status sbm_amr_set_problem(sbm_amr_ctx *c, const double *const *psi_raw,
     AMR_HIP(launch_rhs(l.L, l.tr, nullptr, l.fP, c->iflag, c->st));
     AMR_HIP(launch_check_diag(l.L, c->iflag, c->st));
   }
-  AMR_HIP(hipMemcpyAsync(c->host, c->iflag, sizeof(int), hipMemcpyDeviceToHost, c->st));
+  AMR_HIP(hipMemcpyAsync(c->host, c->iflag, 16 * sizeof(int), hipMemcpyDeviceToHost, c->st));
   AMR_HIP(hipStreamSynchronize(c->st));
-  int flags = 0;
-  memcpy(&flags, c->host, sizeof(int));
+  int flags = 0, iv[16];
+  memcpy(iv, c->host, sizeof(iv));
+  flags = iv[0];
+  for (int a = 1; a <= A; ++a)
+    if (c->lv[a].tiled) c->lv[a].tl.count = iv[8 + a];
+  // tiled levels write partial sums for their listed tiles only
+  AMR_HIP(launch_fill<double>(c->partials, c->npart, 0.0, c->st));
   if (flags & 1) return amr_fail(SBM_E_NONFINITE, "NaN/Inf in psi");
   if (flags & 2) return amr_fail(SBM_E_DIAG, "a free DOF has no solid cell around it");
   // uniform hierarchy of the base level on the averaged-down psi
@@ -1099,7 +1191,7 @@ sbm_status sbm_amr_set_problem(sbm_amr_ctx *c, const double *const *psi_raw,
     AmrLevel &l = c->lv[a];
     AMR_HIP(launch_sumsq(l.L, a >= 1 ? l.cls : nullptr, a < A ? &c->lv[a + 1].L : nullptr,
                          a < A ? c->lv[a + 1].cls : nullptr, nullptr, c->partials + l.part_off,
-                         c->st));
+                         c->st, a >= 1 ? l.tiles() : nullptr));
   }
   AMR_HIP(launch_finalize_sum(c->partials, c->npart, c->scal, c->st));
   AMR_HIP(hipMemcpyAsync(c->host, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->st));
@@ -1150,7 +1242,7 @@ sbm_status sbm_amr_ghost_fill(sbm_amr_ctx *c, int level, const double *xc, doubl
   if (level < 1 || level > c->A) return amr_fail(SBM_E_ARG, "level must be 1..levels-1");
   if (!xc || !xf) return amr_fail(SBM_E_ARG, "NULL argument");
   AMR_HIP(launch_ghost<double>(c->lv[level].L, c->lv[level - 1].L, c->lv[level].cls, xc, xf,
-                               c->st));
+                               c->st, c->lv[level].tiles()));
   return SBM_OK;
 }
 
@@ -1217,7 +1309,8 @@ sbm_status sbm_amr_solve(sbm_amr_ctx *c, double *const *u, double *hist_host, in
       // FP32 loads carry zeros on those rows, so no FP32 sum cancels.
       for (int a = 0; a <= A; ++a) {
         AmrLevel &l = c->lv[a];
-        AMR_HIP(launch_amr_cast(l.L, a >= 1 ? l.cls : nullptr, l.r, l.f32, c->scal, c->st));
+        AMR_HIP(launch_amr_cast(l.L, a >= 1 ? l.cls : nullptr, l.r, l.f32, c->scal, c->st,
+                                a >= 1 ? l.tiles() : nullptr));
         AMR_HIP(launch_fill<float>(l.e32, l.nv(), 0.0f, c->st));
         if (a < A) {
           AMR_HIP(launch_fill<double>(l.w, l.nv(), 0.0, c->st));
@@ -1229,18 +1322,21 @@ sbm_status sbm_amr_solve(sbm_amr_ctx *c, double *const *u, double *hist_host, in
       AMR_HIP(amr_fas<float>(c, A));
       for (int a = 0; a <= A; ++a)
         AMR_HIP(launch_update<float>(c->lv[a].L, a >= 1 ? c->lv[a].cls : nullptr, u[a],
-                                     c->lv[a].e32, c->scal, c->st));
+                                     c->lv[a].e32, c->scal, c->st,
+                                     a >= 1 ? c->lv[a].tiles() : nullptr));
     } else {
       for (int a = 0; a <= A; ++a) AMR_HIP(launch_fill<double>(c->lv[a].e, c->lv[a].nv(), 0.0, c->st));
       AMR_HIP(amr_fas<double>(c, A));
       for (int a = 0; a <= A; ++a)
         AMR_HIP(launch_update<double>(c->lv[a].L, a >= 1 ? c->lv[a].cls : nullptr, u[a],
-                                      c->lv[a].e, nullptr, c->st));
+                                      c->lv[a].e, nullptr, c->st,
+                                      a >= 1 ? c->lv[a].tiles() : nullptr));
     }
     AMR_TRY(amr_inject_all(c, u));
   }
   for (int a = 1; a <= A; ++a)
-    AMR_HIP(launch_ghost<double>(c->lv[a].L, c->lv[a - 1].L, c->lv[a].cls, u[a - 1], u[a], c->st));
+    AMR_HIP(launch_ghost<double>(c->lv[a].L, c->lv[a - 1].L, c->lv[a].cls, u[a - 1], u[a], c->st,
+                                 c->lv[a].tiles()));
   AMR_HIP(hipStreamSynchronize(c->st));
   if (n_cycles_host) *n_cycles_host = m;
   if (final_rel_host) *final_rel_host = rho;

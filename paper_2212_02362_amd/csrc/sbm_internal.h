@@ -39,6 +39,22 @@ struct Level {
   float *e32 = nullptr, *f32 = nullptr, *t32 = nullptr;
 };
 
+// Column tiles of the tiled 3D kernels: kTileX x kTileY nodes in x, y over a
+// chunk of kz planes; tile id = tx + ntx (ty + nty tz).
+#ifndef SBM_TILE_TY
+#define SBM_TILE_TY 8
+#endif
+constexpr int kTileX = 64, kTileY = SBM_TILE_TY;
+struct TileGeom {
+  int ntx, nty, kz, ntiles;
+};
+TileGeom tile_geom_of(const Level &L);
+// A subset of a level's tiles (device ids in increasing order).
+struct TileList {
+  const int *ids = nullptr;
+  int count = 0;
+};
+
 // ---------------------------------------------------------------- launchers
 // All launchers enqueue on `st` and return the launch status.
 template <typename T>
@@ -47,7 +63,7 @@ hipError_t launch_apply(const Level &L, const T *psi, const Coef<T> &C, const T 
 template <typename T>
 hipError_t launch_residual(const Level &L, const T *psi, const Coef<T> &C, const T *u,
                            const T *f, T *r, double *partials, hipStream_t st,
-                           const uint8_t *cls = nullptr);
+                           const uint8_t *cls = nullptr, const TileList *tl = nullptr);
 hipError_t launch_residual_cast(const Level &L, const double *u, const double *f, float *r32,
                                 const double *ss, hipStream_t st);
 template <typename T>
@@ -57,20 +73,26 @@ template <typename T>
 hipError_t launch_rb_half(const Level &L, const T *psi, const Coef<T> &C, const T *u,
                           const T *f, T *u_out, double omega, int colour, hipStream_t st,
                           const uint8_t *cls = nullptr);
+// Tiles of level L holding a node of class >= 1: flags[ntiles] scratch,
+// ids[ntiles] and *count (device) out.
+hipError_t launch_active_tiles(const Level &L, const uint8_t *cls, int *flags, int *ids,
+                               int *count, hipStream_t st);
+
 // LDS-tiled 3D half-sweep (same result as launch_rb_half); tiled_ok tells
-// whether a level is large enough for the 64 x 8 node tiles to pay.
+// whether a level is large enough for the 64 x 8 node tiles to pay.  With a
+// tile list only those tiles are swept (nodes outside them stay untouched).
 bool tiled_ok(const Level &L);
 template <typename T>
 hipError_t launch_rb_tiled(const Level &L, const T *psi, const Coef<T> &C, const T *u, const T *f,
                            T *u_out, double omega, int colour, hipStream_t st,
-                           const uint8_t *cls = nullptr);
+                           const uint8_t *cls = nullptr, const TileList *tl = nullptr);
 // Tiled residual / Krylov Apply (same results as the node-parallel kernels);
 // their partial sums number tiled_partials(L).
 int tiled_partials(const Level &L);
 template <typename T>
 hipError_t launch_residual_tiled(const Level &L, const T *psi, const Coef<T> &C, const T *u,
                                  const T *f, T *r, double *partials, hipStream_t st,
-                                 const uint8_t *cls);
+                                 const uint8_t *cls, const TileList *tl = nullptr);
 hipError_t launch_apply_dot_tiled(const Level &L, const double *p, double *q, double *partials,
                                   hipStream_t st);
 // Number of partial sums launch_residual / launch_apply_dot write for level L.

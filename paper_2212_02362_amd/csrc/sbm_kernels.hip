@@ -1062,8 +1062,8 @@ hipError_t launch_apply(const Level &L, const T *psi, const Coef<T> &C, const T 
 template <typename T>
 hipError_t launch_residual(const Level &L, const T *psi, const Coef<T> &C, const T *u,
                            const T *f, T *r, double *partials, hipStream_t st,
-                           const uint8_t *cls) {
-  if (use_tiled(L)) return launch_residual_tiled<T>(L, psi, C, u, f, r, partials, st, cls);
+                           const uint8_t *cls, const TileList *tl) {
+  if (use_tiled(L)) return launch_residual_tiled<T>(L, psi, C, u, f, r, partials, st, cls, tl);
   if (L.g.dim == 3)
     SBM_LAUNCH((k_residual<T, 3>), grid_blocks(L.g.nn), kBlock, st, L.g, C, psi, u, f, r, partials,
                cls);
@@ -1314,7 +1314,7 @@ hipError_t launch_sensitivity(const Level &L, double lam, double mu, const Tract
                                       hipStream_t);                                            \
   template hipError_t launch_residual<T>(const Level &, const T *, const Coef<T> &, const T *,  \
                                          const T *, T *, double *, hipStream_t,                \
-                                         const uint8_t *);                                     \
+                                         const uint8_t *, const TileList *);                   \
   template hipError_t launch_jacobi<T>(const Level &, const T *, const Coef<T> &, const T *,    \
                                        const T *, T *, double, hipStream_t, const uint8_t *);  \
   template hipError_t launch_rb_half<T>(const Level &, const T *, const Coef<T> &, const T *,   \

@@ -15,9 +15,6 @@
 namespace sbm {
 namespace {
 
-#ifndef SBM_TILE_TY
-#define SBM_TILE_TY 8
-#endif
 #ifndef SBM_TILE_WG
 #define SBM_TILE_WG 1536  // target number of workgroups (sets the z-chunk depth)
 #endif
@@ -31,7 +28,7 @@ namespace {
 #define SBM_TILE_WAVES 2  // waves per SIMD the FP64 register budget is sized for
 #endif
 
-constexpr int TX = 64, TY = SBM_TILE_TY;    // interior nodes of a tile
+constexpr int TX = kTileX, TY = kTileY;     // interior nodes of a tile
 constexpr int LX = TX + 2, LY = TY + 2;     // with the node halo
 constexpr int CXL = TX + 1, CYL = TY + 1;   // cells touching the tile's nodes
 constexpr int NT = TX / 2 * TY;             // threads: one x-pair per thread
@@ -40,10 +37,6 @@ constexpr int NU = 3 * PLANE;
 constexpr int NUPT = (NU + NT - 1) / NT;
 constexpr int NP = CYL * CXL;
 constexpr int NPPT = (NP + NT - 1) / NT;
-
-struct TileGeom {
-  int ntx, nty, kz, ntiles;
-};
 
 // The level geometry the tiled kernels need (3D only; fewer scalar registers
 // than Geom).
@@ -158,13 +151,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(SBM_TILE_WAV
                                                    const T *__restrict__ u,
                                                    const T *__restrict__ f,
                                                    T *__restrict__ u_out, T omega, int colour,
-                                                   TileGeom tg, const uint8_t *__restrict__ cls) {
+                                                   TileGeom tg, const uint8_t *__restrict__ cls,
+                                                   const int *__restrict__ ids, int nids) {
   __shared__ T su[3][NU];
   __shared__ T sp[2][NP];
   const int nwg = gridDim.x;  // a multiple of 8
   const int b = blockIdx.x;
-  const int lt = SBM_TILE_XCD ? (b & 7) * (nwg >> 3) + (b >> 3) : b;
-  if (lt >= tg.ntiles) return;
+  const int li = SBM_TILE_XCD ? (b & 7) * (nwg >> 3) + (b >> 3) : b;
+  if (li >= (ids ? nids : tg.ntiles)) return;
+  const int lt = ids ? ids[li] : li;  // a subset of the tiles, or all of them
   const int tx = lt % tg.ntx;
   const int rest = lt / tg.ntx;
   const int ty = rest % tg.nty;
@@ -288,14 +283,15 @@ template <typename T, int MODE, bool MASK>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(SBM_TILE_WAVES))) void
 k_full_tile(TG g, Coef<T> C, const T *__restrict__ psi, const T *__restrict__ u,
             const T *__restrict__ f, T *__restrict__ r, double *__restrict__ partials,
-            TileGeom tg, const uint8_t *__restrict__ cls) {
+            TileGeom tg, const uint8_t *__restrict__ cls, const int *__restrict__ ids, int nids) {
   __shared__ T su[3][NU];
   __shared__ T sp[2][NP];
   __shared__ double red[NT / 64 + 1];
   const int nwg = gridDim.x;  // a multiple of 8
   const int b = blockIdx.x;
-  const int lt = SBM_TILE_XCD ? (b & 7) * (nwg >> 3) + (b >> 3) : b;
-  if (lt >= tg.ntiles) return;
+  const int li = SBM_TILE_XCD ? (b & 7) * (nwg >> 3) + (b >> 3) : b;
+  if (li >= (ids ? nids : tg.ntiles)) return;
+  const int lt = ids ? ids[li] : li;  // a subset of the tiles, or all of them
   const int tx = lt % tg.ntx;
   const int rest = lt / tg.ntx;
   const int ty = rest % tg.nty;
@@ -416,11 +412,64 @@ k_full_tile(TG g, Coef<T> C, const T *__restrict__ psi, const T *__restrict__ u,
   }
   if (partials) {
     const double s = block_sum(acc, red);
-    if (threadIdx.x == 0) partials[lt] = s;
+    if (threadIdx.x == 0) partials[li] = s;
   }
 }
 
+// Tiles holding any node of class >= 1 (one workgroup per tile).
+__global__ __launch_bounds__(256) void k_tile_flags(TG g, TileGeom tg,
+                                                    const uint8_t *__restrict__ cls,
+                                                    int *__restrict__ flags) {
+  const int t = blockIdx.x;
+  const int tx = t % tg.ntx, rest = t / tg.ntx, ty = rest % tg.nty, tz = rest / tg.nty;
+  const int x0 = tx * TX, y0 = ty * TY, k0 = tz * tg.kz, k1 = min(k0 + tg.kz, g.nz);
+  int any = 0;
+  const int n = TX * TY * (k1 - k0);
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const int x = x0 + e % TX, y = y0 + (e / TX) % TY, k = k0 + e / (TX * TY);
+    if (x < g.nx && y < g.ny && cls[x + g.nx * (y + g.ny * k)] >= 1) any = 1;
+  }
+  any = __syncthreads_or(any);
+  if (threadIdx.x == 0) flags[t] = any;
+}
+
+// Ids of the flagged tiles in increasing order and their number (one
+// workgroup: per-thread chunk counts, an exclusive scan in LDS, then writes).
+__global__ __launch_bounds__(1024) void k_tile_compact(const int *__restrict__ flags, int n,
+                                                       int *__restrict__ ids,
+                                                       int *__restrict__ count) {
+  __shared__ int off[1024];
+  const int t = threadIdx.x;
+  const int chunk = (n + 1023) / 1024;
+  const int lo = min(n, t * chunk), hi = min(n, lo + chunk);
+  int c = 0;
+  for (int i = lo; i < hi; ++i) c += flags[i] ? 1 : 0;
+  off[t] = c;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {  // inclusive scan
+    const int v = t >= d ? off[t - d] : 0;
+    __syncthreads();
+    off[t] += v;
+    __syncthreads();
+  }
+  int w = off[t] - c;
+  for (int i = lo; i < hi; ++i)
+    if (flags[i]) ids[w++] = i;
+  if (t == 1023) *count = off[1023];
+}
+
 }  // namespace
+
+hipError_t launch_active_tiles(const Level &L, const uint8_t *cls, int *flags, int *ids,
+                               int *count, hipStream_t st) {
+  const TG gg = make_tg(L.g);
+  const TileGeom tg = tile_geom(gg);
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(k_tile_flags, dim3(tg.ntiles), dim3(256), 0, st, gg, tg, cls, flags);
+  hipLaunchKernelGGL(k_tile_compact, dim3(1), dim3(1024), 0, st, (const int *)flags, tg.ntiles,
+                     ids, count);
+  return hipGetLastError();
+}
 
 bool tiled_ok(const Level &L) {
 #ifdef SBM_TILE_DISABLE
@@ -431,20 +480,25 @@ bool tiled_ok(const Level &L) {
   return L.g.dim == 3 && L.g.nx > 3 * TX && L.g.ny > 3 * TY;
 }
 
+TileGeom tile_geom_of(const Level &L) { return tile_geom(make_tg(L.g)); }
+
 template <typename T>
 hipError_t launch_rb_tiled(const Level &L, const T *psi, const Coef<T> &C, const T *u, const T *f,
                            T *u_out, double omega, int colour, hipStream_t st,
-                           const uint8_t *cls) {
+                           const uint8_t *cls, const TileList *tl) {
   const TG gg = make_tg(L.g);
   const TileGeom tg = tile_geom(gg);
-  const int grid = (tg.ntiles + 7) / 8 * 8;
+  const int n = tl ? tl->count : tg.ntiles;
+  if (n == 0) return hipSuccess;
+  const int grid = (n + 7) / 8 * 8;
+  const int *ids = tl ? tl->ids : nullptr;
   (void)hipGetLastError();
   if (cls)
     hipLaunchKernelGGL((k_rb_tile<T, true>), dim3(grid), dim3(NT), 0, st, gg, C, psi, u, f,
-                       u_out, (T)omega, colour, tg, cls);
+                       u_out, (T)omega, colour, tg, cls, ids, n);
   else
     hipLaunchKernelGGL((k_rb_tile<T, false>), dim3(grid), dim3(NT), 0, st, gg, C, psi, u, f,
-                       u_out, (T)omega, colour, tg, cls);
+                       u_out, (T)omega, colour, tg, cls, ids, n);
   return hipGetLastError();
 }
 
@@ -453,17 +507,20 @@ int tiled_partials(const Level &L) { return tile_geom(make_tg(L.g)).ntiles; }
 template <typename T>
 hipError_t launch_residual_tiled(const Level &L, const T *psi, const Coef<T> &C, const T *u,
                                  const T *f, T *r, double *partials, hipStream_t st,
-                                 const uint8_t *cls) {
+                                 const uint8_t *cls, const TileList *tl) {
   const TG gg = make_tg(L.g);
   const TileGeom tg = tile_geom(gg);
-  const int grid = (tg.ntiles + 7) / 8 * 8;
+  const int n = tl ? tl->count : tg.ntiles;
+  if (n == 0) return hipSuccess;
+  const int grid = (n + 7) / 8 * 8;
+  const int *ids = tl ? tl->ids : nullptr;
   (void)hipGetLastError();
   if (cls)
     hipLaunchKernelGGL((k_full_tile<T, 0, true>), dim3(grid), dim3(NT), 0, st, gg, C, psi, u, f,
-                       r, partials, tg, cls);
+                       r, partials, tg, cls, ids, n);
   else
     hipLaunchKernelGGL((k_full_tile<T, 0, false>), dim3(grid), dim3(NT), 0, st, gg, C, psi, u, f,
-                       r, partials, tg, cls);
+                       r, partials, tg, cls, ids, n);
   return hipGetLastError();
 }
 
@@ -475,23 +532,23 @@ hipError_t launch_apply_dot_tiled(const Level &L, const double *p, double *q, do
   (void)hipGetLastError();
   hipLaunchKernelGGL((k_full_tile<double, 1, false>), dim3(grid), dim3(NT), 0, st, gg, L.c64,
                      L.psi64, p, (const double *)nullptr, q, partials, tg,
-                     (const uint8_t *)nullptr);
+                     (const uint8_t *)nullptr, (const int *)nullptr, 0);
   return hipGetLastError();
 }
 
 template hipError_t launch_residual_tiled<double>(const Level &, const double *,
                                                   const Coef<double> &, const double *,
                                                   const double *, double *, double *, hipStream_t,
-                                                  const uint8_t *);
+                                                  const uint8_t *, const TileList *);
 template hipError_t launch_residual_tiled<float>(const Level &, const float *, const Coef<float> &,
                                                  const float *, const float *, float *, double *,
-                                                 hipStream_t, const uint8_t *);
+                                                 hipStream_t, const uint8_t *, const TileList *);
 
 template hipError_t launch_rb_tiled<double>(const Level &, const double *, const Coef<double> &,
                                             const double *, const double *, double *, double,
-                                            int, hipStream_t, const uint8_t *);
+                                            int, hipStream_t, const uint8_t *, const TileList *);
 template hipError_t launch_rb_tiled<float>(const Level &, const float *, const Coef<float> &,
                                            const float *, const float *, float *, double, int,
-                                           hipStream_t, const uint8_t *);
+                                           hipStream_t, const uint8_t *, const TileList *);
 
 }  // namespace sbm
