@@ -97,8 +97,10 @@ hipError_t launch_apply_dot_tiled(const Level &L, const double *p, double *q, do
                                   hipStream_t st);
 // Number of partial sums launch_residual / launch_apply_dot write for level L.
 int stencil_partials(const Level &L);
+// fc = R r (full weighting); with ec the coarse correction is zeroed too.
 template <typename T>
-hipError_t launch_restrict(const Level &F, const Level &Cl, const T *r, T *fc, hipStream_t st);
+hipError_t launch_restrict(const Level &F, const Level &Cl, const T *r, T *fc, hipStream_t st,
+                           T *ec = nullptr);
 template <typename T>
 hipError_t launch_prolong_add(const Level &F, const Level &Cl, const T *e, T *u, hipStream_t st);
 template <typename T>

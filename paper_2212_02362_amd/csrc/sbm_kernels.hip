@@ -179,7 +179,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_half(Geom g, Coef<T> C, const T *
 // around the coincident fine node 2I; fine nodes outside the box are absent.
 template <typename T, int DIM>
 __global__ __launch_bounds__(kBlock) void k_restrict(Geom gf, Geom gc, const T *__restrict__ r,
-                                                     T *__restrict__ fc) {
+                                                     T *__restrict__ fc, T *__restrict__ ec) {
   const int64_t id = (int64_t)xcd_block() * kBlock + threadIdx.x;
   if (id >= gc.nn) return;
   int I, J, K;
@@ -208,8 +208,10 @@ __global__ __launch_bounds__(kBlock) void k_restrict(Geom gf, Geom gc, const T *
   }
   const T scale = (DIM == 3) ? T(0.125) : T(0.25);
 #pragma unroll
-  for (int c = 0; c < DIM; ++c)
+  for (int c = 0; c < DIM; ++c) {
     fc[c * gc.nn + id] = is_dirichlet(gc, I, J, K, c) ? T(0) : acc[c] * scale;
+    if (ec) ec[c * gc.nn + id] = T(0);  // the coarse correction starts from zero
+  }
 }
 
 // u_fine += P e_coarse (multilinear, node-centred) on free fine DOF.
@@ -1102,9 +1104,11 @@ hipError_t launch_rb_half(const Level &L, const T *psi, const Coef<T> &C, const 
 }
 
 template <typename T>
-hipError_t launch_restrict(const Level &F, const Level &Cl, const T *r, T *fc, hipStream_t st) {
-  if (F.g.dim == 3) SBM_LAUNCH((k_restrict<T, 3>), grid_blocks(Cl.g.nn), kBlock, st, F.g, Cl.g, r, fc);
-  SBM_LAUNCH((k_restrict<T, 2>), grid_blocks(Cl.g.nn), kBlock, st, F.g, Cl.g, r, fc);
+hipError_t launch_restrict(const Level &F, const Level &Cl, const T *r, T *fc, hipStream_t st,
+                           T *ec) {
+  if (F.g.dim == 3)
+    SBM_LAUNCH((k_restrict<T, 3>), grid_blocks(Cl.g.nn), kBlock, st, F.g, Cl.g, r, fc, ec);
+  SBM_LAUNCH((k_restrict<T, 2>), grid_blocks(Cl.g.nn), kBlock, st, F.g, Cl.g, r, fc, ec);
 }
 
 template <typename T>
@@ -1321,7 +1325,7 @@ hipError_t launch_sensitivity(const Level &L, double lam, double mu, const Tract
                                         const T *, T *, double, int, hipStream_t,              \
                                         const uint8_t *);                                      \
   template hipError_t launch_restrict<T>(const Level &, const Level &, const T *, T *,          \
-                                         hipStream_t);                                         \
+                                         hipStream_t, T *);                                    \
   template hipError_t launch_prolong_add<T>(const Level &, const Level &, const T *, T *,       \
                                             hipStream_t);                                      \
   template hipError_t launch_fill<T>(T *, int64_t, T, hipStream_t);                             \

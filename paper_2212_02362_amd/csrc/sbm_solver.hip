@@ -392,10 +392,9 @@ static hipError_t vcycle(sbm_ctx *c, int l, T *x, const T *f, T *tmp) {
   }
   {
     ProfScope ps(c, SBM_PROF_RESTRICT, l == 0);
-    if ((e = launch_restrict<T>(L, C, tmp, Prec<T>::f(C), c->st)) != hipSuccess) return e;
+    if ((e = launch_restrict<T>(L, C, tmp, Prec<T>::f(C), c->st, Prec<T>::e(C))) != hipSuccess)
+      return e;
   }
-  const int64_t nvc = (int64_t)c->dim * C.g.nn;
-  if ((e = launch_fill<T>(Prec<T>::e(C), nvc, T(0), c->st)) != hipSuccess) return e;
   if ((e = vcycle<T>(c, l + 1, Prec<T>::e(C), Prec<T>::f(C), Prec<T>::t(C))) != hipSuccess) return e;
   {
     ProfScope ps(c, SBM_PROF_PROLONG, l == 0);

@@ -60,7 +60,7 @@ def test_hierarchy_psi_and_coarse_apply(ncell):
             nc = tuple(n // 2 for n in nc)
 
 
-@pytest.mark.parametrize("ncell", GRIDS)
+@pytest.mark.parametrize("ncell", GRIDS + [(8, 6, 10), (20, 16)])
 def test_residual_and_smoothers(ncell):
     p, S, psi, mask, u, f = _setup(ncell, seed=1)
     u = np.where(mask == 1, oracle.dirichlet(p.ncell, p.kind, p.val)[1], u)
