@@ -462,7 +462,9 @@ def main():
                    "cycles": cyc64, "final_rel_residual": max(fin64), "status": st64},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_rb_half<double,3> (finest-level Gauss-Seidel half-sweep)",
+                     "kernel": ("k_rb_tile<double> (LDS-tiled finest-level Gauss-Seidel half-sweep)"
+                                if p.ncell[0] + 1 > 192 and p.dim == 3 else
+                                "k_rb_half<double,3> (finest-level Gauss-Seidel half-sweep)"),
                      "algo_bytes_per_launch": by, "avg_launch_us": avg_ms * 1e3,
                      "timing": "HIP events around each finest-level launch, over the profiled "
                                "pass that follows the timed region (same solves, launched one "
