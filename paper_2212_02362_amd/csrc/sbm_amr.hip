@@ -865,15 +865,12 @@ static hipError_t amr_fas(sbm_amr_ctx *c, int a) {
   hipError_t e;
   T *xf = AV<T>::x(F), *ff = AV<T>::f(F), *wf = AV<T>::w(F), *tf = AV<T>::tmp(F);
   T *xc = AV<T>::x(C), *fc = AV<T>::f(C), *xi = AV<T>::xinj(C), *tc = AV<T>::tmp(C);
-  {
-    AmrProf pr(c, SBM_PROF_GHOST, fin);
-    if ((e = launch_ghost<T>(F.L, C.L, F.cls, xc, xf, c->st, F.tiles())) != hipSuccess) return e;
-  }
+  // The cycle runs in correction form from zero on every level, and nothing
+  // has touched level a-1 when level a is entered (injections write class-1
+  // nodes only), so the ghosts of level a already hold their fill from x_c =
+  // 0 (zero), and the smoother leaves ghosts unchanged: the ghost fills before
+  // and after pre-smoothing would rewrite the same values and are skipped.
   if ((e = amr_smooth<T>(c, a, xf, ff, tf, c->opt.nu_pre)) != hipSuccess) return e;
-  {
-    AmrProf pr(c, SBM_PROF_GHOST, fin);
-    if ((e = launch_ghost<T>(F.L, C.L, F.cls, xc, xf, c->st, F.tiles())) != hipSuccess) return e;
-  }
   {
     AmrProf pr(c, SBM_PROF_RESIDUAL, fin);
     if ((e = launch_residual<T>(F.L, AV<T>::psi(F), AV<T>::coef(F), xf, ff, wf, nullptr, c->st,
