@@ -184,23 +184,29 @@ __global__ __launch_bounds__(kBlock) void k_restrict(Geom gf, Geom gc, const T *
   if (id >= gc.nn) return;
   int I, J, K;
   node_ijk(gc, id, I, J, K);
+  // Branch-free gather (all 27 loads in flight together): a neighbour outside
+  // the box is read at the centre with weight 0, which adds an exact zero, so
+  // the sum equals the one over the neighbours inside, in the same order.
   T acc[3] = {T(0), T(0), T(0)};
-  const int zlo = (DIM == 3) ? -1 : 0, zhi = (DIM == 3) ? 1 : 0;
-  for (int dz = zlo; dz <= zhi; ++dz) {
+  constexpr int ZLO = (DIM == 3) ? -1 : 0, ZHI = (DIM == 3) ? 1 : 0;
+#pragma unroll
+  for (int dz = ZLO; dz <= ZHI; ++dz) {
     const int fk = 2 * K + dz;
-    if (fk < 0 || fk >= gf.nz) continue;
-    const T wz = dz == 0 ? T(1) : T(0.5);
+    const bool okz = fk >= 0 && fk < gf.nz;
+    const T wz = okz ? (dz == 0 ? T(1) : T(0.5)) : T(0);
+    const int fkc = okz ? fk : 2 * K;
 #pragma unroll
     for (int dy = -1; dy <= 1; ++dy) {
       const int fj = 2 * J + dy;
-      if (fj < 0 || fj >= gf.ny) continue;
-      const T wy = dy == 0 ? T(1) : T(0.5);
+      const bool oky = fj >= 0 && fj < gf.ny;
+      const T wy = oky ? (dy == 0 ? T(1) : T(0.5)) : T(0);
+      const int fjc = oky ? fj : 2 * J;
 #pragma unroll
       for (int dx = -1; dx <= 1; ++dx) {
         const int fi = 2 * I + dx;
-        if (fi < 0 || fi >= gf.nx) continue;
-        const T w = wz * wy * (dx == 0 ? T(1) : T(0.5));
-        const int64_t q = fi + (int64_t)gf.nx * (fj + (int64_t)gf.ny * fk);
+        const bool okx = fi >= 0 && fi < gf.nx;
+        const T w = wz * wy * (okx ? (dx == 0 ? T(1) : T(0.5)) : T(0));
+        const int64_t q = (okx ? fi : 2 * I) + (int64_t)gf.nx * (fjc + (int64_t)gf.ny * fkc);
 #pragma unroll
         for (int c = 0; c < DIM; ++c) acc[c] += w * r[c * gf.nn + q];
       }
