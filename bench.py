@@ -146,7 +146,7 @@ def _bench_amr(args):
                    "cycles": r["cyc"], "final_rel_residual": max(r["fin"]), "status": r["st"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_rb_half<double,3> on the finest adaptive level (dense storage, "
+                     "kernel": "k_rb_half<double,3,false> on the finest adaptive level (dense storage, "
                                "class mask)",
                      "algo_bytes_per_launch": by, "avg_launch_us": avg_ms * 1e3,
                      "timing": "HIP events around each finest-level launch, one profiled solve "
@@ -227,7 +227,7 @@ def _traffic(kernel_key, nodes):
     return ent.get("hbm_bytes_per_launch")
 
 
-TRAFFIC_KERNEL = "k_rb_half<double,3>"
+TRAFFIC_KERNEL = "k_rb_half<double,3,false>"
 COPY_BYTES = 400_000_000  # calibration copy: this many bytes read and written
 
 
@@ -277,7 +277,7 @@ def _counter_summary(fetch_dir, write_dir):
                     continue
                 v = float(r["Counter_Value"]) * 1024.0  # KiB -> bytes
                 name = r["Kernel_Name"]
-                if "k_rb_half<double, 3>" in name:
+                if "k_rb_half<double, 3, false>" in name:
                     kern.append(v)
                 elif "copyBuffer" in name and v > 0.25 * COPY_BYTES:
                     copy.append(v)
@@ -464,7 +464,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": ("k_rb_tile<double> (LDS-tiled finest-level Gauss-Seidel half-sweep)"
                                 if p.ncell[0] + 1 > 192 and p.dim == 3 else
-                                "k_rb_half<double,3> (finest-level Gauss-Seidel half-sweep)"),
+                                "k_rb_half<double,3,false> (finest-level Gauss-Seidel half-sweep)"),
                      "algo_bytes_per_launch": by, "avg_launch_us": avg_ms * 1e3,
                      "timing": "HIP events around each finest-level launch, over the profiled "
                                "pass that follows the timed region (same solves, launched one "

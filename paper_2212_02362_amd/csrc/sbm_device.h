@@ -52,12 +52,17 @@ struct Coef {
   T cm[3];     // cross (lambda-mu) part
 };
 
+// Bit 3F is set when node (i, j, k) lies on face F (x-,x+,y-,y+,z-,z+), so
+// that (dmask >> comp) & face_bits tests every face at once (no branches).
+__device__ __forceinline__ uint32_t face_bits(const Geom &g, int i, int j, int k) {
+  uint32_t b = (i == 0 ? 1u : 0u) | (i == g.nx - 1 ? 8u : 0u) | (j == 0 ? 64u : 0u) |
+               (j == g.ny - 1 ? 512u : 0u);
+  if (g.dim == 3) b |= (k == 0 ? 4096u : 0u) | (k == g.nz - 1 ? 32768u : 0u);
+  return b;
+}
+
 __device__ __forceinline__ bool is_dirichlet(const Geom &g, int i, int j, int k, int comp) {
-  const uint32_t m = g.dmask >> comp;
-  bool d = ((i == 0) && (m & 1u)) || ((i == g.nx - 1) && ((m >> 3) & 1u)) ||
-           ((j == 0) && ((m >> 6) & 1u)) || ((j == g.ny - 1) && ((m >> 9) & 1u));
-  if (g.dim == 3) d = d || ((k == 0) && ((m >> 12) & 1u)) || ((k == g.nz - 1) && ((m >> 15) & 1u));
-  return d;
+  return ((g.dmask >> comp) & face_bits(g, i, j, k)) != 0u;
 }
 
 // Node coordinates of a linear node index.
@@ -140,11 +145,12 @@ __device__ __forceinline__ void stencil3(const Coef<T> &C, const T (&P)[2][2][2]
 // Evaluates (K u)(n) for all components and the diagonal at node (i, j, k).
 // Neighbour offsets are clamped at the box boundary: every term that would
 // reach outside carries a zero psi weight, so the clamped value never counts.
+// ctr (optional) receives u at the node itself.
 template <typename T, int DIM>
 __device__ __forceinline__ void node_stencil(const Geom &g, const Coef<T> &C,
                                              const T *__restrict__ psi,
                                              const T *__restrict__ u, int i, int j, int k,
-                                             T out[3], T diag[3]) {
+                                             T out[3], T diag[3], T *ctr = nullptr) {
   // every index fits in 32 bits (nodes x components < 2^31)
   const int sy = g.nx, sz = g.nx * g.ny;
   const int idx = i + sy * j + sz * k;
@@ -153,8 +159,14 @@ __device__ __forceinline__ void node_stencil(const Geom &g, const Coef<T> &C,
   const int nn = (int)g.nn;
   if constexpr (DIM == 3) {
     const int oz[3] = {k > 0 ? -sz : 0, 0, k < g.nz - 1 ? sz : 0};
-    // cells around the node: P[oz][oy][ox] is cell (i-1+ox, j-1+oy, k-1+oz)
-    T P[2][2][2];
+    // Gather: the 8 cells around the node and the 45 displacement values eq. K
+    // reads (all components at the node and its 6 face neighbours, the two
+    // in-plane components at the 12 edge neighbours) are loaded before any of
+    // them is used, so that every load of the thread is in flight at once.
+    // P[oz][oy][ox] is cell (i-1+ox, j-1+oy, k-1+oz), read from a clamped cell
+    // and zeroed outside the box.
+    T pv[2][2][2];
+    bool pin[2][2][2];
 #pragma unroll
     for (int c2 = 0; c2 < 2; ++c2)
 #pragma unroll
@@ -162,13 +174,52 @@ __device__ __forceinline__ void node_stencil(const Geom &g, const Coef<T> &C,
 #pragma unroll
         for (int c0 = 0; c0 < 2; ++c0) {
           const int xi = i - 1 + c0, yj = j - 1 + c1, zk = k - 1 + c2;
-          const bool in = xi >= 0 && xi < g.cx && yj >= 0 && yj < g.cy && zk >= 0 && zk < g.cz;
-          P[c2][c1][c0] = in ? psi[xi + g.cx * (yj + g.cy * zk)] : T(0);
+          pin[c2][c1][c0] = xi >= 0 && xi < g.cx && yj >= 0 && yj < g.cy && zk >= 0 && zk < g.cz;
+          const int xc = min(max(xi, 0), g.cx - 1), yc = min(max(yj, 0), g.cy - 1);
+          const int zc = min(max(zk, 0), g.cz - 1);
+          pv[c2][c1][c0] = psi[xc + g.cx * (yc + g.cy * zc)];
         }
+    T V[3][27];  // V[c][(dx+1) + 3 (dy+1) + 9 (dz+1)]
+    auto ld = [&](int c, int dx, int dy, int dz) {
+      V[c][(dx + 1) + 3 * (dy + 1) + 9 * (dz + 1)] =
+          u[c * nn + idx + ox[dx + 1] + oy[dy + 1] + oz[dz + 1]];
+    };
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      ld(c, 0, 0, 0);
+      ld(c, -1, 0, 0);
+      ld(c, 1, 0, 0);
+      ld(c, 0, -1, 0);
+      ld(c, 0, 1, 0);
+      ld(c, 0, 0, -1);
+      ld(c, 0, 0, 1);
+    }
+#pragma unroll
+    for (int pl = 0; pl < 3; ++pl) {
+      const int a = (pl == 2) ? 1 : 0, b = (pl == 0) ? 1 : 2;
+#pragma unroll
+      for (int sa = -1; sa <= 1; sa += 2)
+#pragma unroll
+        for (int sb = -1; sb <= 1; sb += 2) {
+          int d[3] = {0, 0, 0};
+          d[a] = sa;
+          d[b] = sb;
+          ld(a, d[0], d[1], d[2]);
+          ld(b, d[0], d[1], d[2]);
+        }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    T P[2][2][2];
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      P[q >> 2][(q >> 1) & 1][q & 1] = pin[q >> 2][(q >> 1) & 1][q & 1] ? pv[q >> 2][(q >> 1) & 1][q & 1] : T(0);
     auto U = [&](int c, int dx, int dy, int dz) -> T {
-      return u[c * nn + idx + ox[dx + 1] + oy[dy + 1] + oz[dz + 1]];
+      return V[c][(dx + 1) + 3 * (dy + 1) + 9 * (dz + 1)];
     };
     stencil3<T>(C, P, U, out, diag);
+    if (ctr)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) ctr[c] = U(c, 0, 0, 0);
   } else {
     T P[2][2];  // P[oy][ox]
 #pragma unroll
@@ -177,7 +228,9 @@ __device__ __forceinline__ void node_stencil(const Geom &g, const Coef<T> &C,
       for (int c0 = 0; c0 < 2; ++c0) {
         const int xi = i - 1 + c0, yj = j - 1 + c1;
         const bool in = xi >= 0 && xi < g.cx && yj >= 0 && yj < g.cy;
-        P[c1][c0] = in ? psi[xi + g.cx * yj] : T(0);
+        const int xc = min(max(xi, 0), g.cx - 1), yc = min(max(yj, 0), g.cy - 1);
+        const T v = psi[xc + g.cx * yc];
+        P[c1][c0] = in ? v : T(0);
       }
     T E[2][2];
 #pragma unroll
@@ -215,6 +268,11 @@ __device__ __forceinline__ void node_stencil(const Geom &g, const Coef<T> &C,
     out[1] -= ry;
     out[2] = T(0);
     diag[2] = T(0);
+    if (ctr) {
+      ctr[0] = ux0;
+      ctr[1] = uy0;
+      ctr[2] = T(0);
+    }
   }
 }
 

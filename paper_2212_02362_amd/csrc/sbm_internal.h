@@ -41,10 +41,13 @@ struct Level {
 
 // Column tiles of the tiled 3D kernels: kTileX x kTileY nodes in x, y over a
 // chunk of kz planes; tile id = tx + ntx (ty + nty tz).
+#ifndef SBM_TILE_TX
+#define SBM_TILE_TX 64
+#endif
 #ifndef SBM_TILE_TY
 #define SBM_TILE_TY 8
 #endif
-constexpr int kTileX = 64, kTileY = SBM_TILE_TY;
+constexpr int kTileX = SBM_TILE_TX, kTileY = SBM_TILE_TY;
 struct TileGeom {
   int ntx, nty, kz, ntiles;
 };

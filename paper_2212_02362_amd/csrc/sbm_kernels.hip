@@ -41,9 +41,10 @@ __global__ __launch_bounds__(kBlock) void k_apply(Geom g, Coef<T> C, const T *__
 }
 
 // r = f - K u on free DOF (0 on displacement DOF); optional per-block sums of r^2.
-// With a class array (adaptive levels) only classes 1-3 (interior, interface,
-// first outer layer: the padded region) carry a residual; elsewhere r = 0.
-template <typename T, int DIM>
+// MASK: a class array is given and only classes 1-3 (interior, interface,
+// first outer layer: the padded region of an adaptive level) carry a
+// residual; elsewhere r = 0.
+template <typename T, int DIM, bool MASK>
 __global__ __launch_bounds__(kBlock) void k_residual(Geom g, Coef<T> C, const T *__restrict__ psi,
                                                      const T *__restrict__ u,
                                                      const T *__restrict__ f, T *__restrict__ r,
@@ -52,18 +53,21 @@ __global__ __launch_bounds__(kBlock) void k_residual(Geom g, Coef<T> C, const T 
   __shared__ double lds[kBlock / 64 + 1];
   const int64_t id = (int64_t)xcd_block() * kBlock + threadIdx.x;
   double ss = 0.0;
-  if (id < g.nn && cls && (cls[id] == 0 || cls[id] > 3)) {
+  if (id < g.nn && MASK && (cls[id] == 0 || cls[id] > 3)) {
     for (int c = 0; c < DIM; ++c) r[c * g.nn + id] = T(0);
   } else if (id < g.nn) {
     int i, j, k;
     node_ijk(g, id, i, j, k);
-    T out[3], dg[3];
+    // f is loaded with the stencil's values (one round trip per thread)
+    T fv[3], out[3], dg[3];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) fv[c] = f[c * g.nn + id];
     node_stencil<T, DIM>(g, C, psi, u, i, j, k, out, dg);
+    const uint32_t fb = face_bits(g, i, j, k);
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
-      const int64_t q = c * g.nn + id;
-      const T v = is_dirichlet(g, i, j, k, c) ? T(0) : f[q] - out[c];
-      if (r) r[q] = v;
+      const T v = ((g.dmask >> c) & fb) ? T(0) : fv[c] - out[c];
+      if (r) r[c * g.nn + id] = v;
       ss += (double)v * (double)v;
     }
   }
@@ -90,21 +94,24 @@ __global__ __launch_bounds__(kBlock) void k_residual_cast(Geom g, Coef<double> C
   const double inv_s = sn > 0.0 ? 1.0 / sn : 0.0;
   int i, j, k;
   node_ijk(g, id, i, j, k);
-  double out[3], dg[3];
+  double fv[3], out[3], dg[3];
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) fv[c] = f[c * g.nn + id];
   node_stencil<double, DIM>(g, C, psi, u, i, j, k, out, dg);
+  const uint32_t fb = face_bits(g, i, j, k);
 #pragma unroll
   for (int c = 0; c < DIM; ++c) {
-    const int64_t q = c * g.nn + id;
-    r32[q] = is_dirichlet(g, i, j, k, c) ? 0.0f : (float)((f[q] - out[c]) * inv_s);
+    const float v = (float)((fv[c] - out[c]) * inv_s);
+    r32[c * g.nn + id] = ((g.dmask >> c) & fb) ? 0.0f : v;
   }
 }
 
 // ------------------------------------------------------------- smoothers --
 
 // Damped Jacobi (Sec. 2.3): u_out = u + omega D^-1 (f - K u) on free DOF.
-// With a class array only class-1 nodes (the unknowns of an adaptive level)
-// are relaxed; every other node is copied.
-template <typename T, int DIM>
+// MASK: a class array is given and only class-1 nodes (the unknowns of an
+// adaptive level) are relaxed; every other node is copied.
+template <typename T, int DIM, bool MASK>
 __global__ __launch_bounds__(kBlock) void k_jacobi(Geom g, Coef<T> C, const T *__restrict__ psi,
                                                    const T *__restrict__ u,
                                                    const T *__restrict__ f,
@@ -112,19 +119,21 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(Geom g, Coef<T> C, const T *_
                                                    const uint8_t *__restrict__ cls) {
   const int64_t id = (int64_t)xcd_block() * kBlock + threadIdx.x;
   if (id >= g.nn) return;
-  if (cls && cls[id] != 1) {
+  if (MASK && cls[id] != 1) {
     for (int c = 0; c < DIM; ++c) u_out[c * g.nn + id] = u[c * g.nn + id];
     return;
   }
   int i, j, k;
   node_ijk(g, id, i, j, k);
-  T out[3], dg[3];
-  node_stencil<T, DIM>(g, C, psi, u, i, j, k, out, dg);
+  T fv[3], out[3], dg[3], uc[3];
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) fv[c] = f[c * g.nn + id];
+  node_stencil<T, DIM>(g, C, psi, u, i, j, k, out, dg, uc);
+  const uint32_t fb = face_bits(g, i, j, k);
 #pragma unroll
   for (int c = 0; c < DIM; ++c) {
-    const int64_t q = c * g.nn + id;
-    const T uc = u[q];
-    u_out[q] = is_dirichlet(g, i, j, k, c) ? uc : uc + omega * (f[q] - out[c]) / dg[c];
+    const T w = ((g.dmask >> c) & fb) ? T(0) : omega;
+    u_out[c * g.nn + id] = uc[c] + w * (fv[c] - out[c]) / dg[c];
   }
 }
 
@@ -132,8 +141,9 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(Geom g, Coef<T> C, const T *_
 // ((x+y+z) mod 2) is relaxed from the state at the start of the half-sweep,
 // all components together; nodes of the other colour are copied.  One thread
 // owns the x-pair (2p, 2p+1) of a row: one node of each colour.
-// With a class array only class-1 nodes are relaxed (adaptive levels).
-template <typename T, int DIM>
+// MASK: a class array is given and only class-1 nodes are relaxed (adaptive
+// levels).
+template <typename T, int DIM, bool MASK>
 __global__ __launch_bounds__(kBlock) void k_rb_half(Geom g, Coef<T> C, const T *__restrict__ psi,
                                                     const T *__restrict__ u,
                                                     const T *__restrict__ f,
@@ -150,26 +160,42 @@ __global__ __launch_bounds__(kBlock) void k_rb_half(Geom g, Coef<T> C, const T *
   const int par = (colour + j + k) & 1;
   const int iu = 2 * p + par, ic = 2 * p + 1 - par;
   const int64_t row = (int64_t)g.nx * (j + (int64_t)g.ny * k);
-  // both nodes of the pair are stored back to back at the end, so that every
-  // written line is complete in L2 when it leaves
-  T nv[3] = {T(0), T(0), T(0)};
-  if (iu < g.nx && cls && cls[row + iu] != 1) {
-#pragma unroll
-    for (int c = 0; c < DIM; ++c) nv[c] = u[c * g.nn + row + iu];
-  } else if (iu < g.nx) {
-    T out[3], dg[3];
-    node_stencil<T, DIM>(g, C, psi, u, iu, j, k, out, dg);
-#pragma unroll
-    for (int c = 0; c < DIM; ++c) {
-      const int64_t q = c * g.nn + row + iu;
-      const T uc = u[q];
-      nv[c] = is_dirichlet(g, iu, j, k, c) ? uc : uc + omega * (f[q] - out[c]) / dg[c];
-    }
-  }
+  // In an odd row the last pair has one node; the missing one is replaced by
+  // its partner in every load (in range) and is not stored.
+  const bool oku = iu < g.nx, okc = ic < g.nx;
+  const int iq = oku ? iu : ic;
+  const int64_t qu = row + iq, qc = row + (okc ? ic : iu);
+  // f and the copied node are loaded before the stencil so that every load of
+  // the thread is in flight together
+  T fv[3], cv[3];
 #pragma unroll
   for (int c = 0; c < DIM; ++c) {
-    if (iu < g.nx) u_out[c * g.nn + row + iu] = nv[c];
-    if (ic < g.nx) u_out[c * g.nn + row + ic] = u[c * g.nn + row + ic];
+    fv[c] = f[c * g.nn + qu];
+    cv[c] = u[c * g.nn + qc];
+  }
+  T nv[3] = {T(0), T(0), T(0)};
+  if (MASK && cls[qu] != 1) {
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) nv[c] = u[c * g.nn + qu];
+  } else {
+    T out[3], dg[3], uc[3];
+    node_stencil<T, DIM>(g, C, psi, u, iq, j, k, out, dg, uc);
+    // a zero weight on displacement DOF keeps the update free of branches
+    const uint32_t fb = face_bits(g, iq, j, k);
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+      const T w = ((g.dmask >> c) & fb) ? T(0) : omega;
+      nv[c] = uc[c] + w * (fv[c] - out[c]) / dg[c];
+    }
+  }
+  // Both nodes of the pair are stored back to back, so that every written
+  // line is complete in L2 when it leaves.  The stores are unconditional (a
+  // lone node is written twice with its own value), which keeps the whole
+  // computation out of branches.
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) {
+    u_out[c * g.nn + qu] = oku ? nv[c] : cv[c];
+    u_out[c * g.nn + qc] = okc ? cv[c] : nv[c];
   }
 }
 
@@ -220,28 +246,71 @@ __global__ __launch_bounds__(kBlock) void k_restrict(Geom gf, Geom gc, const T *
   }
 }
 
-// u_fine += P e_coarse (multilinear, node-centred) on free fine DOF.
+// u_fine += P e_coarse (multilinear, node-centred) on free fine DOF.  One
+// thread per coarse node I owns the 2^d fine nodes 2I + delta (delta in
+// {0,1}^d): fine node 2I + delta takes the mean of the coarse corners
+// I + delta' with delta' <= delta, summed in z, y, x order (x fastest).
+// Loads are clamped at the last coarse / fine node; a fine node that does not
+// exist (2I + 1 past the end) is the clamped one and receives that node's own
+// value, so every store is unconditional and every load is in flight at once.
 template <typename T, int DIM>
 __global__ __launch_bounds__(kBlock) void k_prolong_add(Geom gf, Geom gc, const T *__restrict__ e,
                                                         T *__restrict__ u) {
+  constexpr int NZ = (DIM == 3) ? 2 : 1;
   const int64_t id = (int64_t)xcd_block() * kBlock + threadIdx.x;
-  if (id >= gf.nn) return;
-  int i, j, k;
-  node_ijk(gf, id, i, j, k);
-  const int i0 = i >> 1, j0 = j >> 1, k0 = k >> 1;
-  const int ni = (i & 1) ? 2 : 1, nj = (j & 1) ? 2 : 1, nk = (DIM == 3 && (k & 1)) ? 2 : 1;
-  const T w = T(1) / T(ni * nj * nk);
-  T acc[3] = {T(0), T(0), T(0)};
-  for (int b = 0; b < nk; ++b)
-    for (int a = 0; a < nj; ++a)
-      for (int o = 0; o < ni; ++o) {
-        const int64_t q = (i0 + o) + (int64_t)gc.nx * ((j0 + a) + (int64_t)gc.ny * (k0 + b));
+  if (id >= gc.nn) return;
+  int I, J, K;
+  node_ijk(gc, id, I, J, K);
+  const int I1 = min(I + 1, gc.nx - 1), J1 = min(J + 1, gc.ny - 1);
+  const int K1 = (DIM == 3) ? min(K + 1, gc.nz - 1) : K;
+  T ev[NZ][2][2][3], uv[NZ][2][2][3];
+  int64_t fq[NZ][2][2];
+  // the odd fine node of an axis exists unless 2I + 1 is past the end
+  const bool ex = 2 * I + 1 < gf.nx, ey = 2 * J + 1 < gf.ny, ez = DIM == 3 && 2 * K + 1 < gf.nz;
 #pragma unroll
-        for (int c = 0; c < DIM; ++c) acc[c] += e[c * gc.nn + q];
+  for (int b = 0; b < NZ; ++b)
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int o = 0; o < 2; ++o) {
+        const int64_t q = (o ? I1 : I) + (int64_t)gc.nx * ((a ? J1 : J) + (int64_t)gc.ny * (b ? K1 : K));
+        const int fi = 2 * I + (o && ex ? 1 : 0), fj = 2 * J + (a && ey ? 1 : 0);
+        const int fk = (DIM == 3) ? 2 * K + (b && ez ? 1 : 0) : 0;
+        fq[b][a][o] = fi + (int64_t)gf.nx * (fj + (int64_t)gf.ny * fk);
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+          ev[b][a][o][c] = e[c * gc.nn + q];
+          uv[b][a][o][c] = u[c * gf.nn + fq[b][a][o]];
+        }
       }
 #pragma unroll
-  for (int c = 0; c < DIM; ++c)
-    if (!is_dirichlet(gf, i, j, k, c)) u[c * gf.nn + id] += w * acc[c];
+  for (int dz = 0; dz < NZ; ++dz)
+#pragma unroll
+    for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < 2; ++dx) {
+        // a missing odd node stands in for its even neighbour (same address)
+        const int sx = (dx && ex) ? 1 : 0, sy = (dy && ey) ? 1 : 0, sz = (dz && ez) ? 1 : 0;
+        const T w = T(1) / T((dx ? 2 : 1) * (dy ? 2 : 1) * (dz ? 2 : 1));
+        T acc[3] = {T(0), T(0), T(0)};
+#pragma unroll
+        for (int b = 0; b <= dz; ++b)
+#pragma unroll
+          for (int a = 0; a <= dy; ++a)
+#pragma unroll
+            for (int o = 0; o <= dx; ++o)
+#pragma unroll
+              for (int c = 0; c < DIM; ++c) acc[c] += ev[b][a][o][c];
+        const uint32_t fb = face_bits(gf, 2 * I + sx, 2 * J + sy, 2 * K + sz);
+        // value of the node actually addressed: the stand-in's own if missing
+        const bool own = sx == dx && sy == dy && sz == dz;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+          const T add = ((gf.dmask >> c) & fb) ? T(0) : w * acc[c];
+          const T nv = uv[dz][dy][dx][c] + add;
+          if (own) u[c * gf.nn + fq[dz][dy][dx]] = nv;
+        }
+      }
 }
 
 // ----------------------------------------------------------------- vectors --
@@ -493,14 +562,14 @@ __global__ __launch_bounds__(kBlock) void k_apply_dot(Geom g, Coef<double> C,
   if (id < g.nn) {
     int i, j, k;
     node_ijk(g, id, i, j, k);
-    double out[3], dg[3];
-    node_stencil<double, DIM>(g, C, psi, p, i, j, k, out, dg);
+    double out[3], dg[3], pc[3];
+    node_stencil<double, DIM>(g, C, psi, p, i, j, k, out, dg, pc);
+    const uint32_t fb = face_bits(g, i, j, k);
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
-      const int64_t qi = c * g.nn + id;
-      const double v = is_dirichlet(g, i, j, k, c) ? 0.0 : out[c];
-      q[qi] = v;
-      ss += p[qi] * v;
+      const double v = ((g.dmask >> c) & fb) ? 0.0 : out[c];
+      q[c * g.nn + id] = v;
+      ss += pc[c] * v;
     }
   }
   const double s = block_sum(ss, lds);
@@ -1072,11 +1141,13 @@ hipError_t launch_residual(const Level &L, const T *psi, const Coef<T> &C, const
                            const T *f, T *r, double *partials, hipStream_t st,
                            const uint8_t *cls, const TileList *tl) {
   if (use_tiled(L)) return launch_residual_tiled<T>(L, psi, C, u, f, r, partials, st, cls, tl);
-  if (L.g.dim == 3)
-    SBM_LAUNCH((k_residual<T, 3>), grid_blocks(L.g.nn), kBlock, st, L.g, C, psi, u, f, r, partials,
-               cls);
-  SBM_LAUNCH((k_residual<T, 2>), grid_blocks(L.g.nn), kBlock, st, L.g, C, psi, u, f, r, partials,
-             cls);
+  const int nb = grid_blocks(L.g.nn);
+  if (L.g.dim == 3) {
+    if (cls) SBM_LAUNCH((k_residual<T, 3, true>), nb, kBlock, st, L.g, C, psi, u, f, r, partials, cls);
+    SBM_LAUNCH((k_residual<T, 3, false>), nb, kBlock, st, L.g, C, psi, u, f, r, partials, cls);
+  }
+  if (cls) SBM_LAUNCH((k_residual<T, 2, true>), nb, kBlock, st, L.g, C, psi, u, f, r, partials, cls);
+  SBM_LAUNCH((k_residual<T, 2, false>), nb, kBlock, st, L.g, C, psi, u, f, r, partials, cls);
 }
 
 hipError_t launch_residual_cast(const Level &L, const double *u, const double *f, float *r32,
@@ -1091,11 +1162,13 @@ hipError_t launch_residual_cast(const Level &L, const double *u, const double *f
 template <typename T>
 hipError_t launch_jacobi(const Level &L, const T *psi, const Coef<T> &C, const T *u, const T *f,
                          T *u_out, double omega, hipStream_t st, const uint8_t *cls) {
-  if (L.g.dim == 3)
-    SBM_LAUNCH((k_jacobi<T, 3>), grid_blocks(L.g.nn), kBlock, st, L.g, C, psi, u, f, u_out,
-               (T)omega, cls);
-  SBM_LAUNCH((k_jacobi<T, 2>), grid_blocks(L.g.nn), kBlock, st, L.g, C, psi, u, f, u_out, (T)omega,
-             cls);
+  const int nb = grid_blocks(L.g.nn);
+  if (L.g.dim == 3) {
+    if (cls) SBM_LAUNCH((k_jacobi<T, 3, true>), nb, kBlock, st, L.g, C, psi, u, f, u_out, (T)omega, cls);
+    SBM_LAUNCH((k_jacobi<T, 3, false>), nb, kBlock, st, L.g, C, psi, u, f, u_out, (T)omega, cls);
+  }
+  if (cls) SBM_LAUNCH((k_jacobi<T, 2, true>), nb, kBlock, st, L.g, C, psi, u, f, u_out, (T)omega, cls);
+  SBM_LAUNCH((k_jacobi<T, 2, false>), nb, kBlock, st, L.g, C, psi, u, f, u_out, (T)omega, cls);
 }
 
 template <typename T>
@@ -1104,9 +1177,18 @@ hipError_t launch_rb_half(const Level &L, const T *psi, const Coef<T> &C, const 
                           const uint8_t *cls) {
   const int64_t pairs = (int64_t)((L.g.nx + 1) / 2) * L.g.ny * L.g.nz;
   const int nb = grid_blocks(pairs);
-  if (L.g.dim == 3)
-    SBM_LAUNCH((k_rb_half<T, 3>), nb, kBlock, st, L.g, C, psi, u, f, u_out, (T)omega, colour, cls);
-  SBM_LAUNCH((k_rb_half<T, 2>), nb, kBlock, st, L.g, C, psi, u, f, u_out, (T)omega, colour, cls);
+  if (L.g.dim == 3) {
+    if (cls)
+      SBM_LAUNCH((k_rb_half<T, 3, true>), nb, kBlock, st, L.g, C, psi, u, f, u_out, (T)omega,
+                 colour, cls);
+    SBM_LAUNCH((k_rb_half<T, 3, false>), nb, kBlock, st, L.g, C, psi, u, f, u_out, (T)omega,
+               colour, cls);
+  }
+  if (cls)
+    SBM_LAUNCH((k_rb_half<T, 2, true>), nb, kBlock, st, L.g, C, psi, u, f, u_out, (T)omega,
+               colour, cls);
+  SBM_LAUNCH((k_rb_half<T, 2, false>), nb, kBlock, st, L.g, C, psi, u, f, u_out, (T)omega, colour,
+             cls);
 }
 
 template <typename T>
@@ -1120,8 +1202,8 @@ hipError_t launch_restrict(const Level &F, const Level &Cl, const T *r, T *fc, h
 template <typename T>
 hipError_t launch_prolong_add(const Level &F, const Level &Cl, const T *e, T *u, hipStream_t st) {
   if (F.g.dim == 3)
-    SBM_LAUNCH((k_prolong_add<T, 3>), grid_blocks(F.g.nn), kBlock, st, F.g, Cl.g, e, u);
-  SBM_LAUNCH((k_prolong_add<T, 2>), grid_blocks(F.g.nn), kBlock, st, F.g, Cl.g, e, u);
+    SBM_LAUNCH((k_prolong_add<T, 3>), grid_blocks(Cl.g.nn), kBlock, st, F.g, Cl.g, e, u);
+  SBM_LAUNCH((k_prolong_add<T, 2>), grid_blocks(Cl.g.nn), kBlock, st, F.g, Cl.g, e, u);
 }
 
 template <typename T>
