@@ -145,8 +145,10 @@ __device__ __forceinline__ void stencil3(const Coef<T> &C, const T (&P)[2][2][2]
 // Evaluates (K u)(n) for all components and the diagonal at node (i, j, k).
 // Neighbour offsets are clamped at the box boundary: every term that would
 // reach outside carries a zero psi weight, so the clamped value never counts.
-// ctr (optional) receives u at the node itself.
-template <typename T, int DIM>
+// ctr (optional) receives u at the node itself.  GATHER keeps every load
+// ahead of the arithmetic (a scheduling barrier); without it the compiler may
+// interleave them, which needs fewer registers.
+template <typename T, int DIM, bool GATHER = true>
 __device__ __forceinline__ void node_stencil(const Geom &g, const Coef<T> &C,
                                              const T *__restrict__ psi,
                                              const T *__restrict__ u, int i, int j, int k,
@@ -208,7 +210,7 @@ __device__ __forceinline__ void node_stencil(const Geom &g, const Coef<T> &C,
           ld(b, d[0], d[1], d[2]);
         }
     }
-    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (GATHER) __builtin_amdgcn_sched_barrier(0);
     T P[2][2][2];
 #pragma unroll
     for (int q = 0; q < 8; ++q)
@@ -300,6 +302,32 @@ __device__ __forceinline__ void node_diag(const Geom &g, const Coef<T> &C,
 #pragma unroll
     for (int a = 0; a < DIM; ++a) diag[c] += C.cd[c][a] * (E[a][0] + E[a][1]);
   }
+}
+
+// One 32-bit half of a double moved across lanes by a DPP control (lanes
+// whose source lies outside the row read zero).
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWMASK, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWMASK, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a wave, returned in every lane, without LDS
+// traffic: prefix sums inside each 16-lane row (row shifts 1, 2, 4, 8), the
+// row totals carried into rows 1 and 3 and then into rows 2 and 3 (row
+// broadcasts of lanes 15 and 31), the total read from lane 63.  The latency
+// of the bottom CG is dominated by these reductions.
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_move<0x111, 0xf>(v);  // row_shr:1
+  v += dpp_move<0x112, 0xf>(v);  // row_shr:2
+  v += dpp_move<0x114, 0xf>(v);  // row_shr:4
+  v += dpp_move<0x118, 0xf>(v);  // row_shr:8
+  v += dpp_move<0x142, 0xa>(v);  // row_bcast:15
+  v += dpp_move<0x143, 0xc>(v);  // row_bcast:31
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
 }
 
 // Sum over a block of kBlock threads in a fixed order; the result is valid in

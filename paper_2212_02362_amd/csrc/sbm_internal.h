@@ -146,6 +146,30 @@ hipError_t launch_bottom_cg(const Level &L, const T *psi, const Coef<T> &C, cons
 hipError_t launch_bottom_f32io(const Level &L, const float *f32, float *x32, double *f64,
                                double *x64, double *r, double *p, double *Ap, double rtol,
                                int maxit, int *iters, hipStream_t st);
+// The V-cycle from level l0 down to the bottom and back in one workgroup
+// with every vector of those levels in LDS (sbm_tail.hip).  tail_level gives
+// the highest level whose tail fits lds_max bytes of LDS (-1: none);
+// tail_upload writes the tail's level table (kTailArgBytes of device memory)
+// once per problem, after the psi hierarchy is in place, assembles the dense
+// bottom matrix into dense_A (kTailDenseBytes; nullptr: none) when the bottom
+// has few free DOF, and returns the LDS bytes; launch_tail runs the cycle on
+// x (in/out, level l0) for the load f (wide_bottom: a bottom of more than
+// kTailWaveBottom nodes, solved by the whole workgroup).
+constexpr int kTailMaxLevels = 6;
+constexpr size_t kTailArgBytes = 4096;
+constexpr size_t kTailDenseBytes = 32 * 32 * sizeof(double);
+constexpr int kTailWaveBottom = 64;  // bottoms up to this many nodes are solved in one wave
+struct TailOpts {
+  int nu_pre, nu_post, jacobi, reverse;
+  double omega, rtol;
+  int maxit;
+};
+int tail_level(const std::vector<Level> &L, int precision, size_t lds_max);
+hipError_t tail_upload(const std::vector<Level> &L, int precision, int l0, void *dev,
+                       double *dense_A, size_t *lds_bytes, hipStream_t st);
+template <typename T>
+hipError_t launch_tail(int dim, bool wide_bottom, const void *dev, size_t lds_bytes,
+                       T *x, const T *f, const TailOpts &o, int *iters, hipStream_t st);
 hipError_t launch_sensitivity(const Level &L, double lam, double mu, const Traction &tr,
                               const double *u, const double *adj, double lam_scale,
                               const double *design, int chain, double psi_floor, double *g,

@@ -87,6 +87,12 @@ struct sbm_ctx {
   std::string graph_error;
   double g_lam = NAN, g_mu = NAN;
   uint32_t g_dmask = 0;
+  // first level of the one-workgroup tail of the FP64 / FP32 cycle (-1: none),
+  // its level tables (device) and LDS bytes
+  int tail64 = -1, tail32 = -1;
+  char *tail_args = nullptr;
+  double *tail_A = nullptr;  // dense bottom matrix of the tails
+  size_t tail_lds64 = 0, tail_lds32 = 0;
 };
 
 // Brackets one launch sequence with an event pair when profiling is on.
@@ -264,6 +270,8 @@ static size_t carve(sbm_ctx *c, char *base) {
   c->b_Ap = cv.take<double>(nb);
   c->b_x64 = cv.take<double>(nb);
   c->b_r64 = cv.take<double>(nb);
+  c->tail_args = cv.take<char>(2 * (int64_t)kTailArgBytes);
+  c->tail_A = cv.take<double>((int64_t)(kTailDenseBytes / sizeof(double)));
   return cv.off + 256;
 }
 
@@ -376,6 +384,16 @@ static hipError_t bottom32(sbm_ctx *c, const float *f, float *x) {
 template <typename T>
 static hipError_t vcycle(sbm_ctx *c, int l, T *x, const T *f, T *tmp) {
   hipError_t e;
+  if (l == (sizeof(T) == 8 ? c->tail64 : c->tail32)) {
+    // the rest of the cycle in one workgroup (LDS-resident levels)
+    ProfScope ps(c, SBM_PROF_BOTTOM, true);
+    const TailOpts o{c->opt.nu_pre, c->opt.nu_post, c->opt.smoother == 1, c->opt.krylov == 1,
+                     opt_omega(c->opt), c->opt.bottom_rtol, bottom_maxit(c)};
+    const bool fp64 = sizeof(T) == 8;
+    return launch_tail<T>(c->dim, c->L.back().g.nn > kTailWaveBottom,
+                          c->tail_args + (fp64 ? 0 : kTailArgBytes),
+                          fp64 ? c->tail_lds64 : c->tail_lds32, x, f, o, c->iflag + 4, c->st);
+  }
   if (l == c->nlev - 1) {
     ProfScope ps(c, SBM_PROF_BOTTOM, true);
     if constexpr (sizeof(T) == 8) return bottom64(c, f, x);
@@ -740,6 +758,18 @@ sbm_status sbm_create(const sbm_grid *grid, const sbm_options *opts, void *works
   carve(c, c->ws);
   c->opt = *opts;
   c->st = (hipStream_t)hip_stream;
+#ifndef SBM_TAIL_DISABLE
+  {
+    int dev = 0, lds = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        lds <= 0)
+      lds = 64 * 1024;
+    (void)hipGetLastError();
+    c->tail64 = tail_level(c->L, 0, (size_t)lds);
+    c->tail32 = tail_level(c->L, 1, (size_t)lds);
+  }
+#endif
   hipError_t e = hipHostMalloc((void **)&c->host, 64 * sizeof(double), hipHostMallocDefault);
   if (e != hipSuccess) {
     delete c;
@@ -852,6 +882,12 @@ static sbm_status set_problem_impl(sbm_ctx *c, const double *psi_raw, int cube,
   HIP_TRY(launch_floor_psi(psi_raw, mat->psi_floor, L0.psi64, L0.psi32, L0.g.nc, cube, c->iflag,
                            c->st));
   for (int l = 1; l < c->nlev; ++l) HIP_TRY(launch_coarsen_psi(c->L[l - 1], c->L[l], c->st));
+  // tail level tables and the dense bottom matrix (needs the bottom psi)
+  if (c->tail64 >= 0)
+    HIP_TRY(tail_upload(c->L, 0, c->tail64, c->tail_args, c->tail_A, &c->tail_lds64, c->st));
+  if (c->tail32 >= 0)
+    HIP_TRY(tail_upload(c->L, 1, c->tail32, c->tail_args + kTailArgBytes, c->tail_A,
+                        &c->tail_lds32, c->st));
   HIP_TRY(launch_rhs(L0, c->tr, b, L0.f, c->iflag, c->st));
   HIP_TRY(launch_check_diag(L0, c->iflag, c->st));
   int flags = 0;
