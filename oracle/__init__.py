@@ -259,6 +259,33 @@ def sensitivity(ncell, h, lam, mu, kind, val, u, adj, rho=None, psi_floor=0.0):
     return g
 
 
+def plastic_source(ncell, h, lam, mu, psi, eps_p):
+    """Nodal load -div(psi C eps_p) of a cell plastic strain (3D; eps_p of
+    shape (6, nz, ny, nx), components xx, yy, zz, yz, xz, xy)."""
+    fp = np.empty((3,) + node_shape(ncell))
+    st = lib().orc_plastic_source(len(ncell), _long3(ncell), _dbl3(h), ctypes.c_double(lam),
+                                  ctypes.c_double(mu), _d(np.ascontiguousarray(psi, np.float64)),
+                                  _d(np.ascontiguousarray(eps_p, np.float64)), _d(fp))
+    if st != 0:
+        raise ValueError("plastic_source: 3D only")
+    return fp
+
+
+def return_map(ncell, h, lam, mu, sigma_y, hbar, theta, u, eps_p, alpha, beta):
+    """One radial-return update of the cell state (eps_p, alpha, beta) for the
+    displacement u; returns (eps_p, alpha, beta, cells that yielded)."""
+    ep = np.array(eps_p, np.float64, copy=True, order="C")
+    al = np.array(alpha, np.float64, copy=True, order="C")
+    bt = np.array(beta, np.float64, copy=True, order="C")
+    n = lib().orc_return_map(len(ncell), _long3(ncell), _dbl3(h), ctypes.c_double(lam),
+                             ctypes.c_double(mu), ctypes.c_double(sigma_y), ctypes.c_double(hbar),
+                             ctypes.c_double(theta), _d(np.ascontiguousarray(u, np.float64)),
+                             _d(ep), _d(al), _d(bt))
+    if n < 0:
+        raise ValueError("return_map: 3D only")
+    return ep, al, bt, n
+
+
 def assemble(ncell, h, lam, mu, psi):
     """Dense K (small grids only) built column by column from ``apply``."""
     d = len(ncell)

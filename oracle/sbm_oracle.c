@@ -821,6 +821,157 @@ void orc_sensitivity(int dim, const long *nc, const double *h, double lam_, doub
   }
 }
 
+/* ------------------------------------------------ plastic strain (J2) -- */
+
+/* Stress with a plastic strain (Sec. 3.1): sigma = C (grad u - eps_p), so the
+ * equilibrium div(psi sigma) + b = 0 reads K u = b - div(psi C eps_p).  The
+ * plastic strain lives in the cells (3D; components xx, yy, zz, yz, xz, xy,
+ * cell scalar arrays one after another).  The divergence is taken in the same
+ * flux form as eq. K: component i at node n is
+ *     sum_j ( S_ij(n, +j) - S_ij(n, -j) ) / h_j,
+ * S_ij(n, s e_j) = mean over the 4 cells sharing the edge (n, n + s e_j) of
+ * psi_c (C eps_p,c)_ij, cells outside the box counting 0.  For a uniform
+ * eps_p this equals -K applied to the linear field eps_p x at every node (the
+ * direct part of eq. K is the j = l term; the two quadrants of each cross term
+ * sum to the edge mean), so a compatible uniform plastic strain in a free body
+ * is stress-free.  fp = -div(psi C eps_p) is the load it adds. */
+static void voigt_to_mat(const double *v, double e[3][3]) {
+  e[0][0] = v[0]; e[1][1] = v[1]; e[2][2] = v[2];
+  e[1][2] = e[2][1] = v[3];
+  e[0][2] = e[2][0] = v[4];
+  e[0][1] = e[1][0] = v[5];
+}
+
+static void cell_state(const double *a, long NC, long cid, int ncomp, double *out) {
+  for (int q = 0; q < ncomp; ++q) out[q] = a[(long)q * NC + cid];
+}
+
+int orc_plastic_source(int dim, const long *nc, const double *h, double lam, double mu,
+                       const double *psi, const double *eps_p, double *fp) {
+  if (dim != 3) return -1;
+  grid_t g;
+  grid_init(&g, dim, nc, h, lam, mu);
+#pragma omp parallel for schedule(static)
+  for (long id = 0; id < g.NN; ++id) {
+    long n[3];
+    node_of(&g, id, n);
+    double div[3] = {0.0, 0.0, 0.0};
+    for (int j = 0; j < 3; ++j)
+      for (int s = -1; s <= 1; s += 2) {
+        /* S(n, s e_j): mean over the 4 cells around the edge */
+        double S[3] = {0.0, 0.0, 0.0};
+        for (int o = 0; o < 4; ++o) {
+          long c[3];
+          int b = 0;
+          for (int a = 0; a < 3; ++a) {
+            if (a == j) c[a] = (s > 0) ? n[a] : n[a] - 1;
+            else c[a] = n[a] - 1 + ((o >> (b++)) & 1);
+          }
+          int inside = 1;
+          for (int a = 0; a < 3; ++a)
+            if (c[a] < 0 || c[a] >= g.nc[a]) inside = 0;
+          if (!inside) continue;
+          long cid = c[0] + g.nc[0] * (c[1] + g.nc[1] * c[2]);
+          double v[6], e[3][3];
+          cell_state(eps_p, g.NC, cid, 6, v);
+          voigt_to_mat(v, e);
+          for (int i = 0; i < 3; ++i) {
+            double sij = 0.0;
+            for (int k = 0; k < 3; ++k)
+              for (int l = 0; l < 3; ++l) sij += g.C[i][j][k][l] * e[k][l];
+            S[i] += psi[cid] * sij;
+          }
+        }
+        for (int i = 0; i < 3; ++i) div[i] += s * (S[i] / 4.0) / g.h[j];
+      }
+    for (int i = 0; i < 3; ++i) fp[(long)i * g.NN + id] = -div[i];
+  }
+  return 0;
+}
+
+/* J2 plasticity with linear combined hardening (Sec. 3.1, eq. J2Plasticity):
+ * eta = dev(sigma) - beta, f = |eta| - sqrt(2/3) K(alpha),
+ * K(alpha) = sigma_Y + theta Hbar alpha; flow eps_p' = gamma eta/|eta|,
+ * alpha' = sqrt(2/3) gamma, beta' = (2/3)(1 - theta) Hbar gamma eta/|eta|.
+ * Integrated over one load step by the radial return of the cited scheme:
+ *   eps      = sym(G u) at the cell centre (G: mean over the cell's four
+ *              edges along l of the difference quotient of u_k),
+ *   s_trial  = 2 mu dev(eps - eps_p),   eta_trial = s_trial - beta,
+ *   f_trial  = |eta_trial| - sqrt(2/3) K(alpha);  elastic if f_trial <= 0,
+ *   else dgamma solves the consistency condition of the updated state,
+ *   |eta_trial| - (2 mu + (2/3)(1-theta) Hbar) dgamma
+ *        = sqrt(2/3) K(alpha + sqrt(2/3) dgamma),
+ *   i.e. dgamma = f_trial / (2 mu + (2/3) Hbar), and with n = eta_trial/|eta_trial|
+ *   eps_p += dgamma n, alpha += sqrt(2/3) dgamma,
+ *   beta += (2/3)(1 - theta) Hbar dgamma n.
+ * State arrays per cell: eps_p and beta 6 components (xx, yy, zz, yz, xz,
+ * xy), alpha one.  Returns the number of cells that yielded. */
+int orc_return_map(int dim, const long *nc, const double *h, double lam, double mu,
+                   double sigma_y, double hbar, double theta, const double *u, double *eps_p,
+                   double *alpha, double *beta) {
+  if (dim != 3) return -1;
+  grid_t g;
+  grid_init(&g, dim, nc, h, lam, mu);
+  long nplastic = 0;
+  const double r23 = sqrt(2.0 / 3.0);
+#pragma omp parallel for schedule(static) reduction(+ : nplastic)
+  for (long cid = 0; cid < g.NC; ++cid) {
+    long c[3] = {cid % g.nc[0], (cid / g.nc[0]) % g.nc[1], cid / (g.nc[0] * g.nc[1])};
+    /* cell gradient G[k][l] = d u_k / d x_l */
+    double G[3][3];
+    for (int k = 0; k < 3; ++k)
+      for (int l = 0; l < 3; ++l) {
+        double acc = 0.0;
+        for (int o = 0; o < 4; ++o) {
+          long n0[3], n1[3];
+          int b = 0;
+          for (int a = 0; a < 3; ++a) {
+            if (a == l) { n0[a] = c[a]; n1[a] = c[a] + 1; }
+            else { n0[a] = n1[a] = c[a] + ((o >> (b++)) & 1); }
+          }
+          acc += (u[(long)k * g.NN + node_id(&g, n1)] - u[(long)k * g.NN + node_id(&g, n0)]) /
+                 g.h[l];
+        }
+        G[k][l] = acc / 4.0;
+      }
+    double eps[3][3], ep[3][3], bt[3][3], v[6];
+    for (int k = 0; k < 3; ++k)
+      for (int l = 0; l < 3; ++l) eps[k][l] = 0.5 * (G[k][l] + G[l][k]);
+    cell_state(eps_p, g.NC, cid, 6, v);
+    voigt_to_mat(v, ep);
+    cell_state(beta, g.NC, cid, 6, v);
+    voigt_to_mat(v, bt);
+    const double a0 = alpha[cid];
+    /* trial deviatoric stress and relative stress */
+    double ee[3][3], tr = 0.0;
+    for (int k = 0; k < 3; ++k)
+      for (int l = 0; l < 3; ++l) ee[k][l] = eps[k][l] - ep[k][l];
+    for (int k = 0; k < 3; ++k) tr += ee[k][k];
+    double eta[3][3], nrm2 = 0.0;
+    for (int k = 0; k < 3; ++k)
+      for (int l = 0; l < 3; ++l) {
+        const double s = 2.0 * mu * (ee[k][l] - (k == l ? tr / 3.0 : 0.0));
+        eta[k][l] = s - bt[k][l];
+        nrm2 += eta[k][l] * eta[k][l];
+      }
+    const double nrm = sqrt(nrm2);
+    const double ftrial = nrm - r23 * (sigma_y + theta * hbar * a0);
+    if (!(ftrial > 0.0)) continue;
+    ++nplastic;
+    const double dg = ftrial / (2.0 * mu + (2.0 / 3.0) * hbar);
+    double nv[3][3];
+    for (int k = 0; k < 3; ++k)
+      for (int l = 0; l < 3; ++l) nv[k][l] = eta[k][l] / nrm;
+    const int vi[6] = {0, 1, 2, 1, 0, 0}, vj[6] = {0, 1, 2, 2, 2, 1};
+    for (int q = 0; q < 6; ++q) {
+      eps_p[(long)q * g.NC + cid] += dg * nv[vi[q]][vj[q]];
+      beta[(long)q * g.NC + cid] += (2.0 / 3.0) * (1.0 - theta) * hbar * dg * nv[vi[q]][vj[q]];
+    }
+    alpha[cid] = a0 + r23 * dg;
+  }
+  return (int)nplastic;
+}
+
 /* ======================================================================
  * Block-structured adaptive composite solve (BSAMR).
  *
