@@ -205,6 +205,36 @@ sbm_status sbm_sensitivity(sbm_ctx *ctx, const double *u, const double *lam, dou
 sbm_status sbm_set_problem_density(sbm_ctx *ctx, const double *rho, const sbm_material *mat,
                                    const sbm_bc *bc, const double *body_force);
 
+/* ------------------------------------------------ plastic strain (J2) ---
+ * Sec. 3.1: sigma = C (grad u - eps_p), so the equilibrium becomes
+ * K u = b - div(psi C eps_p); the plastic state evolves by J2 plasticity with
+ * linear combined hardening (eq. J2Plasticity), integrated over a load step
+ * by radial return.  3D grids only (SBM_E_SHAPE otherwise).  Cell state
+ * arrays (device, cells, x fastest): eps_p and beta hold 6 components (xx,
+ * yy, zz, yz, xz, xy) one array after another (6 x cells doubles), alpha one
+ * array.  A staggered step passes f as the body force of sbm_set_problem,
+ * solves, and calls sbm_return_map on the solution. */
+typedef struct {
+  double sigma_y; /* yield strength (flow stress) */
+  double hbar;    /* hardening modulus */
+  double theta;   /* isotropic share of the hardening, 0..1 */
+} sbm_j2;
+
+/* f = -div(psi C eps_p) at every node (3 x nodes, device): the flux form of
+ * eq. K with half-edge stresses averaged over the four cells around each
+ * edge and psi the floored psi of sbm_set_problem.  Async. */
+sbm_status sbm_plastic_source(sbm_ctx *ctx, const double *eps_p, double *f);
+
+/* Radial return of every cell for the strain of u (cell-centre sym grad:
+ * mean over the cell's four edges along each axis): eta = 2 mu dev(eps -
+ * eps_p) - beta, f = |eta| - sqrt(2/3)(sigma_y + theta hbar alpha); where
+ * f > 0, dgamma = f / (2 mu + 2 hbar / 3), n = eta / |eta|, eps_p += dgamma n,
+ * alpha += sqrt(2/3) dgamma, beta += (2/3)(1 - theta) hbar dgamma n.  The
+ * state is updated in place.  If n_plastic_host is non-NULL it receives the
+ * number of yielding cells and the call synchronises; otherwise async. */
+sbm_status sbm_return_map(sbm_ctx *ctx, const double *u, const sbm_j2 *mat, double *eps_p,
+                          double *alpha, double *beta, int64_t *n_plastic_host);
+
 /* Compliance J = h^d sum over free DOF of fA . u (Sec. 3.3, the work of the
  * load), written to *J_host; synchronises. */
 sbm_status sbm_compliance(sbm_ctx *ctx, const double *u, double *J_host);

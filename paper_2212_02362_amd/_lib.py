@@ -35,6 +35,10 @@ class SbmMaterial(ctypes.Structure):
                 ("psi_floor", ctypes.c_double)]
 
 
+class SbmJ2(ctypes.Structure):
+    _fields_ = [("sigma_y", ctypes.c_double), ("hbar", ctypes.c_double), ("theta", ctypes.c_double)]
+
+
 class SbmOptions(ctypes.Structure):
     _fields_ = [("smoother", ctypes.c_int), ("omega", ctypes.c_double), ("nu_pre", ctypes.c_int),
                 ("nu_post", ctypes.c_int), ("precision", ctypes.c_int), ("rtol", ctypes.c_double),
@@ -67,6 +71,8 @@ SIGNATURES = {
     "sbm_set_problem_density": (ctypes.c_int, [_P, _P, ctypes.POINTER(SbmMaterial),
                                                ctypes.POINTER(SbmBc), _P]),
     "sbm_compliance": (ctypes.c_int, [_P, _P, _DP]),
+    "sbm_plastic_source": (ctypes.c_int, [_P, _P, _P]),
+    "sbm_return_map": (ctypes.c_int, [_P, _P, ctypes.POINTER(SbmJ2), _P, _P, _P, _I64P]),
     "sbm_profile": (ctypes.c_int, [_P, ctypes.c_int]),
     "sbm_graph_info": (ctypes.c_int, [_P, _I64P, _I64P]),
     "sbm_profile_read": (ctypes.c_int, [_P, _DP, _I64P]),

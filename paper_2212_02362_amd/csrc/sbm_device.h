@@ -52,6 +52,16 @@ struct Coef {
   T cm[3];     // cross (lambda-mu) part
 };
 
+// Logical block of a node-parallel launch: workgroup b runs on XCD b mod 8,
+// so for grids padded to a multiple of 8 each XCD is dealt a contiguous range
+// of logical blocks (rows and planes it shares with its neighbours stay in
+// its own L2).
+__device__ __forceinline__ int xcd_block() {
+  const int nwg = gridDim.x;
+  return (nwg & 7) == 0 ? (int)(blockIdx.x & 7) * (nwg >> 3) + (int)(blockIdx.x >> 3)
+                        : (int)blockIdx.x;
+}
+
 // Bit 3F is set when node (i, j, k) lies on face F (x-,x+,y-,y+,z-,z+), so
 // that (dmask >> comp) & face_bits tests every face at once (no branches).
 __device__ __forceinline__ uint32_t face_bits(const Geom &g, int i, int j, int k) {

@@ -170,6 +170,14 @@ hipError_t tail_upload(const std::vector<Level> &L, int precision, int l0, void 
 template <typename T>
 hipError_t launch_tail(int dim, bool wide_bottom, const void *dev, size_t lds_bytes,
                        T *x, const T *f, const TailOpts &o, int *iters, hipStream_t st);
+// Plastic strain (sbm_plastic.hip, 3D): the load -div(psi C eps_p) at every
+// node, and the J2 radial return of the cell state for the strain of u
+// (count: device int incremented by the yielding cells, nullable).
+hipError_t launch_plastic_source(const Level &L, double lam, double mu, const double *eps_p,
+                                 double *fp, hipStream_t st);
+hipError_t launch_return_map(const Level &L, double mu, double sigma_y, double hbar, double theta,
+                             const double *u, double *eps_p, double *alpha, double *beta,
+                             int *count, hipStream_t st);
 hipError_t launch_sensitivity(const Level &L, double lam, double mu, const Traction &tr,
                               const double *u, const double *adj, double lam_scale,
                               const double *design, int chain, double psi_floor, double *g,

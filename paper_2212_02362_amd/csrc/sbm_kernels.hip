@@ -20,11 +20,6 @@ int grid_blocks(int64_t n) {
   return nb >= 64 ? (nb + 7) / 8 * 8 : nb;
 }
 
-__device__ __forceinline__ int xcd_block() {
-  const int nwg = gridDim.x;
-  return (nwg & 7) == 0 ? (int)(blockIdx.x & 7) * (nwg >> 3) + (int)(blockIdx.x >> 3)
-                        : (int)blockIdx.x;
-}
 
 // ------------------------------------------------------------------ apply --
 

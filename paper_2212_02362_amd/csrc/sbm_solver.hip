@@ -1003,6 +1003,38 @@ sbm_status sbm_sensitivity(sbm_ctx *c, const double *u, const double *lam, doubl
   return SBM_OK;
 }
 
+sbm_status sbm_plastic_source(sbm_ctx *c, const double *eps_p, double *f) {
+  NEED_PROBLEM(c);
+  if (!eps_p || !f) return fail(SBM_E_ARG, "NULL argument");
+  if (c->dim != 3) return fail(SBM_E_SHAPE, "plastic strain: 3D grids only");
+  Level &L0 = c->L[0];
+  HIP_TRY(launch_plastic_source(L0, c->mat.lambda, c->mat.mu, eps_p, f, c->st));
+  return SBM_OK;
+}
+
+sbm_status sbm_return_map(sbm_ctx *c, const double *u, const sbm_j2 *mat, double *eps_p,
+                          double *alpha, double *beta, int64_t *n_plastic) {
+  NEED_PROBLEM(c);
+  if (!u || !mat || !eps_p || !alpha || !beta) return fail(SBM_E_ARG, "NULL argument");
+  if (c->dim != 3) return fail(SBM_E_SHAPE, "plastic strain: 3D grids only");
+  if (!(mat->sigma_y >= 0.0) || !(mat->hbar >= 0.0) || !(mat->theta >= 0.0 && mat->theta <= 1.0) ||
+      !isfinite(mat->sigma_y) || !isfinite(mat->hbar))
+    return fail(SBM_E_ARG, "J2 parameters: sigma_y >= 0, hbar >= 0, 0 <= theta <= 1");
+  Level &L0 = c->L[0];
+  int *cnt = n_plastic ? c->iflag + 12 : nullptr;
+  if (cnt) HIP_TRY(launch_fill<int>(cnt, 1, 0, c->st));
+  HIP_TRY(launch_return_map(L0, c->mat.mu, mat->sigma_y, mat->hbar, mat->theta, u, eps_p, alpha,
+                            beta, cnt, c->st));
+  if (n_plastic) {
+    HIP_TRY(hipMemcpyAsync(c->host, cnt, sizeof(int), hipMemcpyDeviceToHost, c->st));
+    HIP_TRY(hipStreamSynchronize(c->st));
+    int n = 0;
+    memcpy(&n, c->host, sizeof(int));
+    *n_plastic = n;
+  }
+  return SBM_OK;
+}
+
 sbm_status sbm_compliance(sbm_ctx *c, const double *u, double *J) {
   NEED_PROBLEM(c);
   if (!u || !J) return fail(SBM_E_ARG, "NULL argument");

@@ -15,7 +15,7 @@ from typing import Optional, Sequence
 import numpy as np
 import torch
 
-from ._lib import (CHAIN_FLOOR, CHAIN_PSI, CHAIN_RHO3, DISPLACEMENT, SBM_NOT_CONVERGED, SBM_OK,
+from ._lib import (SbmJ2, CHAIN_FLOOR, CHAIN_PSI, CHAIN_RHO3, DISPLACEMENT, SBM_NOT_CONVERGED, SBM_OK,
                    TRACTION, SbmBc, SbmError, SbmGrid, SbmMaterial, SbmOptions, check, lib)
 
 __all__ = ["Solver", "SbmError", "TRACTION", "DISPLACEMENT"]
@@ -207,6 +207,36 @@ class Solver:
         check(lib().sbm_sensitivity(self._ctx, _ptr(u_t), _ptr(l_t), float(lam_scale), _ptr(d_t),
                                     int(chain), _ptr(g)))
         return g
+
+    # ------------------------------------------------- plastic strain (J2)
+    def plastic_source(self, eps_p, out=None):
+        """Nodal load -div(psi C eps_p) of a cell plastic strain (3D; eps_p
+        of shape (6, nz, ny, nx), components xx, yy, zz, yz, xz, xy)."""
+        e_t = self._dev(eps_p, shape=(6,) + self.cell_shape)
+        out = self.new_nodes() if out is None else out
+        check(lib().sbm_plastic_source(self._ctx, _ptr(e_t), _ptr(out)))
+        return out
+
+    def return_map(self, u, eps_p, alpha, beta, sigma_y, hbar, theta, *, inplace=False):
+        """J2 radial return of the cell state for the strain of u.  Returns
+        (eps_p, alpha, beta, number of yielding cells); with inplace=True the
+        given device tensors (float64, contiguous) are updated and returned."""
+        u_t = self._dev(u, shape=(self.dim,) + self.node_shape)
+        state = []
+        for a, shp in ((eps_p, (6,) + self.cell_shape), (alpha, self.cell_shape),
+                       (beta, (6,) + self.cell_shape)):
+            t = self._dev(a, shape=shp)
+            if inplace:
+                if t is not a:
+                    raise ValueError("inplace needs contiguous float64 tensors on the solver's device")
+            else:
+                t = t.clone()
+            state.append(t)
+        m = SbmJ2(float(sigma_y), float(hbar), float(theta))
+        n = ctypes.c_int64(0)
+        check(lib().sbm_return_map(self._ctx, _ptr(u_t), ctypes.byref(m), _ptr(state[0]),
+                                   _ptr(state[1]), _ptr(state[2]), ctypes.byref(n)))
+        return state[0], state[1], state[2], int(n.value)
 
     def compliance(self, u):
         """J = h^d sum over free DOF of f.u."""

@@ -298,3 +298,27 @@ def ellipsoidal_voids_amr(base: int = 64, levels: int = 3, block: int = 32, seed
                 kind, val, extra={"levels": levels, "block": block, "centres": centres,
                                   "axes": axes, "quats": quats})
     return p, psis
+
+
+def j2_void_tension(n: int = 32, radii=(7.5, 4.08, 4.08), floor: float = 1e-4) -> Problem:
+    """The plastic-void tension specimen of the J2 example (Sec. 3.1): the
+    cube [-16, 16]^3 with an ellipsoidal void of semi-axes ``radii`` centred
+    at the origin, indicator 0.5 (1 + tanh(d / eps)) with eps = 0.4 and
+    d = (q - 1)/|grad q|, q = |x / r|; E = 210 (GPa), nu = 0.3.  Face x = -16
+    clamped, the x-displacement of face x = +16 prescribed (``val[1, 0]``, 0
+    here; the caller sets each load step), its other components free.  The
+    J2 parameters sigma_Y = 0.2, Hbar = 50, theta = 1 are in ``extra``."""
+    h = 32.0 / n
+    X, Y, Z = cell_centres((n, n, n), (h, h, h))
+    X, Y, Z = X - 16.0, Y - 16.0, Z - 16.0
+    r = np.asarray(radii, np.float64)
+    qn = np.sqrt((X / r[0]) ** 2 + (Y / r[1]) ** 2 + (Z / r[2]) ** 2)
+    gq = np.sqrt((X / r[0] ** 2) ** 2 + (Y / r[1] ** 2) ** 2 + (Z / r[2] ** 2) ** 2) / np.maximum(qn, 1e-300)
+    dist = (qn - 1.0) / np.maximum(gq, 1e-300)
+    psi = 0.5 * (1.0 + np.tanh(dist / 0.4))
+    kind, val = _bc_table()
+    kind[0, :] = DISPLACEMENT
+    kind[1, 0] = DISPLACEMENT
+    lam, mu = lame(210.0, 0.3)
+    return Problem("j2_void_tension", (n, n, n), (h, h, h), lam, mu, floor, psi, kind, val,
+                   extra={"sigma_y": 0.2, "hbar": 50.0, "theta": 1.0, "radii": tuple(radii)})
