@@ -186,6 +186,158 @@ def _bench_amr(args):
     print(json.dumps(line), flush=True)
 
 
+J2_WORKLOAD = "j2_void_tension_128"
+J2_DESC = ("J2 plastic-void tension specimen (Sec. 3.1): cube [-16,16]^3 with 128^3 cells, "
+           "ellipsoidal void r=(7.5,4.08,4.08) with tanh width 0.4, E=210 nu=0.3, psi floor 1e-4, "
+           "x=-16 clamped, u_x prescribed on x=+16 rising in increments of 0.004; J2 with "
+           "sigma_Y=0.2, Hbar=50, theta=1.  One step = plastic load, set_problem, V(2,2) solve to "
+           "1e-10, radial return; timed steps follow 15 loading steps (plastic zone present)")
+
+
+def _bench_j2(args):
+    """The staggered elastic / plastic step of the J2 example.  value = free
+    DOF / second of whole steps; roofline for the finest half-sweep of the
+    solve (the dominant kernel), plus HIP-event timings of the two plastic
+    kernels against their algorithmic bytes."""
+    import numpy as np
+    import torch
+
+    import sbm_inputs as si
+    from paper_2212_02362_amd import Solver
+
+    p = si.j2_void_tension(128)
+    j2 = p.extra
+    free = _free_dof(p)
+    nodes, cells = p.n_nodes, int(np.prod(p.ncell))
+    shape = tuple(reversed(p.ncell))
+    S = Solver(p.ncell, p.h, rtol=1e-10, max_cycles=400)
+    psi_dev = torch.tensor(p.psi_raw, dtype=torch.float64, device="cuda")
+    ep = torch.zeros((6,) + shape, dtype=torch.float64, device="cuda")
+    al = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    bt = torch.zeros_like(ep)
+    state = {"d": 0.0, "set": False}
+
+    def one():
+        state["d"] += 0.004
+        b = S.plastic_source(ep) if state["set"] else None  # eps_p = 0 before the first step
+        state["set"] = True
+        val = p.val.copy()
+        val[1, 0] = state["d"]
+        S.set_problem(psi_dev, p.lam, p.mu, p.psi_floor, p.kind, val, b)
+        u, hist, st = S.solve()
+        n = S.return_map(u, ep, al, bt, j2["sigma_y"], j2["hbar"], j2["theta"], inplace=True)[3]
+        return u, hist, st, n
+
+    for _ in range(15 + args.warmup):
+        one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cyc, st, fin, npl = [], [], [], []
+    for _ in range(args.steps):
+        u, hist, status, n = one()
+        cyc.append(len(hist) - 1)
+        st.append(int(status))
+        fin.append(float(hist[-1]))
+        npl.append(n)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / args.steps
+    print(f"[bench] {J2_WORKLOAD}: {t * 1e3:.2f} ms/step, cycles {cyc}, yielding cells {npl}",
+          file=sys.stderr, flush=True)
+    # one more step outside the timed region: its solve is profiled (the
+    # dominant kernel) and its plastic kernels are timed on the state before
+    # its return map
+    state["d"] += 0.004
+    b = S.plastic_source(ep)
+    val = p.val.copy()
+    val[1, 0] = state["d"]
+    S.set_problem(psi_dev, p.lam, p.mu, p.psi_floor, p.kind, val, b)
+    S.profile(True)
+    u, _, _ = S.solve()
+    prof = S.profile_read()
+    S.profile(False)
+    ms_s, n_s = prof["smooth"]
+    avg_ms = ms_s / max(n_s, 1)
+    by = ALGO_BYTES["smooth"][0] * nodes
+    achieved = by / (avg_ms * 1e-3) / 1e9
+
+    def timed(make, reps=10):
+        ts, out = [], None
+        for _ in range(reps):
+            fn = make()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            out = fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1) * 1e-3)
+        return float(np.median(ts)), out
+
+    fp = S.new_nodes()
+    t_src, _ = timed(lambda: (lambda: S.plastic_source(ep, out=fp)))
+
+    def rm():
+        e2, a2, b2 = ep.clone(), al.clone(), bt.clone()
+        return lambda: S.return_map(u, e2, a2, b2, j2["sigma_y"], j2["hbar"], j2["theta"],
+                                    inplace=True)[3]
+    t_rm, n_rm = timed(rm)
+    by_src = 56.0 * cells + 24.0 * nodes           # psi, eps_p read; load written
+    by_rm = 24.0 * nodes + 104.0 * cells + 104.0 * n_rm  # u, state read; yielded state written
+    line = {
+        "metric": METRIC,
+        "value": free / t,
+        "unit": "DOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": J2_DESC, "nodes": nodes, "free_dof": free, "precision": "fp64",
+                   "method": "staggered step: V-cycle iteration + radial return",
+                   "cycles": cyc, "final_rel_residual": max(fin), "status": st,
+                   "yielding_cells": npl, "applied_displacement": state["d"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_rb_half<double,3,false> (finest-level Gauss-Seidel half-sweep)",
+                     "algo_bytes_per_launch": by, "avg_launch_us": avg_ms * 1e3,
+                     "timing": "HIP events around each finest-level launch, one profiled solve "
+                               "after the timed steps"},
+        "plastic_kernels": {
+            "plastic_source": {"us": t_src * 1e6, "algo_bytes": by_src,
+                               "algo_GBps": by_src / t_src / 1e9,
+                               "frac_hbm_peak": by_src / t_src / 1e9 / HBM_PEAK_GBS},
+            "return_map": {"us": t_rm * 1e6, "algo_bytes": by_rm, "yielding_cells": n_rm,
+                           "algo_GBps": by_rm / t_rm / 1e9,
+                           "frac_hbm_peak": by_rm / t_rm / 1e9 / HBM_PEAK_GBS},
+            "timing": "HIP events around single launches, median of 10"},
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        import oracle
+        ep_h, al_h, bt_h = ep.cpu().numpy(), al.cpu().numpy(), bt.cpu().numpy()
+        u_h = u.cpu().numpy()
+        psi_f = oracle.floor_psi(p.psi_raw, p.psi_floor)
+        t0 = time.perf_counter()
+        b_h = oracle.plastic_source(p.ncell, p.h, p.lam, p.mu, psi_f, ep_h)
+        oracle.return_map(p.ncell, p.h, p.lam, p.mu, j2["sigma_y"], j2["hbar"], j2["theta"], u_h,
+                          ep_h, al_h, bt_h)
+        t_pl = time.perf_counter() - t0
+        val = p.val.copy()
+        val[1, 0] = state["d"]
+        q = si.Problem(p.name, p.ncell, p.h, p.lam, p.mu, p.psi_floor, p.psi_raw, p.kind, val, b=b_h)
+        base = _cpu_baseline(q, int(np.median(cyc)), free)
+        per_step = t_pl + free / base["value"]
+        line["cpu_baseline"] = {
+            "value": free / per_step, "unit": "DOF/s", "cores": base["cores"], "kind": "oracle",
+            "sample": (f"FP64 oracle on the same step: plastic load and radial return timed "
+                       f"({t_pl:.1f} s), solve " + base["sample"].split("on the same workload: ")[-1]),
+        }
+    print(json.dumps(line), flush=True)
+
+
 def _free_dof(p):
     import numpy as np
     d = p.dim
@@ -371,7 +523,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="spherical_voids_129",
                     choices=["spherical_voids_129", "diffuse_crack_257", "cantilever_193x97x97",
-                             AMR_WORKLOAD])
+                             AMR_WORKLOAD, J2_WORKLOAD])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--counter-driver", action="store_true",
@@ -390,6 +542,8 @@ def main():
 
     if args.workload == AMR_WORKLOAD:
         return _bench_amr(args)
+    if args.workload == J2_WORKLOAD:
+        return _bench_j2(args)
 
     import numpy as np
     import torch
