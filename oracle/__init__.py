@@ -286,6 +286,31 @@ def return_map(ncell, h, lam, mu, sigma_y, hbar, theta, u, eps_p, alpha, beta):
     return ep, al, bt, n
 
 
+def crack_drive(ncell, h, lam, mu, u, H):
+    """Crack driving force (Sec. 3.2): returns (H updated to max(H, W0+), the
+    cells held intact where W0+ < W0-) for the strain of u."""
+    Hn = np.array(H, np.float64, copy=True, order="C")
+    intact = np.empty(cell_shape(ncell), np.uint8)
+    lib().orc_crack_drive(len(ncell), _long3(ncell), _dbl3(h), ctypes.c_double(lam),
+                          ctypes.c_double(mu), _d(np.ascontiguousarray(u, np.float64)), _d(Hn),
+                          _u8(intact))
+    return Hn, intact
+
+
+def phase_step(ncell, h, c, H, intact, Gc, xi, M, dt, eta=1e-4):
+    """One explicit Ginzburg-Landau step of the crack field; returns
+    (c_new, psi = g(c_new) + eta)."""
+    c1 = np.empty(cell_shape(ncell))
+    psi = np.empty(cell_shape(ncell))
+    lib().orc_phase_step(len(ncell), _long3(ncell), _dbl3(h),
+                         _d(np.ascontiguousarray(c, np.float64)),
+                         _d(np.ascontiguousarray(H, np.float64)),
+                         _u8(np.ascontiguousarray(intact, np.uint8)), ctypes.c_double(Gc),
+                         ctypes.c_double(xi), ctypes.c_double(M), ctypes.c_double(dt),
+                         ctypes.c_double(eta), _d(c1), _d(psi))
+    return c1, psi
+
+
 def assemble(ncell, h, lam, mu, psi):
     """Dense K (small grids only) built column by column from ``apply``."""
     d = len(ncell)

@@ -972,6 +972,130 @@ int orc_return_map(int dim, const long *nc, const double *h, double lam, double 
   return (int)nplastic;
 }
 
+/* ------------------------------------------------ phase-field fracture -- */
+
+/* Hybrid phase-field fracture (Sec. 3.2, eqs. PFFracture, PFFractureGL).  The
+ * equilibrium is the SBM equation with psi = g(c) + eta (g(c) = 4c^3 - 3c^4,
+ * eta = 1e-4): linear, the elastic solve of this library.  The crack field c
+ * lives in the cells.  Per cell, from the strain eps = sym(G u) (the cell
+ * gradient of the corner nodes, as for plasticity; plane strain in 2D):
+ *   eigenvalues e_i of eps (2D: the in-plane pair, the zero out-of-plane
+ *   strain contributes nothing to either part),
+ *   W0+- = lambda/2 (sum_i <e_i>+-)^2 + mu sum_i <e_i>+-^2,
+ *   H <- max(H, W0+) (the history field), and the cell is held intact
+ *   (c = 1) where W0+ < W0-.
+ * Eigenvalues by cyclic Jacobi rotations (3D) or the closed form (2D). */
+static void sym_eigs(int d, double a[3][3], double *e) {
+  if (d == 2) {
+    const double m = 0.5 * (a[0][0] + a[1][1]);
+    const double r = sqrt(0.25 * (a[0][0] - a[1][1]) * (a[0][0] - a[1][1]) + a[0][1] * a[0][1]);
+    e[0] = m + r;
+    e[1] = m - r;
+    return;
+  }
+  for (int sweep = 0; sweep < 50; ++sweep) {
+    double off = fabs(a[0][1]) + fabs(a[0][2]) + fabs(a[1][2]);
+    if (off == 0.0) break;
+    for (int p = 0; p < 2; ++p)
+      for (int q = p + 1; q < 3; ++q) {
+        if (a[p][q] == 0.0) continue;
+        const double th = 0.5 * (a[q][q] - a[p][p]) / a[p][q];
+        const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+        const double cs = 1.0 / sqrt(t * t + 1.0), sn = t * cs;
+        /* A <- J^T A J with the rotation in the (p, q) plane */
+        for (int k = 0; k < 3; ++k) {
+          const double akp = a[k][p], akq = a[k][q];
+          a[k][p] = cs * akp - sn * akq;
+          a[k][q] = sn * akp + cs * akq;
+        }
+        for (int k = 0; k < 3; ++k) {
+          const double apk = a[p][k], aqk = a[q][k];
+          a[p][k] = cs * apk - sn * aqk;
+          a[q][k] = sn * apk + cs * aqk;
+        }
+      }
+  }
+  for (int i = 0; i < 3; ++i) e[i] = a[i][i];
+}
+
+static void cell_grad(const grid_t *g, const double *u, const long *c, double G[3][3]) {
+  const int d = g->dim;
+  for (int k = 0; k < 3; ++k)
+    for (int l = 0; l < 3; ++l) G[k][l] = 0.0;
+  const int ne = 1 << (d - 1); /* edges per axis */
+  for (int k = 0; k < d; ++k)
+    for (int l = 0; l < d; ++l) {
+      double acc = 0.0;
+      for (int o = 0; o < ne; ++o) {
+        long n0[3] = {0, 0, 0}, n1[3] = {0, 0, 0};
+        int b = 0;
+        for (int a = 0; a < d; ++a) {
+          if (a == l) { n0[a] = c[a]; n1[a] = c[a] + 1; }
+          else { n0[a] = n1[a] = c[a] + ((o >> (b++)) & 1); }
+        }
+        acc += (u[(long)k * g->NN + node_id(g, n1)] - u[(long)k * g->NN + node_id(g, n0)]) /
+               g->h[l];
+      }
+      G[k][l] = acc / ne;
+    }
+}
+
+void orc_crack_drive(int dim, const long *nc, const double *h, double lam, double mu,
+                     const double *u, double *H, uint8_t *intact) {
+  grid_t g;
+  grid_init(&g, dim, nc, h, lam, mu);
+#pragma omp parallel for schedule(static)
+  for (long cid = 0; cid < g.NC; ++cid) {
+    long c[3] = {cid % g.nc[0], (cid / g.nc[0]) % g.nc[1], dim > 2 ? cid / (g.nc[0] * g.nc[1]) : 0};
+    double G[3][3], eps[3][3], e[3] = {0.0, 0.0, 0.0};
+    cell_grad(&g, u, c, G);
+    for (int k = 0; k < 3; ++k)
+      for (int l = 0; l < 3; ++l) eps[k][l] = 0.5 * (G[k][l] + G[l][k]);
+    sym_eigs(dim, eps, e);
+    double tp = 0.0, tm = 0.0, sp = 0.0, sm = 0.0;
+    for (int i = 0; i < dim; ++i) {
+      const double ep = e[i] > 0.0 ? e[i] : 0.0, em = e[i] < 0.0 ? e[i] : 0.0;
+      tp += ep; tm += em;
+      sp += ep * ep; sm += em * em;
+    }
+    const double wp = 0.5 * lam * tp * tp + mu * sp, wm = 0.5 * lam * tm * tm + mu * sm;
+    if (wp > H[cid]) H[cid] = wp;
+    intact[cid] = wp < wm;
+  }
+}
+
+/* One explicit Ginzburg-Landau step (eq. PFFractureGL) on the cells:
+ *   c <- c - dt M [ g'(c) H - Gc (2 xi lap(c) + w'(c) / (2 xi)) ],
+ * g' = 12 c^2 - 12 c^3, w = 1 - g so w' = -g'; lap(c) is the cell Laplacian
+ * (3 or 5 / 7-point) with zero flux across the box faces; intact cells are
+ * set to 1 (eq. PFFracture, last line).  Also returns psi = g(c) + eta of the
+ * new field (the SBM indicator of the next solve). */
+void orc_phase_step(int dim, const long *nc, const double *h, const double *c0, const double *H,
+                    const uint8_t *intact, double Gc, double xi, double M, double dt,
+                    double eta, double *c1, double *psi) {
+  long n[3] = {nc[0], nc[1], dim > 2 ? nc[2] : 1};
+  const long NC = n[0] * n[1] * n[2];
+#pragma omp parallel for schedule(static)
+  for (long cid = 0; cid < NC; ++cid) {
+    long ci[3] = {cid % n[0], (cid / n[0]) % n[1], cid / (n[0] * n[1])};
+    const double cc = c0[cid];
+    double lap = 0.0;
+    long stride = 1;
+    for (int a = 0; a < dim; ++a) {
+      const double cm = ci[a] > 0 ? c0[cid - stride] : cc;
+      const double cp = ci[a] < n[a] - 1 ? c0[cid + stride] : cc;
+      lap += (cp - 2.0 * cc + cm) / (h[a] * h[a]);
+      stride *= n[a];
+    }
+    const double gp = 12.0 * cc * cc - 12.0 * cc * cc * cc;
+    const double wp = -gp;
+    double cn = cc - dt * M * (gp * H[cid] - Gc * (2.0 * xi * lap + wp / (2.0 * xi)));
+    if (intact[cid]) cn = 1.0;
+    c1[cid] = cn;
+    psi[cid] = 4.0 * cn * cn * cn - 3.0 * cn * cn * cn * cn + eta;
+  }
+}
+
 /* ======================================================================
  * Block-structured adaptive composite solve (BSAMR).
  *
