@@ -1067,7 +1067,9 @@ void orc_crack_drive(int dim, const long *nc, const double *h, double lam, doubl
 /* One explicit Ginzburg-Landau step (eq. PFFractureGL) on the cells:
  *   c <- c - dt M [ g'(c) H - Gc (2 xi lap(c) + w'(c) / (2 xi)) ],
  * g' = 12 c^2 - 12 c^3, w = 1 - g so w' = -g'; lap(c) is the cell Laplacian
- * (3 or 5 / 7-point) with zero flux across the box faces; intact cells are
+ * (3 or 5 / 7-point) with zero flux across the box faces.  The crack field
+ * lives in [0, 1] (0 in the crack, 1 in intact material, Sec. 3.2), so the
+ * step is projected onto that interval (a NaN stays NaN); intact cells are
  * set to 1 (eq. PFFracture, last line).  Also returns psi = g(c) + eta of the
  * new field (the SBM indicator of the next solve). */
 void orc_phase_step(int dim, const long *nc, const double *h, const double *c0, const double *H,
@@ -1090,6 +1092,8 @@ void orc_phase_step(int dim, const long *nc, const double *h, const double *c0, 
     const double gp = 12.0 * cc * cc - 12.0 * cc * cc * cc;
     const double wp = -gp;
     double cn = cc - dt * M * (gp * H[cid] - Gc * (2.0 * xi * lap + wp / (2.0 * xi)));
+    if (cn < 0.0) cn = 0.0;
+    if (cn > 1.0) cn = 1.0;
     if (intact[cid]) cn = 1.0;
     c1[cid] = cn;
     psi[cid] = 4.0 * cn * cn * cn - 3.0 * cn * cn * cn * cn + eta;

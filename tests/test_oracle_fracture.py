@@ -3,9 +3,10 @@
 The crack driving force is checked on strains whose principal values are
 known (a rotated diagonal strain, pure tension, pure compression) and for the
 history property of H; the Ginzburg-Landau step by its fixed point, its
-closed form for a uniform field, and the discrete Laplacian it contains
-(exact for a quadratic in the interior, summing to zero over the box with the
-zero-flux faces)."""
+closed form for a uniform field, its projection onto [0, 1] (the range of
+the crack field), and the discrete Laplacian it contains (exact for a
+quadratic in the interior, summing to zero over the box with the zero-flux
+faces)."""
 import numpy as np
 import pytest
 
@@ -65,25 +66,27 @@ def test_tension_compression_and_history():
     assert np.array_equal(H3, Hbig)                              # history keeps the maximum
 
 
-def _lap_from_step(ncell, h, c):
-    """With H = 0, Gc = M = dt = 1, xi = 1/2 the step is c + lap(c) + w'(c),
-    w' = -g' = -(12 c^2 - 12 c^3): read lap(c) back."""
+def _lap_from_step(ncell, h, c, dt):
+    """With H = 0, Gc = M = 1, xi = 1/2 the step is c + dt (lap(c) + w'(c)),
+    w' = -g' = -(12 c^2 - 12 c^3): read lap(c) back (dt small enough that
+    the step stays inside [0, 1])."""
     shape = tuple(reversed(ncell))
     c1, _ = oracle.phase_step(ncell, h, c, np.zeros(shape), np.zeros(shape, np.uint8), 1.0, 0.5,
-                              1.0, 1.0)
-    return c1 - c + (12 * c ** 2 - 12 * c ** 3)
+                              1.0, dt)
+    assert 0.0 < c1.min() and c1.max() < 1.0
+    return (c1 - c) / dt + (12 * c ** 2 - 12 * c ** 3)
 
 
 @pytest.mark.parametrize("ncell", [(7, 5), (6, 5, 4)])
 def test_laplacian_in_the_step(ncell):
     h = (0.2, 0.25, 0.3)[:len(ncell)]
     cc = si.cell_centres(ncell, h)
-    q = sum((a + 1.0) * x * x for a, x in enumerate(cc))   # lap q = 2 sum (a+1)
-    lap = _lap_from_step(ncell, h, q)
+    q = 0.4 + 0.02 * sum((a + 1.0) * x * x for a, x in enumerate(cc))  # lap q = 0.04 sum (a+1)
+    lap = _lap_from_step(ncell, h, q, 1e-2)
     inner = tuple(slice(1, -1) for _ in ncell)
-    assert np.allclose(lap[inner], 2.0 * sum(a + 1.0 for a in range(len(ncell))), rtol=1e-9)
-    c = np.random.default_rng(3).uniform(size=tuple(reversed(ncell)))
-    lap = _lap_from_step(ncell, h, c)
+    assert np.allclose(lap[inner], 0.04 * sum(a + 1.0 for a in range(len(ncell))), rtol=1e-9)
+    c = np.random.default_rng(3).uniform(0.4, 0.6, size=tuple(reversed(ncell)))
+    lap = _lap_from_step(ncell, h, c, 1e-4)
     assert abs(lap.sum()) <= 1e-10 * np.abs(lap).sum()      # zero flux through the box faces
 
 
@@ -104,3 +107,31 @@ def test_step_closed_form_and_fixed_point():
     held, _ = oracle.phase_step(ncell, h, np.full(shape, 0.2), np.full(shape, H0),
                                 np.ones(shape, np.uint8), Gc, xi, M, dt, eta)
     assert np.array_equal(held, np.ones(shape))              # W0+ < W0- forces c = 1
+
+
+def test_step_stays_in_the_unit_interval():
+    """A driving force far above the threshold takes c below 0 in one explicit
+    step and a field above 1 is pushed further up: both are projected onto
+    [0, 1]; a NaN is not hidden."""
+    ncell, h = (3, 2), (0.1, 0.1)
+    shape = tuple(reversed(ncell))
+    Gc, xi, M, dt = 1.0, 0.1, 1.0, 1.0
+    free = np.zeros(shape, np.uint8)
+    c0 = 0.5
+    gp = 12 * c0 ** 2 - 12 * c0 ** 3
+    H = 10.0
+    raw = c0 - dt * M * (gp * H + Gc * gp / (2 * xi))
+    assert raw < 0
+    c1, psi = oracle.phase_step(ncell, h, np.full(shape, c0), np.full(shape, H), free, Gc, xi, M,
+                                dt, 1e-4)
+    assert np.array_equal(c1, np.zeros(shape)) and np.allclose(psi, 1e-4, rtol=0, atol=1e-18)
+    c0 = 1.2
+    gp = 12 * c0 ** 2 - 12 * c0 ** 3
+    assert c0 - dt * M * (gp * H + Gc * gp / (2 * xi)) > 1
+    c1, _ = oracle.phase_step(ncell, h, np.full(shape, c0), np.full(shape, H), free, Gc, xi, M,
+                              dt, 1e-4)
+    assert np.array_equal(c1, np.ones(shape))
+    c = np.full(shape, 0.5)
+    c[0, 0] = np.nan
+    c1, _ = oracle.phase_step(ncell, h, c, np.zeros(shape), free, Gc, xi, M, 1e-3, 1e-4)
+    assert np.isnan(c1[0, 0])
