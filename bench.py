@@ -338,6 +338,159 @@ def _bench_j2(args):
     print(json.dumps(line), flush=True)
 
 
+PF_WORKLOAD = "pf_mode1_4096"
+PF_DESC = ("Mode-I phase-field fracture (Sec. 3.2, hybrid model) on a uniform 4096^2-cell grid "
+           "(the resolution of the finest of six refinement levels over a 64^2 base, everywhere): "
+           "square [-0.01,0.01]^2, lambda=121.15e9 mu=80.77e9, notch of length 1.5e-4 from the "
+           "centre of the left edge, c0 = 1 - exp(-d/xi), xi=1e-5, Gc=2700, M=1e-5, dt=1e-4, "
+           "eta=1e-4 (psi = g(c) + eta, floor 1e-4), bottom clamped, u_y=1.5e-5 on the top.  One "
+           "step = set_problem(psi), V(2,2)-preconditioned flexible CG solve to 1e-10 warm-started "
+           "from the previous step, "
+           "crack driving force, explicit Ginzburg-Landau step; timed steps follow 5 steps")
+
+
+def _bench_pf(args):
+    """The staggered phase-field fracture step.  value = free DOF / second of
+    whole steps; roofline for the finest half-sweep of the solve (the
+    dominant kernel), plus HIP-event timings of the two fracture kernels
+    against their algorithmic bytes."""
+    import numpy as np
+    import torch
+
+    import sbm_inputs as si
+    from paper_2212_02362_amd import Solver
+
+    p = si.pf_mode1_2d(4096)
+    e = p.extra
+    free = _free_dof(p)
+    nodes, cells = p.n_nodes, int(np.prod(p.ncell))
+    # the crack makes the operator near-singular: V-cycle-preconditioned CG
+    S = Solver(p.ncell, p.h, rtol=1e-10, max_cycles=400, krylov=1)
+    st_ = {"c": torch.tensor(e["c0"], device="cuda"),
+           "psi": torch.tensor(p.psi_raw, device="cuda"),
+           "H": torch.zeros(e["c0"].shape, dtype=torch.float64, device="cuda"),
+           "u": None}
+
+    def one():
+        S.set_problem(st_["psi"], p.lam, p.mu, p.psi_floor, p.kind, p.val)
+        u, hist, status = S.solve(u0=st_["u"])
+        st_["u"] = u
+        H, intact = S.crack_drive(u, st_["H"], inplace=True)
+        st_["c"], st_["psi"] = S.phase_step(st_["c"], H, intact, e["Gc"], e["xi"], e["M"],
+                                            e["dt"], e["eta"])
+        return hist, status, intact
+
+    print(f"[bench] {PF_WORKLOAD}: {nodes} nodes, {free} free DOF", file=sys.stderr, flush=True)
+    first = None
+    for k in range(5 + args.warmup):
+        hist, _, _ = one()
+        if first is None:
+            first = len(hist) - 1
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cyc, sts, fin = [], [], []
+    for _ in range(args.steps):
+        hist, status, intact = one()
+        cyc.append(len(hist) - 1)
+        sts.append(int(status))
+        fin.append(float(hist[-1]))
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / args.steps
+    c = st_["c"]
+    cmin, cmax = float(c.min()), float(c.max())
+    cracked = int((c < 0.5).sum())
+    n_intact = int(intact.sum())
+    print(f"[bench] {PF_WORKLOAD}: {t * 1e3:.2f} ms/step, cycles {cyc} (first solve {first}), "
+          f"c in [{cmin:.3g}, {cmax:.3g}], {cracked} cells c<0.5, {n_intact} held intact",
+          file=sys.stderr, flush=True)
+    # one more solve outside the timed region, profiled (the dominant kernel)
+    S.set_problem(st_["psi"], p.lam, p.mu, p.psi_floor, p.kind, p.val)
+    S.profile(True)
+    u, _, _ = S.solve(u0=st_["u"])
+    prof = S.profile_read()
+    S.profile(False)
+    ms_s, n_s = prof["smooth"]
+    avg_ms = ms_s / max(n_s, 1)
+    by = PF_SMOOTH_BYTES * nodes
+    achieved = by / (avg_ms * 1e-3) / 1e9
+
+    def timed(fn, reps=10):
+        ts, out = [], None
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            out = fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1) * 1e-3)
+        return float(np.median(ts)), out
+
+    Hs = st_["H"].clone()
+    t_cd, (_, intact) = timed(lambda: S.crack_drive(u, Hs, inplace=True))
+    c_out, psi_out = torch.empty_like(st_["c"]), torch.empty_like(st_["c"])
+    t_ps, _ = timed(lambda: S.phase_step(st_["c"], Hs, intact, e["Gc"], e["xi"], e["M"], e["dt"],
+                                         e["eta"], out=(c_out, psi_out)))
+    by_cd = 16.0 * nodes + 17.0 * cells   # u read, H read and written, intact written
+    by_ps = 33.0 * cells                  # c, H, intact read; c, psi written
+    line = {
+        "metric": METRIC,
+        "value": free / t,
+        "unit": "DOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": PF_DESC, "nodes": nodes, "free_dof": free, "precision": "fp64",
+                   "method": "staggered step: warm-started MG-preconditioned CG + crack update",
+                   "cycles": cyc, "first_solve_cycles": first, "final_rel_residual": max(fin),
+                   "status": sts, "crack_cells_c_below_half": cracked, "c_range": [cmin, cmax],
+                   "intact_cells": n_intact},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_rb_half<double,2,false> (finest-level Gauss-Seidel half-sweep)",
+                     "algo_bytes_per_launch": by, "avg_launch_us": avg_ms * 1e3,
+                     "timing": "HIP events around each finest-level launch, one profiled solve "
+                               "after the timed steps"},
+        "fracture_kernels": {
+            "crack_drive": {"us": t_cd * 1e6, "algo_bytes": by_cd,
+                            "algo_GBps": by_cd / t_cd / 1e9,
+                            "frac_hbm_peak": by_cd / t_cd / 1e9 / HBM_PEAK_GBS},
+            "phase_step": {"us": t_ps * 1e6, "algo_bytes": by_ps,
+                           "algo_GBps": by_ps / t_ps / 1e9,
+                           "frac_hbm_peak": by_ps / t_ps / 1e9 / HBM_PEAK_GBS},
+            "timing": "HIP events around single launches, median of 10"},
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        import oracle
+        u_h, H_h, c_h = u.cpu().numpy(), st_["H"].cpu().numpy(), st_["c"].cpu().numpy()
+        psi_h = st_["psi"].cpu().numpy()
+        t0 = time.perf_counter()
+        H_h, i_h = oracle.crack_drive(p.ncell, p.h, p.lam, p.mu, u_h, H_h)
+        oracle.phase_step(p.ncell, p.h, c_h, H_h, i_h, e["Gc"], e["xi"], e["M"], e["dt"], e["eta"])
+        t_pf = time.perf_counter() - t0
+        q = si.Problem(p.name, p.ncell, p.h, p.lam, p.mu, p.psi_floor, psi_h, p.kind, p.val)
+        base = _cpu_baseline(q, int(np.median(cyc)), free, krylov=1)
+        per_step = t_pf + free / base["value"]
+        line["cpu_baseline"] = {
+            "value": free / per_step, "unit": "DOF/s", "cores": base["cores"], "kind": "oracle",
+            "sample": (f"FP64 oracle on the same step: crack driving force and Ginzburg-Landau "
+                       f"step timed ({t_pf:.1f} s), solve " +
+                       base["sample"].split("on the same workload: ")[-1] +
+                       "; the oracle solve starts from zero, its per-iteration cost is used"),
+        }
+    print(json.dumps(line), flush=True)
+
+
+# 2D finest half-sweep: u (16), psi (8), f (16) read, u (16) written per node
+PF_SMOOTH_BYTES = 56.0
+
+
 def _free_dof(p):
     import numpy as np
     d = p.dim
@@ -523,7 +676,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="spherical_voids_129",
                     choices=["spherical_voids_129", "diffuse_crack_257", "cantilever_193x97x97",
-                             AMR_WORKLOAD, J2_WORKLOAD])
+                             AMR_WORKLOAD, J2_WORKLOAD, PF_WORKLOAD])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--counter-driver", action="store_true",
@@ -542,6 +695,8 @@ def main():
 
     if args.workload == AMR_WORKLOAD:
         return _bench_amr(args)
+    if args.workload == PF_WORKLOAD:
+        return _bench_pf(args)
     if args.workload == J2_WORKLOAD:
         return _bench_j2(args)
 

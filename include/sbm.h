@@ -235,6 +235,38 @@ sbm_status sbm_plastic_source(sbm_ctx *ctx, const double *eps_p, double *f);
 sbm_status sbm_return_map(sbm_ctx *ctx, const double *u, const sbm_j2 *mat, double *eps_p,
                           double *alpha, double *beta, int64_t *n_plastic_host);
 
+/* ------------------------------------------- phase-field fracture -------
+ * Sec. 3.2 (hybrid formulation, eqs. PFFracture and PFFractureGL): the
+ * equilibrium is the SBM solve with psi = g(c) + eta, g(c) = 4c^3 - 3c^4; the
+ * crack field c (cells, device) evolves by an explicit Ginzburg-Landau step
+ * driven by the history field H of the tensile strain energy.  2D (plane
+ * strain) and 3D. */
+typedef struct {
+  double Gc;  /* fracture energy */
+  double xi;  /* regularisation length */
+  double M;   /* crack mobility */
+  double dt;  /* time step */
+  double eta; /* residual stiffness (psi = g(c) + eta) */
+} sbm_pf;
+
+/* Crack driving force of every cell for the strain of u (cell-centre sym
+ * grad, as sbm_return_map): principal strains e_i, W0+- = lambda/2
+ * (sum <e_i>+-)^2 + mu sum <e_i>+-^2; H <- max(H, W0+) in place; intact[c] =
+ * 1 where W0+ < W0- (the crack field is held at 1 there), else 0.  H and
+ * intact: cells (double, uint8).  Async. */
+sbm_status sbm_crack_drive(sbm_ctx *ctx, const double *u, double *H, uint8_t *intact);
+
+/* One explicit step c_out = c - dt M [g'(c) H - Gc (2 xi lap(c) + w'(c) /
+ * (2 xi))], w = 1 - g, projected onto [0, 1] (the range of the crack field;
+ * a NaN stays NaN), c_out = 1 where intact; lap is the cell Laplacian
+ * (2d+1 points) with zero flux across the box faces.  Also writes psi_out =
+ * g(c_out) + eta, the indicator of the next sbm_set_problem (pass floor
+ * <= eta).  crack_out must not alias crack.  Needs only the grid of ctx.
+ * Async. */
+sbm_status sbm_phase_step(sbm_ctx *ctx, const double *crack, const double *H,
+                          const uint8_t *intact, const sbm_pf *p, double *crack_out,
+                          double *psi_out);
+
 /* Compliance J = h^d sum over free DOF of fA . u (Sec. 3.3, the work of the
  * load), written to *J_host; synchronises. */
 sbm_status sbm_compliance(sbm_ctx *ctx, const double *u, double *J_host);

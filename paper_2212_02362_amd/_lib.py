@@ -39,6 +39,11 @@ class SbmJ2(ctypes.Structure):
     _fields_ = [("sigma_y", ctypes.c_double), ("hbar", ctypes.c_double), ("theta", ctypes.c_double)]
 
 
+class SbmPf(ctypes.Structure):
+    _fields_ = [("Gc", ctypes.c_double), ("xi", ctypes.c_double), ("M", ctypes.c_double),
+                ("dt", ctypes.c_double), ("eta", ctypes.c_double)]
+
+
 class SbmOptions(ctypes.Structure):
     _fields_ = [("smoother", ctypes.c_int), ("omega", ctypes.c_double), ("nu_pre", ctypes.c_int),
                 ("nu_post", ctypes.c_int), ("precision", ctypes.c_int), ("rtol", ctypes.c_double),
@@ -73,6 +78,8 @@ SIGNATURES = {
     "sbm_compliance": (ctypes.c_int, [_P, _P, _DP]),
     "sbm_plastic_source": (ctypes.c_int, [_P, _P, _P]),
     "sbm_return_map": (ctypes.c_int, [_P, _P, ctypes.POINTER(SbmJ2), _P, _P, _P, _I64P]),
+    "sbm_crack_drive": (ctypes.c_int, [_P, _P, _P, _P]),
+    "sbm_phase_step": (ctypes.c_int, [_P, _P, _P, _P, ctypes.POINTER(SbmPf), _P, _P]),
     "sbm_profile": (ctypes.c_int, [_P, ctypes.c_int]),
     "sbm_graph_info": (ctypes.c_int, [_P, _I64P, _I64P]),
     "sbm_profile_read": (ctypes.c_int, [_P, _DP, _I64P]),

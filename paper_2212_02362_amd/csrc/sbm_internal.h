@@ -178,6 +178,14 @@ hipError_t launch_plastic_source(const Level &L, double lam, double mu, const do
 hipError_t launch_return_map(const Level &L, double mu, double sigma_y, double hbar, double theta,
                              const double *u, double *eps_p, double *alpha, double *beta,
                              int *count, hipStream_t st);
+// Phase-field fracture (sbm_fracture.hip): crack driving force of every cell
+// (H <- max(H, W0+), intact <- W0+ < W0-) and one explicit Ginzburg-Landau
+// step of the crack field c (writing c1 and psi = g(c1) + eta).
+hipError_t launch_crack_drive(const Level &L, double lam, double mu, const double *u, double *H,
+                              uint8_t *intact, hipStream_t st);
+hipError_t launch_phase_step(const Level &L, const double *c0, const double *H,
+                             const uint8_t *intact, double Gc, double xi, double M, double dt,
+                             double eta, double *c1, double *psi, hipStream_t st);
 hipError_t launch_sensitivity(const Level &L, double lam, double mu, const Traction &tr,
                               const double *u, const double *adj, double lam_scale,
                               const double *design, int chain, double psi_floor, double *g,

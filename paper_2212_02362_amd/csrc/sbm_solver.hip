@@ -1035,6 +1035,30 @@ sbm_status sbm_return_map(sbm_ctx *c, const double *u, const sbm_j2 *mat, double
   return SBM_OK;
 }
 
+sbm_status sbm_crack_drive(sbm_ctx *c, const double *u, double *H, uint8_t *intact) {
+  NEED_PROBLEM(c);
+  if (!u || !H || !intact) return fail(SBM_E_ARG, "NULL argument");
+  Level &L0 = c->L[0];
+  HIP_TRY(launch_crack_drive(L0, c->mat.lambda, c->mat.mu, u, H, intact, c->st));
+  return SBM_OK;
+}
+
+sbm_status sbm_phase_step(sbm_ctx *c, const double *crack, const double *H, const uint8_t *intact,
+                          const sbm_pf *p, double *crack_out, double *psi_out) {
+  if (!c) return fail(SBM_E_ARG, "ctx is NULL");
+  if (!crack || !H || !intact || !p || !crack_out || !psi_out)
+    return fail(SBM_E_ARG, "NULL argument");
+  if (crack == crack_out) return fail(SBM_E_ARG, "crack_out must not alias crack");
+  if (!(p->Gc >= 0.0) || !(p->xi > 0.0) || !(p->M >= 0.0) || !(p->dt >= 0.0) || !(p->eta >= 0.0) ||
+      !isfinite(p->Gc) || !isfinite(p->xi) || !isfinite(p->M) || !isfinite(p->dt) ||
+      !isfinite(p->eta))
+    return fail(SBM_E_ARG, "phase-field parameters: Gc, M, dt, eta >= 0, xi > 0, finite");
+  Level &L0 = c->L[0];
+  HIP_TRY(launch_phase_step(L0, crack, H, intact, p->Gc, p->xi, p->M, p->dt, p->eta, crack_out,
+                            psi_out, c->st));
+  return SBM_OK;
+}
+
 sbm_status sbm_compliance(sbm_ctx *c, const double *u, double *J) {
   NEED_PROBLEM(c);
   if (!u || !J) return fail(SBM_E_ARG, "NULL argument");

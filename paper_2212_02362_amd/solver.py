@@ -15,7 +15,7 @@ from typing import Optional, Sequence
 import numpy as np
 import torch
 
-from ._lib import (SbmJ2, CHAIN_FLOOR, CHAIN_PSI, CHAIN_RHO3, DISPLACEMENT, SBM_NOT_CONVERGED, SBM_OK,
+from ._lib import (SbmJ2, SbmPf, CHAIN_FLOOR, CHAIN_PSI, CHAIN_RHO3, DISPLACEMENT, SBM_NOT_CONVERGED, SBM_OK,
                    TRACTION, SbmBc, SbmError, SbmGrid, SbmMaterial, SbmOptions, check, lib)
 
 __all__ = ["Solver", "SbmError", "TRACTION", "DISPLACEMENT"]
@@ -237,6 +237,40 @@ class Solver:
         check(lib().sbm_return_map(self._ctx, _ptr(u_t), ctypes.byref(m), _ptr(state[0]),
                                    _ptr(state[1]), _ptr(state[2]), ctypes.byref(n)))
         return state[0], state[1], state[2], int(n.value)
+
+    # ------------------------------------------------ phase-field fracture
+    def crack_drive(self, u, H, *, inplace=False):
+        """Crack driving force: returns (H updated to max(H, W0+), intact
+        cells as uint8) for the strain of u."""
+        u_t = self._dev(u, shape=(self.dim,) + self.node_shape)
+        h_t = self._dev(H, shape=self.cell_shape)
+        if inplace and h_t is not H:
+            raise ValueError("inplace needs a contiguous float64 tensor on the solver's device")
+        if not inplace:
+            h_t = h_t.clone()
+        intact = torch.empty(self.cell_shape, dtype=torch.uint8, device=self.device)
+        check(lib().sbm_crack_drive(self._ctx, _ptr(u_t), _ptr(h_t), _ptr(intact)))
+        return h_t, intact
+
+    def phase_step(self, c, H, intact, Gc, xi, M, dt, eta=1e-4, out=None):
+        """One explicit Ginzburg-Landau step of the crack field; returns
+        (c_new, psi = g(c_new) + eta), written into ``out`` = (c_new, psi)
+        when given (contiguous float64 cell tensors on the solver's device,
+        c_new not aliasing c)."""
+        c_t = self._dev(c, shape=self.cell_shape)
+        h_t = self._dev(H, shape=self.cell_shape)
+        i_t = self._dev(intact, dtype=torch.uint8, shape=self.cell_shape)
+        if out is None:
+            c1 = torch.empty(self.cell_shape, dtype=torch.float64, device=self.device)
+            psi = torch.empty_like(c1)
+        else:
+            c1, psi = (self._dev(o, shape=self.cell_shape) for o in out)
+            if c1 is not out[0] or psi is not out[1]:
+                raise ValueError("out: contiguous float64 tensors on the solver's device")
+        pf = SbmPf(float(Gc), float(xi), float(M), float(dt), float(eta))
+        check(lib().sbm_phase_step(self._ctx, _ptr(c_t), _ptr(h_t), _ptr(i_t), ctypes.byref(pf),
+                                   _ptr(c1), _ptr(psi)))
+        return c1, psi
 
     def compliance(self, u):
         """J = h^d sum over free DOF of f.u."""

@@ -322,3 +322,32 @@ def j2_void_tension(n: int = 32, radii=(7.5, 4.08, 4.08), floor: float = 1e-4) -
     lam, mu = lame(210.0, 0.3)
     return Problem("j2_void_tension", (n, n, n), (h, h, h), lam, mu, floor, psi, kind, val,
                    extra={"sigma_y": 0.2, "hbar": 50.0, "theta": 1.0, "radii": tuple(radii)})
+
+
+def pf_mode1_2d(n: int = 4096, L: float = 0.02, notch: float = 1.5e-4, xi: float = 1e-5,
+                uy: float = 1.5e-5, floor: float = 1e-4) -> Problem:
+    """The Mode-I phase-field fracture specimen (Sec. 3.2) on a uniform grid:
+    the square [-L/2, L/2]^2 with n x n cells, lambda = 121.15e9, mu =
+    80.77e9 (Pa), a notch of length ``notch`` along y = 0 from the centre of
+    the left edge.  The initial crack field is c = 1 - exp(-d / xi), d the
+    distance of the cell centre to the notch segment; the indicator is
+    psi = g(c) + eta, g(c) = 4c^3 - 3c^4, eta = 1e-4 (``psi_raw``).  Bottom
+    edge clamped, y-displacement ``uy`` prescribed on the top edge (x free),
+    left and right edges traction free.  ``extra`` holds c0 and the
+    Ginzburg-Landau parameters Gc = 2700, xi, M = 1e-5, dt = 1e-4, eta."""
+    h = L / n
+    X, Y = cell_centres((n, n), (h, h))
+    X, Y = X - 0.5 * L, Y - 0.5 * L
+    x1 = -0.5 * L + notch
+    dx = np.maximum(X - x1, 0.0)
+    d = np.sqrt(dx * dx + Y * Y)
+    c0 = 1.0 - np.exp(-d / xi)
+    eta = 1e-4
+    psi = 4.0 * c0 ** 3 - 3.0 * c0 ** 4 + eta
+    kind, val = _bc_table()
+    kind[2, :] = DISPLACEMENT
+    kind[3, 1] = DISPLACEMENT
+    val[3, 1] = uy
+    return Problem("pf_mode1_2d", (n, n), (h, h), 121.15e9, 80.77e9, floor, psi, kind, val,
+                   extra={"c0": c0, "Gc": 2700.0, "xi": xi, "M": 1e-5, "dt": 1e-4, "eta": eta,
+                          "notch": notch, "uy": uy})
