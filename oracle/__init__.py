@@ -311,6 +311,19 @@ def phase_step(ncell, h, c, H, intact, Gc, xi, M, dt, eta=1e-4):
     return c1, psi
 
 
+def diffuse_traction(ncell, h, psi_raw, floor, t_hat=None, pressure=0.0):
+    """Load of a diffuse traction (Sec. 2.1, eq. SBMLinearElasticity):
+    t_hat |grad psi| + pressure grad psi at every node (psi floored)."""
+    d = len(ncell)
+    f = np.empty((d,) + node_shape(ncell))
+    th = None if t_hat is None else np.ascontiguousarray(t_hat, np.float64)
+    lib().orc_diffuse_traction(d, _long3(ncell), _dbl3(h),
+                               _d(np.ascontiguousarray(psi_raw, np.float64)),
+                               ctypes.c_double(floor), _d(th) if th is not None else None,
+                               ctypes.c_double(pressure), _d(f))
+    return f
+
+
 def assemble(ncell, h, lam, mu, psi):
     """Dense K (small grids only) built column by column from ``apply``."""
     d = len(ncell)

@@ -1100,6 +1100,70 @@ void orc_phase_step(int dim, const long *nc, const double *h, const double *c0, 
   }
 }
 
+/* Diffuse traction on the diffuse boundary (Sec. 2.1, eq. SBMLinearElasticity):
+ * the traction t0 of the sharp boundary, extended along the normals as t^0
+ * (constant across the diffuse band), enters the load as t^0 |grad psi|.  In
+ * the sign convention of K u = f (f = b + t for a traction t with the
+ * outward normal of the solid), the load of node n is
+ *     f(n) = t^0(n) |grad psi(n)| + p grad psi(n),
+ * the second term being a pressure p acting on the solid from the empty side
+ * (t = -p n_out with n_out = -grad psi / |grad psi|, so t |grad psi| =
+ * p grad psi: no normal has to be formed).  psi = max(psi_raw, floor).  The
+ * node gradient along axis a is the mean, over the 2^(d-1) pairs of cells
+ * that face each other across the node along a, of their difference quotient;
+ * a cell outside the box takes the value of the nearest cell inside, so the
+ * box faces (whose tractions are the box-face sources) add nothing here.
+ * t_hat: node field, dim components (NULL: none). */
+static double psi_clamped(const grid_t *g, const double *psi, const long *c) {
+  long q[3];
+  for (int a = 0; a < 3; ++a) {
+    q[a] = a < g->dim ? c[a] : 0;
+    if (q[a] < 0) q[a] = 0;
+    if (q[a] > g->nc[a] - 1) q[a] = g->nc[a] - 1;
+  }
+  return psi[q[0] + g->nc[0] * (q[1] + g->nc[1] * q[2])];
+}
+
+void orc_diffuse_traction(int dim, const long *nc, const double *h, const double *psi_raw,
+                          double floor_, const double *t_hat, double p, double *f) {
+  grid_t g;
+  grid_init(&g, dim, nc, h, 0.0, 0.0);
+  double *psi = (double *)malloc(sizeof(double) * g.NC);
+  orc_floor(g.NC, psi_raw, floor_, psi);
+  const int npair = 1 << (dim - 1);
+  for (long id = 0; id < g.NN; ++id) {
+    long n[3];
+    node_of(&g, id, n);
+    double grad[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < dim; ++a) {
+      double acc = 0.0;
+      for (int o = 0; o < npair; ++o) {
+        long lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+        int bit = 0;
+        for (int e = 0; e < dim; ++e) {
+          if (e == a) {
+            lo[e] = n[e] - 1;
+            hi[e] = n[e];
+          } else {
+            lo[e] = hi[e] = n[e] - 1 + ((o >> bit) & 1);
+            ++bit;
+          }
+        }
+        acc += psi_clamped(&g, psi, hi) - psi_clamped(&g, psi, lo);
+      }
+      grad[a] = acc / npair / g.h[a];
+    }
+    double mag = 0.0;
+    for (int a = 0; a < dim; ++a) mag += grad[a] * grad[a];
+    mag = sqrt(mag);
+    for (int k = 0; k < dim; ++k) {
+      const long q = (long)k * g.NN + id;
+      f[q] = (t_hat ? t_hat[q] * mag : 0.0) + p * grad[k];
+    }
+  }
+  free(psi);
+}
+
 /* ======================================================================
  * Block-structured adaptive composite solve (BSAMR).
  *
