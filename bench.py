@@ -487,6 +487,114 @@ def _bench_pf(args):
     print(json.dumps(line), flush=True)
 
 
+PRESS_WORKLOAD = "pressurised_voids_129"
+PRESS_DESC = ("3D unit cube, 129^3 nodes (128^3 cells), E=1 nu=0.3, the 20 seeded spherical voids of "
+              "spherical_voids_129 (seed 0) under an internal pressure 1e-3 applied as the diffuse "
+              "traction load p grad psi (Sec. 2.1), psi floor 1e-6, z=0 clamped, other faces free.  "
+              "One step = diffuse traction load, set_problem, V(2,2) solve to 1e-10")
+
+
+def _bench_pressure(args):
+    """Solves loaded by a diffuse traction (a pressure in every void).  value
+    = free DOF / second of whole steps (load, set-up, FP64 V-cycle solve);
+    roofline for the finest half-sweep; the load kernel is timed apart."""
+    import numpy as np
+    import torch
+
+    import sbm_inputs as si
+    from paper_2212_02362_amd import Solver
+
+    p = si.pressurised_voids_3d(128)
+    pr = p.extra["pressure"]
+    free = _free_dof(p)
+    nodes, cells = p.n_nodes, int(np.prod(p.ncell))
+    S = Solver(p.ncell, p.h, rtol=1e-10, max_cycles=400)
+    psi_dev = torch.tensor(p.psi_raw, dtype=torch.float64, device="cuda")
+    b = S.new_nodes()
+
+    def one():
+        S.diffuse_traction(psi_dev, p.psi_floor, pressure=pr, out=b)
+        S.set_problem(psi_dev, p.lam, p.mu, p.psi_floor, p.kind, p.val, b)
+        return S.solve()
+
+    print(f"[bench] {PRESS_WORKLOAD}: {nodes} nodes, {free} free DOF", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cyc, sts, fin = [], [], []
+    for _ in range(args.steps):
+        u, hist, status = one()
+        cyc.append(len(hist) - 1)
+        sts.append(int(status))
+        fin.append(float(hist[-1]))
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / args.steps
+    print(f"[bench] {PRESS_WORKLOAD}: {t * 1e3:.2f} ms/step, cycles {cyc}, max |u| "
+          f"{float(u.abs().max()):.3e}", file=sys.stderr, flush=True)
+    S.profile(True)
+    S.solve()
+    prof = S.profile_read()
+    S.profile(False)
+    ms_s, n_s = prof["smooth"]
+    avg_ms = ms_s / max(n_s, 1)
+    by = ALGO_BYTES["smooth"][0] * nodes
+    achieved = by / (avg_ms * 1e-3) / 1e9
+    ts = []
+    for _ in range(10):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        S.diffuse_traction(psi_dev, p.psi_floor, pressure=pr, out=b)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3)
+    t_dt = float(np.median(ts))
+    by_dt = 8.0 * cells + 24.0 * nodes   # psi read, load written
+    line = {
+        "metric": METRIC,
+        "value": free / t,
+        "unit": "DOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": PRESS_DESC, "nodes": nodes, "free_dof": free, "precision": "fp64",
+                   "method": "diffuse traction load + V-cycle iteration", "cycles": cyc,
+                   "final_rel_residual": max(fin), "status": sts},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_rb_half<double,3,false> (finest-level Gauss-Seidel half-sweep)",
+                     "algo_bytes_per_launch": by, "avg_launch_us": avg_ms * 1e3,
+                     "timing": "HIP events around each finest-level launch, one profiled solve "
+                               "after the timed steps"},
+        "traction_kernel": {"k_diffuse_traction": {
+            "us": t_dt * 1e6, "algo_bytes": by_dt, "algo_GBps": by_dt / t_dt / 1e9,
+            "frac_hbm_peak": by_dt / t_dt / 1e9 / HBM_PEAK_GBS},
+            "timing": "HIP events around single launches, median of 10"},
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        import oracle
+        t0 = time.perf_counter()
+        load = oracle.diffuse_traction(p.ncell, p.h, p.psi_raw, p.psi_floor, pressure=pr)
+        t_ld = time.perf_counter() - t0
+        q = si.Problem(p.name, p.ncell, p.h, p.lam, p.mu, p.psi_floor, p.psi_raw, p.kind, p.val,
+                       b=load)
+        base = _cpu_baseline(q, int(np.median(cyc)), free)
+        per_step = t_ld + free / base["value"]
+        line["cpu_baseline"] = {
+            "value": free / per_step, "unit": "DOF/s", "cores": base["cores"], "kind": "oracle",
+            "sample": (f"FP64 oracle on the same step: diffuse traction load timed ({t_ld:.2f} s), "
+                       f"solve " + base["sample"].split("on the same workload: ")[-1]),
+        }
+    print(json.dumps(line), flush=True)
+
+
 # 2D finest half-sweep: u (16), psi (8), f (16) read, u (16) written per node
 PF_SMOOTH_BYTES = 56.0
 
@@ -676,7 +784,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="spherical_voids_129",
                     choices=["spherical_voids_129", "diffuse_crack_257", "cantilever_193x97x97",
-                             AMR_WORKLOAD, J2_WORKLOAD, PF_WORKLOAD])
+                             AMR_WORKLOAD, J2_WORKLOAD, PF_WORKLOAD, PRESS_WORKLOAD])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--counter-driver", action="store_true",
@@ -695,6 +803,8 @@ def main():
 
     if args.workload == AMR_WORKLOAD:
         return _bench_amr(args)
+    if args.workload == PRESS_WORKLOAD:
+        return _bench_pressure(args)
     if args.workload == PF_WORKLOAD:
         return _bench_pf(args)
     if args.workload == J2_WORKLOAD:

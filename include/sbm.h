@@ -235,6 +235,25 @@ sbm_status sbm_plastic_source(sbm_ctx *ctx, const double *eps_p, double *f);
 sbm_status sbm_return_map(sbm_ctx *ctx, const double *u, const sbm_j2 *mat, double *eps_p,
                           double *alpha, double *beta, int64_t *n_plastic_host);
 
+/* ----------------------------------------------- diffuse traction -------
+ * Sec. 2.1, eq. SBMLinearElasticity: a traction t0 on the (diffuse) surface
+ * of the solid, extended along the normals across the diffuse band (t_hat,
+ * the value at the closest point of the sharp boundary), is the load
+ * t_hat |grad psi|.  This call writes, at every node,
+ *   f = t_hat |grad psi| + pressure * grad psi,
+ * psi = max(psi_raw, psi_floor) (cells, device), t_hat a node field of d
+ * components (device, may be NULL), f a node field of d components (device,
+ * overwritten).  The pressure term is the load of a pressure acting on the
+ * solid from the empty side.  The sign is that of the box-face tractions of
+ * sbm_set_problem (a traction along the outward normal of the solid pulls).
+ * The node gradient along axis a is the mean of the difference quotients of
+ * the 2^(d-1) cell pairs facing each other across the node; cells outside the
+ * box take the value of the nearest cell inside (the box faces carry their
+ * own tractions).  Pass f as (part of) the body force b of sbm_set_problem.
+ * Needs only the grid of ctx.  Async. */
+sbm_status sbm_diffuse_traction(sbm_ctx *ctx, const double *psi_raw, double psi_floor,
+                                const double *t_hat, double pressure, double *f);
+
 /* ------------------------------------------- phase-field fracture -------
  * Sec. 3.2 (hybrid formulation, eqs. PFFracture and PFFractureGL): the
  * equilibrium is the SBM solve with psi = g(c) + eta, g(c) = 4c^3 - 3c^4; the

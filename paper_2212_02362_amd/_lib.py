@@ -78,6 +78,7 @@ SIGNATURES = {
     "sbm_compliance": (ctypes.c_int, [_P, _P, _DP]),
     "sbm_plastic_source": (ctypes.c_int, [_P, _P, _P]),
     "sbm_return_map": (ctypes.c_int, [_P, _P, ctypes.POINTER(SbmJ2), _P, _P, _P, _I64P]),
+    "sbm_diffuse_traction": (ctypes.c_int, [_P, _P, ctypes.c_double, _P, ctypes.c_double, _P]),
     "sbm_crack_drive": (ctypes.c_int, [_P, _P, _P, _P]),
     "sbm_phase_step": (ctypes.c_int, [_P, _P, _P, _P, ctypes.POINTER(SbmPf), _P, _P]),
     "sbm_profile": (ctypes.c_int, [_P, ctypes.c_int]),

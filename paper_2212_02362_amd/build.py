@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsbm.so")
-SOURCES = ["sbm_kernels.hip", "sbm_tiled.hip", "sbm_tail.hip", "sbm_plastic.hip", "sbm_fracture.hip", "sbm_solver.hip", "sbm_amr.hip"]
+SOURCES = ["sbm_kernels.hip", "sbm_tiled.hip", "sbm_tail.hip", "sbm_plastic.hip", "sbm_fracture.hip", "sbm_traction.hip", "sbm_solver.hip", "sbm_amr.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -178,6 +178,10 @@ hipError_t launch_plastic_source(const Level &L, double lam, double mu, const do
 hipError_t launch_return_map(const Level &L, double mu, double sigma_y, double hbar, double theta,
                              const double *u, double *eps_p, double *alpha, double *beta,
                              int *count, hipStream_t st);
+// Diffuse traction (sbm_traction.hip): f = t_hat |grad psi| + p grad psi at
+// every node of the finest grid, psi = max(psi_raw, floor); t_hat may be NULL.
+hipError_t launch_diffuse_traction(const Level &L, const double *psi_raw, double floor_,
+                                   const double *t_hat, double p, double *f, hipStream_t st);
 // Phase-field fracture (sbm_fracture.hip): crack driving force of every cell
 // (H <- max(H, W0+), intact <- W0+ < W0-) and one explicit Ginzburg-Landau
 // step of the crack field c (writing c1 and psi = g(c1) + eta).

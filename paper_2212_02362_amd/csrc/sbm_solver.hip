@@ -1035,6 +1035,16 @@ sbm_status sbm_return_map(sbm_ctx *c, const double *u, const sbm_j2 *mat, double
   return SBM_OK;
 }
 
+sbm_status sbm_diffuse_traction(sbm_ctx *c, const double *psi_raw, double psi_floor,
+                                const double *t_hat, double pressure, double *f) {
+  if (!c) return fail(SBM_E_ARG, "ctx is NULL");
+  if (!psi_raw || !f) return fail(SBM_E_ARG, "NULL argument");
+  if (!(psi_floor >= 0.0) || !isfinite(psi_floor) || !isfinite(pressure))
+    return fail(SBM_E_ARG, "psi_floor >= 0 and pressure must be finite");
+  HIP_TRY(launch_diffuse_traction(c->L[0], psi_raw, psi_floor, t_hat, pressure, f, c->st));
+  return SBM_OK;
+}
+
 sbm_status sbm_crack_drive(sbm_ctx *c, const double *u, double *H, uint8_t *intact) {
   NEED_PROBLEM(c);
   if (!u || !H || !intact) return fail(SBM_E_ARG, "NULL argument");

@@ -238,6 +238,21 @@ class Solver:
                                    _ptr(state[1]), _ptr(state[2]), ctypes.byref(n)))
         return state[0], state[1], state[2], int(n.value)
 
+    # ---------------------------------------------------- diffuse traction
+    def diffuse_traction(self, psi_raw, psi_floor, t_hat=None, pressure=0.0, out=None):
+        """Node load t_hat |grad psi| + pressure grad psi of a traction on the
+        diffuse boundary (psi = max(psi_raw, psi_floor)); pass it as b."""
+        p_t = self._dev(psi_raw, shape=self.cell_shape)
+        t_t = self._dev(t_hat, shape=(self.dim,) + self.node_shape)
+        if out is None:
+            out = torch.empty((self.dim,) + self.node_shape, dtype=torch.float64,
+                              device=self.device)
+        elif self._dev(out, shape=(self.dim,) + self.node_shape) is not out:
+            raise ValueError("out: a contiguous float64 node tensor on the solver's device")
+        check(lib().sbm_diffuse_traction(self._ctx, _ptr(p_t), float(psi_floor), _ptr(t_t),
+                                         float(pressure), _ptr(out)))
+        return out
+
     # ------------------------------------------------ phase-field fracture
     def crack_drive(self, u, H, *, inplace=False):
         """Crack driving force: returns (H updated to max(H, W0+), intact

@@ -139,6 +139,38 @@ def spherical_voids_3d(n: int = 128, seed: int = 0, nvoid: int = 20,
                    extra={"centres": centres, "radii": radii})
 
 
+def pressurised_voids_3d(n: int = 128, seed: int = 0, nvoid: int = 20, pressure: float = 1e-3,
+                         floor: float = 1e-6) -> Problem:
+    """The voids of ``spherical_voids_3d`` (same draws) under an internal
+    pressure instead of a displacement load: z=0 clamped, every other box
+    face traction free, the load a pressure ``pressure`` on the diffuse void
+    surfaces (Sec. 2.1 diffuse traction; in ``extra``, the load itself is not
+    formed here)."""
+    p = spherical_voids_3d(n, seed, nvoid, floor)
+    kind, val = _bc_table()
+    kind[4, :] = DISPLACEMENT
+    return Problem("pressurised_voids_3d", p.ncell, p.h, p.lam, p.mu, floor, p.psi_raw, kind, val,
+                   extra=dict(p.extra, pressure=pressure))
+
+
+def pressurised_hole_quarter(n: int = 64, L: float = 16.0, a: float = 1.0, width=None,
+                             pressure: float = 1e-3, floor: float = 1e-6) -> Problem:
+    """Quarter plate [0, L]^2 with a circular hole of radius a at the origin
+    under an internal pressure: rollers on x=0 (u_x=0) and y=0 (u_y=0), outer
+    edges free, indicator 0.5(1+tanh((r-a)/width)) (width 2h by default);
+    the pressure is in ``extra``."""
+    h = L / n
+    w = 2.0 * h if width is None else width
+    X, Y = cell_centres((n, n), (h, h))
+    psi = 0.5 * (1 + np.tanh((np.hypot(X, Y) - a) / w))
+    kind, val = _bc_table()
+    kind[0, 0] = DISPLACEMENT
+    kind[2, 1] = DISPLACEMENT
+    lam, mu = lame(1.0, 0.3)
+    return Problem("pressurised_hole_quarter", (n, n), (h, h), lam, mu, floor, psi, kind, val,
+                   extra={"L": L, "a": a, "width": w, "pressure": pressure})
+
+
 def _smooth_field(rng, shape, sigma_cells):
     from scipy.ndimage import gaussian_filter
     g = rng.standard_normal(shape)
