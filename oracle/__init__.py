@@ -340,6 +340,25 @@ def assemble(ncell, h, lam, mu, psi):
 
 # ------------------------------------------------------------------ BSAMR
 
+def br_cluster(flags, eff):
+    """Berger-Rigoutsos clustering of a block flag array (numpy axis order
+    (z, y, x) or (y, x)): returns (flags of the blocks inside the accepted
+    boxes, boxes as [(lo, hi)] with (x, y, z) block indices, inclusive)."""
+    f = np.ascontiguousarray(flags, np.uint8)
+    d = f.ndim
+    nb = tuple(reversed(f.shape))
+    out = np.empty_like(f)
+    cap = int(f.size) + 1
+    boxes = np.zeros(6 * cap, np.int64)
+    L = lib()
+    L.orc_br_cluster.restype = ctypes.c_long
+    n = L.orc_br_cluster(d, _long3(nb), _u8(f), ctypes.c_double(eff), _u8(out),
+                         boxes.ctypes.data_as(ctypes.POINTER(ctypes.c_long)), cap)
+    bx = [(tuple(boxes[6 * i:6 * i + 3][:d]), tuple(boxes[6 * i + 3:6 * i + 6][:d]))
+          for i in range(n)]
+    return out, bx
+
+
 class AmrProblem:
     """Oracle of the block-structured adaptive composite solve.  psi_levels
     are the raw indicators sampled at each level's cell centres (dense,
@@ -347,7 +366,7 @@ class AmrProblem:
 
     def __init__(self, ncell0, h0, lam, mu, psi_levels, psi_floor, kind, val, *, block=32,
                  thresh=0.05, smoother=0, omega=None, nu_pre=2, nu_post=2, bottom_rtol=1e-12,
-                 bottom_max_iter=0, blocks=None):
+                 bottom_max_iter=0, blocks=None, cluster_eff=0.0):
         L = lib()
         L.orc_amr_new.restype = ctypes.c_void_p
         L.orc_amr_fnorm.restype = ctypes.c_double
@@ -373,7 +392,7 @@ class AmrProblem:
                                   ctypes.c_double(psi_floor), k.ctypes.data_as(_ip), _d(v),
                                   ctypes.c_double(thresh), int(smoother), ctypes.c_double(omega),
                                   int(nu_pre), int(nu_post), ctypes.c_double(bottom_rtol),
-                                  int(bottom_max_iter), blk)
+                                  int(bottom_max_iter), blk, ctypes.c_double(cluster_eff))
 
     def __del__(self):
         if getattr(self, "_ctx", None):

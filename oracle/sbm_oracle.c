@@ -1244,8 +1244,155 @@ void orc_amr_tags(int dim, const long *nc, const double *h, const double *psi, d
   }
 }
 
-/* Block flags of levels 1..A from the tags of levels 0..A-1. */
-static void amr_blocks(amr_t *m, uint8_t *const *tags) {
+/* Point clustering of flagged blocks into boxes (the Berger-Rigoutsos
+ * algorithm the paper's AMR uses for regridding, Sec. 2.2): a box is the
+ * bounding box of the flags it holds; it is accepted when flags >= eff *
+ * volume; otherwise it is cut in two and each part is clustered again:
+ *   (1) at a hole: an interior slab with no flag (the signature, the flag
+ *       count per slab, is 0 there); first axis that has one, the hole
+ *       nearest the middle of the box, the lower one on a tie; the hole slab
+ *       belongs to neither part;
+ *   (2) else at the strongest inflection of the signature: Lap(i) =
+ *       S(i-1) - 2 S(i) + S(i+1) for interior slabs, a cut between slabs i and
+ *       i+1 where Lap(i) Lap(i+1) < 0, strength |Lap(i+1) - Lap(i)|; the
+ *       strongest over all axes, the first found (axis order, then i
+ *       ascending) on a tie;
+ *   (3) else in the middle of the longest axis (first longest), the lower
+ *       half taking the middle slab.
+ * Every block inside an accepted box is flagged in out.  Boxes in block
+ * units, [lo, hi] inclusive.  Returns the number of accepted boxes; when
+ * boxes != NULL, writes 6 longs (lo[3], hi[3]) per box (at most max_boxes). */
+typedef struct {
+  int dim;
+  long n[3];
+  const uint8_t *in;
+  uint8_t *out;
+  double eff;
+  long nbox, max_boxes;
+  long *boxes;
+} br_t;
+
+static int br_flag(const br_t *b, long x, long y, long z) {
+  return b->in[x + b->n[0] * (y + b->n[1] * z)] != 0;
+}
+
+static void br_box(br_t *b, const long *lo0, const long *hi0) {
+  long lo[3] = {lo0[0], lo0[1], lo0[2]}, hi[3] = {hi0[0], hi0[1], hi0[2]};
+  /* shrink to the bounding box of the flags inside */
+  long blo[3] = {hi[0] + 1, hi[1] + 1, hi[2] + 1}, bhi[3] = {lo[0] - 1, lo[1] - 1, lo[2] - 1};
+  long cnt = 0;
+  for (long z = lo[2]; z <= hi[2]; ++z)
+    for (long y = lo[1]; y <= hi[1]; ++y)
+      for (long x = lo[0]; x <= hi[0]; ++x) {
+        if (!br_flag(b, x, y, z)) continue;
+        ++cnt;
+        const long p[3] = {x, y, z};
+        for (int a = 0; a < 3; ++a) {
+          if (p[a] < blo[a]) blo[a] = p[a];
+          if (p[a] > bhi[a]) bhi[a] = p[a];
+        }
+      }
+  if (cnt == 0) return;
+  for (int a = 0; a < 3; ++a) { lo[a] = blo[a]; hi[a] = bhi[a]; }
+  double vol = 1.0;
+  for (int a = 0; a < 3; ++a) vol *= (double)(hi[a] - lo[a] + 1);
+  if ((double)cnt >= b->eff * vol) {
+    for (long z = lo[2]; z <= hi[2]; ++z)
+      for (long y = lo[1]; y <= hi[1]; ++y)
+        for (long x = lo[0]; x <= hi[0]; ++x) b->out[x + b->n[0] * (y + b->n[1] * z)] = 1;
+    if (b->boxes && b->nbox < b->max_boxes)
+      for (int a = 0; a < 3; ++a) {
+        b->boxes[6 * b->nbox + a] = lo[a];
+        b->boxes[6 * b->nbox + 3 + a] = hi[a];
+      }
+    ++b->nbox;
+    return;
+  }
+  /* signatures */
+  long *sig[3] = {0, 0, 0};
+  for (int a = 0; a < b->dim; ++a) sig[a] = (long *)calloc(hi[a] - lo[a] + 1, sizeof(long));
+  for (long z = lo[2]; z <= hi[2]; ++z)
+    for (long y = lo[1]; y <= hi[1]; ++y)
+      for (long x = lo[0]; x <= hi[0]; ++x) {
+        if (!br_flag(b, x, y, z)) continue;
+        const long p[3] = {x, y, z};
+        for (int a = 0; a < b->dim; ++a) ++sig[a][p[a] - lo[a]];
+      }
+  int cut_axis = -1;
+  long cut_lo_end = 0, cut_hi_start = 0; /* lower part ends at, upper part starts at */
+  /* (1) holes */
+  for (int a = 0; a < b->dim && cut_axis < 0; ++a) {
+    long best = -1, bestd = 0;
+    for (long i = lo[a] + 1; i < hi[a]; ++i) {
+      if (sig[a][i - lo[a]] != 0) continue;
+      long dist = 2 * i - (lo[a] + hi[a]);
+      if (dist < 0) dist = -dist;
+      if (best < 0 || dist < bestd) { best = i; bestd = dist; }
+    }
+    if (best >= 0) { cut_axis = a; cut_lo_end = best - 1; cut_hi_start = best + 1; }
+  }
+  /* (2) inflections */
+  if (cut_axis < 0) {
+    long best_s = 0;
+    for (int a = 0; a < b->dim; ++a) {
+      for (long i = lo[a] + 1; i + 1 <= hi[a] - 1; ++i) {
+        const long *S = sig[a];
+        long l0 = S[i - 1 - lo[a]] - 2 * S[i - lo[a]] + S[i + 1 - lo[a]];
+        long l1 = S[i - lo[a]] - 2 * S[i + 1 - lo[a]] + S[i + 2 - lo[a]];
+        if (!((l0 < 0 && l1 > 0) || (l0 > 0 && l1 < 0))) continue;
+        long st = l1 - l0;
+        if (st < 0) st = -st;
+        if (st > best_s) { best_s = st; cut_axis = a; cut_lo_end = i; cut_hi_start = i + 1; }
+      }
+    }
+  }
+  /* (3) middle of the longest axis */
+  if (cut_axis < 0) {
+    long len = 0;
+    for (int a = 0; a < b->dim; ++a)
+      if (hi[a] - lo[a] + 1 > len) { len = hi[a] - lo[a] + 1; cut_axis = a; }
+    const long mid = (lo[cut_axis] + hi[cut_axis]) / 2;
+    cut_lo_end = mid;
+    cut_hi_start = mid + 1;
+  }
+  for (int a = 0; a < b->dim; ++a) free(sig[a]);
+  long lo1[3] = {lo[0], lo[1], lo[2]}, hi1[3] = {hi[0], hi[1], hi[2]};
+  long lo2[3] = {lo[0], lo[1], lo[2]}, hi2[3] = {hi[0], hi[1], hi[2]};
+  hi1[cut_axis] = cut_lo_end;
+  lo2[cut_axis] = cut_hi_start;
+  br_box(b, lo1, hi1);
+  br_box(b, lo2, hi2);
+}
+
+long orc_br_cluster(int dim, const long *nb, const uint8_t *in, double eff, uint8_t *out,
+                    long *boxes, long max_boxes) {
+  br_t b;
+  memset(&b, 0, sizeof(b));
+  b.dim = dim;
+  for (int a = 0; a < 3; ++a) b.n[a] = a < dim ? nb[a] : 1;
+  b.in = in;
+  b.out = out;
+  b.eff = eff;
+  b.boxes = boxes;
+  b.max_boxes = max_boxes;
+  memset(out, 0, (size_t)(b.n[0] * b.n[1] * b.n[2]));
+  const long lo[3] = {0, 0, 0}, hi[3] = {b.n[0] - 1, b.n[1] - 1, b.n[2] - 1};
+  br_box(&b, lo, hi);
+  return b.nbox;
+}
+
+/* Block flags of levels 1..A from the tags of levels 0..A-1; with eff > 0
+ * the flags of each level, finest first, are replaced by the blocks of their
+ * Berger-Rigoutsos boxes before they nest into the next coarser level. */
+static void amr_cluster_level(amr_t *m, int a, double eff) {
+  const long nbt = m->nb[a][0] * m->nb[a][1] * m->nb[a][2];
+  uint8_t *tmp = (uint8_t *)malloc(nbt);
+  orc_br_cluster(m->dim, m->nb[a], m->blk[a], eff, tmp, NULL, 0);
+  memcpy(m->blk[a], tmp, nbt);
+  free(tmp);
+}
+
+static void amr_blocks(amr_t *m, uint8_t *const *tags, double eff) {
   const int d = m->dim;
   for (int a = 1; a <= m->A; ++a) {
     grid_t *gc = &m->g[a - 1];
@@ -1273,6 +1420,7 @@ static void amr_blocks(amr_t *m, uint8_t *const *tags) {
   /* nesting, finest first: parent and the parent's neighbours on the sides
    * the block touches */
   for (int a = m->A; a >= 2; --a) {
+    if (eff > 0.0) amr_cluster_level(m, a, eff);
     long nbt = m->nb[a][0] * m->nb[a][1] * m->nb[a][2];
     for (long b = 0; b < nbt; ++b) {
       if (!m->blk[a][b]) continue;
@@ -1296,6 +1444,7 @@ static void amr_blocks(amr_t *m, uint8_t *const *tags) {
       }
     }
   }
+  if (eff > 0.0 && m->A >= 1) amr_cluster_level(m, 1, eff);
 }
 
 static int amr_cell_active(const amr_t *m, int a, const long *c) {
@@ -1550,7 +1699,8 @@ static void amr_fas(amr_t *m, int a, double **x, double **f, double **w, double 
 void *orc_amr_new(int dim, int A, int bc, const long *nc0, const double *h0, double lam, double mu,
                   const double *const *psi_raw, double psi_floor, const int *kind, const double *val,
                   double thresh, int smoother, double omega, int nu_pre, int nu_post,
-                  double bottom_rtol, int bottom_max_iter, const uint8_t *const *blk_in) {
+                  double bottom_rtol, int bottom_max_iter, const uint8_t *const *blk_in,
+                  double cluster_eff) {
   amr_t *m = (amr_t *)calloc(1, sizeof(amr_t));
   m->dim = dim; m->A = A; m->bc = bc; m->lam = lam; m->mu = mu;
   memcpy(m->kind, kind, sizeof(int) * 18);
@@ -1585,7 +1735,7 @@ void *orc_amr_new(int dim, int A, int bc, const long *nc0, const double *h0, dou
       tags[a] = (uint8_t *)malloc(m->g[a].NC);
       orc_amr_tags(dim, m->g[a].nc, m->g[a].h, m->psi[a], thresh, tags[a]);
     }
-    amr_blocks(m, tags);
+    amr_blocks(m, tags, cluster_eff);
     for (int a = 0; a < A; ++a) free(tags[a]);
   }
   for (int a = 1; a <= A; ++a) amr_classify(m, a);
