@@ -84,6 +84,8 @@ def _bench_amr(args):
           file=sys.stderr, flush=True)
     psi_dev = [torch.tensor(x, dtype=torch.float64, device="cuda") for x in psis]
     S = AmrSolver(p.ncell, p.h, 3, 32, rtol=1e-10, max_cycles=400)
+    if args.cluster_eff > 0.0:
+        S.set_clustering(args.cluster_eff)
 
     def one():
         S.set_problem(psi_dev, p.lam, p.mu, p.psi_floor, p.kind, p.val, thresh=0.05)
@@ -138,7 +140,10 @@ def _bench_amr(args):
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": AMR_DESC, "composite_dof": dof,
+        "config": {"workload": AMR_DESC + (f"; blocks regridded by Berger-Rigoutsos clustering "
+                                           f"at efficiency {args.cluster_eff}"
+                                           if args.cluster_eff > 0.0 else ""),
+                   "composite_dof": dof,
                    "level1_block_fraction": float(blk1.mean()),
                    "level2_block_fraction": float(blk2.mean()),
                    "finest_unknown_nodes": n_active, "finest_dense_nodes": nodes2,
@@ -166,7 +171,7 @@ def _bench_amr(args):
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         t0 = time.perf_counter()
         m = oracle.AmrProblem(p.ncell, p.h, p.lam, p.mu, psis, p.psi_floor, p.kind, p.val,
-                              block=32, thresh=0.05)
+                              block=32, thresh=0.05, cluster_eff=args.cluster_eff)
         t_setup = time.perf_counter() - t0
         t0 = time.perf_counter()
         m.solve(rtol=0.0, max_cycles=0)
@@ -786,6 +791,8 @@ def main():
                     choices=["spherical_voids_129", "diffuse_crack_257", "cantilever_193x97x97",
                              AMR_WORKLOAD, J2_WORKLOAD, PF_WORKLOAD, PRESS_WORKLOAD])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cluster-eff", type=float, default=0.0,
+                    help="adaptive workload: Berger-Rigoutsos efficiency of the block boxes")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--counter-driver", action="store_true",
                     help="run the dominant kernel and a calibration copy (under rocprofv3 --pmc)")

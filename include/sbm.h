@@ -422,6 +422,27 @@ sbm_status sbm_amr_create(const sbm_grid *base, int levels, int block, const sbm
 
 sbm_status sbm_amr_set_options(sbm_amr_ctx *ctx, const sbm_options *opts);
 
+/* Regridding by Berger-Rigoutsos point clustering (Sec. 2.2), used by the
+ * next sbm_amr_set_problem that tags (blocks_host == NULL): on each level
+ * a >= 1, finest first, the tagged block flags are replaced by the blocks of
+ * boxes that each hold flags >= efficiency * volume, before they nest into
+ * level a-1.  A box is the bounding box of its flags; one that is too sparse
+ * is cut at an interior slab without flags (first axis that has one, the
+ * slab nearest the middle, the lower on a tie), else between slabs i, i+1
+ * where the discrete Laplacian of the signature (flags per slab) changes
+ * sign, at the largest jump (first in axis order, then ascending i, on a
+ * tie), else in the middle of its longest axis (the lower part keeps the
+ * middle slab).  efficiency in [0, 1]; 0 (the default) keeps the tagged
+ * blocks as they are.  Host-side; set_problem synchronises per level. */
+sbm_status sbm_amr_set_clustering(sbm_amr_ctx *ctx, double efficiency);
+
+/* The same clustering of one flag array, on the host (no device, no
+ * context): flags_host / out_host are uint8 [nb2][nb1][nb0] (2D: [nb1][nb0]),
+ * nblocks[0..dim-1] the counts per axis; out_host gets the blocks of the
+ * accepted boxes (it must not alias flags_host). */
+sbm_status sbm_amr_cluster(int dim, const int64_t *nblocks, const uint8_t *flags_host,
+                           double efficiency, uint8_t *out_host);
+
 /* psi_raw[a]: raw indicator at the cell centres of level a (device, dense),
  * floored cell-wise by mat->psi_floor.  blocks_host: NULL (tag with
  * tag_threshold) or levels-1 host arrays of block flags of levels 1.. that

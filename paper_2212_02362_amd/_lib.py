@@ -104,6 +104,8 @@ SIGNATURES = {
                                       ctypes.POINTER(SbmOptions), _P, ctypes.c_size_t, _P,
                                       ctypes.POINTER(_P)]),
     "sbm_amr_set_options": (ctypes.c_int, [_P, ctypes.POINTER(SbmOptions)]),
+    "sbm_amr_set_clustering": (ctypes.c_int, [_P, ctypes.c_double]),
+    "sbm_amr_cluster": (ctypes.c_int, [ctypes.c_int, _P, _P, ctypes.c_double, _P]),
     "sbm_amr_set_problem": (ctypes.c_int, [_P, ctypes.POINTER(_P), ctypes.POINTER(SbmMaterial),
                                            ctypes.POINTER(SbmBc), ctypes.c_double,
                                            ctypes.POINTER(_P)]),

@@ -28,6 +28,19 @@ def _ptr_array(tensors):
     return arr
 
 
+def cluster_blocks(flags, efficiency):
+    """Berger-Rigoutsos clustering of a uint8 block-flag array (numpy axis
+    order (z, y, x) or (y, x)) on the host, by the library's own routine."""
+    f = np.ascontiguousarray(flags, np.uint8)
+    if f.ndim not in (2, 3):
+        raise ValueError("flags must be 2D or 3D")
+    nb = (ctypes.c_int64 * 3)(*(list(reversed(f.shape)) + [1] * (3 - f.ndim)))
+    out = np.empty_like(f)
+    check(lib().sbm_amr_cluster(f.ndim, ctypes.cast(nb, _P), f.ctypes.data_as(_P),
+                                float(efficiency), out.ctypes.data_as(_P)))
+    return out
+
+
 class AmrSolver:
     """Base grid ``ncell0`` with spacing ``h0``, ``levels`` AMR levels (base
     included, refinement ratio 2) and cubic blocks of ``block`` cells.
@@ -80,6 +93,12 @@ class AmrSolver:
                 self._ctx = None
         except Exception:
             pass
+
+    def set_clustering(self, efficiency):
+        """Berger-Rigoutsos clustering of the tagged blocks at the next
+        ``set_problem`` without ``blocks`` (0 turns it off)."""
+        check(lib().sbm_amr_set_clustering(self._ctx, float(efficiency)))
+        return self
 
     def set_options(self, **options):
         for k, v in options.items():

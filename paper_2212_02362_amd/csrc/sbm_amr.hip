@@ -641,6 +641,7 @@ struct sbm_amr_ctx {
   double fnorm = 0.0;
   int64_t comp_dof = 0;
   bool have_problem = false;
+  double cluster_eff = 0.0;  // Berger-Rigoutsos efficiency of the block boxes (0: off)
   // live timing of finest-level launches
   bool prof_on = false;
   std::vector<hipEvent_t> prof_ev;  // pairs
@@ -648,6 +649,120 @@ struct sbm_amr_ctx {
   double prof_ms[SBM_PROF_N] = {0};
   int64_t prof_n[SBM_PROF_N] = {0};
 };
+
+// Berger-Rigoutsos point clustering of the block flags of one level (host):
+// every flagged block ends inside an accepted box, a box being the bounding
+// box of its flags, accepted when flags >= eff * volume.  A box that is not
+// accepted is cut, and both parts are processed again, at
+//   1. a hole: an interior slab without flags (first axis that has one; the
+//      hole nearest the middle, the lower on a tie; the slab joins neither
+//      part), else
+//   2. the strongest inflection of the signature s (flags per slab): where
+//      the discrete Laplacian s(i-1) - 2 s(i) + s(i+1) changes sign strictly
+//      between slabs i and i+1, strength the jump of the Laplacian; strongest
+//      over all axes, the first met (axis order, ascending i) on a tie, else
+//   3. the middle of the longest axis (first longest; the lower part keeps
+//      the middle slab).
+// The blocks of the accepted boxes form the new flags.  Parts are processed
+// from an explicit stack; the union of the boxes does not depend on order.
+struct BrBox {
+  int lo[3], hi[3];
+};
+
+static void br_cluster(int dim, const int nb[3], const uint8_t *in, double eff, uint8_t *out) {
+  const int64_t nx = nb[0], nxy = (int64_t)nb[0] * nb[1];
+  auto at = [&](int x, int y, int z) { return x + nx * y + nxy * z; };
+  std::fill(out, out + nxy * nb[2], (uint8_t)0);
+  std::vector<BrBox> todo;
+  todo.push_back(BrBox{{0, 0, 0}, {nb[0] - 1, nb[1] - 1, nb[2] - 1}});
+  std::vector<int> sig[3];
+  while (!todo.empty()) {
+    BrBox B = todo.back();
+    todo.pop_back();
+    int lo[3] = {B.hi[0] + 1, B.hi[1] + 1, B.hi[2] + 1};
+    int hi[3] = {B.lo[0] - 1, B.lo[1] - 1, B.lo[2] - 1};
+    int64_t cnt = 0;
+    for (int z = B.lo[2]; z <= B.hi[2]; ++z)
+      for (int y = B.lo[1]; y <= B.hi[1]; ++y)
+        for (int x = B.lo[0]; x <= B.hi[0]; ++x)
+          if (in[at(x, y, z)]) {
+            ++cnt;
+            const int q[3] = {x, y, z};
+            for (int a = 0; a < 3; ++a) {
+              lo[a] = std::min(lo[a], q[a]);
+              hi[a] = std::max(hi[a], q[a]);
+            }
+          }
+    if (cnt == 0) continue;
+    double vol = 1.0;
+    for (int a = 0; a < 3; ++a) vol *= (double)(hi[a] - lo[a] + 1);
+    if ((double)cnt >= eff * vol) {
+      for (int z = lo[2]; z <= hi[2]; ++z)
+        for (int y = lo[1]; y <= hi[1]; ++y)
+          for (int x = lo[0]; x <= hi[0]; ++x) out[at(x, y, z)] = 1;
+      continue;
+    }
+    for (int a = 0; a < dim; ++a) sig[a].assign(hi[a] - lo[a] + 1, 0);
+    for (int z = lo[2]; z <= hi[2]; ++z)
+      for (int y = lo[1]; y <= hi[1]; ++y)
+        for (int x = lo[0]; x <= hi[0]; ++x)
+          if (in[at(x, y, z)]) {
+            const int q[3] = {x, y, z};
+            for (int a = 0; a < dim; ++a) ++sig[a][q[a] - lo[a]];
+          }
+    int axis = -1, end_lo = 0, start_hi = 0;
+    for (int a = 0; a < dim && axis < 0; ++a) {  // 1. holes
+      int best = -1, bestd = 0;
+      for (int i = lo[a] + 1; i < hi[a]; ++i) {
+        if (sig[a][i - lo[a]]) continue;
+        const int dd = std::abs(2 * i - lo[a] - hi[a]);
+        if (best < 0 || dd < bestd) {
+          best = i;
+          bestd = dd;
+        }
+      }
+      if (best >= 0) {
+        axis = a;
+        end_lo = best - 1;
+        start_hi = best + 1;
+      }
+    }
+    if (axis < 0) {  // 2. inflections
+      int64_t best = 0;
+      for (int a = 0; a < dim; ++a) {
+        const std::vector<int> &S = sig[a];
+        const int n = hi[a] - lo[a] + 1;
+        for (int i = 1; i + 2 < n; ++i) {  // slabs lo+i and lo+i+1, both interior
+          const int64_t l0 = (int64_t)S[i - 1] - 2 * S[i] + S[i + 1];
+          const int64_t l1 = (int64_t)S[i] - 2 * S[i + 1] + S[i + 2];
+          if (!((l0 < 0 && l1 > 0) || (l0 > 0 && l1 < 0))) continue;
+          const int64_t jump = l1 > l0 ? l1 - l0 : l0 - l1;
+          if (jump > best) {
+            best = jump;
+            axis = a;
+            end_lo = lo[a] + i;
+            start_hi = lo[a] + i + 1;
+          }
+        }
+      }
+    }
+    if (axis < 0) {  // 3. middle of the longest axis
+      int len = 0;
+      for (int a = 0; a < dim; ++a)
+        if (hi[a] - lo[a] + 1 > len) {
+          len = hi[a] - lo[a] + 1;
+          axis = a;
+        }
+      end_lo = (lo[axis] + hi[axis]) / 2;
+      start_hi = end_lo + 1;
+    }
+    BrBox P{{lo[0], lo[1], lo[2]}, {hi[0], hi[1], hi[2]}}, Q = P;
+    P.hi[axis] = end_lo;
+    Q.lo[axis] = start_hi;
+    todo.push_back(Q);
+    todo.push_back(P);
+  }
+}
 
 // Brackets the launches of its scope with an event pair when profiling is on
 // and the scope belongs to the finest level.
@@ -1050,6 +1165,43 @@ sbm_status sbm_amr_set_options(sbm_amr_ctx *c, const sbm_options *opts) {
   return SBM_OK;
 }
 
+// Replaces the block flags of level a by the blocks of their Berger-Rigoutsos
+// boxes (device flags, staged through the host; synchronises).
+static sbm_status amr_cluster_level(sbm_amr_ctx *c, int a) {
+  AmrLevel &l = c->lv[a];
+  const size_t n = l.nblocks();
+  std::vector<uint8_t> in(n), out(n);
+  AMR_HIP(hipMemcpyAsync(in.data(), l.blk, n, hipMemcpyDeviceToHost, c->st));
+  AMR_HIP(hipStreamSynchronize(c->st));
+  const int nb[3] = {l.nb[0], l.nb[1], l.nb[2]};
+  br_cluster(c->dim, nb, in.data(), c->cluster_eff, out.data());
+  AMR_HIP(hipMemcpyAsync(l.blk, out.data(), n, hipMemcpyHostToDevice, c->st));
+  AMR_HIP(hipStreamSynchronize(c->st));
+  return SBM_OK;
+}
+
+sbm_status sbm_amr_cluster(int dim, const int64_t *nblocks, const uint8_t *flags_host,
+                           double efficiency, uint8_t *out_host) {
+  if (!nblocks || !flags_host || !out_host) return amr_fail(SBM_E_ARG, "NULL argument");
+  if (dim != 2 && dim != 3) return amr_fail(SBM_E_SHAPE, "dim must be 2 or 3");
+  if (!(efficiency >= 0.0 && efficiency <= 1.0)) return amr_fail(SBM_E_ARG, "efficiency in [0, 1]");
+  int nb[3] = {1, 1, 1};
+  for (int a = 0; a < dim; ++a) {
+    if (nblocks[a] < 1 || nblocks[a] > (1 << 20)) return amr_fail(SBM_E_SHAPE, "block counts");
+    nb[a] = (int)nblocks[a];
+  }
+  if ((int64_t)nb[0] * nb[1] * nb[2] > ((int64_t)1 << 30)) return amr_fail(SBM_E_SHAPE, "too many blocks");
+  br_cluster(dim, nb, flags_host, efficiency, out_host);
+  return SBM_OK;
+}
+
+sbm_status sbm_amr_set_clustering(sbm_amr_ctx *c, double efficiency) {
+  if (!c) return amr_fail(SBM_E_ARG, "ctx is NULL");
+  if (!(efficiency >= 0.0 && efficiency <= 1.0)) return amr_fail(SBM_E_ARG, "efficiency in [0, 1]");
+  c->cluster_eff = efficiency;
+  return SBM_OK;
+}
+
 sbm_status sbm_amr_set_problem(sbm_amr_ctx *c, const double *const *psi_raw,
                                const sbm_material *mat, const sbm_bc *bc, double tag_threshold,
                                const uint8_t *const *blocks_host) {
@@ -1107,12 +1259,21 @@ sbm_status sbm_amr_set_problem(sbm_amr_ctx *c, const double *const *psi_raw,
                          l.blk);
       AMR_HIP(hipGetLastError());
     }
+    // finest first: cluster (when enabled), then nest into the next coarser level
     for (int a = A; a >= 2; --a) {
       AmrLevel &l = c->lv[a], &p = c->lv[a - 1];
+      if (c->cluster_eff > 0.0) {
+        const sbm_status s = amr_cluster_level(c, a);
+        if (s != SBM_OK) return s;
+      }
       (void)hipGetLastError();
       hipLaunchKernelGGL(k_amr_nest, dim3(num_blocks(l.nblocks())), dim3(kBlock), 0, c->st, d,
                          l.nb[0], l.nb[1], l.nb[2], l.blk, p.nb[0], p.nb[1], p.nb[2], p.blk);
       AMR_HIP(hipGetLastError());
+    }
+    if (c->cluster_eff > 0.0 && A >= 1) {
+      const sbm_status s = amr_cluster_level(c, 1);
+      if (s != SBM_OK) return s;
     }
   }
   // node classes
