@@ -491,7 +491,17 @@ __global__ __launch_bounds__(1024) void k_finalize_sum(const double *__restrict_
                                                        double *__restrict__ out) {
   __shared__ double lds[1024 / 64 + 1];
   double s = 0.0;
-  for (int q = threadIdx.x; q < n; q += 1024) s += partials[q];
+  int q = threadIdx.x;
+  // eight loads in flight per thread; the additions keep the order q, q +
+  // 1024, q + 2048, ... (the result does not depend on the unrolling)
+  for (; q + 7 * 1024 < n; q += 8 * 1024) {
+    double v[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) v[t] = partials[q + t * 1024];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) s += v[t];
+  }
+  for (; q < n; q += 1024) s += partials[q];
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
   if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = s;
