@@ -233,24 +233,38 @@ __device__ __forceinline__ void node_stencil(const Geom &g, const Coef<T> &C,
 #pragma unroll
       for (int c = 0; c < 3; ++c) ctr[c] = U(c, 0, 0, 0);
   } else {
-    T P[2][2];  // P[oy][ox]
+    // Gather as in 3D: the 4 cells and both components at the node and its 8
+    // neighbours (every one of them enters eq. K in 2D) before any arithmetic.
+    T pv[2][2];
+    bool pin[2][2];
 #pragma unroll
     for (int c1 = 0; c1 < 2; ++c1)
 #pragma unroll
       for (int c0 = 0; c0 < 2; ++c0) {
         const int xi = i - 1 + c0, yj = j - 1 + c1;
-        const bool in = xi >= 0 && xi < g.cx && yj >= 0 && yj < g.cy;
+        pin[c1][c0] = xi >= 0 && xi < g.cx && yj >= 0 && yj < g.cy;
         const int xc = min(max(xi, 0), g.cx - 1), yc = min(max(yj, 0), g.cy - 1);
-        const T v = psi[xc + g.cx * yc];
-        P[c1][c0] = in ? v : T(0);
+        pv[c1][c0] = psi[xc + g.cx * yc];
       }
+    T V[2][9];  // V[c][(dx+1) + 3 (dy+1)]
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx)
+          V[c][(dx + 1) + 3 * (dy + 1)] = u[c * nn + idx + ox[dx + 1] + oy[dy + 1]];
+    if constexpr (GATHER) __builtin_amdgcn_sched_barrier(0);
+    T P[2][2];  // P[oy][ox]
+#pragma unroll
+    for (int q = 0; q < 4; ++q) P[q >> 1][q & 1] = pin[q >> 1][q & 1] ? pv[q >> 1][q & 1] : T(0);
     T E[2][2];
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
       E[0][s] = P[0][s] + P[1][s];
       E[1][s] = P[s][0] + P[s][1];
     }
-    auto U = [&](int c, int dx, int dy) -> T { return u[c * nn + idx + ox[dx + 1] + oy[dy + 1]]; };
+    auto U = [&](int c, int dx, int dy) -> T { return V[c][(dx + 1) + 3 * (dy + 1)]; };
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       const T uc = U(c, 0, 0);
