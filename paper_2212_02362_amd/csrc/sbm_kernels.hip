@@ -543,9 +543,17 @@ __global__ __launch_bounds__(kBlock) void k_dot_free(Geom g, const double *__res
   if (id < g.nn) {
     int i, j, k;
     node_ijk(g, id, i, j, k);
+    // all loads first (one memory round trip), displacement DOF masked after
+    double av[3], bv[3];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+      av[c] = a[c * g.nn + id];
+      bv[c] = b[c * g.nn + id];
+    }
+    const uint32_t fb = face_bits(g, i, j, k);
 #pragma unroll
     for (int c = 0; c < DIM; ++c)
-      if (!is_dirichlet(g, i, j, k, c)) ss += a[c * g.nn + id] * b[c * g.nn + id];
+      if (!((g.dmask >> c) & fb)) ss += av[c] * bv[c];
   }
   const double s = block_sum(ss, lds);
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
@@ -602,15 +610,28 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(Geom g, double *__restrict
   if (id < g.nn) {
     int i, j, k;
     node_ijk(g, id, i, j, k);
+    // all loads first (one memory round trip); displacement DOF are neither
+    // updated nor summed
+    double xv[3], pv[3], rv[3], qv[3], zv[3];
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
-      if (is_dirichlet(g, i, j, k, c)) continue;
       const int64_t qi = c * g.nn + id;
-      x[qi] += alpha * p[qi];
-      const double rv = r[qi] - alpha * q[qi];
-      r[qi] = rv;
-      srr += rv * rv;
-      srz += rv * z[qi];
+      xv[c] = x[qi];
+      pv[c] = p[qi];
+      rv[c] = r[qi];
+      qv[c] = q[qi];
+      zv[c] = z[qi];
+    }
+    const uint32_t fb = face_bits(g, i, j, k);
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+      if ((g.dmask >> c) & fb) continue;
+      const int64_t qi = c * g.nn + id;
+      x[qi] = xv[c] + alpha * pv[c];
+      const double rn = rv[c] - alpha * qv[c];
+      r[qi] = rn;
+      srr += rn * rn;
+      srz += rn * zv[c];
     }
   }
   const double a = block_sum(srr, lds);
@@ -635,11 +656,16 @@ __global__ __launch_bounds__(kBlock) void k_xpby(Geom g, double *__restrict__ p,
   const double beta = rz ? (*rznew - *rzold) / *rz : 0.0;
   int i, j, k;
   node_ijk(g, id, i, j, k);
+  double zv[3], pv[3];
 #pragma unroll
   for (int c = 0; c < DIM; ++c) {
-    const int64_t qi = c * g.nn + id;
-    p[qi] = is_dirichlet(g, i, j, k, c) ? 0.0 : z[qi] + (rz ? beta * p[qi] : 0.0);
+    zv[c] = z[c * g.nn + id];
+    pv[c] = rz ? p[c * g.nn + id] : 0.0;
   }
+  const uint32_t fb = face_bits(g, i, j, k);
+#pragma unroll
+  for (int c = 0; c < DIM; ++c)
+    p[c * g.nn + id] = ((g.dmask >> c) & fb) ? 0.0 : zv[c] + (rz ? beta * pv[c] : 0.0);
 }
 
 // r32 = fp32(r / s) and z = s * e32 (s = sqrt(*ss)): the FP32 preconditioner
