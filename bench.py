@@ -623,9 +623,9 @@ def _free_dof(p):
     return free
 
 
-def _kernel_hash():
+def _kernel_hash(files=("sbm_device.h", "sbm_kernels.hip")):
     h = hashlib.sha256()
-    for fn in ("sbm_device.h", "sbm_kernels.hip"):
+    for fn in files:
         with open(os.path.join(ROOT, "paper_2212_02362_amd", "csrc", fn), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -640,31 +640,51 @@ def _traffic(kernel_key, nodes):
     with open(path) as fh:
         data = json.load(fh)
     ent = data.get(kernel_key)
-    if not ent or ent.get("kernel_hash") != _kernel_hash() or ent.get("nodes") != nodes:
+    files = next((v[2] for v in COUNTER_KERNELS.values() if v[0] == kernel_key), None)
+    if not ent or files is None or ent.get("kernel_hash") != _kernel_hash(files) or \
+            ent.get("nodes") != nodes:
         return None
     return ent.get("hbm_bytes_per_launch")
 
 
 TRAFFIC_KERNEL = "k_rb_half<double,3,false>"
+# counter runs per workload: (key in traffic_counters.json, kernel name in the
+# rocprofv3 trace, the sources whose hash keys the entry).  The 129^3 vectors
+# fit the 256 MB Infinity Cache; the 257^3 ones do not.
+COUNTER_KERNELS = {
+    "spherical_voids_129": (TRAFFIC_KERNEL, "k_rb_half<double, 3, false>",
+                            ("sbm_device.h", "sbm_kernels.hip")),
+    "diffuse_crack_257": ("k_rb_tile<double,false>", "k_rb_tile<double, false>",
+                          ("sbm_device.h", "sbm_tiled.hip")),
+}
 COPY_BYTES = 400_000_000  # calibration copy: this many bytes read and written
 
 
-def _counter_driver():
+def _counter_driver(workload="spherical_voids_129"):
     """Workload for the two rocprofv3 counter passes: the finest-level
-    half-sweep of the default workload, launched as inside its V-cycles
-    (same kernel, level and launch shape), then a plain device copy of known
-    size that calibrates FETCH_SIZE / WRITE_SIZE."""
+    half-sweep of the workload, launched as inside its V-cycles (same kernel,
+    level and launch shape), then a plain device copy of known size that
+    calibrates FETCH_SIZE / WRITE_SIZE."""
     import torch
 
     from paper_2212_02362_amd import Solver
 
-    p, _ = _workload("spherical_voids_129")
+    if workload not in COUNTER_KERNELS:
+        raise SystemExit(f"no counter run defined for {workload}")
+    p, _ = _workload(workload)
     S = Solver(p.ncell, p.h)
     S.set_problem(torch.tensor(p.psi_raw, device="cuda"), p.lam, p.mu, p.psi_floor, p.kind, p.val)
+    import ctypes
+
+    from paper_2212_02362_amd._lib import check, lib
     u = torch.randn((p.dim,) + p.node_shape, dtype=torch.float64, device="cuda")
     f = torch.randn_like(u)
+    v = torch.empty_like(u)
+    ptr = lambda t: ctypes.c_void_p(t.data_ptr())  # noqa: E731
+    # ping-pong between two resident buffers, as the V-cycle does
     for it in range(10):
-        u = S.level_smooth(0, it % 2, 1.0, u, f)
+        check(lib().sbm_level_smooth(S._ctx, 0, it % 2, 1.0, ptr(u), ptr(f), ptr(v)))
+        u, v = v, u
     x = torch.randn(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
     y = torch.empty_like(x)
     for _ in range(3):
@@ -673,12 +693,16 @@ def _counter_driver():
     print("[counters] driver done", flush=True)
 
 
-def _counter_summary(fetch_dir, write_dir):
+def _counter_summary(fetch_dir, write_dir, workload="spherical_voids_129"):
     """HBM bytes per launch of the dominant kernel from the two counter runs,
     each counter scaled by its reading for the calibration copy; writes
     profiles/traffic_counters.json (keyed by the kernel-source hash, so a
     changed kernel reports no traffic) and a text summary."""
     import csv
+
+    if workload not in COUNTER_KERNELS:
+        raise SystemExit(f"no counter run defined for {workload}")
+    key, trace_name, files = COUNTER_KERNELS[workload]
 
     def read(d, counter):
         path = None
@@ -695,7 +719,7 @@ def _counter_summary(fetch_dir, write_dir):
                     continue
                 v = float(r["Counter_Value"]) * 1024.0  # KiB -> bytes
                 name = r["Kernel_Name"]
-                if "k_rb_half<double, 3, false>" in name:
+                if trace_name in name:
                     kern.append(v)
                 elif "copyBuffer" in name and v > 0.25 * COPY_BYTES:
                     copy.append(v)
@@ -706,10 +730,11 @@ def _counter_summary(fetch_dir, write_dir):
     fk, fc, nf = read(fetch_dir, "FETCH_SIZE")
     wk, wc, nw = read(write_dir, "WRITE_SIZE")
     ff, fw = COPY_BYTES / fc, COPY_BYTES / wc
-    p, _ = _workload("spherical_voids_129")
+    p, _ = _workload(workload)
     nodes = p.n_nodes
     fetch, write = fk * ff, wk * fw
-    ent = {"kernel_hash": _kernel_hash(), "nodes": nodes, "hbm_bytes_per_launch": fetch + write,
+    ent = {"kernel_hash": _kernel_hash(files), "nodes": nodes, "workload": workload,
+           "hbm_bytes_per_launch": fetch + write,
            "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
            "fetch_factor": ff, "write_factor": fw, "launches": [nf, nw],
            "algo_bytes_per_launch": ALGO_BYTES["smooth"][0] * nodes}
@@ -718,7 +743,7 @@ def _counter_summary(fetch_dir, write_dir):
     if os.path.exists(path):
         with open(path) as fh:
             data = json.load(fh)
-    data[TRAFFIC_KERNEL] = ent
+    data[key] = ent
     with open(path, "w") as fh:
         json.dump(data, fh, indent=1)
         fh.write("\n")
@@ -800,9 +825,9 @@ def main():
                     help="turn two rocprofv3 counter runs into profiles/traffic_counters.json")
     args = ap.parse_args()
     if args.counter_driver:
-        return _counter_driver()
+        return _counter_driver(args.workload)
     if args.counter_summary:
-        return _counter_summary(*args.counter_summary)
+        return _counter_summary(*args.counter_summary, workload=args.workload)
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for "
               f"--gpus {args.gpus}).  Run with --gpus 1.", file=sys.stderr)
@@ -868,7 +893,8 @@ def main():
     avg_ms = ms_s / max(n_s, 1)
     by = ALGO_BYTES["smooth"][0] * nodes
     achieved = by / (avg_ms * 1e-3) / 1e9
-    traffic = _traffic(TRAFFIC_KERNEL, nodes)
+    tiled = p.ncell[0] + 1 > 192 and p.dim == 3
+    traffic = _traffic("k_rb_tile<double,false>" if tiled else TRAFFIC_KERNEL, nodes)
     line = {
         "metric": METRIC,
         "value": free / t64,
@@ -889,7 +915,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": ("k_rb_tile<double> (LDS-tiled finest-level Gauss-Seidel half-sweep)"
-                                if p.ncell[0] + 1 > 192 and p.dim == 3 else
+                                if tiled else
                                 "k_rb_half<double,3,false> (finest-level Gauss-Seidel half-sweep)"),
                      "algo_bytes_per_launch": by, "avg_launch_us": avg_ms * 1e3,
                      "timing": "HIP events around each finest-level launch, over the profiled "
