@@ -250,6 +250,7 @@ sbm_status sbm_return_map(sbm_ctx *ctx, const double *u, const sbm_j2 *mat, doub
  * the 2^(d-1) cell pairs facing each other across the node; cells outside the
  * box take the value of the nearest cell inside (the box faces carry their
  * own tractions).  Pass f as (part of) the body force b of sbm_set_problem.
+ * f may be t_hat (each node reads its own t_hat before writing), not psi_raw.
  * Needs only the grid of ctx.  Async. */
 sbm_status sbm_diffuse_traction(sbm_ctx *ctx, const double *psi_raw, double psi_floor,
                                 const double *t_hat, double pressure, double *f);
@@ -280,7 +281,8 @@ sbm_status sbm_crack_drive(sbm_ctx *ctx, const double *u, double *H, uint8_t *in
  * a NaN stays NaN), c_out = 1 where intact; lap is the cell Laplacian
  * (2d+1 points) with zero flux across the box faces.  Also writes psi_out =
  * g(c_out) + eta, the indicator of the next sbm_set_problem (pass floor
- * <= eta).  crack_out must not alias crack.  Needs only the grid of ctx.
+ * <= eta).  crack_out and psi_out must not alias each other or the inputs
+ * (SBM_E_ARG).  Needs only the grid of ctx.
  * Async. */
 sbm_status sbm_phase_step(sbm_ctx *ctx, const double *crack, const double *H,
                           const uint8_t *intact, const sbm_pf *p, double *crack_out,

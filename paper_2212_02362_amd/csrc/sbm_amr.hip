@@ -1183,6 +1183,7 @@ static sbm_status amr_cluster_level(sbm_amr_ctx *c, int a) {
 sbm_status sbm_amr_cluster(int dim, const int64_t *nblocks, const uint8_t *flags_host,
                            double efficiency, uint8_t *out_host) {
   if (!nblocks || !flags_host || !out_host) return amr_fail(SBM_E_ARG, "NULL argument");
+  if (flags_host == out_host) return amr_fail(SBM_E_ARG, "out_host must not alias flags_host");
   if (dim != 2 && dim != 3) return amr_fail(SBM_E_SHAPE, "dim must be 2 or 3");
   if (!(efficiency >= 0.0 && efficiency <= 1.0)) return amr_fail(SBM_E_ARG, "efficiency in [0, 1]");
   int nb[3] = {1, 1, 1};

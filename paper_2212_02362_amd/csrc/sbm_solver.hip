@@ -1039,6 +1039,7 @@ sbm_status sbm_diffuse_traction(sbm_ctx *c, const double *psi_raw, double psi_fl
                                 const double *t_hat, double pressure, double *f) {
   if (!c) return fail(SBM_E_ARG, "ctx is NULL");
   if (!psi_raw || !f) return fail(SBM_E_ARG, "NULL argument");
+  if (f == psi_raw) return fail(SBM_E_ARG, "f must not alias psi_raw");
   if (!(psi_floor >= 0.0) || !isfinite(psi_floor) || !isfinite(pressure))
     return fail(SBM_E_ARG, "psi_floor >= 0 and pressure must be finite");
   HIP_TRY(launch_diffuse_traction(c->L[0], psi_raw, psi_floor, t_hat, pressure, f, c->st));
@@ -1058,7 +1059,10 @@ sbm_status sbm_phase_step(sbm_ctx *c, const double *crack, const double *H, cons
   if (!c) return fail(SBM_E_ARG, "ctx is NULL");
   if (!crack || !H || !intact || !p || !crack_out || !psi_out)
     return fail(SBM_E_ARG, "NULL argument");
-  if (crack == crack_out) return fail(SBM_E_ARG, "crack_out must not alias crack");
+  if (crack_out == crack || crack_out == H || psi_out == crack || psi_out == H ||
+      psi_out == crack_out || (const void *)crack_out == (const void *)intact ||
+      (const void *)psi_out == (const void *)intact)
+    return fail(SBM_E_ARG, "crack_out and psi_out must not alias each other or the inputs");
   if (!(p->Gc >= 0.0) || !(p->xi > 0.0) || !(p->M >= 0.0) || !(p->dt >= 0.0) || !(p->eta >= 0.0) ||
       !isfinite(p->Gc) || !isfinite(p->xi) || !isfinite(p->M) || !isfinite(p->dt) ||
       !isfinite(p->eta))

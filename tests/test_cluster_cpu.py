@@ -46,3 +46,13 @@ def test_cluster_argument_checks():
         cluster_blocks(np.ones((3, 3), np.uint8), 1.5)
     with pytest.raises(ValueError):
         cluster_blocks(np.ones(4, np.uint8), 0.5)
+
+
+def test_cluster_rejects_aliased_output():
+    import ctypes
+    from paper_2212_02362_amd._lib import lib
+    f = np.ones((3, 4), np.uint8)
+    nb = (ctypes.c_int64 * 3)(4, 3, 1)
+    st = lib().sbm_amr_cluster(2, ctypes.cast(nb, ctypes.c_void_p), f.ctypes.data_as(ctypes.c_void_p),
+                               0.5, f.ctypes.data_as(ctypes.c_void_p))
+    assert st == -1

@@ -150,3 +150,21 @@ def test_phase_step_projection():
     assert c1 is out[0] and psi is out[1]
     assert rel_max(to_np(c1), cref) < 1e-12 and rel_max(to_np(psi), psiref) < 1e-12
     assert np.array_equal(to_np(c1) == 0.0, cref == 0.0)
+
+
+def test_phase_step_rejects_aliased_outputs():
+    import ctypes
+
+    from paper_2212_02362_amd._lib import SbmPf, lib
+    p = random_problem((6, 5), seed=2, body=False)
+    S = solver_for(p)
+    c = torch.full((5, 6), 0.5, dtype=torch.float64, device="cuda")
+    H = torch.zeros_like(c)
+    i8 = torch.zeros((5, 6), dtype=torch.uint8, device="cuda")
+    out = torch.empty_like(c)
+    pf = SbmPf(1.0, 0.1, 1.0, 1e-3, 1e-4)
+    P = lambda t: ctypes.c_void_p(t.data_ptr())
+    say("phase step aliasing")
+    for co, po in ((c, out), (out, c), (out, out), (H, out), (out, H)):
+        st = lib().sbm_phase_step(S._ctx, P(c), P(H), P(i8), ctypes.byref(pf), P(co), P(po))
+        assert st == -1
