@@ -157,7 +157,7 @@ hipError_t launch_bottom_f32io(const Level &L, const float *f32, float *x32, dou
 // kTailWaveBottom nodes, solved by the whole workgroup).
 constexpr int kTailMaxLevels = 6;
 constexpr size_t kTailArgBytes = 4096;
-constexpr size_t kTailDenseBytes = 32 * 32 * sizeof(double);
+constexpr size_t kTailDenseBytes = 64 * 64 * sizeof(double);
 constexpr int kTailWaveBottom = 64;  // bottoms up to this many nodes are solved in one wave
 struct TailOpts {
   int nu_pre, nu_post, jacobi, reverse;
@@ -166,7 +166,7 @@ struct TailOpts {
 };
 int tail_level(const std::vector<Level> &L, int precision, size_t lds_max);
 hipError_t tail_upload(const std::vector<Level> &L, int precision, int l0, void *dev,
-                       double *dense_A, size_t *lds_bytes, hipStream_t st);
+                       double *dense_A, size_t lds_max, size_t *lds_bytes, hipStream_t st);
 template <typename T>
 hipError_t launch_tail(int dim, bool wide_bottom, const void *dev, size_t lds_bytes,
                        T *x, const T *f, const TailOpts &o, int *iters, hipStream_t st);

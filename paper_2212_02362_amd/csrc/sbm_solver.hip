@@ -93,6 +93,7 @@ struct sbm_ctx {
   char *tail_args = nullptr;
   double *tail_A = nullptr;  // dense bottom matrix of the tails
   size_t tail_lds64 = 0, tail_lds32 = 0;
+  size_t tail_lds_max = 64 * 1024;  // LDS bytes a workgroup may hold on this device
 };
 
 // Brackets one launch sequence with an event pair when profiling is on.
@@ -766,6 +767,7 @@ sbm_status sbm_create(const sbm_grid *grid, const sbm_options *opts, void *works
         lds <= 0)
       lds = 64 * 1024;
     (void)hipGetLastError();
+    c->tail_lds_max = (size_t)lds;
     c->tail64 = tail_level(c->L, 0, (size_t)lds);
     c->tail32 = tail_level(c->L, 1, (size_t)lds);
   }
@@ -884,10 +886,11 @@ static sbm_status set_problem_impl(sbm_ctx *c, const double *psi_raw, int cube,
   for (int l = 1; l < c->nlev; ++l) HIP_TRY(launch_coarsen_psi(c->L[l - 1], c->L[l], c->st));
   // tail level tables and the dense bottom matrix (needs the bottom psi)
   if (c->tail64 >= 0)
-    HIP_TRY(tail_upload(c->L, 0, c->tail64, c->tail_args, c->tail_A, &c->tail_lds64, c->st));
+    HIP_TRY(tail_upload(c->L, 0, c->tail64, c->tail_args, c->tail_A, c->tail_lds_max,
+                        &c->tail_lds64, c->st));
   if (c->tail32 >= 0)
     HIP_TRY(tail_upload(c->L, 1, c->tail32, c->tail_args + kTailArgBytes, c->tail_A,
-                        &c->tail_lds32, c->st));
+                        c->tail_lds_max, &c->tail_lds32, c->st));
   HIP_TRY(launch_rhs(L0, c->tr, b, L0.f, c->iflag, c->st));
   HIP_TRY(launch_check_diag(L0, c->iflag, c->st));
   int flags = 0;

@@ -22,7 +22,8 @@ namespace {
 
 constexpr int kTailThreads = 512;  // threads of the tail workgroup
 constexpr int kTailQ = 2;          // nodes per thread on a tail level (at most)
-constexpr int kTailDenseMax = 32;  // free bottom DOF up to which the bottom matrix is assembled
+constexpr int kTailDenseMax = 32;  // free bottom DOF up to which the matrix rows sit in registers
+constexpr int kTailDenseLds = 64;  // ... and up to which the matrix is assembled (LDS beyond 32)
 
 // Level table of a tail, written to device memory once per problem (the
 // kernel indexes it by a runtime level; as a kernel argument that would be
@@ -41,11 +42,13 @@ struct TailArgs {
   int ored;           // reduction buffer of the workgroup-wide bottom CG
   int oxb, ofb;       // bottom x and f (copies of ox[nl-1], of[nl-1])
   // Dense bottom (nf > 0): the bottom operator on its nf free DOF, assembled
-  // once per problem (A[i nf + j] = (K e_j)_i); fidx[i] = c nn + node of the
-  // i-th free DOF.
+  // once per problem; fidx[i] = c nn + node of the i-th free DOF.  nf <=
+  // kTailDenseMax: rows in registers, A[i nf + j] = (K e_j)_i; otherwise the
+  // matrix is copied into LDS at byte offset oA, A[j nf + i] = (K e_j)_i.
   int nf;
+  int oA;
   const double *A;
-  int fidx[kTailDenseMax];
+  int fidx[kTailDenseLds];
 };
 static_assert(sizeof(TailArgs<double>) <= kTailArgBytes, "tail table too large");
 
@@ -313,11 +316,78 @@ struct Tail {
     __syncthreads();
   }
 
+  // The dense CG for kTailDenseMax < nf <= kTailDenseLds: the matrix is
+  // copied into LDS (column j at stride kTailDenseLds, rows past nf zero) and
+  // lane i reads row i one column at a time; the search direction stays in
+  // the lanes' registers and entry j is broadcast from lane j (readlane), so
+  // A p is the same zero-padded sum of 64 products as in the register version.
+  __device__ __forceinline__ void bottom_dense_lds(int *iters) const {
+    T *xb = (T *)(sm + a.oxb);
+    const T *fb_ = (const T *)(sm + a.ofb);
+    double *As = (double *)(sm + a.oA);
+    const int nf = a.nf;
+    for (int q = threadIdx.x; q < kTailDenseLds * kTailDenseLds; q += kTailThreads) {
+      const int j = q / kTailDenseLds, i = q - j * kTailDenseLds;
+      As[q] = (i < nf && j < nf) ? a.A[j * nf + i] : 0.0;
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      const int lane = threadIdx.x;
+      const double rtol = o.rtol;
+      const int maxit = o.maxit;
+      const bool on = lane < nf;
+      const int fi = on ? a.fidx[lane] : 0;
+      const double r0v = on ? (double)fb_[fi] : 0.0;
+      const double dinv = on ? 1.0 / As[lane * kTailDenseLds + lane] : 0.0;
+      double r = r0v, d = 0.0;
+      double z = r * dinv;
+      double pl = on ? z : 0.0;  // this lane's entry of the search direction
+      double rr = wave_sum(r * r), rz = wave_sum(r * z);
+      const double r0 = sqrt(rr);
+      int it = 0;
+      auto bcast = [&](int j) {
+        const int lo = __builtin_amdgcn_readlane(__double2loint(pl), j);
+        const int hi = __builtin_amdgcn_readlane(__double2hiint(pl), j);
+        return __hiloint2double(hi, lo);
+      };
+      while (r0 > 0.0 && sqrt(rr) > rtol * r0 && it < maxit) {
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+        for (int j = 0; j < kTailDenseLds; j += 4) {
+          s0 += As[j * kTailDenseLds + lane] * bcast(j);
+          s1 += As[(j + 1) * kTailDenseLds + lane] * bcast(j + 1);
+          s2 += As[(j + 2) * kTailDenseLds + lane] * bcast(j + 2);
+          s3 += As[(j + 3) * kTailDenseLds + lane] * bcast(j + 3);
+        }
+        const double ap = (s0 + s1) + (s2 + s3);
+        const double pap = wave_sum(pl * ap);
+        if (!(pap > 0.0)) break;
+        const double alpha = rz / pap;
+        d += alpha * pl;
+        r -= alpha * ap;
+        z = r * dinv;
+        const double nrr = wave_sum(r * r), nrz = wave_sum(r * z);
+        const double beta = nrz / rz;
+        rr = nrr;
+        rz = nrz;
+        pl = on ? z + beta * pl : 0.0;
+        ++it;
+      }
+      if (on) xb[fi] = (T)d;  // displacement DOF stay 0 (zeroed by the restriction)
+      if (lane == 0 && iters) *iters = it;
+    }
+    __syncthreads();
+  }
+
   // X(B) = CG(K_B, F(B)) from zero, in FP64 in the first wave: Jacobi
   // preconditioning, stop at ||r|| <= rtol ||r0|| or maxit iterations.
   __device__ __forceinline__ void bottom(int *iters) const {
     if constexpr (WIDE) {
       bottom_wide(iters);
+      return;
+    }
+    if (a.nf > kTailDenseMax) {
+      bottom_dense_lds(iters);
       return;
     }
     if (a.nf > 0) {
@@ -489,7 +559,8 @@ __global__ __launch_bounds__(64) void k_tail_assemble(const TailArgs<T> *__restr
     if (lane < nf) {
       double out[3], dg[3];
       node_stencil<double, DIM, false>(g, Cb, psib, p, i, j, k, out, dg);
-      A[lane * nf + col] = out[c];
+      if (nf > kTailDenseMax) A[col * nf + lane] = out[c];  // column-major (LDS copy)
+      else A[lane * nf + col] = out[c];
     }
     wave_sync();
     if (lane == 0) p[a.fidx[col]] = 0.0;
@@ -514,7 +585,7 @@ const Coef<float> &tail_coef<float>(const Level &L) { return L.c32; }
 // more nodes than threads, fewer than two levels, too many levels).
 template <typename T>
 size_t tail_layout(const std::vector<Level> &L, int l0, TailArgs<T> *a,
-                   const double *dense_A = nullptr) {
+                   const double *dense_A = nullptr, size_t lds_max = 0) {
   const int nlev = (int)L.size();
   const int nl = nlev - l0;
   if (nl < 2 || nl > kTailMaxLevels) return 0;
@@ -543,7 +614,7 @@ size_t tail_layout(const std::vector<Level> &L, int l0, TailArgs<T> *a,
   }
   t.orr = take(sizeof(T) * d * L[l0].g.nn);
   t.opb = take(sizeof(double) * L[B].g.nc);
-  t.opp = take(sizeof(double) * std::max<int64_t>(d * L[B].g.nn, kTailDenseMax));
+  t.opp = take(sizeof(double) * std::max<int64_t>(d * L[B].g.nn, kTailDenseLds));
   t.ored = take(sizeof(double) * 64);
   t.gb = L[B].g;
   t.oxb = t.ox[nl - 1];
@@ -560,10 +631,17 @@ size_t tail_layout(const std::vector<Level> &L, int l0, TailArgs<T> *a,
                     (j == gb.ny - 1 ? 512u : 0u);
       if (d == 3) fb |= (k == 0 ? 4096u : 0u) | (k == gb.nz - 1 ? 32768u : 0u);
       if ((gb.dmask >> c) & fb) continue;
-      if (nf < kTailDenseMax) t.fidx[nf] = c * (int)gb.nn + n;
+      if (nf < kTailDenseLds) t.fidx[nf] = c * (int)gb.nn + n;
       ++nf;
     }
-  t.nf = (dense_A && nf <= kTailDenseMax && gb.nn <= kTailWaveBottom) ? nf : 0;
+  t.nf = (dense_A && nf <= kTailDenseLds && gb.nn <= kTailWaveBottom) ? nf : 0;
+  t.oA = -1;
+  if (t.nf > kTailDenseMax) {
+    if (off + sizeof(double) * kTailDenseLds * kTailDenseLds <= lds_max)
+      t.oA = take(sizeof(double) * kTailDenseLds * kTailDenseLds);
+    else
+      t.nf = 0;  // no room in LDS: the stencil CG
+  }
   t.A = dense_A;
   if (a) *a = t;
   return off;
@@ -582,13 +660,13 @@ int tail_level(const std::vector<Level> &L, int precision, size_t lds_max) {
 }
 
 hipError_t tail_upload(const std::vector<Level> &L, int precision, int l0, void *dev,
-                       double *dense_A, size_t *lds_bytes, hipStream_t st) {
+                       double *dense_A, size_t lds_max, size_t *lds_bytes, hipStream_t st) {
   hipError_t e;
   const int dim = L[0].g.dim;
   (void)hipGetLastError();
   if (precision == 1) {
     TailArgs<float> a{};
-    *lds_bytes = tail_layout<float>(L, l0, &a, dense_A);
+    *lds_bytes = tail_layout<float>(L, l0, &a, dense_A, lds_max);
     if (*lds_bytes == 0) return hipErrorInvalidValue;
     if ((e = hipMemcpyAsync(dev, &a, sizeof(a), hipMemcpyHostToDevice, st)) != hipSuccess) return e;
     if (a.nf > 0) {
@@ -598,7 +676,7 @@ hipError_t tail_upload(const std::vector<Level> &L, int precision, int l0, void 
     }
   } else {
     TailArgs<double> a{};
-    *lds_bytes = tail_layout<double>(L, l0, &a, dense_A);
+    *lds_bytes = tail_layout<double>(L, l0, &a, dense_A, lds_max);
     if (*lds_bytes == 0) return hipErrorInvalidValue;
     if ((e = hipMemcpyAsync(dev, &a, sizeof(a), hipMemcpyHostToDevice, st)) != hipSuccess) return e;
     if (a.nf > 0) {
