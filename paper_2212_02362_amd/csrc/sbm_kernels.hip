@@ -20,6 +20,19 @@ int grid_blocks(int64_t n) {
   return nb >= 64 ? (nb + 7) / 8 * 8 : nb;
 }
 
+// Threads per block of the V-cycle stencil and transfer kernels on a level
+// of n work items: small levels take blocks of 128 (twice as many blocks,
+// spread over more CUs; their launches are bound by latency, not bytes).
+#ifndef SBM_SMALL_LEVEL
+#define SBM_SMALL_LEVEL 300000
+#endif
+static int level_block(int64_t n) { return n < SBM_SMALL_LEVEL ? 128 : kBlock; }
+static int level_grid(int64_t n) {
+  const int bs = level_block(n);
+  const int nb = (int)((n + bs - 1) / bs);
+  return nb >= 64 ? (nb + 7) / 8 * 8 : nb;
+}
+
 
 // ------------------------------------------------------------------ apply --
 
@@ -47,7 +60,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(Geom g, Coef<T> C, const T 
                                                      double *__restrict__ partials,
                                                      const uint8_t *__restrict__ cls) {
   __shared__ double lds[kBlock / 64 + 1];
-  const int64_t id = (int64_t)xcd_block() * kBlock + threadIdx.x;
+  const int64_t id = (int64_t)xcd_block() * (int)blockDim.x + threadIdx.x;
   double ss = 0.0;
   if (id < g.nn && MASK && (cls[id] == 0 || cls[id] > 3)) {
     for (int c = 0; c < DIM; ++c) r[c * g.nn + id] = T(0);
@@ -113,7 +126,7 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(Geom g, Coef<T> C, const T *_
                                                    const T *__restrict__ f,
                                                    T *__restrict__ u_out, T omega,
                                                    const uint8_t *__restrict__ cls) {
-  const int64_t id = (int64_t)xcd_block() * kBlock + threadIdx.x;
+  const int64_t id = (int64_t)xcd_block() * (int)blockDim.x + threadIdx.x;
   if (id >= g.nn) return;
   if (MASK && cls[id] != 1) {
     for (int c = 0; c < DIM; ++c) u_out[c * g.nn + id] = u[c * g.nn + id];
@@ -146,7 +159,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_half(Geom g, Coef<T> C, const T *
                                                     T *__restrict__ u_out, T omega, int colour,
                                                     const uint8_t *__restrict__ cls) {
   const int npx = (g.nx + 1) >> 1;
-  const int64_t tid = (int64_t)xcd_block() * kBlock + threadIdx.x;
+  const int64_t tid = (int64_t)xcd_block() * (int)blockDim.x + threadIdx.x;
   const int64_t total = (int64_t)npx * g.ny * g.nz;
   if (tid >= total) return;
   const uint32_t rest = g.fpx.div((uint32_t)tid);
@@ -202,7 +215,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_half(Geom g, Coef<T> C, const T *
 template <typename T, int DIM>
 __global__ __launch_bounds__(kBlock) void k_restrict(Geom gf, Geom gc, const T *__restrict__ r,
                                                      T *__restrict__ fc, T *__restrict__ ec) {
-  const int64_t id = (int64_t)xcd_block() * kBlock + threadIdx.x;
+  const int64_t id = (int64_t)xcd_block() * (int)blockDim.x + threadIdx.x;
   if (id >= gc.nn) return;
   int I, J, K;
   node_ijk(gc, id, I, J, K);
@@ -253,7 +266,7 @@ template <typename T, int DIM>
 __global__ __launch_bounds__(kBlock) void k_prolong_add(Geom gf, Geom gc, const T *__restrict__ e,
                                                         T *__restrict__ u) {
   constexpr int NZ = (DIM == 3) ? 2 : 1;
-  const int64_t id = (int64_t)xcd_block() * kBlock + threadIdx.x;
+  const int64_t id = (int64_t)xcd_block() * (int)blockDim.x + threadIdx.x;
   if (id >= gc.nn) return;
   int I, J, K;
   node_ijk(gc, id, I, J, K);
@@ -1017,13 +1030,15 @@ hipError_t launch_residual(const Level &L, const T *psi, const Coef<T> &C, const
                            const T *f, T *r, double *partials, hipStream_t st,
                            const uint8_t *cls, const TileList *tl) {
   if (use_tiled(L)) return launch_residual_tiled<T>(L, psi, C, u, f, r, partials, st, cls, tl);
-  const int nb = grid_blocks(L.g.nn);
+  // partial sums are counted per block of kBlock threads
+  const int bs = partials ? kBlock : level_block(L.g.nn);
+  const int nb = partials ? grid_blocks(L.g.nn) : level_grid(L.g.nn);
   if (L.g.dim == 3) {
-    if (cls) SBM_LAUNCH((k_residual<T, 3, true>), nb, kBlock, st, L.g, C, psi, u, f, r, partials, cls);
-    SBM_LAUNCH((k_residual<T, 3, false>), nb, kBlock, st, L.g, C, psi, u, f, r, partials, cls);
+    if (cls) SBM_LAUNCH((k_residual<T, 3, true>), nb, bs, st, L.g, C, psi, u, f, r, partials, cls);
+    SBM_LAUNCH((k_residual<T, 3, false>), nb, bs, st, L.g, C, psi, u, f, r, partials, cls);
   }
-  if (cls) SBM_LAUNCH((k_residual<T, 2, true>), nb, kBlock, st, L.g, C, psi, u, f, r, partials, cls);
-  SBM_LAUNCH((k_residual<T, 2, false>), nb, kBlock, st, L.g, C, psi, u, f, r, partials, cls);
+  if (cls) SBM_LAUNCH((k_residual<T, 2, true>), nb, bs, st, L.g, C, psi, u, f, r, partials, cls);
+  SBM_LAUNCH((k_residual<T, 2, false>), nb, bs, st, L.g, C, psi, u, f, r, partials, cls);
 }
 
 hipError_t launch_residual_cast(const Level &L, const double *u, const double *f, float *r32,
@@ -1038,13 +1053,13 @@ hipError_t launch_residual_cast(const Level &L, const double *u, const double *f
 template <typename T>
 hipError_t launch_jacobi(const Level &L, const T *psi, const Coef<T> &C, const T *u, const T *f,
                          T *u_out, double omega, hipStream_t st, const uint8_t *cls) {
-  const int nb = grid_blocks(L.g.nn);
+  const int nb = level_grid(L.g.nn), bs = level_block(L.g.nn);
   if (L.g.dim == 3) {
-    if (cls) SBM_LAUNCH((k_jacobi<T, 3, true>), nb, kBlock, st, L.g, C, psi, u, f, u_out, (T)omega, cls);
-    SBM_LAUNCH((k_jacobi<T, 3, false>), nb, kBlock, st, L.g, C, psi, u, f, u_out, (T)omega, cls);
+    if (cls) SBM_LAUNCH((k_jacobi<T, 3, true>), nb, bs, st, L.g, C, psi, u, f, u_out, (T)omega, cls);
+    SBM_LAUNCH((k_jacobi<T, 3, false>), nb, bs, st, L.g, C, psi, u, f, u_out, (T)omega, cls);
   }
-  if (cls) SBM_LAUNCH((k_jacobi<T, 2, true>), nb, kBlock, st, L.g, C, psi, u, f, u_out, (T)omega, cls);
-  SBM_LAUNCH((k_jacobi<T, 2, false>), nb, kBlock, st, L.g, C, psi, u, f, u_out, (T)omega, cls);
+  if (cls) SBM_LAUNCH((k_jacobi<T, 2, true>), nb, bs, st, L.g, C, psi, u, f, u_out, (T)omega, cls);
+  SBM_LAUNCH((k_jacobi<T, 2, false>), nb, bs, st, L.g, C, psi, u, f, u_out, (T)omega, cls);
 }
 
 template <typename T>
@@ -1052,34 +1067,34 @@ hipError_t launch_rb_half(const Level &L, const T *psi, const Coef<T> &C, const 
                           const T *f, T *u_out, double omega, int colour, hipStream_t st,
                           const uint8_t *cls) {
   const int64_t pairs = (int64_t)((L.g.nx + 1) / 2) * L.g.ny * L.g.nz;
-  const int nb = grid_blocks(pairs);
+  const int nb = level_grid(pairs), bs = level_block(pairs);
   if (L.g.dim == 3) {
     if (cls)
-      SBM_LAUNCH((k_rb_half<T, 3, true>), nb, kBlock, st, L.g, C, psi, u, f, u_out, (T)omega,
+      SBM_LAUNCH((k_rb_half<T, 3, true>), nb, bs, st, L.g, C, psi, u, f, u_out, (T)omega,
                  colour, cls);
-    SBM_LAUNCH((k_rb_half<T, 3, false>), nb, kBlock, st, L.g, C, psi, u, f, u_out, (T)omega,
+    SBM_LAUNCH((k_rb_half<T, 3, false>), nb, bs, st, L.g, C, psi, u, f, u_out, (T)omega,
                colour, cls);
   }
   if (cls)
-    SBM_LAUNCH((k_rb_half<T, 2, true>), nb, kBlock, st, L.g, C, psi, u, f, u_out, (T)omega,
+    SBM_LAUNCH((k_rb_half<T, 2, true>), nb, bs, st, L.g, C, psi, u, f, u_out, (T)omega,
                colour, cls);
-  SBM_LAUNCH((k_rb_half<T, 2, false>), nb, kBlock, st, L.g, C, psi, u, f, u_out, (T)omega, colour,
+  SBM_LAUNCH((k_rb_half<T, 2, false>), nb, bs, st, L.g, C, psi, u, f, u_out, (T)omega, colour,
              cls);
 }
 
 template <typename T>
 hipError_t launch_restrict(const Level &F, const Level &Cl, const T *r, T *fc, hipStream_t st,
                            T *ec) {
-  if (F.g.dim == 3)
-    SBM_LAUNCH((k_restrict<T, 3>), grid_blocks(Cl.g.nn), kBlock, st, F.g, Cl.g, r, fc, ec);
-  SBM_LAUNCH((k_restrict<T, 2>), grid_blocks(Cl.g.nn), kBlock, st, F.g, Cl.g, r, fc, ec);
+  const int nb = level_grid(Cl.g.nn), bs = level_block(Cl.g.nn);
+  if (F.g.dim == 3) SBM_LAUNCH((k_restrict<T, 3>), nb, bs, st, F.g, Cl.g, r, fc, ec);
+  SBM_LAUNCH((k_restrict<T, 2>), nb, bs, st, F.g, Cl.g, r, fc, ec);
 }
 
 template <typename T>
 hipError_t launch_prolong_add(const Level &F, const Level &Cl, const T *e, T *u, hipStream_t st) {
-  if (F.g.dim == 3)
-    SBM_LAUNCH((k_prolong_add<T, 3>), grid_blocks(Cl.g.nn), kBlock, st, F.g, Cl.g, e, u);
-  SBM_LAUNCH((k_prolong_add<T, 2>), grid_blocks(Cl.g.nn), kBlock, st, F.g, Cl.g, e, u);
+  const int nb = level_grid(Cl.g.nn), bs = level_block(Cl.g.nn);
+  if (F.g.dim == 3) SBM_LAUNCH((k_prolong_add<T, 3>), nb, bs, st, F.g, Cl.g, e, u);
+  SBM_LAUNCH((k_prolong_add<T, 2>), nb, bs, st, F.g, Cl.g, e, u);
 }
 
 template <typename T>
