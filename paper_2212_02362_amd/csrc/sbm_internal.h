@@ -81,6 +81,14 @@ hipError_t launch_rb_half(const Level &L, const T *psi, const Coef<T> &C, const 
 hipError_t launch_active_tiles(const Level &L, const uint8_t *cls, int *flags, int *ids,
                                int *count, hipStream_t st);
 
+// Residual-norm partials of u (as launch_residual with partials, counted by
+// stencil_partials) together with the colour half-sweep of u into u_out (same
+// result as launch_rb_half, omega applied); residual_sweep_ok: the level is
+// swept by the node-parallel kernels.
+bool residual_sweep_ok(const Level &L);
+hipError_t launch_residual_sweep(const Level &L, const double *u, const double *f,
+                                 double *u_out, double omega, int colour, double *partials,
+                                 hipStream_t st);
 // LDS-tiled 3D half-sweep (same result as launch_rb_half); tiled_ok tells
 // whether a level is large enough for the 64 x 8 node tiles to pay.  With a
 // tile list only those tiles are swept (nodes outside them stay untouched).
@@ -130,6 +138,14 @@ hipError_t launch_cg_update(const Level &L, double *x, double *r, const double *
                             double *pz, hipStream_t st);
 hipError_t launch_xpby(const Level &L, double *p, const double *z, const double *rznew,
                        const double *rzold, const double *rz, hipStream_t st);
+// r32 = fp32(r / sqrt(*ss)) for a residual r in memory (the expression of
+// launch_residual_cast).
+hipError_t launch_scale_cast(const double *r, float *r32, int64_t n, const double *ss,
+                             hipStream_t st);
+// ... and the first colour half-sweep of the FP32 correction from zero into
+// t32 (finest level, FP32 operator).
+hipError_t launch_scale_cast_sweep(const Level &L, const double *r, float *r32, float *t32,
+                                   double omega, int colour, const double *ss, hipStream_t st);
 hipError_t launch_cast_scaled(const double *r, float *r32, int64_t n, const double *ss,
                               hipStream_t st);
 hipError_t launch_scale_set(double *z, const float *e32, int64_t n, const double *ss,

@@ -86,6 +86,45 @@ __global__ __launch_bounds__(kBlock) void k_residual(Geom g, Coef<T> C, const T 
   }
 }
 
+// Residual norm of u (partials of ||f - K u||^2 over free DOF, as
+// k_residual) and, from the same stencil evaluations, the colour-`colour`
+// half-sweep of u into u_out (the nodes of the other colour copied): the
+// convergence test of one V-cycle and the first smoothing step of the next in
+// one pass.  Each relaxed node takes the expression of k_rb_half on the same
+// values, so u_out equals that half-sweep.
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_residual_sweep(Geom g, Coef<double> C,
+                                                           const double *__restrict__ psi,
+                                                           const double *__restrict__ u,
+                                                           const double *__restrict__ f,
+                                                           double *__restrict__ u_out,
+                                                           double omega, int colour,
+                                                           double *__restrict__ partials) {
+  __shared__ double lds[kBlock / 64 + 1];
+  const int64_t id = (int64_t)xcd_block() * kBlock + threadIdx.x;
+  double ss = 0.0;
+  if (id < g.nn) {
+    int i, j, k;
+    node_ijk(g, id, i, j, k);
+    double fv[3], out[3], dg[3], uc[3];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) fv[c] = f[c * g.nn + id];
+    node_stencil<double, DIM>(g, C, psi, u, i, j, k, out, dg, uc);
+    const uint32_t fb = face_bits(g, i, j, k);
+    const bool relax = ((i + j + k) & 1) == colour;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+      const bool dir = ((g.dmask >> c) & fb) != 0u;
+      const double v = dir ? 0.0 : fv[c] - out[c];
+      ss += v * v;
+      const double w = dir ? 0.0 : omega;
+      u_out[c * g.nn + id] = relax ? uc[c] + w * (fv[c] - out[c]) / dg[c] : uc[c];
+    }
+  }
+  const double s = block_sum(ss, lds);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
 // r32 = fp32((f - K u) / s) on free DOF: the scaled residual handed to the
 // FP32 cycle of the mixed-precision solve.  s = sqrt(*ss) is the residual
 // norm the convergence test just computed (device-resident, so a captured
@@ -692,6 +731,49 @@ __global__ __launch_bounds__(kBlock) void k_cast_scaled(const double *__restrict
   r32[q] = sn > 0.0 ? (float)(r[q] / sn) : 0.0f;
 }
 
+// r32 = fp32(r / s) as k_residual_cast forms it (times the reciprocal of
+// s = sqrt(*ss)), for a residual r already in memory.
+__global__ __launch_bounds__(kBlock) void k_scale_cast(const double *__restrict__ r,
+                                                       float *__restrict__ r32, int64_t n,
+                                                       const double *__restrict__ ss) {
+  const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (q >= n) return;
+  const double sn = sqrt(*ss);
+  const double inv_s = sn > 0.0 ? 1.0 / sn : 0.0;
+  r32[q] = (float)(r[q] * inv_s);
+}
+
+// As k_scale_cast, and the first colour-`colour` half-sweep of the FP32
+// correction cycle from e = 0 written into t32 (relaxed nodes omega r32 / D
+// with D the FP32 diagonal, the others 0): the FP32 V-cycle then starts at its
+// second half-sweep.
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_scale_cast_sweep(Geom g, Coef<float> C,
+                                                             const float *__restrict__ psi,
+                                                             const double *__restrict__ r,
+                                                             float *__restrict__ r32,
+                                                             float *__restrict__ t32,
+                                                             float omega, int colour,
+                                                             const double *__restrict__ ss) {
+  const int64_t id = (int64_t)xcd_block() * kBlock + threadIdx.x;
+  if (id >= g.nn) return;
+  int i, j, k;
+  node_ijk(g, id, i, j, k);
+  const double sn = sqrt(*ss);
+  const double inv_s = sn > 0.0 ? 1.0 / sn : 0.0;
+  float dg[3];
+  node_diag<float, DIM>(g, C, psi, i, j, k, dg);
+  const uint32_t fb = face_bits(g, i, j, k);
+  const bool relax = ((i + j + k) & 1) == colour;
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) {
+    const float v = (float)(r[c * g.nn + id] * inv_s);
+    r32[c * g.nn + id] = v;
+    const float w = ((g.dmask >> c) & fb) ? 0.0f : omega;
+    t32[c * g.nn + id] = relax ? 0.0f + w * (v - 0.0f) / dg[c] : 0.0f;
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_scale_set(double *__restrict__ z,
                                                       const float *__restrict__ e32, int64_t n,
                                                       const double *__restrict__ ss) {
@@ -1041,6 +1123,19 @@ hipError_t launch_residual(const Level &L, const T *psi, const Coef<T> &C, const
   SBM_LAUNCH((k_residual<T, 2, false>), nb, bs, st, L.g, C, psi, u, f, r, partials, cls);
 }
 
+hipError_t launch_residual_sweep(const Level &L, const double *u, const double *f,
+                                 double *u_out, double omega, int colour, double *partials,
+                                 hipStream_t st) {
+  if (use_tiled(L)) return hipErrorInvalidValue;  // partials are counted per node block
+  if (L.g.dim == 3)
+    SBM_LAUNCH((k_residual_sweep<3>), grid_blocks(L.g.nn), kBlock, st, L.g, L.c64, L.psi64, u, f,
+               u_out, omega, colour, partials);
+  SBM_LAUNCH((k_residual_sweep<2>), grid_blocks(L.g.nn), kBlock, st, L.g, L.c64, L.psi64, u, f,
+             u_out, omega, colour, partials);
+}
+
+bool residual_sweep_ok(const Level &L) { return !use_tiled(L); }
+
 hipError_t launch_residual_cast(const Level &L, const double *u, const double *f, float *r32,
                                 const double *ss, hipStream_t st) {
   if (L.g.dim == 3)
@@ -1177,6 +1272,20 @@ hipError_t launch_xpby(const Level &L, double *p, const double *z, const double 
 hipError_t launch_cast_scaled(const double *r, float *r32, int64_t n, const double *ss,
                               hipStream_t st) {
   SBM_LAUNCH(k_cast_scaled, num_blocks(n), kBlock, st, r, r32, n, ss);
+}
+
+hipError_t launch_scale_cast(const double *r, float *r32, int64_t n, const double *ss,
+                             hipStream_t st) {
+  SBM_LAUNCH(k_scale_cast, num_blocks(n), kBlock, st, r, r32, n, ss);
+}
+
+hipError_t launch_scale_cast_sweep(const Level &L, const double *r, float *r32, float *t32,
+                                   double omega, int colour, const double *ss, hipStream_t st) {
+  if (L.g.dim == 3)
+    SBM_LAUNCH((k_scale_cast_sweep<3>), grid_blocks(L.g.nn), kBlock, st, L.g, L.c32, L.psi32, r,
+               r32, t32, (float)omega, colour, ss);
+  SBM_LAUNCH((k_scale_cast_sweep<2>), grid_blocks(L.g.nn), kBlock, st, L.g, L.c32, L.psi32, r, r32,
+             t32, (float)omega, colour, ss);
 }
 
 hipError_t launch_scale_set(double *z, const float *e32, int64_t n, const double *ss,

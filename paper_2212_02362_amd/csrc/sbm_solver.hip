@@ -70,7 +70,10 @@ struct sbm_ctx {
   int64_t prof_n[SBM_PROF_N] = {0};
   // captured V-cycles
   struct CycleGraph {
-    int mode;  // 0: outer-loop cycle on x0, 1: preconditioner z = M r
+    int mode;  // 0: outer-loop cycle on x0, 1: preconditioner z = M r, 2: as 0 with work
+               // done by the convergence test (FP64: the first finest half-sweep;
+               // mixed: the finest residual), 3: mixed, also the FP32 cycle's first
+               // half-sweep made by the cast
     int precision;
     const double *f;
     bool prof;
@@ -94,6 +97,9 @@ struct sbm_ctx {
   double *tail_A = nullptr;  // dense bottom matrix of the tails
   size_t tail_lds64 = 0, tail_lds32 = 0;
   size_t tail_lds_max = 64 * 1024;  // LDS bytes a workgroup may hold on this device
+  // set while a cycle runs whose first finest-level half-sweep was already
+  // done by the convergence test (its result is in the level's tmp vector)
+  bool first_half_done = false;
 };
 
 // Brackets one launch sequence with an event pair when profiling is on.
@@ -352,13 +358,17 @@ static hipError_t smooth(sbm_ctx *c, int l, T *x, const T *f, T *tmp, int nu, bo
     return e;
   }
   const int c0 = reverse ? 1 : 0;
+  // the first half-sweep of the outer cycle's pre-smoothing may already be in
+  // tmp (computed with the convergence test of the previous cycle)
+  const bool first_done = l == 0 && c->first_half_done;
+  c->first_half_done = false;
   const bool tiled = tiled_ok(L);
   auto half = [&](const T *src, T *dst, int colour) {
     return tiled ? launch_rb_tiled<T>(L, psi, C, src, f, dst, om, colour, c->st)
                  : launch_rb_half<T>(L, psi, C, src, f, dst, om, colour, c->st);
   };
   for (int s = 0; s < nu; ++s) {
-    {
+    if (s > 0 || !first_done) {
       ProfScope ps(c, SBM_PROF_SMOOTH, l == 0);
       if ((e = half(x, tmp, c0)) != hipSuccess) return e;
     }
@@ -445,6 +455,40 @@ static sbm_status residual_norm2(sbm_ctx *c, const double *u, const double *f, d
   return SBM_OK;
 }
 
+// As residual_norm2, and the first pre-smoothing half-sweep of the next
+// V-cycle from the same pass (into the finest level's tmp vector).
+static sbm_status residual_norm2_sweep(sbm_ctx *c, const double *u, const double *f,
+                                       double *out) {
+  Level &L = c->L[0];
+  {
+    ProfScope ps(c, SBM_PROF_NORM, true);
+    HIP_TRY(launch_residual_sweep(L, u, f, L.t, opt_omega(c->opt), 0, c->partials, c->st));
+  }
+  HIP_TRY(launch_finalize_sum(c->partials, stencil_partials(L), c->scal, c->st));
+  HIP_TRY(hipMemcpyAsync(c->host, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIP_TRY(hipStreamSynchronize(c->st));
+  if (c->prof_on) prof_harvest(c);
+  *out = c->host[0];
+  return SBM_OK;
+}
+
+// As residual_norm2, and f - K u written into the finest tmp vector (the
+// residual the mixed cycle then casts).
+static sbm_status residual_norm2_keep(sbm_ctx *c, const double *u, const double *f,
+                                      double *out) {
+  Level &L = c->L[0];
+  {
+    ProfScope ps(c, SBM_PROF_NORM, true);
+    HIP_TRY((launch_residual<double>(L, L.psi64, L.c64, u, f, L.t, c->partials, c->st)));
+  }
+  HIP_TRY(launch_finalize_sum(c->partials, stencil_partials(L), c->scal, c->st));
+  HIP_TRY(hipMemcpyAsync(c->host, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIP_TRY(hipStreamSynchronize(c->st));
+  if (c->prof_on) prof_harvest(c);
+  *out = c->host[0];
+  return SBM_OK;
+}
+
 // One cycle of the outer loop on the finest iterate x0 for the load f: an
 // FP64 V-cycle, or (mixed) r32 = (f - K x0)/s, an FP32 V-cycle for e32 from
 // zero, x0 += s e32 with s the residual norm left in scal[0] by the
@@ -466,12 +510,30 @@ static hipError_t cycle_body(sbm_ctx *c, const double *f, int mode) {
     return vcycle<double>(c, 0, c->kz, c->kr, L0.t);
   }
   if (c->opt.precision == 1) {
-    if ((e = launch_residual_cast(L0, c->x0, f, L0.f32, c->scal, c->st)) != hipSuccess) return e;
+    if (mode == 3) {
+      // the convergence test left f - K x0 in the finest tmp vector; its cast
+      // also makes the FP32 cycle's first half-sweep from zero (into t32)
+      if ((e = launch_scale_cast_sweep(L0, L0.t, L0.f32, L0.t32, opt_omega(c->opt), 0, c->scal,
+                                       c->st)) != hipSuccess)
+        return e;
+      c->first_half_done = true;
+      e = vcycle<float>(c, 0, L0.e32, L0.f32, L0.t32);
+      c->first_half_done = false;
+      if (e != hipSuccess) return e;
+      return launch_correct(L0, c->x0, L0.e32, c->scal, c->st);
+    }
+    // mode 2: the convergence test left f - K x0 in the finest tmp vector
+    if ((e = mode == 2 ? launch_scale_cast(L0.t, L0.f32, nv, c->scal, c->st)
+                       : launch_residual_cast(L0, c->x0, f, L0.f32, c->scal, c->st)) != hipSuccess)
+      return e;
     if ((e = launch_fill<float>(L0.e32, nv, 0.0f, c->st)) != hipSuccess) return e;
     if ((e = vcycle<float>(c, 0, L0.e32, L0.f32, L0.t32)) != hipSuccess) return e;
     return launch_correct(L0, c->x0, L0.e32, c->scal, c->st);
   }
-  return vcycle<double>(c, 0, c->x0, f, L0.t);
+  c->first_half_done = mode == 2;
+  e = vcycle<double>(c, 0, c->x0, f, L0.t);
+  c->first_half_done = false;
+  return e;
 }
 
 // Finds or captures the graph of cycle_body for (precision, f, profiling).
@@ -659,9 +721,23 @@ static sbm_status solve_impl(sbm_ctx *c, const double *f, double fnorm, double *
   int m = 0;
   sbm_status status = SBM_NOT_CONVERGED;
   HIP_TRY(launch_copy<double>(u, c->x0, nv, c->st));
+  // FP64 V-cycles with Gauss-Seidel pre-smoothing on a finest level swept by
+  // the node-parallel kernels: the convergence test also makes the next
+  // cycle's first half-sweep (the iterate itself is left as it is, so a
+  // converged solve returns the tested iterate)
+  const bool fused = c->opt.precision == 0 && c->opt.smoother == 0 && c->opt.nu_pre >= 1 &&
+                     c->nlev > 1 && c->tail64 != 0 && residual_sweep_ok(L0);
+  // mixed: the convergence test keeps f - K x0 for the cycle's cast, which
+  // also makes the FP32 cycle's first half-sweep when the finest level
+  // smooths outside the tail
+  const bool keep = c->opt.precision == 1 && residual_sweep_ok(L0);
+  const bool keep_sweep = keep && c->opt.smoother == 0 && c->opt.nu_pre >= 1 && c->nlev > 1 &&
+                          c->tail32 != 0;
   for (m = 0;; ++m) {
     double ss = 0.0;
-    sbm_status s = residual_norm2(c, c->x0, f, &ss);
+    sbm_status s = fused  ? residual_norm2_sweep(c, c->x0, f, &ss)
+                   : keep ? residual_norm2_keep(c, c->x0, f, &ss)
+                          : residual_norm2(c, c->x0, f, &ss);
     if (s != SBM_OK) return s;
     rho = fnorm > 0.0 ? sqrt(ss) / fnorm : (ss > 0.0 ? INFINITY : 0.0);
     if (hist && m < cap) hist[m] = rho;
@@ -684,7 +760,7 @@ static sbm_status solve_impl(sbm_ctx *c, const double *f, double fnorm, double *
       status = SBM_NOT_CONVERGED;
       break;
     }
-    s = run_cycle(c, f, 0);
+    s = run_cycle(c, f, keep_sweep ? 3 : (fused || keep ? 2 : 0));
     if (s != SBM_OK) return s;
   }
   if (ncyc) *ncyc = m;

@@ -173,5 +173,8 @@ def test_graph_replay_matches_eager(precision):
     captures, launches = S2.graph_info()
     assert S1.graph_info() == (0, 0)
     assert captures == 1 and launches == 2 * ncyc  # the timed solve runs launch by launch
-    assert prof["smooth"][1] == 2 * 4 * ncyc and prof["smooth"][0] > 0
+    # V(2,2): 8 finest half-sweeps per cycle, the first of them made by the
+    # convergence test's pass (FP64) or by the cast of its residual (mixed)
+    per = 2 * 4 - 1
+    assert prof["smooth"][1] == per * ncyc and prof["smooth"][0] > 0
     assert prof["bottom"][1] == ncyc
