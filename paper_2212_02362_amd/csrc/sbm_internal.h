@@ -142,6 +142,10 @@ hipError_t launch_xpby(const Level &L, double *p, const double *z, const double 
 // launch_residual_cast).
 hipError_t launch_scale_cast(const double *r, float *r32, int64_t n, const double *ss,
                              hipStream_t st);
+// The first colour half-sweep from a zero iterate for the load f into t
+// (finest level, FP64 operator).
+hipError_t launch_zero_sweep(const Level &L, const double *f, double *t, double omega, int colour,
+                             hipStream_t st);
 // ... and the first colour half-sweep of the FP32 correction from zero into
 // t32 (finest level, FP32 operator).
 hipError_t launch_scale_cast_sweep(const Level &L, const double *r, float *r32, float *t32,

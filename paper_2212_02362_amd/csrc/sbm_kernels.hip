@@ -1279,6 +1279,36 @@ hipError_t launch_scale_cast(const double *r, float *r32, int64_t n, const doubl
   SBM_LAUNCH(k_scale_cast, num_blocks(n), kBlock, st, r, r32, n, ss);
 }
 
+// The first colour-`colour` half-sweep from a zero iterate for the load f,
+// into t: omega f / D on the relaxed colour (D the diagonal), 0 elsewhere.
+template <typename T, int DIM>
+__global__ __launch_bounds__(kBlock) void k_zero_sweep(Geom g, Coef<T> C, const T *__restrict__ psi,
+                                                       const T *__restrict__ f, T *__restrict__ t,
+                                                       T omega, int colour) {
+  const int64_t id = (int64_t)xcd_block() * kBlock + threadIdx.x;
+  if (id >= g.nn) return;
+  int i, j, k;
+  node_ijk(g, id, i, j, k);
+  T dg[3];
+  node_diag<T, DIM>(g, C, psi, i, j, k, dg);
+  const uint32_t fb = face_bits(g, i, j, k);
+  const bool relax = ((i + j + k) & 1) == colour;
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) {
+    const T w = ((g.dmask >> c) & fb) ? T(0) : omega;
+    t[c * g.nn + id] = relax ? T(0) + w * (f[c * g.nn + id] - T(0)) / dg[c] : T(0);
+  }
+}
+
+hipError_t launch_zero_sweep(const Level &L, const double *f, double *t, double omega, int colour,
+                             hipStream_t st) {
+  if (L.g.dim == 3)
+    SBM_LAUNCH((k_zero_sweep<double, 3>), grid_blocks(L.g.nn), kBlock, st, L.g, L.c64, L.psi64, f,
+               t, omega, colour);
+  SBM_LAUNCH((k_zero_sweep<double, 2>), grid_blocks(L.g.nn), kBlock, st, L.g, L.c64, L.psi64, f, t,
+             omega, colour);
+}
+
 hipError_t launch_scale_cast_sweep(const Level &L, const double *r, float *r32, float *t32,
                                    double omega, int colour, const double *ss, hipStream_t st) {
   if (L.g.dim == 3)

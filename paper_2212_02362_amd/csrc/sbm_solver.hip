@@ -499,15 +499,35 @@ static hipError_t cycle_body(sbm_ctx *c, const double *f, int mode) {
   hipError_t e;
   if (mode == 1) {
     // preconditioner: kz = M kr, one V-cycle from zero (mixed: on kr / ||kr||
-    // in FP32, ||kr||^2 in scal[0])
+    // in FP32, ||kr||^2 in scal[0]).  When the finest level smooths outside
+    // the tail, its first half-sweep from zero is pointwise (omega kr / D on
+    // one colour) and is made together with the cast or instead of the fill.
+    const bool skip = c->opt.smoother == 0 && c->opt.nu_pre >= 1 && c->nlev > 1;
     if (c->opt.precision == 1) {
-      if ((e = launch_cast_scaled(c->kr, L0.f32, nv, c->scal, c->st)) != hipSuccess) return e;
-      if ((e = launch_fill<float>(L0.e32, nv, 0.0f, c->st)) != hipSuccess) return e;
-      if ((e = vcycle<float>(c, 0, L0.e32, L0.f32, L0.t32)) != hipSuccess) return e;
+      if (skip && c->tail32 != 0) {
+        if ((e = launch_scale_cast_sweep(L0, c->kr, L0.f32, L0.t32, opt_omega(c->opt), 0, c->scal,
+                                         c->st)) != hipSuccess)
+          return e;
+        c->first_half_done = true;
+      } else {
+        if ((e = launch_cast_scaled(c->kr, L0.f32, nv, c->scal, c->st)) != hipSuccess) return e;
+        if ((e = launch_fill<float>(L0.e32, nv, 0.0f, c->st)) != hipSuccess) return e;
+      }
+      e = vcycle<float>(c, 0, L0.e32, L0.f32, L0.t32);
+      c->first_half_done = false;
+      if (e != hipSuccess) return e;
       return launch_scale_set(c->kz, L0.e32, nv, c->scal, c->st);
     }
-    if ((e = launch_fill<double>(c->kz, nv, 0.0, c->st)) != hipSuccess) return e;
-    return vcycle<double>(c, 0, c->kz, c->kr, L0.t);
+    if (skip && c->tail64 != 0) {
+      if ((e = launch_zero_sweep(L0, c->kr, L0.t, opt_omega(c->opt), 0, c->st)) != hipSuccess)
+        return e;
+      c->first_half_done = true;
+    } else if ((e = launch_fill<double>(c->kz, nv, 0.0, c->st)) != hipSuccess) {
+      return e;
+    }
+    e = vcycle<double>(c, 0, c->kz, c->kr, L0.t);
+    c->first_half_done = false;
+    return e;
   }
   if (c->opt.precision == 1) {
     if (mode == 3) {
