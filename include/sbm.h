@@ -273,7 +273,8 @@ typedef struct {
  * grad, as sbm_return_map): principal strains e_i, W0+- = lambda/2
  * (sum <e_i>+-)^2 + mu sum <e_i>+-^2; H <- max(H, W0+) in place; intact[c] =
  * 1 where W0+ < W0- (the crack field is held at 1 there), else 0.  H and
- * intact: cells (double, uint8).  Async. */
+ * intact: cells (double, uint8).  u, H and intact must not alias each other
+ * (SBM_E_ARG).  Async. */
 sbm_status sbm_crack_drive(sbm_ctx *ctx, const double *u, double *H, uint8_t *intact);
 
 /* One explicit step c_out = c - dt M [g'(c) H - Gc (2 xi lap(c) + w'(c) /

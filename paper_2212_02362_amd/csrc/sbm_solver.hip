@@ -1148,6 +1148,9 @@ sbm_status sbm_diffuse_traction(sbm_ctx *c, const double *psi_raw, double psi_fl
 sbm_status sbm_crack_drive(sbm_ctx *c, const double *u, double *H, uint8_t *intact) {
   NEED_PROBLEM(c);
   if (!u || !H || !intact) return fail(SBM_E_ARG, "NULL argument");
+  if ((const void *)u == (const void *)H || (const void *)u == (const void *)intact ||
+      (const void *)H == (const void *)intact)
+    return fail(SBM_E_ARG, "u, H and intact must not alias each other");
   Level &L0 = c->L[0];
   HIP_TRY(launch_crack_drive(L0, c->mat.lambda, c->mat.mu, u, H, intact, c->st));
   return SBM_OK;

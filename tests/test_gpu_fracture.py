@@ -152,7 +152,7 @@ def test_phase_step_projection():
     assert np.array_equal(to_np(c1) == 0.0, cref == 0.0)
 
 
-def test_phase_step_rejects_aliased_outputs():
+def test_fracture_calls_reject_aliased_buffers():
     import ctypes
 
     from paper_2212_02362_amd._lib import SbmPf, lib
@@ -168,3 +168,7 @@ def test_phase_step_rejects_aliased_outputs():
     for co, po in ((c, out), (out, c), (out, out), (H, out), (out, H)):
         st = lib().sbm_phase_step(S._ctx, P(c), P(H), P(i8), ctypes.byref(pf), P(co), P(po))
         assert st == -1
+    say("crack drive aliasing")
+    u = torch.zeros((2, 6, 7), dtype=torch.float64, device="cuda")
+    for uu, hh, ii in ((u, u, i8), (u, H, u), (u, H, H)):
+        assert lib().sbm_crack_drive(S._ctx, P(uu), P(hh), P(ii)) == -1
