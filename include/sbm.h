@@ -26,6 +26,10 @@
  * _host.  The caller owns all memory.  The library never allocates device
  * memory: every device buffer it needs is carved from the caller's workspace
  * (sbm_workspace_bytes), which must stay alive until sbm_destroy.
+ * An output array must not be one of the call's input arrays or another of
+ * its outputs unless the call says so (solution vectors documented "in/out"
+ * are one array by design); the same pointer passed twice is rejected with
+ * SBM_E_ARG (partial overlaps of distinct pointers are not detected).
  *
  * Streams: all device work is enqueued on the HIP stream given to sbm_create.
  * Calls documented "async" return before the work completes; the others
@@ -52,7 +56,7 @@ typedef struct sbm_ctx sbm_ctx;
 typedef enum {
   SBM_OK = 0,
   SBM_NOT_CONVERGED = 1, /* max_cycles reached; u and history valid */
-  SBM_E_ARG = -1,        /* null pointer or out-of-range argument */
+  SBM_E_ARG = -1,        /* null pointer, aliased buffers or out-of-range argument */
   SBM_E_SHAPE = -2,      /* unsupported grid (dim, cell counts) */
   SBM_E_HIP = -3,        /* a HIP runtime call failed */
   SBM_E_NONFINITE = -4,  /* NaN/Inf in psi, b, u0 or a residual */

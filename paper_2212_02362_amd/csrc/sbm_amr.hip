@@ -1400,6 +1400,7 @@ sbm_status sbm_amr_ghost_fill(sbm_amr_ctx *c, int level, const double *xc, doubl
   AMR_NEED(c);
   if (level < 1 || level > c->A) return amr_fail(SBM_E_ARG, "level must be 1..levels-1");
   if (!xc || !xf) return amr_fail(SBM_E_ARG, "NULL argument");
+  if (xc == xf) return amr_fail(SBM_E_ARG, "xf must not alias xc");
   AMR_HIP(launch_ghost<double>(c->lv[level].L, c->lv[level - 1].L, c->lv[level].cls, xc, xf,
                                c->st, c->lv[level].tiles()));
   return SBM_OK;

@@ -12,6 +12,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <initializer_list>
 #include <string>
 #include <vector>
 
@@ -28,6 +29,20 @@ static sbm_status fail(sbm_status s, const std::string &msg) {
 }
 
 sbm_status sbm::set_error(sbm_status s, const std::string &msg) { return fail(s, msg); }
+
+// True when two of the non-NULL pointers are equal (an output passed as an
+// input or as another output of the same call).
+static bool aliased(std::initializer_list<const void *> p) {
+  for (auto a = p.begin(); a != p.end(); ++a)
+    for (auto b = a + 1; b != p.end(); ++b)
+      if (*a && *a == *b) return true;
+  return false;
+}
+#define NO_ALIAS(...)                                                                   \
+  do {                                                                                  \
+    if (aliased({__VA_ARGS__}))                                                         \
+      return fail(SBM_E_ARG, "an output buffer aliases an input or another output");    \
+  } while (0)
 
 #define HIP_TRY(expr)                                                                      \
   do {                                                                                     \
@@ -1053,6 +1068,7 @@ sbm_status sbm_solve_rhs(sbm_ctx *c, const double *g, double *x, double *hist, i
 sbm_status sbm_apply(sbm_ctx *c, const double *u, double *Ku) {
   NEED_PROBLEM(c);
   if (!u || !Ku) return fail(SBM_E_ARG, "NULL argument");
+  NO_ALIAS(u, Ku);
   Level &L0 = c->L[0];
   HIP_TRY(launch_apply<double>(L0, L0.psi64, L0.c64, u, Ku, c->st));
   return SBM_OK;
@@ -1061,6 +1077,7 @@ sbm_status sbm_apply(sbm_ctx *c, const double *u, double *Ku) {
 sbm_status sbm_residual(sbm_ctx *c, const double *u, double *r, double *norm_host) {
   NEED_PROBLEM(c);
   if (!u) return fail(SBM_E_ARG, "u is NULL");
+  NO_ALIAS(u, r);
   Level &L0 = c->L[0];
   if (!norm_host) {
     if (!r) return fail(SBM_E_ARG, "r and norm_host both NULL");
@@ -1078,6 +1095,7 @@ sbm_status sbm_residual(sbm_ctx *c, const double *u, double *r, double *norm_hos
 sbm_status sbm_rhs(sbm_ctx *c, double *fA, double *fB) {
   NEED_PROBLEM(c);
   if (!fA) return fail(SBM_E_ARG, "fA is NULL");
+  NO_ALIAS(fA, fB);
   Level &L0 = c->L[0];
   const int64_t nv = (int64_t)c->dim * L0.g.nn;
   HIP_TRY(launch_copy<double>(L0.f, fA, nv, c->st));
@@ -1093,6 +1111,8 @@ sbm_status sbm_sensitivity(sbm_ctx *c, const double *u, const double *lam, doubl
                            const double *design, int chain, double *g) {
   NEED_PROBLEM(c);
   if (!u || !lam || !g) return fail(SBM_E_ARG, "NULL argument");
+  if (aliased({u, g}) || aliased({lam, g}) || aliased({design, g}))
+    return fail(SBM_E_ARG, "g aliases an input");
   if (chain < 0 || chain > 2 || (chain > 0 && !design))
     return fail(SBM_E_ARG, "chain must be 0, 1 or 2 (1 and 2 need design)");
   if (!isfinite(lam_scale)) return fail(SBM_E_ARG, "lam_scale must be finite");
@@ -1105,6 +1125,7 @@ sbm_status sbm_sensitivity(sbm_ctx *c, const double *u, const double *lam, doubl
 sbm_status sbm_plastic_source(sbm_ctx *c, const double *eps_p, double *f) {
   NEED_PROBLEM(c);
   if (!eps_p || !f) return fail(SBM_E_ARG, "NULL argument");
+  NO_ALIAS(eps_p, f);
   if (c->dim != 3) return fail(SBM_E_SHAPE, "plastic strain: 3D grids only");
   Level &L0 = c->L[0];
   HIP_TRY(launch_plastic_source(L0, c->mat.lambda, c->mat.mu, eps_p, f, c->st));
@@ -1115,6 +1136,7 @@ sbm_status sbm_return_map(sbm_ctx *c, const double *u, const sbm_j2 *mat, double
                           double *alpha, double *beta, int64_t *n_plastic) {
   NEED_PROBLEM(c);
   if (!u || !mat || !eps_p || !alpha || !beta) return fail(SBM_E_ARG, "NULL argument");
+  NO_ALIAS(u, eps_p, alpha, beta, n_plastic);
   if (c->dim != 3) return fail(SBM_E_SHAPE, "plastic strain: 3D grids only");
   if (!(mat->sigma_y >= 0.0) || !(mat->hbar >= 0.0) || !(mat->theta >= 0.0 && mat->theta <= 1.0) ||
       !isfinite(mat->sigma_y) || !isfinite(mat->hbar))
@@ -1217,6 +1239,7 @@ sbm_status sbm_level_psi(sbm_ctx *c, int l, double *psi) {
 sbm_status sbm_level_apply(sbm_ctx *c, int l, const double *u, double *Ku) {
   LEVEL_OK(c, l);
   if (!u || !Ku) return fail(SBM_E_ARG, "NULL argument");
+  NO_ALIAS(u, Ku);
   Level &L = c->L[l];
   HIP_TRY(launch_apply<double>(L, L.psi64, L.c64, u, Ku, c->st));
   return SBM_OK;
@@ -1225,6 +1248,7 @@ sbm_status sbm_level_apply(sbm_ctx *c, int l, const double *u, double *Ku) {
 sbm_status sbm_level_apply_f32(sbm_ctx *c, int l, const float *u, float *Ku) {
   LEVEL_OK(c, l);
   if (!u || !Ku) return fail(SBM_E_ARG, "NULL argument");
+  NO_ALIAS(u, Ku);
   Level &L = c->L[l];
   HIP_TRY(launch_apply<float>(L, L.psi32, L.c32, u, Ku, c->st));
   return SBM_OK;
@@ -1233,7 +1257,9 @@ sbm_status sbm_level_apply_f32(sbm_ctx *c, int l, const float *u, float *Ku) {
 sbm_status sbm_level_smooth(sbm_ctx *c, int l, int colour, double omega, const double *u_in,
                             const double *f, double *u_out) {
   LEVEL_OK(c, l);
-  if (!u_in || !f || !u_out || u_in == u_out) return fail(SBM_E_ARG, "bad buffers");
+  if (!u_in || !f || !u_out) return fail(SBM_E_ARG, "NULL argument");
+  NO_ALIAS(u_in, u_out);
+  NO_ALIAS(f, u_out);
   if (!(omega > 0.0 && omega < 2.0) || colour > 1) return fail(SBM_E_ARG, "bad omega/colour");
   Level &L = c->L[l];
   if (colour < 0) HIP_TRY(launch_jacobi<double>(L, L.psi64, L.c64, u_in, f, u_out, omega, c->st));
@@ -1246,6 +1272,8 @@ sbm_status sbm_level_smooth(sbm_ctx *c, int l, int colour, double omega, const d
 sbm_status sbm_level_residual(sbm_ctx *c, int l, const double *u, const double *f, double *r) {
   LEVEL_OK(c, l);
   if (!u || !f || !r) return fail(SBM_E_ARG, "NULL argument");
+  NO_ALIAS(u, r);
+  NO_ALIAS(f, r);
   Level &L = c->L[l];
   HIP_TRY((launch_residual<double>(L, L.psi64, L.c64, u, f, r, nullptr, c->st)));
   return SBM_OK;
@@ -1255,6 +1283,7 @@ sbm_status sbm_level_restrict(sbm_ctx *c, int l, const double *r, double *fc) {
   LEVEL_OK(c, l);
   if (l + 1 >= c->nlev) return fail(SBM_E_ARG, "no coarser level");
   if (!r || !fc) return fail(SBM_E_ARG, "NULL argument");
+  NO_ALIAS(r, fc);
   HIP_TRY(launch_restrict<double>(c->L[l], c->L[l + 1], r, fc, c->st));
   return SBM_OK;
 }
@@ -1263,6 +1292,7 @@ sbm_status sbm_level_prolong_add(sbm_ctx *c, int l, const double *e, double *u) 
   LEVEL_OK(c, l);
   if (l + 1 >= c->nlev) return fail(SBM_E_ARG, "no coarser level");
   if (!e || !u) return fail(SBM_E_ARG, "NULL argument");
+  NO_ALIAS(e, u);
   HIP_TRY(launch_prolong_add<double>(c->L[l], c->L[l + 1], e, u, c->st));
   return SBM_OK;
 }
@@ -1270,6 +1300,7 @@ sbm_status sbm_level_prolong_add(sbm_ctx *c, int l, const double *e, double *u) 
 sbm_status sbm_bottom_solve(sbm_ctx *c, const double *f, double *x, int *iters) {
   NEED_PROBLEM(c);
   if (!f || !x) return fail(SBM_E_ARG, "NULL argument");
+  NO_ALIAS(f, x);
   HIP_TRY(bottom64(c, f, x));
   HIP_TRY(hipMemcpyAsync(c->host, c->iflag + 4, sizeof(int), hipMemcpyDeviceToHost, c->st));
   HIP_TRY(hipStreamSynchronize(c->st));
