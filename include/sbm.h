@@ -473,7 +473,8 @@ sbm_status sbm_amr_stats(sbm_amr_ctx *ctx, int64_t *composite_dof_host, double *
 sbm_status sbm_amr_ghost_fill(sbm_amr_ctx *ctx, int level, const double *xc, double *xf);
 
 /* Composite residual of u (ghosts of u are refilled in place) into r (per
- * level; r or any r[a] may be NULL) and its norm (absolute).  Synchronises. */
+ * level; r or any r[a] may be NULL, r[a] must not be u[a]) and its norm
+ * (absolute).  Synchronises. */
 sbm_status sbm_amr_residual(sbm_amr_ctx *ctx, double *const *u, double *const *r,
                             double *norm_host);
 

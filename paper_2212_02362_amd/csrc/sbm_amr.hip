@@ -1413,6 +1413,7 @@ sbm_status sbm_amr_residual(sbm_amr_ctx *c, double *const *u, double *const *r,
   double *f[kMaxAmrLevels], *rr[kMaxAmrLevels];
   for (int a = 0; a <= c->A; ++a) {
     if (!u[a]) return amr_fail(SBM_E_ARG, "u of a level is NULL");
+    if (r && r[a] == u[a]) return amr_fail(SBM_E_ARG, "r of a level must not alias its u");
     f[a] = c->lv[a].fP;
     rr[a] = (r && r[a]) ? r[a] : c->lv[a].r;
   }

@@ -126,6 +126,13 @@ def test_composite_residual(name):
         assert np.array_equal(to_np(u_g[a]), u_o[a]), a  # ghosts refilled identically
         assert rel_max(to_np(r_g[a]), r_o[a]) < 1e-12, a
     assert abs(n_g - n_o) <= 1e-12 * n_o
+    # a level's r passed as its u is rejected before any launch
+    import ctypes
+
+    from paper_2212_02362_amd._lib import lib
+    arr = (ctypes.c_void_p * len(u_g))(*[t.data_ptr() for t in u_g])
+    assert lib().sbm_amr_residual(S._ctx, arr, arr, None) == -1
+    assert b"alias" in lib().sbm_last_error()
 
 
 @pytest.mark.parametrize("name", CASES)
