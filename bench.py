@@ -155,8 +155,8 @@ def _bench_amr(args):
                    "cycles": r["cyc"], "final_rel_residual": max(r["fin"]), "status": r["st"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_rb_half<double,3,false> on the finest adaptive level (dense storage, "
-                               "class mask)",
+                     "kernel": "k_rb_tile<double,true> (LDS-tiled class-masked half-sweep) over the "
+                               "tiles of the finest adaptive level that hold active blocks",
                      "algo_bytes_per_launch": by, "avg_launch_us": avg_ms * 1e3,
                      "timing": "HIP events around each finest-level launch, one profiled solve "
                                "after the timed region"},
