@@ -112,7 +112,11 @@ typedef struct {
  *                  gradients (Polak-Ribiere) preconditioned by one V-cycle
  *                  from zero per iteration, post-smoothing colours reversed
  *                  (black, red); the history then has one entry per CG
- *                  iteration and max_cycles caps the iterations */
+ *                  iteration and max_cycles caps the iterations
+ *   fused_sweep    1: on levels wider than 192 nodes every Gauss-Seidel sweep
+ *                  is one launch that relaxes the second colour one plane
+ *                  behind the first (the same iterates as two half-sweeps);
+ *                  0: two half-sweep launches per sweep [0] */
 typedef struct {
   int smoother;
   double omega;
@@ -124,6 +128,7 @@ typedef struct {
   int bottom_max_iter;
   int use_graphs;
   int krylov;
+  int fused_sweep;
 } sbm_options;
 
 /* Fills *opts with the defaults above. */
@@ -322,6 +327,15 @@ sbm_status sbm_profile_read(sbm_ctx *ctx, double *ms_host, int64_t *count_host);
  * reason of a failed capture is then in sbm_last_error()). */
 sbm_status sbm_graph_info(sbm_ctx *ctx, int64_t *captures_host, int64_t *launches_host);
 
+/* Bandwidth probe, not part of the method: a[i] = b[i] + s c[i] for i < n
+ * (device arrays of n doubles, 16-byte aligned, a distinct from b and c), one
+ * pass of 16-byte loads and stores enqueued on hip_stream (NULL: the null
+ * stream).  Benchmarks time it to measure the bandwidth a plain streaming
+ * kernel reaches on the device (24 bytes per element).  Async; SBM_E_ARG on
+ * NULL, misaligned or aliased arrays or n < 1. */
+sbm_status sbm_stream_triad(double *a, const double *b, const double *c, int64_t n, double s,
+                            void *hip_stream);
+
 /* Releases host-side state; the workspace stays the caller's. */
 void sbm_destroy(sbm_ctx *ctx);
 
@@ -352,6 +366,20 @@ sbm_status sbm_level_apply_f32(sbm_ctx *ctx, int level, const float *u, float *K
  * Displacement DOF are copied unchanged. */
 sbm_status sbm_level_smooth(sbm_ctx *ctx, int level, int colour, double omega,
                             const double *u_in, const double *f, double *u_out);
+
+/* One complete two-colour Gauss-Seidel sweep on level l (Sec. 2.3), out of
+ * place: the half-sweep of first_colour (0 or 1) from u_in, then the
+ * half-sweep of the other colour from that intermediate state, each
+ * colour-synchronous as in sbm_level_smooth; displacement DOF keep their
+ * values.  u_in == NULL stands for a zero iterate.  u_out must differ from
+ * u_in and f.  Levels wider than 192 nodes run it as one fused launch (the
+ * second colour one plane behind the first); other levels run two half-sweeps
+ * through the level's internal scratch vector.  The _f32 variant uses the
+ * FP32 operator (FP32 psi copy) on FP32 vectors.  Async. */
+sbm_status sbm_level_sweep(sbm_ctx *ctx, int level, int first_colour, double omega,
+                           const double *u_in, const double *f, double *u_out);
+sbm_status sbm_level_sweep_f32(sbm_ctx *ctx, int level, int first_colour, double omega,
+                               const float *u_in, const float *f, float *u_out);
 
 /* r = f - K u on free DOF of level l, 0 on displacement DOF. */
 sbm_status sbm_level_residual(sbm_ctx *ctx, int level, const double *u, const double *f,

@@ -49,7 +49,7 @@ class SbmOptions(ctypes.Structure):
                 ("nu_post", ctypes.c_int), ("precision", ctypes.c_int), ("rtol", ctypes.c_double),
                 ("max_cycles", ctypes.c_int), ("bottom_rtol", ctypes.c_double),
                 ("bottom_max_iter", ctypes.c_int), ("use_graphs", ctypes.c_int),
-                ("krylov", ctypes.c_int)]
+                ("krylov", ctypes.c_int), ("fused_sweep", ctypes.c_int)]
 
 
 _P = ctypes.c_void_p
@@ -83,6 +83,7 @@ SIGNATURES = {
     "sbm_phase_step": (ctypes.c_int, [_P, _P, _P, _P, ctypes.POINTER(SbmPf), _P, _P]),
     "sbm_profile": (ctypes.c_int, [_P, ctypes.c_int]),
     "sbm_graph_info": (ctypes.c_int, [_P, _I64P, _I64P]),
+    "sbm_stream_triad": (ctypes.c_int, [_P, _P, _P, ctypes.c_int64, ctypes.c_double, _P]),
     "sbm_profile_read": (ctypes.c_int, [_P, _DP, _I64P]),
     "sbm_destroy": (None, [_P]),
     "sbm_last_error": (ctypes.c_char_p, []),
@@ -92,6 +93,10 @@ SIGNATURES = {
     "sbm_level_apply_f32": (ctypes.c_int, [_P, ctypes.c_int, _P, _P]),
     "sbm_level_smooth": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_double, _P, _P,
                                         _P]),
+    "sbm_level_sweep": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_double, _P, _P,
+                                       _P]),
+    "sbm_level_sweep_f32": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_double, _P,
+                                           _P, _P]),
     "sbm_level_residual": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P]),
     "sbm_level_restrict": (ctypes.c_int, [_P, ctypes.c_int, _P, _P]),
     "sbm_level_prolong_add": (ctypes.c_int, [_P, ctypes.c_int, _P, _P]),

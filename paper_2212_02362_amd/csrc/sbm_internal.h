@@ -41,13 +41,7 @@ struct Level {
 
 // Column tiles of the tiled 3D kernels: kTileX x kTileY nodes in x, y over a
 // chunk of kz planes; tile id = tx + ntx (ty + nty tz).
-#ifndef SBM_TILE_TX
-#define SBM_TILE_TX 64
-#endif
-#ifndef SBM_TILE_TY
-#define SBM_TILE_TY 8
-#endif
-constexpr int kTileX = SBM_TILE_TX, kTileY = SBM_TILE_TY;
+constexpr int kTileX = 64, kTileY = 8;
 struct TileGeom {
   int ntx, nty, kz, ntiles;
 };
@@ -97,6 +91,13 @@ template <typename T>
 hipError_t launch_rb_tiled(const Level &L, const T *psi, const Coef<T> &C, const T *u, const T *f,
                            T *u_out, double omega, int colour, hipStream_t st,
                            const uint8_t *cls = nullptr, const TileList *tl = nullptr);
+// One complete two-colour Gauss-Seidel sweep on a tiled level in one launch
+// (the same result as the half-sweep of first_colour from u followed by the
+// half-sweep of the other colour): u_out must not be u.  u == nullptr means
+// a zero iterate (nothing is read).
+template <typename T>
+hipError_t launch_rb_fused(const Level &L, const T *psi, const Coef<T> &C, const T *u, const T *f,
+                           T *u_out, double omega, int first_colour, hipStream_t st);
 // Tiled residual / Krylov Apply (same results as the node-parallel kernels);
 // their partial sums number tiled_partials(L).
 int tiled_partials(const Level &L);
@@ -118,6 +119,9 @@ template <typename T>
 hipError_t launch_fill(T *p, int64_t n, T v, hipStream_t st);
 template <typename T>
 hipError_t launch_copy(const T *src, T *dst, int64_t n, hipStream_t st);
+// a = b + s c over n doubles (16-byte aligned arrays; bandwidth probe).
+hipError_t launch_triad(double *a, const double *b, const double *c, int64_t n, double s,
+                        hipStream_t st);
 hipError_t launch_correct(const Level &L, double *u, const float *e32, const double *ss,
                           hipStream_t st);
 hipError_t launch_set_dirichlet(const Level &L, double *u, const DispValues &dv, hipStream_t st);

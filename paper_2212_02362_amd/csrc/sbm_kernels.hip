@@ -23,10 +23,8 @@ int grid_blocks(int64_t n) {
 // Threads per block of the V-cycle stencil and transfer kernels on a level
 // of n work items: small levels take blocks of 128 (twice as many blocks,
 // spread over more CUs; their launches are bound by latency, not bytes).
-#ifndef SBM_SMALL_LEVEL
-#define SBM_SMALL_LEVEL 300000
-#endif
-static int level_block(int64_t n) { return n < SBM_SMALL_LEVEL ? 128 : kBlock; }
+constexpr int64_t kSmallLevel = 300000;
+static int level_block(int64_t n) { return n < kSmallLevel ? 128 : kBlock; }
 static int level_grid(int64_t n) {
   const int bs = level_block(n);
   const int nb = (int)((n + bs - 1) / bs);
@@ -1195,6 +1193,28 @@ hipError_t launch_prolong_add(const Level &F, const Level &Cl, const T *e, T *u,
 template <typename T>
 hipError_t launch_fill(T *p, int64_t n, T v, hipStream_t st) {
   SBM_LAUNCH((k_fill<T>), fill_blocks(n), kBlock, st, p, n, v);
+}
+
+// Bandwidth probe (not part of the method): a = b + s c with 16-byte loads
+// and stores, two doubles per thread.
+__global__ __launch_bounds__(kBlock) void k_triad(double *__restrict__ a,
+                                                  const double *__restrict__ b,
+                                                  const double *__restrict__ c, int64_t n,
+                                                  double s) {
+  const int64_t i = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * 2;
+  if (i + 1 < n) {
+    const double2 bv = *reinterpret_cast<const double2 *>(b + i);
+    const double2 cv = *reinterpret_cast<const double2 *>(c + i);
+    *reinterpret_cast<double2 *>(a + i) = make_double2(bv.x + s * cv.x, bv.y + s * cv.y);
+  } else if (i < n) {
+    a[i] = b[i] + s * c[i];
+  }
+}
+
+hipError_t launch_triad(double *a, const double *b, const double *c, int64_t n, double s,
+                        hipStream_t st) {
+  const int64_t blocks = (n + 2 * kBlock - 1) / (2 * kBlock);
+  SBM_LAUNCH(k_triad, (unsigned)blocks, kBlock, st, a, b, c, n, s);
 }
 
 template <typename T>

@@ -115,6 +115,10 @@ struct sbm_ctx {
   // set while a cycle runs whose first finest-level half-sweep was already
   // done by the convergence test (its result is in the level's tmp vector)
   bool first_half_done = false;
+  // set while a cycle runs whose finest-level correction starts from zero on a
+  // level swept by the fused two-colour kernel (nothing is filled or read: the
+  // first sweep relaxes from a zero iterate)
+  bool zero_start = false;
 };
 
 // Brackets one launch sequence with an event pair when profiling is on.
@@ -373,6 +377,23 @@ static hipError_t smooth(sbm_ctx *c, int l, T *x, const T *f, T *tmp, int nu, bo
     return e;
   }
   const int c0 = reverse ? 1 : 0;
+  if (c->opt.fused_sweep == 1 && tiled_ok(L)) {
+    // whole two-colour sweeps in one launch each, ping-ponging between x and
+    // tmp so that the last lands in x; from a zero iterate (zero_start) the
+    // first sweep reads nothing
+    const bool zero = l == 0 && c->zero_start;
+    c->zero_start = false;
+    T *cur = zero ? nullptr : x;
+    for (int s = 0; s < nu; ++s) {
+      T *dst = cur ? (cur == x ? tmp : x) : (((nu - 1 - s) % 2 == 0) ? x : tmp);
+      ProfScope ps(c, SBM_PROF_SMOOTH, l == 0);
+      if ((e = launch_rb_fused<T>(L, psi, C, cur, f, dst, om, c0, c->st)) != hipSuccess) return e;
+      cur = dst;
+    }
+    if (!cur) return launch_fill<T>(x, (int64_t)c->dim * L.g.nn, T(0), c->st);
+    if (cur != x) return launch_copy<T>(cur, x, (int64_t)c->dim * L.g.nn, c->st);
+    return hipSuccess;
+  }
   // the first half-sweep of the outer cycle's pre-smoothing may already be in
   // tmp (computed with the convergence test of the previous cycle)
   const bool first_done = l == 0 && c->first_half_done;
@@ -518,8 +539,13 @@ static hipError_t cycle_body(sbm_ctx *c, const double *f, int mode) {
     // the tail, its first half-sweep from zero is pointwise (omega kr / D on
     // one colour) and is made together with the cast or instead of the fill.
     const bool skip = c->opt.smoother == 0 && c->opt.nu_pre >= 1 && c->nlev > 1;
+    // a finest level swept by the fused kernel starts that sweep from zero
+    const bool zs = skip && c->opt.fused_sweep == 1 && tiled_ok(L0);
     if (c->opt.precision == 1) {
-      if (skip && c->tail32 != 0) {
+      if (zs && c->tail32 != 0) {
+        if ((e = launch_cast_scaled(c->kr, L0.f32, nv, c->scal, c->st)) != hipSuccess) return e;
+        c->zero_start = true;
+      } else if (skip && c->tail32 != 0) {
         if ((e = launch_scale_cast_sweep(L0, c->kr, L0.f32, L0.t32, opt_omega(c->opt), 0, c->scal,
                                          c->st)) != hipSuccess)
           return e;
@@ -530,10 +556,13 @@ static hipError_t cycle_body(sbm_ctx *c, const double *f, int mode) {
       }
       e = vcycle<float>(c, 0, L0.e32, L0.f32, L0.t32);
       c->first_half_done = false;
+      c->zero_start = false;
       if (e != hipSuccess) return e;
       return launch_scale_set(c->kz, L0.e32, nv, c->scal, c->st);
     }
-    if (skip && c->tail64 != 0) {
+    if (zs && c->tail64 != 0) {
+      c->zero_start = true;
+    } else if (skip && c->tail64 != 0) {
       if ((e = launch_zero_sweep(L0, c->kr, L0.t, opt_omega(c->opt), 0, c->st)) != hipSuccess)
         return e;
       c->first_half_done = true;
@@ -542,6 +571,7 @@ static hipError_t cycle_body(sbm_ctx *c, const double *f, int mode) {
     }
     e = vcycle<double>(c, 0, c->kz, c->kr, L0.t);
     c->first_half_done = false;
+    c->zero_start = false;
     return e;
   }
   if (c->opt.precision == 1) {
@@ -561,8 +591,14 @@ static hipError_t cycle_body(sbm_ctx *c, const double *f, int mode) {
     if ((e = mode == 2 ? launch_scale_cast(L0.t, L0.f32, nv, c->scal, c->st)
                        : launch_residual_cast(L0, c->x0, f, L0.f32, c->scal, c->st)) != hipSuccess)
       return e;
-    if ((e = launch_fill<float>(L0.e32, nv, 0.0f, c->st)) != hipSuccess) return e;
-    if ((e = vcycle<float>(c, 0, L0.e32, L0.f32, L0.t32)) != hipSuccess) return e;
+    if (c->opt.fused_sweep == 1 && tiled_ok(L0) && c->opt.smoother == 0 && c->opt.nu_pre >= 1 &&
+        c->nlev > 1 && c->tail32 != 0)
+      c->zero_start = true;
+    else if ((e = launch_fill<float>(L0.e32, nv, 0.0f, c->st)) != hipSuccess)
+      return e;
+    e = vcycle<float>(c, 0, L0.e32, L0.f32, L0.t32);
+    c->zero_start = false;
+    if (e != hipSuccess) return e;
     return launch_correct(L0, c->x0, L0.e32, c->scal, c->st);
   }
   c->first_half_done = mode == 2;
@@ -823,6 +859,7 @@ void sbm_default_options(sbm_options *o) {
   o->bottom_max_iter = 0;
   o->use_graphs = 1;
   o->krylov = 0;
+  o->fused_sweep = 0;
 }
 
 const char *sbm_last_error(void) { return g_last_error.c_str(); }
@@ -836,7 +873,8 @@ static bool opts_ok(const sbm_options *o) {
   return o && (o->smoother == 0 || o->smoother == 1) && o->nu_pre >= 0 && o->nu_post >= 0 &&
          (o->precision == 0 || o->precision == 1) && o->rtol >= 0.0 && o->max_cycles >= 0 &&
          o->bottom_rtol >= 0.0 && isfinite(o->omega) && o->omega >= 0.0 && o->omega < 2.0 &&
-         (o->use_graphs == 0 || o->use_graphs == 1) && (o->krylov == 0 || o->krylov == 1);
+         (o->use_graphs == 0 || o->use_graphs == 1) && (o->krylov == 0 || o->krylov == 1) &&
+         (o->fused_sweep == 0 || o->fused_sweep == 1);
 }
 
 size_t sbm_workspace_bytes(const sbm_grid *grid, const sbm_options *opts) {
@@ -870,7 +908,6 @@ sbm_status sbm_create(const sbm_grid *grid, const sbm_options *opts, void *works
   carve(c, c->ws);
   c->opt = *opts;
   c->st = (hipStream_t)hip_stream;
-#ifndef SBM_TAIL_DISABLE
   {
     int dev = 0, lds = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -882,7 +919,6 @@ sbm_status sbm_create(const sbm_grid *grid, const sbm_options *opts, void *works
     c->tail64 = tail_level(c->L, 0, (size_t)lds);
     c->tail32 = tail_level(c->L, 1, (size_t)lds);
   }
-#endif
   hipError_t e = hipHostMalloc((void **)&c->host, 64 * sizeof(double), hipHostMallocDefault);
   if (e != hipSuccess) {
     delete c;
@@ -899,7 +935,7 @@ sbm_status sbm_set_options(sbm_ctx *c, const sbm_options *opts) {
   const bool same = o.smoother == opts->smoother && o.omega == opts->omega &&
                     o.nu_pre == opts->nu_pre && o.nu_post == opts->nu_post &&
                     o.bottom_rtol == opts->bottom_rtol && o.bottom_max_iter == opts->bottom_max_iter &&
-                    o.krylov == opts->krylov;
+                    o.krylov == opts->krylov && o.fused_sweep == opts->fused_sweep;
   if (!same) {
     HIP_TRY(hipStreamSynchronize(c->st));
     drop_graphs(c);
@@ -927,6 +963,18 @@ sbm_status sbm_profile(sbm_ctx *c, int enable) {
     c->prof_n[k] = 0;
   }
   c->prof_on = enable != 0;
+  return SBM_OK;
+}
+
+sbm_status sbm_stream_triad(double *a, const double *b, const double *cc, int64_t n, double s,
+                            void *hip_stream) {
+  if (!a || !b || !cc || n < 1) return fail(SBM_E_ARG, "NULL argument or n < 1");
+  if (((uintptr_t)a | (uintptr_t)b | (uintptr_t)cc) & 15)
+    return fail(SBM_E_ARG, "triad arrays must be 16-byte aligned");
+  if (n > ((int64_t)1 << 40)) return fail(SBM_E_ARG, "n too large");
+  NO_ALIAS(a, b);
+  NO_ALIAS(a, cc);
+  HIP_TRY(launch_triad(a, b, cc, n, s, (hipStream_t)hip_stream));
   return SBM_OK;
 }
 
@@ -1267,6 +1315,48 @@ sbm_status sbm_level_smooth(sbm_ctx *c, int l, int colour, double omega, const d
     HIP_TRY(launch_rb_tiled<double>(L, L.psi64, L.c64, u_in, f, u_out, omega, colour, c->st));
   else HIP_TRY(launch_rb_half<double>(L, L.psi64, L.c64, u_in, f, u_out, omega, colour, c->st));
   return SBM_OK;
+}
+
+}  // extern "C"
+
+template <typename T>
+static sbm_status level_sweep(sbm_ctx *c, int l, int first, double omega, const T *u_in,
+                              const T *f, T *u_out) {
+  LEVEL_OK(c, l);
+  if (!f || !u_out) return fail(SBM_E_ARG, "NULL argument");
+  NO_ALIAS(u_in, u_out);
+  NO_ALIAS(f, u_out);
+  if (!(omega > 0.0 && omega < 2.0) || first < 0 || first > 1)
+    return fail(SBM_E_ARG, "bad omega/colour");
+  Level &L = c->L[l];
+  const T *psi = Prec<T>::psi(L);
+  const Coef<T> &C = Prec<T>::coef(L);
+  if (tiled_ok(L)) {
+    HIP_TRY(launch_rb_fused<T>(L, psi, C, u_in, f, u_out, omega, first, c->st));
+    return SBM_OK;
+  }
+  // two half-sweeps through the level's scratch vector
+  T *mid = Prec<T>::t(L);
+  const T *src = u_in;
+  if (!src) {
+    HIP_TRY(launch_fill<T>(u_out, (int64_t)c->dim * L.g.nn, T(0), c->st));
+    src = u_out;
+  }
+  HIP_TRY(launch_rb_half<T>(L, psi, C, src, f, mid, omega, first, c->st));
+  HIP_TRY(launch_rb_half<T>(L, psi, C, mid, f, u_out, omega, 1 - first, c->st));
+  return SBM_OK;
+}
+
+extern "C" {
+
+sbm_status sbm_level_sweep(sbm_ctx *c, int l, int first_colour, double omega, const double *u_in,
+                           const double *f, double *u_out) {
+  return level_sweep<double>(c, l, first_colour, omega, u_in, f, u_out);
+}
+
+sbm_status sbm_level_sweep_f32(sbm_ctx *c, int l, int first_colour, double omega,
+                               const float *u_in, const float *f, float *u_out) {
+  return level_sweep<float>(c, l, first_colour, omega, u_in, f, u_out);
 }
 
 sbm_status sbm_level_residual(sbm_ctx *c, int l, const double *u, const double *f, double *r) {

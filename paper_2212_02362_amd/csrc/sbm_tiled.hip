@@ -15,18 +15,8 @@
 namespace sbm {
 namespace {
 
-#ifndef SBM_TILE_WG
-#define SBM_TILE_WG 1536  // target number of workgroups (sets the z-chunk depth)
-#endif
-#ifndef SBM_TILE_KZMAX
-#define SBM_TILE_KZMAX 32
-#endif
-#ifndef SBM_TILE_XCD
-#define SBM_TILE_XCD 1
-#endif
-#ifndef SBM_TILE_WAVES
-#define SBM_TILE_WAVES 2  // waves per SIMD the FP64 register budget is sized for
-#endif
+constexpr int kTileWG = 1536;  // target number of workgroups (sets the z-chunk depth)
+constexpr int kTileKzMax = 32;
 
 constexpr int TX = kTileX, TY = kTileY;     // interior nodes of a tile
 constexpr int LX = TX + 2, LY = TY + 2;     // with the node halo
@@ -61,8 +51,8 @@ TileGeom tile_geom(const TG &g) {
   const int cols = t.ntx * t.nty;
   // enough workgroups to fill 256 CUs several times over; each chunk re-reads
   // two planes
-  int kz = (int)((int64_t)g.nz * cols / SBM_TILE_WG);
-  kz = kz < 4 ? 4 : (kz > SBM_TILE_KZMAX ? SBM_TILE_KZMAX : kz);
+  int kz = (int)((int64_t)g.nz * cols / kTileWG);
+  kz = kz < 4 ? 4 : (kz > kTileKzMax ? kTileKzMax : kz);
   t.kz = kz;
   t.ntiles = cols * ((g.nz + kz - 1) / kz);
   return t;
@@ -147,7 +137,7 @@ __device__ __forceinline__ void put_p(const TG &g, const Slots &s, int kc, T *ld
 // only class-1 nodes are updated.  Both nodes of a thread's x-pair are stored
 // back to back so that every written line is complete in L2.
 template <typename T, bool MASK>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(SBM_TILE_WAVES))) void k_rb_tile(TG g, Coef<T> C, const T *__restrict__ psi,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_rb_tile(TG g, Coef<T> C, const T *__restrict__ psi,
                                                    const T *__restrict__ u,
                                                    const T *__restrict__ f,
                                                    T *__restrict__ u_out, T omega, int colour,
@@ -157,7 +147,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(SBM_TILE_WAV
   __shared__ T sp[2][NP];
   const int nwg = gridDim.x;  // a multiple of 8
   const int b = blockIdx.x;
-  const int li = SBM_TILE_XCD ? (b & 7) * (nwg >> 3) + (b >> 3) : b;
+  const int li = (b & 7) * (nwg >> 3) + (b >> 3);
   if (li >= (ids ? nids : tg.ntiles)) return;
   const int lt = ids ? ids[li] : li;  // a subset of the tiles, or all of them
   const int tx = lt % tg.ntx;
@@ -202,17 +192,19 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(SBM_TILE_WAV
 
   for (int k = k0; k < k1; ++k) {
     const bool pre = k + 1 < k1;
-    T fn[3] = {T(0), T(0), T(0)};
-    if (pre && gy < g.ny && upd_x(k + 1) < g.nx) {
-      const int q = gy * g.nx + (k + 1) * nxy + upd_x(k + 1);
+    // next plane's f and the plane two ahead, loaded unconditionally
+    // (in-range dummies past the chunk): loads under a branch make the
+    // compiler wait for every older load at their first use
+    T fn[3];
+    {
+      const bool ok = pre && gy < g.ny && upd_x(k + 1) < g.nx;
+      const int q = ok ? gy * g.nx + (k + 1) * nxy + upd_x(k + 1) : 0;
 #pragma unroll
       for (int c = 0; c < 3; ++c) fn[c] = f[c * nn + q];
     }
     T ru[NUPT], rp[NPPT];
-    if (pre) {
-      fetch_u(g, sl, u, k + 2, ru);
-      fetch_p(g, sl, psi, k + 1, rp);
-    }
+    fetch_u(g, sl, u, k + 2, ru);
+    fetch_p(g, sl, psi, k + 1, rp);
     const T *Lm = su[(k + 2) % 3];
     const T *L0 = su[k % 3];
     const T *L1 = su[(k + 1) % 3];
@@ -280,7 +272,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(SBM_TILE_WAV
 //     partial sum of u . v per tile.
 // Partials land in partials[tile], tiles in their logical order.
 template <typename T, int MODE, bool MASK>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(SBM_TILE_WAVES))) void
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void
 k_full_tile(TG g, Coef<T> C, const T *__restrict__ psi, const T *__restrict__ u,
             const T *__restrict__ f, T *__restrict__ r, double *__restrict__ partials,
             TileGeom tg, const uint8_t *__restrict__ cls, const int *__restrict__ ids, int nids) {
@@ -289,7 +281,7 @@ k_full_tile(TG g, Coef<T> C, const T *__restrict__ psi, const T *__restrict__ u,
   __shared__ double red[NT / 64 + 1];
   const int nwg = gridDim.x;  // a multiple of 8
   const int b = blockIdx.x;
-  const int li = SBM_TILE_XCD ? (b & 7) * (nwg >> 3) + (b >> 3) : b;
+  const int li = (b & 7) * (nwg >> 3) + (b >> 3);
   if (li >= (ids ? nids : tg.ntiles)) return;
   const int lt = ids ? ids[li] : li;  // a subset of the tiles, or all of them
   const int tx = lt % tg.ntx;
@@ -337,19 +329,19 @@ k_full_tile(TG g, Coef<T> C, const T *__restrict__ psi, const T *__restrict__ u,
   for (int k = k0; k < k1; ++k) {
     const bool pre = k + 1 < k1;
     T fn[2][3] = {{T(0), T(0), T(0)}, {T(0), T(0), T(0)}};
-    if (MODE == 0 && pre && row_ok) {
-      const int q = gy * g.nx + (k + 1) * nxy + gx0;
+    if (MODE == 0) {
+      // unconditional loads (in-range dummies where not needed), as above
 #pragma unroll
-      for (int h = 0; h < 2; ++h)
-        if (gx0 + h < g.nx)
+      for (int h = 0; h < 2; ++h) {
+        const bool ok = pre && row_ok && gx0 + h < g.nx;
+        const int q = ok ? gy * g.nx + (k + 1) * nxy + gx0 + h : 0;
 #pragma unroll
-          for (int c = 0; c < 3; ++c) fn[h][c] = f[c * nn + q + h];
+        for (int c = 0; c < 3; ++c) fn[h][c] = f[c * nn + q];
+      }
     }
     T ru[NUPT], rp[NPPT];
-    if (pre) {
-      fetch_u(g, sl, u, k + 2, ru);
-      fetch_p(g, sl, psi, k + 1, rp);
-    }
+    fetch_u(g, sl, u, k + 2, ru);
+    fetch_p(g, sl, psi, k + 1, rp);
     const T *Lm = su[(k + 2) % 3];
     const T *L0 = su[k % 3];
     const T *L1 = su[(k + 1) % 3];
@@ -458,6 +450,410 @@ __global__ __launch_bounds__(1024) void k_tile_compact(const int *__restrict__ f
   if (t == 1023) *count = off[1023];
 }
 
+
+// ------------------------------------------------- fused two-colour sweep
+//
+// One launch makes a whole Gauss-Seidel sweep (Sec. 2.3): the half-sweep of
+// the first colour A from u, then the half-sweep of the second colour B from
+// that intermediate state, each colour-synchronous (every node of a colour
+// relaxed from the state at the start of its half-sweep), as two k_rb_tile
+// launches would.  The tile marches up its chunk with B one plane behind A:
+// at step k it relaxes A on plane k from the old planes k-1..k+1, then B on
+// plane k-1 from the intermediate planes k-2..k.  B on the tile's edge nodes
+// reads A values of the edge nodes of the neighbouring tiles, so A is also
+// relaxed on the ring of nodes around the tile (the old state is held with a
+// two-node halo for that); an A value depends on the old state alone, so the
+// neighbour computes the same value bit for bit.  A chunk relaxes A on one
+// plane below and one plane above its own for the same reason.
+//
+// LDS (FP64): three old planes with the two-node halo (58.8 KB), three
+// intermediate planes with the one-node halo (47.5 KB) and four cell planes
+// (23.6 KB): 130 KB, one workgroup per CU (FP32: half, two).  Each step
+// fetches the old plane and the cell plane it stores one step later, and the
+// loads of f two steps before their use, so that about two planes of loads
+// are in flight per workgroup.  ZERO: u is zero on entry (the first sweep of
+// a V-cycle from zero); no old state is read and A is omega f / D.
+constexpr int FX = TX + 4, FY = TY + 4, FPL = FX * FY;  // old u, two-node halo
+constexpr int HX = TX + 2, HY = TY + 2, HPL = HX * HY;  // intermediate state, one-node halo
+constexpr int QX = TX + 3, QY = TY + 3, QPL = QX * QY;  // cells under the intermediate region
+constexpr int NRING = 2 * HX + 2 * TY;                  // ring nodes of the intermediate region
+constexpr int NRA = TX + TY;                            // of them colour A, corners excluded
+constexpr int FU = (3 * FPL + NT - 1) / NT;             // old-u load slots per thread
+constexpr int FQ = (QPL + NT - 1) / NT;                 // cell load slots per thread
+static_assert(NRING <= NT && NRA <= NT, "ring work needs one thread per ring node");
+
+struct FSlots {
+  int u[FU];
+  int q[FQ];
+};
+
+__device__ __forceinline__ void make_fslots(const TG &g, int x0, int y0, FSlots &s) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < FU; ++i) {
+    const int e = t + i * NT;
+    s.u[i] = -1;
+    if (e < 3 * FPL) {
+      const int c = e / FPL, r = e - c * FPL;
+      const int y = r / FX, x = r - y * FX;
+      const int gx = x0 - 2 + x, gy = y0 - 2 + y;
+      if (gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny) s.u[i] = c * g.nn + gx + g.nx * gy;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < FQ; ++i) {
+    const int e = t + i * NT;
+    s.q[i] = -1;
+    if (e < QPL) {
+      const int y = e / QX, x = e - y * QX;
+      const int gx = x0 - 2 + x, gy = y0 - 2 + y;
+      if (gx >= 0 && gx < g.cx && gy >= 0 && gy < g.cy) s.q[i] = gx + g.cx * gy;
+    }
+  }
+}
+
+// A plane of old u and a plane of cells in registers (loads in flight).
+template <typename T, bool ZERO>
+struct PlaneRegs {
+  T u[ZERO ? 1 : FU];
+  T q[FQ];
+};
+
+// Loads of old-u plane ku and cell plane kq; out-of-box entries load
+// element 0 (in range) and are replaced by zeros only when stored.
+template <typename T, bool ZERO>
+__device__ __forceinline__ void fetch_planes(const TG &g, const FSlots &s, const T *__restrict__ u,
+                                             const T *__restrict__ psi, int ku, int kq,
+                                             PlaneRegs<T, ZERO> &r) {
+  if constexpr (!ZERO) {
+    const int zo = (ku >= 0 && ku < g.nz) ? ku * g.nx * g.ny : 0;
+#pragma unroll
+    for (int i = 0; i < FU; ++i) r.u[i] = u[s.u[i] >= 0 ? s.u[i] + zo : 0];
+  }
+  const int zq = (kq >= 0 && kq < g.cz) ? kq * g.cx * g.cy : 0;
+#pragma unroll
+  for (int i = 0; i < FQ; ++i) r.q[i] = psi[s.q[i] >= 0 ? s.q[i] + zq : 0];
+}
+
+template <typename T, bool ZERO>
+__device__ __forceinline__ void store_planes(const TG &g, const FSlots &s, int ku, int kq, T *so,
+                                             T *sq, const PlaneRegs<T, ZERO> &r) {
+  if constexpr (!ZERO) {
+    const bool kin = ku >= 0 && ku < g.nz;
+#pragma unroll
+    for (int i = 0; i < FU; ++i) {
+      const int e = threadIdx.x + i * NT;
+      if (e < 3 * FPL) so[e] = (kin && s.u[i] >= 0) ? r.u[i] : T(0);
+    }
+  }
+  const bool qin = kq >= 0 && kq < g.cz;
+#pragma unroll
+  for (int i = 0; i < FQ; ++i) {
+    const int e = threadIdx.x + i * NT;
+    if (e < QPL) sq[e] = (qin && s.q[i] >= 0) ? r.q[i] : T(0);
+  }
+}
+
+// The loads of f one step needs: a = f at the thread's A node of plane k,
+// b = f at its B node of plane k-1 (the same column), r = f at the thread's
+// ring A node of plane k (threads below NRA).
+template <typename T>
+struct FRegs {
+  T a[3], b[3], r[3];
+};
+
+// Ring A node `r` (< NRA) of plane k: the ring rows first, then the ring
+// columns; corners are never needed by B.  x0 and y0 are even.  (Written
+// with selects only: branches that assign x in one arm and y in the other
+// made the compiler keep the pair in scratch memory.)
+struct XY {
+  int x, y;
+};
+__device__ __forceinline__ XY ring_a_node(int r, int x0, int y0, int k, int c0) {
+  const bool row = r < TX;
+  const bool lo = row ? r < TX / 2 : r < TX + TY / 2;
+  const int j = row ? (lo ? r : r - TX / 2) : (lo ? r - TX : r - TX - TY / 2);
+  const int fixed = row ? (lo ? y0 - 1 : y0 + TY) : (lo ? x0 - 1 : x0 + TX);
+  const int run = (row ? x0 : y0) + 2 * j + ((c0 + fixed + k) & 1);
+  return XY{row ? run : fixed, row ? fixed : run};
+}
+
+template <typename T>
+__device__ __forceinline__ void fetch_f(const TG &g, const T *__restrict__ f, int k, int x0, int y0,
+                                        int p, int gy, int c0, FRegs<T> &F) {
+  const int nxy = g.nx * g.ny;
+  const int xa = x0 + 2 * p + ((c0 + gy + k) & 1);
+  const bool col = gy < g.ny && xa < g.nx;
+  const int qa = (col && k >= 0 && k < g.nz) ? gy * g.nx + k * nxy + xa : 0;
+  const int qb = (col && k >= 1 && k <= g.nz) ? gy * g.nx + (k - 1) * nxy + xa : 0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) F.a[c] = f[c * g.nn + qa];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) F.b[c] = f[c * g.nn + qb];
+  // every thread loads (threads past NRA load element 0): with loads under a
+  // branch the compiler's wait counting must assume none were issued and
+  // waits for every older load at the next use
+  const XY n = ring_a_node(min((int)threadIdx.x, NRA - 1), x0, y0, k, c0);
+  const bool in = (int)threadIdx.x < NRA && n.x >= 0 && n.x < g.nx && n.y >= 0 && n.y < g.ny &&
+                  k >= 0 && k < g.nz;
+  const int qr = in ? n.y * g.nx + k * nxy + n.x : 0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) F.r[c] = f[c * g.nn + qr];
+}
+
+// eq. K and the diagonal at a node from LDS planes Lm / L0 / L1 (below, at,
+// above; S entries per component, row pitch W, the node at index ci) and
+// the cell planes Pm / P0 below and above it (row pitch QX, cell (i-1, j-1)
+// at index qi).
+template <typename T, int S, int W>
+__device__ __forceinline__ void lds_stencil(const Coef<T> &C, const T *Lm, const T *L0,
+                                            const T *L1, int ci, const T *Pm, const T *P0, int qi,
+                                            T out[3], T dg[3]) {
+  T P[2][2][2];
+#pragma unroll
+  for (int c1 = 0; c1 < 2; ++c1)
+#pragma unroll
+    for (int c0 = 0; c0 < 2; ++c0) {
+      P[0][c1][c0] = Pm[qi + c1 * QX + c0];
+      P[1][c1][c0] = P0[qi + c1 * QX + c0];
+    }
+  auto U = [&](int c, int dx, int dy, int dz) -> T {
+    const T *L = dz < 0 ? Lm : (dz > 0 ? L1 : L0);
+    return L[c * S + ci + dx + dy * W];
+  };
+  stencil3<T>(C, P, U, out, dg);
+}
+
+// The diagonal alone (the same sums as stencil3).
+template <typename T>
+__device__ __forceinline__ void lds_diag(const Coef<T> &C, const T *Pm, const T *P0, int qi,
+                                         T dg[3]) {
+  T P[2][2][2];
+#pragma unroll
+  for (int c1 = 0; c1 < 2; ++c1)
+#pragma unroll
+    for (int c0 = 0; c0 < 2; ++c0) {
+      P[0][c1][c0] = Pm[qi + c1 * QX + c0];
+      P[1][c1][c0] = P0[qi + c1 * QX + c0];
+    }
+  T E[3][2];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    E[0][s] = P[0][0][s] + P[0][1][s] + P[1][0][s] + P[1][1][s];
+    E[1][s] = P[0][s][0] + P[0][s][1] + P[1][s][0] + P[1][s][1];
+    E[2][s] = P[s][0][0] + P[s][0][1] + P[s][1][0] + P[s][1][1];
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+    dg[c] = C.cd[c][0] * (E[0][0] + E[0][1]) + C.cd[c][1] * (E[1][0] + E[1][1]) +
+            C.cd[c][2] * (E[2][0] + E[2][1]);
+}
+
+template <typename T, bool ZERO>
+__global__ __launch_bounds__(NT) void k_rb_fused(TG g, Coef<T> C, const T *__restrict__ psi,
+                                                 const T *__restrict__ u, const T *__restrict__ f,
+                                                 T *__restrict__ u_out, T omega, int c0,
+                                                 TileGeom tg) {
+  __shared__ T so[ZERO ? 1 : 3][ZERO ? 1 : 3 * FPL];  // old u, planes k-1, k, k+1
+  __shared__ T sa[3][3 * HPL];                         // intermediate, planes k-2, k-1, k
+  __shared__ T sq[4][QPL];                             // cells, planes k-2 .. k+1
+  const int nwg = gridDim.x;  // a multiple of 8
+  const int b = blockIdx.x;
+  const int li = (b & 7) * (nwg >> 3) + (b >> 3);
+  if (li >= tg.ntiles) return;
+  const int tx = li % tg.ntx;
+  const int rest = li / tg.ntx;
+  const int ty = rest % tg.nty;
+  const int tz = rest / tg.nty;
+  const int x0 = tx * TX, y0 = ty * TY;
+  const int k0 = tz * tg.kz;
+  const int k1 = min(k0 + tg.kz, g.nz);
+  const int nn = g.nn, nxy = g.nx * g.ny;
+  const int t = threadIdx.x;
+  const int yl = t / (TX / 2), p = t % (TX / 2);
+  const int gy = y0 + yl;
+  const bool row_ok = gy < g.ny;
+  // ring slots: the planes k-2..k+1 live at k mod 3 (u, intermediate) and
+  // k mod 4 (cells); k >= -2 here
+  auto s3 = [](int k) { return (k + 6) % 3; };
+  auto s4 = [](int k) { return (k + 8) & 3; };
+
+  FSlots sl;
+  make_fslots(g, x0, y0, sl);
+
+  // f of the first two steps, then the prologue planes: old u k0-2..k0 and
+  // cells k0-2, k0-1 straight to LDS, old u k0+1 and cells k0 in registers
+  // (stored during the first step)
+  FRegs<T> FA, FB;
+  fetch_f(g, f, k0 - 1, x0, y0, p, gy, c0, FA);
+  fetch_f(g, f, k0, x0, y0, p, gy, c0, FB);
+  PlaneRegs<T, ZERO> RA, RB;
+  {
+    PlaneRegs<T, ZERO> r0, r1, r2;
+    fetch_planes<T, ZERO>(g, sl, u, psi, k0 - 2, k0 - 2, r0);
+    fetch_planes<T, ZERO>(g, sl, u, psi, k0 - 1, k0 - 1, r1);
+    fetch_planes<T, ZERO>(g, sl, u, psi, k0, k0, r2);
+    fetch_planes<T, ZERO>(g, sl, u, psi, k0 + 1, k0, RB);
+    store_planes<T, ZERO>(g, sl, k0 - 2, k0 - 2, so[ZERO ? 0 : s3(k0 - 2)], sq[s4(k0 - 2)], r0);
+    store_planes<T, ZERO>(g, sl, k0 - 1, k0 - 1, so[ZERO ? 0 : s3(k0 - 1)], sq[s4(k0 - 1)], r1);
+    store_planes<T, ZERO>(g, sl, k0, k0, so[ZERO ? 0 : s3(k0)], sq[s4(k0)], r2);
+  }
+  __syncthreads();
+
+  // One step: A on plane k (interior and ring), then B on plane k-1 with the
+  // store of the planes fetched a step earlier (`st`), while `is` receives the
+  // next ones; `fr` holds this step's f and receives the f of step k+2.
+  auto step = [&](int k, PlaneRegs<T, ZERO> &is, PlaneRegs<T, ZERO> &st,
+                  FRegs<T> &fr) __attribute__((always_inline)) {
+    T fa[3], fb[3], frr[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      fa[c] = fr.a[c];
+      fb[c] = fr.b[c];
+      frr[c] = fr.r[c];
+    }
+    // unconditional (planes past the chunk load in-range dummies): the loads
+    // of a step are then always the same, and the waits for them exact
+    fetch_f(g, f, k + 2, x0, y0, p, gy, c0, fr);
+    fetch_planes<T, ZERO>(g, sl, u, psi, k + 3, k + 2, is);
+
+    // ---- A on plane k -> sa[k]
+    T *H = sa[s3(k)];
+    const int par = (c0 + gy + k) & 1;
+    const int xa = 2 * p + par, xb = 2 * p + 1 - par;  // tile-local columns
+    if (k >= 0 && k < g.nz) {
+      const T *Om = so[ZERO ? 0 : s3(k - 1)], *O0 = so[ZERO ? 0 : s3(k)],
+              *O1 = so[ZERO ? 0 : s3(k + 1)];
+      const T *Qm = sq[s4(k - 1)], *Q0 = sq[s4(k)];
+      auto relax_a = [&](int gx, int gyy, const T *fv, T va[3]) __attribute__((always_inline)) {
+        const int lx = gx - x0 + 2, ly = gyy - y0 + 2;
+        const int qi = (ly - 1) * QX + lx - 1;
+        const bool face = gx == 0 || gx == g.nx - 1 || gyy == 0 || gyy == g.ny - 1 || k == 0 ||
+                          k == g.nz - 1;
+        T out[3], dg[3];
+        if constexpr (ZERO) {
+          lds_diag<T>(C, Qm, Q0, qi, dg);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const T upd = T(0) + omega * (fv[c] - T(0)) / dg[c];
+            va[c] = (face && tg_dirichlet(g, gx, gyy, k, c)) ? T(0) : upd;
+          }
+        } else {
+          const int ci = ly * FX + lx;
+          lds_stencil<T, FPL, FX>(C, Om, O0, O1, ci, Qm, Q0, qi, out, dg);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const T uc = O0[c * FPL + ci];
+            const T upd = uc + omega * (fv[c] - out[c]) / dg[c];
+            va[c] = (face && tg_dirichlet(g, gx, gyy, k, c)) ? uc : upd;
+          }
+        }
+      };
+      // interior pair: A relaxed, B copied (zeros outside the box)
+      {
+        const int gxa = x0 + xa, gxb = x0 + xb;
+        T va[3] = {T(0), T(0), T(0)};
+        if (row_ok && gxa < g.nx) relax_a(gxa, gy, fa, va);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          H[c * HPL + (yl + 1) * HX + xa + 1] = va[c];
+          T vb = T(0);
+          if constexpr (!ZERO) vb = O0[c * FPL + (yl + 2) * FX + xb + 2];
+          H[c * HPL + (yl + 1) * HX + xb + 1] = (row_ok && gxb < g.nx) ? vb : T(0);
+        }
+      }
+      // ring: B nodes and corners copied, nodes outside the box zeroed
+      if (t < NRING) {
+        const bool row = t < 2 * HX;
+        const bool lo = row ? t < HX : t < 2 * HX + TY;
+        const int j = row ? (lo ? t : t - HX) : (lo ? t - 2 * HX : t - 2 * HX - TY);
+        const int fixed = row ? (lo ? y0 - 1 : y0 + TY) : (lo ? x0 - 1 : x0 + TX);
+        const int run = row ? x0 - 1 + j : y0 + j;
+        const int x = row ? run : fixed, y = row ? fixed : run;
+        const bool in = x >= 0 && x < g.nx && y >= 0 && y < g.ny;
+        const bool corner = t == 0 || t == HX - 1 || t == HX || t == 2 * HX - 1;
+        const bool isa = ((x + y + k) & 1) == c0;
+        const int hi = (y - y0 + 1) * HX + (x - x0 + 1);
+        if (!in) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) H[c * HPL + hi] = T(0);
+        } else if (!isa || corner) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            T v = T(0);
+            if constexpr (!ZERO) v = O0[c * FPL + (y - y0 + 2) * FX + (x - x0 + 2)];
+            H[c * HPL + hi] = v;
+          }
+        }
+      }
+      // ring A nodes inside the box
+      if (t < NRA) {
+        const XY n = ring_a_node(t, x0, y0, k, c0);
+        const int x = n.x, y = n.y;
+        if (x >= 0 && x < g.nx && y >= 0 && y < g.ny) {
+          T va[3];
+          relax_a(x, y, frr, va);
+          const int hi = (y - y0 + 1) * HX + (x - x0 + 1);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) H[c * HPL + hi] = va[c];
+        }
+      }
+    } else {
+      // a plane outside the box: zeros
+      for (int e = t; e < 3 * HPL; e += NT) H[e] = T(0);
+    }
+    __syncthreads();
+
+    // the planes fetched a step earlier (old u k+2, cells k+1) go to the slots
+    // round A has just released, before any store to global memory (so that
+    // waiting for them never waits for a store)
+    store_planes<T, ZERO>(g, sl, k + 2, k + 1, so[ZERO ? 0 : s3(k + 2)], sq[s4(k + 1)], st);
+
+    // ---- B on plane k-1 (this chunk's planes only) and the output of plane k-1
+    if (k - 1 >= k0) {
+      const int kb = k - 1;
+      const T *Hm = sa[s3(k - 2)], *H0 = sa[s3(k - 1)], *H1 = sa[s3(k)];
+      const T *Qm = sq[s4(k - 2)], *Q0 = sq[s4(k - 1)];
+      if (row_ok) {
+        const int gxb = x0 + xa;       // B node of plane k-1: the column of A on plane k
+        const int gxo = x0 + xb;       // A node of plane k-1 (relaxed at the previous step)
+        const int row = gy * g.nx + kb * nxy;
+        T vb[3] = {T(0), T(0), T(0)};
+        if (gxb < g.nx) {
+          const int lx = xa + 1, ly = yl + 1;
+          const int ci = ly * HX + lx;
+          const int qi = ly * QX + lx;  // cell (i-1, j-1): rows/columns shifted by one
+          T out[3], dg[3];
+          lds_stencil<T, HPL, HX>(C, Hm, H0, H1, ci, Qm, Q0, qi, out, dg);
+          const bool face = gxb == 0 || gxb == g.nx - 1 || gy == 0 || gy == g.ny - 1 ||
+                            kb == 0 || kb == g.nz - 1;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const T uc = H0[c * HPL + ci];
+            const T upd = uc + omega * (fb[c] - out[c]) / dg[c];
+            vb[c] = (face && tg_dirichlet(g, gxb, gy, kb, c)) ? uc : upd;
+          }
+        }
+        // both nodes of the pair back to back (complete lines)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const T aval = H0[c * HPL + (yl + 1) * HX + xb + 1];
+          if (gxb < g.nx) u_out[c * nn + row + gxb] = vb[c];
+          if (gxo < g.nx) u_out[c * nn + row + gxo] = aval;
+        }
+      }
+    }
+    __syncthreads();
+  };
+
+  int k = k0 - 1;
+  for (; k + 1 <= k1; k += 2) {
+    step(k, RA, RB, FA);
+    step(k + 1, RB, RA, FB);
+  }
+  if (k <= k1) step(k, RA, RB, FA);
+}
+
 }  // namespace
 
 hipError_t launch_active_tiles(const Level &L, const uint8_t *cls, int *flags, int *ids,
@@ -472,9 +868,6 @@ hipError_t launch_active_tiles(const Level &L, const uint8_t *cls, int *flags, i
 }
 
 bool tiled_ok(const Level &L) {
-#ifdef SBM_TILE_DISABLE
-  return false;
-#endif
   // measured: 1.5x faster than the pair kernel at 257^3 nodes; at 129^3 the
   // vectors stay in the Infinity Cache and the pair kernel is as fast
   return L.g.dim == 3 && L.g.nx > 3 * TX && L.g.ny > 3 * TY;
@@ -501,6 +894,29 @@ hipError_t launch_rb_tiled(const Level &L, const T *psi, const Coef<T> &C, const
                        u_out, (T)omega, colour, tg, cls, ids, n);
   return hipGetLastError();
 }
+
+template <typename T>
+hipError_t launch_rb_fused(const Level &L, const T *psi, const Coef<T> &C, const T *u, const T *f,
+                           T *u_out, double omega, int first_colour, hipStream_t st) {
+  const TG gg = make_tg(L.g);
+  const TileGeom tg = tile_geom(gg);
+  const int grid = (tg.ntiles + 7) / 8 * 8;
+  (void)hipGetLastError();
+  if (u)
+    hipLaunchKernelGGL((k_rb_fused<T, false>), dim3(grid), dim3(NT), 0, st, gg, C, psi, u, f,
+                       u_out, (T)omega, first_colour, tg);
+  else
+    hipLaunchKernelGGL((k_rb_fused<T, true>), dim3(grid), dim3(NT), 0, st, gg, C, psi, u, f,
+                       u_out, (T)omega, first_colour, tg);
+  return hipGetLastError();
+}
+
+template hipError_t launch_rb_fused<double>(const Level &, const double *, const Coef<double> &,
+                                            const double *, const double *, double *, double, int,
+                                            hipStream_t);
+template hipError_t launch_rb_fused<float>(const Level &, const float *, const Coef<float> &,
+                                           const float *, const float *, float *, double, int,
+                                           hipStream_t);
 
 int tiled_partials(const Level &L) { return tile_geom(make_tg(L.g)).ntiles; }
 

@@ -345,6 +345,18 @@ class Solver:
                                      _ptr(f_t), _ptr(out)))
         return out
 
+    def level_sweep(self, level, first_colour, omega, u, f, fp32=False):
+        """One two-colour Gauss-Seidel sweep on `level` (u None: a zero iterate)."""
+        dt = torch.float32 if fp32 else torch.float64
+        shp = (self.dim,) + tuple(n + 1 for n in reversed(self.level_shape(level)))
+        f_t = self._dev(f, dtype=dt, shape=shp)
+        u_t = None if u is None else self._dev(u, dtype=dt, shape=shp)
+        out = torch.empty_like(f_t)
+        fn = lib().sbm_level_sweep_f32 if fp32 else lib().sbm_level_sweep
+        check(fn(self._ctx, int(level), int(first_colour), float(omega),
+                 None if u_t is None else _ptr(u_t), _ptr(f_t), _ptr(out)))
+        return out
+
     def level_residual(self, level, u, f):
         u_t, f_t = self._dev(u), self._dev(f)
         out = torch.empty_like(u_t)
@@ -369,3 +381,17 @@ class Solver:
         it = ctypes.c_int(0)
         check(lib().sbm_bottom_solve(self._ctx, _ptr(f_t), _ptr(x), ctypes.byref(it)))
         return x, it.value
+
+
+def stream_triad(a, b, c, s):
+    """a = b + s c on device float64 tensors through the library's bandwidth
+    probe kernel, enqueued on the current stream."""
+    for t in (a, b, c):
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("stream_triad needs contiguous float64 device tensors")
+    if not (a.numel() == b.numel() == c.numel()):
+        raise ValueError("stream_triad arrays differ in size")
+    st = torch.cuda.current_stream(a.device)
+    check(lib().sbm_stream_triad(_ptr(a), _ptr(b), _ptr(c), a.numel(), float(s),
+                                 ctypes.c_void_p(st.cuda_stream)))
+

@@ -361,12 +361,14 @@ def pf_mode1_2d(n: int = 4096, L: float = 0.02, notch: float = 1.5e-4, xi: float
     """The Mode-I phase-field fracture specimen (Sec. 3.2) on a uniform grid:
     the square [-L/2, L/2]^2 with n x n cells, lambda = 121.15e9, mu =
     80.77e9 (Pa), a notch of length ``notch`` along y = 0 from the centre of
-    the left edge.  The initial crack field is c = 1 - exp(-d / xi), d the
-    distance of the cell centre to the notch segment; the indicator is
-    psi = g(c) + eta, g(c) = 4c^3 - 3c^4, eta = 1e-4 (``psi_raw``).  Bottom
-    edge clamped, y-displacement ``uy`` prescribed on the top edge (x free),
-    left and right edges traction free.  ``extra`` holds c0 and the
-    Ginzburg-Landau parameters Gc = 2700, xi, M = 1e-5, dt = 1e-4, eta."""
+    the left edge.  The initial crack field is c0 = 1 - exp(-d / xi), d the
+    distance of the cell centre to the notch segment.  The indicator the solve
+    needs, psi = g(c0) + eta, is NOT formed here (``psi_raw`` is None): it is
+    model arithmetic, so each path computes it with its own degradation
+    function (its crack step with dt = 0).  Bottom edge clamped,
+    y-displacement ``uy`` prescribed on the top edge (x free), left and right
+    edges traction free.  ``extra`` holds c0 and the Ginzburg-Landau
+    parameters Gc = 2700, xi, M = 1e-5, dt = 1e-4, eta = 1e-4."""
     h = L / n
     X, Y = cell_centres((n, n), (h, h))
     X, Y = X - 0.5 * L, Y - 0.5 * L
@@ -375,11 +377,10 @@ def pf_mode1_2d(n: int = 4096, L: float = 0.02, notch: float = 1.5e-4, xi: float
     d = np.sqrt(dx * dx + Y * Y)
     c0 = 1.0 - np.exp(-d / xi)
     eta = 1e-4
-    psi = 4.0 * c0 ** 3 - 3.0 * c0 ** 4 + eta
     kind, val = _bc_table()
     kind[2, :] = DISPLACEMENT
     kind[3, 1] = DISPLACEMENT
     val[3, 1] = uy
-    return Problem("pf_mode1_2d", (n, n), (h, h), 121.15e9, 80.77e9, floor, psi, kind, val,
+    return Problem("pf_mode1_2d", (n, n), (h, h), 121.15e9, 80.77e9, floor, None, kind, val,
                    extra={"c0": c0, "Gc": 2700.0, "xi": xi, "M": 1e-5, "dt": 1e-4, "eta": eta,
                           "notch": notch, "uy": uy})

@@ -88,9 +88,29 @@ def _mode1():
     return si.pf_mode1_2d(n, L=L, notch=0.25 * L, xi=2.0 * L / n, uy=1.5e-5)
 
 
+def _oracle_initial_psi(p):
+    """psi = g(c0) + eta from the oracle's own crack step with dt = 0."""
+    e = p.extra
+    z = np.zeros_like(e["c0"])
+    c, psi = oracle.phase_step(p.ncell, p.h, e["c0"], z, z.astype(np.uint8), e["Gc"], e["xi"],
+                               e["M"], 0.0, e["eta"])
+    assert np.array_equal(c, e["c0"])
+    return psi
+
+
+def _gpu_initial_psi(S, p):
+    """psi = g(c0) + eta from the library's crack step with dt = 0."""
+    e = p.extra
+    c = torch.tensor(e["c0"], device="cuda")
+    z = torch.zeros_like(c)
+    c1, psi = S.phase_step(c, z, z.to(torch.uint8), e["Gc"], e["xi"], e["M"], 0.0, e["eta"])
+    assert torch.equal(c1, c)
+    return psi
+
+
 def _stagger_oracle(p, nstep):
     e = p.extra
-    c, H, psi, u = e["c0"].copy(), np.zeros_like(e["c0"]), p.psi_raw, None
+    c, H, psi, u = e["c0"].copy(), np.zeros_like(e["c0"]), _oracle_initial_psi(p), None
     small = []
     for _ in range(nstep):
         u, hist, st = oracle.solve(p.ncell, p.h, p.lam, p.mu, psi, p.psi_floor, p.kind, p.val,
@@ -115,7 +135,7 @@ def test_staggered_mode1_sequence():
     S = Solver(p.ncell, p.h)
     c = torch.tensor(e["c0"], device="cuda")
     H = torch.zeros_like(c)
-    psi = torch.tensor(p.psi_raw, device="cuda")
+    psi = _gpu_initial_psi(S, p)
     u = None
     small = []
     for k in range(nstep):

@@ -37,11 +37,20 @@ def test_fracture_4096():
     e = p.extra
     S = Solver(p.ncell, p.h, krylov=1, rtol=1e-10, max_cycles=400)
     say("full size fracture solve")
-    S.set_problem(p.psi_raw, p.lam, p.mu, p.psi_floor, p.kind, p.val)
+    # the initial indicator psi = g(c0) + eta, each side from its own crack
+    # step with dt = 0
+    c0 = torch.tensor(e["c0"], device="cuda")
+    z = torch.zeros_like(c0)
+    _, psi0 = S.phase_step(c0, z, z.to(torch.uint8), e["Gc"], e["xi"], e["M"], 0.0, e["eta"])
+    zh = np.zeros_like(e["c0"])
+    _, psi0_ref = oracle.phase_step(p.ncell, p.h, e["c0"], zh, zh.astype(np.uint8), e["Gc"],
+                                    e["xi"], e["M"], 0.0, e["eta"])
+    assert rel_max(to_np(psi0), psi0_ref) < 1e-14
+    S.set_problem(psi0, p.lam, p.mu, p.psi_floor, p.kind, p.val)
     u, hist, st = S.solve()
     assert st == 0
     u_h = to_np(u)
-    assert _oracle_rel_residual(p, p.psi_raw, u_h) < 1.1e-10
+    assert _oracle_rel_residual(p, psi0_ref, u_h) < 1.1e-10
     rng = np.random.default_rng(0)
     H0 = rng.uniform(0.0, 2.0 * e["Gc"] / (2.0 * e["xi"]), e["c0"].shape)
     say("full size crack drive / step")

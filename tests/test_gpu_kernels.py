@@ -10,7 +10,7 @@ import torch
 
 import oracle
 import sbm_inputs as si
-from _util import random_problem, rel_max, say, solver_for, to_np
+from _util import random_problem, rel_l2, rel_max, say, solver_for, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -99,6 +99,36 @@ def test_tiled_half_sweep(ncell):
         idx = np.indices(p.node_shape).sum(0) % 2
         other = np.broadcast_to(idx != colour, got.shape)
         assert np.array_equal(got[other], u[other])
+
+
+@pytest.mark.parametrize("ncell", [(200, 30, 12), (230, 25, 9), (256, 33, 6), (256, 20, 40)])
+def test_fused_two_colour_sweep(ncell):
+    """A whole Gauss-Seidel sweep in one launch (levels wider than 192 nodes):
+    equal to the oracle's half-sweep of the first colour followed by the
+    half-sweep of the second, for both colour orders, from a given iterate and
+    from zero; several tiles, ragged last tiles in x and y, several z chunks
+    (40 planes make ten).  The FP32 sweep is held to the FP32 bar against the
+    FP64 oracle on the same (FP32-representable) inputs."""
+    p, S, psi, mask, u, f = _setup(ncell, seed=13)
+    u = np.where(mask == 1, oracle.dirichlet(p.ncell, p.kind, p.val)[1], u)
+    half = lambda c, v: oracle.rb_half(p.ncell, p.h, p.lam, p.mu, psi, mask, 1.0, c, v, f)  # noqa: E731
+    for c0 in (0, 1):
+        say("fused sweep", ncell, c0)
+        ref = half(1 - c0, half(c0, u))
+        got = to_np(S.level_sweep(0, c0, 1.0, u, f))
+        assert rel_max(got, ref) < 1e-13
+        say("fused sweep from zero", ncell, c0)
+        z = np.zeros_like(u)
+        ref0 = half(1 - c0, half(c0, z))
+        got0 = to_np(S.level_sweep(0, c0, 1.0, None, f))
+        assert rel_max(got0, ref0) < 1e-13
+    u32, f32 = u.astype(np.float32), f.astype(np.float32)
+    u64, f64 = u32.astype(np.float64), f32.astype(np.float64)
+    half64 = lambda c, v: oracle.rb_half(p.ncell, p.h, p.lam, p.mu, psi, mask, 1.0, c, v, f64)  # noqa: E731
+    say("fused sweep fp32", ncell)
+    ref = half64(1, half64(0, u64))
+    got = to_np(S.level_sweep(0, 0, 1.0, u32, f32, fp32=True)).astype(np.float64)
+    assert rel_l2(got, ref) < 1e-5
 
 
 @pytest.mark.parametrize("ncell", [(200, 30, 12), (256, 33, 6)])

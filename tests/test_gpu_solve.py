@@ -72,14 +72,17 @@ def test_krylov_trajectory_parity(case, smoother):
     assert rel_l2(u_g, u_o) <= 1e-9, rel_l2(u_g, u_o)
 
 
+@pytest.mark.parametrize("fused", [0, 1])
 @pytest.mark.parametrize("krylov", [0, 1])
-def test_wide_grid_first_iterations(krylov):
-    """209 x 33 x 17 nodes: the finest level takes the LDS-tiled half-sweep,
-    residual and (Krylov) Apply; the first iterations follow the oracle's."""
+def test_wide_grid_first_iterations(krylov, fused):
+    """209 x 33 x 17 nodes: the finest level takes the LDS-tiled half-sweep
+    (or, with fused_sweep, the one-launch two-colour sweep, also from zero in
+    the preconditioner), residual and (Krylov) Apply; the first iterations
+    follow the oracle's."""
     p = random_problem((208, 32, 16), seed=6, floor=1e-3)
-    say("wide grid", krylov)
+    say("wide grid", krylov, fused)
     u_o, hist_o, _ = oracle_solve(p, rtol=0.0, max_cycles=5, krylov=krylov)
-    S = solver_for(p, rtol=0.0, max_cycles=5, krylov=krylov)
+    S = solver_for(p, rtol=0.0, max_cycles=5, krylov=krylov, fused_sweep=fused)
     u_g, hist_g, _ = S.solve()
     assert len(hist_g) == len(hist_o) == 6
     dh = np.abs(hist_g - hist_o)
@@ -103,6 +106,29 @@ def test_mixed_precision_converges_to_fp64_solution(case):
         print(f"[mixed] {case} krylov {krylov}: iterations {len(hist_g) - 1} (fp64 oracle "
               f"{len(hist_o) - 1}), rel L2 error vs FP64 oracle {err:.3e}")
         assert err <= 1e-7
+
+
+@pytest.mark.parametrize("fused", [0, 1])
+def test_wide_grid_trajectory_to_tolerance(fused):
+    """The wide grid solved to 1e-10 by preconditioned CG in exactly the
+    oracle's iteration count m*, FP64 (half-sweeps or fused sweeps), and the
+    mixed solve to the same tolerance within 1e-7 of the FP64 oracle."""
+    p = random_problem((208, 32, 16), seed=8, floor=1e-3)
+    say("wide grid to tolerance", fused)
+    u_o, hist_o, st_o = oracle_solve(p, rtol=1e-10, max_cycles=400, krylov=1)
+    assert st_o == 0
+    m = len(hist_o) - 1
+    S = solver_for(p, rtol=0.0, max_cycles=m, krylov=1, fused_sweep=fused)
+    u_g, hist_g, _ = S.solve()
+    assert len(hist_g) == m + 1
+    dh = np.abs(hist_g - hist_o)
+    assert np.all(dh <= 1e-6 * hist_o + RHO_ATOL), dh.max()
+    assert rel_l2(to_np(u_g), u_o) <= 1e-9, rel_l2(to_np(u_g), u_o)
+    say("wide grid mixed", fused)
+    Sm = solver_for(p, precision=1, rtol=1e-10, max_cycles=400, krylov=1, fused_sweep=fused)
+    u_m, hist_m, st_m = Sm.solve()
+    assert st_m == 0 and hist_m[-1] <= 1e-10
+    assert rel_l2(to_np(u_m), u_o) <= 1e-7, rel_l2(to_np(u_m), u_o)
 
 
 def test_warm_start_and_history():
