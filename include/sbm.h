@@ -191,6 +191,24 @@ sbm_status sbm_residual(sbm_ctx *ctx, const double *u, double *r, double *norm_h
  * the residual.  Async. */
 sbm_status sbm_rhs(sbm_ctx *ctx, double *fA, double *fB);
 
+/* sbm_residual without a context or workspace, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): r = f - K u on free DOF, 0 on
+ * displacement DOF (r may be NULL), and *norm_host = ||r||_2 over the free
+ * DOF.  K is eq. K on the grid with the material's Lame constants and the
+ * displacement faces of bc (bc values are not used: u carries them); psi is
+ * the floored cell indicator (cells, finite, >= 0; not checked), u and f
+ * node vectors; all device arrays.  The residual partial sums live in a
+ * file-scope device array of 2^17 doubles (1 MiB per device, held until the
+ * process ends), so grids needing more than 2^17 - 1 partial sums (about
+ * 33 M nodes) are rejected with SBM_E_SHAPE.  Nothing is allocated: no
+ * hipMalloc, no workspace.  Calls that overlap on one device (other host
+ * threads, other streams) share that array and race.  Synchronises
+ * hip_stream (NULL: the null stream). */
+sbm_status sbm_residual_static(const sbm_grid *grid, const sbm_material *mat, const sbm_bc *bc,
+                               const double *psi, const double *u, const double *f, double *r,
+                               double *norm_host, void *hip_stream);
+
 /* Adjoint sensitivity per cell: g_c = -lam_c^T K_c u_c + lam^T df/dpsi_c,
  * where K = sum_c psi_c K_c and f depends on psi through the traction source.
  * This is dL/dpsi for L(u(psi)) with K lam = dL/du.  u: node vector carrying

@@ -83,6 +83,8 @@ SIGNATURES = {
     "sbm_phase_step": (ctypes.c_int, [_P, _P, _P, _P, ctypes.POINTER(SbmPf), _P, _P]),
     "sbm_profile": (ctypes.c_int, [_P, ctypes.c_int]),
     "sbm_graph_info": (ctypes.c_int, [_P, _I64P, _I64P]),
+    "sbm_residual_static": (ctypes.c_int, [ctypes.POINTER(SbmGrid), ctypes.POINTER(SbmMaterial),
+                                           ctypes.POINTER(SbmBc), _P, _P, _P, _P, _DP, _P]),
     "sbm_stream_triad": (ctypes.c_int, [_P, _P, _P, ctypes.c_int64, ctypes.c_double, _P]),
     "sbm_profile_read": (ctypes.c_int, [_P, _DP, _I64P]),
     "sbm_destroy": (None, [_P]),

@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <initializer_list>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -963,6 +964,77 @@ sbm_status sbm_profile(sbm_ctx *c, int enable) {
     c->prof_n[k] = 0;
   }
   c->prof_on = enable != 0;
+  return SBM_OK;
+}
+
+// -------------------------------------------- allocation-free residual
+//
+// sbm_residual_static keeps its partial sums in this file-scope device array
+// (one copy per device, for the life of the process) instead of a workspace.
+// Host code never passes `scratch` itself to a kernel: its device address is
+// looked up once per device with hipGetSymbolAddress and kept in
+// g_scratch_dev.
+constexpr int kScratchDoubles = 1 << 17;  // 1 MiB: partial sums + the total
+__device__ __align__(256) double scratch[kScratchDoubles];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_dev[kMaxDevices] = {};
+
+static sbm_status scratch_address(double **out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(SBM_E_ARG, "device id out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void *p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(SBM_E_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_dev[dev] = (double *)p;
+  }
+  *out = g_scratch_dev[dev];
+  return SBM_OK;
+}
+
+sbm_status sbm_residual_static(const sbm_grid *grid, const sbm_material *mat, const sbm_bc *bc,
+                               const double *psi, const double *u, const double *f, double *r,
+                               double *norm_host, void *hip_stream) {
+  if (!grid_ok(grid)) return fail(SBM_E_SHAPE, "unsupported grid");
+  if (!mat || !bc || !psi || !u || !f || !norm_host) return fail(SBM_E_ARG, "NULL argument");
+  NO_ALIAS(u, r);
+  NO_ALIAS(f, r);
+  NO_ALIAS(psi, r);
+  if (!isfinite(mat->lambda) || !isfinite(mat->mu) || !(mat->mu > 0.0) ||
+      !(mat->lambda + mat->mu > 0.0))
+    return fail(SBM_E_ARG, "material needs mu > 0, lambda + mu > 0");
+  uint32_t dmask = 0;
+  for (int F = 0; F < 2 * grid->dim; ++F)
+    for (int k = 0; k < grid->dim; ++k) {
+      if (bc->kind[F][k] != SBM_TRACTION && bc->kind[F][k] != SBM_DISPLACEMENT)
+        return fail(SBM_E_ARG, "bc kind must be TRACTION or DISPLACEMENT");
+      if (bc->kind[F][k] == SBM_DISPLACEMENT) dmask |= 1u << (3 * F + k);
+    }
+  Level L;
+  make_level(grid->dim, grid->ncell, grid->h, L);
+  L.g.dmask = dmask;
+  set_coefs(L, mat->lambda, mat->mu, grid->dim);
+  const int np = stencil_partials(L);
+  if (np > kScratchDoubles - 1)
+    return fail(SBM_E_SHAPE, "grid too large for the static scratch of sbm_residual_static (" +
+                                 std::to_string(np) + " partial sums, at most " +
+                                 std::to_string(kScratchDoubles - 1) + ")");
+  double *sc = nullptr;
+  sbm_status s = scratch_address(&sc);
+  if (s != SBM_OK) return s;
+  hipStream_t st = (hipStream_t)hip_stream;
+  // every partial sum and the total are written before they are read: the
+  // array needs no clearing between calls
+  HIP_TRY((launch_residual<double>(L, psi, L.c64, u, f, r, sc, st)));
+  HIP_TRY(launch_finalize_sum(sc, np, sc + kScratchDoubles - 1, st));
+  double ss = 0.0;
+  HIP_TRY(hipMemcpyAsync(&ss, sc + kScratchDoubles - 1, sizeof(double), hipMemcpyDeviceToHost,
+                         st));
+  HIP_TRY(hipStreamSynchronize(st));
+  *norm_host = sqrt(ss);
   return SBM_OK;
 }
 

@@ -395,3 +395,36 @@ def stream_triad(a, b, c, s):
     check(lib().sbm_stream_triad(_ptr(a), _ptr(b), _ptr(c), a.numel(), float(s),
                                  ctypes.c_void_p(st.cuda_stream)))
 
+
+def residual_static(ncell, h, lam, mu, kind, psi, u, f, want_r=True):
+    """r = f - K u on free DOF and ||r|| without a solver context (the
+    library's allocation-free entry point): psi the floored cell indicator,
+    u and f node tensors on the current device; returns (r or None, norm)."""
+    d = len(ncell)
+    g = SbmGrid()
+    g.dim = d
+    for a in range(3):
+        g.ncell[a] = int(ncell[a]) if a < d else 0
+        g.h[a] = float(h[a]) if a < d else 1.0
+    kind = np.asarray(kind).reshape(6, 3)
+    bc = SbmBc()
+    for F in range(6):
+        for k in range(3):
+            bc.kind[F][k] = int(kind[F, k])
+    m = SbmMaterial(float(lam), float(mu), 0.0)
+    node = (d,) + tuple(int(n) + 1 for n in reversed(ncell))
+    cell = tuple(int(n) for n in reversed(ncell))
+    ts = []
+    for t, shp in ((psi, cell), (u, node), (f, node)):
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or \
+                tuple(t.shape) != shp:
+            raise ValueError(f"expected a contiguous float64 device tensor of shape {shp}")
+        ts.append(t)
+    r = torch.empty_like(u) if want_r else None
+    nrm = ctypes.c_double(0.0)
+    st = torch.cuda.current_stream(u.device)
+    check(lib().sbm_residual_static(ctypes.byref(g), ctypes.byref(m), ctypes.byref(bc),
+                                    _ptr(ts[0]), _ptr(ts[1]), _ptr(ts[2]), _ptr(r),
+                                    ctypes.byref(nrm), ctypes.c_void_p(st.cuda_stream)))
+    return r, nrm.value
+
