@@ -286,24 +286,29 @@ def _quat_rot(q):
 
 
 def ellipsoidal_voids_amr(base: int = 64, levels: int = 3, block: int = 32, seed: int = 0,
-                          nvoid: int = 10, floor: float = 1e-5):
+                          nvoid: int = 10, floor: float = 1e-5, shape=None):
     """Unit cube with seeded ellipsoidal voids for the adaptive solve: centres
     U[0,1]^3, then semi-axes U[0.04,0.12] (nvoid x 3), then orientations from
     unit quaternions drawn from N(0, I4).  The indicator is the product of
     0.5 (1 + tanh(d / (2 h_f))) with d = (q - 1)/|grad q|, q = |A^-1 R^T (x - c)|
     and h_f the finest spacing, sampled at the cell centres of every level
     (level a: base * 2^a cells per axis).  z=0 clamped, u=(0,0,1e-3) on z=1.
+    ``shape`` (cells per axis x, y, z of the base level) makes the box
+    shape[a] / base long along axis a, with the same spacing 1 / base and
+    the centres scaled to the box (the same draws).
     Returns (Problem of the base level, list of per-level raw psi)."""
     rng = np.random.default_rng(seed)
     centres = rng.uniform(0.0, 1.0, (nvoid, 3))
     axes = rng.uniform(0.04, 0.12, (nvoid, 3))
     quats = rng.standard_normal((nvoid, 4))
+    shape = (base, base, base) if shape is None else tuple(int(n) for n in shape)
+    centres = centres * (np.asarray(shape, np.float64) / base)
     hf = 1.0 / (base << (levels - 1))
     psis = []
     for a in range(levels):
-        n = base << a
-        h = 1.0 / n
-        X, Y, Z = cell_centres((n, n, n), (h, h, h))
+        ns = tuple(n << a for n in shape)
+        h = 1.0 / (base << a)
+        X, Y, Z = cell_centres(ns, (h, h, h))
         psi = np.ones_like(X)
         for c, ax, q in zip(centres, axes, quats):
             M = np.diag(1.0 / ax) @ _quat_rot(q).T
@@ -326,7 +331,7 @@ def ellipsoidal_voids_amr(base: int = 64, levels: int = 3, block: int = 32, seed
     val[5, 2] = 1e-3
     lam, mu = lame(1.0, 0.3)
     h0 = 1.0 / base
-    p = Problem("ellipsoidal_voids_amr", (base, base, base), (h0, h0, h0), lam, mu, floor, psis[0],
+    p = Problem("ellipsoidal_voids_amr", shape, (h0, h0, h0), lam, mu, floor, psis[0],
                 kind, val, extra={"levels": levels, "block": block, "centres": centres,
                                   "axes": axes, "quats": quats})
     return p, psis

@@ -6,6 +6,10 @@ whole solve there in seconds, so the checks are properties it can evaluate:
   within the tolerance (any size);
 * Apply parity on the full grid;
 * the first two V-cycles match the oracle's two cycles (129^3 only);
+* at 129^3 the whole solve under the trajectory protocol: the oracle's solve
+  to 1e-10 in m* V-cycles (about a minute and a half of the oracle on the
+  host), the GPU for exactly m* cycles, every residual of the history to
+  1e-6 relative plus 1e-13 and the displacement to 1e-9 relative L2;
 * central differences of the GPU compliance at the 32 drawn cells of the
   193x97x97 density workload."""
 import numpy as np
@@ -52,6 +56,24 @@ def test_fullsize_solution_residual(name, precision):
     print(f"[fullsize] {name} precision {precision}: {len(hist) - 1} cycles, "
           f"GPU rho {hist[-1]:.3e}, oracle-evaluated rho {rho:.3e}")
     assert rho <= 1.05e-10
+
+
+def test_fullsize_trajectory_parity_129():
+    """Spherical voids at the full 129^3: exactly the oracle's m* V-cycles."""
+    p = WORKLOADS["spherical_voids_129"]()
+    say("full size 129 trajectory: oracle solve")
+    u_o, hist_o, st_o = oracle_solve(p, rtol=1e-10, max_cycles=400)
+    assert st_o == 0
+    m = len(hist_o) - 1
+    S = solver_for(p, rtol=0.0, max_cycles=m)
+    say("full size 129 trajectory: GPU, m*", m)
+    u_g, hist_g, _ = S.solve()
+    assert len(hist_g) == m + 1
+    dh = np.abs(np.asarray(hist_g) - np.asarray(hist_o))
+    assert np.all(dh <= 1e-6 * np.asarray(hist_o) + 1e-13), dh.max()
+    err = rel_l2(to_np(u_g), u_o)
+    print(f"[fullsize] spherical_voids_129: m* = {m}, rel L2 vs oracle {err:.3e}")
+    assert err <= 1e-9
 
 
 def test_fullsize_apply_and_first_cycles_129():
