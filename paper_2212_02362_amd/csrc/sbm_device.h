@@ -158,8 +158,8 @@ __device__ __forceinline__ void stencil3(const Coef<T> &C, const T (&P)[2][2][2]
 // ctr (optional) receives u at the node itself.  GATHER keeps every load
 // ahead of the arithmetic (a scheduling barrier); without it the compiler may
 // interleave them, which needs fewer registers.
-template <typename T, int DIM, bool GATHER = true>
-__device__ __forceinline__ void node_stencil(const Geom &g, const Coef<T> &C,
+template <typename T, int DIM, bool GATHER = true, typename G = Geom>
+__device__ __forceinline__ void node_stencil(const G &g, const Coef<T> &C,
                                              const T *__restrict__ psi,
                                              const T *__restrict__ u, int i, int j, int k,
                                              T out[3], T diag[3], T *ctr = nullptr) {

@@ -40,10 +40,16 @@ struct Level {
 };
 
 // Column tiles of the tiled 3D kernels: kTileX x kTileY nodes in x, y over a
-// chunk of kz planes; tile id = tx + ntx (ty + nty tz).
+// chunk of kz planes; tile id = tx + ntx (ty + nty tz).  When a level has one
+// node more than a whole number of tiles along x (or y) -- the 2^n + 1 node
+// counts of the benchmark grids -- the full launches stop the tiles before the
+// last node column (row) and give those face nodes to `nface` node-parallel
+// blocks launched after the tiles (xface / yface say which); a tile holding that single
+// column would cost a whole tile's stencil rounds for 1/64 of the work.
 constexpr int kTileX = 64, kTileY = 8;
 struct TileGeom {
   int ntx, nty, kz, ntiles;
+  int xface, yface, nface;
 };
 TileGeom tile_geom_of(const Level &L);
 // A subset of a level's tiles (device ids in increasing order).

@@ -44,10 +44,48 @@ __device__ __forceinline__ bool tg_dirichlet(const TG &g, int i, int j, int k, i
          ((k == 0) && ((m >> 12) & 1u)) || ((k == g.nz - 1) && ((m >> 15) & 1u));
 }
 
-TileGeom tile_geom(const TG &g) {
+// faces: the last node column / row of a 2^n + 1 level go to node-parallel
+// face blocks (launches over the whole level only; tile lists and the fused
+// sweep keep whole tiles).
+TileGeom tile_geom(const TG &g, bool faces = false);
+
+// Face node f of a launch with face blocks: the last column x = nx-1 (all
+// rows) first, then the last row y = ny-1 (the other columns), plane by plane.
+__device__ __forceinline__ bool face_node(const TG &g, const TileGeom &tg, int f, int &x, int &y,
+                                          int &z) {
+  const int per = (tg.xface ? g.ny : 0) + (tg.yface ? g.nx - tg.xface : 0);
+  if (f >= per * g.nz) return false;
+  z = f / per;
+  const int e = f - z * per;
+  if (tg.xface && e < g.ny) {
+    x = g.nx - 1;
+    y = e;
+  } else {
+    x = e - (tg.xface ? g.ny : 0);
+    y = g.ny - 1;
+  }
+  return true;
+}
+
+// Hardware block b of a launch over ntl tiles: the tiles first, in the
+// XCD-ordered numbering of the first ntl rounded up to 8 blocks; the face
+// blocks last (short node-parallel blocks that fill the slots the last tiles
+// leave idle).  Returns the logical tile, or -1 - fb for face block fb.
+__device__ __forceinline__ int tile_or_face(int ntl) {
+  const int nt8 = (ntl + 7) / 8 * 8;
+  const int b = blockIdx.x;
+  if (b >= nt8) return -1 - (b - nt8);
+  return (b & 7) * (nt8 >> 3) + (b >> 3);
+}
+
+TileGeom tile_geom(const TG &g, bool faces) {
   TileGeom t;
-  t.ntx = (g.nx + TX - 1) / TX;
-  t.nty = (g.ny + TY - 1) / TY;
+  t.xface = faces && g.nx > TX && g.nx % TX == 1;
+  t.yface = faces && g.ny > TY && g.ny % TY == 1;
+  t.ntx = t.xface ? g.nx / TX : (g.nx + TX - 1) / TX;
+  t.nty = t.yface ? g.ny / TY : (g.ny + TY - 1) / TY;
+  const int64_t per_plane = (t.xface ? g.ny : 0) + (t.yface ? g.nx - t.xface : 0);
+  t.nface = (int)((per_plane * g.nz + NT - 1) / NT);
   const int cols = t.ntx * t.nty;
   // enough workgroups to fill 256 CUs several times over; each chunk re-reads
   // two planes
@@ -145,9 +183,31 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
                                                    const int *__restrict__ ids, int nids) {
   __shared__ T su[3][NU];
   __shared__ T sp[2][NP];
-  const int nwg = gridDim.x;  // a multiple of 8
-  const int b = blockIdx.x;
-  const int li = (b & 7) * (nwg >> 3) + (b >> 3);
+  const int li = tile_or_face(ids ? nids : tg.ntiles);
+  const int nn = g.nn, nxy = g.nx * g.ny;
+  if (li < 0) {
+    // a face block: one node per thread, the same update from global memory
+    int x, y, z;
+    if (-1 - li < tg.nface && face_node(g, tg, (-1 - li) * NT + (int)threadIdx.x, x, y, z)) {
+      const int q = x + g.nx * (y + g.ny * z);
+      T nv[3];
+      if (((x + y + z) & 1) == colour && !(MASK && cls[q] != 1)) {
+        T out[3], dg[3], uc[3];
+        node_stencil<T, 3>(g, C, psi, u, x, y, z, out, dg, uc);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const T upd_c = uc[c] + omega * (f[c * nn + q] - out[c]) / dg[c];
+          nv[c] = tg_dirichlet(g, x, y, z, c) ? uc[c] : upd_c;
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) nv[c] = u[c * nn + q];
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) u_out[c * nn + q] = nv[c];
+    }
+    return;
+  }
   if (li >= (ids ? nids : tg.ntiles)) return;
   const int lt = ids ? ids[li] : li;  // a subset of the tiles, or all of them
   const int tx = lt % tg.ntx;
@@ -157,23 +217,30 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
   const int x0 = tx * TX, y0 = ty * TY;
   const int k0 = tz * tg.kz;
   const int k1 = min(k0 + tg.kz, g.nz);
-  const int nn = g.nn, nxy = g.nx * g.ny;
 
   Slots sl;
   make_slots(g, x0, y0, sl);
   const int yl = threadIdx.x / (TX / 2), p = threadIdx.x % (TX / 2);
   const int gy = y0 + yl;
-  // the load row of this thread's updated node in plane k (f is read one
-  // plane ahead, issued before the plane prefetch, and the first plane's f is
-  // issued before the prologue loads, so that no wait for f ever waits for a
-  // prefetch: vector loads retire in order)
+  // the load row of this thread's updated node in plane k
   auto upd_x = [&](int k) { return x0 + 2 * p + ((colour + gy + k) & 1); };
-  T fv[3] = {T(0), T(0), T(0)};
-  if (gy < g.ny && upd_x(k0) < g.nx) {
-    const int q = gy * g.nx + k0 * nxy + upd_x(k0);
+  // f of the updated node of plane k (in-range dummy where there is none)
+  auto fetch_fv = [&](int k, T (&r)[3]) {
+    const bool ok = k < k1 && gy < g.ny && upd_x(k) < g.nx;
+    const int q = ok ? gy * g.nx + k * nxy + upd_x(k) : 0;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) fv[c] = f[c * nn + q];
-  }
+    for (int c = 0; c < 3; ++c) r[c] = f[c * nn + q];
+  };
+  // Loads run two steps ahead: step k issues f of plane k+2 and the u / psi
+  // planes it stores one step later (u k+3, psi k+2), so every load has about
+  // two steps of stencil work to arrive.  All loads are unconditional (dummy
+  // in-range addresses past the chunk): with loads under a branch the
+  // compiler must wait for every older load at their first use.  Vector
+  // loads retire in order, so f is issued before the planes.
+  T FA[3], FB[3];
+  fetch_fv(k0, FA);
+  fetch_fv(k0 + 1, FB);
+  T RAu[NUPT], RAp[NPPT], RBu[NUPT], RBp[NPPT];
   {
     // all prologue loads in flight at once
     T r0[NUPT], r1[NUPT], r2[NUPT], q0[NPPT], q1[NPPT];
@@ -182,6 +249,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     fetch_u(g, sl, u, k0 + 1, r2);
     fetch_p(g, sl, psi, k0 - 1, q0);
     fetch_p(g, sl, psi, k0, q1);
+    fetch_u(g, sl, u, k0 + 2, RBu);
+    fetch_p(g, sl, psi, k0 + 1, RBp);
     put_u(g, sl, k0 - 1, su[(k0 + 2) % 3], r0);
     put_u(g, sl, k0, su[k0 % 3], r1);
     put_u(g, sl, k0 + 1, su[(k0 + 1) % 3], r2);
@@ -190,21 +259,17 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
   }
   __syncthreads();
 
-  for (int k = k0; k < k1; ++k) {
-    const bool pre = k + 1 < k1;
-    // next plane's f and the plane two ahead, loaded unconditionally
-    // (in-range dummies past the chunk): loads under a branch make the
-    // compiler wait for every older load at their first use
-    T fn[3];
-    {
-      const bool ok = pre && gy < g.ny && upd_x(k + 1) < g.nx;
-      const int q = ok ? gy * g.nx + (k + 1) * nxy + upd_x(k + 1) : 0;
+  // step k: fr holds f of plane k and receives f of plane k+2; (iu, ip)
+  // receive u k+3 and psi k+2; (su_, sp_) hold u k+2 and psi k+1, stored
+  // after the compute
+  auto step = [&](int k, T (&fr)[3], T (&iu)[NUPT], T (&ip)[NPPT], T (&stu)[NUPT],
+                  T (&stp)[NPPT]) __attribute__((always_inline)) {
+    T fv[3];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) fn[c] = f[c * nn + q];
-    }
-    T ru[NUPT], rp[NPPT];
-    fetch_u(g, sl, u, k + 2, ru);
-    fetch_p(g, sl, psi, k + 1, rp);
+    for (int c = 0; c < 3; ++c) fv[c] = fr[c];
+    fetch_fv(k + 2, fr);
+    fetch_u(g, sl, u, k + 3, iu);
+    fetch_p(g, sl, psi, k + 2, ip);
     const T *Lm = su[(k + 2) % 3];
     const T *L0 = su[k % 3];
     const T *L1 = su[(k + 1) % 3];
@@ -253,15 +318,19 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
         if (gxc < g.nx) u_out[c * nn + row + gxc] = L0[c * PLANE + cc];
       }
     }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) fv[c] = fn[c];
     __syncthreads();
-    if (pre) {
-      put_u(g, sl, k + 2, su[(k + 2) % 3], ru);
-      put_p(g, sl, k + 1, sp[(k + 1) & 1], rp);
-    }
+    // planes past the chunk (or the box) are stored as zeros into a free slot
+    put_u(g, sl, k + 2, su[(k + 2) % 3], stu);
+    put_p(g, sl, k + 1, sp[(k + 1) & 1], stp);
     __syncthreads();
+  };
+
+  int k = k0;
+  for (; k + 1 < k1; k += 2) {
+    step(k, FA, RAu, RAp, RBu, RBp);
+    step(k + 1, FB, RBu, RBp, RAu, RAp);
   }
+  if (k < k1) step(k, FA, RAu, RAp, RBu, RBp);
 }
 
 // Full stencil pass over the tile (every node computed), thread per x-pair:
@@ -270,7 +339,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
 //     v^2 per tile when partials is given;
 //   MODE 1 (Krylov Apply): v = K u on free DOF, 0 on displacement DOF; r = v;
 //     partial sum of u . v per tile.
-// Partials land in partials[tile], tiles in their logical order.
+// Partials land in partials[tile], tiles in their logical order, then one per
+// face block (partials[ntiles + face block]).
 template <typename T, int MODE, bool MASK>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void
 k_full_tile(TG g, Coef<T> C, const T *__restrict__ psi, const T *__restrict__ u,
@@ -279,9 +349,38 @@ k_full_tile(TG g, Coef<T> C, const T *__restrict__ psi, const T *__restrict__ u,
   __shared__ T su[3][NU];
   __shared__ T sp[2][NP];
   __shared__ double red[NT / 64 + 1];
-  const int nwg = gridDim.x;  // a multiple of 8
-  const int b = blockIdx.x;
-  const int li = (b & 7) * (nwg >> 3) + (b >> 3);
+  const int li = tile_or_face(ids ? nids : tg.ntiles);
+  const int nn = g.nn, nxy = g.nx * g.ny;
+  if (li < 0) {
+    // a face block: one node per thread from global memory, the block's sum
+    // after the tiles' partials
+    const int fb = -1 - li;
+    double acc = 0.0;
+    int x, y, z;
+    if (fb < tg.nface && face_node(g, tg, fb * NT + (int)threadIdx.x, x, y, z)) {
+      const int q = x + g.nx * (y + g.ny * z);
+      T v[3] = {T(0), T(0), T(0)};
+      if (!(MASK && (cls[q] == 0 || cls[q] > 3))) {
+        T out[3], dg[3], uc[3];
+        node_stencil<T, 3>(g, C, psi, u, x, y, z, out, dg, uc);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const T val = MODE == 0 ? f[c * nn + q] - out[c] : out[c];
+          v[c] = tg_dirichlet(g, x, y, z, c) ? T(0) : val;
+          if (MODE == 0) acc += (double)v[c] * (double)v[c];
+          else acc += (double)uc[c] * (double)v[c];
+        }
+      }
+      if (r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) r[c * nn + q] = v[c];
+    }
+    if (partials) {
+      const double sum = block_sum(acc, red);
+      if (threadIdx.x == 0 && fb < tg.nface) partials[tg.ntiles + fb] = sum;
+    }
+    return;
+  }
   if (li >= (ids ? nids : tg.ntiles)) return;
   const int lt = ids ? ids[li] : li;  // a subset of the tiles, or all of them
   const int tx = lt % tg.ntx;
@@ -291,7 +390,6 @@ k_full_tile(TG g, Coef<T> C, const T *__restrict__ psi, const T *__restrict__ u,
   const int x0 = tx * TX, y0 = ty * TY;
   const int k0 = tz * tg.kz;
   const int k1 = min(k0 + tg.kz, g.nz);
-  const int nn = g.nn, nxy = g.nx * g.ny;
 
   Slots sl;
   make_slots(g, x0, y0, sl);
@@ -875,15 +973,19 @@ bool tiled_ok(const Level &L) {
 
 TileGeom tile_geom_of(const Level &L) { return tile_geom(make_tg(L.g)); }
 
+// Blocks of a tiled launch: n tiles rounded up to a multiple of 8, then the
+// face blocks.
+static int tiled_grid(const TileGeom &tg, int n) { return (n + 7) / 8 * 8 + tg.nface; }
+
 template <typename T>
 hipError_t launch_rb_tiled(const Level &L, const T *psi, const Coef<T> &C, const T *u, const T *f,
                            T *u_out, double omega, int colour, hipStream_t st,
                            const uint8_t *cls, const TileList *tl) {
   const TG gg = make_tg(L.g);
-  const TileGeom tg = tile_geom(gg);
+  const TileGeom tg = tile_geom(gg, tl == nullptr);
   const int n = tl ? tl->count : tg.ntiles;
-  if (n == 0) return hipSuccess;
-  const int grid = (n + 7) / 8 * 8;
+  if (n == 0 && tg.nface == 0) return hipSuccess;
+  const int grid = tiled_grid(tg, n);
   const int *ids = tl ? tl->ids : nullptr;
   (void)hipGetLastError();
   if (cls)
@@ -918,17 +1020,20 @@ template hipError_t launch_rb_fused<float>(const Level &, const float *, const C
                                            const float *, const float *, float *, double, int,
                                            hipStream_t);
 
-int tiled_partials(const Level &L) { return tile_geom(make_tg(L.g)).ntiles; }
+int tiled_partials(const Level &L) {
+  const TileGeom tg = tile_geom(make_tg(L.g), true);
+  return tg.ntiles + tg.nface;
+}
 
 template <typename T>
 hipError_t launch_residual_tiled(const Level &L, const T *psi, const Coef<T> &C, const T *u,
                                  const T *f, T *r, double *partials, hipStream_t st,
                                  const uint8_t *cls, const TileList *tl) {
   const TG gg = make_tg(L.g);
-  const TileGeom tg = tile_geom(gg);
+  const TileGeom tg = tile_geom(gg, tl == nullptr);
   const int n = tl ? tl->count : tg.ntiles;
-  if (n == 0) return hipSuccess;
-  const int grid = (n + 7) / 8 * 8;
+  if (n == 0 && tg.nface == 0) return hipSuccess;
+  const int grid = tiled_grid(tg, n);
   const int *ids = tl ? tl->ids : nullptr;
   (void)hipGetLastError();
   if (cls)
@@ -943,8 +1048,8 @@ hipError_t launch_residual_tiled(const Level &L, const T *psi, const Coef<T> &C,
 hipError_t launch_apply_dot_tiled(const Level &L, const double *p, double *q, double *partials,
                                   hipStream_t st) {
   const TG gg = make_tg(L.g);
-  const TileGeom tg = tile_geom(gg);
-  const int grid = (tg.ntiles + 7) / 8 * 8;
+  const TileGeom tg = tile_geom(gg, true);
+  const int grid = tiled_grid(tg, tg.ntiles);
   (void)hipGetLastError();
   hipLaunchKernelGGL((k_full_tile<double, 1, false>), dim3(grid), dim3(NT), 0, st, gg, L.c64,
                      L.psi64, p, (const double *)nullptr, q, partials, tg,

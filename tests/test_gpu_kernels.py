@@ -85,10 +85,11 @@ def test_residual_and_smoothers(ncell):
         assert np.array_equal(got[other], u[other])
 
 
-@pytest.mark.parametrize("ncell", [(200, 30, 12), (230, 25, 9), (256, 33, 6)])
+@pytest.mark.parametrize("ncell", [(200, 30, 12), (230, 25, 9), (256, 33, 6), (256, 32, 10)])
 def test_tiled_half_sweep(ncell):
     """Levels wider than 192 nodes in x take the LDS-tiled half-sweep: several
-    64 x 8 tiles, a ragged last tile in x and y, z chunks."""
+    64 x 8 tiles, a ragged last tile in x and y, z chunks; 257 nodes in x (and
+    33 in y) leave the last column (row) to the node-parallel face blocks."""
     p, S, psi, mask, u, f = _setup(ncell, seed=11)
     u = np.where(mask == 1, oracle.dirichlet(p.ncell, p.kind, p.val)[1], u)
     for colour in (0, 1):
@@ -131,7 +132,7 @@ def test_fused_two_colour_sweep(ncell):
     assert rel_l2(got, ref) < 1e-5
 
 
-@pytest.mark.parametrize("ncell", [(200, 30, 12), (256, 33, 6)])
+@pytest.mark.parametrize("ncell", [(200, 30, 12), (256, 33, 6), (256, 32, 10)])
 def test_tiled_residual_and_norm(ncell):
     """The tiled residual (r and its per-tile norm partials) at widths that
     take the tiled path."""
