@@ -44,6 +44,7 @@ ALGO_BYTES = {              # (FP64, FP32) bytes per finest-level node
     "restrict": (27.0, 13.5),  # r read, coarse f written (1/8 of the nodes)
     "prolong": (51.0, 25.5),   # coarse e read, u read and written
     "norm": (56.0, 56.0),      # u, psi, f read (always FP64)
+    "sweep0": (56.0, 28.0),    # one-launch sweep from zero: psi, f read, u written
 }
 # V-cycle iteration: the convergence-test pass also writes the next cycle's
 # first half-sweep (FP64) or the residual the FP32 cycle casts (mixed): u,

@@ -19,7 +19,7 @@ STATUS_NAMES = {0: "SBM_OK", 1: "SBM_NOT_CONVERGED", -1: "SBM_E_ARG", -2: "SBM_E
 TRACTION = 0
 DISPLACEMENT = 1
 CHAIN_PSI, CHAIN_FLOOR, CHAIN_RHO3 = 0, 1, 2
-PROF_CLASSES = ("smooth", "residual", "restrict", "prolong", "norm", "bottom", "ghost")
+PROF_CLASSES = ("smooth", "residual", "restrict", "prolong", "norm", "bottom", "ghost", "sweep0")
 
 
 class SbmGrid(ctypes.Structure):

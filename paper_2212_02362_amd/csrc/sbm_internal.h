@@ -143,11 +143,18 @@ hipError_t launch_dot_free(const Level &L, const double *a, const double *b, dou
 hipError_t launch_sumsq_free(const Level &L, const double *v, double *partials, hipStream_t st);
 hipError_t launch_apply_dot(const Level &L, const double *p, double *q, double *partials,
                            hipStream_t st);
-hipError_t launch_cg_update(const Level &L, double *x, double *r, const double *p, const double *q,
-                            const double *z, const double *rz, const double *pq, double *pr,
-                            double *pz, hipStream_t st);
-hipError_t launch_xpby(const Level &L, double *p, const double *z, const double *rznew,
-                       const double *rzold, const double *rz, hipStream_t st);
+// The flexible-CG vector updates with the iterate update deferred: r -= alpha q
+// (alpha = rz / pq, stored to *alpha_out) with the r.r and r.z partials; then
+// x += (*alpha) p (alpha may be NULL) and p = z + beta p in one pass; or
+// x += (*alpha) p alone.
+hipError_t launch_cg_update_r(const Level &L, double *r, const double *q, const double *z,
+                              const double *rz, const double *pq, double *alpha_out, double *pr,
+                              double *pz, hipStream_t st);
+hipError_t launch_xpby_x(const Level &L, double *x, double *p, const double *z,
+                         const double *rznew, const double *rzold, const double *rz,
+                         const double *alpha, hipStream_t st);
+hipError_t launch_axpy_free(const Level &L, double *x, const double *p, const double *alpha,
+                            hipStream_t st);
 // r32 = fp32(r / sqrt(*ss)) for a residual r in memory (the expression of
 // launch_residual_cast).
 hipError_t launch_scale_cast(const double *r, float *r32, int64_t n, const double *ss,

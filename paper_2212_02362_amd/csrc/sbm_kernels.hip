@@ -640,34 +640,32 @@ __global__ __launch_bounds__(kBlock) void k_apply_dot(Geom g, Coef<double> C,
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
-// x += alpha p, r -= alpha q on free DOF, alpha = rz / pq read from device
-// scalars; partials of r.r (pr) and r.z (pz, z = the previous preconditioned
-// residual).
+// The CG update without the iterate: alpha = rz / pq (also stored to
+// *alpha_out by the first thread), r -= alpha q on free DOF, partials of r.r
+// (pr) and r.z (pz, z = the previous preconditioned residual).  The update
+// x += alpha p is left to the next direction update (k_xpby_x) or to
+// k_axpy_free: the same products, one vector pass fewer.
 template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_cg_update(Geom g, double *__restrict__ x,
-                                                      double *__restrict__ r,
-                                                      const double *__restrict__ p,
-                                                      const double *__restrict__ q,
-                                                      const double *__restrict__ z,
-                                                      const double *__restrict__ rz,
-                                                      const double *__restrict__ pq,
-                                                      double *__restrict__ pr,
-                                                      double *__restrict__ pz) {
+__global__ __launch_bounds__(kBlock) void k_cg_update_r(Geom g, double *__restrict__ r,
+                                                        const double *__restrict__ q,
+                                                        const double *__restrict__ z,
+                                                        const double *__restrict__ rz,
+                                                        const double *__restrict__ pq,
+                                                        double *__restrict__ alpha_out,
+                                                        double *__restrict__ pr,
+                                                        double *__restrict__ pz) {
   __shared__ double lds[kBlock / 64 + 1];
   const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const double alpha = *rz / *pq;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *alpha_out = alpha;
   double srr = 0.0, srz = 0.0;
   if (id < g.nn) {
     int i, j, k;
     node_ijk(g, id, i, j, k);
-    // all loads first (one memory round trip); displacement DOF are neither
-    // updated nor summed
-    double xv[3], pv[3], rv[3], qv[3], zv[3];
+    double rv[3], qv[3], zv[3];
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
       const int64_t qi = c * g.nn + id;
-      xv[c] = x[qi];
-      pv[c] = p[qi];
       rv[c] = r[qi];
       qv[c] = q[qi];
       zv[c] = z[qi];
@@ -676,10 +674,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(Geom g, double *__restrict
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
       if ((g.dmask >> c) & fb) continue;
-      const int64_t qi = c * g.nn + id;
-      x[qi] = xv[c] + alpha * pv[c];
       const double rn = rv[c] - alpha * qv[c];
-      r[qi] = rn;
+      r[c * g.nn + id] = rn;
       srr += rn * rn;
       srz += rn * zv[c];
     }
@@ -693,29 +689,53 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(Geom g, double *__restrict
   }
 }
 
-// p = z + beta p on free DOF (0 on displacement DOF), beta = (rznew - rzold) / rz
-// from device scalars (beta = 0 when rz is NULL: restart).
+// The deferred iterate update and the new direction in one pass: on free DOF
+// x += (*alpha) p (when alpha is given), then p = z + beta p, beta = (rznew -
+// rzold) / rz (beta = 0 when rz is NULL: restart); p = 0 on displacement DOF.
 template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_xpby(Geom g, double *__restrict__ p,
-                                                 const double *__restrict__ z,
-                                                 const double *__restrict__ rznew,
-                                                 const double *__restrict__ rzold,
-                                                 const double *__restrict__ rz) {
+__global__ __launch_bounds__(kBlock) void k_xpby_x(Geom g, double *__restrict__ x,
+                                                   double *__restrict__ p,
+                                                   const double *__restrict__ z,
+                                                   const double *__restrict__ rznew,
+                                                   const double *__restrict__ rzold,
+                                                   const double *__restrict__ rz,
+                                                   const double *__restrict__ alpha) {
   const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (id >= g.nn) return;
   const double beta = rz ? (*rznew - *rzold) / *rz : 0.0;
+  const double al = alpha ? *alpha : 0.0;
   int i, j, k;
   node_ijk(g, id, i, j, k);
-  double zv[3], pv[3];
+  double zv[3], pv[3], xv[3];
 #pragma unroll
   for (int c = 0; c < DIM; ++c) {
     zv[c] = z[c * g.nn + id];
-    pv[c] = rz ? p[c * g.nn + id] : 0.0;
+    pv[c] = p[c * g.nn + id];
+    xv[c] = alpha ? x[c * g.nn + id] : 0.0;
   }
   const uint32_t fb = face_bits(g, i, j, k);
 #pragma unroll
+  for (int c = 0; c < DIM; ++c) {
+    const bool fixed = (g.dmask >> c) & fb;
+    if (alpha && !fixed) x[c * g.nn + id] = xv[c] + al * pv[c];
+    p[c * g.nn + id] = fixed ? 0.0 : zv[c] + (rz ? beta * pv[c] : 0.0);
+  }
+}
+
+// x += (*alpha) p on free DOF (the deferred CG update, when the iteration ends).
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_axpy_free(Geom g, double *__restrict__ x,
+                                                      const double *__restrict__ p,
+                                                      const double *__restrict__ alpha) {
+  const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (id >= g.nn) return;
+  const double al = *alpha;
+  int i, j, k;
+  node_ijk(g, id, i, j, k);
+  const uint32_t fb = face_bits(g, i, j, k);
+#pragma unroll
   for (int c = 0; c < DIM; ++c)
-    p[c * g.nn + id] = ((g.dmask >> c) & fb) ? 0.0 : zv[c] + (rz ? beta * pv[c] : 0.0);
+    if (!((g.dmask >> c) & fb)) x[c * g.nn + id] += al * p[c * g.nn + id];
 }
 
 // r32 = fp32(r / s) and z = s * e32 (s = sqrt(*ss)): the FP32 preconditioner
@@ -1275,19 +1295,31 @@ hipError_t launch_apply_dot(const Level &L, const double *p, double *q, double *
   SBM_LAUNCH((k_apply_dot<2>), grid_blocks(L.g.nn), kBlock, st, L.g, L.c64, L.psi64, p, q, partials);
 }
 
-hipError_t launch_cg_update(const Level &L, double *x, double *r, const double *p, const double *q,
-                            const double *z, const double *rz, const double *pq, double *pr,
-                            double *pz, hipStream_t st) {
+hipError_t launch_cg_update_r(const Level &L, double *r, const double *q, const double *z,
+                              const double *rz, const double *pq, double *alpha_out, double *pr,
+                              double *pz, hipStream_t st) {
   if (L.g.dim == 3)
-    SBM_LAUNCH((k_cg_update<3>), num_blocks(L.g.nn), kBlock, st, L.g, x, r, p, q, z, rz, pq, pr, pz);
-  SBM_LAUNCH((k_cg_update<2>), num_blocks(L.g.nn), kBlock, st, L.g, x, r, p, q, z, rz, pq, pr, pz);
+    SBM_LAUNCH((k_cg_update_r<3>), num_blocks(L.g.nn), kBlock, st, L.g, r, q, z, rz, pq,
+               alpha_out, pr, pz);
+  SBM_LAUNCH((k_cg_update_r<2>), num_blocks(L.g.nn), kBlock, st, L.g, r, q, z, rz, pq, alpha_out,
+             pr, pz);
 }
 
-hipError_t launch_xpby(const Level &L, double *p, const double *z, const double *rznew,
-                       const double *rzold, const double *rz, hipStream_t st) {
-  if (L.g.dim == 3) SBM_LAUNCH((k_xpby<3>), num_blocks(L.g.nn), kBlock, st, L.g, p, z, rznew, rzold, rz);
-  SBM_LAUNCH((k_xpby<2>), num_blocks(L.g.nn), kBlock, st, L.g, p, z, rznew, rzold, rz);
+hipError_t launch_xpby_x(const Level &L, double *x, double *p, const double *z,
+                         const double *rznew, const double *rzold, const double *rz,
+                         const double *alpha, hipStream_t st) {
+  if (L.g.dim == 3)
+    SBM_LAUNCH((k_xpby_x<3>), num_blocks(L.g.nn), kBlock, st, L.g, x, p, z, rznew, rzold, rz,
+               alpha);
+  SBM_LAUNCH((k_xpby_x<2>), num_blocks(L.g.nn), kBlock, st, L.g, x, p, z, rznew, rzold, rz, alpha);
 }
+
+hipError_t launch_axpy_free(const Level &L, double *x, const double *p, const double *alpha,
+                            hipStream_t st) {
+  if (L.g.dim == 3) SBM_LAUNCH((k_axpy_free<3>), num_blocks(L.g.nn), kBlock, st, L.g, x, p, alpha);
+  SBM_LAUNCH((k_axpy_free<2>), num_blocks(L.g.nn), kBlock, st, L.g, x, p, alpha);
+}
+
 
 hipError_t launch_cast_scaled(const double *r, float *r32, int64_t n, const double *ss,
                               hipStream_t st) {

@@ -378,18 +378,42 @@ static hipError_t smooth(sbm_ctx *c, int l, T *x, const T *f, T *tmp, int nu, bo
     return e;
   }
   const int c0 = reverse ? 1 : 0;
-  if (c->opt.fused_sweep == 1 && tiled_ok(L)) {
-    // whole two-colour sweeps in one launch each, ping-ponging between x and
-    // tmp so that the last lands in x; from a zero iterate (zero_start) the
-    // first sweep reads nothing
-    const bool zero = l == 0 && c->zero_start;
-    c->zero_start = false;
+  const bool zero = l == 0 && c->zero_start;
+  c->zero_start = false;
+  if (tiled_ok(L) && (zero || c->opt.fused_sweep == 1)) {
+    // A sweep from a zero iterate (zero_start: the first sweep of a correction
+    // that starts from zero) is always one fused launch that reads no iterate;
+    // with fused_sweep every other sweep is one fused launch too (out of
+    // place: cur -> the other buffer), else two half-sweeps (cur -> tmp ->
+    // cur).  The first sweep's output buffer is chosen so that the last
+    // sweep lands in x.
+    const bool all = c->opt.fused_sweep == 1;
     T *cur = zero ? nullptr : x;
     for (int s = 0; s < nu; ++s) {
-      T *dst = cur ? (cur == x ? tmp : x) : (((nu - 1 - s) % 2 == 0) ? x : tmp);
-      ProfScope ps(c, SBM_PROF_SMOOTH, l == 0);
-      if ((e = launch_rb_fused<T>(L, psi, C, cur, f, dst, om, c0, c->st)) != hipSuccess) return e;
-      cur = dst;
+      if (!cur) {
+        const int toggles = all ? nu - 1 - s : 0;
+        T *dst = toggles % 2 == 0 ? x : tmp;
+        ProfScope ps(c, SBM_PROF_SWEEP0, l == 0);
+        if ((e = launch_rb_fused<T>(L, psi, C, nullptr, f, dst, om, c0, c->st)) != hipSuccess)
+          return e;
+        cur = dst;
+      } else if (all) {
+        T *dst = cur == x ? tmp : x;
+        ProfScope ps(c, SBM_PROF_SMOOTH, l == 0);
+        if ((e = launch_rb_fused<T>(L, psi, C, cur, f, dst, om, c0, c->st)) != hipSuccess)
+          return e;
+        cur = dst;
+      } else {
+        T *oth = cur == x ? tmp : x;
+        {
+          ProfScope ps(c, SBM_PROF_SMOOTH, l == 0);
+          if ((e = launch_rb_tiled<T>(L, psi, C, cur, f, oth, om, c0, c->st)) != hipSuccess)
+            return e;
+        }
+        ProfScope ps(c, SBM_PROF_SMOOTH, l == 0);
+        if ((e = launch_rb_tiled<T>(L, psi, C, oth, f, cur, om, 1 - c0, c->st)) != hipSuccess)
+          return e;
+      }
     }
     if (!cur) return launch_fill<T>(x, (int64_t)c->dim * L.g.nn, T(0), c->st);
     if (cur != x) return launch_copy<T>(cur, x, (int64_t)c->dim * L.g.nn, c->st);
@@ -541,7 +565,7 @@ static hipError_t cycle_body(sbm_ctx *c, const double *f, int mode) {
     // one colour) and is made together with the cast or instead of the fill.
     const bool skip = c->opt.smoother == 0 && c->opt.nu_pre >= 1 && c->nlev > 1;
     // a finest level swept by the fused kernel starts that sweep from zero
-    const bool zs = skip && c->opt.fused_sweep == 1 && tiled_ok(L0);
+    const bool zs = skip && tiled_ok(L0);
     if (c->opt.precision == 1) {
       if (zs && c->tail32 != 0) {
         if ((e = launch_cast_scaled(c->kr, L0.f32, nv, c->scal, c->st)) != hipSuccess) return e;
@@ -592,8 +616,8 @@ static hipError_t cycle_body(sbm_ctx *c, const double *f, int mode) {
     if ((e = mode == 2 ? launch_scale_cast(L0.t, L0.f32, nv, c->scal, c->st)
                        : launch_residual_cast(L0, c->x0, f, L0.f32, c->scal, c->st)) != hipSuccess)
       return e;
-    if (c->opt.fused_sweep == 1 && tiled_ok(L0) && c->opt.smoother == 0 && c->opt.nu_pre >= 1 &&
-        c->nlev > 1 && c->tail32 != 0)
+    if (tiled_ok(L0) && c->opt.smoother == 0 && c->opt.nu_pre >= 1 && c->nlev > 1 &&
+        c->tail32 != 0)
       c->zero_start = true;
     else if ((e = launch_fill<float>(L0.e32, nv, 0.0f, c->st)) != hipSuccess)
       return e;
@@ -691,7 +715,10 @@ static sbm_status fin_to_host(sbm_ctx *c, const double *partials, int n, int slo
 // Flexible CG (Polak-Ribiere beta) on the finest level, preconditioned by one
 // V-cycle from zero per iteration.  Device scalars: scal[0] = r.r,
 // scal[1] = r.z (new), scal[2] = p.q, scal[3] = r.z (old z), scal[4] = r.z
-// of the previous iteration.
+// of the previous iteration, scal[5] = alpha of the last update.  The update
+// x += alpha p is deferred to the pass that forms the next direction (which
+// reads p anyway), or made on its own when the iteration ends: the iterates
+// are the same numbers.
 static sbm_status solve_krylov(sbm_ctx *c, const double *f, double fnorm, double *u, double *hist,
                                int cap, int *ncyc, double *final_rel) {
   Level &L0 = c->L[0];
@@ -734,7 +761,7 @@ static sbm_status solve_krylov(sbm_ctx *c, const double *f, double fnorm, double
       SBM_TRY(run_cycle(c, nullptr, 1));
       HIP_TRY(launch_dot_free(L0, c->kr, c->kz, c->partials, c->st));
       HIP_TRY(launch_finalize_sum(c->partials, nb, c->scal + 4, c->st));
-      HIP_TRY(launch_xpby(L0, c->kp, c->kz, nullptr, nullptr, nullptr, c->st));
+      HIP_TRY(launch_xpby_x(L0, c->x0, c->kp, c->kz, nullptr, nullptr, nullptr, nullptr, c->st));
       restart = false;
     }
     HIP_TRY(launch_apply_dot(L0, c->kp, c->kq, c->partials, c->st));
@@ -745,8 +772,10 @@ static sbm_status solve_krylov(sbm_ctx *c, const double *f, double fnorm, double
       status = fail(SBM_E_DIVERGED, "preconditioned CG lost positivity (p.Kp <= 0)");
       break;
     }
-    HIP_TRY(launch_cg_update(L0, c->x0, c->kr, c->kp, c->kq, c->kz, c->scal + 4, c->scal + 2,
-                             c->partials, c->partials2, c->st));
+    // r -= alpha q; the iterate update x += alpha p (alpha kept in scal[5]) is
+    // made by the next direction update, or below when the iteration ends
+    HIP_TRY(launch_cg_update_r(L0, c->kr, c->kq, c->kz, c->scal + 4, c->scal + 2, c->scal + 5,
+                               c->partials, c->partials2, c->st));
     SBM_TRY(fin_to_host(c, c->partials, nb, 0));
     SBM_TRY(fin_to_host(c, c->partials2, nb, 3));
     HIP_TRY(hipStreamSynchronize(c->st));
@@ -754,6 +783,7 @@ static sbm_status solve_krylov(sbm_ctx *c, const double *f, double fnorm, double
     rho = fnorm > 0.0 ? sqrt(c->host[0]) / fnorm : 0.0;
     if (rho <= c->opt.rtol) {
       // accept on the true residual only; otherwise restart from it
+      HIP_TRY(launch_axpy_free(L0, c->x0, c->kp, c->scal + 5, c->st));
       {
         ProfScope ps(c, SBM_PROF_NORM, true);
         HIP_TRY((launch_residual<double>(L0, L0.psi64, L0.c64, c->x0, f, c->kr, c->partials,
@@ -770,7 +800,8 @@ static sbm_status solve_krylov(sbm_ctx *c, const double *f, double fnorm, double
     SBM_TRY(run_cycle(c, nullptr, 1));
     HIP_TRY(launch_dot_free(L0, c->kr, c->kz, c->partials, c->st));
     HIP_TRY(launch_finalize_sum(c->partials, nb, c->scal + 1, c->st));
-    HIP_TRY(launch_xpby(L0, c->kp, c->kz, c->scal + 1, c->scal + 3, c->scal + 4, c->st));
+    HIP_TRY(launch_xpby_x(L0, c->x0, c->kp, c->kz, c->scal + 1, c->scal + 3, c->scal + 4,
+                          c->scal + 5, c->st));
     HIP_TRY(launch_copy<double>(c->scal + 1, c->scal + 4, 1, c->st));
   }
   if (ncyc) *ncyc = m;
