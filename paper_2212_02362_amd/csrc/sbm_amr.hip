@@ -47,6 +47,10 @@ using namespace sbm;
 namespace {
 
 constexpr int kMaxAmrLevels = 4;  // base + up to 3 refined levels
+// Tile lists of sparsely refined levels: shallowest chunk depth, and the
+// number of workgroups the listed tiles should give (a few per CU).
+constexpr int kAmrKzMin = 6;
+constexpr int64_t kAmrTiles = 2048;
 
 #define AMR_LAUNCH(kern, grid, block, st, ...)                             \
   do {                                                                     \
@@ -275,35 +279,113 @@ __device__ __forceinline__ int quad_axis(int n, int idx[3], T w[3]) {
 // Ghost nodes (classes 2-4) of the fine level from the coarse level; fixed
 // displacement DOF keep their values.  Weight products are exact dyadic
 // numbers; every term is rounded before it is added.
-template <typename T, int DIM, bool TILED>
-__global__ __launch_bounds__(kBlock) void k_amr_ghost(Geom gf, Geom gc,
-                                                      const uint8_t *__restrict__ cls,
-                                                      const T *__restrict__ xc,
-                                                      T *__restrict__ xf, TileArg ta) {
+template <typename T, int DIM>
+__device__ __forceinline__ void ghost_node(const Geom &gf, const Geom &gc,
+                                           const T *__restrict__ xc, T *__restrict__ xf,
+                                           int64_t id) {
 #pragma clang fp contract(off)
-  for_nodes<TILED>(gf, ta, [&](int64_t id) {
-    if (cls[id] < 2) return;
-    int i, j, k;
-    node_ijk(gf, id, i, j, k);
-    int ix[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-    T w[3][3] = {{T(1), T(0), T(0)}, {T(1), T(0), T(0)}, {T(1), T(0), T(0)}};
-    int cnt[3] = {1, 1, 1};
-    cnt[0] = quad_axis<T>(i, ix[0], w[0]);
-    cnt[1] = quad_axis<T>(j, ix[1], w[1]);
-    if (DIM == 3) cnt[2] = quad_axis<T>(k, ix[2], w[2]);
+  int i, j, k;
+  node_ijk(gf, id, i, j, k);
+  int ix[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  T w[3][3] = {{T(1), T(0), T(0)}, {T(1), T(0), T(0)}, {T(1), T(0), T(0)}};
+  int cnt[3] = {1, 1, 1};
+  cnt[0] = quad_axis<T>(i, ix[0], w[0]);
+  cnt[1] = quad_axis<T>(j, ix[1], w[1]);
+  if (DIM == 3) cnt[2] = quad_axis<T>(k, ix[2], w[2]);
 #pragma unroll
-    for (int c = 0; c < DIM; ++c) {
-      if (is_dirichlet(gf, i, j, k, c)) continue;
-      T s = T(0);
-      for (int t2 = 0; t2 < cnt[2]; ++t2)
-        for (int t1 = 0; t1 < cnt[1]; ++t1)
-          for (int t0 = 0; t0 < cnt[0]; ++t0) {
-            const int64_t q = ix[0][t0] + (int64_t)gc.nx * (ix[1][t1] + (int64_t)gc.ny * ix[2][t2]);
-            s += w[0][t0] * w[1][t1] * w[2][t2] * xc[c * gc.nn + q];
-          }
-      xf[c * gf.nn + id] = s;
-    }
-  });
+  for (int c = 0; c < DIM; ++c) {
+    if (is_dirichlet(gf, i, j, k, c)) continue;
+    T s = T(0);
+    for (int t2 = 0; t2 < cnt[2]; ++t2)
+      for (int t1 = 0; t1 < cnt[1]; ++t1)
+        for (int t0 = 0; t0 < cnt[0]; ++t0) {
+          const int64_t q = ix[0][t0] + (int64_t)gc.nx * (ix[1][t1] + (int64_t)gc.ny * ix[2][t2]);
+          s += w[0][t0] * w[1][t1] * w[2][t2] * xc[c * gc.nn + q];
+        }
+    xf[c * gf.nn + id] = s;
+  }
+}
+
+// The same over a list of the level's ghost nodes (one per thread).
+template <typename T, int DIM>
+__global__ __launch_bounds__(kBlock) void k_amr_ghost_list(Geom gf, Geom gc,
+                                                           const int *__restrict__ ids, int n,
+                                                           const T *__restrict__ xc,
+                                                           T *__restrict__ xf) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= n) return;
+  ghost_node<T, DIM>(gf, gc, xc, xf, ids[t]);
+}
+
+// Ghost-node list of a level (ids of the nodes of class >= 2, increasing), by
+// a three-pass compaction: per-block counts, one-workgroup scan of the
+// counts, per-block writes in node order.
+constexpr int kCompactNodes = 4 * kBlock;  // nodes per block (four per thread)
+
+__global__ __launch_bounds__(kBlock) void k_ghost_count(int64_t nn, const uint8_t *__restrict__ cls,
+                                                        int *__restrict__ bcnt) {
+  __shared__ int red[kBlock];
+  const int64_t base = (int64_t)blockIdx.x * kCompactNodes + 4 * threadIdx.x;
+  int c = 0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) c += (base + e < nn && cls[base + e] >= 2) ? 1 : 0;
+  red[threadIdx.x] = c;
+  __syncthreads();
+  for (int d = kBlock / 2; d > 0; d >>= 1) {
+    if ((int)threadIdx.x < d) red[threadIdx.x] += red[threadIdx.x + d];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) bcnt[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(1024) void k_scan_counts(const int *__restrict__ cnt, int n,
+                                                      int *__restrict__ off, int *__restrict__ total) {
+  __shared__ int sh[1024];
+  const int t = threadIdx.x;
+  const int chunk = (n + 1023) / 1024;
+  const int lo = min(n, t * chunk), hi = min(n, lo + chunk);
+  int c = 0;
+  for (int i = lo; i < hi; ++i) c += cnt[i];
+  sh[t] = c;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {  // inclusive scan
+    const int v = t >= d ? sh[t - d] : 0;
+    __syncthreads();
+    sh[t] += v;
+    __syncthreads();
+  }
+  int w = sh[t] - c;
+  for (int i = lo; i < hi; ++i) {
+    off[i] = w;
+    w += cnt[i];
+  }
+  if (t == 1023) *total = sh[1023];
+}
+
+__global__ __launch_bounds__(kBlock) void k_ghost_write(int64_t nn, const uint8_t *__restrict__ cls,
+                                                        const int *__restrict__ boff,
+                                                        int *__restrict__ ids) {
+  __shared__ int sh[kBlock];
+  const int64_t base = (int64_t)blockIdx.x * kCompactNodes + 4 * threadIdx.x;
+  bool g[4];
+  int c = 0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    g[e] = base + e < nn && cls[base + e] >= 2;
+    c += g[e] ? 1 : 0;
+  }
+  sh[threadIdx.x] = c;
+  __syncthreads();
+  for (int d = 1; d < kBlock; d <<= 1) {  // inclusive scan
+    const int v = (int)threadIdx.x >= d ? sh[threadIdx.x - d] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int w = boff[blockIdx.x] + sh[threadIdx.x] - c;
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    if (g[e]) ids[w++] = (int)(base + e);
 }
 
 // Coarse nodes on or inside the fine region (fine class 1 or 2 at the
@@ -497,7 +579,7 @@ struct NodeGrid {
 
 static NodeGrid node_grid(const Level &L, const TileList *tl) {
   if (tl) {
-    const TileGeom tg = tile_geom_of(L);
+    const TileGeom tg = tile_geom_of(L, tl->kz);
     return NodeGrid{tl->count * tg.kz, true, TileArg{tg, tl->ids}};
   }
   return NodeGrid{num_blocks(L.g.nn), false, TileArg{TileGeom{1, 1, 1, 1}, nullptr}};
@@ -510,15 +592,32 @@ static NodeGrid node_grid(const Level &L, const TileList *tl) {
     AMR_LAUNCH(KD, (ng).blocks, kBlock, st, __VA_ARGS__, (ng).ta);              \
   } while (0)
 
+// The ghost nodes of a level listed at set-up.
+struct GhostList {
+  const int *ids = nullptr;
+  int count = 0;
+};
+
 template <typename T>
-hipError_t launch_ghost(const Level &F, const Level &C, const uint8_t *cls, const T *xc, T *xf,
-                        hipStream_t st, const TileList *tl = nullptr) {
-  const NodeGrid ng = node_grid(F, tl);
+hipError_t launch_ghost_list(const Level &F, const Level &C, const GhostList &gl, const T *xc,
+                             T *xf, hipStream_t st) {
+  if (gl.count == 0) return hipSuccess;
+  const int nb = (gl.count + kBlock - 1) / kBlock;
   if (F.g.dim == 3)
-    AMR_NODE_LAUNCH((k_amr_ghost<T, 3, true>), (k_amr_ghost<T, 3, false>), ng, st, F.g, C.g, cls,
-                    xc, xf);
-  AMR_NODE_LAUNCH((k_amr_ghost<T, 2, true>), (k_amr_ghost<T, 2, false>), ng, st, F.g, C.g, cls, xc,
-                  xf);
+    AMR_LAUNCH((k_amr_ghost_list<T, 3>), nb, kBlock, st, F.g, C.g, gl.ids, gl.count, xc, xf);
+  AMR_LAUNCH((k_amr_ghost_list<T, 2>), nb, kBlock, st, F.g, C.g, gl.ids, gl.count, xc, xf);
+}
+
+hipError_t launch_ghost_listing(const Level &F, const uint8_t *cls, int *bcnt, int *boff, int *ids,
+                                int *total, hipStream_t st) {
+  const int64_t nb = (F.g.nn + kCompactNodes - 1) / kCompactNodes;
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(k_ghost_count, dim3((unsigned)nb), dim3(kBlock), 0, st, F.g.nn, cls, bcnt);
+  hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, (const int *)bcnt, (int)nb, boff,
+                     total);
+  hipLaunchKernelGGL(k_ghost_write, dim3((unsigned)nb), dim3(kBlock), 0, st, F.g.nn, cls,
+                     (const int *)boff, ids);
+  return hipGetLastError();
 }
 
 template <typename T>
@@ -614,6 +713,8 @@ struct AmrLevel {
   float *e32 = nullptr, *f32 = nullptr, *w32 = nullptr, *xinj32 = nullptr, *tmp32 = nullptr;
   float *g32 = nullptr;    // FP32 cycle: R of the finer level's ghost-row loads (a < A)
   int *tflags = nullptr, *tids = nullptr;  // active column tiles (tiled levels a >= 1)
+  int *gids = nullptr, *gcnt = nullptr, *goff = nullptr;  // ghost-node list and its scratch
+  GhostList gl;            // the level's ghost nodes (a >= 1; count 0 until set_problem)
   TileList tl;             // the level's active tiles (count 0 until set_problem)
   bool tiled = false;      // the level sweeps only its active tiles
   const TileList *tiles() const { return tiled ? &tl : nullptr; }
@@ -859,10 +960,17 @@ static size_t amr_carve(sbm_amr_ctx *c, char *base) {
       l.blk = cv.take<uint8_t>(l.nblocks());
       l.cls = cv.take<uint8_t>(l.L.g.nn);
       l.clo = cv.take<uint8_t>(l.L.g.nn);
+      l.gids = cv.take<int>(l.L.g.nn);
+      const int64_t ncb = (l.L.g.nn + 4 * kBlock - 1) / (4 * kBlock);
+      l.gcnt = cv.take<int>(ncb);
+      l.goff = cv.take<int>(ncb);
       l.tiled = tiled_ok(l.L) && tile_geom_of(l.L).ntiles <= num_blocks(l.L.g.nn);
       if (l.tiled) {
-        l.tflags = cv.take<int>(tile_geom_of(l.L).ntiles);
-        l.tids = cv.take<int>(tile_geom_of(l.L).ntiles);
+        // sized for the most tiles the set-up may list: the default chunks
+        // or the shallowest ones it may choose
+        const int nt = std::max(tile_geom_of(l.L).ntiles, tile_geom_of(l.L, kAmrKzMin).ntiles);
+        l.tflags = cv.take<int>(nt);
+        l.tids = cv.take<int>(nt);
       }
     }
     if (a < A) l.tags = cv.take<uint8_t>(l.L.g.nc);
@@ -1011,7 +1119,7 @@ static hipError_t amr_fas(sbm_amr_ctx *c, int a) {
   }
   {
     AmrProf pr(c, SBM_PROF_GHOST, fin);
-    if ((e = launch_ghost<T>(F.L, C.L, F.cls, xc, xf, c->st, F.tiles())) != hipSuccess) return e;
+    if ((e = launch_ghost_list<T>(F.L, C.L, F.gl, xc, xf, c->st)) != hipSuccess) return e;
   }
   return amr_smooth<T>(c, a, xf, ff, tf, c->opt.nu_post);
 }
@@ -1022,8 +1130,8 @@ static sbm_status amr_comp_residual(sbm_amr_ctx *c, double *const *x, double *co
                                     double *const *r, bool sync) {
   const int A = c->A;
   for (int a = 1; a <= A; ++a)
-    AMR_HIP(launch_ghost<double>(c->lv[a].L, c->lv[a - 1].L, c->lv[a].cls, x[a - 1], x[a], c->st,
-                                 c->lv[a].tiles()));
+    AMR_HIP(launch_ghost_list<double>(c->lv[a].L, c->lv[a - 1].L, c->lv[a].gl, x[a - 1], x[a],
+                                      c->st));
   for (int a = A; a >= 0; --a) {
     AmrLevel &l = c->lv[a];
     AmrProf pr(c, SBM_PROF_NORM, a == A);
@@ -1296,8 +1404,12 @@ sbm_status sbm_amr_set_problem(sbm_amr_ctx *c, const double *const *psi_raw,
   // active column tiles of the tiled levels (their counts read back below)
   for (int a = 1; a <= A; ++a) {
     AmrLevel &l = c->lv[a];
-    l.tl = TileList{l.tids, 0};
+    l.tl = TileList{l.tids, 0, 0};
     if (l.tiled) AMR_HIP(launch_active_tiles(l.L, l.cls, l.tflags, l.tids, c->iflag + 8 + a, c->st));
+    // the ghost nodes (classes 2-4), filled from the coarser level by a list
+    // of their ids rather than by a pass over the level or its tiles
+    l.gl = GhostList{l.gids, 0};
+    AMR_HIP(launch_ghost_listing(l.L, l.cls, l.gcnt, l.goff, l.gids, c->iflag + 12 + a, c->st));
   }
   // psi of covered coarse cells, finest first
   for (int a = A; a >= 1; --a) {
@@ -1324,8 +1436,35 @@ sbm_status sbm_amr_set_problem(sbm_amr_ctx *c, const double *const *psi_raw,
   int flags = 0, iv[16];
   memcpy(iv, c->host, sizeof(iv));
   flags = iv[0];
-  for (int a = 1; a <= A; ++a)
+  for (int a = 1; a <= A; ++a) {
     if (c->lv[a].tiled) c->lv[a].tl.count = iv[8 + a];
+    c->lv[a].gl.count = iv[12 + a];
+  }
+  // A level whose active tiles are few for the GPU (a fraction of its
+  // default tile count) lists them again in shallower chunks, so that the
+  // tiled kernels run about kAmrTiles workgroups: each chunk then re-reads
+  // two more planes per kz, but the CUs are no longer half idle.
+  bool relisted = false;
+  for (int a = 1; a <= A; ++a) {
+    AmrLevel &l = c->lv[a];
+    if (!l.tiled || l.tl.count == 0) continue;
+    const int kz0 = tile_geom_of(l.L).kz;
+    const int kz = std::max(kAmrKzMin, std::min(kz0, (int)((int64_t)kz0 * l.tl.count / kAmrTiles)));
+    // every listed tile-plane writes one partial sum of the level's share
+    const TileGeom tn = tile_geom_of(l.L, kz);
+    if (kz >= kz0 || (int64_t)tn.ntiles * tn.kz > num_blocks(l.L.g.nn)) continue;
+    l.tl.kz = kz;
+    AMR_HIP(launch_fill<int>(c->iflag + 8 + a, 1, 0, c->st));
+    AMR_HIP(launch_active_tiles(l.L, l.cls, l.tflags, l.tids, c->iflag + 8 + a, c->st, kz));
+    relisted = true;
+  }
+  if (relisted) {
+    AMR_HIP(hipMemcpyAsync(c->host, c->iflag, 16 * sizeof(int), hipMemcpyDeviceToHost, c->st));
+    AMR_HIP(hipStreamSynchronize(c->st));
+    memcpy(iv, c->host, sizeof(iv));
+    for (int a = 1; a <= A; ++a)
+      if (c->lv[a].tiled) c->lv[a].tl.count = iv[8 + a];
+  }
   // tiled levels write partial sums for their listed tiles only
   AMR_HIP(launch_fill<double>(c->partials, c->npart, 0.0, c->st));
   if (flags & 1) return amr_fail(SBM_E_NONFINITE, "NaN/Inf in psi");
@@ -1401,8 +1540,8 @@ sbm_status sbm_amr_ghost_fill(sbm_amr_ctx *c, int level, const double *xc, doubl
   if (level < 1 || level > c->A) return amr_fail(SBM_E_ARG, "level must be 1..levels-1");
   if (!xc || !xf) return amr_fail(SBM_E_ARG, "NULL argument");
   if (xc == xf) return amr_fail(SBM_E_ARG, "xf must not alias xc");
-  AMR_HIP(launch_ghost<double>(c->lv[level].L, c->lv[level - 1].L, c->lv[level].cls, xc, xf,
-                               c->st, c->lv[level].tiles()));
+  AMR_HIP(launch_ghost_list<double>(c->lv[level].L, c->lv[level - 1].L, c->lv[level].gl, xc, xf,
+                                    c->st));
   return SBM_OK;
 }
 
@@ -1496,8 +1635,8 @@ sbm_status sbm_amr_solve(sbm_amr_ctx *c, double *const *u, double *hist_host, in
     AMR_TRY(amr_inject_all(c, u));
   }
   for (int a = 1; a <= A; ++a)
-    AMR_HIP(launch_ghost<double>(c->lv[a].L, c->lv[a - 1].L, c->lv[a].cls, u[a - 1], u[a], c->st,
-                                 c->lv[a].tiles()));
+    AMR_HIP(launch_ghost_list<double>(c->lv[a].L, c->lv[a - 1].L, c->lv[a].gl, u[a - 1], u[a],
+                                      c->st));
   AMR_HIP(hipStreamSynchronize(c->st));
   if (n_cycles_host) *n_cycles_host = m;
   if (final_rel_host) *final_rel_host = rho;

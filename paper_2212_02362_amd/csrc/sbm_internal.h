@@ -51,11 +51,15 @@ struct TileGeom {
   int ntx, nty, kz, ntiles;
   int xface, yface, nface;
 };
-TileGeom tile_geom_of(const Level &L);
-// A subset of a level's tiles (device ids in increasing order).
+// Tiles of level L in chunks of kz planes (0: the default depth, chosen so
+// that the whole level gives about 1536 tiles).
+TileGeom tile_geom_of(const Level &L, int kz = 0);
+// A subset of a level's tiles (device ids in increasing order) and the chunk
+// depth they were listed with.
 struct TileList {
   const int *ids = nullptr;
   int count = 0;
+  int kz = 0;
 };
 
 // ---------------------------------------------------------------- launchers
@@ -79,7 +83,7 @@ hipError_t launch_rb_half(const Level &L, const T *psi, const Coef<T> &C, const 
 // Tiles of level L holding a node of class >= 1: flags[ntiles] scratch,
 // ids[ntiles] and *count (device) out.
 hipError_t launch_active_tiles(const Level &L, const uint8_t *cls, int *flags, int *ids,
-                               int *count, hipStream_t st);
+                               int *count, hipStream_t st, int kz = 0);
 
 // Residual-norm partials of u (as launch_residual with partials, counted by
 // stencil_partials) together with the colour half-sweep of u into u_out (same

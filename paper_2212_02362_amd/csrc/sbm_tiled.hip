@@ -47,7 +47,7 @@ __device__ __forceinline__ bool tg_dirichlet(const TG &g, int i, int j, int k, i
 // faces: the last node column / row of a 2^n + 1 level go to node-parallel
 // face blocks (launches over the whole level only; tile lists and the fused
 // sweep keep whole tiles).
-TileGeom tile_geom(const TG &g, bool faces = false);
+TileGeom tile_geom(const TG &g, bool faces = false, int kz_set = 0);
 
 // Face node f of a launch with face blocks: the last column x = nx-1 (all
 // rows) first, then the last row y = ny-1 (the other columns), plane by plane.
@@ -78,7 +78,7 @@ __device__ __forceinline__ int tile_or_face(int ntl) {
   return (b & 7) * (nt8 >> 3) + (b >> 3);
 }
 
-TileGeom tile_geom(const TG &g, bool faces) {
+TileGeom tile_geom(const TG &g, bool faces, int kz_set) {
   TileGeom t;
   t.xface = faces && g.nx > TX && g.nx % TX == 1;
   t.yface = faces && g.ny > TY && g.ny % TY == 1;
@@ -89,7 +89,7 @@ TileGeom tile_geom(const TG &g, bool faces) {
   const int cols = t.ntx * t.nty;
   // enough workgroups to fill 256 CUs several times over; each chunk re-reads
   // two planes
-  int kz = (int)((int64_t)g.nz * cols / kTileWG);
+  int kz = kz_set > 0 ? kz_set : (int)((int64_t)g.nz * cols / kTileWG);
   kz = kz < 4 ? 4 : (kz > kTileKzMax ? kTileKzMax : kz);
   t.kz = kz;
   t.ntiles = cols * ((g.nz + kz - 1) / kz);
@@ -955,9 +955,9 @@ __global__ __launch_bounds__(NT) void k_rb_fused(TG g, Coef<T> C, const T *__res
 }  // namespace
 
 hipError_t launch_active_tiles(const Level &L, const uint8_t *cls, int *flags, int *ids,
-                               int *count, hipStream_t st) {
+                               int *count, hipStream_t st, int kz) {
   const TG gg = make_tg(L.g);
-  const TileGeom tg = tile_geom(gg);
+  const TileGeom tg = tile_geom(gg, false, kz);
   (void)hipGetLastError();
   hipLaunchKernelGGL(k_tile_flags, dim3(tg.ntiles), dim3(256), 0, st, gg, tg, cls, flags);
   hipLaunchKernelGGL(k_tile_compact, dim3(1), dim3(1024), 0, st, (const int *)flags, tg.ntiles,
@@ -971,7 +971,7 @@ bool tiled_ok(const Level &L) {
   return L.g.dim == 3 && L.g.nx > 3 * TX && L.g.ny > 3 * TY;
 }
 
-TileGeom tile_geom_of(const Level &L) { return tile_geom(make_tg(L.g)); }
+TileGeom tile_geom_of(const Level &L, int kz) { return tile_geom(make_tg(L.g), false, kz); }
 
 // Blocks of a tiled launch: n tiles rounded up to a multiple of 8, then the
 // face blocks.
@@ -982,7 +982,7 @@ hipError_t launch_rb_tiled(const Level &L, const T *psi, const Coef<T> &C, const
                            T *u_out, double omega, int colour, hipStream_t st,
                            const uint8_t *cls, const TileList *tl) {
   const TG gg = make_tg(L.g);
-  const TileGeom tg = tile_geom(gg, tl == nullptr);
+  const TileGeom tg = tile_geom(gg, tl == nullptr, tl ? tl->kz : 0);
   const int n = tl ? tl->count : tg.ntiles;
   if (n == 0 && tg.nface == 0) return hipSuccess;
   const int grid = tiled_grid(tg, n);
@@ -1030,7 +1030,7 @@ hipError_t launch_residual_tiled(const Level &L, const T *psi, const Coef<T> &C,
                                  const T *f, T *r, double *partials, hipStream_t st,
                                  const uint8_t *cls, const TileList *tl) {
   const TG gg = make_tg(L.g);
-  const TileGeom tg = tile_geom(gg, tl == nullptr);
+  const TileGeom tg = tile_geom(gg, tl == nullptr, tl ? tl->kz : 0);
   const int n = tl ? tl->count : tg.ntiles;
   if (n == 0 && tg.nface == 0) return hipSuccess;
   const int grid = tiled_grid(tg, n);
