@@ -62,6 +62,15 @@ struct TileList {
   int kz = 0;
 };
 
+// A node vector read by the Krylov kernels: given in memory (z), or as
+// s * e with e the FP32 correction of the mixed preconditioner and s = *s
+// (the scaled-back preconditioned residual, never written out in FP64).
+struct ZSrc {
+  const double *z = nullptr;
+  const float *e = nullptr;
+  const double *s = nullptr;
+};
+
 // ---------------------------------------------------------------- launchers
 // All launchers enqueue on `st` and return the launch status.
 template <typename T>
@@ -142,8 +151,10 @@ hipError_t launch_rhs(const Level &L, const Traction &tr, const double *b, doubl
                       hipStream_t st);
 hipError_t launch_check_diag(const Level &L, int *flag, hipStream_t st);
 hipError_t launch_finalize_sum(const double *partials, int n, double *out, hipStream_t st);
-hipError_t launch_dot_free(const Level &L, const double *a, const double *b, double *partials,
+hipError_t launch_dot_free(const Level &L, const double *a, const ZSrc &b, double *partials,
                            hipStream_t st);
+// *s_out = sqrt(*ss) (the scale of the mixed preconditioner's output).
+hipError_t launch_store_sqrt(const double *ss, double *s_out, hipStream_t st);
 hipError_t launch_sumsq_free(const Level &L, const double *v, double *partials, hipStream_t st);
 hipError_t launch_apply_dot(const Level &L, const double *p, double *q, double *partials,
                            hipStream_t st);
@@ -151,10 +162,10 @@ hipError_t launch_apply_dot(const Level &L, const double *p, double *q, double *
 // (alpha = rz / pq, stored to *alpha_out) with the r.r and r.z partials; then
 // x += (*alpha) p (alpha may be NULL) and p = z + beta p in one pass; or
 // x += (*alpha) p alone.
-hipError_t launch_cg_update_r(const Level &L, double *r, const double *q, const double *z,
+hipError_t launch_cg_update_r(const Level &L, double *r, const double *q, const ZSrc &z,
                               const double *rz, const double *pq, double *alpha_out, double *pr,
                               double *pz, hipStream_t st);
-hipError_t launch_xpby_x(const Level &L, double *x, double *p, const double *z,
+hipError_t launch_xpby_x(const Level &L, double *x, double *p, const ZSrc &z,
                          const double *rznew, const double *rzold, const double *rz,
                          const double *alpha, hipStream_t st);
 hipError_t launch_axpy_free(const Level &L, double *x, const double *p, const double *alpha,
@@ -173,8 +184,6 @@ hipError_t launch_scale_cast_sweep(const Level &L, const double *r, float *r32, 
                                    double omega, int colour, const double *ss, hipStream_t st);
 hipError_t launch_cast_scaled(const double *r, float *r32, int64_t n, const double *ss,
                               hipStream_t st);
-hipError_t launch_scale_set(double *z, const float *e32, int64_t n, const double *ss,
-                            hipStream_t st);
 int num_blocks(int64_t n);
 // Grid of the XCD-ordered stencil kernels over n items (>= num_blocks(n)).
 int grid_blocks(int64_t n);

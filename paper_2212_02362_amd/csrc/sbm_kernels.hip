@@ -583,10 +583,14 @@ __global__ __launch_bounds__(kBlock) void k_sumsq_free(Geom g, const double *__r
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
+// An entry of a Krylov vector given in memory or as s * e (s = sc here).
+__device__ __forceinline__ double zload(const ZSrc &zs, double sc, int64_t q) {
+  return zs.z ? zs.z[q] : sc * (double)zs.e[q];
+}
+
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_dot_free(Geom g, const double *__restrict__ a,
-                                                     const double *__restrict__ b,
-                                                     double *__restrict__ partials) {
+                                                     ZSrc b, double *__restrict__ partials) {
   __shared__ double lds[kBlock / 64 + 1];
   const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   double ss = 0.0;
@@ -594,11 +598,12 @@ __global__ __launch_bounds__(kBlock) void k_dot_free(Geom g, const double *__res
     int i, j, k;
     node_ijk(g, id, i, j, k);
     // all loads first (one memory round trip), displacement DOF masked after
+    const double sb = b.z ? 0.0 : *b.s;
     double av[3], bv[3];
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
       av[c] = a[c * g.nn + id];
-      bv[c] = b[c * g.nn + id];
+      bv[c] = zload(b, sb, c * g.nn + id);
     }
     const uint32_t fb = face_bits(g, i, j, k);
 #pragma unroll
@@ -647,8 +652,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_dot(Geom g, Coef<double> C,
 // k_axpy_free: the same products, one vector pass fewer.
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_cg_update_r(Geom g, double *__restrict__ r,
-                                                        const double *__restrict__ q,
-                                                        const double *__restrict__ z,
+                                                        const double *__restrict__ q, ZSrc z,
                                                         const double *__restrict__ rz,
                                                         const double *__restrict__ pq,
                                                         double *__restrict__ alpha_out,
@@ -662,13 +666,14 @@ __global__ __launch_bounds__(kBlock) void k_cg_update_r(Geom g, double *__restri
   if (id < g.nn) {
     int i, j, k;
     node_ijk(g, id, i, j, k);
+    const double sz = z.z ? 0.0 : *z.s;
     double rv[3], qv[3], zv[3];
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
       const int64_t qi = c * g.nn + id;
       rv[c] = r[qi];
       qv[c] = q[qi];
-      zv[c] = z[qi];
+      zv[c] = zload(z, sz, qi);
     }
     const uint32_t fb = face_bits(g, i, j, k);
 #pragma unroll
@@ -694,8 +699,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update_r(Geom g, double *__restri
 // rzold) / rz (beta = 0 when rz is NULL: restart); p = 0 on displacement DOF.
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_xpby_x(Geom g, double *__restrict__ x,
-                                                   double *__restrict__ p,
-                                                   const double *__restrict__ z,
+                                                   double *__restrict__ p, ZSrc z,
                                                    const double *__restrict__ rznew,
                                                    const double *__restrict__ rzold,
                                                    const double *__restrict__ rz,
@@ -706,10 +710,11 @@ __global__ __launch_bounds__(kBlock) void k_xpby_x(Geom g, double *__restrict__ 
   const double al = alpha ? *alpha : 0.0;
   int i, j, k;
   node_ijk(g, id, i, j, k);
+  const double sz = z.z ? 0.0 : *z.s;
   double zv[3], pv[3], xv[3];
 #pragma unroll
   for (int c = 0; c < DIM; ++c) {
-    zv[c] = z[c * g.nn + id];
+    zv[c] = zload(z, sz, c * g.nn + id);
     pv[c] = p[c * g.nn + id];
     xv[c] = alpha ? x[c * g.nn + id] : 0.0;
   }
@@ -738,8 +743,9 @@ __global__ __launch_bounds__(kBlock) void k_axpy_free(Geom g, double *__restrict
     if (!((g.dmask >> c) & fb)) x[c * g.nn + id] += al * p[c * g.nn + id];
 }
 
-// r32 = fp32(r / s) and z = s * e32 (s = sqrt(*ss)): the FP32 preconditioner
-// of the mixed flexible CG sees a unit-norm residual.
+// r32 = fp32(r / s) (s = sqrt(*ss)): the FP32 preconditioner of the mixed
+// flexible CG sees a unit-norm residual; its output e32 is used as s * e32
+// (ZSrc) without being written out in FP64.
 __global__ __launch_bounds__(kBlock) void k_cast_scaled(const double *__restrict__ r,
                                                         float *__restrict__ r32, int64_t n,
                                                         const double *__restrict__ ss) {
@@ -792,12 +798,8 @@ __global__ __launch_bounds__(kBlock) void k_scale_cast_sweep(Geom g, Coef<float>
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_scale_set(double *__restrict__ z,
-                                                      const float *__restrict__ e32, int64_t n,
-                                                      const double *__restrict__ ss) {
-  const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (q >= n) return;
-  z[q] = sqrt(*ss) * (double)e32[q];
+__global__ void k_store_sqrt(const double *__restrict__ ss, double *__restrict__ s_out) {
+  if (threadIdx.x == 0) *s_out = sqrt(*ss);
 }
 
 // ----------------------------------------------------------------- bottom --
@@ -1281,7 +1283,7 @@ hipError_t launch_finalize_sum(const double *partials, int n, double *out, hipSt
   SBM_LAUNCH(k_finalize_sum, 1, 1024, st, partials, n, out);
 }
 
-hipError_t launch_dot_free(const Level &L, const double *a, const double *b, double *partials,
+hipError_t launch_dot_free(const Level &L, const double *a, const ZSrc &b, double *partials,
                            hipStream_t st) {
   if (L.g.dim == 3) SBM_LAUNCH((k_dot_free<3>), num_blocks(L.g.nn), kBlock, st, L.g, a, b, partials);
   SBM_LAUNCH((k_dot_free<2>), num_blocks(L.g.nn), kBlock, st, L.g, a, b, partials);
@@ -1295,7 +1297,7 @@ hipError_t launch_apply_dot(const Level &L, const double *p, double *q, double *
   SBM_LAUNCH((k_apply_dot<2>), grid_blocks(L.g.nn), kBlock, st, L.g, L.c64, L.psi64, p, q, partials);
 }
 
-hipError_t launch_cg_update_r(const Level &L, double *r, const double *q, const double *z,
+hipError_t launch_cg_update_r(const Level &L, double *r, const double *q, const ZSrc &z,
                               const double *rz, const double *pq, double *alpha_out, double *pr,
                               double *pz, hipStream_t st) {
   if (L.g.dim == 3)
@@ -1305,7 +1307,7 @@ hipError_t launch_cg_update_r(const Level &L, double *r, const double *q, const 
              pr, pz);
 }
 
-hipError_t launch_xpby_x(const Level &L, double *x, double *p, const double *z,
+hipError_t launch_xpby_x(const Level &L, double *x, double *p, const ZSrc &z,
                          const double *rznew, const double *rzold, const double *rz,
                          const double *alpha, hipStream_t st) {
   if (L.g.dim == 3)
@@ -1370,9 +1372,8 @@ hipError_t launch_scale_cast_sweep(const Level &L, const double *r, float *r32, 
              t32, (float)omega, colour, ss);
 }
 
-hipError_t launch_scale_set(double *z, const float *e32, int64_t n, const double *ss,
-                            hipStream_t st) {
-  SBM_LAUNCH(k_scale_set, num_blocks(n), kBlock, st, z, e32, n, ss);
+hipError_t launch_store_sqrt(const double *ss, double *s_out, hipStream_t st) {
+  SBM_LAUNCH(k_store_sqrt, 1, 64, st, ss, s_out);
 }
 
 hipError_t launch_sumsq_free(const Level &L, const double *v, double *partials, hipStream_t st) {

@@ -583,7 +583,9 @@ static hipError_t cycle_body(sbm_ctx *c, const double *f, int mode) {
       c->first_half_done = false;
       c->zero_start = false;
       if (e != hipSuccess) return e;
-      return launch_scale_set(c->kz, L0.e32, nv, c->scal, c->st);
+      // z = s e32 with s = ||kr|| kept in scal[6]: the Krylov kernels read e32
+      // and scale it themselves (the FP64 z is never written)
+      return launch_store_sqrt(c->scal, c->scal + 6, c->st);
     }
     if (zs && c->tail64 != 0) {
       c->zero_start = true;
@@ -727,6 +729,9 @@ static sbm_status solve_krylov(sbm_ctx *c, const double *f, double fnorm, double
   const int ns = stencil_partials(L0);      // residual / Apply kernels
   double rho_min = INFINITY, rho = 0.0;
   sbm_status status = SBM_NOT_CONVERGED;
+  // the preconditioned residual: kz, or (mixed) scal[6] * the FP32 correction
+  const ZSrc z = c->opt.precision == 1 ? ZSrc{nullptr, L0.e32, c->scal + 6}
+                                       : ZSrc{c->kz, nullptr, nullptr};
   HIP_TRY(launch_copy<double>(u, c->x0, nv, c->st));
   {
     ProfScope ps(c, SBM_PROF_NORM, true);
@@ -759,9 +764,9 @@ static sbm_status solve_krylov(sbm_ctx *c, const double *f, double fnorm, double
     }
     if (restart) {
       SBM_TRY(run_cycle(c, nullptr, 1));
-      HIP_TRY(launch_dot_free(L0, c->kr, c->kz, c->partials, c->st));
+      HIP_TRY(launch_dot_free(L0, c->kr, z, c->partials, c->st));
       HIP_TRY(launch_finalize_sum(c->partials, nb, c->scal + 4, c->st));
-      HIP_TRY(launch_xpby_x(L0, c->x0, c->kp, c->kz, nullptr, nullptr, nullptr, nullptr, c->st));
+      HIP_TRY(launch_xpby_x(L0, c->x0, c->kp, z, nullptr, nullptr, nullptr, nullptr, c->st));
       restart = false;
     }
     HIP_TRY(launch_apply_dot(L0, c->kp, c->kq, c->partials, c->st));
@@ -774,7 +779,7 @@ static sbm_status solve_krylov(sbm_ctx *c, const double *f, double fnorm, double
     }
     // r -= alpha q; the iterate update x += alpha p (alpha kept in scal[5]) is
     // made by the next direction update, or below when the iteration ends
-    HIP_TRY(launch_cg_update_r(L0, c->kr, c->kq, c->kz, c->scal + 4, c->scal + 2, c->scal + 5,
+    HIP_TRY(launch_cg_update_r(L0, c->kr, c->kq, z, c->scal + 4, c->scal + 2, c->scal + 5,
                                c->partials, c->partials2, c->st));
     SBM_TRY(fin_to_host(c, c->partials, nb, 0));
     SBM_TRY(fin_to_host(c, c->partials2, nb, 3));
@@ -798,9 +803,9 @@ static sbm_status solve_krylov(sbm_ctx *c, const double *f, double fnorm, double
     }
     if (hist && m < cap) hist[m] = rho;
     SBM_TRY(run_cycle(c, nullptr, 1));
-    HIP_TRY(launch_dot_free(L0, c->kr, c->kz, c->partials, c->st));
+    HIP_TRY(launch_dot_free(L0, c->kr, z, c->partials, c->st));
     HIP_TRY(launch_finalize_sum(c->partials, nb, c->scal + 1, c->st));
-    HIP_TRY(launch_xpby_x(L0, c->x0, c->kp, c->kz, c->scal + 1, c->scal + 3, c->scal + 4,
+    HIP_TRY(launch_xpby_x(L0, c->x0, c->kp, z, c->scal + 1, c->scal + 3, c->scal + 4,
                           c->scal + 5, c->st));
     HIP_TRY(launch_copy<double>(c->scal + 1, c->scal + 4, 1, c->st));
   }
@@ -1352,7 +1357,7 @@ sbm_status sbm_compliance(sbm_ctx *c, const double *u, double *J) {
   NEED_PROBLEM(c);
   if (!u || !J) return fail(SBM_E_ARG, "NULL argument");
   Level &L0 = c->L[0];
-  HIP_TRY(launch_dot_free(L0, L0.f, u, c->partials, c->st));
+  HIP_TRY(launch_dot_free(L0, L0.f, ZSrc{u, nullptr, nullptr}, c->partials, c->st));
   HIP_TRY(launch_finalize_sum(c->partials, num_blocks(L0.g.nn), c->scal, c->st));
   HIP_TRY(hipMemcpyAsync(c->host, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->st));
   HIP_TRY(hipStreamSynchronize(c->st));
