@@ -93,11 +93,32 @@ __device__ __forceinline__ void cell_ijk(const Geom &g, int64_t id, int &i, int 
   j = (int)(row - (uint32_t)k * (uint32_t)g.cy);
 }
 
+// Coefficients of a level with cubic cells (h equal on every axis): the
+// direct coefficients take two values (diagonal i == j, off-diagonal) and the
+// cross coefficients one per kind, so a kernel needs 4 scalars instead of 15.
+template <typename T>
+struct CoefCubic {
+  T dd, od, p, m;
+};
+template <typename T>
+__device__ __forceinline__ T coef_cd(const Coef<T> &C, int i, int j) { return C.cd[i][j]; }
+template <typename T>
+__device__ __forceinline__ T coef_cp(const Coef<T> &C, int pl) { return C.cp[pl]; }
+template <typename T>
+__device__ __forceinline__ T coef_cm(const Coef<T> &C, int pl) { return C.cm[pl]; }
+template <typename T>
+__device__ __forceinline__ T coef_cd(const CoefCubic<T> &C, int i, int j) { return i == j ? C.dd : C.od; }
+template <typename T>
+__device__ __forceinline__ T coef_cp(const CoefCubic<T> &C, int) { return C.p; }
+template <typename T>
+__device__ __forceinline__ T coef_cm(const CoefCubic<T> &C, int) { return C.m; }
+
 // 3D eq. K at one node: P[c2][c1][c0] is the psi of cell (i-1+c0, j-1+c1,
 // k-1+c2) (0 outside the box) and U(c, dx, dy, dz) the c-th displacement at the
-// neighbour (i+dx, j+dy, k+dz).  Writes (K u)(n) and the diagonal of K.
-template <typename T, typename UF>
-__device__ __forceinline__ void stencil3(const Coef<T> &C, const T (&P)[2][2][2], UF &&U,
+// neighbour (i+dx, j+dy, k+dz).  Writes (K u)(n) and the diagonal of K.  C is a
+// Coef<T> or a CoefCubic<T>.
+template <typename T, typename CO, typename UF>
+__device__ __forceinline__ void stencil3(const CO &C, const T (&P)[2][2][2], UF &&U,
                                          T out[3], T diag[3]) {
   T E[3][2];
 #pragma unroll
@@ -113,18 +134,18 @@ __device__ __forceinline__ void stencil3(const Coef<T> &C, const T (&P)[2][2][2]
     const T xp = U(c, 1, 0, 0) - uc, xm = U(c, -1, 0, 0) - uc;
     const T yp = U(c, 0, 1, 0) - uc, ym = U(c, 0, -1, 0) - uc;
     const T zp = U(c, 0, 0, 1) - uc, zm = U(c, 0, 0, -1) - uc;
-    out[c] = -(C.cd[c][0] * (E[0][1] * xp + E[0][0] * xm) +
-               C.cd[c][1] * (E[1][1] * yp + E[1][0] * ym) +
-               C.cd[c][2] * (E[2][1] * zp + E[2][0] * zm));
-    diag[c] = C.cd[c][0] * (E[0][0] + E[0][1]) + C.cd[c][1] * (E[1][0] + E[1][1]) +
-              C.cd[c][2] * (E[2][0] + E[2][1]);
+    out[c] = -(coef_cd(C, c, 0) * (E[0][1] * xp + E[0][0] * xm) +
+               coef_cd(C, c, 1) * (E[1][1] * yp + E[1][0] * ym) +
+               coef_cd(C, c, 2) * (E[2][1] * zp + E[2][0] * zm));
+    diag[c] = coef_cd(C, c, 0) * (E[0][0] + E[0][1]) + coef_cd(C, c, 1) * (E[1][0] + E[1][1]) +
+              coef_cd(C, c, 2) * (E[2][0] + E[2][1]);
   }
   // cross part, plane (a, b) with third axis m
 #pragma unroll
   for (int pl = 0; pl < 3; ++pl) {
     const int a = (pl == 2) ? 1 : 0;
     const int b = (pl == 0) ? 1 : 2;
-    const T cp = C.cp[pl], cm = C.cm[pl];
+    const T cp = coef_cp(C, pl), cm = coef_cm(C, pl);
     const T ua0 = U(a, 0, 0, 0), ub0 = U(b, 0, 0, 0);
     T ra = T(0), rb = T(0);
 #pragma unroll
@@ -158,8 +179,8 @@ __device__ __forceinline__ void stencil3(const Coef<T> &C, const T (&P)[2][2][2]
 // ctr (optional) receives u at the node itself.  GATHER keeps every load
 // ahead of the arithmetic (a scheduling barrier); without it the compiler may
 // interleave them, which needs fewer registers.
-template <typename T, int DIM, bool GATHER = true, typename G = Geom>
-__device__ __forceinline__ void node_stencil(const G &g, const Coef<T> &C,
+template <typename T, int DIM, bool GATHER = true, typename G = Geom, typename CO = Coef<T>>
+__device__ __forceinline__ void node_stencil(const G &g, const CO &C,
                                              const T *__restrict__ psi,
                                              const T *__restrict__ u, int i, int j, int k,
                                              T out[3], T diag[3], T *ctr = nullptr) {
@@ -270,11 +291,11 @@ __device__ __forceinline__ void node_stencil(const G &g, const Coef<T> &C,
       const T uc = U(c, 0, 0);
       const T xp = U(c, 1, 0) - uc, xm = U(c, -1, 0) - uc;
       const T yp = U(c, 0, 1) - uc, ym = U(c, 0, -1) - uc;
-      out[c] = -(C.cd[c][0] * (E[0][1] * xp + E[0][0] * xm) +
-                 C.cd[c][1] * (E[1][1] * yp + E[1][0] * ym));
-      diag[c] = C.cd[c][0] * (E[0][0] + E[0][1]) + C.cd[c][1] * (E[1][0] + E[1][1]);
+      out[c] = -(coef_cd(C, c, 0) * (E[0][1] * xp + E[0][0] * xm) +
+                 coef_cd(C, c, 1) * (E[1][1] * yp + E[1][0] * ym));
+      diag[c] = coef_cd(C, c, 0) * (E[0][0] + E[0][1]) + coef_cd(C, c, 1) * (E[1][0] + E[1][1]);
     }
-    const T cp = C.cp[0], cm = C.cm[0];
+    const T cp = coef_cp(C, 0), cm = coef_cm(C, 0);
     const T ux0 = U(0, 0, 0), uy0 = U(1, 0, 0);
     T rx = T(0), ry = T(0);
 #pragma unroll

@@ -25,8 +25,6 @@ constexpr int NT = TX / 2 * TY;             // threads: one x-pair per thread
 constexpr int PLANE = LY * LX;              // LDS entries per component and plane
 constexpr int NU = 3 * PLANE;
 constexpr int NUPT = (NU + NT - 1) / NT;
-constexpr int NP = CYL * CXL;
-constexpr int NPPT = (NP + NT - 1) / NT;
 
 // The level geometry the tiled kernels need (3D only; fewer scalar registers
 // than Geom).
@@ -67,17 +65,6 @@ __device__ __forceinline__ bool face_node(const TG &g, const TileGeom &tg, int f
   return true;
 }
 
-// Hardware block b of a launch over ntl tiles: the tiles first, in the
-// XCD-ordered numbering of the first ntl rounded up to 8 blocks; the face
-// blocks last (short node-parallel blocks that fill the slots the last tiles
-// leave idle).  Returns the logical tile, or -1 - fb for face block fb.
-__device__ __forceinline__ int tile_or_face(int ntl) {
-  const int nt8 = (ntl + 7) / 8 * 8;
-  const int b = blockIdx.x;
-  if (b >= nt8) return -1 - (b - nt8);
-  return (b & 7) * (nt8 >> 3) + (b >> 3);
-}
-
 TileGeom tile_geom(const TG &g, bool faces, int kz_set) {
   TileGeom t;
   t.xface = faces && g.nx > TX && g.nx % TX == 1;
@@ -96,244 +83,343 @@ TileGeom tile_geom(const TG &g, bool faces, int kz_set) {
   return t;
 }
 
-// Per-thread load slots of one plane: global offsets without the z term
-// (-1 outside the box or past the tile's entries).
-struct Slots {
-  int u[NUPT];
-  int p[NPPT];
-};
+// ---------------------------------------------------------------- buffers
+//
+// The tiled kernels address u, f, psi and the outputs through raw buffer
+// descriptors: the per-thread byte offset within a plane (a VGPR computed once)
+// plus the plane's offset (an SGPR) is added by the memory unit, and an offset
+// at or past the buffer's size reads 0 and drops a store.  Halo entries
+// outside the box therefore load as the zeros eq. K needs there, with no
+// select per value, and a thread without a node stores nothing.  Offsets stay
+// below 2^31 (tiled_ok limits a level's vector to that many bytes).
+constexpr int kOOB = 0x7ffffff8;    // byte offset past every buffer
+constexpr int kRsrcW3 = 0x00020000; // descriptor word 3: 32-bit data format, raw access
 
-__device__ __forceinline__ void make_slots(const TG &g, int x0, int y0, Slots &s) {
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, bytes, kRsrcW3);
+}
+template <typename T>
+__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  if constexpr (sizeof(T) == 8)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  else
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+typedef unsigned int u32x2 __attribute__((__vector_size__(2 * sizeof(unsigned int))));
+template <typename T>
+__device__ __forceinline__ void bstore(T v, __amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  if constexpr (sizeof(T) == 8)
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+  else
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+}
+
+// ---------------------------------------------------------------- LDS tile
+//
+// A plane of u holds 3 components x LY rows x LX columns (the tile and its
+// one-node halo); a plane of psi CYL rows of the CXL cells under them.  Each
+// row is split by parity: the even local columns first, then the odd ones, so
+// that the nodes a wave relaxes in one colour (every other column) and their
+// x-neighbours (the other parity) sit in consecutive LDS words (no bank
+// conflicts).  Local column lx is global x0 - 1 + lx.  Slots are padded to a
+// whole number of loads per thread, so every thread stores every load.
+constexpr int HUX = LX / 2;                  // columns per parity half (u rows)
+constexpr int HCX = (CXL + 1) / 2;           // the same for cell rows
+constexpr int CROW = 2 * HCX;                // LDS cell row (one pad entry)
+constexpr int NPC = CYL * CROW;             // cell entries per plane
+constexpr int NPCT = (NPC + NT - 1) / NT;
+constexpr int SLOT_U = NUPT * NT, SLOT_P = NPCT * NT;
+static_assert(LX % 2 == 0, "u rows split into two equal halves");
+
+__device__ __forceinline__ int lds_col(int lx, int half) { return (lx & 1) * half + (lx >> 1); }
+
+// Byte offsets (within a plane) of a thread's u and psi load slots, in LDS
+// order; kOOB for halo entries outside the box and for padding.
+template <int W>
+__device__ __forceinline__ void tile_slots(const TG &g, int x0, int y0, int (&vu)[NUPT],
+                                           int (&vp)[NPCT]) {
   const int t = threadIdx.x;
 #pragma unroll
-  for (int i = 0; i < NUPT; ++i) {
-    const int e = t + i * NT;
-    s.u[i] = -1;
+  for (int j = 0; j < NUPT; ++j) {
+    const int e = t + j * NT;
+    vu[j] = kOOB;
     if (e < NU) {
       const int c = e / PLANE, r = e - c * PLANE;
-      const int y = r / LX, x = r - y * LX;
-      const int gx = x0 - 1 + x, gy = y0 - 1 + y;
-      if (gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny) s.u[i] = c * g.nn + gx + g.nx * gy;
+      const int y = r / LX, xr = r - y * LX;
+      const int hf = xr >= HUX ? 1 : 0;
+      const int gx = x0 - 1 + 2 * (xr - hf * HUX) + hf, gy = y0 - 1 + y;
+      if (gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny) vu[j] = (c * g.nn + gx + g.nx * gy) * W;
     }
   }
 #pragma unroll
-  for (int i = 0; i < NPPT; ++i) {
-    const int e = t + i * NT;
-    s.p[i] = -1;
-    if (e < NP) {
-      const int y = e / CXL, x = e - y * CXL;
-      const int gx = x0 - 1 + x, gy = y0 - 1 + y;
-      if (gx >= 0 && gx < g.cx && gy >= 0 && gy < g.cy) s.p[i] = gx + g.cx * gy;
+  for (int j = 0; j < NPCT; ++j) {
+    const int e = t + j * NT;
+    vp[j] = kOOB;
+    if (e < NPC) {
+      const int y = e / CROW, xr = e - y * CROW;
+      const int hf = xr >= HCX ? 1 : 0;
+      const int lx = 2 * (xr - hf * HCX) + hf;
+      const int gx = x0 - 1 + lx, gy = y0 - 1 + y;
+      if (lx < CXL && gx >= 0 && gx < g.cx && gy >= 0 && gy < g.cy) vp[j] = (gx + g.cx * gy) * W;
     }
   }
 }
 
-// Plane loads without per-lane branches and without touching the loaded
-// values: lanes whose element lies outside the box read element 0 and the
-// zero is substituted only when the plane is stored to LDS (after the
-// compute of the current plane), so the loads stay in flight meanwhile.
-template <typename T>
-__device__ __forceinline__ void fetch_u(const TG &g, const Slots &s, const T *__restrict__ u,
-                                        int k, T (&r)[NUPT]) {
-  const int zo = (k >= 0 && k < g.nz) ? k * g.nx * g.ny : 0;
-#pragma unroll
-  for (int i = 0; i < NUPT; ++i) r[i] = u[s.u[i] >= 0 ? s.u[i] + zo : 0];
-}
+// The buffers a tiled kernel reads (rnull: an empty buffer, every load 0).
+struct TileBufs {
+  __amdgpu_buffer_rsrc_t u, f, psi, out, null;
+};
 
 template <typename T>
-__device__ __forceinline__ void fetch_p(const TG &g, const Slots &s, const T *__restrict__ psi,
-                                        int kc, T (&r)[NPPT]) {
-  const int zo = (kc >= 0 && kc < g.cz) ? kc * g.cx * g.cy : 0;
+__device__ __forceinline__ void tile_put_u(T *slot, const T (&ru)[NUPT]) {
 #pragma unroll
-  for (int i = 0; i < NPPT; ++i) r[i] = psi[s.p[i] >= 0 ? s.p[i] + zo : 0];
+  for (int j = 0; j < NUPT; ++j) slot[threadIdx.x + j * NT] = ru[j];
+}
+template <typename T>
+__device__ __forceinline__ void tile_put_p(T *slot, const T (&rp)[NPCT]) {
+#pragma unroll
+  for (int j = 0; j < NPCT; ++j) slot[threadIdx.x + j * NT] = rp[j];
 }
 
+// Loads of u plane z / cell plane zc into registers (zeros outside the box).
 template <typename T>
-__device__ __forceinline__ void put_u(const TG &g, const Slots &s, int k, T *lds,
-                                      const T (&r)[NUPT]) {
-  const bool kin = k >= 0 && k < g.nz;
+__device__ __forceinline__ void tile_fetch_u(const TG &g, const TileBufs &B, const int (&vu)[NUPT],
+                                             int z, T (&ru)[NUPT]) {
+  const bool zin = z >= 0 && z < g.nz;
+  const __amdgpu_buffer_rsrc_t r1 = zin ? B.u : B.null;
+  const int so = zin ? z * g.nx * g.ny * (int)sizeof(T) : 0;
 #pragma unroll
-  for (int i = 0; i < NUPT; ++i) {
-    const int e = threadIdx.x + i * NT;
-    if (e < NU) lds[e] = (kin && s.u[i] >= 0) ? r[i] : T(0);
+  for (int j = 0; j < NUPT; ++j) ru[j] = bload<T>(r1, vu[j], so);
+}
+template <typename T>
+__device__ __forceinline__ void tile_fetch_p(const TG &g, const TileBufs &B, const int (&vp)[NPCT],
+                                             int zc, T (&rp)[NPCT]) {
+  const bool zin = zc >= 0 && zc < g.cz;
+  const __amdgpu_buffer_rsrc_t r2 = zin ? B.psi : B.null;
+  const int sq = zin ? zc * g.cx * g.cy * (int)sizeof(T) : 0;
+#pragma unroll
+  for (int j = 0; j < NPCT; ++j) rp[j] = bload<T>(r2, vp[j], sq);
+}
+
+// The first step's planes: u k0-1..k0+1 and cells k0-1, k0 into their slots.
+template <typename T>
+__device__ __forceinline__ void tile_prologue(const TG &g, const TileBufs &B,
+                                              const int (&vu)[NUPT], const int (&vp)[NPCT],
+                                              int k0, T (*su)[SLOT_U], T (*sp)[SLOT_P]) {
+  T r0[NUPT], r1[NUPT], r2[NUPT], q0[NPCT], q1[NPCT];
+  tile_fetch_u<T>(g, B, vu, k0 - 1, r0);
+  tile_fetch_u<T>(g, B, vu, k0, r1);
+  tile_fetch_u<T>(g, B, vu, k0 + 1, r2);
+  tile_fetch_p<T>(g, B, vp, k0 - 1, q0);
+  tile_fetch_p<T>(g, B, vp, k0, q1);
+  tile_put_u<T>(su[(k0 + 2) % 3], r0);
+  tile_put_u<T>(su[k0 % 3], r1);
+  tile_put_u<T>(su[(k0 + 1) % 3], r2);
+  tile_put_p<T>(sp[(k0 + 1) & 1], q0);
+  tile_put_p<T>(sp[k0 & 1], q1);
+}
+
+// eq. K at the node of local column lx (1..TX) and row yl of the tile from the
+// LDS planes Lm / L0 / L1 (below, at, above) and the cell planes Pm / P0.
+template <typename T, typename CO>
+__device__ __forceinline__ void tile_stencil(const CO &C, const T *Lm, const T *L0, const T *L1,
+                                             const T *Pm, const T *P0, int lx, int yl, T out[3],
+                                             T dg[3]) {
+  const int row = (yl + 1) * LX;
+  const int cu = row + lds_col(lx, HUX);       // the node
+  const int cm = row + lds_col(lx - 1, HUX);   // x - 1
+  const int cp = row + lds_col(lx + 1, HUX);   // x + 1
+  const int pc0 = lds_col(lx - 1, HCX), pc1 = lds_col(lx, HCX);  // cells i-1, i
+  T P[2][2][2];
+#pragma unroll
+  for (int c1 = 0; c1 < 2; ++c1) {
+    P[0][c1][0] = Pm[(yl + c1) * CROW + pc0];
+    P[0][c1][1] = Pm[(yl + c1) * CROW + pc1];
+    P[1][c1][0] = P0[(yl + c1) * CROW + pc0];
+    P[1][c1][1] = P0[(yl + c1) * CROW + pc1];
   }
+  auto U = [&](int c, int dx, int dy, int dz) -> T {
+    const T *L = dz < 0 ? Lm : (dz > 0 ? L1 : L0);
+    return L[c * PLANE + (dx == 0 ? cu : (dx > 0 ? cp : cm)) + dy * LX];
+  };
+  stencil3<T>(C, P, U, out, dg);
 }
 
-template <typename T>
-__device__ __forceinline__ void put_p(const TG &g, const Slots &s, int kc, T *lds,
-                                      const T (&r)[NPPT]) {
-  const bool kin = kc >= 0 && kc < g.cz;
+// Hardware block b of a launch over n listed (or all) tiles: the tiles first,
+// in the XCD-ordered numbering of the first n rounded up to 8 blocks (workgroup
+// b runs on XCD b mod 8; each XCD gets a contiguous range of tiles); the face
+// blocks of a whole-level launch last (short node-parallel blocks that fill
+// the slots the last tiles leave idle).  Returns the logical tile, or -1 - fb
+// for face block fb.
+__device__ __forceinline__ int tile_or_face(int n) {
+  const int n8 = (n + 7) / 8 * 8;
+  const int b = blockIdx.x;
+  if (b >= n8) return -1 - (b - n8);
+  return (b & 7) * (n8 >> 3) + (b >> 3);
+}
+
+// A face node (last column / row of a 2^n + 1 level) of a whole-level tiled
+// half-sweep: one node per thread from global memory, the same update.
+template <typename T, typename CO, bool MASK>
+__device__ __forceinline__ void rb_face_node(const TG &g, const CO &C, const T *psi,
+                                             const T *u, const T *f, T *u_out, T omega,
+                                             int colour, const TileGeom &tg,
+                                             const uint8_t *cls, int fb) {
+  int x, y, z;
+  if (!face_node(g, tg, fb * NT + (int)threadIdx.x, x, y, z)) return;
+  const int nn = g.nn;
+  const int q = x + g.nx * (y + g.ny * z);
+  T nv[3];
+  if (((x + y + z) & 1) == colour && !(MASK && cls[q] != 1)) {
+    T out[3], dg[3], uc[3];
+    node_stencil<T, 3, true, TG, CO>(g, C, psi, u, x, y, z, out, dg, uc);
 #pragma unroll
-  for (int i = 0; i < NPPT; ++i) {
-    const int e = threadIdx.x + i * NT;
-    if (e < NP) lds[e] = (kin && s.p[i] >= 0) ? r[i] : T(0);
+    for (int c = 0; c < 3; ++c) {
+      const T upd_c = uc[c] + omega * (f[c * nn + q] - out[c]) / dg[c];
+      nv[c] = tg_dirichlet(g, x, y, z, c) ? uc[c] : upd_c;
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) nv[c] = u[c * nn + q];
   }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) u_out[c * nn + q] = nv[c];
 }
 
 // Colour-synchronous Gauss-Seidel half-sweep (nodes with (x+y+z) mod 2 ==
-// colour updated from u, the others copied to u_out), as k_rb_half.  With MASK
-// only class-1 nodes are updated.  Both nodes of a thread's x-pair are stored
-// back to back so that every written line is complete in L2.
-template <typename T, bool MASK>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_rb_tile(TG g, Coef<T> C, const T *__restrict__ psi,
-                                                   const T *__restrict__ u,
-                                                   const T *__restrict__ f,
-                                                   T *__restrict__ u_out, T omega, int colour,
-                                                   TileGeom tg, const uint8_t *__restrict__ cls,
-                                                   const int *__restrict__ ids, int nids) {
-  __shared__ T su[3][NU];
-  __shared__ T sp[2][NP];
-  const int li = tile_or_face(ids ? nids : tg.ntiles);
-  const int nn = g.nn, nxy = g.nx * g.ny;
+// colour updated from u, the others copied to u_out), as k_rb_half, over the
+// tiles and, in a whole-level launch, the face blocks.  With MASK only
+// class-1 nodes are updated.  A thread owns an x-pair (one node of each
+// colour) and stores both.  The u and psi planes of the next step and f of
+// the next plane are loaded while the current plane is computed.
+template <typename T, typename CO, bool MASK>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_rb_tile(
+    TG g, CO C, const T *__restrict__ psi, const T *__restrict__ u, const T *__restrict__ f,
+    T *__restrict__ u_out, T omega, int colour, TileGeom tg, const uint8_t *__restrict__ cls,
+    const int *__restrict__ ids, int n) {
+  __shared__ T su[3][SLOT_U];
+  __shared__ T sp[2][SLOT_P];
+  const int li = tile_or_face(n);
   if (li < 0) {
-    // a face block: one node per thread, the same update from global memory
-    int x, y, z;
-    if (-1 - li < tg.nface && face_node(g, tg, (-1 - li) * NT + (int)threadIdx.x, x, y, z)) {
-      const int q = x + g.nx * (y + g.ny * z);
-      T nv[3];
-      if (((x + y + z) & 1) == colour && !(MASK && cls[q] != 1)) {
-        T out[3], dg[3], uc[3];
-        node_stencil<T, 3>(g, C, psi, u, x, y, z, out, dg, uc);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const T upd_c = uc[c] + omega * (f[c * nn + q] - out[c]) / dg[c];
-          nv[c] = tg_dirichlet(g, x, y, z, c) ? uc[c] : upd_c;
-        }
-      } else {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) nv[c] = u[c * nn + q];
-      }
-#pragma unroll
-      for (int c = 0; c < 3; ++c) u_out[c * nn + q] = nv[c];
-    }
+    rb_face_node<T, CO, MASK>(g, C, psi, u, f, u_out, omega, colour, tg, cls, -1 - li);
     return;
   }
-  if (li >= (ids ? nids : tg.ntiles)) return;
-  const int lt = ids ? ids[li] : li;  // a subset of the tiles, or all of them
-  const int tx = lt % tg.ntx;
-  const int rest = lt / tg.ntx;
-  const int ty = rest % tg.nty;
-  const int tz = rest / tg.nty;
+  if (li >= n) return;
+  const int lt = ids ? ids[li] : li;
+  constexpr int W = sizeof(T);
+  const int nn = g.nn, nxy = g.nx * g.ny;
+  const int vbytes = 3 * nn * W;
+  const TileBufs B{make_rsrc(u, vbytes), make_rsrc(f, vbytes), make_rsrc(psi, g.cx * g.cy * g.cz * W),
+                   make_rsrc(u_out, vbytes), make_rsrc(u, 0)};
+  const int tx = lt % tg.ntx, rest = lt / tg.ntx;
+  const int ty = rest % tg.nty, tz = rest / tg.nty;
   const int x0 = tx * TX, y0 = ty * TY;
-  const int k0 = tz * tg.kz;
-  const int k1 = min(k0 + tg.kz, g.nz);
-
-  Slots sl;
-  make_slots(g, x0, y0, sl);
+  const int k0 = tz * tg.kz, k1 = min(k0 + tg.kz, g.nz);
+  int vu[NUPT], vp[NPCT];
+  tile_slots<W>(g, x0, y0, vu, vp);
   const int yl = threadIdx.x / (TX / 2), p = threadIdx.x % (TX / 2);
   const int gy = y0 + yl;
-  // the load row of this thread's updated node in plane k
-  auto upd_x = [&](int k) { return x0 + 2 * p + ((colour + gy + k) & 1); };
-  // f of the updated node of plane k (in-range dummy where there is none)
-  auto fetch_fv = [&](int k, T (&r)[3]) {
-    const bool ok = k < k1 && gy < g.ny && upd_x(k) < g.nx;
-    const int q = ok ? gy * g.nx + k * nxy + upd_x(k) : 0;
+  // byte offsets (in a plane) of the thread's two nodes, columns x0+2p and x0+2p+1
+  const int vn0 = (gy < g.ny && x0 + 2 * p < g.nx) ? (gy * g.nx + x0 + 2 * p) * W : kOOB;
+  const int vn1 = (gy < g.ny && x0 + 2 * p + 1 < g.nx) ? (gy * g.nx + x0 + 2 * p + 1) * W : kOOB;
+  const int pg = (colour + gy) & 1;  // the updated column of plane k is x0 + 2p + ((pg + k) & 1)
+  // f at the updated node of plane k (zeros past the chunk)
+  auto fetch_f = [&](int k, T (&r)[3]) __attribute__((always_inline)) {
+    const bool ok = k < k1;
+    const __amdgpu_buffer_rsrc_t rf = ok ? B.f : B.null;
+    const int vo = ((pg + k) & 1) ? vn1 : vn0;
+    const int so = ok ? k * nxy * W : 0;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) r[c] = f[c * nn + q];
+    for (int c = 0; c < 3; ++c) r[c] = bload<T>(rf, vo, so + (ok ? c * nn * W : 0));
   };
-  // Loads run two steps ahead: step k issues f of plane k+2 and the u / psi
-  // planes it stores one step later (u k+3, psi k+2), so every load has about
-  // two steps of stencil work to arrive.  All loads are unconditional (dummy
-  // in-range addresses past the chunk): with loads under a branch the
-  // compiler must wait for every older load at their first use.  Vector
-  // loads retire in order, so f is issued before the planes.
-  T FA[3], FB[3];
-  fetch_fv(k0, FA);
-  fetch_fv(k0 + 1, FB);
-  T RAu[NUPT], RAp[NPPT], RBu[NUPT], RBp[NPPT];
-  {
-    // all prologue loads in flight at once
-    T r0[NUPT], r1[NUPT], r2[NUPT], q0[NPPT], q1[NPPT];
-    fetch_u(g, sl, u, k0 - 1, r0);
-    fetch_u(g, sl, u, k0, r1);
-    fetch_u(g, sl, u, k0 + 1, r2);
-    fetch_p(g, sl, psi, k0 - 1, q0);
-    fetch_p(g, sl, psi, k0, q1);
-    fetch_u(g, sl, u, k0 + 2, RBu);
-    fetch_p(g, sl, psi, k0 + 1, RBp);
-    put_u(g, sl, k0 - 1, su[(k0 + 2) % 3], r0);
-    put_u(g, sl, k0, su[k0 % 3], r1);
-    put_u(g, sl, k0 + 1, su[(k0 + 1) % 3], r2);
-    put_p(g, sl, k0 - 1, sp[(k0 + 1) & 1], q0);
-    put_p(g, sl, k0, sp[k0 & 1], q1);
-  }
+  T FN[3];
+  fetch_f(k0, FN);
+  tile_prologue<T>(g, B, vu, vp, k0, su, sp);
   __syncthreads();
-
-  // step k: fr holds f of plane k and receives f of plane k+2; (iu, ip)
-  // receive u k+3 and psi k+2; (su_, sp_) hold u k+2 and psi k+1, stored
-  // after the compute
-  auto step = [&](int k, T (&fr)[3], T (&iu)[NUPT], T (&ip)[NPPT], T (&stu)[NUPT],
-                  T (&stp)[NPPT]) __attribute__((always_inline)) {
+  T RU[NUPT], RP[NPCT];
+  for (int k = k0; k < k1; ++k) {
     T fv[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) fv[c] = fr[c];
-    fetch_fv(k + 2, fr);
-    fetch_u(g, sl, u, k + 3, iu);
-    fetch_p(g, sl, psi, k + 2, ip);
-    const T *Lm = su[(k + 2) % 3];
-    const T *L0 = su[k % 3];
-    const T *L1 = su[(k + 1) % 3];
-    const T *Pm = sp[(k + 1) & 1];
-    const T *P0 = sp[k & 1];
-    if (gy < g.ny) {
-      const int par = (colour + gy + k) & 1;
-      const int xu = 2 * p + par, xc = 2 * p + 1 - par;
-      const int gxu = x0 + xu, gxc = x0 + xc;
-      const int row = gy * g.nx + k * nxy;
-      const int cu = (yl + 1) * LX + xu + 1;  // LDS index of the updated node
-      const int cc = (yl + 1) * LX + xc + 1;  // LDS index of the copied node
-      T nv[3];
-      const bool upd = gxu < g.nx && !(MASK && cls[row + gxu] != 1);
-      if (upd) {
-        T P[2][2][2];
-#pragma unroll
-        for (int c1 = 0; c1 < 2; ++c1)
-#pragma unroll
-          for (int c0 = 0; c0 < 2; ++c0) {
-            P[0][c1][c0] = Pm[(yl + c1) * CXL + xu + c0];
-            P[1][c1][c0] = P0[(yl + c1) * CXL + xu + c0];
-          }
-        auto U = [&](int c, int dx, int dy, int dz) -> T {
-          const T *L = dz < 0 ? Lm : (dz > 0 ? L1 : L0);
-          return L[c * PLANE + cu + dx + dy * LX];
-        };
-        T out[3], dg[3];
-        stencil3<T>(C, P, U, out, dg);
-        // displacement DOF only exist on the box faces
-        const bool face = gxu == 0 || gxu == g.nx - 1 || gy == 0 || gy == g.ny - 1 || k == 0 ||
-                          k == g.nz - 1;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const T uc = L0[c * PLANE + cu];
-          const T upd_c = uc + omega * (fv[c] - out[c]) / dg[c];
-          nv[c] = (face && tg_dirichlet(g, gxu, gy, k, c)) ? uc : upd_c;
-        }
-      } else {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) nv[c] = L0[c * PLANE + cu];
-      }
+    for (int c = 0; c < 3; ++c) fv[c] = FN[c];
+    fetch_f(k + 1, FN);
+    tile_fetch_u<T>(g, B, vu, k + 2, RU);
+    tile_fetch_p<T>(g, B, vp, k + 1, RP);
+    const T *Lm = su[(k + 2) % 3], *L0 = su[k % 3], *L1 = su[(k + 1) % 3];
+    const T *Pm = sp[(k + 1) & 1], *P0 = sp[k & 1];
+    const int par = (pg + k) & 1;
+    const int xu = 2 * p + par, gxu = x0 + xu;  // updated node; the copied one is xu +- 1
+    const int lx = xu + 1;
+    const int cu = (yl + 1) * LX + lds_col(lx, HUX);
+    const int cc = (yl + 1) * LX + lds_col(par ? lx - 1 : lx + 1, HUX);
+    const int so = k * nxy * W;
+    T nv[3];
+    bool upd = gy < g.ny && gxu < g.nx;
+    if (MASK && upd) upd = cls[k * nxy + gy * g.nx + gxu] == 1;
+    if (upd) {
+      T out[3], dg[3];
+      tile_stencil<T>(C, Lm, L0, L1, Pm, P0, lx, yl, out, dg);
+      // displacement DOF only exist on the box faces
+      const bool face = gxu == 0 || gxu == g.nx - 1 || gy == 0 || gy == g.ny - 1 || k == 0 ||
+                        k == g.nz - 1;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        if (gxu < g.nx) u_out[c * nn + row + gxu] = nv[c];
-        if (gxc < g.nx) u_out[c * nn + row + gxc] = L0[c * PLANE + cc];
+        const T uc = L0[c * PLANE + cu];
+        const T upd_c = uc + omega * (fv[c] - out[c]) / dg[c];
+        nv[c] = (face && tg_dirichlet(g, gxu, gy, k, c)) ? uc : upd_c;
       }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) nv[c] = L0[c * PLANE + cu];
+    }
+    const int vo_u = par ? vn1 : vn0, vo_c = par ? vn0 : vn1;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      bstore<T>(nv[c], B.out, vo_u, so + c * nn * W);
+      bstore<T>(L0[c * PLANE + cc], B.out, vo_c, so + c * nn * W);
     }
     __syncthreads();
-    // planes past the chunk (or the box) are stored as zeros into a free slot
-    put_u(g, sl, k + 2, su[(k + 2) % 3], stu);
-    put_p(g, sl, k + 1, sp[(k + 1) & 1], stp);
+    // the planes of the next step go to the slots of planes k - 1 (u, cells)
+    tile_put_u<T>(su[(k + 2) % 3], RU);
+    tile_put_p<T>(sp[(k + 1) & 1], RP);
     __syncthreads();
-  };
-
-  int k = k0;
-  for (; k + 1 < k1; k += 2) {
-    step(k, FA, RAu, RAp, RBu, RBp);
-    step(k + 1, FB, RBu, RBp, RAu, RAp);
   }
-  if (k < k1) step(k, FA, RAu, RAp, RBu, RBp);
 }
 
-// Full stencil pass over the tile (every node computed), thread per x-pair:
+// A face block of a whole-level k_full_tile pass: one node per thread, the
+// block's sum in partials[ntiles + fb].
+template <typename T, typename CO, int MODE, bool MASK>
+__device__ __forceinline__ void full_face_block(const TG &g, const CO &C, const T *psi, const T *u,
+                                                const T *f, T *r, double *partials,
+                                                const TileGeom &tg, const uint8_t *cls, int fb,
+                                                double *red) {
+  const int nn = g.nn;
+  double acc = 0.0;
+  int x, y, z;
+  if (face_node(g, tg, fb * NT + (int)threadIdx.x, x, y, z)) {
+    const int q = x + g.nx * (y + g.ny * z);
+    T v[3] = {T(0), T(0), T(0)};
+    if (!(MASK && (cls[q] == 0 || cls[q] > 3))) {
+      T out[3], dg[3], uc[3];
+      node_stencil<T, 3, true, TG, CO>(g, C, psi, u, x, y, z, out, dg, uc);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const T val = MODE == 0 ? f[c * nn + q] - out[c] : out[c];
+        v[c] = tg_dirichlet(g, x, y, z, c) ? T(0) : val;
+        if (MODE == 0) acc += (double)v[c] * (double)v[c];
+        else acc += (double)uc[c] * (double)v[c];
+      }
+    }
+    if (r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) r[c * nn + q] = v[c];
+  }
+  if (partials) {
+    const double sum = block_sum(acc, red);
+    if (threadIdx.x == 0) partials[tg.ntiles + fb] = sum;
+  }
+}
+
+// Full stencil pass over the tiles (every node computed), thread per x-pair:
 //   MODE 0 (residual): v = f - K u on free DOF, 0 on displacement DOF (and,
 //     with MASK, outside classes 1-3); r = v when r is given; partial sum of
 //     v^2 per tile when partials is given;
@@ -341,163 +427,97 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
 //     partial sum of u . v per tile.
 // Partials land in partials[tile], tiles in their logical order, then one per
 // face block (partials[ntiles + face block]).
-template <typename T, int MODE, bool MASK>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void
-k_full_tile(TG g, Coef<T> C, const T *__restrict__ psi, const T *__restrict__ u,
-            const T *__restrict__ f, T *__restrict__ r, double *__restrict__ partials,
-            TileGeom tg, const uint8_t *__restrict__ cls, const int *__restrict__ ids, int nids) {
-  __shared__ T su[3][NU];
-  __shared__ T sp[2][NP];
+template <typename T, typename CO, int MODE, bool MASK>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_full_tile(
+    TG g, CO C, const T *__restrict__ psi, const T *__restrict__ u, const T *__restrict__ f,
+    T *__restrict__ r, double *__restrict__ partials, TileGeom tg,
+    const uint8_t *__restrict__ cls, const int *__restrict__ ids, int n) {
+  __shared__ T su[3][SLOT_U];
+  __shared__ T sp[2][SLOT_P];
   __shared__ double red[NT / 64 + 1];
-  const int li = tile_or_face(ids ? nids : tg.ntiles);
-  const int nn = g.nn, nxy = g.nx * g.ny;
+  const int li = tile_or_face(n);
   if (li < 0) {
-    // a face block: one node per thread from global memory, the block's sum
-    // after the tiles' partials
-    const int fb = -1 - li;
-    double acc = 0.0;
-    int x, y, z;
-    if (fb < tg.nface && face_node(g, tg, fb * NT + (int)threadIdx.x, x, y, z)) {
-      const int q = x + g.nx * (y + g.ny * z);
+    full_face_block<T, CO, MODE, MASK>(g, C, psi, u, f, r, partials, tg, cls, -1 - li, red);
+    return;
+  }
+  if (li >= n) return;
+  const int lt = ids ? ids[li] : li;
+  constexpr int W = sizeof(T);
+  const int nn = g.nn, nxy = g.nx * g.ny;
+  const int vbytes = 3 * nn * W;
+  const TileBufs B{make_rsrc(u, vbytes), make_rsrc(f, MODE == 0 ? vbytes : 0),
+                   make_rsrc(psi, g.cx * g.cy * g.cz * W), make_rsrc(r, r ? vbytes : 0),
+                   make_rsrc(u, 0)};
+  const int tx = lt % tg.ntx, rest = lt / tg.ntx;
+  const int ty = rest % tg.nty, tz = rest / tg.nty;
+  const int x0 = tx * TX, y0 = ty * TY;
+  const int k0 = tz * tg.kz, k1 = min(k0 + tg.kz, g.nz);
+  int vu[NUPT], vp[NPCT];
+  tile_slots<W>(g, x0, y0, vu, vp);
+  const int yl = threadIdx.x / (TX / 2), p = threadIdx.x % (TX / 2);
+  const int gy = y0 + yl;
+  const int gx0 = x0 + 2 * p;  // the pair: gx0, gx0 + 1
+  const int vn[2] = {(gy < g.ny && gx0 < g.nx) ? (gy * g.nx + gx0) * W : kOOB,
+                     (gy < g.ny && gx0 + 1 < g.nx) ? (gy * g.nx + gx0 + 1) * W : kOOB};
+  // f of both nodes, one plane ahead
+  auto fetch_f = [&](int k, T (&fr)[2][3]) __attribute__((always_inline)) {
+    const bool ok = MODE == 0 && k < k1;
+    const __amdgpu_buffer_rsrc_t rf = ok ? B.f : B.null;
+    const int so = ok ? k * nxy * W : 0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) fr[h][c] = bload<T>(rf, vn[h], so + (ok ? c * nn * W : 0));
+  };
+  T FN[2][3];
+  fetch_f(k0, FN);
+  tile_prologue<T>(g, B, vu, vp, k0, su, sp);
+  __syncthreads();
+  double acc = 0.0;
+  T RU[NUPT], RP[NPCT];
+  for (int k = k0; k < k1; ++k) {
+    T fv[2][3];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) fv[h][c] = FN[h][c];
+    fetch_f(k + 1, FN);
+    tile_fetch_u<T>(g, B, vu, k + 2, RU);
+    tile_fetch_p<T>(g, B, vp, k + 1, RP);
+    const T *Lm = su[(k + 2) % 3], *L0 = su[k % 3], *L1 = su[(k + 1) % 3];
+    const T *Pm = sp[(k + 1) & 1], *P0 = sp[k & 1];
+    const int so = k * nxy * W;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int gx = gx0 + h, lx = 2 * p + h + 1;
       T v[3] = {T(0), T(0), T(0)};
-      if (!(MASK && (cls[q] == 0 || cls[q] > 3))) {
-        T out[3], dg[3], uc[3];
-        node_stencil<T, 3>(g, C, psi, u, x, y, z, out, dg, uc);
+      bool live = gy < g.ny && gx < g.nx;
+      if (MASK && live) {
+        const uint8_t cl = cls[k * nxy + gy * g.nx + gx];
+        live = cl != 0 && cl <= 3;
+      }
+      if (live) {
+        T out[3], dg[3];
+        tile_stencil<T>(C, Lm, L0, L1, Pm, P0, lx, yl, out, dg);
+        const bool face = gx == 0 || gx == g.nx - 1 || gy == 0 || gy == g.ny - 1 || k == 0 ||
+                          k == g.nz - 1;
+        const int cu = (yl + 1) * LX + lds_col(lx, HUX);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          const T val = MODE == 0 ? f[c * nn + q] - out[c] : out[c];
-          v[c] = tg_dirichlet(g, x, y, z, c) ? T(0) : val;
+          const bool fixed = face && tg_dirichlet(g, gx, gy, k, c);
+          const T val = MODE == 0 ? fv[h][c] - out[c] : out[c];
+          v[c] = fixed ? T(0) : val;
           if (MODE == 0) acc += (double)v[c] * (double)v[c];
-          else acc += (double)uc[c] * (double)v[c];
+          else acc += (double)L0[c * PLANE + cu] * (double)v[c];
         }
       }
       if (r)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) r[c * nn + q] = v[c];
+        for (int c = 0; c < 3; ++c) bstore<T>(v[c], B.out, vn[h], so + c * nn * W);
     }
-    if (partials) {
-      const double sum = block_sum(acc, red);
-      if (threadIdx.x == 0 && fb < tg.nface) partials[tg.ntiles + fb] = sum;
-    }
-    return;
-  }
-  if (li >= (ids ? nids : tg.ntiles)) return;
-  const int lt = ids ? ids[li] : li;  // a subset of the tiles, or all of them
-  const int tx = lt % tg.ntx;
-  const int rest = lt / tg.ntx;
-  const int ty = rest % tg.nty;
-  const int tz = rest / tg.nty;
-  const int x0 = tx * TX, y0 = ty * TY;
-  const int k0 = tz * tg.kz;
-  const int k1 = min(k0 + tg.kz, g.nz);
-
-  Slots sl;
-  make_slots(g, x0, y0, sl);
-  const int yl = threadIdx.x / (TX / 2), p = threadIdx.x % (TX / 2);
-  const int gy = y0 + yl;
-  const int gx0 = x0 + 2 * p;  // the pair: gx0, gx0 + 1
-  const bool row_ok = gy < g.ny;
-  // loads of f one plane ahead, issued before the plane prefetch (and the
-  // first before the prologue), so no wait for f waits for a prefetch
-  T fv[2][3] = {{T(0), T(0), T(0)}, {T(0), T(0), T(0)}};
-  if (MODE == 0 && row_ok) {
-    const int q = gy * g.nx + k0 * nxy + gx0;
-#pragma unroll
-    for (int h = 0; h < 2; ++h)
-      if (gx0 + h < g.nx)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) fv[h][c] = f[c * nn + q + h];
-  }
-  {
-    T r0[NUPT], r1[NUPT], r2[NUPT], q0[NPPT], q1[NPPT];
-    fetch_u(g, sl, u, k0 - 1, r0);
-    fetch_u(g, sl, u, k0, r1);
-    fetch_u(g, sl, u, k0 + 1, r2);
-    fetch_p(g, sl, psi, k0 - 1, q0);
-    fetch_p(g, sl, psi, k0, q1);
-    put_u(g, sl, k0 - 1, su[(k0 + 2) % 3], r0);
-    put_u(g, sl, k0, su[k0 % 3], r1);
-    put_u(g, sl, k0 + 1, su[(k0 + 1) % 3], r2);
-    put_p(g, sl, k0 - 1, sp[(k0 + 1) & 1], q0);
-    put_p(g, sl, k0, sp[k0 & 1], q1);
-  }
-  __syncthreads();
-
-  double acc = 0.0;
-  for (int k = k0; k < k1; ++k) {
-    const bool pre = k + 1 < k1;
-    T fn[2][3] = {{T(0), T(0), T(0)}, {T(0), T(0), T(0)}};
-    if (MODE == 0) {
-      // unconditional loads (in-range dummies where not needed), as above
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const bool ok = pre && row_ok && gx0 + h < g.nx;
-        const int q = ok ? gy * g.nx + (k + 1) * nxy + gx0 + h : 0;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) fn[h][c] = f[c * nn + q];
-      }
-    }
-    T ru[NUPT], rp[NPPT];
-    fetch_u(g, sl, u, k + 2, ru);
-    fetch_p(g, sl, psi, k + 1, rp);
-    const T *Lm = su[(k + 2) % 3];
-    const T *L0 = su[k % 3];
-    const T *L1 = su[(k + 1) % 3];
-    const T *Pm = sp[(k + 1) & 1];
-    const T *P0 = sp[k & 1];
-    if (row_ok) {
-      const int row = gy * g.nx + k * nxy;
-      T v[2][3];
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int xl = 2 * p + h, gx = x0 + xl;
-        const int cu = (yl + 1) * LX + xl + 1;
-        const bool live = gx < g.nx && !(MASK && (cls[row + gx] == 0 || cls[row + gx] > 3));
-        v[h][0] = v[h][1] = v[h][2] = T(0);
-        if (live) {
-          T P[2][2][2];
-#pragma unroll
-          for (int c1 = 0; c1 < 2; ++c1)
-#pragma unroll
-            for (int c0 = 0; c0 < 2; ++c0) {
-              P[0][c1][c0] = Pm[(yl + c1) * CXL + xl + c0];
-              P[1][c1][c0] = P0[(yl + c1) * CXL + xl + c0];
-            }
-          auto U = [&](int c, int dx, int dy, int dz) -> T {
-            const T *L = dz < 0 ? Lm : (dz > 0 ? L1 : L0);
-            return L[c * PLANE + cu + dx + dy * LX];
-          };
-          T out[3], dg[3];
-          stencil3<T>(C, P, U, out, dg);
-          const bool face = gx == 0 || gx == g.nx - 1 || gy == 0 || gy == g.ny - 1 || k == 0 ||
-                            k == g.nz - 1;
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            const bool fixed = face && tg_dirichlet(g, gx, gy, k, c);
-            const T val = MODE == 0 ? fv[h][c] - out[c] : out[c];
-            v[h][c] = fixed ? T(0) : val;
-            if (MODE == 0) acc += (double)v[h][c] * (double)v[h][c];
-            else acc += (double)L0[c * PLANE + cu] * (double)v[h][c];
-          }
-        }
-      }
-      if (r) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          if (gx0 < g.nx) r[c * nn + row + gx0] = v[0][c];
-          if (gx0 + 1 < g.nx) r[c * nn + row + gx0 + 1] = v[1][c];
-        }
-      }
-    }
-#pragma unroll
-    for (int h = 0; h < 2; ++h)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) fv[h][c] = fn[h][c];
     __syncthreads();
-    if (pre) {
-      put_u(g, sl, k + 2, su[(k + 2) % 3], ru);
-      put_p(g, sl, k + 1, sp[(k + 1) & 1], rp);
-    }
+    tile_put_u<T>(su[(k + 2) % 3], RU);
+    tile_put_p<T>(sp[(k + 1) & 1], RP);
     __syncthreads();
   }
   if (partials) {
@@ -967,15 +987,30 @@ hipError_t launch_active_tiles(const Level &L, const uint8_t *cls, int *flags, i
 
 bool tiled_ok(const Level &L) {
   // measured: 1.5x faster than the pair kernel at 257^3 nodes; at 129^3 the
-  // vectors stay in the Infinity Cache and the pair kernel is as fast
-  return L.g.dim == 3 && L.g.nx > 3 * TX && L.g.ny > 3 * TY;
+  // vectors stay in the Infinity Cache and the pair kernel is as fast.  The
+  // buffer offsets of a vector must stay below kOOB.
+  return L.g.dim == 3 && L.g.nx > 3 * TX && L.g.ny > 3 * TY &&
+         3 * L.g.nn * (int64_t)sizeof(double) < (int64_t)kOOB;
+}
+
+// The level's coefficients as the 4 scalars of CoefCubic when its cells are
+// cubic (the same numbers, so the results are those of Coef).
+template <typename T>
+static bool cubic_coef(const Coef<T> &C, CoefCubic<T> &cc) {
+  cc = CoefCubic<T>{C.cd[0][0], C.cd[0][1], C.cp[0], C.cm[0]};
+  for (int i = 0; i < 3; ++i) {
+    if (C.cp[i] != cc.p || C.cm[i] != cc.m) return false;
+    for (int j = 0; j < 3; ++j)
+      if (C.cd[i][j] != (i == j ? cc.dd : cc.od)) return false;
+  }
+  return true;
 }
 
 TileGeom tile_geom_of(const Level &L, int kz) { return tile_geom(make_tg(L.g), false, kz); }
 
-// Blocks of a tiled launch: n tiles rounded up to a multiple of 8, then the
-// face blocks.
-static int tiled_grid(const TileGeom &tg, int n) { return (n + 7) / 8 * 8 + tg.nface; }
+// Workgroups of a tiled launch over n tiles: the tiles rounded up to a
+// multiple of 8 (XCD order), then the face blocks of a whole-level launch.
+static int tiled_grid(int n, int nface) { return (n + 7) / 8 * 8 + nface; }
 
 template <typename T>
 hipError_t launch_rb_tiled(const Level &L, const T *psi, const Coef<T> &C, const T *u, const T *f,
@@ -984,16 +1019,26 @@ hipError_t launch_rb_tiled(const Level &L, const T *psi, const Coef<T> &C, const
   const TG gg = make_tg(L.g);
   const TileGeom tg = tile_geom(gg, tl == nullptr, tl ? tl->kz : 0);
   const int n = tl ? tl->count : tg.ntiles;
-  if (n == 0 && tg.nface == 0) return hipSuccess;
-  const int grid = tiled_grid(tg, n);
   const int *ids = tl ? tl->ids : nullptr;
+  CoefCubic<T> cc;
+  const bool cubic = cubic_coef(C, cc);
   (void)hipGetLastError();
-  if (cls)
-    hipLaunchKernelGGL((k_rb_tile<T, true>), dim3(grid), dim3(NT), 0, st, gg, C, psi, u, f,
-                       u_out, (T)omega, colour, tg, cls, ids, n);
-  else
-    hipLaunchKernelGGL((k_rb_tile<T, false>), dim3(grid), dim3(NT), 0, st, gg, C, psi, u, f,
-                       u_out, (T)omega, colour, tg, cls, ids, n);
+  const int nface = tl ? 0 : tg.nface;
+  if (n + nface > 0) {
+    const dim3 grid(tiled_grid(n, nface)), block(NT);
+    if (cls && cubic)
+      hipLaunchKernelGGL((k_rb_tile<T, CoefCubic<T>, true>), grid, block, 0, st, gg, cc, psi, u,
+                         f, u_out, (T)omega, colour, tg, cls, ids, n);
+    else if (cls)
+      hipLaunchKernelGGL((k_rb_tile<T, Coef<T>, true>), grid, block, 0, st, gg, C, psi, u, f,
+                         u_out, (T)omega, colour, tg, cls, ids, n);
+    else if (cubic)
+      hipLaunchKernelGGL((k_rb_tile<T, CoefCubic<T>, false>), grid, block, 0, st, gg, cc, psi, u,
+                         f, u_out, (T)omega, colour, tg, cls, ids, n);
+    else
+      hipLaunchKernelGGL((k_rb_tile<T, Coef<T>, false>), grid, block, 0, st, gg, C, psi, u, f,
+                         u_out, (T)omega, colour, tg, cls, ids, n);
+  }
   return hipGetLastError();
 }
 
@@ -1025,35 +1070,48 @@ int tiled_partials(const Level &L) {
   return tg.ntiles + tg.nface;
 }
 
+template <typename T, int MODE>
+static void full_tiled(const Level &L, const T *psi, const Coef<T> &C, const T *u, const T *f,
+                       T *r, double *partials, hipStream_t st, const uint8_t *cls,
+                       const TileList *tl) {
+  const TG gg = make_tg(L.g);
+  const TileGeom tg = tile_geom(gg, tl == nullptr, tl ? tl->kz : 0);
+  const int n = tl ? tl->count : tg.ntiles;
+  const int *ids = tl ? tl->ids : nullptr;
+  CoefCubic<T> cc;
+  const bool cubic = cubic_coef(C, cc);
+  const int nface = tl ? 0 : tg.nface;
+  if (n + nface > 0) {
+    const dim3 grid(tiled_grid(n, nface)), block(NT);
+    if (cls && cubic)
+      hipLaunchKernelGGL((k_full_tile<T, CoefCubic<T>, MODE, true>), grid, block, 0, st, gg, cc,
+                         psi, u, f, r, partials, tg, cls, ids, n);
+    else if (cls)
+      hipLaunchKernelGGL((k_full_tile<T, Coef<T>, MODE, true>), grid, block, 0, st, gg, C, psi,
+                         u, f, r, partials, tg, cls, ids, n);
+    else if (cubic)
+      hipLaunchKernelGGL((k_full_tile<T, CoefCubic<T>, MODE, false>), grid, block, 0, st, gg, cc,
+                         psi, u, f, r, partials, tg, cls, ids, n);
+    else
+      hipLaunchKernelGGL((k_full_tile<T, Coef<T>, MODE, false>), grid, block, 0, st, gg, C, psi,
+                         u, f, r, partials, tg, cls, ids, n);
+  }
+}
+
 template <typename T>
 hipError_t launch_residual_tiled(const Level &L, const T *psi, const Coef<T> &C, const T *u,
                                  const T *f, T *r, double *partials, hipStream_t st,
                                  const uint8_t *cls, const TileList *tl) {
-  const TG gg = make_tg(L.g);
-  const TileGeom tg = tile_geom(gg, tl == nullptr, tl ? tl->kz : 0);
-  const int n = tl ? tl->count : tg.ntiles;
-  if (n == 0 && tg.nface == 0) return hipSuccess;
-  const int grid = tiled_grid(tg, n);
-  const int *ids = tl ? tl->ids : nullptr;
   (void)hipGetLastError();
-  if (cls)
-    hipLaunchKernelGGL((k_full_tile<T, 0, true>), dim3(grid), dim3(NT), 0, st, gg, C, psi, u, f,
-                       r, partials, tg, cls, ids, n);
-  else
-    hipLaunchKernelGGL((k_full_tile<T, 0, false>), dim3(grid), dim3(NT), 0, st, gg, C, psi, u, f,
-                       r, partials, tg, cls, ids, n);
+  full_tiled<T, 0>(L, psi, C, u, f, r, partials, st, cls, tl);
   return hipGetLastError();
 }
 
 hipError_t launch_apply_dot_tiled(const Level &L, const double *p, double *q, double *partials,
                                   hipStream_t st) {
-  const TG gg = make_tg(L.g);
-  const TileGeom tg = tile_geom(gg, true);
-  const int grid = tiled_grid(tg, tg.ntiles);
   (void)hipGetLastError();
-  hipLaunchKernelGGL((k_full_tile<double, 1, false>), dim3(grid), dim3(NT), 0, st, gg, L.c64,
-                     L.psi64, p, (const double *)nullptr, q, partials, tg,
-                     (const uint8_t *)nullptr, (const int *)nullptr, 0);
+  full_tiled<double, 1>(L, L.psi64, L.c64, p, (const double *)nullptr, q, partials, st, nullptr,
+                        nullptr);
   return hipGetLastError();
 }
 
