@@ -972,6 +972,297 @@ __global__ __launch_bounds__(NT) void k_rb_fused(TG g, Coef<T> C, const T *__res
   if (k <= k1) step(k, RA, RB, FA);
 }
 
+
+// ------------------------------------------- first sweep from a zero iterate
+//
+// The first Gauss-Seidel sweep of a correction that starts from zero (Sec.
+// 2.3), in one launch: colour A is relaxed from u = 0, which is pointwise
+// (a = omega f / D), and colour B from u_mid = (a on A, 0 on B).  At a B node
+// the centre and the edge neighbours of eq. K are B nodes, all 0 in u_mid, so
+// K u_mid there needs only the A values of the six face neighbours: the terms
+// of the other neighbours are exact zeros and are left out (the sums are the
+// same numbers).  A workgroup owns a 64 x 8 node column and marches up its
+// chunk; the A values of the plane two steps ahead (halo included) are made in
+// LDS from f and the cells, one row half per row (LDS holds only A values),
+// and B is relaxed on the current plane.  The node column / row past the last
+// whole tile of a 2^n + 1 level (x = nx - 1, y = ny - 1) belongs to the last
+// tile of its row / column.
+constexpr int ZX = TX + 4, ZY = TY + 3;     // local columns x0-1..x0+66, rows y0-1..y0+9
+constexpr int ZHX = ZX / 2;                 // A nodes per row (one parity half)
+constexpr int ZPA = ZY * ZHX;               // A nodes per plane and component
+constexpr int ZCX = TX + 4, ZCY = TY + 4;   // cells: columns x0-2..x0+65, rows y0-2..y0+9
+constexpr int ZNC = ZCX * ZCY, ZHC = ZCX / 2;
+constexpr int ZSN = (ZPA + NT - 1) / NT;    // A nodes made per thread and plane
+constexpr int ZSC = (ZNC + NT - 1) / NT;    // cell loads per thread and plane
+static_assert(ZX % 2 == 0 && ZCX % 2 == 0, "rows split into two equal halves");
+
+// Cell-local index of cell column clx (cells from x0 - 2, parity split).
+__device__ __forceinline__ int zcell(int clx, int cly) { return cly * ZCX + lds_col(clx, ZHC); }
+
+// The psi of the 8 cells around the node whose cells are (clx + a, cly + b) of
+// the planes below / above (P[c2][c1][c0] as in stencil3), their edge sums E
+// and the diagonal D of K (stencil3's direct part).
+template <typename T, typename CO>
+__device__ __forceinline__ void zero_cells(const CO &C, const T *Pm, const T *P0, int clx, int cly,
+                                           T (&P)[2][2][2], T (&E)[3][2], T dg[3]) {
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      P[0][b][a] = Pm[zcell(clx + a, cly + b)];
+      P[1][b][a] = P0[zcell(clx + a, cly + b)];
+    }
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    E[0][s] = P[0][0][s] + P[0][1][s] + P[1][0][s] + P[1][1][s];
+    E[1][s] = P[0][s][0] + P[0][s][1] + P[1][s][0] + P[1][s][1];
+    E[2][s] = P[s][0][0] + P[s][0][1] + P[s][1][0] + P[s][1][1];
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+    dg[c] = coef_cd(C, c, 0) * (E[0][0] + E[0][1]) + coef_cd(C, c, 1) * (E[1][0] + E[1][1]) +
+            coef_cd(C, c, 2) * (E[2][0] + E[2][1]);
+}
+
+// (K u)(n) at a node n whose centre and edge neighbours are 0: F[c][a][s] is
+// component c at the face neighbour n + (2s - 1) e_a.  The expressions are
+// stencil3's with the zero terms removed.
+template <typename T, typename CO>
+__device__ __forceinline__ void zero_face_stencil(const CO &C, const T (&P)[2][2][2],
+                                                  const T (&E)[3][2], const T (&F)[3][3][2],
+                                                  T out[3]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+    out[c] = -(coef_cd(C, c, 0) * (E[0][1] * F[c][0][1] + E[0][0] * F[c][0][0]) +
+               coef_cd(C, c, 1) * (E[1][1] * F[c][1][1] + E[1][0] * F[c][1][0]) +
+               coef_cd(C, c, 2) * (E[2][1] * F[c][2][1] + E[2][0] * F[c][2][0]));
+#pragma unroll
+  for (int pl = 0; pl < 3; ++pl) {
+    const int a = (pl == 2) ? 1 : 0;
+    const int b = (pl == 0) ? 1 : 2;
+    const T cm = coef_cm(C, pl);
+    T ra = T(0), rb = T(0);
+#pragma unroll
+    for (int qa = 0; qa < 2; ++qa)
+#pragma unroll
+      for (int qb = 0; qb < 2; ++qb) {
+        const int sa = 2 * qa - 1, sb = 2 * qb - 1;
+        T Fs;
+        if (pl == 0) Fs = P[0][qb][qa] + P[1][qb][qa];
+        else if (pl == 1) Fs = P[qb][0][qa] + P[qb][1][qa];
+        else Fs = P[qb][qa][0] + P[qb][qa][1];
+        const T w = (sa * sb > 0) ? Fs : -Fs;
+        // u_b(n + sb e_b) - u_b(n + sa e_a) and u_a(n + sa e_a) - u_a(n + sb e_b)
+        ra += w * (cm * (F[b][b][qb] - F[b][a][qa]));
+        rb += w * (cm * (F[a][a][qa] - F[a][b][qb]));
+      }
+    out[a] -= ra;
+    out[b] -= rb;
+  }
+}
+
+template <typename T, typename CO>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_rb_zero(
+    TG g, CO C, const T *__restrict__ psi, const T *__restrict__ f, T *__restrict__ u_out,
+    T omega, int c0, TileGeom tg) {
+  __shared__ T sm[3][3 * ZPA];   // A values of planes k-1, k, k+1 (slot z mod 3)
+  __shared__ T sc[4][ZNC];       // cell planes k-1 .. k+2 (slot z mod 4)
+  const int n = tg.ntiles;
+  const int n8 = (n + 7) / 8 * 8;
+  const int li = (int)(blockIdx.x & 7) * (n8 >> 3) + (int)(blockIdx.x >> 3);
+  if (li >= n) return;
+  constexpr int W = sizeof(T);
+  const int nn = g.nn, nxy = g.nx * g.ny;
+  const int vbytes = 3 * nn * W;
+  const __amdgpu_buffer_rsrc_t rf = make_rsrc(f, vbytes), rp = make_rsrc(psi, g.cx * g.cy * g.cz * W),
+                               ro = make_rsrc(u_out, vbytes);
+  const int tx = li % tg.ntx, rest = li / tg.ntx;
+  const int ty = rest % tg.nty, tz = rest / tg.nty;
+  const int x0 = tx * TX, y0 = ty * TY;
+  const int k0 = tz * tg.kz, k1 = min(k0 + tg.kz, g.nz);
+  const int xe = (tg.xface && tx == tg.ntx - 1) ? 1 : 0;  // the tile also owns x = x0 + 64
+  const int ye = (tg.yface && ty == tg.nty - 1) ? 1 : 0;  // ... and y = y0 + 8
+  const int t = threadIdx.x;
+  // A-node slot j of this thread: entry e = t + j NT of (row ly, index hi); in
+  // plane z its local column is lx = 2 hi + ((c0 + x0 - 1 + y0 - 1 + ly + z) & 1)
+  auto a_node = [&](int j, int z, int &lx, int &ly, int &gx, int &gyy) __attribute__((always_inline)) {
+    const int e = t + j * NT;
+    ly = e / ZHX;
+    const int hi = e - ly * ZHX;
+    gyy = y0 - 1 + ly;
+    lx = 2 * hi + ((c0 + x0 - 1 + gyy + z) & 1);
+    gx = x0 - 1 + lx;
+    return e < ZPA && gx >= 0 && gx < g.nx && gyy >= 0 && gyy < g.ny && lx <= TX + 1 + xe &&
+           ly <= TY + 1 + ye;
+  };
+  int vc[ZSC];
+#pragma unroll
+  for (int j = 0; j < ZSC; ++j) {
+    const int e = t + j * NT;
+    vc[j] = kOOB;
+    if (e < ZNC) {
+      const int cly = e / ZCX, xr = e - cly * ZCX;
+      const int hf = xr >= ZHC ? 1 : 0;
+      const int clx = 2 * (xr - hf * ZHC) + hf;
+      const int gx = x0 - 2 + clx, gy = y0 - 2 + cly;
+      if (gx >= 0 && gx < g.cx && gy >= 0 && gy < g.cy) vc[j] = (gx + g.cx * gy) * W;
+    }
+  }
+  auto fetch_cells = [&](int zc_, T (&r)[ZSC]) __attribute__((always_inline)) {
+    const bool in = zc_ >= 0 && zc_ < g.cz;
+    const int so = in ? zc_ * g.cx * g.cy * W : 0;
+#pragma unroll
+    for (int j = 0; j < ZSC; ++j) r[j] = bload<T>(rp, in ? vc[j] : kOOB, so);
+  };
+  auto put_cells = [&](int zc_, const T (&r)[ZSC]) __attribute__((always_inline)) {
+    T *d = sc[(zc_ + 4) & 3];
+#pragma unroll
+    for (int j = 0; j < ZSC; ++j)
+      if (j < ZSC - 1 || t + j * NT < ZNC) d[t + j * NT] = r[j];
+  };
+  // f of the A nodes of plane z
+  auto fetch_zf = [&](int z, T (&r)[ZSN][3]) __attribute__((always_inline)) {
+    const bool in = z >= 0 && z < g.nz;
+    const int so = in ? z * nxy * W : 0;
+#pragma unroll
+    for (int j = 0; j < ZSN; ++j) {
+      int lx, ly, gx, gyy;
+      const bool ok = in && a_node(j, z, lx, ly, gx, gyy);
+      const int vo = ok ? (gx + g.nx * gyy) * W : kOOB;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) r[j][c] = bload<T>(rf, vo, so + c * nn * W);
+    }
+  };
+  // A values of plane z: omega f / D (0 on displacement DOF and outside the box)
+  auto make_a = [&](int z, const T (&fz)[ZSN][3]) __attribute__((always_inline)) {
+    T *d = sm[(z + 3) % 3];
+    const T *Pm = sc[(z + 3) & 3], *P0 = sc[(z + 4) & 3];
+    const bool zin = z >= 0 && z < g.nz;
+#pragma unroll
+    for (int j = 0; j < ZSN; ++j) {
+      int lx, ly, gx, gyy;
+      const bool inb = a_node(j, z, lx, ly, gx, gyy);
+      const int e = t + j * NT;
+      if (j < ZSN - 1 || e < ZPA) {
+        T v[3] = {T(0), T(0), T(0)};
+        if (zin && inb) {
+          T P[2][2][2], E[3][2], dg[3];
+          zero_cells<T>(C, Pm, P0, lx, ly, P, E, dg);
+          const bool face = gx == 0 || gx == g.nx - 1 || gyy == 0 || gyy == g.ny - 1 || z == 0 ||
+                            z == g.nz - 1;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const T upd = T(0) + omega * (fz[j][c] - T(0)) / dg[c];
+            v[c] = (face && tg_dirichlet(g, gx, gyy, z, c)) ? T(0) : upd;
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) d[c * ZPA + e] = v[c];
+      }
+    }
+  };
+  // B nodes of this thread: the x-pair (2p, 2p+1) of row yl; in an edge tile
+  // of a 2^n + 1 level also row 8 (threads 0-31: columns 2t, 2t+1) or column 64
+  // (threads 32-40: with the out-of-box column 65 as its pair)
+  const int yl = t / (TX / 2), p = t % (TX / 2);
+  const int gy = y0 + yl;
+  const int vn0 = (gy < g.ny && x0 + 2 * p < g.nx) ? (gy * g.nx + x0 + 2 * p) * W : kOOB;
+  const int vn1 = (gy < g.ny && x0 + 2 * p + 1 < g.nx) ? (gy * g.nx + x0 + 2 * p + 1) * W : kOOB;
+  const bool xrow = ye && t < TX / 2;
+  const bool xcol = xe && t >= 32 && t < 32 + TY + ye && y0 + t - 32 < g.ny;
+  const int ex = xrow ? 2 * t : TX, ey = xrow ? TY : t - 32;
+  const int gey = y0 + ey;
+  const int ve0 = ((xrow || xcol) && x0 + ex < g.nx) ? (gey * g.nx + x0 + ex) * W : kOOB;
+  const int ve1 = (xrow && x0 + ex + 1 < g.nx) ? (gey * g.nx + x0 + ex + 1) * W : kOOB;
+  // f of the B node of the pair and of the extra pair, plane k
+  auto fetch_fb = [&](int k, T (&r)[2][3]) __attribute__((always_inline)) {
+    const bool in = k < k1;
+    const int so = in ? k * nxy * W : 0;
+    const int pb0 = ((1 - c0) + gy + x0 + 2 * p + k) & 1;
+    const int pb1 = ((1 - c0) + gey + x0 + ex + k) & 1;
+    const int vo = pb0 ? vn1 : vn0, ve = pb1 ? ve1 : ve0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      r[0][c] = bload<T>(rf, in ? vo : kOOB, so + c * nn * W);
+      r[1][c] = bload<T>(rf, in ? ve : kOOB, so + c * nn * W);
+    }
+  };
+
+  // prologue: cells k0-2..k0+1, A values of planes k0-1..k0+1
+  T CQ[ZSC], FZ[ZSN][3], FB[2][3];
+  fetch_cells(k0 - 2, CQ);
+  put_cells(k0 - 2, CQ);
+  fetch_cells(k0 - 1, CQ);
+  put_cells(k0 - 1, CQ);
+  fetch_cells(k0, CQ);
+  put_cells(k0, CQ);
+  fetch_cells(k0 + 1, CQ);
+  put_cells(k0 + 1, CQ);
+  __syncthreads();
+  for (int z = k0 - 1; z <= k0 + 1; ++z) {
+    fetch_zf(z, FZ);
+    make_a(z, FZ);
+  }
+  fetch_fb(k0, FB);
+  fetch_cells(k0 + 2, CQ);
+  __syncthreads();
+  for (int k = k0; k < k1; ++k) {
+    // cells k + 2 (fetched a step ago) go to the slot of k - 2, unused from here
+    put_cells(k + 2, CQ);
+    fetch_zf(k + 2, FZ);
+    fetch_cells(k + 3, CQ);
+    const T *Am = sm[(k + 2) % 3], *A0 = sm[k % 3], *A1 = sm[(k + 1) % 3];
+    const T *Pm = sc[(k + 3) & 3], *P0 = sc[k & 3];
+    const int so = k * nxy * W;
+    const int npass = (xrow || xcol) ? 2 : 1;
+    for (int pass = 0; pass < npass; ++pass) {
+      const int px = pass ? ex : 2 * p, py = pass ? ey : yl;
+      const int gpy = y0 + py;
+      const int o0 = pass ? ve0 : vn0, o1 = pass ? ve1 : vn1;
+      const int pb = ((1 - c0) + gpy + x0 + px + k) & 1;  // 1: the second column is B
+      const int lx = px + pb + 1, lxa = px + 1 - pb + 1, ly = py + 1;
+      T vb[3] = {T(0), T(0), T(0)};
+      if (gpy < g.ny && x0 + lx - 1 < g.nx) {
+        T P[2][2][2], E[3][2], dg[3], F[3][3][2];
+        zero_cells<T>(C, Pm, P0, lx, ly, P, E, dg);
+        const int hx = ly * ZHX, hm = hx + ((lx - 1) >> 1), hp = hx + ((lx + 1) >> 1);
+        const int hc = lx >> 1;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          F[c][0][0] = A0[c * ZPA + hm];
+          F[c][0][1] = A0[c * ZPA + hp];
+          F[c][1][0] = A0[c * ZPA + hx - ZHX + hc];
+          F[c][1][1] = A0[c * ZPA + hx + ZHX + hc];
+          F[c][2][0] = Am[c * ZPA + hx + hc];
+          F[c][2][1] = A1[c * ZPA + hx + hc];
+        }
+        T out[3];
+        zero_face_stencil<T>(C, P, E, F, out);
+        const int gx = x0 + lx - 1;
+        const bool face = gx == 0 || gx == g.nx - 1 || gpy == 0 || gpy == g.ny - 1 || k == 0 ||
+                          k == g.nz - 1;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const T fv = pass ? FB[1][c] : FB[0][c];
+          const T upd = T(0) + omega * (fv - out[c]) / dg[c];
+          vb[c] = (face && tg_dirichlet(g, gx, gpy, k, c)) ? T(0) : upd;
+        }
+      }
+      const int ca = ly * ZHX + (lxa >> 1);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        bstore<T>(vb[c], ro, pb ? o1 : o0, so + c * nn * W);
+        bstore<T>(A0[c * ZPA + ca], ro, pb ? o0 : o1, so + c * nn * W);
+      }
+    }
+    // f of the next plane's B nodes (used a step later)
+    fetch_fb(k + 1, FB);
+    __syncthreads();
+    // A values of plane k + 2 into the slot of plane k - 1
+    make_a(k + 2, FZ);
+    __syncthreads();
+  }
+}
 }  // namespace
 
 hipError_t launch_active_tiles(const Level &L, const uint8_t *cls, int *flags, int *ids,
@@ -1049,12 +1340,24 @@ hipError_t launch_rb_fused(const Level &L, const T *psi, const Coef<T> &C, const
   const TileGeom tg = tile_geom(gg);
   const int grid = (tg.ntiles + 7) / 8 * 8;
   (void)hipGetLastError();
-  if (u)
+  if (u) {
     hipLaunchKernelGGL((k_rb_fused<T, false>), dim3(grid), dim3(NT), 0, st, gg, C, psi, u, f,
                        u_out, (T)omega, first_colour, tg);
-  else
-    hipLaunchKernelGGL((k_rb_fused<T, true>), dim3(grid), dim3(NT), 0, st, gg, C, psi, u, f,
-                       u_out, (T)omega, first_colour, tg);
+  } else {
+    // from zero: k_rb_zero over the tiles of the whole level (the last node
+    // column / row of a 2^n + 1 level in the edge tiles)
+    const TileGeom tz = tile_geom(gg, true);
+    TileGeom tf = tz;
+    tf.nface = 0;
+    const dim3 zgrid((tf.ntiles + 7) / 8 * 8);
+    CoefCubic<T> cc;
+    if (cubic_coef(C, cc))
+      hipLaunchKernelGGL((k_rb_zero<T, CoefCubic<T>>), zgrid, dim3(NT), 0, st, gg, cc, psi, f,
+                         u_out, (T)omega, first_colour, tf);
+    else
+      hipLaunchKernelGGL((k_rb_zero<T, Coef<T>>), zgrid, dim3(NT), 0, st, gg, C, psi, f, u_out,
+                         (T)omega, first_colour, tf);
+  }
   return hipGetLastError();
 }
 

@@ -32,9 +32,10 @@ def rel_max(a, b):
     return float(np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), 1e-300))
 
 
-def random_problem(ncell, seed=0, floor=1e-6, zero_frac=0.2, body=True, traction=True):
+def random_problem(ncell, seed=0, floor=1e-6, zero_frac=0.2, body=True, traction=True, cubic=False):
     """Random indicator with a fraction of empty cells, a mixed boundary table
-    and a random body force."""
+    and a random body force; cells of slightly different sizes per axis, or
+    cubic cells (the same spacing on every axis)."""
     rng = np.random.default_rng(seed)
     d = len(ncell)
     psi = rng.uniform(0.05, 1.0, tuple(reversed(ncell)))
@@ -43,7 +44,8 @@ def random_problem(ncell, seed=0, floor=1e-6, zero_frac=0.2, body=True, traction
     if not traction:
         val[kind == si.TRACTION] = 0.0
     b = rng.standard_normal((d,) + tuple(n + 1 for n in reversed(ncell))) if body else None
-    h = tuple(1.0 / n * (1.0 + 0.05 * a) for a, n in enumerate(ncell))
+    h = (tuple(1.0 / max(ncell) for _ in ncell) if cubic else
+         tuple(1.0 / n * (1.0 + 0.05 * a) for a, n in enumerate(ncell)))
     lam, mu = si.lame(1.0, 0.3)
     return si.Problem("random", tuple(ncell), h, lam, mu, floor, psi, kind, val, b=b)
 

@@ -17,9 +17,9 @@ pytestmark = pytest.mark.gpu
 GRIDS = [(40, 30), (37, 26), (20, 12, 16), (12, 18, 9)]
 
 
-def _setup(ncell, seed=0):
-    p = random_problem(ncell, seed=seed)
-    say("kernel setup", ncell, seed)
+def _setup(ncell, seed=0, cubic=False):
+    p = random_problem(ncell, seed=seed, cubic=cubic)
+    say("kernel setup", ncell, seed, "cubic" if cubic else "")
     S = solver_for(p)
     psi = oracle.floor_psi(p.psi_raw, p.psi_floor)
     mask, uD = oracle.dirichlet(p.ncell, p.kind, p.val)
@@ -85,12 +85,14 @@ def test_residual_and_smoothers(ncell):
         assert np.array_equal(got[other], u[other])
 
 
+@pytest.mark.parametrize("cubic", [False, True])
 @pytest.mark.parametrize("ncell", [(200, 30, 12), (230, 25, 9), (256, 33, 6), (256, 32, 10)])
-def test_tiled_half_sweep(ncell):
+def test_tiled_half_sweep(ncell, cubic):
     """Levels wider than 192 nodes in x take the LDS-tiled half-sweep: several
     64 x 8 tiles, a ragged last tile in x and y, z chunks; 257 nodes in x (and
-    33 in y) leave the last column (row) to the node-parallel face blocks."""
-    p, S, psi, mask, u, f = _setup(ncell, seed=11)
+    33 in y) leave the last column (row) to the node-parallel face blocks.
+    Cubic cells take the kernels' 4-coefficient form."""
+    p, S, psi, mask, u, f = _setup(ncell, seed=11, cubic=cubic)
     u = np.where(mask == 1, oracle.dirichlet(p.ncell, p.kind, p.val)[1], u)
     for colour in (0, 1):
         say("tiled half sweep", ncell, colour)
@@ -102,13 +104,17 @@ def test_tiled_half_sweep(ncell):
         assert np.array_equal(got[other], u[other])
 
 
-@pytest.mark.parametrize("ncell", [(200, 30, 12), (230, 25, 9), (256, 33, 6), (256, 20, 40)])
-def test_fused_two_colour_sweep(ncell):
+@pytest.mark.parametrize("cubic", [False, True])
+@pytest.mark.parametrize("ncell", [(200, 30, 12), (230, 25, 9), (256, 33, 6), (256, 20, 40),
+                                   (256, 32, 7), (208, 32, 9)])
+def test_fused_two_colour_sweep(ncell, cubic):
     """A whole Gauss-Seidel sweep in one launch (levels wider than 192 nodes):
     equal to the oracle's half-sweep of the first colour followed by the
     half-sweep of the second, for both colour orders, from a given iterate and
     from zero; several tiles, ragged last tiles in x and y, several z chunks
-    (40 planes make ten).  The FP32 sweep is held to the FP32 bar against the
+    (40 planes make ten); 257 x 33 nodes put the last node column and row into
+    the edge tiles of the sweep from zero, 209 x 33 the last row with a ragged
+    last tile in x.  The FP32 sweep is held to the FP32 bar against the
     FP64 oracle on the same (FP32-representable) inputs."""
     p, S, psi, mask, u, f = _setup(ncell, seed=13)
     u = np.where(mask == 1, oracle.dirichlet(p.ncell, p.kind, p.val)[1], u)
@@ -132,11 +138,12 @@ def test_fused_two_colour_sweep(ncell):
     assert rel_l2(got, ref) < 1e-5
 
 
+@pytest.mark.parametrize("cubic", [False, True])
 @pytest.mark.parametrize("ncell", [(200, 30, 12), (256, 33, 6), (256, 32, 10)])
-def test_tiled_residual_and_norm(ncell):
+def test_tiled_residual_and_norm(ncell, cubic):
     """The tiled residual (r and its per-tile norm partials) at widths that
-    take the tiled path."""
-    p, S, psi, mask, u, f = _setup(ncell, seed=12)
+    take the tiled path, with anisotropic and cubic cells."""
+    p, S, psi, mask, u, f = _setup(ncell, seed=12, cubic=cubic)
     u = np.where(mask == 1, oracle.dirichlet(p.ncell, p.kind, p.val)[1], u)
     say("tiled residual", ncell)
     got = to_np(S.level_residual(0, u, f))

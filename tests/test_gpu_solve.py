@@ -72,15 +72,20 @@ def test_krylov_trajectory_parity(case, smoother):
     assert rel_l2(u_g, u_o) <= 1e-9, rel_l2(u_g, u_o)
 
 
+@pytest.mark.parametrize("shape", ["208x32x16", "256x32x16 cubic"])
 @pytest.mark.parametrize("fused", [0, 1])
 @pytest.mark.parametrize("krylov", [0, 1])
-def test_wide_grid_first_iterations(krylov, fused):
+def test_wide_grid_first_iterations(krylov, fused, shape):
     """209 x 33 x 17 nodes: the finest level takes the LDS-tiled half-sweep
     (or, with fused_sweep, the one-launch two-colour sweep, also from zero in
     the preconditioner), residual and (Krylov) Apply; the first iterations
-    follow the oracle's."""
-    p = random_problem((208, 32, 16), seed=6, floor=1e-3)
-    say("wide grid", krylov, fused)
+    follow the oracle's.  257 x 33 x 17 nodes with cubic cells: the last node
+    column and row of the level in the edge tiles or the face blocks, and the
+    kernels' 4-coefficient form."""
+    cubic = shape.endswith("cubic")
+    ncell = tuple(int(n) for n in shape.split()[0].split("x"))
+    p = random_problem(ncell, seed=6, floor=1e-3, cubic=cubic)
+    say("wide grid", krylov, fused, shape)
     u_o, hist_o, _ = oracle_solve(p, rtol=0.0, max_cycles=5, krylov=krylov)
     S = solver_for(p, rtol=0.0, max_cycles=5, krylov=krylov, fused_sweep=fused)
     u_g, hist_g, _ = S.solve()
