@@ -110,6 +110,9 @@ template <typename T>
 hipError_t launch_rb_tiled(const Level &L, const T *psi, const Coef<T> &C, const T *u, const T *f,
                            T *u_out, double omega, int colour, hipStream_t st,
                            const uint8_t *cls = nullptr, const TileList *tl = nullptr);
+// Levels whose first sweep from a zero iterate runs as one launch
+// (launch_rb_fused with u == nullptr).
+bool zero_sweep_ok(const Level &L);
 // One complete two-colour Gauss-Seidel sweep on a tiled level in one launch
 // (the same result as the half-sweep of first_colour from u followed by the
 // half-sweep of the other colour): u_out must not be u.  u == nullptr means

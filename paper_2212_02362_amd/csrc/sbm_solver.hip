@@ -359,9 +359,18 @@ struct Prec<float> {
   static float *t(Level &L) { return L.t32; }
 };
 
+// A colour half-sweep of level L (LDS-tiled on wide 3D levels).
+template <typename T>
+static hipError_t half_sweep(const Level &L, const T *psi, const Coef<T> &C, const T *src,
+                             const T *f, T *dst, double om, int colour, hipStream_t st) {
+  return tiled_ok(L) ? launch_rb_tiled<T>(L, psi, C, src, f, dst, om, colour, st)
+                     : launch_rb_half<T>(L, psi, C, src, f, dst, om, colour, st);
+}
+
 // nu sweeps on level l for x with load f; tmp is the ping-pong buffer.
 template <typename T>
-static hipError_t smooth(sbm_ctx *c, int l, T *x, const T *f, T *tmp, int nu, bool reverse) {
+static hipError_t smooth(sbm_ctx *c, int l, T *x, const T *f, T *tmp, int nu, bool reverse,
+                         bool pre) {
   Level &L = c->L[l];
   const T *psi = Prec<T>::psi(L);
   const Coef<T> &C = Prec<T>::coef(L);
@@ -378,16 +387,19 @@ static hipError_t smooth(sbm_ctx *c, int l, T *x, const T *f, T *tmp, int nu, bo
     return e;
   }
   const int c0 = reverse ? 1 : 0;
-  const bool zero = l == 0 && c->zero_start;
-  c->zero_start = false;
-  if (tiled_ok(L) && (zero || c->opt.fused_sweep == 1)) {
-    // A sweep from a zero iterate (zero_start: the first sweep of a correction
-    // that starts from zero) is always one fused launch that reads no iterate;
-    // with fused_sweep every other sweep is one fused launch too (out of
-    // place: cur -> the other buffer), else two half-sweeps (cur -> tmp ->
-    // cur).  The first sweep's output buffer is chosen so that the last
-    // sweep lands in x.
-    const bool all = c->opt.fused_sweep == 1;
+  // the finest level starts from zero when the caller says so (zero_start);
+  // a coarser level always does on its pre-smoothing (its correction is the
+  // zero the restriction wrote)
+  const bool zero = ((l == 0 && c->zero_start) || (l > 0 && pre)) && zero_sweep_ok(L);
+  if (l == 0) c->zero_start = false;
+  if (zero || (tiled_ok(L) && c->opt.fused_sweep == 1)) {
+    // A sweep from a zero iterate (the first sweep of a correction that starts
+    // from zero) is one launch that reads no iterate; with fused_sweep every
+    // other sweep of a tiled level is one fused launch too (out of place:
+    // cur -> the other buffer), else two half-sweeps (cur -> tmp -> cur).
+    // The first sweep's output buffer is chosen so that the last sweep lands
+    // in x.
+    const bool all = c->opt.fused_sweep == 1 && tiled_ok(L);
     T *cur = zero ? nullptr : x;
     for (int s = 0; s < nu; ++s) {
       if (!cur) {
@@ -407,12 +419,10 @@ static hipError_t smooth(sbm_ctx *c, int l, T *x, const T *f, T *tmp, int nu, bo
         T *oth = cur == x ? tmp : x;
         {
           ProfScope ps(c, SBM_PROF_SMOOTH, l == 0);
-          if ((e = launch_rb_tiled<T>(L, psi, C, cur, f, oth, om, c0, c->st)) != hipSuccess)
-            return e;
+          if ((e = half_sweep<T>(L, psi, C, cur, f, oth, om, c0, c->st)) != hipSuccess) return e;
         }
         ProfScope ps(c, SBM_PROF_SMOOTH, l == 0);
-        if ((e = launch_rb_tiled<T>(L, psi, C, oth, f, cur, om, 1 - c0, c->st)) != hipSuccess)
-          return e;
+        if ((e = half_sweep<T>(L, psi, C, oth, f, cur, om, 1 - c0, c->st)) != hipSuccess) return e;
       }
     }
     if (!cur) return launch_fill<T>(x, (int64_t)c->dim * L.g.nn, T(0), c->st);
@@ -473,7 +483,7 @@ static hipError_t vcycle(sbm_ctx *c, int l, T *x, const T *f, T *tmp) {
   }
   Level &L = c->L[l];
   Level &C = c->L[l + 1];
-  if ((e = smooth<T>(c, l, x, f, tmp, c->opt.nu_pre, false)) != hipSuccess) return e;
+  if ((e = smooth<T>(c, l, x, f, tmp, c->opt.nu_pre, false, true)) != hipSuccess) return e;
   {
     ProfScope ps(c, SBM_PROF_RESIDUAL, l == 0);
     if ((e = launch_residual<T>(L, Prec<T>::psi(L), Prec<T>::coef(L), x, f, tmp, nullptr,
@@ -492,7 +502,7 @@ static hipError_t vcycle(sbm_ctx *c, int l, T *x, const T *f, T *tmp) {
   }
   // as a CG preconditioner the cycle is made symmetric: post-smoothing runs
   // the colours in reverse order
-  return smooth<T>(c, l, x, f, tmp, c->opt.nu_post, c->opt.krylov == 1);
+  return smooth<T>(c, l, x, f, tmp, c->opt.nu_post, c->opt.krylov == 1, false);
 }
 
 hipError_t sbm::base_vcycle(sbm_ctx *c, int precision, void *x, const void *f) {
