@@ -47,9 +47,15 @@ struct Level {
 // blocks launched after the tiles (xface / yface say which); a tile holding that single
 // column would cost a whole tile's stencil rounds for 1/64 of the work.
 constexpr int kTileX = 64, kTileY = 8;
+// Chunks along z: with nzc > 0 (launches over a whole level) chunk tz holds
+// planes [tz nz / nzc, (tz + 1) nz / nzc), depths differing by at most one, so
+// that every tile -- and every XCD's contiguous range of tiles -- carries the
+// same work; with nzc == 0 (tile lists, per-plane block maps) chunk tz holds
+// planes [tz kz, min((tz + 1) kz, nz)).  kz is the deepest chunk either way.
 struct TileGeom {
   int ntx, nty, kz, ntiles;
   int xface, yface, nface;
+  int nzc;
 };
 // Tiles of level L in chunks of kz planes (0: the default depth, chosen so
 // that the whole level gives about 1536 tiles).

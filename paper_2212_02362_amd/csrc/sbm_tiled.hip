@@ -42,10 +42,39 @@ __device__ __forceinline__ bool tg_dirichlet(const TG &g, int i, int j, int k, i
          ((k == 0) && ((m >> 12) & 1u)) || ((k == g.nz - 1) && ((m >> 15) & 1u));
 }
 
-// faces: the last node column / row of a 2^n + 1 level go to node-parallel
-// face blocks (launches over the whole level only; tile lists and the fused
-// sweep keep whole tiles).
-TileGeom tile_geom(const TG &g, bool faces = false, int kz_set = 0);
+// whole: a launch over the whole level -- the last node column / row of a
+// 2^n + 1 level go to node-parallel face blocks, and the z chunks are
+// balanced (tile lists and the fused sweep keep whole tiles and fixed-depth
+// chunks).  target: the number of tiles a whole-level launch aims at.
+TileGeom tile_geom(const TG &g, bool whole = false, int kz_set = 0, int target = kTileWG);
+
+// Whole-level tile targets per kernel, measured at the 257^3 level (128 tile
+// columns; isolated launches, balanced chunks of 10 to 24 planes):
+//   FP64 half-sweep: 14 chunks (335 us; 12, 16 and 24 chunks 354-360 us --
+//     the eight XCDs then start their tile ranges at the same place in a
+//     layer of tiles);
+//   FP64 sweep from zero (three workgroups per CU): 12 chunks, two full
+//     rounds of resident workgroups (342 us; 14 chunks 363 us);
+//   FP64 residual and Krylov Apply: 14 chunks (386 and 296 us, within 2 %
+//     of the best count);
+//   FP32 (half the LDS, more resident workgroups): 16 chunks for all three
+//     (200, 228 and 206 us).
+enum class TileKind { half, zero, full };
+template <typename T>
+constexpr int tile_target(TileKind k) {
+  return sizeof(T) != 8 ? 2048 : (k == TileKind::zero ? 1536 : 1792);
+}
+
+// Planes [k0, k1) of chunk tz.
+__device__ __forceinline__ void tile_chunk(const TileGeom &tg, int tz, int nz, int &k0, int &k1) {
+  if (tg.nzc > 0) {
+    k0 = tz * nz / tg.nzc;
+    k1 = (tz + 1) * nz / tg.nzc;
+  } else {
+    k0 = tz * tg.kz;
+    k1 = min(k0 + tg.kz, nz);
+  }
+}
 
 // Face node f of a launch with face blocks: the last column x = nx-1 (all
 // rows) first, then the last row y = ny-1 (the other columns), plane by plane.
@@ -65,15 +94,27 @@ __device__ __forceinline__ bool face_node(const TG &g, const TileGeom &tg, int f
   return true;
 }
 
-TileGeom tile_geom(const TG &g, bool faces, int kz_set) {
+TileGeom tile_geom(const TG &g, bool whole, int kz_set, int target) {
   TileGeom t;
-  t.xface = faces && g.nx > TX && g.nx % TX == 1;
-  t.yface = faces && g.ny > TY && g.ny % TY == 1;
+  t.xface = whole && g.nx > TX && g.nx % TX == 1;
+  t.yface = whole && g.ny > TY && g.ny % TY == 1;
   t.ntx = t.xface ? g.nx / TX : (g.nx + TX - 1) / TX;
   t.nty = t.yface ? g.ny / TY : (g.ny + TY - 1) / TY;
   const int64_t per_plane = (t.xface ? g.ny : 0) + (t.yface ? g.nx - t.xface : 0);
   t.nface = (int)((per_plane * g.nz + NT - 1) / NT);
   const int cols = t.ntx * t.nty;
+  t.nzc = 0;
+  if (whole && kz_set == 0) {
+    // about `target` tiles (at the 257^3 level a whole number of rounds of
+    // the resident workgroups), each chunk 4 to kTileKzMax planes deep
+    int nzc = target / cols;
+    nzc = std::min(nzc, g.nz / 4);
+    nzc = std::max(nzc, (g.nz + kTileKzMax - 1) / kTileKzMax);
+    t.nzc = std::max(nzc, 1);
+    t.kz = (g.nz + t.nzc - 1) / t.nzc;
+    t.ntiles = cols * t.nzc;
+    return t;
+  }
   // enough workgroups to fill 256 CUs several times over; each chunk re-reads
   // two planes
   int kz = kz_set > 0 ? kz_set : (int)((int64_t)g.nz * cols / kTileWG);
@@ -314,7 +355,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
   const int tx = lt % tg.ntx, rest = lt / tg.ntx;
   const int ty = rest % tg.nty, tz = rest / tg.nty;
   const int x0 = tx * TX, y0 = ty * TY;
-  const int k0 = tz * tg.kz, k1 = min(k0 + tg.kz, g.nz);
+  int k0, k1;
+  tile_chunk(tg, tz, g.nz, k0, k1);
   int vu[NUPT], vp[NPCT];
   tile_slots<W>(g, x0, y0, vu, vp);
   const int yl = threadIdx.x / (TX / 2), p = threadIdx.x % (TX / 2);
@@ -451,7 +493,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
   const int tx = lt % tg.ntx, rest = lt / tg.ntx;
   const int ty = rest % tg.nty, tz = rest / tg.nty;
   const int x0 = tx * TX, y0 = ty * TY;
-  const int k0 = tz * tg.kz, k1 = min(k0 + tg.kz, g.nz);
+  int k0, k1;
+  tile_chunk(tg, tz, g.nz, k0, k1);
   int vu[NUPT], vp[NPCT];
   tile_slots<W>(g, x0, y0, vu, vp);
   const int yl = threadIdx.x / (TX / 2), p = threadIdx.x % (TX / 2);
@@ -532,7 +575,9 @@ __global__ __launch_bounds__(256) void k_tile_flags(TG g, TileGeom tg,
                                                     int *__restrict__ flags) {
   const int t = blockIdx.x;
   const int tx = t % tg.ntx, rest = t / tg.ntx, ty = rest % tg.nty, tz = rest / tg.nty;
-  const int x0 = tx * TX, y0 = ty * TY, k0 = tz * tg.kz, k1 = min(k0 + tg.kz, g.nz);
+  const int x0 = tx * TX, y0 = ty * TY;
+  int k0, k1;
+  tile_chunk(tg, tz, g.nz, k0, k1);
   int any = 0;
   const int n = TX * TY * (k1 - k0);
   for (int e = threadIdx.x; e < n; e += blockDim.x) {
@@ -784,8 +829,8 @@ __global__ __launch_bounds__(NT) void k_rb_fused(TG g, Coef<T> C, const T *__res
   const int ty = rest % tg.nty;
   const int tz = rest / tg.nty;
   const int x0 = tx * TX, y0 = ty * TY;
-  const int k0 = tz * tg.kz;
-  const int k1 = min(k0 + tg.kz, g.nz);
+  int k0, k1;
+  tile_chunk(tg, tz, g.nz, k0, k1);
   const int nn = g.nn, nxy = g.nx * g.ny;
   const int t = threadIdx.x;
   const int yl = t / (TX / 2), p = t % (TX / 2);
@@ -1079,7 +1124,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_
   const int tx = li % tg.ntx, rest = li / tg.ntx;
   const int ty = rest % tg.nty, tz = rest / tg.nty;
   const int x0 = tx * TX, y0 = ty * TY;
-  const int k0 = tz * tg.kz, k1 = min(k0 + tg.kz, g.nz);
+  int k0, k1;
+  tile_chunk(tg, tz, g.nz, k0, k1);
   const int xe = (tg.xface && tx == tg.ntx - 1) ? 1 : 0;  // the tile also owns x = x0 + 64
   const int ye = (tg.yface && ty == tg.nty - 1) ? 1 : 0;  // ... and y = y0 + 8
   const int t = threadIdx.x;
@@ -1316,7 +1362,8 @@ hipError_t launch_rb_tiled(const Level &L, const T *psi, const Coef<T> &C, const
                            T *u_out, double omega, int colour, hipStream_t st,
                            const uint8_t *cls, const TileList *tl) {
   const TG gg = make_tg(L.g);
-  const TileGeom tg = tile_geom(gg, tl == nullptr, tl ? tl->kz : 0);
+  const TileGeom tg =
+      tile_geom(gg, tl == nullptr, tl ? tl->kz : 0, tile_target<T>(TileKind::half));
   const int n = tl ? tl->count : tg.ntiles;
   const int *ids = tl ? tl->ids : nullptr;
   CoefCubic<T> cc;
@@ -1354,7 +1401,7 @@ hipError_t launch_rb_fused(const Level &L, const T *psi, const Coef<T> &C, const
   } else {
     // from zero: k_rb_zero over the tiles of the whole level (the last node
     // column / row of a 2^n + 1 level in the edge tiles)
-    const TileGeom tz = tile_geom(gg, true);
+    const TileGeom tz = tile_geom(gg, true, 0, tile_target<T>(TileKind::zero));
     TileGeom tf = tz;
     tf.nface = 0;
     const dim3 zgrid((tf.ntiles + 7) / 8 * 8);
@@ -1376,8 +1423,9 @@ template hipError_t launch_rb_fused<float>(const Level &, const float *, const C
                                            const float *, const float *, float *, double, int,
                                            hipStream_t);
 
+// (the FP64 launch geometry: only FP64 launches write partial sums)
 int tiled_partials(const Level &L) {
-  const TileGeom tg = tile_geom(make_tg(L.g), true);
+  const TileGeom tg = tile_geom(make_tg(L.g), true, 0, tile_target<double>(TileKind::full));
   return tg.ntiles + tg.nface;
 }
 
@@ -1386,7 +1434,8 @@ static void full_tiled(const Level &L, const T *psi, const Coef<T> &C, const T *
                        T *r, double *partials, hipStream_t st, const uint8_t *cls,
                        const TileList *tl) {
   const TG gg = make_tg(L.g);
-  const TileGeom tg = tile_geom(gg, tl == nullptr, tl ? tl->kz : 0);
+  const TileGeom tg =
+      tile_geom(gg, tl == nullptr, tl ? tl->kz : 0, tile_target<T>(TileKind::full));
   const int n = tl ? tl->count : tg.ntiles;
   const int *ids = tl ? tl->ids : nullptr;
   CoefCubic<T> cc;
@@ -1413,6 +1462,7 @@ template <typename T>
 hipError_t launch_residual_tiled(const Level &L, const T *psi, const Coef<T> &C, const T *u,
                                  const T *f, T *r, double *partials, hipStream_t st,
                                  const uint8_t *cls, const TileList *tl) {
+  if (partials && sizeof(T) != 8) return hipErrorInvalidValue;  // counted for FP64 tiles
   (void)hipGetLastError();
   full_tiled<T, 0>(L, psi, C, u, f, r, partials, st, cls, tl);
   return hipGetLastError();
