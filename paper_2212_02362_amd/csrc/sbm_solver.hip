@@ -77,6 +77,9 @@ struct sbm_ctx {
   int last_bottom_iters = 0;
   double *x0 = nullptr;  // finest-level iterate (fixed address for captured cycles)
   double *kr = nullptr, *kz = nullptr, *kp = nullptr, *kq = nullptr;  // flexible CG vectors
+  // set while an FP64 CG preconditioner cycle is built: its last finest
+  // half-sweep also writes the partials of r . z there
+  double *rz_partials = nullptr;
   double *partials2 = nullptr;
   // live kernel timing (sbm_profile)
   bool prof_on = false;
@@ -444,9 +447,29 @@ static hipError_t smooth(sbm_ctx *c, int l, T *x, const T *f, T *tmp, int nu, bo
       if ((e = half(x, tmp, c0)) != hipSuccess) return e;
     }
     ProfScope ps(c, SBM_PROF_SMOOTH, l == 0);
+    // the last half-sweep of a CG preconditioner's cycle writes z (= x) and
+    // forms the partials of r . z (r = f) on the way
+    double *dot = (l == 0 && !pre && s == nu - 1 && tiled) ? c->rz_partials : nullptr;
+    if constexpr (sizeof(T) == 8) {
+      if (dot) {
+        if ((e = launch_rb_tiled<T>(L, psi, C, tmp, f, x, om, 1 - c0, c->st, nullptr, nullptr,
+                                    dot)) != hipSuccess)
+          return e;
+        continue;
+      }
+    }
     if ((e = half(tmp, x, 1 - c0)) != hipSuccess) return e;
   }
   return e;
+}
+
+// Whether the FP64 CG preconditioner's last finest half-sweep forms r . z
+// (Gauss-Seidel post-smoothing of a tiled finest level outside the tail).
+static bool rz_fused(const sbm_ctx *c) {
+  const Level &L0 = c->L[0];
+  return c->opt.precision == 0 && c->opt.smoother == 0 && c->opt.nu_post >= 1 && c->nlev > 1 &&
+         c->tail64 != 0 && c->opt.fused_sweep != 1 && tiled_ok(L0) &&
+         rb_tiled_partials(L0) <= c->npart;
 }
 
 static hipError_t bottom64(sbm_ctx *c, const double *f, double *x) {
@@ -606,7 +629,9 @@ static hipError_t cycle_body(sbm_ctx *c, const double *f, int mode) {
     } else if ((e = launch_fill<double>(c->kz, nv, 0.0, c->st)) != hipSuccess) {
       return e;
     }
+    c->rz_partials = rz_fused(c) ? c->partials : nullptr;
     e = vcycle<double>(c, 0, c->kz, c->kr, L0.t);
+    c->rz_partials = nullptr;
     c->first_half_done = false;
     c->zero_start = false;
     return e;
@@ -737,6 +762,9 @@ static sbm_status solve_krylov(sbm_ctx *c, const double *f, double fnorm, double
   const int64_t nv = (int64_t)c->dim * L0.g.nn;
   const int nb = num_blocks(L0.g.nn);       // node-parallel kernels
   const int ns = stencil_partials(L0);      // residual / Apply kernels
+  // r . z from the preconditioner's last half-sweep, else a pass of its own
+  const bool rzf = rz_fused(c);
+  const int nrz = rzf ? rb_tiled_partials(L0) : 0;
   double rho_min = INFINITY, rho = 0.0;
   sbm_status status = SBM_NOT_CONVERGED;
   // the preconditioned residual: kz, or (mixed) scal[6] * the FP32 correction
@@ -774,8 +802,12 @@ static sbm_status solve_krylov(sbm_ctx *c, const double *f, double fnorm, double
     }
     if (restart) {
       SBM_TRY(run_cycle(c, nullptr, 1));
-      HIP_TRY(launch_dot_free(L0, c->kr, z, c->partials, c->st));
-      HIP_TRY(launch_finalize_sum(c->partials, nb, c->scal + 4, c->st));
+      if (rzf) {
+        HIP_TRY(launch_finalize_sum(c->partials, nrz, c->scal + 4, c->st));
+      } else {
+        HIP_TRY(launch_dot_free(L0, c->kr, z, c->partials, c->st));
+        HIP_TRY(launch_finalize_sum(c->partials, nb, c->scal + 4, c->st));
+      }
       HIP_TRY(launch_xpby_x(L0, c->x0, c->kp, z, nullptr, nullptr, nullptr, nullptr, c->st));
       restart = false;
     }
@@ -813,8 +845,12 @@ static sbm_status solve_krylov(sbm_ctx *c, const double *f, double fnorm, double
     }
     if (hist && m < cap) hist[m] = rho;
     SBM_TRY(run_cycle(c, nullptr, 1));
-    HIP_TRY(launch_dot_free(L0, c->kr, z, c->partials, c->st));
-    HIP_TRY(launch_finalize_sum(c->partials, nb, c->scal + 1, c->st));
+    if (rzf) {
+      HIP_TRY(launch_finalize_sum(c->partials, nrz, c->scal + 1, c->st));
+    } else {
+      HIP_TRY(launch_dot_free(L0, c->kr, z, c->partials, c->st));
+      HIP_TRY(launch_finalize_sum(c->partials, nb, c->scal + 1, c->st));
+    }
     HIP_TRY(launch_xpby_x(L0, c->x0, c->kp, z, c->scal + 1, c->scal + 3, c->scal + 4,
                           c->scal + 5, c->st));
     HIP_TRY(launch_copy<double>(c->scal + 1, c->scal + 4, 1, c->st));

@@ -300,31 +300,42 @@ __device__ __forceinline__ int tile_or_face(int n) {
 }
 
 // A face node (last column / row of a 2^n + 1 level) of a whole-level tiled
-// half-sweep: one node per thread from global memory, the same update.
-template <typename T, typename CO, bool MASK>
+// half-sweep: one node per thread from global memory, the same update.  With
+// DOT the block's sum of f . u_out over free DOF goes to partials[ntiles + fb].
+template <typename T, typename CO, bool MASK, bool DOT>
 __device__ __forceinline__ void rb_face_node(const TG &g, const CO &C, const T *psi,
                                              const T *u, const T *f, T *u_out, T omega,
                                              int colour, const TileGeom &tg,
-                                             const uint8_t *cls, int fb) {
+                                             const uint8_t *cls, int fb, double *partials,
+                                             double *red) {
   int x, y, z;
-  if (!face_node(g, tg, fb * NT + (int)threadIdx.x, x, y, z)) return;
-  const int nn = g.nn;
-  const int q = x + g.nx * (y + g.ny * z);
-  T nv[3];
-  if (((x + y + z) & 1) == colour && !(MASK && cls[q] != 1)) {
-    T out[3], dg[3], uc[3];
-    node_stencil<T, 3, true, TG, CO>(g, C, psi, u, x, y, z, out, dg, uc);
+  double acc = 0.0;
+  if (face_node(g, tg, fb * NT + (int)threadIdx.x, x, y, z)) {
+    const int nn = g.nn;
+    const int q = x + g.nx * (y + g.ny * z);
+    T nv[3];
+    if (((x + y + z) & 1) == colour && !(MASK && cls[q] != 1)) {
+      T out[3], dg[3], uc[3];
+      node_stencil<T, 3, true, TG, CO>(g, C, psi, u, x, y, z, out, dg, uc);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const T upd_c = uc[c] + omega * (f[c * nn + q] - out[c]) / dg[c];
+        nv[c] = tg_dirichlet(g, x, y, z, c) ? uc[c] : upd_c;
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) nv[c] = u[c * nn + q];
+    }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const T upd_c = uc[c] + omega * (f[c * nn + q] - out[c]) / dg[c];
-      nv[c] = tg_dirichlet(g, x, y, z, c) ? uc[c] : upd_c;
+      u_out[c * nn + q] = nv[c];
+      if (DOT && !tg_dirichlet(g, x, y, z, c)) acc += (double)f[c * nn + q] * (double)nv[c];
     }
-  } else {
-#pragma unroll
-    for (int c = 0; c < 3; ++c) nv[c] = u[c * nn + q];
   }
-#pragma unroll
-  for (int c = 0; c < 3; ++c) u_out[c * nn + q] = nv[c];
+  if constexpr (DOT) {
+    const double sum = block_sum(acc, red);
+    if (threadIdx.x == 0) partials[tg.ntiles + fb] = sum;
+  }
 }
 
 // Colour-synchronous Gauss-Seidel half-sweep (nodes with (x+y+z) mod 2 ==
@@ -332,17 +343,22 @@ __device__ __forceinline__ void rb_face_node(const TG &g, const CO &C, const T *
 // tiles and, in a whole-level launch, the face blocks.  With MASK only
 // class-1 nodes are updated.  A thread owns an x-pair (one node of each
 // colour) and stores both.  The u and psi planes of the next step and f of
-// the next plane are loaded while the current plane is computed.
-template <typename T, typename CO, bool MASK>
+// the next plane are loaded while the current plane is computed.  With DOT
+// (a whole-level launch) each tile also sums f . u_out over its free DOF --
+// r . z of a preconditioned CG whose V-cycle ends with this half-sweep -- into
+// partials[tile], the face blocks into partials[ntiles + face block].
+template <typename T, typename CO, bool MASK, bool DOT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_rb_tile(
     TG g, CO C, const T *__restrict__ psi, const T *__restrict__ u, const T *__restrict__ f,
     T *__restrict__ u_out, T omega, int colour, TileGeom tg, const uint8_t *__restrict__ cls,
-    const int *__restrict__ ids, int n) {
+    const int *__restrict__ ids, int n, double *__restrict__ partials) {
   __shared__ T su[3][SLOT_U];
   __shared__ T sp[2][SLOT_P];
+  __shared__ double red[DOT ? NT / 64 + 1 : 1];
   const int li = tile_or_face(n);
   if (li < 0) {
-    rb_face_node<T, CO, MASK>(g, C, psi, u, f, u_out, omega, colour, tg, cls, -1 - li);
+    rb_face_node<T, CO, MASK, DOT>(g, C, psi, u, f, u_out, omega, colour, tg, cls, -1 - li,
+                                   partials, red);
     return;
   }
   if (li >= n) return;
@@ -366,24 +382,34 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
   const int vn1 = (gy < g.ny && x0 + 2 * p + 1 < g.nx) ? (gy * g.nx + x0 + 2 * p + 1) * W : kOOB;
   const int pg = (colour + gy) & 1;  // the updated column of plane k is x0 + 2p + ((pg + k) & 1)
   // f at the updated node of plane k (zeros past the chunk)
-  auto fetch_f = [&](int k, T (&r)[3]) __attribute__((always_inline)) {
+  // (with DOT also at the copied node)
+  auto fetch_f = [&](int k, T (&r)[3], T (&rc)[3]) __attribute__((always_inline)) {
     const bool ok = k < k1;
     const __amdgpu_buffer_rsrc_t rf = ok ? B.f : B.null;
     const int vo = ((pg + k) & 1) ? vn1 : vn0;
     const int so = ok ? k * nxy * W : 0;
 #pragma unroll
     for (int c = 0; c < 3; ++c) r[c] = bload<T>(rf, vo, so + (ok ? c * nn * W : 0));
+    if constexpr (DOT) {
+      const int vc = ((pg + k) & 1) ? vn0 : vn1;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) rc[c] = bload<T>(rf, vc, so + (ok ? c * nn * W : 0));
+    }
   };
-  T FN[3];
-  fetch_f(k0, FN);
+  T FN[3], FC[3];
+  fetch_f(k0, FN, FC);
   tile_prologue<T>(g, B, vu, vp, k0, su, sp);
   __syncthreads();
+  double acc = 0.0;
   T RU[NUPT], RP[NPCT];
   for (int k = k0; k < k1; ++k) {
-    T fv[3];
+    T fv[3], fc[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) fv[c] = FN[c];
-    fetch_f(k + 1, FN);
+    for (int c = 0; c < 3; ++c) {
+      fv[c] = FN[c];
+      if (DOT) fc[c] = FC[c];
+    }
+    fetch_f(k + 1, FN, FC);
     tile_fetch_u<T>(g, B, vu, k + 2, RU);
     tile_fetch_p<T>(g, B, vp, k + 1, RP);
     const T *Lm = su[(k + 2) % 3], *L0 = su[k % 3], *L1 = su[(k + 1) % 3];
@@ -419,11 +445,27 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
       bstore<T>(nv[c], B.out, vo_u, so + c * nn * W);
       bstore<T>(L0[c * PLANE + cc], B.out, vo_c, so + c * nn * W);
     }
+    if constexpr (DOT) {
+      // f . u_out at both nodes (f reads 0 at a node outside the box)
+      const int gxc = par ? gxu - 1 : gxu + 1;
+      const bool fy = gy == 0 || gy == g.ny - 1 || k == 0 || k == g.nz - 1;
+      const bool fu = fy || gxu == 0 || gxu == g.nx - 1, fcn = fy || gxc == 0 || gxc == g.nx - 1;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if (!(fu && tg_dirichlet(g, gxu, gy, k, c))) acc += (double)fv[c] * (double)nv[c];
+        if (!(fcn && tg_dirichlet(g, gxc, gy, k, c)))
+          acc += (double)fc[c] * (double)L0[c * PLANE + cc];
+      }
+    }
     __syncthreads();
     // the planes of the next step go to the slots of planes k - 1 (u, cells)
     tile_put_u<T>(su[(k + 2) % 3], RU);
     tile_put_p<T>(sp[(k + 1) & 1], RP);
     __syncthreads();
+  }
+  if constexpr (DOT) {
+    const double sum = block_sum(acc, red);
+    if (threadIdx.x == 0) partials[li] = sum;
   }
 }
 
@@ -1360,7 +1402,7 @@ static int tiled_grid(int n, int nface) { return (n + 7) / 8 * 8 + nface; }
 template <typename T>
 hipError_t launch_rb_tiled(const Level &L, const T *psi, const Coef<T> &C, const T *u, const T *f,
                            T *u_out, double omega, int colour, hipStream_t st,
-                           const uint8_t *cls, const TileList *tl) {
+                           const uint8_t *cls, const TileList *tl, double *partials) {
   const TG gg = make_tg(L.g);
   const TileGeom tg =
       tile_geom(gg, tl == nullptr, tl ? tl->kz : 0, tile_target<T>(TileKind::half));
@@ -1369,23 +1411,36 @@ hipError_t launch_rb_tiled(const Level &L, const T *psi, const Coef<T> &C, const
   CoefCubic<T> cc;
   const bool cubic = cubic_coef(C, cc);
   (void)hipGetLastError();
+  // the f . u_out partials: FP64 whole-level launches only
+  if (partials && (cls || tl || sizeof(T) != 8)) return hipErrorInvalidValue;
   const int nface = tl ? 0 : tg.nface;
   if (n + nface > 0) {
     const dim3 grid(tiled_grid(n, nface)), block(NT);
-    if (cls && cubic)
-      hipLaunchKernelGGL((k_rb_tile<T, CoefCubic<T>, true>), grid, block, 0, st, gg, cc, psi, u,
-                         f, u_out, (T)omega, colour, tg, cls, ids, n);
+    if (partials && cubic)
+      hipLaunchKernelGGL((k_rb_tile<T, CoefCubic<T>, false, true>), grid, block, 0, st, gg, cc,
+                         psi, u, f, u_out, (T)omega, colour, tg, cls, ids, n, partials);
+    else if (partials)
+      hipLaunchKernelGGL((k_rb_tile<T, Coef<T>, false, true>), grid, block, 0, st, gg, C, psi,
+                         u, f, u_out, (T)omega, colour, tg, cls, ids, n, partials);
+    else if (cls && cubic)
+      hipLaunchKernelGGL((k_rb_tile<T, CoefCubic<T>, true, false>), grid, block, 0, st, gg, cc,
+                         psi, u, f, u_out, (T)omega, colour, tg, cls, ids, n, partials);
     else if (cls)
-      hipLaunchKernelGGL((k_rb_tile<T, Coef<T>, true>), grid, block, 0, st, gg, C, psi, u, f,
-                         u_out, (T)omega, colour, tg, cls, ids, n);
+      hipLaunchKernelGGL((k_rb_tile<T, Coef<T>, true, false>), grid, block, 0, st, gg, C, psi,
+                         u, f, u_out, (T)omega, colour, tg, cls, ids, n, partials);
     else if (cubic)
-      hipLaunchKernelGGL((k_rb_tile<T, CoefCubic<T>, false>), grid, block, 0, st, gg, cc, psi, u,
-                         f, u_out, (T)omega, colour, tg, cls, ids, n);
+      hipLaunchKernelGGL((k_rb_tile<T, CoefCubic<T>, false, false>), grid, block, 0, st, gg, cc,
+                         psi, u, f, u_out, (T)omega, colour, tg, cls, ids, n, partials);
     else
-      hipLaunchKernelGGL((k_rb_tile<T, Coef<T>, false>), grid, block, 0, st, gg, C, psi, u, f,
-                         u_out, (T)omega, colour, tg, cls, ids, n);
+      hipLaunchKernelGGL((k_rb_tile<T, Coef<T>, false, false>), grid, block, 0, st, gg, C, psi,
+                         u, f, u_out, (T)omega, colour, tg, cls, ids, n, partials);
   }
   return hipGetLastError();
+}
+
+int rb_tiled_partials(const Level &L) {
+  const TileGeom tg = tile_geom(make_tg(L.g), true, 0, tile_target<double>(TileKind::half));
+  return tg.ntiles + tg.nface;
 }
 
 template <typename T>
@@ -1486,9 +1541,11 @@ template hipError_t launch_residual_tiled<float>(const Level &, const float *, c
 
 template hipError_t launch_rb_tiled<double>(const Level &, const double *, const Coef<double> &,
                                             const double *, const double *, double *, double,
-                                            int, hipStream_t, const uint8_t *, const TileList *);
+                                            int, hipStream_t, const uint8_t *, const TileList *,
+                                            double *);
 template hipError_t launch_rb_tiled<float>(const Level &, const float *, const Coef<float> &,
                                            const float *, const float *, float *, double, int,
-                                           hipStream_t, const uint8_t *, const TileList *);
+                                           hipStream_t, const uint8_t *, const TileList *,
+                                           double *);
 
 }  // namespace sbm
