@@ -162,7 +162,7 @@ def _bench_amr(args):
                    "cycles": r["cyc"], "final_rel_residual": max(r["fin"]), "status": r["st"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_rb_tile<double, CoefCubic<double>, true> (LDS-tiled class-masked half-sweep) over the "
+                     "kernel": "k_rb_tile<double, CoefCubic<double>, true, false> (LDS-tiled class-masked half-sweep) over the "
                                "tiles of the finest adaptive level that hold active blocks",
                      "algo_bytes_per_launch": by, "avg_launch_us": avg_ms * 1e3,
                      "timing": "HIP events around each finest-level launch, one profiled solve "
@@ -669,7 +669,7 @@ COUNTER_KERNELS = {
     "spherical_voids_129": (TRAFFIC_KERNEL, "k_rb_half<double, 3, false>",
                             ("sbm_device.h", "sbm_kernels.hip")),
     "diffuse_crack_257": ("k_rb_tile<double,false>",
-                          "k_rb_tile<double, sbm::CoefCubic<double>, false>",
+                          "k_rb_tile<double, sbm::CoefCubic<double>, false, false>",
                           ("sbm_device.h", "sbm_tiled.hip")),
 }
 COPY_BYTES = 400_000_000  # calibration copy: this many bytes read and written
@@ -975,8 +975,9 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "measured_triad_GBps": triad["GBps"],
                      "frac_of_measured_triad": achieved / triad["GBps"],
-                     "kernel": ("k_rb_tile<double, CoefCubic<double>, false> (LDS-tiled "
-                                "finest-level Gauss-Seidel half-sweep)" if tiled else
+                     "kernel": ("k_rb_tile<double, CoefCubic<double>, false, false|true> (LDS-tiled "
+                                "finest-level Gauss-Seidel half-sweep; the last of a cycle "
+                                "also sums r.z)" if tiled else
                                 "k_rb_half<double,3,false> (finest-level Gauss-Seidel half-sweep)"),
                      "algo_bytes_per_launch": by, "avg_launch_us": avg_ms * 1e3,
                      "timing": "HIP events on the solver's stream around each finest-level launch "

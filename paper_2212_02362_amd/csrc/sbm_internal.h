@@ -175,9 +175,11 @@ hipError_t launch_apply_dot(const Level &L, const double *p, double *q, double *
 // (alpha = rz / pq, stored to *alpha_out) with the r.r and r.z partials; then
 // x += (*alpha) p (alpha may be NULL) and p = z + beta p in one pass; or
 // x += (*alpha) p alone.
+// With r32, also r32 = fp32(r / sqrt(*ss)) for the mixed preconditioner.
 hipError_t launch_cg_update_r(const Level &L, double *r, const double *q, const ZSrc &z,
                               const double *rz, const double *pq, double *alpha_out, double *pr,
-                              double *pz, hipStream_t st);
+                              double *pz, hipStream_t st, float *r32 = nullptr,
+                              const double *ss = nullptr);
 hipError_t launch_xpby_x(const Level &L, double *x, double *p, const ZSrc &z,
                          const double *rznew, const double *rzold, const double *rz,
                          const double *alpha, hipStream_t st);

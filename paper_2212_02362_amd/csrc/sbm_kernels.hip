@@ -649,7 +649,9 @@ __global__ __launch_bounds__(kBlock) void k_apply_dot(Geom g, Coef<double> C,
 // *alpha_out by the first thread), r -= alpha q on free DOF, partials of r.r
 // (pr) and r.z (pz, z = the previous preconditioned residual).  The update
 // x += alpha p is left to the next direction update (k_xpby_x) or to
-// k_axpy_free: the same products, one vector pass fewer.
+// k_axpy_free: the same products, one vector pass fewer.  With r32 the new
+// residual is also cast for the mixed preconditioner: r32 = fp32(r / s) with
+// s = sqrt(*ss) (0 on displacement DOF), as k_cast_scaled forms it.
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_cg_update_r(Geom g, double *__restrict__ r,
                                                         const double *__restrict__ q, ZSrc z,
@@ -657,7 +659,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_update_r(Geom g, double *__restri
                                                         const double *__restrict__ pq,
                                                         double *__restrict__ alpha_out,
                                                         double *__restrict__ pr,
-                                                        double *__restrict__ pz) {
+                                                        double *__restrict__ pz,
+                                                        float *__restrict__ r32,
+                                                        const double *__restrict__ ss) {
   __shared__ double lds[kBlock / 64 + 1];
   const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const double alpha = *rz / *pq;
@@ -676,11 +680,16 @@ __global__ __launch_bounds__(kBlock) void k_cg_update_r(Geom g, double *__restri
       zv[c] = zload(z, sz, qi);
     }
     const uint32_t fb = face_bits(g, i, j, k);
+    const double sn = r32 ? sqrt(*ss) : 0.0;
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
-      if ((g.dmask >> c) & fb) continue;
+      if ((g.dmask >> c) & fb) {
+        if (r32) r32[c * g.nn + id] = 0.0f;
+        continue;
+      }
       const double rn = rv[c] - alpha * qv[c];
       r[c * g.nn + id] = rn;
+      if (r32) r32[c * g.nn + id] = sn > 0.0 ? (float)(rn / sn) : 0.0f;
       srr += rn * rn;
       srz += rn * zv[c];
     }
@@ -1299,12 +1308,12 @@ hipError_t launch_apply_dot(const Level &L, const double *p, double *q, double *
 
 hipError_t launch_cg_update_r(const Level &L, double *r, const double *q, const ZSrc &z,
                               const double *rz, const double *pq, double *alpha_out, double *pr,
-                              double *pz, hipStream_t st) {
+                              double *pz, hipStream_t st, float *r32, const double *ss) {
   if (L.g.dim == 3)
     SBM_LAUNCH((k_cg_update_r<3>), num_blocks(L.g.nn), kBlock, st, L.g, r, q, z, rz, pq,
-               alpha_out, pr, pz);
+               alpha_out, pr, pz, r32, ss);
   SBM_LAUNCH((k_cg_update_r<2>), num_blocks(L.g.nn), kBlock, st, L.g, r, q, z, rz, pq, alpha_out,
-             pr, pz);
+             pr, pz, r32, ss);
 }
 
 hipError_t launch_xpby_x(const Level &L, double *x, double *p, const ZSrc &z,

@@ -463,6 +463,14 @@ static hipError_t smooth(sbm_ctx *c, int l, T *x, const T *f, T *tmp, int nu, bo
   return e;
 }
 
+// Whether the mixed CG update casts the new residual for the preconditioner
+// itself (a tiled finest level whose cycle starts with the sweep from zero):
+// the cycle then runs as mode 4.
+static bool cast_fused(const sbm_ctx *c) {
+  return c->opt.precision == 1 && c->opt.smoother == 0 && c->opt.nu_pre >= 1 && c->nlev > 1 &&
+         c->tail32 != 0 && tiled_ok(c->L[0]);
+}
+
 // Whether the FP64 CG preconditioner's last finest half-sweep forms r . z
 // (Gauss-Seidel post-smoothing of a tiled finest level outside the tail).
 static bool rz_fused(const sbm_ctx *c) {
@@ -591,6 +599,15 @@ static hipError_t cycle_body(sbm_ctx *c, const double *f, int mode) {
   Level &L0 = c->L[0];
   const int64_t nv = (int64_t)c->dim * L0.g.nn;
   hipError_t e;
+  if (mode == 4) {
+    // the mixed preconditioner on an FP32 load the CG update already cast
+    // (kr / s, s^2 in scal[7]): the finest level starts from zero
+    c->zero_start = true;
+    e = vcycle<float>(c, 0, L0.e32, L0.f32, L0.t32);
+    c->zero_start = false;
+    if (e != hipSuccess) return e;
+    return launch_store_sqrt(c->scal + 7, c->scal + 6, c->st);
+  }
   if (mode == 1) {
     // preconditioner: kz = M kr, one V-cycle from zero (mixed: on kr / ||kr||
     // in FP32, ||kr||^2 in scal[0]).  When the finest level smooths outside
@@ -752,7 +769,9 @@ static sbm_status fin_to_host(sbm_ctx *c, const double *partials, int n, int slo
 // Flexible CG (Polak-Ribiere beta) on the finest level, preconditioned by one
 // V-cycle from zero per iteration.  Device scalars: scal[0] = r.r,
 // scal[1] = r.z (new), scal[2] = p.q, scal[3] = r.z (old z), scal[4] = r.z
-// of the previous iteration, scal[5] = alpha of the last update.  The update
+// of the previous iteration, scal[5] = alpha of the last update; mixed:
+// scal[6] = the scale s of z = s e32, scal[7] = s^2 of the cast the CG update
+// makes.  The update
 // x += alpha p is deferred to the pass that forms the next direction (which
 // reads p anyway), or made on its own when the iteration ends: the iterates
 // are the same numbers.
@@ -764,6 +783,7 @@ static sbm_status solve_krylov(sbm_ctx *c, const double *f, double fnorm, double
   const int ns = stencil_partials(L0);      // residual / Apply kernels
   // r . z from the preconditioner's last half-sweep, else a pass of its own
   const bool rzf = rz_fused(c);
+  const bool castf = cast_fused(c);
   const int nrz = rzf ? rb_tiled_partials(L0) : 0;
   double rho_min = INFINITY, rho = 0.0;
   sbm_status status = SBM_NOT_CONVERGED;
@@ -820,9 +840,13 @@ static sbm_status solve_krylov(sbm_ctx *c, const double *f, double fnorm, double
       break;
     }
     // r -= alpha q; the iterate update x += alpha p (alpha kept in scal[5]) is
-    // made by the next direction update, or below when the iteration ends
+    // made by the next direction update, or below when the iteration ends.
+    // Mixed: the same pass casts r / s for the next cycle, s = the norm of
+    // the residual before the update (scal[0] -> scal[7]).
+    if (castf) HIP_TRY(launch_copy<double>(c->scal, c->scal + 7, 1, c->st));
     HIP_TRY(launch_cg_update_r(L0, c->kr, c->kq, z, c->scal + 4, c->scal + 2, c->scal + 5,
-                               c->partials, c->partials2, c->st));
+                               c->partials, c->partials2, c->st, castf ? L0.f32 : nullptr,
+                               castf ? c->scal + 7 : nullptr));
     SBM_TRY(fin_to_host(c, c->partials, nb, 0));
     SBM_TRY(fin_to_host(c, c->partials2, nb, 3));
     HIP_TRY(hipStreamSynchronize(c->st));
@@ -844,7 +868,7 @@ static sbm_status solve_krylov(sbm_ctx *c, const double *f, double fnorm, double
       continue;
     }
     if (hist && m < cap) hist[m] = rho;
-    SBM_TRY(run_cycle(c, nullptr, 1));
+    SBM_TRY(run_cycle(c, nullptr, castf ? 4 : 1));
     if (rzf) {
       HIP_TRY(launch_finalize_sum(c->partials, nrz, c->scal + 1, c->st));
     } else {
