@@ -336,7 +336,8 @@ typedef enum {
   SBM_PROF_BOTTOM = 5,   /* whole bottom solve */
   SBM_PROF_GHOST = 6,    /* coarse-fine ghost fill of the finest adaptive level */
   SBM_PROF_SWEEP0 = 7,   /* one-launch sweep from a zero iterate, finest level */
-  SBM_PROF_N = 8
+  SBM_PROF_SMOOTH_DOT = 8, /* finest-level half-sweep that also forms the CG product r.z */
+  SBM_PROF_N = 9
 } sbm_prof_class;
 sbm_status sbm_profile(sbm_ctx *ctx, int enable);
 sbm_status sbm_profile_read(sbm_ctx *ctx, double *ms_host, int64_t *count_host);

@@ -19,7 +19,8 @@ STATUS_NAMES = {0: "SBM_OK", 1: "SBM_NOT_CONVERGED", -1: "SBM_E_ARG", -2: "SBM_E
 TRACTION = 0
 DISPLACEMENT = 1
 CHAIN_PSI, CHAIN_FLOOR, CHAIN_RHO3 = 0, 1, 2
-PROF_CLASSES = ("smooth", "residual", "restrict", "prolong", "norm", "bottom", "ghost", "sweep0")
+PROF_CLASSES = ("smooth", "residual", "restrict", "prolong", "norm", "bottom", "ghost", "sweep0",
+                "smooth_dot")
 
 
 class SbmGrid(ctypes.Structure):

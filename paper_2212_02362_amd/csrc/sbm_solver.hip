@@ -446,10 +446,10 @@ static hipError_t smooth(sbm_ctx *c, int l, T *x, const T *f, T *tmp, int nu, bo
       ProfScope ps(c, SBM_PROF_SMOOTH, l == 0);
       if ((e = half(x, tmp, c0)) != hipSuccess) return e;
     }
-    ProfScope ps(c, SBM_PROF_SMOOTH, l == 0);
     // the last half-sweep of a CG preconditioner's cycle writes z (= x) and
     // forms the partials of r . z (r = f) on the way
     double *dot = (l == 0 && !pre && s == nu - 1 && tiled) ? c->rz_partials : nullptr;
+    ProfScope ps(c, dot ? SBM_PROF_SMOOTH_DOT : SBM_PROF_SMOOTH, l == 0);
     if constexpr (sizeof(T) == 8) {
       if (dot) {
         if ((e = launch_rb_tiled<T>(L, psi, C, tmp, f, x, om, 1 - c0, c->st, nullptr, nullptr,
