@@ -249,13 +249,10 @@ __global__ __launch_bounds__(kBlock) void k_rb_half(Geom g, Coef<T> C, const T *
 
 // f_coarse(I) = 2^-d sum_n P(n, I) r(n): full weighting [1/2, 1, 1/2] per axis
 // around the coincident fine node 2I; fine nodes outside the box are absent.
+// The coarse node (I, J, K) with linear index id.
 template <typename T, int DIM>
-__global__ __launch_bounds__(kBlock) void k_restrict(Geom gf, Geom gc, const T *__restrict__ r,
-                                                     T *__restrict__ fc, T *__restrict__ ec) {
-  const int64_t id = (int64_t)xcd_block() * (int)blockDim.x + threadIdx.x;
-  if (id >= gc.nn) return;
-  int I, J, K;
-  node_ijk(gc, id, I, J, K);
+__device__ __forceinline__ void restrict_node(const Geom &gf, const Geom &gc, const T *r, T *fc,
+                                              T *ec, int64_t id, int I, int J, int K) {
   // Branch-free gather (all 27 loads in flight together): a neighbour outside
   // the box is read at the centre with weight 0, which adds an exact zero, so
   // the sum equals the one over the neighbours inside, in the same order.
@@ -290,6 +287,186 @@ __global__ __launch_bounds__(kBlock) void k_restrict(Geom gf, Geom gc, const T *
     fc[c * gc.nn + id] = is_dirichlet(gc, I, J, K, c) ? T(0) : acc[c] * scale;
     if (ec) ec[c * gc.nn + id] = T(0);  // the coarse correction starts from zero
   }
+}
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(kBlock) void k_restrict(Geom gf, Geom gc, const T *__restrict__ r,
+                                                     T *__restrict__ fc, T *__restrict__ ec) {
+  const int64_t id = (int64_t)xcd_block() * (int)blockDim.x + threadIdx.x;
+  if (id >= gc.nn) return;
+  int I, J, K;
+  node_ijk(gc, id, I, J, K);
+  restrict_node<T, DIM>(gf, gc, r, fc, ec, id, I, J, K);
+}
+
+// Tiled full weighting for 3D levels.  A workgroup owns RCX x RCY coarse node
+// columns and a chunk of coarse planes [K0, K1); the fine planes 2 K0 - 1 ..
+// 2 K1 - 1 of the (2 RCX + 1) x (2 RCY + 1) fine window under it pass through
+// LDS, the next one loaded into registers while the current one is summed.
+// LDS rows hold the even local columns first, then the odd ones, so a coarse
+// column's centre (odd) and its two x-neighbours (even) are consecutive
+// across the threads.  Each coarse node adds its 27 weighted fine values in
+// k_restrict's order (z, y, x; a value outside the box is 0), so both give
+// the same numbers.  The tiles cover the coarse columns [0, cxn) x [0, cyn);
+// the last column / row of a 2^n + 1 coarse level (when cxn or cyn stops one
+// short) goes to k_restrict_rest.
+constexpr int RCX = 64, RCY = 4, RNT = RCX * RCY;
+constexpr int RHE = RCX + 1;                  // even local columns of the 2 RCX + 1 window
+constexpr int RROW = 2 * RHE;                 // LDS row (the odd half has one pad entry)
+constexpr int RWY = 2 * RCY + 1;              // fine rows of the window
+constexpr int RPL = 3 * RWY * RROW;           // LDS entries per fine plane
+constexpr int RPT = (RPL + RNT - 1) / RNT;
+
+struct RTile {
+  int cxn, cyn, ntx, nty, nzc, ntiles;
+};
+
+static RTile restrict_tiles(const Geom &gc) {
+  RTile t;
+  t.cxn = (gc.nx > RCX && gc.nx % RCX == 1) ? gc.nx - 1 : gc.nx;
+  t.cyn = (gc.ny > RCY && gc.ny % RCY == 1) ? gc.ny - 1 : gc.ny;
+  t.ntx = (t.cxn + RCX - 1) / RCX;
+  t.nty = (t.cyn + RCY - 1) / RCY;
+  // about 1024 workgroups (two rounds of two per CU), chunks of 2 or more
+  // coarse planes
+  const int cols = t.ntx * t.nty;
+  int nzc = 1024 / cols;
+  nzc = nzc > gc.nz / 2 ? gc.nz / 2 : nzc;
+  t.nzc = nzc < 1 ? 1 : nzc;
+  t.ntiles = cols * t.nzc;
+  return t;
+}
+
+template <typename T>
+__global__ __launch_bounds__(RNT) void k_restrict_tile(Geom gf, Geom gc, RTile rt,
+                                                       const T *__restrict__ r,
+                                                       T *__restrict__ fc, T *__restrict__ ec) {
+  __shared__ T sw[2][RPT * RNT];  // padded: every thread stores all its slots
+  const int n8 = gridDim.x;       // a multiple of 8
+  const int b = blockIdx.x;
+  const int li = (b & 7) * (n8 >> 3) + (b >> 3);
+  if (li >= rt.ntiles) return;
+  const int tx = li % rt.ntx, rest = li / rt.ntx;
+  const int ty = rest % rt.nty, tz = rest / rt.nty;
+  const int I0 = tx * RCX, J0 = ty * RCY;
+  const int K0 = tz * gc.nz / rt.nzc, K1 = (tz + 1) * gc.nz / rt.nzc;
+  const int t = threadIdx.x;
+  const int64_t fnxy = (int64_t)gf.nx * gf.ny;
+  // the thread's load slots: offset within a fine plane, or -1 (outside the
+  // box, or padding)
+  int off[RPT];
+#pragma unroll
+  for (int j = 0; j < RPT; ++j) {
+    const int e = t + j * RNT;
+    off[j] = -1;
+    if (e < RPL) {
+      const int c = e / (RWY * RROW), rr = e - c * (RWY * RROW);
+      const int y = rr / RROW, s = rr - y * RROW;
+      const int lx = s < RHE ? 2 * s : 2 * (s - RHE) + 1;
+      const int gx = 2 * I0 - 1 + lx, gy = 2 * J0 - 1 + y;
+      if (lx <= 2 * RCX && gx >= 0 && gx < gf.nx && gy >= 0 && gy < gf.ny)
+        off[j] = (int)(c * gf.nn + gx + (int64_t)gf.nx * gy);
+    }
+  }
+  auto fetch = [&](int fz, T (&v)[RPT]) __attribute__((always_inline)) {
+    const bool zin = fz >= 0 && fz < gf.nz;
+    const T *pl = r + (zin ? fz : 0) * fnxy;
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+      const bool ok = zin && off[j] >= 0;
+      const T val = pl[ok ? off[j] : 0];
+      v[j] = ok ? val : T(0);
+    }
+  };
+  auto put = [&](int buf, const T (&v)[RPT]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) sw[buf][t + j * RNT] = v[j];
+  };
+  const int cx = t % RCX, cy = t / RCX;
+  const int I = I0 + cx, J = J0 + cy;
+  const bool own = I < rt.cxn && J < rt.cyn;
+  // 2 K + dz, dz = -1, 0, 1, over the chunk's fine planes; a plane past the
+  // box reads 0
+  const int fz0 = 2 * K0 - 1, fz1 = 2 * K1 - 1;
+  T R[RPT];
+  fetch(fz0, R);
+  put(0, R);
+  __syncthreads();
+  T acc[3] = {T(0), T(0), T(0)};
+  for (int fz = fz0; fz <= fz1; ++fz) {
+    const int buf = (fz - fz0) & 1;
+    if (fz < fz1) fetch(fz + 1, R);
+    const T *W = sw[buf];
+    const bool odd = (fz & 1) != 0;
+    // the weighted values of this plane for the node (z weight 1/2 on odd
+    // planes, 1 on even), in k_restrict's y, x order
+    T pv[3][9];
+    const T wz = odd ? T(0.5) : T(1);
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+      const T wy = dy == 0 ? T(1) : T(0.5);
+      const int row = (2 * cy + 1 + dy) * RROW;
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        const T w = wz * wy * (dx == 0 ? T(1) : T(0.5));
+        const int col = dx == 0 ? RHE + cx : cx + (dx > 0 ? 1 : 0);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) pv[c][(dy + 1) * 3 + dx + 1] = w * W[c * RWY * RROW + row + col];
+      }
+    }
+    // an odd plane 2K + 1 closes coarse plane K (its dz = +1 terms) and opens
+    // K + 1 (dz = -1); an even plane 2K is the dz = 0 term of K
+    if (odd && fz > fz0) {
+      const int K = (fz - 1) / 2;
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int q = 0; q < 9; ++q) acc[c] += pv[c][q];
+      if (own) {
+        const int64_t id = I + (int64_t)gc.nx * (J + (int64_t)gc.ny * K);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          fc[c * gc.nn + id] = is_dirichlet(gc, I, J, K, c) ? T(0) : acc[c] * T(0.125);
+          if (ec) ec[c * gc.nn + id] = T(0);
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[c] = T(0);
+    }
+    if (fz < fz1 || !odd) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int q = 0; q < 9; ++q) acc[c] += pv[c][q];
+    }
+    if (fz < fz1) put(buf ^ 1, R);
+    __syncthreads();
+  }
+}
+
+// The coarse nodes the tiles leave (column cxn and row cyn of a 2^n + 1
+// coarse level), node-parallel as k_restrict.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_restrict_rest(Geom gf, Geom gc, RTile rt,
+                                                          const T *__restrict__ r,
+                                                          T *__restrict__ fc, T *__restrict__ ec,
+                                                          int n) {
+  const int e = blockIdx.x * kBlock + threadIdx.x;
+  if (e >= n) return;
+  const int ncol = gc.nx - rt.cxn;                      // 0 or 1 columns (all rows)
+  const int per = ncol * gc.ny + (gc.ny - rt.cyn) * rt.cxn;  // nodes per coarse plane
+  const int K = e / per;
+  const int q = e - K * per;
+  int I, J;
+  if (q < ncol * gc.ny) {
+    I = rt.cxn;
+    J = q;
+  } else {
+    I = q - ncol * gc.ny;
+    J = rt.cyn;
+  }
+  const int64_t id = I + (int64_t)gc.nx * (J + (int64_t)gc.ny * K);
+  restrict_node<T, 3>(gf, gc, r, fc, ec, id, I, J, K);
 }
 
 // u_fine += P e_coarse (multilinear, node-centred) on free fine DOF.  One
@@ -1209,6 +1386,18 @@ hipError_t launch_rb_half(const Level &L, const T *psi, const Coef<T> &C, const 
 template <typename T>
 hipError_t launch_restrict(const Level &F, const Level &Cl, const T *r, T *fc, hipStream_t st,
                            T *ec) {
+  if (F.g.dim == 3 && tiled_ok(F)) {
+    // the tiles, then the last coarse column / row they leave
+    const RTile rt = restrict_tiles(Cl.g);
+    (void)hipGetLastError();
+    hipLaunchKernelGGL((k_restrict_tile<T>), dim3((rt.ntiles + 7) / 8 * 8), dim3(RNT), 0, st,
+                       F.g, Cl.g, rt, r, fc, ec);
+    const int nrest = ((Cl.g.nx - rt.cxn) * Cl.g.ny + (Cl.g.ny - rt.cyn) * rt.cxn) * Cl.g.nz;
+    if (nrest > 0)
+      hipLaunchKernelGGL((k_restrict_rest<T>), dim3((nrest + kBlock - 1) / kBlock), dim3(kBlock),
+                         0, st, F.g, Cl.g, rt, r, fc, ec, nrest);
+    return hipGetLastError();
+  }
   const int nb = level_grid(Cl.g.nn), bs = level_block(Cl.g.nn);
   if (F.g.dim == 3) SBM_LAUNCH((k_restrict<T, 3>), nb, bs, st, F.g, Cl.g, r, fc, ec);
   SBM_LAUNCH((k_restrict<T, 2>), nb, bs, st, F.g, Cl.g, r, fc, ec);

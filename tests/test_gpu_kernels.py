@@ -175,6 +175,27 @@ def test_transfers(ncell):
     assert rel_max(got, ref) < 1e-14
 
 
+@pytest.mark.parametrize("ncell", [(200, 30, 12), (232, 26, 10), (256, 34, 6), (256, 32, 14)])
+def test_tiled_restriction(ncell):
+    """Full weighting from levels wider than 192 nodes runs as 64 x 4 coarse
+    column tiles over chunks of coarse planes, plus a node-parallel pass over
+    the last coarse column / row a 2^n + 1 level leaves: equal to the
+    oracle's restriction (ragged last tiles, 129 coarse columns, coarse
+    displacement DOF zeroed)."""
+    p, S, psi, mask, u, f = _setup(ncell, seed=31)
+    ncc = S.level_shape(1)
+    maskc, _ = oracle.dirichlet(ncc, p.kind, p.val)
+    say("tiled restriction", ncell)
+    ref = oracle.restrict(p.ncell, f, maskc)
+    got = to_np(S.level_restrict(0, f))
+    assert rel_max(got, ref) < 1e-14
+    assert np.all(got[maskc == 1] == 0.0)
+    # the same numbers on every call (each coarse node is written by one
+    # thread, from LDS planes no other thread writes meanwhile)
+    for _ in range(3):
+        assert np.array_equal(to_np(S.level_restrict(0, f)), got)
+
+
 @pytest.mark.parametrize("ncell", [(16, 16), (24, 12, 12), (8, 8, 8), (35, 33)])
 def test_bottom_cg(ncell):
     """The single-workgroup CG on the bottom grid reaches the dense solution
