@@ -975,9 +975,9 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "measured_triad_GBps": triad["GBps"],
                      "frac_of_measured_triad": achieved / triad["GBps"],
-                     "kernel": ("k_rb_tile<double, CoefCubic<double>, false, false|true> (LDS-tiled "
-                                "finest-level Gauss-Seidel half-sweep; the last of a cycle "
-                                "also sums r.z)" if tiled else
+                     "kernel": ("k_rb_tile<double, CoefCubic<double>, false, false> (LDS-tiled "
+                                "finest-level Gauss-Seidel half-sweep; the cycle's last one, "
+                                "which also sums r.z, is timed apart as smooth_dot)" if tiled else
                                 "k_rb_half<double,3,false> (finest-level Gauss-Seidel half-sweep)"),
                      "algo_bytes_per_launch": by, "avg_launch_us": avg_ms * 1e3,
                      "timing": "HIP events on the solver's stream around each finest-level launch "
