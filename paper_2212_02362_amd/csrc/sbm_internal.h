@@ -111,15 +111,19 @@ hipError_t launch_residual_sweep(const Level &L, const double *u, const double *
 // LDS-tiled 3D half-sweep (same result as launch_rb_half); tiled_ok tells
 // whether a level is large enough for the 64 x 8 node tiles to pay.  With a
 // tile list only those tiles are swept (nodes outside them stay untouched).
-// With partials (FP64, whole level, no classes) the launch also writes the
-// partial sums of f . u_out over free DOF, rb_tiled_partials(L) of them.
+// With partials (whole level, no classes) the launch also writes the partial
+// sums of f . u_out over free DOF, rb_tiled_partials(L, fp32) of them; an
+// FP32 launch then reads the FP64 residual r64 instead of f (its load is
+// fp32(r64 / s), s = sqrt(*ss), as the mixed cast makes it) and sums
+// r64 . (s u_out).
 bool tiled_ok(const Level &L);
 template <typename T>
 hipError_t launch_rb_tiled(const Level &L, const T *psi, const Coef<T> &C, const T *u, const T *f,
                            T *u_out, double omega, int colour, hipStream_t st,
                            const uint8_t *cls = nullptr, const TileList *tl = nullptr,
-                           double *partials = nullptr);
-int rb_tiled_partials(const Level &L);
+                           double *partials = nullptr, const double *r64 = nullptr,
+                           const double *ss = nullptr);
+int rb_tiled_partials(const Level &L, bool fp32);
 // Levels whose first sweep from a zero iterate runs as one launch
 // (launch_rb_fused with u == nullptr).
 bool zero_sweep_ok(const Level &L);

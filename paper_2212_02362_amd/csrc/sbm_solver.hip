@@ -80,6 +80,8 @@ struct sbm_ctx {
   // set while an FP64 CG preconditioner cycle is built: its last finest
   // half-sweep also writes the partials of r . z there
   double *rz_partials = nullptr;
+  // (mixed: the FP64 residual and the squared scale of its FP32 cast)
+  const double *rz_r64 = nullptr, *rz_ss = nullptr;
   double *partials2 = nullptr;
   // live kernel timing (sbm_profile)
   bool prof_on = false;
@@ -450,13 +452,11 @@ static hipError_t smooth(sbm_ctx *c, int l, T *x, const T *f, T *tmp, int nu, bo
     // forms the partials of r . z (r = f) on the way
     double *dot = (l == 0 && !pre && s == nu - 1 && tiled) ? c->rz_partials : nullptr;
     ProfScope ps(c, dot ? SBM_PROF_SMOOTH_DOT : SBM_PROF_SMOOTH, l == 0);
-    if constexpr (sizeof(T) == 8) {
-      if (dot) {
-        if ((e = launch_rb_tiled<T>(L, psi, C, tmp, f, x, om, 1 - c0, c->st, nullptr, nullptr,
-                                    dot)) != hipSuccess)
-          return e;
-        continue;
-      }
+    if (dot) {
+      if ((e = launch_rb_tiled<T>(L, psi, C, tmp, f, x, om, 1 - c0, c->st, nullptr, nullptr, dot,
+                                  c->rz_r64, c->rz_ss)) != hipSuccess)
+        return e;
+      continue;
     }
     if ((e = half(tmp, x, 1 - c0)) != hipSuccess) return e;
   }
@@ -471,13 +471,24 @@ static bool cast_fused(const sbm_ctx *c) {
          c->tail32 != 0 && tiled_ok(c->L[0]);
 }
 
-// Whether the FP64 CG preconditioner's last finest half-sweep forms r . z
-// (Gauss-Seidel post-smoothing of a tiled finest level outside the tail).
+// Whether the CG preconditioner's last finest half-sweep forms r . z
+// (Gauss-Seidel post-smoothing of a tiled finest level outside the tail; in
+// the mixed cycle the FP32 half-sweep reads the FP64 residual for it).
 static bool rz_fused(const sbm_ctx *c) {
   const Level &L0 = c->L[0];
-  return c->opt.precision == 0 && c->opt.smoother == 0 && c->opt.nu_post >= 1 && c->nlev > 1 &&
-         c->tail64 != 0 && c->opt.fused_sweep != 1 && tiled_ok(L0) &&
-         rb_tiled_partials(L0) <= c->npart;
+  const bool fp32 = c->opt.precision == 1;
+  return c->opt.smoother == 0 && c->opt.nu_post >= 1 && c->nlev > 1 &&
+         (fp32 ? c->tail32 : c->tail64) != 0 && c->opt.fused_sweep != 1 && tiled_ok(L0) &&
+         rb_tiled_partials(L0, fp32) <= c->npart;
+}
+
+// Arms (ss: the mixed cast's squared scale; fp64: the FP64 cycle) or
+// disarms the r . z partials of the next preconditioner cycle.
+static void rz_set(sbm_ctx *c, const double *ss, bool fp64 = false) {
+  const bool on = (ss || fp64) && rz_fused(c);
+  c->rz_partials = on ? c->partials : nullptr;
+  c->rz_r64 = on && ss ? c->kr : nullptr;
+  c->rz_ss = on ? ss : nullptr;
 }
 
 static hipError_t bottom64(sbm_ctx *c, const double *f, double *x) {
@@ -603,7 +614,9 @@ static hipError_t cycle_body(sbm_ctx *c, const double *f, int mode) {
     // the mixed preconditioner on an FP32 load the CG update already cast
     // (kr / s, s^2 in scal[7]): the finest level starts from zero
     c->zero_start = true;
+    rz_set(c, c->scal + 7);
     e = vcycle<float>(c, 0, L0.e32, L0.f32, L0.t32);
+    rz_set(c, nullptr);
     c->zero_start = false;
     if (e != hipSuccess) return e;
     return launch_store_sqrt(c->scal + 7, c->scal + 6, c->st);
@@ -629,7 +642,9 @@ static hipError_t cycle_body(sbm_ctx *c, const double *f, int mode) {
         if ((e = launch_cast_scaled(c->kr, L0.f32, nv, c->scal, c->st)) != hipSuccess) return e;
         if ((e = launch_fill<float>(L0.e32, nv, 0.0f, c->st)) != hipSuccess) return e;
       }
+      rz_set(c, c->scal);  // every branch above cast kr with s^2 = scal[0]
       e = vcycle<float>(c, 0, L0.e32, L0.f32, L0.t32);
+      rz_set(c, nullptr);
       c->first_half_done = false;
       c->zero_start = false;
       if (e != hipSuccess) return e;
@@ -646,9 +661,9 @@ static hipError_t cycle_body(sbm_ctx *c, const double *f, int mode) {
     } else if ((e = launch_fill<double>(c->kz, nv, 0.0, c->st)) != hipSuccess) {
       return e;
     }
-    c->rz_partials = rz_fused(c) ? c->partials : nullptr;
+    rz_set(c, nullptr, true);
     e = vcycle<double>(c, 0, c->kz, c->kr, L0.t);
-    c->rz_partials = nullptr;
+    rz_set(c, nullptr);
     c->first_half_done = false;
     c->zero_start = false;
     return e;
@@ -784,7 +799,7 @@ static sbm_status solve_krylov(sbm_ctx *c, const double *f, double fnorm, double
   // r . z from the preconditioner's last half-sweep, else a pass of its own
   const bool rzf = rz_fused(c);
   const bool castf = cast_fused(c);
-  const int nrz = rzf ? rb_tiled_partials(L0) : 0;
+  const int nrz = rzf ? rb_tiled_partials(L0, c->opt.precision == 1) : 0;
   double rho_min = INFINITY, rho = 0.0;
   sbm_status status = SBM_NOT_CONVERGED;
   // the preconditioned residual: kz, or (mixed) scal[6] * the FP32 correction

@@ -10,6 +10,8 @@
 // b mod 8), so neighbouring tiles that share halo rows sit behind the same
 // L2.  Outside the box the halo holds zeros: every term that reaches there
 // carries a zero psi weight, as in the unclamped form of eq. K.
+#include <type_traits>
+
 #include "sbm_internal.h"
 
 namespace sbm {
@@ -299,15 +301,33 @@ __device__ __forceinline__ int tile_or_face(int n) {
   return (b & 7) * (n8 >> 3) + (b >> 3);
 }
 
+// The FP64 residual an FP32 half-sweep with DOT reads instead of its load:
+// the load is r / s (s = sqrt(*ss)) formed as the mixed cast forms it, and the
+// sum is r . (s u_out), the CG's r . z with z = s e.
+struct DotSrc {
+  const double *r, *ss;
+};
+
 // A face node (last column / row of a 2^n + 1 level) of a whole-level tiled
 // half-sweep: one node per thread from global memory, the same update.  With
-// DOT the block's sum of f . u_out over free DOF goes to partials[ntiles + fb].
+// DOT the block's sum of f . u_out over free DOF goes to partials[ntiles + fb]
+// (FP32: r . (s u_out), see DotSrc).
 template <typename T, typename CO, bool MASK, bool DOT>
 __device__ __forceinline__ void rb_face_node(const TG &g, const CO &C, const T *psi,
                                              const T *u, const T *f, T *u_out, T omega,
                                              int colour, const TileGeom &tg,
                                              const uint8_t *cls, int fb, double *partials,
-                                             double *red) {
+                                             double *red, const DotSrc &ds) {
+  constexpr bool R64 = DOT && sizeof(T) == 4;
+  const double sn = R64 ? sqrt(*ds.ss) : 0.0;
+  auto fval = [&](int qq) -> T {
+    if constexpr (R64) {
+      const double r = ds.r[qq];
+      return sn > 0.0 ? (T)(r / sn) : T(0);
+    } else {
+      return f[qq];
+    }
+  };
   int x, y, z;
   double acc = 0.0;
   if (face_node(g, tg, fb * NT + (int)threadIdx.x, x, y, z)) {
@@ -319,7 +339,7 @@ __device__ __forceinline__ void rb_face_node(const TG &g, const CO &C, const T *
       node_stencil<T, 3, true, TG, CO>(g, C, psi, u, x, y, z, out, dg, uc);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const T upd_c = uc[c] + omega * (f[c * nn + q] - out[c]) / dg[c];
+        const T upd_c = uc[c] + omega * (fval(c * nn + q) - out[c]) / dg[c];
         nv[c] = tg_dirichlet(g, x, y, z, c) ? uc[c] : upd_c;
       }
     } else {
@@ -329,7 +349,10 @@ __device__ __forceinline__ void rb_face_node(const TG &g, const CO &C, const T *
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       u_out[c * nn + q] = nv[c];
-      if (DOT && !tg_dirichlet(g, x, y, z, c)) acc += (double)f[c * nn + q] * (double)nv[c];
+      if (DOT && !tg_dirichlet(g, x, y, z, c)) {
+        if constexpr (R64) acc += ds.r[c * nn + q] * (sn * (double)nv[c]);
+        else acc += (double)f[c * nn + q] * (double)nv[c];
+      }
     }
   }
   if constexpr (DOT) {
@@ -351,14 +374,14 @@ template <typename T, typename CO, bool MASK, bool DOT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_rb_tile(
     TG g, CO C, const T *__restrict__ psi, const T *__restrict__ u, const T *__restrict__ f,
     T *__restrict__ u_out, T omega, int colour, TileGeom tg, const uint8_t *__restrict__ cls,
-    const int *__restrict__ ids, int n, double *__restrict__ partials) {
+    const int *__restrict__ ids, int n, double *__restrict__ partials, DotSrc ds) {
   __shared__ T su[3][SLOT_U];
   __shared__ T sp[2][SLOT_P];
   __shared__ double red[DOT ? NT / 64 + 1 : 1];
   const int li = tile_or_face(n);
   if (li < 0) {
     rb_face_node<T, CO, MASK, DOT>(g, C, psi, u, f, u_out, omega, colour, tg, cls, -1 - li,
-                                   partials, red);
+                                   partials, red, ds);
     return;
   }
   if (li >= n) return;
@@ -383,30 +406,46 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
   const int pg = (colour + gy) & 1;  // the updated column of plane k is x0 + 2p + ((pg + k) & 1)
   // f at the updated node of plane k (zeros past the chunk)
   // (with DOT also at the copied node)
-  auto fetch_f = [&](int k, T (&r)[3], T (&rc)[3]) __attribute__((always_inline)) {
+  // (with DOT also at the copied node; an FP32 DOT sweep loads the FP64
+  // residual instead, see DotSrc)
+  constexpr bool R64 = DOT && sizeof(T) == 4;
+  using FT = std::conditional_t<R64, double, T>;
+  const __amdgpu_buffer_rsrc_t rr = make_rsrc(R64 ? (const void *)ds.r : (const void *)f,
+                                              R64 ? 3 * nn * 8 : vbytes);
+  const int fw = R64 ? 8 / W : 1;  // FP64 offsets from FP32 ones
+  const double sn = R64 ? sqrt(*ds.ss) : 0.0;
+  auto fetch_f = [&](int k, FT (&r)[3], FT (&rc)[3]) __attribute__((always_inline)) {
     const bool ok = k < k1;
-    const __amdgpu_buffer_rsrc_t rf = ok ? B.f : B.null;
+    const __amdgpu_buffer_rsrc_t rf = ok ? (R64 ? rr : B.f) : B.null;
     const int vo = ((pg + k) & 1) ? vn1 : vn0;
-    const int so = ok ? k * nxy * W : 0;
+    const int so = ok ? k * nxy * W * fw : 0;
+    const int vof = vo == kOOB ? kOOB : vo * fw;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) r[c] = bload<T>(rf, vo, so + (ok ? c * nn * W : 0));
+    for (int c = 0; c < 3; ++c) r[c] = bload<FT>(rf, vof, so + (ok ? c * nn * W * fw : 0));
     if constexpr (DOT) {
       const int vc = ((pg + k) & 1) ? vn0 : vn1;
+      const int vcf = vc == kOOB ? kOOB : vc * fw;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) rc[c] = bload<T>(rf, vc, so + (ok ? c * nn * W : 0));
+      for (int c = 0; c < 3; ++c) rc[c] = bload<FT>(rf, vcf, so + (ok ? c * nn * W * fw : 0));
     }
   };
-  T FN[3], FC[3];
+  FT FN[3], FC[3];
   fetch_f(k0, FN, FC);
   tile_prologue<T>(g, B, vu, vp, k0, su, sp);
   __syncthreads();
   double acc = 0.0;
   T RU[NUPT], RP[NPCT];
   for (int k = k0; k < k1; ++k) {
-    T fv[3], fc[3];
+    T fv[3];
+    FT fc[3], fr[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      fv[c] = FN[c];
+      if constexpr (R64) {
+        fr[c] = FN[c];
+        fv[c] = sn > 0.0 ? (T)(FN[c] / sn) : T(0);
+      } else {
+        fv[c] = FN[c];
+      }
       if (DOT) fc[c] = FC[c];
     }
     fetch_f(k + 1, FN, FC);
@@ -452,9 +491,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
       const bool fu = fy || gxu == 0 || gxu == g.nx - 1, fcn = fy || gxc == 0 || gxc == g.nx - 1;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        if (!(fu && tg_dirichlet(g, gxu, gy, k, c))) acc += (double)fv[c] * (double)nv[c];
-        if (!(fcn && tg_dirichlet(g, gxc, gy, k, c)))
-          acc += (double)fc[c] * (double)L0[c * PLANE + cc];
+        if constexpr (R64) {
+          if (!(fu && tg_dirichlet(g, gxu, gy, k, c))) acc += fr[c] * (sn * (double)nv[c]);
+          if (!(fcn && tg_dirichlet(g, gxc, gy, k, c)))
+            acc += fc[c] * (sn * (double)L0[c * PLANE + cc]);
+        } else {
+          if (!(fu && tg_dirichlet(g, gxu, gy, k, c))) acc += (double)fv[c] * (double)nv[c];
+          if (!(fcn && tg_dirichlet(g, gxc, gy, k, c)))
+            acc += (double)fc[c] * (double)L0[c * PLANE + cc];
+        }
       }
     }
     __syncthreads();
@@ -1402,7 +1447,8 @@ static int tiled_grid(int n, int nface) { return (n + 7) / 8 * 8 + nface; }
 template <typename T>
 hipError_t launch_rb_tiled(const Level &L, const T *psi, const Coef<T> &C, const T *u, const T *f,
                            T *u_out, double omega, int colour, hipStream_t st,
-                           const uint8_t *cls, const TileList *tl, double *partials) {
+                           const uint8_t *cls, const TileList *tl, double *partials,
+                           const double *r64, const double *ss) {
   const TG gg = make_tg(L.g);
   const TileGeom tg =
       tile_geom(gg, tl == nullptr, tl ? tl->kz : 0, tile_target<T>(TileKind::half));
@@ -1411,35 +1457,39 @@ hipError_t launch_rb_tiled(const Level &L, const T *psi, const Coef<T> &C, const
   CoefCubic<T> cc;
   const bool cubic = cubic_coef(C, cc);
   (void)hipGetLastError();
-  // the f . u_out partials: FP64 whole-level launches only
-  if (partials && (cls || tl || sizeof(T) != 8)) return hipErrorInvalidValue;
+  // the partials: whole-level launches; FP32 ones sum r . (s u_out) from the
+  // FP64 residual r64 and s^2 = *ss
+  if (partials && (cls || tl || (sizeof(T) != 8 && (!r64 || !ss)))) return hipErrorInvalidValue;
+  const DotSrc ds{r64, ss};
   const int nface = tl ? 0 : tg.nface;
   if (n + nface > 0) {
     const dim3 grid(tiled_grid(n, nface)), block(NT);
     if (partials && cubic)
       hipLaunchKernelGGL((k_rb_tile<T, CoefCubic<T>, false, true>), grid, block, 0, st, gg, cc,
-                         psi, u, f, u_out, (T)omega, colour, tg, cls, ids, n, partials);
+                         psi, u, f, u_out, (T)omega, colour, tg, cls, ids, n, partials, ds);
     else if (partials)
       hipLaunchKernelGGL((k_rb_tile<T, Coef<T>, false, true>), grid, block, 0, st, gg, C, psi,
-                         u, f, u_out, (T)omega, colour, tg, cls, ids, n, partials);
+                         u, f, u_out, (T)omega, colour, tg, cls, ids, n, partials, ds);
     else if (cls && cubic)
       hipLaunchKernelGGL((k_rb_tile<T, CoefCubic<T>, true, false>), grid, block, 0, st, gg, cc,
-                         psi, u, f, u_out, (T)omega, colour, tg, cls, ids, n, partials);
+                         psi, u, f, u_out, (T)omega, colour, tg, cls, ids, n, partials, ds);
     else if (cls)
       hipLaunchKernelGGL((k_rb_tile<T, Coef<T>, true, false>), grid, block, 0, st, gg, C, psi,
-                         u, f, u_out, (T)omega, colour, tg, cls, ids, n, partials);
+                         u, f, u_out, (T)omega, colour, tg, cls, ids, n, partials, ds);
     else if (cubic)
       hipLaunchKernelGGL((k_rb_tile<T, CoefCubic<T>, false, false>), grid, block, 0, st, gg, cc,
-                         psi, u, f, u_out, (T)omega, colour, tg, cls, ids, n, partials);
+                         psi, u, f, u_out, (T)omega, colour, tg, cls, ids, n, partials, ds);
     else
       hipLaunchKernelGGL((k_rb_tile<T, Coef<T>, false, false>), grid, block, 0, st, gg, C, psi,
-                         u, f, u_out, (T)omega, colour, tg, cls, ids, n, partials);
+                         u, f, u_out, (T)omega, colour, tg, cls, ids, n, partials, ds);
   }
   return hipGetLastError();
 }
 
-int rb_tiled_partials(const Level &L) {
-  const TileGeom tg = tile_geom(make_tg(L.g), true, 0, tile_target<double>(TileKind::half));
+int rb_tiled_partials(const Level &L, bool fp32) {
+  const TileGeom tg = tile_geom(make_tg(L.g), true, 0,
+                                fp32 ? tile_target<float>(TileKind::half)
+                                     : tile_target<double>(TileKind::half));
   return tg.ntiles + tg.nface;
 }
 
@@ -1542,10 +1592,10 @@ template hipError_t launch_residual_tiled<float>(const Level &, const float *, c
 template hipError_t launch_rb_tiled<double>(const Level &, const double *, const Coef<double> &,
                                             const double *, const double *, double *, double,
                                             int, hipStream_t, const uint8_t *, const TileList *,
-                                            double *);
+                                            double *, const double *, const double *);
 template hipError_t launch_rb_tiled<float>(const Level &, const float *, const Coef<float> &,
                                            const float *, const float *, float *, double, int,
                                            hipStream_t, const uint8_t *, const TileList *,
-                                           double *);
+                                           double *, const double *, const double *);
 
 }  // namespace sbm
