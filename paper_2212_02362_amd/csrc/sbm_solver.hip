@@ -77,10 +77,9 @@ struct sbm_ctx {
   int last_bottom_iters = 0;
   double *x0 = nullptr;  // finest-level iterate (fixed address for captured cycles)
   double *kr = nullptr, *kz = nullptr, *kp = nullptr, *kq = nullptr;  // flexible CG vectors
-  // set while an FP64 CG preconditioner cycle is built: its last finest
-  // half-sweep also writes the partials of r . z there
-  double *rz_partials = nullptr;
-  // (mixed: the FP64 residual and the squared scale of its FP32 cast)
+  // set while a CG preconditioner cycle is built: its last finest half-sweep
+  // also writes the partials of r . z there (mixed: from the FP64 residual
+  // rz_r64, its FP32 cast scaled by sqrt(*rz_ss))
   const double *rz_r64 = nullptr, *rz_ss = nullptr;
   double *partials2 = nullptr;
   // live kernel timing (sbm_profile)

@@ -368,7 +368,8 @@ __device__ __forceinline__ void rb_face_node(const TG &g, const CO &C, const T *
 // colour) and stores both.  The u and psi planes of the next step and f of
 // the next plane are loaded while the current plane is computed.  With DOT
 // (a whole-level launch) each tile also sums f . u_out over its free DOF --
-// r . z of a preconditioned CG whose V-cycle ends with this half-sweep -- into
+// r . z of a preconditioned CG whose V-cycle ends with this half-sweep; in
+// FP32 r . (s u_out) from the FP64 residual, see DotSrc -- into
 // partials[tile], the face blocks into partials[ntiles + face block].
 template <typename T, typename CO, bool MASK, bool DOT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_rb_tile(
