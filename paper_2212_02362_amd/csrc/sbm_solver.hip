@@ -80,6 +80,7 @@ struct sbm_ctx {
   // set while a CG preconditioner cycle is built: its last finest half-sweep
   // also writes the partials of r . z there (mixed: from the FP64 residual
   // rz_r64, its FP32 cast scaled by sqrt(*rz_ss))
+  double *rz_partials = nullptr;
   const double *rz_r64 = nullptr, *rz_ss = nullptr;
   double *partials2 = nullptr;
   // live kernel timing (sbm_profile)
