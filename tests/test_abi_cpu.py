@@ -35,6 +35,18 @@ def test_header_functions_exported(L):
     assert set(names) == set(L.SIGNATURES), set(names) ^ set(L.SIGNATURES)
 
 
+def test_profile_classes_match_header(L):
+    """The binding names one timing class per SBM_PROF_* constant, in the
+    header's order (sbm_profile_read fills SBM_PROF_N entries)."""
+    text = open(HEADER).read()
+    consts = dict((k, int(v)) for k, v in re.findall(r"\b(SBM_PROF_[A-Z0-9_]+)\s*=\s*(\d+)", text))
+    n = consts.pop("SBM_PROF_N")
+    assert len(L.PROF_CLASSES) == n
+    assert sorted(consts.values()) == list(range(n))
+    for k, v in consts.items():
+        assert L.PROF_CLASSES[v] == k[len("SBM_PROF_"):].lower(), (k, L.PROF_CLASSES[v])
+
+
 def test_options_defaults_and_levels(L):
     lib = L.lib()
     o = L.SbmOptions()
