@@ -117,6 +117,9 @@ hipError_t launch_residual_sweep(const Level &L, const double *u, const double *
 // fp32(r64 / s), s = sqrt(*ss), as the mixed cast makes it) and sums
 // r64 . (s u_out).
 bool tiled_ok(const Level &L);
+// Levels whose colour half-sweeps take the tiled kernel (a superset of
+// tiled_ok: the half-sweep pays from smaller levels than the other passes).
+bool tiled_sweep_ok(const Level &L);
 template <typename T>
 hipError_t launch_rb_tiled(const Level &L, const T *psi, const Coef<T> &C, const T *u, const T *f,
                            T *u_out, double omega, int colour, hipStream_t st,

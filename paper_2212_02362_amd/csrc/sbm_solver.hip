@@ -368,7 +368,7 @@ struct Prec<float> {
 template <typename T>
 static hipError_t half_sweep(const Level &L, const T *psi, const Coef<T> &C, const T *src,
                              const T *f, T *dst, double om, int colour, hipStream_t st) {
-  return tiled_ok(L) ? launch_rb_tiled<T>(L, psi, C, src, f, dst, om, colour, st)
+  return tiled_sweep_ok(L) ? launch_rb_tiled<T>(L, psi, C, src, f, dst, om, colour, st)
                      : launch_rb_half<T>(L, psi, C, src, f, dst, om, colour, st);
 }
 
@@ -438,7 +438,7 @@ static hipError_t smooth(sbm_ctx *c, int l, T *x, const T *f, T *tmp, int nu, bo
   // tmp (computed with the convergence test of the previous cycle)
   const bool first_done = l == 0 && c->first_half_done;
   c->first_half_done = false;
-  const bool tiled = tiled_ok(L);
+  const bool tiled = tiled_sweep_ok(L);
   auto half = [&](const T *src, T *dst, int colour) {
     return tiled ? launch_rb_tiled<T>(L, psi, C, src, f, dst, om, colour, c->st)
                  : launch_rb_half<T>(L, psi, C, src, f, dst, om, colour, c->st);
@@ -1504,7 +1504,7 @@ sbm_status sbm_level_smooth(sbm_ctx *c, int l, int colour, double omega, const d
   if (!(omega > 0.0 && omega < 2.0) || colour > 1) return fail(SBM_E_ARG, "bad omega/colour");
   Level &L = c->L[l];
   if (colour < 0) HIP_TRY(launch_jacobi<double>(L, L.psi64, L.c64, u_in, f, u_out, omega, c->st));
-  else if (tiled_ok(L))
+  else if (tiled_sweep_ok(L))
     HIP_TRY(launch_rb_tiled<double>(L, L.psi64, L.c64, u_in, f, u_out, omega, colour, c->st));
   else HIP_TRY(launch_rb_half<double>(L, L.psi64, L.c64, u_in, f, u_out, omega, colour, c->st));
   return SBM_OK;

@@ -1411,10 +1411,19 @@ hipError_t launch_active_tiles(const Level &L, const uint8_t *cls, int *flags, i
 }
 
 bool tiled_ok(const Level &L) {
-  // measured: 1.5x faster than the pair kernel at 257^3 nodes; at 129^3 the
-  // vectors stay in the Infinity Cache and the pair kernel is as fast.  The
-  // buffer offsets of a vector must stay below kOOB.
+  // the residual, Krylov Apply and restriction passes (and the tile lists of
+  // adaptive levels): levels wider than 192 nodes, where they outrun the
+  // node-parallel kernels (the half-sweep 1.5x at 257^3).  The buffer offsets
+  // of a vector must stay below kOOB.
   return L.g.dim == 3 && L.g.nx > 3 * TX && L.g.ny > 3 * TY &&
+         3 * L.g.nn * (int64_t)sizeof(double) < (int64_t)kOOB;
+}
+
+bool tiled_sweep_ok(const Level &L) {
+  // the half-sweep alone: also from 97 nodes (129^3, whose vectors sit in the
+  // Infinity Cache: 41.2 us against 44.6 us for the node-parallel kernel in
+  // FP64, 27.5 us against 36.2 us in FP32)
+  return L.g.dim == 3 && L.g.nx > 96 && L.g.ny > 3 * TY &&
          3 * L.g.nn * (int64_t)sizeof(double) < (int64_t)kOOB;
 }
 

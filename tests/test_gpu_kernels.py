@@ -86,11 +86,13 @@ def test_residual_and_smoothers(ncell):
 
 
 @pytest.mark.parametrize("cubic", [False, True])
-@pytest.mark.parametrize("ncell", [(200, 30, 12), (230, 25, 9), (256, 33, 6), (256, 32, 10)])
+@pytest.mark.parametrize("ncell", [(200, 30, 12), (230, 25, 9), (256, 33, 6), (256, 32, 10),
+                                   (128, 30, 10), (100, 26, 7)])
 def test_tiled_half_sweep(ncell, cubic):
-    """Levels wider than 192 nodes in x take the LDS-tiled half-sweep: several
-    64 x 8 tiles, a ragged last tile in x and y, z chunks; 257 nodes in x (and
-    33 in y) leave the last column (row) to the node-parallel face blocks.
+    """Levels wider than 96 nodes in x take the LDS-tiled half-sweep: several
+    64 x 8 tiles, a ragged last tile in x and y, z chunks; 257 and 129 nodes in
+    x (and 33 in y) leave the last column (row) to the node-parallel face
+    blocks.
     Cubic cells take the kernels' 4-coefficient form."""
     p, S, psi, mask, u, f = _setup(ncell, seed=11, cubic=cubic)
     u = np.where(mask == 1, oracle.dirichlet(p.ncell, p.kind, p.val)[1], u)
