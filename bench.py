@@ -317,7 +317,8 @@ def _bench_j2(args):
                    "yielding_cells": npl, "applied_displacement": state["d"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_rb_half<double,3,false> (finest-level Gauss-Seidel half-sweep)",
+                     "kernel": "k_rb_tile<double, ..., false, false> (LDS-tiled finest-level "
+                               "Gauss-Seidel half-sweep; 129 nodes in x)",
                      "algo_bytes_per_launch": by, "avg_launch_us": avg_ms * 1e3,
                      "timing": "HIP events around each finest-level launch, one profiled solve "
                                "after the timed steps"},
@@ -587,7 +588,8 @@ def _bench_pressure(args):
                    "final_rel_residual": max(fin), "status": sts},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_rb_half<double,3,false> (finest-level Gauss-Seidel half-sweep)",
+                     "kernel": "k_rb_tile<double, ..., false, false> (LDS-tiled finest-level "
+                               "Gauss-Seidel half-sweep; 129 nodes in x)",
                      "algo_bytes_per_launch": by, "avg_launch_us": avg_ms * 1e3,
                      "timing": "HIP events around each finest-level launch, one profiled solve "
                                "after the timed steps"},
@@ -951,8 +953,11 @@ def main():
     avg_ms = ms_s / max(n_s, 1)
     by = ALGO_BYTES["smooth"][0] * nodes
     achieved = by / (avg_ms * 1e-3) / 1e9
+    # the library's thresholds: half-sweeps go tiled from 97 nodes in x, the
+    # other finest-level passes (and the fused r.z) from 193
     tiled = p.ncell[0] + 1 > 192 and p.dim == 3
-    traffic = _traffic("k_rb_tile<double,false>" if tiled else TRAFFIC_KERNEL, nodes)
+    tiled_sweep = p.ncell[0] + 1 > 96 and p.dim == 3
+    traffic = _traffic("k_rb_tile<double,false>" if tiled_sweep else TRAFFIC_KERNEL, nodes)
     line = {
         "metric": METRIC,
         "value": free / t64,
@@ -975,9 +980,11 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "measured_triad_GBps": triad["GBps"],
                      "frac_of_measured_triad": achieved / triad["GBps"],
-                     "kernel": ("k_rb_tile<double, CoefCubic<double>, false, false> (LDS-tiled "
-                                "finest-level Gauss-Seidel half-sweep; the cycle's last one, "
-                                "which also sums r.z, is timed apart as smooth_dot)" if tiled else
+                     "kernel": (("k_rb_tile<double, CoefCubic<double>, false, false> (LDS-tiled "
+                                 "finest-level Gauss-Seidel half-sweep" +
+                                 ("; the cycle's last one, which also sums r.z, is timed apart as "
+                                  "smooth_dot)" if tiled and head != "fp64" else ")"))
+                                if tiled_sweep else
                                 "k_rb_half<double,3,false> (finest-level Gauss-Seidel half-sweep)"),
                      "algo_bytes_per_launch": by, "avg_launch_us": avg_ms * 1e3,
                      "timing": "HIP events on the solver's stream around each finest-level launch "
