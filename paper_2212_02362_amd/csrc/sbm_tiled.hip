@@ -405,10 +405,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
   const int vn0 = (gy < g.ny && x0 + 2 * p < g.nx) ? (gy * g.nx + x0 + 2 * p) * W : kOOB;
   const int vn1 = (gy < g.ny && x0 + 2 * p + 1 < g.nx) ? (gy * g.nx + x0 + 2 * p + 1) * W : kOOB;
   const int pg = (colour + gy) & 1;  // the updated column of plane k is x0 + 2p + ((pg + k) & 1)
-  // f at the updated node of plane k (zeros past the chunk)
-  // (with DOT also at the copied node)
-  // (with DOT also at the copied node; an FP32 DOT sweep loads the FP64
-  // residual instead, see DotSrc)
+  // f at the updated node of plane k (zeros past the chunk; with DOT also at
+  // the copied node; an FP32 DOT sweep loads the FP64 residual instead, see
+  // DotSrc)
   constexpr bool R64 = DOT && sizeof(T) == 4;
   using FT = std::conditional_t<R64, double, T>;
   const __amdgpu_buffer_rsrc_t rr = make_rsrc(R64 ? (const void *)ds.r : (const void *)f,
@@ -430,13 +429,25 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
       for (int c = 0; c < 3; ++c) rc[c] = bload<FT>(rf, vcf, so + (ok ? c * nn * W * fw : 0));
     }
   };
+  // MASK: the class of the updated node of plane k, loaded a plane ahead too
+  auto fetch_cls = [&](int k) __attribute__((always_inline)) -> int {
+    if constexpr (MASK) {
+      const int gx = x0 + 2 * p + ((pg + k) & 1);
+      return (k < k1 && gy < g.ny && gx < g.nx) ? (int)cls[k * nxy + gy * g.nx + gx] : 0;
+    } else {
+      return 0;
+    }
+  };
   FT FN[3], FC[3];
   fetch_f(k0, FN, FC);
+  int CLN = fetch_cls(k0);
   tile_prologue<T>(g, B, vu, vp, k0, su, sp);
   __syncthreads();
   double acc = 0.0;
   T RU[NUPT], RP[NPCT];
   for (int k = k0; k < k1; ++k) {
+    const int clk = CLN;
+    CLN = fetch_cls(k + 1);
     T fv[3];
     FT fc[3], fr[3];
 #pragma unroll
@@ -462,7 +473,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     const int so = k * nxy * W;
     T nv[3];
     bool upd = gy < g.ny && gxu < g.nx;
-    if (MASK && upd) upd = cls[k * nxy + gy * g.nx + gxu] == 1;
+    if (MASK && upd) upd = clk == 1;
     if (upd) {
       T out[3], dg[3];
       tile_stencil<T>(C, Lm, L0, L1, Pm, P0, lx, yl, out, dg);
@@ -600,8 +611,21 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
 #pragma unroll
       for (int c = 0; c < 3; ++c) fr[h][c] = bload<T>(rf, vn[h], so + (ok ? c * nn * W : 0));
   };
+  // MASK: the classes of both nodes of plane k, loaded a plane ahead too
+  auto fetch_cls = [&](int k, int (&cl)[2]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      cl[h] = 0;
+      if constexpr (MASK) {
+        const int gx = gx0 + h;
+        if (k < k1 && gy < g.ny && gx < g.nx) cl[h] = cls[k * nxy + gy * g.nx + gx];
+      }
+    }
+  };
   T FN[2][3];
   fetch_f(k0, FN);
+  int CLN[2];
+  fetch_cls(k0, CLN);
   tile_prologue<T>(g, B, vu, vp, k0, su, sp);
   __syncthreads();
   double acc = 0.0;
@@ -613,6 +637,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
 #pragma unroll
       for (int c = 0; c < 3; ++c) fv[h][c] = FN[h][c];
     fetch_f(k + 1, FN);
+    const int clk[2] = {CLN[0], CLN[1]};
+    fetch_cls(k + 1, CLN);
     tile_fetch_u<T>(g, B, vu, k + 2, RU);
     tile_fetch_p<T>(g, B, vp, k + 1, RP);
     const T *Lm = su[(k + 2) % 3], *L0 = su[k % 3], *L1 = su[(k + 1) % 3];
@@ -624,7 +650,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
       T v[3] = {T(0), T(0), T(0)};
       bool live = gy < g.ny && gx < g.nx;
       if (MASK && live) {
-        const uint8_t cl = cls[k * nxy + gy * g.nx + gx];
+        const int cl = clk[h];
         live = cl != 0 && cl <= 3;
       }
       if (live) {
