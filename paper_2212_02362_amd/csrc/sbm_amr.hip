@@ -1055,12 +1055,17 @@ static hipError_t amr_smooth(sbm_amr_ctx *c, int a, T *x, const T *f, T *tmp, in
     if (src != x) e = launch_copy<T>(src, x, l.nv(), c->st);
     return e;
   }
+  // levels with tile lists sweep their listed tiles; a smaller level whose
+  // half-sweep still pays tiled (from 97 nodes) sweeps all its tiles, the
+  // class mask applied, as the node-parallel kernel does
   const bool tiled = tiled_ok(l.L);
+  const bool whole = !tiled && tiled_sweep_ok(l.L);
   auto half = [&](const T *src, T *dst, int colour) {
-    return tiled ? launch_rb_tiled<T>(l.L, AV<T>::psi(l), AV<T>::coef(l), src, f, dst, om, colour,
-                                      c->st, l.cls, l.tiles())
-                 : launch_rb_half<T>(l.L, AV<T>::psi(l), AV<T>::coef(l), src, f, dst, om, colour,
-                                     c->st, l.cls);
+    if (tiled || whole)
+      return launch_rb_tiled<T>(l.L, AV<T>::psi(l), AV<T>::coef(l), src, f, dst, om, colour, c->st,
+                                l.cls, tiled ? l.tiles() : nullptr);
+    return launch_rb_half<T>(l.L, AV<T>::psi(l), AV<T>::coef(l), src, f, dst, om, colour, c->st,
+                             l.cls);
   };
   for (int s = 0; s < nu; ++s) {
     {
