@@ -163,7 +163,7 @@ def _bench_amr(args):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_rb_tile<double, CoefCubic<double>, true, false> (LDS-tiled class-masked half-sweep) over the "
-                               "tiles of the finest adaptive level that hold active blocks",
+                               "tiles of the finest adaptive level that hold unknowns",
                      "algo_bytes_per_launch": by, "avg_launch_us": avg_ms * 1e3,
                      "timing": "HIP events around each finest-level launch, one profiled solve "
                                "after the timed region"},

@@ -47,6 +47,9 @@ using namespace sbm;
 namespace {
 
 constexpr int kMaxAmrLevels = 4;  // base + up to 3 refined levels
+// device ints of the set-up: [0] error flags, [8 + a] active tiles, [12 + a]
+// ghost nodes, [16 + a] tiles with unknowns of level a
+constexpr int kIflags = 24;
 // Tile lists of sparsely refined levels: shallowest chunk depth, and the
 // number of workgroups the listed tiles should give (a few per CU).
 constexpr int kAmrKzMin = 6;
@@ -315,6 +318,18 @@ __global__ __launch_bounds__(kBlock) void k_amr_ghost_list(Geom gf, Geom gc,
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (t >= n) return;
   ghost_node<T, DIM>(gf, gc, xc, xf, ids[t]);
+}
+
+// dst = src on the listed ghost nodes (all components).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_amr_ghost_copy(int64_t nn, int dim,
+                                                           const int *__restrict__ ids, int n,
+                                                           const T *__restrict__ src,
+                                                           T *__restrict__ dst) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= n) return;
+  const int64_t id = ids[t];
+  for (int c = 0; c < dim; ++c) dst[c * nn + id] = src[c * nn + id];
 }
 
 // Ghost-node list of a level (ids of the nodes of class >= 2, increasing), by
@@ -608,6 +623,14 @@ hipError_t launch_ghost_list(const Level &F, const Level &C, const GhostList &gl
   AMR_LAUNCH((k_amr_ghost_list<T, 2>), nb, kBlock, st, F.g, C.g, gl.ids, gl.count, xc, xf);
 }
 
+template <typename T>
+hipError_t launch_ghost_copy(const Level &L, const GhostList &gl, const T *src, T *dst,
+                             hipStream_t st) {
+  if (gl.count == 0) return hipSuccess;
+  const int nb = (gl.count + kBlock - 1) / kBlock;
+  AMR_LAUNCH((k_amr_ghost_copy<T>), nb, kBlock, st, L.g.nn, L.g.dim, gl.ids, gl.count, src, dst);
+}
+
 hipError_t launch_ghost_listing(const Level &F, const uint8_t *cls, int *bcnt, int *boff, int *ids,
                                 int *total, hipStream_t st) {
   const int64_t nb = (F.g.nn + kCompactNodes - 1) / kCompactNodes;
@@ -713,11 +736,16 @@ struct AmrLevel {
   float *e32 = nullptr, *f32 = nullptr, *w32 = nullptr, *xinj32 = nullptr, *tmp32 = nullptr;
   float *g32 = nullptr;    // FP32 cycle: R of the finer level's ghost-row loads (a < A)
   int *tflags = nullptr, *tids = nullptr;  // active column tiles (tiled levels a >= 1)
+  int *tids1 = nullptr;    // the tiles of them that hold unknowns (class 1)
   int *gids = nullptr, *gcnt = nullptr, *goff = nullptr;  // ghost-node list and its scratch
   GhostList gl;            // the level's ghost nodes (a >= 1; count 0 until set_problem)
   TileList tl;             // the level's active tiles (count 0 until set_problem)
+  TileList tl1;            // its tiles with unknowns, in the same chunks
   bool tiled = false;      // the level sweeps only its active tiles
   const TileList *tiles() const { return tiled ? &tl : nullptr; }
+  // for the passes that touch class-1 nodes only: smoothing, correction,
+  // update, norm (the ghost rows of the residual and the loads need tl)
+  const TileList *unknown_tiles() const { return tiled ? &tl1 : nullptr; }
   int part_off = 0;        // offset of this level's partial sums
   Traction tr{};
   int64_t nblocks() const { return (int64_t)nb[0] * nb[1] * nb[2]; }
@@ -971,6 +999,7 @@ static size_t amr_carve(sbm_amr_ctx *c, char *base) {
         const int nt = std::max(tile_geom_of(l.L).ntiles, tile_geom_of(l.L, kAmrKzMin).ntiles);
         l.tflags = cv.take<int>(nt);
         l.tids = cv.take<int>(nt);
+        l.tids1 = cv.take<int>(nt);
       }
     }
     if (a < A) l.tags = cv.take<uint8_t>(l.L.g.nc);
@@ -994,7 +1023,7 @@ static size_t amr_carve(sbm_amr_ctx *c, char *base) {
   c->npart = npart;
   c->partials = cv.take<double>(npart);
   c->scal = cv.take<double>(16);
-  c->iflag = cv.take<int>(16);
+  c->iflag = cv.take<int>(kIflags);
   cv.off = (cv.off + 255) & ~(size_t)255;
   return cv.off;
 }
@@ -1058,12 +1087,15 @@ static hipError_t amr_smooth(sbm_amr_ctx *c, int a, T *x, const T *f, T *tmp, in
   // levels with tile lists sweep their listed tiles; a smaller level whose
   // half-sweep still pays tiled (from 97 nodes) sweeps all its tiles, the
   // class mask applied, as the node-parallel kernel does
-  const bool tiled = tiled_ok(l.L);
+  const bool tiled = l.tiled;
   const bool whole = !tiled && tiled_sweep_ok(l.L);
+  // The listed tiles cover the unknowns, not every ghost node their stencils
+  // read: the second half-sweep reads those from tmp, so tmp gets x's ghosts.
+  if (tiled && (e = launch_ghost_copy<T>(l.L, l.gl, x, tmp, c->st)) != hipSuccess) return e;
   auto half = [&](const T *src, T *dst, int colour) {
     if (tiled || whole)
       return launch_rb_tiled<T>(l.L, AV<T>::psi(l), AV<T>::coef(l), src, f, dst, om, colour, c->st,
-                                l.cls, tiled ? l.tiles() : nullptr);
+                                l.cls, l.unknown_tiles());
     return launch_rb_half<T>(l.L, AV<T>::psi(l), AV<T>::coef(l), src, f, dst, om, colour, c->st,
                              l.cls);
   };
@@ -1119,7 +1151,8 @@ static hipError_t amr_fas(sbm_amr_ctx *c, int a) {
   if ((e = amr_fas<T>(c, a - 1)) != hipSuccess) return e;
   {
     AmrProf pr(c, SBM_PROF_PROLONG, fin);
-    if ((e = launch_amr_correct<T>(F.L, C.L, F.cls, xc, xi, xf, c->st, F.tiles())) != hipSuccess)
+    if ((e = launch_amr_correct<T>(F.L, C.L, F.cls, xc, xi, xf, c->st, F.unknown_tiles())) !=
+        hipSuccess)
       return e;
   }
   {
@@ -1150,7 +1183,7 @@ static sbm_status amr_comp_residual(sbm_amr_ctx *c, double *const *x, double *co
     AmrLevel &l = c->lv[a];
     AMR_HIP(launch_sumsq(l.L, a >= 1 ? l.cls : nullptr, a < A ? &c->lv[a + 1].L : nullptr,
                          a < A ? c->lv[a + 1].cls : nullptr, r[a], c->partials + l.part_off,
-                         c->st, a >= 1 ? l.tiles() : nullptr));
+                         c->st, a >= 1 ? l.unknown_tiles() : nullptr));
   }
   AMR_HIP(launch_finalize_sum(c->partials, c->npart, c->scal, c->st));
   if (sync) {
@@ -1345,7 +1378,7 @@ sbm_status sbm_amr_set_problem(sbm_amr_ctx *c, const double *const *psi_raw,
     }
   c->have_problem = false;
   c->mat = *mat;
-  AMR_HIP(launch_fill<int>(c->iflag, 16, 0, c->st));
+  AMR_HIP(launch_fill<int>(c->iflag, kIflags, 0, c->st));
   for (int a = 0; a <= A; ++a) {
     AmrLevel &l = c->lv[a];
     l.L.g.dmask = dmask;
@@ -1436,9 +1469,9 @@ sbm_status sbm_amr_set_problem(sbm_amr_ctx *c, const double *const *psi_raw,
     AMR_HIP(launch_rhs(l.L, l.tr, nullptr, l.fP, c->iflag, c->st));
     AMR_HIP(launch_check_diag(l.L, c->iflag, c->st));
   }
-  AMR_HIP(hipMemcpyAsync(c->host, c->iflag, 16 * sizeof(int), hipMemcpyDeviceToHost, c->st));
+  AMR_HIP(hipMemcpyAsync(c->host, c->iflag, kIflags * sizeof(int), hipMemcpyDeviceToHost, c->st));
   AMR_HIP(hipStreamSynchronize(c->st));
-  int flags = 0, iv[16];
+  int flags = 0, iv[kIflags];
   memcpy(iv, c->host, sizeof(iv));
   flags = iv[0];
   for (int a = 1; a <= A; ++a) {
@@ -1449,7 +1482,6 @@ sbm_status sbm_amr_set_problem(sbm_amr_ctx *c, const double *const *psi_raw,
   // default tile count) lists them again in shallower chunks, so that the
   // tiled kernels run about kAmrTiles workgroups: each chunk then re-reads
   // two more planes per kz, but the CUs are no longer half idle.
-  bool relisted = false;
   for (int a = 1; a <= A; ++a) {
     AmrLevel &l = c->lv[a];
     if (!l.tiled || l.tl.count == 0) continue;
@@ -1461,14 +1493,29 @@ sbm_status sbm_amr_set_problem(sbm_amr_ctx *c, const double *const *psi_raw,
     l.tl.kz = kz;
     AMR_HIP(launch_fill<int>(c->iflag + 8 + a, 1, 0, c->st));
     AMR_HIP(launch_active_tiles(l.L, l.cls, l.tflags, l.tids, c->iflag + 8 + a, c->st, kz));
-    relisted = true;
   }
-  if (relisted) {
-    AMR_HIP(hipMemcpyAsync(c->host, c->iflag, 16 * sizeof(int), hipMemcpyDeviceToHost, c->st));
+  // The smoother relaxes class-1 nodes only, so it sweeps the tiles that hold
+  // them (in the 64^3 x 3 voids workload 1.3x the unknowns against 2.4x for
+  // all active tiles: a block's ghost faces lie in the next tile); the same
+  // chunks, so their partial sums stay within the level's share.
+  bool listed = false;
+  for (int a = 1; a <= A; ++a) {
+    AmrLevel &l = c->lv[a];
+    l.tl1 = TileList{l.tids1, 0, l.tl.kz};
+    if (!l.tiled) continue;
+    AMR_HIP(launch_active_tiles(l.L, l.cls, l.tflags, l.tids1, c->iflag + 16 + a, c->st, l.tl.kz,
+                                true));
+    listed = true;
+  }
+  if (listed) {
+    AMR_HIP(hipMemcpyAsync(c->host, c->iflag, kIflags * sizeof(int), hipMemcpyDeviceToHost, c->st));
     AMR_HIP(hipStreamSynchronize(c->st));
     memcpy(iv, c->host, sizeof(iv));
     for (int a = 1; a <= A; ++a)
-      if (c->lv[a].tiled) c->lv[a].tl.count = iv[8 + a];
+      if (c->lv[a].tiled) {
+        c->lv[a].tl.count = iv[8 + a];
+        c->lv[a].tl1.count = iv[16 + a];
+      }
   }
   // tiled levels write partial sums for their listed tiles only
   AMR_HIP(launch_fill<double>(c->partials, c->npart, 0.0, c->st));
@@ -1494,7 +1541,7 @@ sbm_status sbm_amr_set_problem(sbm_amr_ctx *c, const double *const *psi_raw,
     AmrLevel &l = c->lv[a];
     AMR_HIP(launch_sumsq(l.L, a >= 1 ? l.cls : nullptr, a < A ? &c->lv[a + 1].L : nullptr,
                          a < A ? c->lv[a + 1].cls : nullptr, nullptr, c->partials + l.part_off,
-                         c->st, a >= 1 ? l.tiles() : nullptr));
+                         c->st, a >= 1 ? l.unknown_tiles() : nullptr));
   }
   AMR_HIP(launch_finalize_sum(c->partials, c->npart, c->scal, c->st));
   AMR_HIP(hipMemcpyAsync(c->host, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->st));
@@ -1628,14 +1675,14 @@ sbm_status sbm_amr_solve(sbm_amr_ctx *c, double *const *u, double *hist_host, in
       for (int a = 0; a <= A; ++a)
         AMR_HIP(launch_update<float>(c->lv[a].L, a >= 1 ? c->lv[a].cls : nullptr, u[a],
                                      c->lv[a].e32, c->scal, c->st,
-                                     a >= 1 ? c->lv[a].tiles() : nullptr));
+                                     a >= 1 ? c->lv[a].unknown_tiles() : nullptr));
     } else {
       for (int a = 0; a <= A; ++a) AMR_HIP(launch_fill<double>(c->lv[a].e, c->lv[a].nv(), 0.0, c->st));
       AMR_HIP(amr_fas<double>(c, A));
       for (int a = 0; a <= A; ++a)
         AMR_HIP(launch_update<double>(c->lv[a].L, a >= 1 ? c->lv[a].cls : nullptr, u[a],
                                       c->lv[a].e, nullptr, c->st,
-                                      a >= 1 ? c->lv[a].tiles() : nullptr));
+                                      a >= 1 ? c->lv[a].unknown_tiles() : nullptr));
     }
     AMR_TRY(amr_inject_all(c, u));
   }

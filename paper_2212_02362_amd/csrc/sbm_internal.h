@@ -95,10 +95,10 @@ template <typename T>
 hipError_t launch_rb_half(const Level &L, const T *psi, const Coef<T> &C, const T *u,
                           const T *f, T *u_out, double omega, int colour, hipStream_t st,
                           const uint8_t *cls = nullptr);
-// Tiles of level L holding a node of class >= 1: flags[ntiles] scratch,
-// ids[ntiles] and *count (device) out.
+// Tiles of level L holding a node of class >= 1 (unknowns: of class 1):
+// flags[ntiles] scratch, ids[ntiles] and *count (device) out.
 hipError_t launch_active_tiles(const Level &L, const uint8_t *cls, int *flags, int *ids,
-                               int *count, hipStream_t st, int kz = 0);
+                               int *count, hipStream_t st, int kz = 0, bool unknowns = false);
 
 // Residual-norm partials of u (as launch_residual with partials, counted by
 // stencil_partials) together with the colour half-sweep of u into u_out (same

@@ -683,9 +683,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
   }
 }
 
-// Tiles holding any node of class >= 1 (one workgroup per tile).
+// Tiles holding any node of class 1 .. cmax (one workgroup per tile).
 __global__ __launch_bounds__(256) void k_tile_flags(TG g, TileGeom tg,
-                                                    const uint8_t *__restrict__ cls,
+                                                    const uint8_t *__restrict__ cls, int cmax,
                                                     int *__restrict__ flags) {
   const int t = blockIdx.x;
   const int tx = t % tg.ntx, rest = t / tg.ntx, ty = rest % tg.nty, tz = rest / tg.nty;
@@ -696,7 +696,10 @@ __global__ __launch_bounds__(256) void k_tile_flags(TG g, TileGeom tg,
   const int n = TX * TY * (k1 - k0);
   for (int e = threadIdx.x; e < n; e += blockDim.x) {
     const int x = x0 + e % TX, y = y0 + (e / TX) % TY, k = k0 + e / (TX * TY);
-    if (x < g.nx && y < g.ny && cls[x + g.nx * (y + g.ny * k)] >= 1) any = 1;
+    if (x < g.nx && y < g.ny) {
+      const int cl = cls[x + g.nx * (y + g.ny * k)];
+      if (cl >= 1 && cl <= cmax) any = 1;
+    }
   }
   any = __syncthreads_or(any);
   if (threadIdx.x == 0) flags[t] = any;
@@ -1426,11 +1429,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_
 }  // namespace
 
 hipError_t launch_active_tiles(const Level &L, const uint8_t *cls, int *flags, int *ids,
-                               int *count, hipStream_t st, int kz) {
+                               int *count, hipStream_t st, int kz, bool unknowns) {
   const TG gg = make_tg(L.g);
   const TileGeom tg = tile_geom(gg, false, kz);
   (void)hipGetLastError();
-  hipLaunchKernelGGL(k_tile_flags, dim3(tg.ntiles), dim3(256), 0, st, gg, tg, cls, flags);
+  hipLaunchKernelGGL(k_tile_flags, dim3(tg.ntiles), dim3(256), 0, st, gg, tg, cls,
+                     unknowns ? 1 : 255, flags);
   hipLaunchKernelGGL(k_tile_compact, dim3(1), dim3(1024), 0, st, (const int *)flags, tg.ntiles,
                      ids, count);
   return hipGetLastError();

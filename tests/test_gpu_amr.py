@@ -10,9 +10,11 @@ count m* (the first cycle at a 1e-10 relative composite residual), every
 residual of the history agrees to 1e-6 relative plus 1e-13 absolute (the
 rounding floor of the residual evaluation) and the displacement to 1e-9
 relative L2 on every level; the mixed solve reaches the same residual and
-agrees to 1e-8.  The "wide3d" case has a finest level 225 nodes wide and 33
-deep, so its finest-level kernels run the LDS-tiled path over the list of
-tiles that hold active nodes (the path of the 64^3 x 3 workload)."""
+agrees to 1e-8.  The "wide3d" cases have a finest level 225 nodes wide and 33
+deep, so its finest-level kernels run the LDS-tiled path over the lists of
+tiles that hold active nodes (residual) and unknowns (smoothing, correction,
+update, norm), the path of the 64^3 x 3 workload; in "wide3d_sparse" some
+ghost faces lie in tiles without unknowns, which the smoother never sweeps."""
 import numpy as np
 import pytest
 import torch
@@ -47,6 +49,15 @@ def _case(name):
         # cells (225 x 33 x 17 nodes), wide enough for the tiled kernels
         p, psis = si.ellipsoidal_voids_amr(base=64, levels=2, block=8, seed=3, shape=(112, 16, 8))
         return p, psis, 8, None
+    if name == "wide3d_sparse":
+        # the same level with a few blocks: the block at cells x 56..64,
+        # y 0..8 has its ghost faces x = 64 and y = 8 in the next tiles
+        # (64 x 8 node columns), which hold no unknowns
+        p, psis = si.ellipsoidal_voids_amr(base=64, levels=2, block=8, seed=3, shape=(112, 16, 8))
+        b1 = np.zeros((2, 4, 28), np.uint8)
+        b1[:, 0, 7] = 1
+        b1[1, 2:4, 20:22] = 1
+        return p, psis, 8, [b1]
     raise KeyError(name)
 
 
@@ -75,7 +86,7 @@ def _gpu(name, **opts):
     return S
 
 
-CASES = ["voids3d", "voids3d_partial", "plate2d", "wide3d"]
+CASES = ["voids3d", "voids3d_partial", "plate2d", "wide3d", "wide3d_sparse"]
 RHO_ATOL = 1e-13  # rounding floor of the composite residual evaluation
 
 
@@ -166,15 +177,24 @@ def test_solve_parity_fp64(name):
     assert nrm <= 1.01e-10 * S.stats()[1]
 
 
-def test_wide_case_takes_the_tiled_path():
-    """The wide case's finest level passes the tiled kernels' size test
-    (more than 192 nodes in x, more than 24 in y) and has inactive tiles."""
-    p, psis, block, _ = _case("wide3d")
+@pytest.mark.parametrize("name", ["wide3d", "wide3d_sparse"])
+def test_wide_case_takes_the_tiled_path(name):
+    """The wide cases' finest level passes the tiled kernels' size test
+    (more than 192 nodes in x, more than 24 in y) and has inactive tiles; the
+    sparse one has 64 x 8 node columns with ghost nodes and no unknown, so
+    whatever its z chunks, the smoother's tile list leaves ghosts out."""
+    p, psis, block, _ = _case(name)
     nz, ny, nx = psis[-1].shape
     assert nx + 1 > 192 and ny + 1 > 24
-    m = _oracle("wide3d")
+    m = _oracle(name)
     blk, cls, _ = m.info(1)
     assert 0 < blk.mean() < 1, blk.mean()
+    ghost_only = 0
+    for y0 in range(0, cls.shape[1], 8):
+        for x0 in range(0, cls.shape[2], 64):
+            col = cls[:, y0:y0 + 8, x0:x0 + 64]
+            ghost_only += int((col >= 2).any() and not (col == 1).any())
+    assert (ghost_only > 0) == (name == "wide3d_sparse"), ghost_only
 
 
 def test_solve_parity_jacobi_trajectory():
@@ -191,7 +211,7 @@ def test_solve_parity_jacobi_trajectory():
         assert rel_l2(to_np(u_g[a]), u_o[a]) < 1e-11, a
 
 
-@pytest.mark.parametrize("name", ["voids3d", "plate2d"])
+@pytest.mark.parametrize("name", ["voids3d", "plate2d", "wide3d_sparse"])
 def test_solve_mixed(name):
     u_o, h_o, _ = _oracle_solution(name)
     S = _gpu(name, precision=1)
