@@ -48,7 +48,8 @@ namespace {
 
 constexpr int kMaxAmrLevels = 4;  // base + up to 3 refined levels
 // device ints of the set-up: [0] error flags, [8 + a] active tiles, [12 + a]
-// ghost nodes, [16 + a] tiles with unknowns of level a
+// ghost nodes, [16 + a] tiles with unknowns, [20 + a] ghost nodes outside
+// them, of level a
 constexpr int kIflags = 24;
 // Tile lists of sparsely refined levels: shallowest chunk depth, and the
 // number of workgroups the listed tiles should give (a few per CU).
@@ -330,6 +331,50 @@ __global__ __launch_bounds__(kBlock) void k_amr_ghost_copy(int64_t nn, int dim,
   if (t >= n) return;
   const int64_t id = ids[t];
   for (int c = 0; c < dim; ++c) dst[c * nn + id] = src[c * nn + id];
+}
+
+// The listed ghost nodes that lie in no flagged tile (tflags: the flags of a
+// tile list of geometry tg), appended to out in any order.
+__global__ __launch_bounds__(kBlock) void k_ghost_outside(Geom g, TileGeom tg,
+                                                          const int *__restrict__ tflags,
+                                                          const int *__restrict__ ids, int n,
+                                                          int *__restrict__ out,
+                                                          int *__restrict__ count) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= n) return;
+  const int id = ids[t];
+  int i, j, k;
+  node_ijk(g, id, i, j, k);
+  if (tflags[i / kTileX + tg.ntx * (j / kTileY + tg.nty * (k / tg.kz))]) return;
+  out[atomicAdd(count, 1)] = id;
+}
+
+// r = f - K u at the listed nodes of a level with classes (a padded residual
+// as k_residual with a class mask: classes 2-3 carry one, class 4 gets 0).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_residual_list(Geom g, Coef<T> C,
+                                                          const T *__restrict__ psi,
+                                                          const T *__restrict__ u,
+                                                          const T *__restrict__ f,
+                                                          T *__restrict__ r,
+                                                          const uint8_t *__restrict__ cls,
+                                                          const int *__restrict__ ids, int n) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= n) return;
+  const int64_t id = ids[t];
+  if (cls[id] == 0 || cls[id] > 3) {
+    for (int c = 0; c < 3; ++c) r[c * g.nn + id] = T(0);
+    return;
+  }
+  int i, j, k;
+  node_ijk(g, id, i, j, k);
+  T fv[3], out[3], dg[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) fv[c] = f[c * g.nn + id];
+  node_stencil<T, 3>(g, C, psi, u, i, j, k, out, dg);
+  const uint32_t fb = face_bits(g, i, j, k);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) r[c * g.nn + id] = ((g.dmask >> c) & fb) ? T(0) : fv[c] - out[c];
 }
 
 // Ghost-node list of a level (ids of the nodes of class >= 2, increasing), by
@@ -631,6 +676,22 @@ hipError_t launch_ghost_copy(const Level &L, const GhostList &gl, const T *src, 
   AMR_LAUNCH((k_amr_ghost_copy<T>), nb, kBlock, st, L.g.nn, L.g.dim, gl.ids, gl.count, src, dst);
 }
 
+hipError_t launch_ghost_outside(const Level &L, const TileGeom &tg, const int *tflags,
+                                const GhostList &gl, int *out, int *count, hipStream_t st) {
+  if (gl.count == 0) return hipSuccess;
+  const int nb = (gl.count + kBlock - 1) / kBlock;
+  AMR_LAUNCH(k_ghost_outside, nb, kBlock, st, L.g, tg, tflags, gl.ids, gl.count, out, count);
+}
+
+template <typename T>
+hipError_t launch_residual_list(const Level &L, const T *psi, const Coef<T> &C, const T *u,
+                                const T *f, T *r, const uint8_t *cls, const GhostList &nl,
+                                hipStream_t st) {
+  if (nl.count == 0) return hipSuccess;
+  const int nb = (nl.count + kBlock - 1) / kBlock;
+  AMR_LAUNCH((k_residual_list<T>), nb, kBlock, st, L.g, C, psi, u, f, r, cls, nl.ids, nl.count);
+}
+
 hipError_t launch_ghost_listing(const Level &F, const uint8_t *cls, int *bcnt, int *boff, int *ids,
                                 int *total, hipStream_t st) {
   const int64_t nb = (F.g.nn + kCompactNodes - 1) / kCompactNodes;
@@ -737,10 +798,12 @@ struct AmrLevel {
   float *g32 = nullptr;    // FP32 cycle: R of the finer level's ghost-row loads (a < A)
   int *tflags = nullptr, *tids = nullptr;  // active column tiles (tiled levels a >= 1)
   int *tids1 = nullptr;    // the tiles of them that hold unknowns (class 1)
+  int *goids = nullptr;    // ghost nodes outside those tiles
   int *gids = nullptr, *gcnt = nullptr, *goff = nullptr;  // ghost-node list and its scratch
   GhostList gl;            // the level's ghost nodes (a >= 1; count 0 until set_problem)
   TileList tl;             // the level's active tiles (count 0 until set_problem)
   TileList tl1;            // its tiles with unknowns, in the same chunks
+  GhostList go;            // its ghost nodes in none of those tiles
   bool tiled = false;      // the level sweeps only its active tiles
   const TileList *tiles() const { return tiled ? &tl : nullptr; }
   // for the passes that touch class-1 nodes only: smoothing, correction,
@@ -1000,6 +1063,7 @@ static size_t amr_carve(sbm_amr_ctx *c, char *base) {
         l.tflags = cv.take<int>(nt);
         l.tids = cv.take<int>(nt);
         l.tids1 = cv.take<int>(nt);
+        l.goids = cv.take<int>(l.L.g.nn);
       }
     }
     if (a < A) l.tags = cv.take<uint8_t>(l.L.g.nc);
@@ -1066,6 +1130,20 @@ static double amr_omega(const sbm_options &o) {
 }
 
 // nu sweeps on the unknowns of level a >= 1 (class 1); other nodes keep x.
+// Padded residual of level l (classes 1-3; 0 at the other nodes of its
+// tiles): a tiled level evaluates it over its tiles with unknowns and the
+// ghost nodes outside them, so that no pass sweeps the tiles that only hold
+// ghost faces.
+template <typename T>
+static hipError_t amr_residual(sbm_amr_ctx *c, const AmrLevel &l, const T *psi, const Coef<T> &C,
+                               const T *x, const T *f, T *r) {
+  if (!l.tiled)
+    return launch_residual<T>(l.L, psi, C, x, f, r, nullptr, c->st, l.cls, l.tiles());
+  hipError_t e = launch_residual<T>(l.L, psi, C, x, f, r, nullptr, c->st, l.cls, l.unknown_tiles());
+  if (e != hipSuccess) return e;
+  return launch_residual_list<T>(l.L, psi, C, x, f, r, l.cls, l.go, c->st);
+}
+
 template <typename T>
 static hipError_t amr_smooth(sbm_amr_ctx *c, int a, T *x, const T *f, T *tmp, int nu) {
   AmrLevel &l = c->lv[a];
@@ -1133,8 +1211,7 @@ static hipError_t amr_fas(sbm_amr_ctx *c, int a) {
   if ((e = amr_smooth<T>(c, a, xf, ff, tf, c->opt.nu_pre)) != hipSuccess) return e;
   {
     AmrProf pr(c, SBM_PROF_RESIDUAL, fin);
-    if ((e = launch_residual<T>(F.L, AV<T>::psi(F), AV<T>::coef(F), xf, ff, wf, nullptr, c->st,
-                                F.cls, F.tiles())) != hipSuccess)
+    if ((e = amr_residual<T>(c, F, AV<T>::psi(F), AV<T>::coef(F), xf, ff, wf)) != hipSuccess)
       return e;
   }
   if ((e = launch_inject<T>(F.L, C.L, F.cls, xf, xc, c->st)) != hipSuccess) return e;
@@ -1173,8 +1250,11 @@ static sbm_status amr_comp_residual(sbm_amr_ctx *c, double *const *x, double *co
   for (int a = A; a >= 0; --a) {
     AmrLevel &l = c->lv[a];
     AmrProf pr(c, SBM_PROF_NORM, a == A);
-    AMR_HIP(launch_residual<double>(l.L, l.L.psi64, l.L.c64, x[a], f[a], r[a], nullptr, c->st,
-                                    a >= 1 ? l.cls : nullptr, a >= 1 ? l.tiles() : nullptr));
+    if (a >= 1)
+      AMR_HIP(amr_residual<double>(c, l, l.L.psi64, l.L.c64, x[a], f[a], r[a]));
+    else
+      AMR_HIP(launch_residual<double>(l.L, l.L.psi64, l.L.c64, x[a], f[a], r[a], nullptr, c->st,
+                                      nullptr, nullptr));
     if (a < A)
       AMR_HIP(launch_restrict_cif<double>(c->lv[a + 1].L, l.L, c->lv[a + 1].cls, r[a + 1], nullptr,
                                           nullptr, r[a], c->st));
@@ -1502,9 +1582,14 @@ sbm_status sbm_amr_set_problem(sbm_amr_ctx *c, const double *const *psi_raw,
   for (int a = 1; a <= A; ++a) {
     AmrLevel &l = c->lv[a];
     l.tl1 = TileList{l.tids1, 0, l.tl.kz};
+    l.go = GhostList{l.goids, 0};
     if (!l.tiled) continue;
     AMR_HIP(launch_active_tiles(l.L, l.cls, l.tflags, l.tids1, c->iflag + 16 + a, c->st, l.tl.kz,
                                 true));
+    // the residual (classes 1-3) runs over the same tiles and, node by node,
+    // over the ghost nodes they leave out
+    AMR_HIP(launch_ghost_outside(l.L, tile_geom_of(l.L, l.tl.kz), l.tflags, l.gl, l.goids,
+                                 c->iflag + 20 + a, c->st));
     listed = true;
   }
   if (listed) {
@@ -1515,6 +1600,7 @@ sbm_status sbm_amr_set_problem(sbm_amr_ctx *c, const double *const *psi_raw,
       if (c->lv[a].tiled) {
         c->lv[a].tl.count = iv[8 + a];
         c->lv[a].tl1.count = iv[16 + a];
+        c->lv[a].go.count = iv[20 + a];
       }
   }
   // tiled levels write partial sums for their listed tiles only
