@@ -1168,6 +1168,8 @@ static double amr_omega(const sbm_options &o) {
 template <typename T>
 static hipError_t amr_residual(sbm_amr_ctx *c, const AmrLevel &l, const T *psi, const Coef<T> &C,
                                const T *x, const T *f, T *r) {
+  if (!l.tiled && tiled_sweep_ok(l.L))
+    return launch_residual_tiled<T>(l.L, psi, C, x, f, r, nullptr, c->st, l.cls, nullptr);
   if (!l.tiled)
     return launch_residual<T>(l.L, psi, C, x, f, r, nullptr, c->st, l.cls, l.tiles());
   hipError_t e = launch_residual<T>(l.L, psi, C, x, f, r, nullptr, c->st, l.cls, l.unknown_tiles());
