@@ -549,47 +549,32 @@ __global__ __launch_bounds__(kBlock) void k_amr_correct(Geom gf, Geom gc,
     const int hi[3] = {(i + 1) >> 1, (j + 1) >> 1, DIM == 3 ? (k + 1) >> 1 : 0};
     const T wx = lo[0] == hi[0] ? T(1) : T(0.5), wy = lo[1] == hi[1] ? T(1) : T(0.5);
     const T wz = lo[2] == hi[2] ? T(1) : T(0.5);
-    if constexpr (sizeof(T) == 4) {
-      // FP32: the 2^DIM corners (lo or hi on each axis, x fastest), every
-      // load issued up front; a corner repeating lo on an axis where hi == lo
-      // is not summed, so the sum takes the distinct coarse nodes in x-fastest
-      // order, as below (FP32 correction 99 -> 59 us on the 257^3 level; in
-      // FP64 the repeated loads cost more than the latency they hide)
-      constexpr int NB = DIM == 3 ? 8 : 4;
-      int64_t qb[NB];
-      bool use[NB];
+    // the 2^DIM corners (lo or hi on each axis, x fastest), their loads
+    // issued together; a corner repeating lo on an axis where hi == lo is
+    // neither loaded (FP64) nor summed, so the sum takes the distinct coarse
+    // nodes in x-fastest order
+    constexpr int NB = DIM == 3 ? 8 : 4;
+    int64_t qb[NB];
+    bool use[NB];
 #pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        const int b0 = b & 1, b1 = (b >> 1) & 1, b2 = b >> 2;
-        qb[b] = (b0 ? hi[0] : lo[0]) + (int64_t)gc.nx * ((b1 ? hi[1] : lo[1]) +
-                                                         (int64_t)gc.ny * (b2 ? hi[2] : lo[2]));
-        use[b] = (!b0 || hi[0] != lo[0]) && (!b1 || hi[1] != lo[1]) && (!b2 || hi[2] != lo[2]);
-      }
+    for (int b = 0; b < NB; ++b) {
+      const int b0 = b & 1, b1 = (b >> 1) & 1, b2 = b >> 2;
+      qb[b] = (b0 ? hi[0] : lo[0]) + (int64_t)gc.nx * ((b1 ? hi[1] : lo[1]) +
+                                                       (int64_t)gc.ny * (b2 ? hi[2] : lo[2]));
+      use[b] = (!b0 || hi[0] != lo[0]) && (!b1 || hi[1] != lo[1]) && (!b2 || hi[2] != lo[2]);
+    }
 #pragma unroll
-      for (int c = 0; c < DIM; ++c) {
-        if (is_dirichlet(gf, i, j, k, c)) continue;
-        T d[NB];
+    for (int c = 0; c < DIM; ++c) {
+      if (is_dirichlet(gf, i, j, k, c)) continue;
+      T d[NB];
 #pragma unroll
-        for (int b = 0; b < NB; ++b) d[b] = xc[c * gc.nn + qb[b]] - xinj[c * gc.nn + qb[b]];
-        T acc = T(0);
+      for (int b = 0; b < NB; ++b)
+        d[b] = (sizeof(T) == 4 || use[b]) ? xc[c * gc.nn + qb[b]] - xinj[c * gc.nn + qb[b]] : T(0);
+      T acc = T(0);
 #pragma unroll
-        for (int b = 0; b < NB; ++b)
-          if (use[b]) acc += wx * wy * wz * d[b];
-        xf[c * gf.nn + id] += acc;
-      }
-    } else {
-#pragma unroll
-      for (int c = 0; c < DIM; ++c) {
-        if (is_dirichlet(gf, i, j, k, c)) continue;
-        T acc = T(0);
-        for (int I2 = lo[2]; I2 <= hi[2]; ++I2)
-          for (int I1 = lo[1]; I1 <= hi[1]; ++I1)
-            for (int I0 = lo[0]; I0 <= hi[0]; ++I0) {
-              const int64_t q = c * gc.nn + I0 + (int64_t)gc.nx * (I1 + (int64_t)gc.ny * I2);
-              acc += wx * wy * wz * (xc[q] - xinj[q]);
-            }
-        xf[c * gf.nn + id] += acc;
-      }
+      for (int b = 0; b < NB; ++b)
+        if (use[b]) acc += wx * wy * wz * d[b];
+      xf[c * gf.nn + id] += acc;
     }
   });
 }
