@@ -296,16 +296,32 @@ __device__ __forceinline__ void ghost_node(const Geom &gf, const Geom &gc,
   cnt[0] = quad_axis<T>(i, ix[0], w[0]);
   cnt[1] = quad_axis<T>(j, ix[1], w[1]);
   if (DIM == 3) cnt[2] = quad_axis<T>(k, ix[2], w[2]);
+  // the loads of all taken coarse nodes are issued together, then summed in
+  // x-fastest order
+  constexpr int NZ = DIM == 3 ? 3 : 1;
 #pragma unroll
   for (int c = 0; c < DIM; ++c) {
     if (is_dirichlet(gf, i, j, k, c)) continue;
-    T s = T(0);
-    for (int t2 = 0; t2 < cnt[2]; ++t2)
-      for (int t1 = 0; t1 < cnt[1]; ++t1)
-        for (int t0 = 0; t0 < cnt[0]; ++t0) {
+    T v[NZ][3][3];
+#pragma unroll
+    for (int t2 = 0; t2 < NZ; ++t2)
+#pragma unroll
+      for (int t1 = 0; t1 < 3; ++t1)
+#pragma unroll
+        for (int t0 = 0; t0 < 3; ++t0) {
           const int64_t q = ix[0][t0] + (int64_t)gc.nx * (ix[1][t1] + (int64_t)gc.ny * ix[2][t2]);
-          s += w[0][t0] * w[1][t1] * w[2][t2] * xc[c * gc.nn + q];
+          v[t2][t1][t0] =
+              (t0 < cnt[0] && t1 < cnt[1] && t2 < cnt[2]) ? xc[c * gc.nn + q] : T(0);
         }
+    T s = T(0);
+#pragma unroll
+    for (int t2 = 0; t2 < NZ; ++t2)
+#pragma unroll
+      for (int t1 = 0; t1 < 3; ++t1)
+#pragma unroll
+        for (int t0 = 0; t0 < 3; ++t0)
+          if (t0 < cnt[0] && t1 < cnt[1] && t2 < cnt[2])
+            s += w[0][t0] * w[1][t1] * w[2][t2] * v[t2][t1][t0];
     xf[c * gf.nn + id] = s;
   }
 }
