@@ -49,8 +49,8 @@ namespace {
 constexpr int kMaxAmrLevels = 4;  // base + up to 3 refined levels
 // device ints of the set-up: [0] error flags, [8 + a] active tiles, [12 + a]
 // ghost nodes, [16 + a] tiles with unknowns, [20 + a] ghost nodes outside
-// them, of level a
-constexpr int kIflags = 24;
+// them, [24 + a] coarse nodes under the region, of level a
+constexpr int kIflags = 28;
 // Tile lists of sparsely refined levels: shallowest chunk depth, and the
 // number of workgroups the listed tiles should give (a few per CU).
 constexpr int kAmrKzMin = 6;
@@ -393,18 +393,36 @@ __global__ __launch_bounds__(kBlock) void k_residual_list(Geom g, Coef<T> C,
   for (int c = 0; c < 3; ++c) r[c * g.nn + id] = ((g.dmask >> c) & fb) ? T(0) : fv[c] - out[c];
 }
 
-// Ghost-node list of a level (ids of the nodes of class >= 2, increasing), by
-// a three-pass compaction: per-block counts, one-workgroup scan of the
-// counts, per-block writes in node order.
+// Node lists of a level (ids of the nodes a predicate selects, increasing),
+// by a three-pass compaction: per-block counts, one-workgroup scan of the
+// counts, per-block writes in node order.  Ghost nodes: class >= 2.  Coarse
+// nodes the composite restriction writes: fine class 1 or 2 at the
+// coinciding fine node.
 constexpr int kCompactNodes = 4 * kBlock;  // nodes per block (four per thread)
 
-__global__ __launch_bounds__(kBlock) void k_ghost_count(int64_t nn, const uint8_t *__restrict__ cls,
-                                                        int *__restrict__ bcnt) {
+struct GhostPick {
+  const uint8_t *cls;
+  __device__ bool operator()(int64_t id) const { return cls[id] >= 2; }
+};
+struct CifPick {
+  Geom gf, gc;
+  const uint8_t *clsf;
+  __device__ bool operator()(int64_t id) const {
+    int I, J, K;
+    node_ijk(gc, id, I, J, K);
+    const uint8_t fc = clsf[fine_of_coarse(gf, I, J, K)];
+    return fc == 1 || fc == 2;
+  }
+};
+
+template <class P>
+__global__ __launch_bounds__(kBlock) void k_list_count(int64_t nn, P pick,
+                                                       int *__restrict__ bcnt) {
   __shared__ int red[kBlock];
   const int64_t base = (int64_t)blockIdx.x * kCompactNodes + 4 * threadIdx.x;
   int c = 0;
 #pragma unroll
-  for (int e = 0; e < 4; ++e) c += (base + e < nn && cls[base + e] >= 2) ? 1 : 0;
+  for (int e = 0; e < 4; ++e) c += (base + e < nn && pick(base + e)) ? 1 : 0;
   red[threadIdx.x] = c;
   __syncthreads();
   for (int d = kBlock / 2; d > 0; d >>= 1) {
@@ -438,16 +456,17 @@ __global__ __launch_bounds__(1024) void k_scan_counts(const int *__restrict__ cn
   if (t == 1023) *total = sh[1023];
 }
 
-__global__ __launch_bounds__(kBlock) void k_ghost_write(int64_t nn, const uint8_t *__restrict__ cls,
-                                                        const int *__restrict__ boff,
-                                                        int *__restrict__ ids) {
+template <class P>
+__global__ __launch_bounds__(kBlock) void k_list_write(int64_t nn, P pick,
+                                                       const int *__restrict__ boff,
+                                                       int *__restrict__ ids) {
   __shared__ int sh[kBlock];
   const int64_t base = (int64_t)blockIdx.x * kCompactNodes + 4 * threadIdx.x;
   bool g[4];
   int c = 0;
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
-    g[e] = base + e < nn && cls[base + e] >= 2;
+    g[e] = base + e < nn && pick(base + e);
     c += g[e] ? 1 : 0;
   }
   sh[threadIdx.x] = c;
@@ -468,19 +487,20 @@ __global__ __launch_bounds__(kBlock) void k_ghost_write(int64_t nn, const uint8_
 // coinciding node), free DOF: out = R r_f (+ add) (+ add2), R the
 // full-weighting transpose of multilinear P over 2^d.  With ONLY_GHOSTS only
 // fine nodes of class 2 and 3 contribute.  Other nodes are left untouched.
+// One thread per listed coarse node (ids: those nodes, from CifPick).
 template <typename T, int DIM, bool ONLY_GHOSTS>
 __global__ __launch_bounds__(kBlock) void k_amr_restrict_cif(Geom gf, Geom gc,
                                                              const uint8_t *__restrict__ clsf,
+                                                             const int *__restrict__ ids, int n,
                                                              const T *__restrict__ rf,
                                                              const T *__restrict__ add,
                                                              const T *__restrict__ add2,
                                                              T *__restrict__ out) {
-  const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (id >= gc.nn) return;
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= n) return;
+  const int64_t id = ids[t];
   int I, J, K;
   node_ijk(gc, id, I, J, K);
-  const uint8_t fc = clsf[fine_of_coarse(gf, I, J, K)];
-  if (fc != 1 && fc != 2) return;
   T acc[3] = {T(0), T(0), T(0)};
   const int zlo = (DIM == 3) ? -1 : 0, zhi = (DIM == 3) ? 1 : 0;
   for (int dz = zlo; dz <= zhi; ++dz) {
@@ -723,31 +743,40 @@ hipError_t launch_residual_list(const Level &L, const T *psi, const Coef<T> &C, 
   AMR_LAUNCH((k_residual_list<T>), nb, kBlock, st, L.g, C, psi, u, f, r, cls, nl.ids, nl.count);
 }
 
-hipError_t launch_ghost_listing(const Level &F, const uint8_t *cls, int *bcnt, int *boff, int *ids,
-                                int *total, hipStream_t st) {
-  const int64_t nb = (F.g.nn + kCompactNodes - 1) / kCompactNodes;
+// ids (increasing) of the nodes 0 .. nn-1 that pick selects, their number in
+// *total; bcnt and boff hold one int per kCompactNodes nodes.
+template <class P>
+hipError_t launch_listing(int64_t nn, const P &pick, int *bcnt, int *boff, int *ids, int *total,
+                          hipStream_t st) {
+  const int64_t nb = (nn + kCompactNodes - 1) / kCompactNodes;
   (void)hipGetLastError();
-  hipLaunchKernelGGL(k_ghost_count, dim3((unsigned)nb), dim3(kBlock), 0, st, F.g.nn, cls, bcnt);
+  hipLaunchKernelGGL(k_list_count<P>, dim3((unsigned)nb), dim3(kBlock), 0, st, nn, pick, bcnt);
   hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, (const int *)bcnt, (int)nb, boff,
                      total);
-  hipLaunchKernelGGL(k_ghost_write, dim3((unsigned)nb), dim3(kBlock), 0, st, F.g.nn, cls,
+  hipLaunchKernelGGL(k_list_write<P>, dim3((unsigned)nb), dim3(kBlock), 0, st, nn, pick,
                      (const int *)boff, ids);
   return hipGetLastError();
 }
 
+// cl: the coarse nodes on or inside the fine region, listed at set-up.
 template <typename T>
-hipError_t launch_restrict_cif(const Level &F, const Level &C, const uint8_t *clsf, const T *rf,
-                               const T *add, const T *add2, T *out, hipStream_t st,
-                               bool only_ghosts = false) {
-  const int nb = num_blocks(C.g.nn);
+hipError_t launch_restrict_cif(const Level &F, const Level &C, const uint8_t *clsf,
+                               const GhostList &cl, const T *rf, const T *add, const T *add2,
+                               T *out, hipStream_t st, bool only_ghosts = false) {
+  if (cl.count == 0) return hipSuccess;
+  const int nb = (cl.count + kBlock - 1) / kBlock;
   if (only_ghosts) {
     if (F.g.dim == 3)
-      AMR_LAUNCH((k_amr_restrict_cif<T, 3, true>), nb, kBlock, st, F.g, C.g, clsf, rf, add, add2, out);
-    AMR_LAUNCH((k_amr_restrict_cif<T, 2, true>), nb, kBlock, st, F.g, C.g, clsf, rf, add, add2, out);
+      AMR_LAUNCH((k_amr_restrict_cif<T, 3, true>), nb, kBlock, st, F.g, C.g, clsf, cl.ids,
+                 cl.count, rf, add, add2, out);
+    AMR_LAUNCH((k_amr_restrict_cif<T, 2, true>), nb, kBlock, st, F.g, C.g, clsf, cl.ids, cl.count,
+               rf, add, add2, out);
   }
   if (F.g.dim == 3)
-    AMR_LAUNCH((k_amr_restrict_cif<T, 3, false>), nb, kBlock, st, F.g, C.g, clsf, rf, add, add2, out);
-  AMR_LAUNCH((k_amr_restrict_cif<T, 2, false>), nb, kBlock, st, F.g, C.g, clsf, rf, add, add2, out);
+    AMR_LAUNCH((k_amr_restrict_cif<T, 3, false>), nb, kBlock, st, F.g, C.g, clsf, cl.ids,
+               cl.count, rf, add, add2, out);
+  AMR_LAUNCH((k_amr_restrict_cif<T, 2, false>), nb, kBlock, st, F.g, C.g, clsf, cl.ids, cl.count,
+             rf, add, add2, out);
 }
 
 hipError_t launch_amr_cast(const Level &L, const uint8_t *cls, const double *r, float *r32,
@@ -830,11 +859,13 @@ struct AmrLevel {
   int *tflags = nullptr, *tids = nullptr;  // active column tiles (tiled levels a >= 1)
   int *tids1 = nullptr;    // the tiles of them that hold unknowns (class 1)
   int *goids = nullptr;    // ghost nodes outside those tiles
+  int *cids = nullptr;     // level a-1 nodes on or inside this level's region
   int *gids = nullptr, *gcnt = nullptr, *goff = nullptr;  // ghost-node list and its scratch
   GhostList gl;            // the level's ghost nodes (a >= 1; count 0 until set_problem)
   TileList tl;             // the level's active tiles (count 0 until set_problem)
   TileList tl1;            // its tiles with unknowns, in the same chunks
   GhostList go;            // its ghost nodes in none of those tiles
+  GhostList cl;            // the coarse nodes its composite restriction writes
   bool tiled = false;      // the level sweeps only its active tiles
   const TileList *tiles() const { return tiled ? &tl : nullptr; }
   // for the passes that touch class-1 nodes only: smoothing, correction,
@@ -1087,6 +1118,7 @@ static size_t amr_carve(sbm_amr_ctx *c, char *base) {
       const int64_t ncb = (l.L.g.nn + 4 * kBlock - 1) / (4 * kBlock);
       l.gcnt = cv.take<int>(ncb);
       l.goff = cv.take<int>(ncb);
+      l.cids = cv.take<int>(c->lv[a - 1].L.g.nn);
       l.tiled = tiled_ok(l.L) && tile_geom_of(l.L).ntiles <= num_blocks(l.L.g.nn);
       if (l.tiled) {
         // sized for the most tiles the set-up may list: the default chunks
@@ -1257,7 +1289,8 @@ static hipError_t amr_fas(sbm_amr_ctx *c, int a) {
   if constexpr (sizeof(T) == 4) g = C.g32;
   {
     AmrProf pr(c, SBM_PROF_RESTRICT, fin);
-    if ((e = launch_restrict_cif<T>(F.L, C.L, F.cls, wf, tc, g, fc, c->st)) != hipSuccess) return e;
+    if ((e = launch_restrict_cif<T>(F.L, C.L, F.cls, F.cl, wf, tc, g, fc, c->st)) != hipSuccess)
+      return e;
   }
   if ((e = amr_fas<T>(c, a - 1)) != hipSuccess) return e;
   {
@@ -1290,8 +1323,8 @@ static sbm_status amr_comp_residual(sbm_amr_ctx *c, double *const *x, double *co
       AMR_HIP(launch_residual<double>(l.L, l.L.psi64, l.L.c64, x[a], f[a], r[a], nullptr, c->st,
                                       nullptr, nullptr));
     if (a < A)
-      AMR_HIP(launch_restrict_cif<double>(c->lv[a + 1].L, l.L, c->lv[a + 1].cls, r[a + 1], nullptr,
-                                          nullptr, r[a], c->st));
+      AMR_HIP(launch_restrict_cif<double>(c->lv[a + 1].L, l.L, c->lv[a + 1].cls, c->lv[a + 1].cl,
+                                          r[a + 1], nullptr, nullptr, r[a], c->st));
   }
   for (int a = 0; a <= A; ++a) {
     AmrLevel &l = c->lv[a];
@@ -1561,7 +1594,13 @@ sbm_status sbm_amr_set_problem(sbm_amr_ctx *c, const double *const *psi_raw,
     // the ghost nodes (classes 2-4), filled from the coarser level by a list
     // of their ids rather than by a pass over the level or its tiles
     l.gl = GhostList{l.gids, 0};
-    AMR_HIP(launch_ghost_listing(l.L, l.cls, l.gcnt, l.goff, l.gids, c->iflag + 12 + a, c->st));
+    AMR_HIP(launch_listing(l.L.g.nn, GhostPick{l.cls}, l.gcnt, l.goff, l.gids, c->iflag + 12 + a,
+                           c->st));
+    // the level a-1 nodes that the composite restriction writes, so that it
+    // runs a thread per such node rather than over the whole coarse level
+    l.cl = GhostList{l.cids, 0};
+    AMR_HIP(launch_listing(c->lv[a - 1].L.g.nn, CifPick{l.L.g, c->lv[a - 1].L.g, l.cls}, l.gcnt,
+                           l.goff, l.cids, c->iflag + 24 + a, c->st));
   }
   // psi of covered coarse cells, finest first
   for (int a = A; a >= 1; --a) {
@@ -1591,6 +1630,7 @@ sbm_status sbm_amr_set_problem(sbm_amr_ctx *c, const double *const *psi_raw,
   for (int a = 1; a <= A; ++a) {
     if (c->lv[a].tiled) c->lv[a].tl.count = iv[8 + a];
     c->lv[a].gl.count = iv[12 + a];
+    c->lv[a].cl.count = iv[24 + a];
   }
   // A level whose active tiles are few for the GPU (a fraction of its
   // default tile count) lists them again in shallower chunks, so that the
@@ -1787,7 +1827,8 @@ sbm_status sbm_amr_solve(sbm_amr_ctx *c, double *const *u, double *hist_host, in
         if (a < A) {
           AMR_HIP(launch_fill<double>(l.w, l.nv(), 0.0, c->st));
           AMR_HIP(launch_restrict_cif<double>(c->lv[a + 1].L, l.L, c->lv[a + 1].cls,
-                                              c->lv[a + 1].r, nullptr, nullptr, l.w, c->st, true));
+                                              c->lv[a + 1].cl, c->lv[a + 1].r, nullptr, nullptr,
+                                              l.w, c->st, true));
           AMR_HIP(launch_cast_scaled(l.w, l.g32, l.nv(), c->scal, c->st));
         }
       }
