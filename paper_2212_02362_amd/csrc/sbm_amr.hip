@@ -337,7 +337,7 @@ __global__ __launch_bounds__(kBlock) void k_amr_ghost_list(Geom gf, Geom gc,
   ghost_node<T, DIM>(gf, gc, xc, xf, ids[t]);
 }
 
-// dst = src on the listed ghost nodes (all components).
+// dst = src (0 when src is null) on the listed nodes (all components).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_amr_ghost_copy(int64_t nn, int dim,
                                                            const int *__restrict__ ids, int n,
@@ -346,7 +346,7 @@ __global__ __launch_bounds__(kBlock) void k_amr_ghost_copy(int64_t nn, int dim,
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (t >= n) return;
   const int64_t id = ids[t];
-  for (int c = 0; c < dim; ++c) dst[c * nn + id] = src[c * nn + id];
+  for (int c = 0; c < dim; ++c) dst[c * nn + id] = src ? src[c * nn + id] : T(0);
 }
 
 // The listed ghost nodes that lie in no flagged tile (tflags: the flags of a
@@ -1821,8 +1821,11 @@ sbm_status sbm_amr_solve(sbm_amr_ctx *c, double *const *u, double *hist_host, in
       // FP32 loads carry zeros on those rows, so no FP32 sum cancels.
       for (int a = 0; a <= A; ++a) {
         AmrLevel &l = c->lv[a];
+        // a tiled level casts over its tiles with unknowns; the ghost nodes
+        // outside them get the zero load the cast gives every ghost row
         AMR_HIP(launch_amr_cast(l.L, a >= 1 ? l.cls : nullptr, l.r, l.f32, c->scal, c->st,
-                                a >= 1 ? l.tiles() : nullptr));
+                                a >= 1 ? l.unknown_tiles() : nullptr));
+        if (a >= 1 && l.tiled) AMR_HIP(launch_ghost_copy<float>(l.L, l.go, nullptr, l.f32, c->st));
         AMR_HIP(launch_fill<float>(l.e32, l.nv(), 0.0f, c->st));
         if (a < A) {
           AMR_HIP(launch_fill<double>(l.w, l.nv(), 0.0, c->st));
