@@ -337,6 +337,14 @@ __global__ __launch_bounds__(kBlock) void k_amr_ghost_list(Geom gf, Geom gc,
   ghost_node<T, DIM>(gf, gc, xc, xf, ids[t]);
 }
 
+// x = 0 at the nodes of a level (of its listed tiles when TILED).
+template <typename T, bool TILED>
+__global__ __launch_bounds__(kBlock) void k_amr_zero(Geom g, T *__restrict__ x, TileArg ta) {
+  for_nodes<TILED>(g, ta, [&](int64_t id) {
+    for (int c = 0; c < g.dim; ++c) x[c * g.nn + id] = T(0);
+  });
+}
+
 // dst = src (0 when src is null) on the listed nodes (all components).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_amr_ghost_copy(int64_t nn, int dim,
@@ -717,6 +725,12 @@ hipError_t launch_ghost_list(const Level &F, const Level &C, const GhostList &gl
   if (F.g.dim == 3)
     AMR_LAUNCH((k_amr_ghost_list<T, 3>), nb, kBlock, st, F.g, C.g, gl.ids, gl.count, xc, xf);
   AMR_LAUNCH((k_amr_ghost_list<T, 2>), nb, kBlock, st, F.g, C.g, gl.ids, gl.count, xc, xf);
+}
+
+template <typename T>
+hipError_t launch_zero_nodes(const Level &L, const TileList *tl, T *x, hipStream_t st) {
+  const NodeGrid ng = node_grid(L, tl);
+  AMR_NODE_LAUNCH((k_amr_zero<T, true>), (k_amr_zero<T, false>), ng, st, L.g, x);
 }
 
 template <typename T>
@@ -1194,6 +1208,17 @@ static double amr_omega(const sbm_options &o) {
 }
 
 // nu sweeps on the unknowns of level a >= 1 (class 1); other nodes keep x.
+// The cycle's iterate from zero: a tiled level zeroes its tiles with
+// unknowns and the ghost nodes outside them (the nodes any of its passes
+// read), not the whole level.
+template <typename T>
+static hipError_t amr_zero(sbm_amr_ctx *c, const AmrLevel &l, T *x) {
+  if (!l.tiled) return launch_fill<T>(x, l.nv(), T(0), c->st);
+  hipError_t e = launch_zero_nodes<T>(l.L, l.unknown_tiles(), x, c->st);
+  if (e != hipSuccess) return e;
+  return launch_ghost_copy<T>(l.L, l.go, nullptr, x, c->st);
+}
+
 // Padded residual of level l (classes 1-3; 0 at the other nodes of its
 // tiles): a tiled level evaluates it over its tiles with unknowns and the
 // ghost nodes outside them, so that no pass sweeps the tiles that only hold
@@ -1826,7 +1851,7 @@ sbm_status sbm_amr_solve(sbm_amr_ctx *c, double *const *u, double *hist_host, in
         AMR_HIP(launch_amr_cast(l.L, a >= 1 ? l.cls : nullptr, l.r, l.f32, c->scal, c->st,
                                 a >= 1 ? l.unknown_tiles() : nullptr));
         if (a >= 1 && l.tiled) AMR_HIP(launch_ghost_copy<float>(l.L, l.go, nullptr, l.f32, c->st));
-        AMR_HIP(launch_fill<float>(l.e32, l.nv(), 0.0f, c->st));
+        AMR_HIP(amr_zero<float>(c, l, l.e32));
         if (a < A) {
           AMR_HIP(launch_fill<double>(l.w, l.nv(), 0.0, c->st));
           AMR_HIP(launch_restrict_cif<double>(c->lv[a + 1].L, l.L, c->lv[a + 1].cls,
@@ -1841,7 +1866,7 @@ sbm_status sbm_amr_solve(sbm_amr_ctx *c, double *const *u, double *hist_host, in
                                      c->lv[a].e32, c->scal, c->st,
                                      a >= 1 ? c->lv[a].unknown_tiles() : nullptr));
     } else {
-      for (int a = 0; a <= A; ++a) AMR_HIP(launch_fill<double>(c->lv[a].e, c->lv[a].nv(), 0.0, c->st));
+      for (int a = 0; a <= A; ++a) AMR_HIP(amr_zero<double>(c, c->lv[a], c->lv[a].e));
       AMR_HIP(amr_fas<double>(c, A));
       for (int a = 0; a <= A; ++a)
         AMR_HIP(launch_update<double>(c->lv[a].L, a >= 1 ? c->lv[a].cls : nullptr, u[a],
