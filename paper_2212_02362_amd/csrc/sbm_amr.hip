@@ -357,24 +357,8 @@ __global__ __launch_bounds__(kBlock) void k_amr_ghost_copy(int64_t nn, int dim,
   for (int c = 0; c < dim; ++c) dst[c * nn + id] = src ? src[c * nn + id] : T(0);
 }
 
-// The listed ghost nodes that lie in no flagged tile (tflags: the flags of a
-// tile list of geometry tg), appended to out in any order.
-__global__ __launch_bounds__(kBlock) void k_ghost_outside(Geom g, TileGeom tg,
-                                                          const int *__restrict__ tflags,
-                                                          const int *__restrict__ ids, int n,
-                                                          int *__restrict__ out,
-                                                          int *__restrict__ count) {
-  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (t >= n) return;
-  const int id = ids[t];
-  int i, j, k;
-  node_ijk(g, id, i, j, k);
-  if (tflags[i / kTileX + tg.ntx * (j / kTileY + tg.nty * (k / tg.kz))]) return;
-  out[atomicAdd(count, 1)] = id;
-}
-
 // r = f - K u at the listed nodes of a level with classes (a padded residual
-// as k_residual with a class mask: classes 2-3 carry one, class 4 gets 0).
+// as k_residual with a class mask: classes 1-3 carry one, the others get 0).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_residual_list(Geom g, Coef<T> C,
                                                           const T *__restrict__ psi,
@@ -403,14 +387,27 @@ __global__ __launch_bounds__(kBlock) void k_residual_list(Geom g, Coef<T> C,
 
 // Node lists of a level (ids of the nodes a predicate selects, increasing),
 // by a three-pass compaction: per-block counts, one-workgroup scan of the
-// counts, per-block writes in node order.  Ghost nodes: class >= 2.  Coarse
-// nodes the composite restriction writes: fine class 1 or 2 at the
-// coinciding fine node.
+// counts, per-block writes in node order.  Ghost nodes: class >= 2.  Ghost
+// nodes in no flagged tile of a fixed-depth tile geometry (tflags: the flags
+// of a tile list).  Coarse nodes the composite restriction writes: fine class
+// 1 or 2 at the coinciding fine node.
 constexpr int kCompactNodes = 4 * kBlock;  // nodes per block (four per thread)
 
 struct GhostPick {
   const uint8_t *cls;
   __device__ bool operator()(int64_t id) const { return cls[id] >= 2; }
+};
+struct OutsidePick {
+  Geom g;
+  TileGeom tg;
+  const int *tflags;
+  const uint8_t *cls;
+  __device__ bool operator()(int64_t id) const {
+    if (cls[id] < 2) return false;
+    int i, j, k;
+    node_ijk(g, id, i, j, k);
+    return !tflags[i / kTileX + tg.ntx * (j / kTileY + tg.nty * (k / tg.kz))];
+  }
 };
 struct CifPick {
   Geom gf, gc;
@@ -739,13 +736,6 @@ hipError_t launch_ghost_copy(const Level &L, const GhostList &gl, const T *src, 
   if (gl.count == 0) return hipSuccess;
   const int nb = (gl.count + kBlock - 1) / kBlock;
   AMR_LAUNCH((k_amr_ghost_copy<T>), nb, kBlock, st, L.g.nn, L.g.dim, gl.ids, gl.count, src, dst);
-}
-
-hipError_t launch_ghost_outside(const Level &L, const TileGeom &tg, const int *tflags,
-                                const GhostList &gl, int *out, int *count, hipStream_t st) {
-  if (gl.count == 0) return hipSuccess;
-  const int nb = (gl.count + kBlock - 1) / kBlock;
-  AMR_LAUNCH(k_ghost_outside, nb, kBlock, st, L.g, tg, tflags, gl.ids, gl.count, out, count);
 }
 
 template <typename T>
@@ -1687,8 +1677,8 @@ sbm_status sbm_amr_set_problem(sbm_amr_ctx *c, const double *const *psi_raw,
                                 true));
     // the residual (classes 1-3) runs over the same tiles and, node by node,
     // over the ghost nodes they leave out
-    AMR_HIP(launch_ghost_outside(l.L, tile_geom_of(l.L, l.tl.kz), l.tflags, l.gl, l.goids,
-                                 c->iflag + 20 + a, c->st));
+    const OutsidePick outside{l.L.g, tile_geom_of(l.L, l.tl.kz), l.tflags, l.cls};
+    AMR_HIP(launch_listing(l.L.g.nn, outside, l.gcnt, l.goff, l.goids, c->iflag + 20 + a, c->st));
     listed = true;
   }
   if (listed) {
