@@ -1667,21 +1667,16 @@ sbm_status sbm_amr_set_problem(sbm_amr_ctx *c, const double *const *psi_raw,
   // them (in the 64^3 x 3 voids workload 1.3x the unknowns against 2.4x for
   // all active tiles: a block's ghost faces lie in the next tile); the same
   // chunks, so their partial sums stay within the level's share.
-  bool listed = false;
-  for (int a = 1; a <= A; ++a) {
-    AmrLevel &l = c->lv[a];
-    l.tl1 = TileList{l.tids1, 0, l.tl.kz};
-    l.go = GhostList{l.goids, 0};
-    if (!l.tiled) continue;
-    AMR_HIP(launch_active_tiles(l.L, l.cls, l.tflags, l.tids1, c->iflag + 16 + a, c->st, l.tl.kz,
-                                true));
-    // the residual (classes 1-3) runs over the same tiles and, node by node,
-    // over the ghost nodes they leave out
-    const OutsidePick outside{l.L.g, tile_geom_of(l.L, l.tl.kz), l.tflags, l.cls};
+  // The residual (classes 1-3) runs over the same tiles and, node by node,
+  // over the ghost nodes they leave out.
+  auto list_unknowns = [&](AmrLevel &l, int a, int kz) -> sbm_status {
+    l.tl1 = TileList{l.tids1, 0, kz};
+    AMR_HIP(launch_active_tiles(l.L, l.cls, l.tflags, l.tids1, c->iflag + 16 + a, c->st, kz, true));
+    const OutsidePick outside{l.L.g, tile_geom_of(l.L, kz), l.tflags, l.cls};
     AMR_HIP(launch_listing(l.L.g.nn, outside, l.gcnt, l.goff, l.goids, c->iflag + 20 + a, c->st));
-    listed = true;
-  }
-  if (listed) {
+    return SBM_OK;
+  };
+  auto read_counts = [&]() -> sbm_status {
     AMR_HIP(hipMemcpyAsync(c->host, c->iflag, kIflags * sizeof(int), hipMemcpyDeviceToHost, c->st));
     AMR_HIP(hipStreamSynchronize(c->st));
     memcpy(iv, c->host, sizeof(iv));
@@ -1691,7 +1686,33 @@ sbm_status sbm_amr_set_problem(sbm_amr_ctx *c, const double *const *psi_raw,
         c->lv[a].tl1.count = iv[16 + a];
         c->lv[a].go.count = iv[20 + a];
       }
+    return SBM_OK;
+  };
+  bool listed = false;
+  for (int a = 1; a <= A; ++a) {
+    AmrLevel &l = c->lv[a];
+    l.tl1 = TileList{l.tids1, 0, l.tl.kz};
+    l.go = GhostList{l.goids, 0};
+    if (!l.tiled) continue;
+    AMR_TRY(list_unknowns(l, a, l.tl.kz));
+    listed = true;
   }
+  if (listed) AMR_TRY(read_counts());
+  // The tiles with unknowns are fewer than the active ones: a level whose
+  // list is short for the GPU lists them again in shallower chunks, by the
+  // rule above.
+  bool relisted = false;
+  for (int a = 1; a <= A; ++a) {
+    AmrLevel &l = c->lv[a];
+    if (!l.tiled || l.tl1.count == 0) continue;
+    const int kzc = tile_geom_of(l.L, l.tl.kz).kz;
+    const int kz = std::max(kAmrKzMin, std::min(kzc, (int)((int64_t)kzc * l.tl1.count / kAmrTiles)));
+    const TileGeom tn = tile_geom_of(l.L, kz);
+    if (kz >= kzc || (int64_t)tn.ntiles * tn.kz > num_blocks(l.L.g.nn)) continue;
+    AMR_TRY(list_unknowns(l, a, kz));
+    relisted = true;
+  }
+  if (relisted) AMR_TRY(read_counts());
   // tiled levels write partial sums for their listed tiles only
   AMR_HIP(launch_fill<double>(c->partials, c->npart, 0.0, c->st));
   if (flags & 1) return amr_fail(SBM_E_NONFINITE, "NaN/Inf in psi");
