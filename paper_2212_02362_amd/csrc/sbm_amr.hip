@@ -47,9 +47,9 @@ using namespace sbm;
 namespace {
 
 constexpr int kMaxAmrLevels = 4;  // base + up to 3 refined levels
-// device ints of the set-up: [0] error flags, [8 + a] active tiles, [12 + a]
-// ghost nodes, [16 + a] tiles with unknowns, [20 + a] ghost nodes outside
-// them, [24 + a] coarse nodes under the region, of level a
+// device ints of the set-up: [0] error flags, [12 + a] ghost nodes, [16 + a]
+// tiles with unknowns, [20 + a] ghost nodes outside them, [24 + a] coarse
+// nodes under the region, of level a
 constexpr int kIflags = 28;
 // Tile lists of sparsely refined levels: shallowest chunk depth, and the
 // number of workgroups the listed tiles should give (a few per CU).
@@ -860,21 +860,19 @@ struct AmrLevel {
   double *fP = nullptr, *r = nullptr, *e = nullptr, *w = nullptr, *xinj = nullptr, *tmp = nullptr;
   float *e32 = nullptr, *f32 = nullptr, *w32 = nullptr, *xinj32 = nullptr, *tmp32 = nullptr;
   float *g32 = nullptr;    // FP32 cycle: R of the finer level's ghost-row loads (a < A)
-  int *tflags = nullptr, *tids = nullptr;  // active column tiles (tiled levels a >= 1)
-  int *tids1 = nullptr;    // the tiles of them that hold unknowns (class 1)
+  int *tflags = nullptr;   // tile flags (listing scratch, tiled levels a >= 1)
+  int *tids1 = nullptr;    // the column tiles that hold unknowns (class 1)
   int *goids = nullptr;    // ghost nodes outside those tiles
   int *cids = nullptr;     // level a-1 nodes on or inside this level's region
   int *gids = nullptr, *gcnt = nullptr, *goff = nullptr;  // ghost-node list and its scratch
   GhostList gl;            // the level's ghost nodes (a >= 1; count 0 until set_problem)
-  TileList tl;             // the level's active tiles (count 0 until set_problem)
-  TileList tl1;            // its tiles with unknowns, in the same chunks
+  TileList tl1;            // its tiles with unknowns (count 0 until set_problem)
   GhostList go;            // its ghost nodes in none of those tiles
   GhostList cl;            // the coarse nodes its composite restriction writes
-  bool tiled = false;      // the level sweeps only its active tiles
-  const TileList *tiles() const { return tiled ? &tl : nullptr; }
-  // for the passes that touch class-1 nodes only: smoothing, correction,
-  // update, norm; the residual adds the list go, the FP32 loads (which also
-  // zero the ghost rows) take tl
+  bool tiled = false;      // the level's passes run over tl1 (and the lists)
+  // the tiles of every pass over the level: the smoothing, correction, update,
+  // norm and zeroing touch class-1 nodes only; the residual and the FP32 loads
+  // also reach the ghost nodes, by the list go for those outside the tiles
   const TileList *unknown_tiles() const { return tiled ? &tl1 : nullptr; }
   int part_off = 0;        // offset of this level's partial sums
   Traction tr{};
@@ -1129,7 +1127,6 @@ static size_t amr_carve(sbm_amr_ctx *c, char *base) {
         // or the shallowest ones it may choose
         const int nt = std::max(tile_geom_of(l.L).ntiles, tile_geom_of(l.L, kAmrKzMin).ntiles);
         l.tflags = cv.take<int>(nt);
-        l.tids = cv.take<int>(nt);
         l.tids1 = cv.take<int>(nt);
         l.goids = cv.take<int>(l.L.g.nn);
       }
@@ -1219,7 +1216,7 @@ static hipError_t amr_residual(sbm_amr_ctx *c, const AmrLevel &l, const T *psi, 
   if (!l.tiled && tiled_sweep_ok(l.L))
     return launch_residual_tiled<T>(l.L, psi, C, x, f, r, nullptr, c->st, l.cls, nullptr);
   if (!l.tiled)
-    return launch_residual<T>(l.L, psi, C, x, f, r, nullptr, c->st, l.cls, l.tiles());
+    return launch_residual<T>(l.L, psi, C, x, f, r, nullptr, c->st, l.cls, nullptr);
   hipError_t e = launch_residual<T>(l.L, psi, C, x, f, r, nullptr, c->st, l.cls, l.unknown_tiles());
   if (e != hipSuccess) return e;
   return launch_residual_list<T>(l.L, psi, C, x, f, r, l.cls, l.go, c->st);
@@ -1601,11 +1598,8 @@ sbm_status sbm_amr_set_problem(sbm_amr_ctx *c, const double *const *psi_raw,
     }
     AMR_HIP(hipGetLastError());
   }
-  // active column tiles of the tiled levels (their counts read back below)
   for (int a = 1; a <= A; ++a) {
     AmrLevel &l = c->lv[a];
-    l.tl = TileList{l.tids, 0, 0};
-    if (l.tiled) AMR_HIP(launch_active_tiles(l.L, l.cls, l.tflags, l.tids, c->iflag + 8 + a, c->st));
     // the ghost nodes (classes 2-4), filled from the coarser level by a list
     // of their ids rather than by a pass over the level or its tiles
     l.gl = GhostList{l.gids, 0};
@@ -1643,32 +1637,15 @@ sbm_status sbm_amr_set_problem(sbm_amr_ctx *c, const double *const *psi_raw,
   memcpy(iv, c->host, sizeof(iv));
   flags = iv[0];
   for (int a = 1; a <= A; ++a) {
-    if (c->lv[a].tiled) c->lv[a].tl.count = iv[8 + a];
     c->lv[a].gl.count = iv[12 + a];
     c->lv[a].cl.count = iv[24 + a];
   }
-  // A level whose active tiles are few for the GPU (a fraction of its
-  // default tile count) lists them again in shallower chunks, so that the
-  // tiled kernels run about kAmrTiles workgroups: each chunk then re-reads
-  // two more planes per kz, but the CUs are no longer half idle.
-  for (int a = 1; a <= A; ++a) {
-    AmrLevel &l = c->lv[a];
-    if (!l.tiled || l.tl.count == 0) continue;
-    const int kz0 = tile_geom_of(l.L).kz;
-    const int kz = std::max(kAmrKzMin, std::min(kz0, (int)((int64_t)kz0 * l.tl.count / kAmrTiles)));
-    // every listed tile-plane writes one partial sum of the level's share
-    const TileGeom tn = tile_geom_of(l.L, kz);
-    if (kz >= kz0 || (int64_t)tn.ntiles * tn.kz > num_blocks(l.L.g.nn)) continue;
-    l.tl.kz = kz;
-    AMR_HIP(launch_fill<int>(c->iflag + 8 + a, 1, 0, c->st));
-    AMR_HIP(launch_active_tiles(l.L, l.cls, l.tflags, l.tids, c->iflag + 8 + a, c->st, kz));
-  }
-  // The smoother relaxes class-1 nodes only, so it sweeps the tiles that hold
-  // them (in the 64^3 x 3 voids workload 1.3x the unknowns against 2.4x for
-  // all active tiles: a block's ghost faces lie in the next tile); the same
-  // chunks, so their partial sums stay within the level's share.
-  // The residual (classes 1-3) runs over the same tiles and, node by node,
-  // over the ghost nodes they leave out.
+  // The passes over a tiled level run over its column tiles that hold
+  // unknowns: the smoother relaxes class-1 nodes only, and the tiles of every
+  // active node would cover 2.4x the unknowns of the 64^3 x 3 voids workload
+  // against 1.3x (a block's ghost faces lie in the next tile).  The residual
+  // (classes 1-3) runs over the same tiles and, node by node, over the ghost
+  // nodes they leave out.
   auto list_unknowns = [&](AmrLevel &l, int a, int kz) -> sbm_status {
     l.tl1 = TileList{l.tids1, 0, kz};
     AMR_HIP(launch_active_tiles(l.L, l.cls, l.tflags, l.tids1, c->iflag + 16 + a, c->st, kz, true));
@@ -1682,7 +1659,6 @@ sbm_status sbm_amr_set_problem(sbm_amr_ctx *c, const double *const *psi_raw,
     memcpy(iv, c->host, sizeof(iv));
     for (int a = 1; a <= A; ++a)
       if (c->lv[a].tiled) {
-        c->lv[a].tl.count = iv[8 + a];
         c->lv[a].tl1.count = iv[16 + a];
         c->lv[a].go.count = iv[20 + a];
       }
@@ -1691,24 +1667,26 @@ sbm_status sbm_amr_set_problem(sbm_amr_ctx *c, const double *const *psi_raw,
   bool listed = false;
   for (int a = 1; a <= A; ++a) {
     AmrLevel &l = c->lv[a];
-    l.tl1 = TileList{l.tids1, 0, l.tl.kz};
+    l.tl1 = TileList{l.tids1, 0, 0};
     l.go = GhostList{l.goids, 0};
     if (!l.tiled) continue;
-    AMR_TRY(list_unknowns(l, a, l.tl.kz));
+    AMR_TRY(list_unknowns(l, a, 0));
     listed = true;
   }
   if (listed) AMR_TRY(read_counts());
-  // The tiles with unknowns are fewer than the active ones: a level whose
-  // list is short for the GPU lists them again in shallower chunks, by the
-  // rule above.
+  // A level whose tiles with unknowns are few for the GPU (a fraction of its
+  // default tile count) lists them again in shallower chunks, so that the
+  // tiled kernels run about kAmrTiles workgroups: each chunk then re-reads
+  // two more planes per kz, but the CUs are no longer half idle.  Every
+  // listed tile-plane writes one partial sum of the level's share.
   bool relisted = false;
   for (int a = 1; a <= A; ++a) {
     AmrLevel &l = c->lv[a];
     if (!l.tiled || l.tl1.count == 0) continue;
-    const int kzc = tile_geom_of(l.L, l.tl.kz).kz;
-    const int kz = std::max(kAmrKzMin, std::min(kzc, (int)((int64_t)kzc * l.tl1.count / kAmrTiles)));
+    const int kz0 = tile_geom_of(l.L).kz;
+    const int kz = std::max(kAmrKzMin, std::min(kz0, (int)((int64_t)kz0 * l.tl1.count / kAmrTiles)));
     const TileGeom tn = tile_geom_of(l.L, kz);
-    if (kz >= kzc || (int64_t)tn.ntiles * tn.kz > num_blocks(l.L.g.nn)) continue;
+    if (kz >= kz0 || (int64_t)tn.ntiles * tn.kz > num_blocks(l.L.g.nn)) continue;
     AMR_TRY(list_unknowns(l, a, kz));
     relisted = true;
   }
