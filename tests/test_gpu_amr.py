@@ -11,10 +11,11 @@ residual of the history agrees to 1e-6 relative plus 1e-13 absolute (the
 rounding floor of the residual evaluation) and the displacement to 1e-9
 relative L2 on every level; the mixed solve reaches the same residual and
 agrees to 1e-8.  The "wide3d" cases have a finest level 225 nodes wide and 33
-deep, so its finest-level kernels run the LDS-tiled path over the lists of
-tiles that hold active nodes (residual) and unknowns (smoothing, correction,
-update, norm), the path of the 64^3 x 3 workload; in "wide3d_sparse" some
-ghost faces lie in tiles without unknowns, which the smoother never sweeps."""
+deep, so its finest-level kernels run the LDS-tiled path over the list of
+tiles that hold unknowns (with the ghost nodes outside them listed node by
+node for the residual), the path of the 64^3 x 3 workload; in
+"wide3d_sparse" some ghost faces lie in tiles without unknowns, which the
+tiled passes never sweep."""
 import numpy as np
 import pytest
 import torch
